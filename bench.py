@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched Monte Carlo propagation hot path on one MI355X.
+
+One bench step = one fsg_simulate call: seeds -> synchronous pull steps until
+absorption or the step cap -> final states [n][B] and per-node counts, for a
+batch of B replicates of the workload.  Inputs are resident in HBM before the
+timed region.  The metric is replicate-edge updates per second:
+nnz * B * steps_run / wall time of the step.
+
+Workloads (synthetic stand-ins for the paper's datasets):
+  c2  SIR on Chung-Lu n=1e6 (exponent 2.5, mean degree 20), beta 0.02,
+      gamma 0.1, 1% seeds, B=1024, 200 steps            (default)
+  c1  IC on directed G(1000, mean out-degree 10), p 0.1, B=100
+  c4  IC weighted cascade on R-MAT scale 26, edge factor 16, B=64
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_step(model: str, n: int, nnz: int, B: int) -> float:
+    """Bytes one pull step must move if every array is touched once per use:
+    sources 4 B/arc, row pointers 4 B/row, the gathered neighbour word group
+    8 W B/arc, and the node's own planes (IC: read A, write A and F;
+    SIR-family: read h, r, write h, r; LT: read and write the active plane)."""
+    W = (B + 63) // 64
+    own = {"ic": 24, "lt": 16}.get(model, 32) * W
+    return 4.0 * nnz + 8.0 * W * nnz + 4.0 * (n + 1) + own * n
+
+
+def make_workload(name: str):
+    from paper_2603_14895_amd import workloads as Wl
+    if name == "c1":
+        return Wl.config_c1()
+    if name == "c2":
+        return Wl.config_c2()
+    if name == "c4":
+        dev = "cuda"
+        return Wl.config_c4(device=dev)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def params_of(c):
+    if c["model"] == "ic":
+        return dict(p=c.get("p", 0.0), ic_prob=c.get("ic_prob", "uniform"),
+                    max_steps=c["max_steps"])
+    if c["model"] in ("sir", "sis", "si"):
+        return dict(beta=c["beta"], gamma=c["gamma"], max_steps=c["max_steps"])
+    return dict(max_steps=c["max_steps"])
+
+
+def cpu_baseline(c, ptr, src, target_seconds: float):
+    """The oracle as it stands on a bounded sample of the same workload:
+    `threads` replicates (one per host thread), same graph, seeds, key and
+    step cap.  Rate in replicate-edge updates per second."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    R = threads
+    t0 = time.perf_counter()
+    kw = params_of(c)
+    okw = dict(kw)
+    if "ic_prob" in okw:
+        from paper_2603_14895_amd import fsg
+        okw["ic_prob"] = fsg.IC_PROBS[okw["ic_prob"]]
+    if c["model"] == "ic" and ptr.size > 50_000_000:
+        # the plain loop nest is far too slow at web scale: the live-edge BFS
+        # oracle computes the same final states
+        _, _, _, steps, _ = oracle.ic_live_edge(ptr, src, c["seeds"], R, c["rng_key"],
+                                                want_states=False, nthreads=threads, **okw)
+        kind = "oracle-live-edge-bfs"
+    else:
+        _, _, steps, _ = oracle.simulate(c["model"], ptr, src, c["seeds"], R, c["rng_key"],
+                                         want_states=False, nthreads=threads, **okw)
+        kind = "oracle"
+    dt = time.perf_counter() - t0
+    nnz = src.size
+    rate = nnz * R * steps / dt
+    return {"value": rate, "unit": "replicate-edge updates/s", "cores": threads, "kind": kind,
+            "sample": f"{R} replicates (of B={c['B']}) x {steps} steps on the full graph, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--schedule", default=None, help="JSON dict of fsg_schedule fields")
+    ap.add_argument("--no-states", action="store_true", help="counts only (no [n][B] output)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(replicate sharding across GPUs is described in DESIGN.md); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2603_14895_amd import fsg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    c = make_workload(args.workload)
+    gr = c["graph"]
+    ptr, src = gr.numpy()
+    log(f"[bench] workload {c['name']}: n={gr.n} nnz={gr.nnz} B={c['B']} "
+        f"(generated in {time.perf_counter() - t0:.1f}s)")
+    del gr
+    c["graph"] = None
+    dg = fsg.DeviceGraph(ptr, src, device="cuda:0")
+    sched = json.loads(args.schedule) if args.schedule else {}
+    sched["time_kernels"] = 1
+    sim = fsg.Simulation(dg, c["model"], c["B"], schedule=sched, want_states=not args.no_states,
+                         **params_of(c))
+    log(f"[bench] workspace {sim.ws_bytes / 2**30:.2f} GiB, schedule "
+        f"{fsg.fsg_default_schedule(dg.handle, sim.prm, c['B']).as_dict()} overrides {sched}")
+    for i in range(args.warmup):
+        info = sim.run(c["seeds"], c["rng_key"])
+        log(f"[bench] warmup {i}: steps_run={info.steps_run} absorbed={info.absorbed}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    total_updates = 0.0
+    kernel_ms = 0.0
+    launches = 0
+    steps_seen = []
+    for i in range(args.steps):
+        info = sim.run(c["seeds"], c["rng_key"])
+        total_updates += float(src.size) * c["B"] * info.steps_run
+        kernel_ms += info.step_kernel_ms
+        launches += info.step_launches
+        steps_seen.append(int(info.steps_run))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    value = total_updates / dt
+    ms_per_step = dt * 1000.0 / args.steps
+    counts = sim.counts.cpu().numpy()
+    attack = float(counts.sum()) / (ptr.size - 1) / c["B"]
+    log(f"[bench] {args.steps} steps in {dt:.3f}s: {ms_per_step:.2f} ms/step, "
+        f"steps_run={steps_seen}, mean counted fraction {attack:.4f}")
+
+    avg_kernel_ms = kernel_ms / max(launches, 1)
+    abytes = algorithmic_bytes_per_step(c["model"], ptr.size - 1, src.size, c["B"])
+    achieved = abytes / (avg_kernel_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": "k_step (pull step; heavy-row combine included)",
+                "avg_launch_ms": round(avg_kernel_ms, 5), "launches": launches,
+                "algorithmic_bytes_per_launch": abytes}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        cpu = cpu_baseline(c, ptr, src, args.cpu_seconds)
+        log(f"[bench] cpu baseline {cpu}")
+    out = {
+        "metric": "replicate-edge updates/s", "value": value, "unit": "replicate-edge updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64 bit-packed replicates / u32 integer draws",
+        "data": "synthetic",
+        "config": {"workload": c["name"], "model": c["model"], "n": int(ptr.size - 1),
+                   "nnz": int(src.size), "B": c["B"], "max_steps": c["max_steps"],
+                   "steps_run": steps_seen[-1] if steps_seen else 0, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

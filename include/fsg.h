@@ -1,0 +1,214 @@
+/*
+ * fsg.h -- C-ABI of libfsg, batched Monte Carlo graph propagation on MI355X.
+ *
+ * The library runs the synchronous message-passing step of FS_GPlib
+ * (arxiv 2603.14895): for every node and every Monte Carlo replicate, gather
+ * the previous-round states of the in-neighbours, aggregate, and update the
+ * node's state (Sec. 3.1, Eq. ms, Eq. agg, Eq. updata), for all replicates of
+ * a batch at once (Definition "Batched Monte Carlo Method", Eq. batch), until
+ * no replicate can change any more or a step cap is reached.  The calls
+ * follow the problem statement of the paper's model interface (Sec. 4,
+ * Eq. model: graph, seed set, parameters, device; run_epochs returns the
+ * final states of all runs), plus the replicate count, the replicate offset
+ * of the batch and the RNG key.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns FSG_OK (0) or a negative status; no C++ exception
+ *   crosses this boundary.  fsg_last_error() describes the last failure on
+ *   the calling thread.  On failure, outputs are unspecified and nothing has
+ *   been written to caller memory except possibly the outputs themselves.
+ * - Arguments are validated on the host before anything is launched.
+ * - The caller owns every buffer.  All device memory comes from the caller
+ *   (a workspace sized by the *_workspace_size queries); the library never
+ *   allocates or frees device memory.  It may allocate host memory.
+ * - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ * - Randomness: Philox4x32-10 (Salmon et al., SC'11) keyed by rng_key.  A
+ *   draw for (domain, unit, replicate g, step) uses counter
+ *   (lo32 unit, g >> 2, step, domain << 24 | hi32 unit) and keeps word g & 3;
+ *   g = replicate_offset + r is the global replicate index, so results do
+ *   not depend on how a Monte Carlo run is split into batches.  Domains:
+ *   1 = IC edge trial (unit = edge id, step 0), 2 = per-node step draw
+ *   (unit = node, step = t), 3 = LT threshold (unit = node, step 0).
+ *   A Bernoulli(p) fires iff t == 0xFFFFFFFF or draw < t, with
+ *   t = thr(p) = 0 for p <= 0, 0xFFFFFFFF for p >= 1, otherwise
+ *   min(floor(p * 2^32), 0xFFFFFFFE), computed in FP64 on the host.
+ */
+#ifndef FSG_H
+#define FSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSG_ABI_VERSION 1
+
+/* status codes */
+#define FSG_OK 0
+#define FSG_EINVAL (-1)       /* an argument is out of its documented range    */
+#define FSG_ENOMEM (-2)       /* host allocation failed                        */
+#define FSG_EDEVICE (-3)      /* a HIP call failed; the message names it       */
+#define FSG_EUNSUPPORTED (-4) /* valid but outside what this build handles     */
+#define FSG_EWORKSPACE (-5)   /* workspace missing, too small or misaligned    */
+
+/* models (Table tab:29s; SIR rule of Appendix A.1) */
+#define FSG_IC 0  /* independent cascade: 0 inactive, 1 newly active, 2 active  */
+#define FSG_SI 1  /* SI: SIR without recovery                                   */
+#define FSG_SIS 2 /* SIS: recovery returns the node to S                        */
+#define FSG_SIR 3 /* SIR: 0 S, 1 I, 2 R                                         */
+#define FSG_LT 4  /* linear threshold, in-weights 1/indeg, thresholds U(0,1)    */
+
+/* IC edge probability */
+#define FSG_IC_UNIFORM 0          /* p for every arc                         */
+#define FSG_IC_WEIGHTED_CASCADE 1 /* p = 1/indeg(target)                     */
+#define FSG_IC_PER_EDGE 2         /* edge_p[e], host array of nnz doubles    */
+
+typedef struct fsg_graph fsg_graph;
+
+/* Model and parameters.
+ * max_steps: step cap K >= 0.  For IC and LT a negative value means "until
+ * absorption" (at most n steps can change anything).  SI, SIS, SIR require
+ * K >= 0.  p, beta, gamma, edge_p[] must lie in [0, 1] and not be NaN.
+ * For SI, gamma is ignored (no recovery). */
+typedef struct {
+    int32_t model;
+    int32_t ic_prob;
+    double p;
+    const double *edge_p; /* host, [nnz], only for FSG_IC_PER_EDGE */
+    double beta;
+    double gamma;
+    int64_t max_steps;
+} fsg_params;
+
+/* steps_run: number of synchronous steps executed (the batch shares one
+ * loop that stops once no replicate has a state-1 node, or at max_steps).
+ * absorbed: 1 iff no replicate ends with a state-1 node.
+ * step_kernel_ms, step_launches: when the schedule asks for kernel timing,
+ * the summed device time of the pull-step kernels (HIP events recorded on the
+ * call's stream around each step) and the number of steps timed; else 0. */
+typedef struct {
+    int64_t steps_run;
+    int32_t absorbed;
+    int32_t reserved;
+    double step_kernel_ms;
+    int64_t step_launches;
+} fsg_run_info;
+
+/* Launch schedule of the pull step (what the autotuner searches).  A value
+ * of 0 in any field means "library default".
+ *   row_lanes      lanes that share one row, a power of two in [1, 64].
+ *                  The lanes split first over the row's state words
+ *                  (min(row_lanes, next_pow2(ceil(B/64))) of them), the
+ *                  rest split the row's in-edge list.
+ *   block_threads  workgroup size: 64, 128, 256, 512 or 1024.
+ *   tile_edges     target in-edges per workgroup tile (contiguous rows).
+ *   heavy_threshold rows with more in-edges than this are cut into
+ *                  segments of at most this many edges, processed in
+ *                  parallel and merged (OR / integer add, order-free).
+ *   steps_per_sync synchronous steps launched between host polls of the
+ *                  absorption flags.
+ *   time_kernels   1: time every pull step with HIP events (reported in
+ *                  fsg_run_info); 0: no timing. */
+typedef struct {
+    int32_t row_lanes;
+    int32_t block_threads;
+    int32_t tile_edges;
+    int32_t heavy_threshold;
+    int32_t steps_per_sync;
+    int32_t time_kernels;
+    int32_t reserved[2];
+} fsg_schedule;
+
+/* Library version of this header (FSG_ABI_VERSION). */
+int fsg_abi_version(void);
+
+/* Message for the last failing call on this thread; valid until the next
+ * fsg_* call on the same thread.  Never NULL. */
+const char *fsg_last_error(void);
+
+/* Graph (Sec. 2, Definitions "Graph" and "CSR"; update rule Eq. nodestate
+ * pulls over in-neighbours N^-(v)).
+ * n >= 1 nodes, nnz >= 0 arcs, nnz < 2^31.  in_ptr: host int64 [n+1],
+ * in_ptr[0] = 0, non-decreasing, in_ptr[n] = nnz.  in_src: host int32
+ * [nnz]; in_src[in_ptr[v] .. in_ptr[v+1]) are the sources u of the arcs
+ * u -> v.  The edge id of an arc is its position in in_src.  Undirected
+ * graphs store both arcs.  Self-loops and repeated arcs are allowed.
+ * in_ptr is copied; in_src is borrowed until fsg_graph_bind returns.
+ * Errors: FSG_EINVAL (NULL pointers, n < 1, a malformed CSR, a source out
+ * of range), FSG_EUNSUPPORTED (nnz >= 2^31), FSG_ENOMEM. */
+int fsg_graph_create(int64_t n, int64_t nnz, const int64_t *in_ptr, const int32_t *in_src,
+                     fsg_graph **out);
+
+/* Device bytes the graph needs (row pointers and sources on the device). */
+int fsg_graph_workspace_size(const fsg_graph *g, size_t *bytes);
+
+/* Copies the graph into caller device memory dev_ws (at least
+ * fsg_graph_workspace_size bytes, 256-byte aligned), which must stay valid
+ * and untouched while the graph is used.  Synchronous on `stream`.
+ * Errors: FSG_EWORKSPACE, FSG_EDEVICE. */
+int fsg_graph_bind(fsg_graph *g, void *dev_ws, size_t ws_bytes, void *stream);
+
+/* n, nnz and the largest in-degree; any output may be NULL. */
+int fsg_graph_stats(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg);
+
+/* Frees the host-side graph object (never the caller's device memory). */
+int fsg_graph_destroy(fsg_graph *g);
+
+/* Schedule the library picks for this graph, model and B without tuning. */
+int fsg_default_schedule(const fsg_graph *g, const fsg_params *prm, int64_t B,
+                         fsg_schedule *out);
+
+/* Device bytes fsg_simulate needs for (graph, params, B, schedule); sched
+ * may be NULL (default schedule). */
+int fsg_sim_workspace_size(const fsg_graph *g, const fsg_params *prm, int64_t B,
+                           const fsg_schedule *sched, size_t *bytes);
+
+/* Batched Monte Carlo propagation (Algorithm 1 run as Eq. batch): B >= 1
+ * replicates with global indices replicate_offset + r, r < B
+ * (replicate_offset >= 0, replicate_offset + B <= 2^34), every replicate
+ * starting with the seed set in state 1 and everything else in state 0.
+ * seeds: host int32 [n_seeds], each in [0, n); duplicates are ignored and an
+ * empty set is valid (nothing happens).
+ * Outputs (device, either may be NULL):
+ *   final_states [n][B] uint8, final_states[v*B + r] = state of node v in
+ *     replicate r (IC 0/1/2, SIR 0/1/2, SI and SIS 0/1, LT 0/1);
+ *   infected_counts [n] uint32, the number of replicates in which v is
+ *     counted: ever active (IC), ever infected (SI, SIR), infected at the
+ *     end (SIS), active (LT).
+ * info (host, may be NULL) receives steps_run and absorbed.
+ * The graph must be bound.  dev_ws: at least fsg_sim_workspace_size bytes,
+ * 256-byte aligned; its contents on entry do not matter.  The call returns
+ * after the work on `stream` has completed.
+ * Errors: FSG_EINVAL, FSG_EWORKSPACE, FSG_EDEVICE, FSG_EUNSUPPORTED. */
+int fsg_simulate(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t n_seeds,
+                 int64_t B, int64_t replicate_offset, uint64_t rng_key, const fsg_schedule *sched,
+                 void *dev_ws, size_t ws_bytes, uint8_t *final_states, uint32_t *infected_counts,
+                 fsg_run_info *info, void *stream);
+
+/* Row-tile planner (host only; Sec. 3.2, Definition "Target-Node-Based
+ * Partitioning via Longest Processing Time Heuristic", kept in CSR order so
+ * every part is a contiguous row range).  Row v weighs
+ * (indeg(v) > heavy ? 0 : indeg(v)) + row_cost; with prefix weight C_v and
+ * total W, row v goes to part ceil(n_parts * C_v / W).  Empty parts are
+ * dropped.  bounds_out (host, n + 2 int64) receives the row boundaries
+ * 0 = b_0 < b_1 < ... < b_k = n of the k <= n_parts non-empty parts and
+ * *n_out = k.  Each part's weight differs from W / n_parts by less than the
+ * largest row weight (Proposition "Load Balance Guarantee").
+ * Errors: FSG_EINVAL. */
+int fsg_plan_row_tiles(const int64_t *in_ptr, int64_t n, int64_t heavy, int64_t row_cost,
+                       int64_t n_parts, int64_t *bounds_out, int64_t *n_out);
+
+/* The generator itself: out[4i .. 4i+3] = Philox4x32-10(ctr[4i .. 4i+3],
+ * key) for i < count, computed on the device.  dev_ctr and dev_out are
+ * device arrays of 4*count uint32.  Asynchronous on `stream`. */
+int fsg_philox4x32_10(const uint32_t *dev_ctr, uint32_t key0, uint32_t key1, uint32_t *dev_out,
+                      int64_t count, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSG_H */

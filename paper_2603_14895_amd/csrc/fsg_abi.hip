@@ -1,0 +1,652 @@
+// fsg_abi.hip -- host side of libfsg: argument validation, FP64 threshold
+// tables, the row-tile planner, workspace layout and the step loop.
+// Declarations and contracts: include/fsg.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fsg.h"
+#include "fsg_internal.hpp"
+
+using namespace fsg;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(FSG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// Probability -> uint32 threshold (the Bernoulli fires iff t == 2^32-1 or
+// draw < t).  Scaling by 2^32 is exact in FP64.
+uint32_t threshold_of(double p)
+{
+    if (!(p > 0.0)) return 0u;
+    if (p >= 1.0) return 0xFFFFFFFFu;
+    double x = floor(p * 4294967296.0);
+    return x > 4294967294.0 ? 0xFFFFFFFEu : (uint32_t)x;
+}
+
+// Appendix A.1: with k infected in-neighbours the infection probability is
+// 1 - exp(k log(1-beta)) = 1 - (1-beta)^k.  The survival power is built by
+// repeated FP64 multiplication; the table stops where it saturates.
+std::vector<uint32_t> infection_table(double beta, int64_t max_k)
+{
+    std::vector<uint32_t> t;
+    t.reserve((size_t)std::min<int64_t>(max_k + 1, 1 << 16));
+    volatile double surv = 1.0;
+    for (int64_t k = 0; k <= max_k; ++k) {
+        if (k > 0) surv = surv * (1.0 - beta);
+        const uint32_t x = threshold_of(1.0 - surv);
+        t.push_back(x);
+        if (x == 0xFFFFFFFFu) break;  // every later entry is "always" too
+    }
+    return t;
+}
+
+bool bad_prob(double p) { return !(p >= 0.0 && p <= 1.0); }
+
+int64_t next_pow2(int64_t x)
+{
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+int ilog2(int64_t x)
+{
+    int l = 0;
+    while ((1ll << l) < x) ++l;
+    return l;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+    std::vector<int32_t> tiles;      // row boundaries of non-empty tiles
+    std::vector<int32_t> heavy_rows; // rows with indeg > heavy
+    std::vector<int32_t> heavy_seg;  // [n_heavy + 1] first segment of each heavy row
+    std::vector<int32_t> seg_row, seg_e0, seg_e1;
+    int64_t max_light = 0;           // largest light in-degree
+    int64_t max_seg = 0;             // longest segment
+};
+
+}  // namespace
+
+struct fsg_graph {
+    int64_t n = 0, nnz = 0, max_indeg = 0;
+    std::vector<int64_t> ptr;
+    const int32_t *src_host = nullptr;
+    bool bound = false;
+    int32_t *d_ptr = nullptr;
+    int32_t *d_src = nullptr;
+    std::map<std::tuple<int64_t, int64_t, int64_t>, Plan> plans;
+};
+
+// Target-node partition by prefix sums (Sec. 3.2, Definition "Target-Node-
+// Based Partitioning"): node i with prefix load C_i goes to part
+// ceil(d C_i / W_total); here the nodes keep their CSR order so each part is
+// a contiguous row range owned by one workgroup.  Load of a row: in-degree
+// (0 for heavy rows, which are processed as segments) plus row_cost.
+extern "C" int fsg_plan_row_tiles(const int64_t *in_ptr, int64_t n, int64_t heavy,
+                                  int64_t row_cost, int64_t n_parts, int64_t *bounds_out,
+                                  int64_t *n_out)
+{
+    if (!in_ptr || !bounds_out || !n_out || n < 1 || n_parts < 1 || row_cost < 0)
+        return fail(FSG_EINVAL, "fsg_plan_row_tiles: bad arguments");
+    unsigned __int128 total = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t d = in_ptr[v + 1] - in_ptr[v];
+        total += (unsigned __int128)((d > heavy ? 0 : d) + row_cost);
+    }
+    int64_t nb = 0;
+    bounds_out[nb++] = 0;
+    if (total == 0) {
+        bounds_out[nb++] = n;
+        *n_out = nb - 1;
+        return FSG_OK;
+    }
+    unsigned __int128 c = 0;
+    int64_t cur = 1;  // part of the rows seen so far
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t d = in_ptr[v + 1] - in_ptr[v];
+        c += (unsigned __int128)((d > heavy ? 0 : d) + row_cost);
+        const unsigned __int128 num = (unsigned __int128)n_parts * c;
+        int64_t q = (int64_t)((num + total - 1) / total);
+        if (q < 1) q = 1;
+        if (q > cur) {
+            // row v opens part q: close the previous one before v (if non-empty)
+            if (v > bounds_out[nb - 1]) bounds_out[nb++] = v;
+            cur = q;
+        }
+    }
+    if (bounds_out[nb - 1] != n) bounds_out[nb++] = n;
+    *n_out = nb - 1;
+    return FSG_OK;
+}
+
+namespace {
+
+constexpr int64_t kRowCost = 4;
+
+const Plan &get_plan(fsg_graph *g, int64_t heavy, int64_t tile_edges)
+{
+    auto key = std::make_tuple(heavy, tile_edges, kRowCost);
+    auto it = g->plans.find(key);
+    if (it != g->plans.end()) return it->second;
+    Plan p;
+    const int64_t n = g->n;
+    const int64_t *ptr = g->ptr.data();
+    unsigned __int128 total = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t d = ptr[v + 1] - ptr[v];
+        total += (unsigned __int128)((d > heavy ? 0 : d) + kRowCost);
+        if (d > heavy) {
+            p.heavy_rows.push_back((int32_t)v);
+            p.heavy_seg.push_back((int32_t)p.seg_row.size());
+            for (int64_t e = ptr[v]; e < ptr[v + 1]; e += heavy) {
+                p.seg_row.push_back((int32_t)v);
+                p.seg_e0.push_back((int32_t)e);
+                p.seg_e1.push_back((int32_t)std::min(ptr[v + 1], e + heavy));
+            }
+            p.max_seg = std::max(p.max_seg, std::min(d, heavy));
+        } else {
+            p.max_light = std::max(p.max_light, d);
+        }
+    }
+    p.heavy_seg.push_back((int32_t)p.seg_row.size());
+    int64_t parts = (int64_t)((total + (unsigned __int128)tile_edges - 1) / (unsigned __int128)tile_edges);
+    parts = std::max<int64_t>(1, std::min<int64_t>(parts, n));
+    std::vector<int64_t> b((size_t)n + 2);
+    int64_t nt = 0;
+    fsg_plan_row_tiles(ptr, n, heavy, kRowCost, parts, b.data(), &nt);
+    p.tiles.resize((size_t)nt + 1);
+    for (int64_t i = 0; i <= nt; ++i) p.tiles[(size_t)i] = (int32_t)b[(size_t)i];
+    return g->plans.emplace(key, std::move(p)).first->second;
+}
+
+int model_kind(int model)
+{
+    if (model == kIC) return kKindIC;
+    if (model == kLT) return kKindLT;
+    return kKindEpidemic;
+}
+
+int check_params(const fsg_graph *g, const fsg_params *prm, int64_t B)
+{
+    if (!g) return fail(FSG_EINVAL, "graph is NULL");
+    if (!prm) return fail(FSG_EINVAL, "params is NULL");
+    if (prm->model < FSG_IC || prm->model > FSG_LT) return fail(FSG_EINVAL, "unknown model");
+    if (B < 1) return fail(FSG_EINVAL, "B must be >= 1");
+    if (B > (int64_t)1 << 31) return fail(FSG_EUNSUPPORTED, "B above 2^31");
+    const bool epi = prm->model == FSG_SI || prm->model == FSG_SIS || prm->model == FSG_SIR;
+    if (epi && prm->max_steps < 0) return fail(FSG_EINVAL, "SI/SIS/SIR need max_steps >= 0");
+    if (prm->max_steps > 0x7FFFFFFF) return fail(FSG_EUNSUPPORTED, "max_steps above 2^31-1");
+    if (prm->model == FSG_IC) {
+        if (prm->ic_prob < FSG_IC_UNIFORM || prm->ic_prob > FSG_IC_PER_EDGE)
+            return fail(FSG_EINVAL, "unknown ic_prob");
+        if (prm->ic_prob == FSG_IC_UNIFORM && bad_prob(prm->p))
+            return fail(FSG_EINVAL, "p must be in [0, 1]");
+        if (prm->ic_prob == FSG_IC_PER_EDGE) {
+            if (g->nnz > 0 && !prm->edge_p) return fail(FSG_EINVAL, "edge_p is NULL");
+            for (int64_t e = 0; e < g->nnz; ++e)
+                if (bad_prob(prm->edge_p[e])) return fail(FSG_EINVAL, "edge_p[e] outside [0, 1]");
+        }
+    }
+    if (epi) {
+        if (bad_prob(prm->beta)) return fail(FSG_EINVAL, "beta must be in [0, 1]");
+        if (prm->model != FSG_SI && bad_prob(prm->gamma))
+            return fail(FSG_EINVAL, "gamma must be in [0, 1]");
+    }
+    return FSG_OK;
+}
+
+struct Sched {
+    int G, S, lgG, lgS, block, tile_edges, heavy, sync, timed;
+};
+
+void default_sched(const fsg_graph *g, int64_t B, fsg_schedule *o)
+{
+    const int64_t W = (B + 63) / 64;
+    memset(o, 0, sizeof(*o));
+    o->row_lanes = W >= 16 ? 64 : 16;
+    o->block_threads = 256;
+    o->tile_edges = 4096;
+    o->heavy_threshold = 2048;
+    o->steps_per_sync = 16;
+    (void)g;
+}
+
+int resolve_sched(const fsg_graph *g, int64_t B, const fsg_schedule *in, Sched *s)
+{
+    fsg_schedule d;
+    default_sched(g, B, &d);
+    fsg_schedule u = in ? *in : d;
+    if (u.row_lanes == 0) u.row_lanes = d.row_lanes;
+    if (u.block_threads == 0) u.block_threads = d.block_threads;
+    if (u.tile_edges == 0) u.tile_edges = d.tile_edges;
+    if (u.heavy_threshold == 0) u.heavy_threshold = d.heavy_threshold;
+    if (u.steps_per_sync == 0) u.steps_per_sync = d.steps_per_sync;
+    if (u.row_lanes < 1 || u.row_lanes > 64 || (u.row_lanes & (u.row_lanes - 1)))
+        return fail(FSG_EINVAL, "row_lanes must be a power of two in [1, 64]");
+    if (u.block_threads < 64 || u.block_threads > 1024 || (u.block_threads & (u.block_threads - 1)))
+        return fail(FSG_EINVAL, "block_threads must be a power of two in [64, 1024]");
+    if (u.tile_edges < 1) return fail(FSG_EINVAL, "tile_edges must be >= 1");
+    if (u.heavy_threshold < 1 || u.heavy_threshold > 65535)
+        return fail(FSG_EINVAL, "heavy_threshold must be in [1, 65535]");
+    if (u.steps_per_sync < 1 || u.steps_per_sync > 4096)
+        return fail(FSG_EINVAL, "steps_per_sync must be in [1, 4096]");
+    const int64_t W = (B + 63) / 64;
+    const int64_t G = std::min<int64_t>(u.row_lanes, std::min<int64_t>(next_pow2(W), 64));
+    s->G = (int)G;
+    s->S = (int)(u.row_lanes / G);
+    s->lgG = ilog2(s->G);
+    s->lgS = ilog2(s->S);
+    s->block = u.block_threads;
+    s->tile_edges = u.tile_edges;
+    s->heavy = u.heavy_threshold;
+    s->sync = u.steps_per_sync;
+    s->timed = u.time_kernels != 0;
+    return FSG_OK;
+}
+
+struct Layout {
+    size_t planes[3];
+    int n_planes;
+    size_t flags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
+        seeds, total;
+    int64_t W, plane_words, n_tinf, n_seed_stage;
+    int L;
+};
+
+constexpr int64_t kSeedStage = 65536;
+
+// HIP events for optional per-step timing, released on scope exit.
+struct EventPool {
+    std::vector<hipEvent_t> e;
+    hipError_t init(size_t count)
+    {
+        e.resize(count, nullptr);
+        for (auto &x : e) {
+            hipError_t r = hipEventCreate(&x);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    ~EventPool()
+    {
+        for (auto x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const Plan &p,
+           Layout *L)
+{
+    const int kind = model_kind(prm->model);
+    L->W = (B + 63) / 64;
+    L->plane_words = g->n * L->W;
+    L->n_planes = kind == kKindLT ? 2 : 3;
+    L->L = kind == kKindIC ? 1 : counter_planes_for(std::max(p.max_light, p.max_seg));
+    if (kind == kKindEpidemic) {
+        const double beta = prm->beta;
+        L->n_tinf = (int64_t)infection_table(beta, g->max_indeg).size();
+    } else {
+        L->n_tinf = 1;
+    }
+    L->n_seed_stage = std::min<int64_t>(g->n, kSeedStage);
+    size_t off = 0;
+    for (int i = 0; i < L->n_planes; ++i) {
+        L->planes[i] = off;
+        off = align256(off + (size_t)L->plane_words * 8);
+    }
+    const int ring = s.sync + 1;
+    L->flags = off; off = align256(off + (size_t)ring * 4);
+    L->tiles = off; off = align256(off + p.tiles.size() * 4);
+    L->heavy_rows = off; off = align256(off + (p.heavy_rows.size() + 1) * 4);
+    L->heavy_seg = off; off = align256(off + p.heavy_seg.size() * 4);
+    L->seg_row = off; off = align256(off + (p.seg_row.size() + 1) * 4);
+    L->seg_e0 = off; off = align256(off + (p.seg_e0.size() + 1) * 4);
+    L->seg_e1 = off; off = align256(off + (p.seg_e1.size() + 1) * 4);
+    L->partial = off; off = align256(off + p.seg_row.size() * (size_t)L->L * (size_t)L->W * 8);
+    L->tinf = off; off = align256(off + (size_t)L->n_tinf * 4);
+    L->edge_t = off;
+    if (prm->model == FSG_IC && prm->ic_prob == FSG_IC_PER_EDGE)
+        off = align256(off + (size_t)g->nnz * 4);
+    L->seeds = off; off = align256(off + (size_t)L->n_seed_stage * 4);
+    L->total = off;
+    return FSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fsg_abi_version(void) { return FSG_ABI_VERSION; }
+
+const char *fsg_last_error(void) { return g_err.c_str(); }
+
+int fsg_graph_create(int64_t n, int64_t nnz, const int64_t *in_ptr, const int32_t *in_src,
+                     fsg_graph **out)
+{
+    try {
+        if (!out) return fail(FSG_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (n < 1) return fail(FSG_EINVAL, "n must be >= 1");
+        if (n > 0x7FFFFFFF - 1) return fail(FSG_EUNSUPPORTED, "n above 2^31-2");
+        if (nnz < 0) return fail(FSG_EINVAL, "nnz must be >= 0");
+        if (nnz >= ((int64_t)1 << 31)) return fail(FSG_EUNSUPPORTED, "nnz must be below 2^31");
+        if (!in_ptr) return fail(FSG_EINVAL, "in_ptr is NULL");
+        if (nnz > 0 && !in_src) return fail(FSG_EINVAL, "in_src is NULL");
+        if (in_ptr[0] != 0) return fail(FSG_EINVAL, "in_ptr[0] must be 0");
+        if (in_ptr[n] != nnz) return fail(FSG_EINVAL, "in_ptr[n] must equal nnz");
+        int64_t dmax = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            const int64_t d = in_ptr[v + 1] - in_ptr[v];
+            if (d < 0) return fail(FSG_EINVAL, "in_ptr must be non-decreasing");
+            dmax = std::max(dmax, d);
+        }
+        for (int64_t e = 0; e < nnz; ++e)
+            if (in_src[e] < 0 || (int64_t)in_src[e] >= n)
+                return fail(FSG_EINVAL, "in_src entry out of range at edge " + std::to_string(e));
+        fsg_graph *g = new fsg_graph;
+        g->n = n;
+        g->nnz = nnz;
+        g->max_indeg = dmax;
+        g->ptr.assign(in_ptr, in_ptr + n + 1);
+        g->src_host = in_src;
+        *out = g;
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(FSG_EINVAL, "unexpected host exception");
+    }
+}
+
+int fsg_graph_workspace_size(const fsg_graph *g, size_t *bytes)
+{
+    if (!g || !bytes) return fail(FSG_EINVAL, "NULL argument");
+    *bytes = align256((size_t)(g->n + 1) * 4) + align256((size_t)std::max<int64_t>(g->nnz, 1) * 4);
+    return FSG_OK;
+}
+
+int fsg_graph_bind(fsg_graph *g, void *dev_ws, size_t ws_bytes, void *stream)
+{
+    try {
+        if (!g) return fail(FSG_EINVAL, "graph is NULL");
+        size_t need = 0;
+        fsg_graph_workspace_size(g, &need);
+        if (!dev_ws || ws_bytes < need) return fail(FSG_EWORKSPACE, "graph workspace too small");
+        if (((uintptr_t)dev_ws & 255) != 0) return fail(FSG_EWORKSPACE, "workspace not 256-byte aligned");
+        if (g->nnz > 0 && !g->src_host) return fail(FSG_EINVAL, "graph already bound; sources released");
+        hipStream_t s = (hipStream_t)stream;
+        char *base = (char *)dev_ws;
+        int32_t *dptr = (int32_t *)base;
+        int32_t *dsrc = (int32_t *)(base + align256((size_t)(g->n + 1) * 4));
+        std::vector<int32_t> p32(g->ptr.begin(), g->ptr.end());
+        HIP_TRY(hipMemcpyAsync(dptr, p32.data(), p32.size() * 4, hipMemcpyHostToDevice, s));
+        if (g->nnz > 0)
+            HIP_TRY(hipMemcpyAsync(dsrc, g->src_host, (size_t)g->nnz * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        g->d_ptr = dptr;
+        g->d_src = dsrc;
+        g->bound = true;
+        g->src_host = nullptr;
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+int fsg_graph_stats(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg)
+{
+    if (!g) return fail(FSG_EINVAL, "graph is NULL");
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+    if (max_indeg) *max_indeg = g->max_indeg;
+    return FSG_OK;
+}
+
+int fsg_graph_destroy(fsg_graph *g)
+{
+    delete g;
+    return FSG_OK;
+}
+
+int fsg_default_schedule(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_schedule *out)
+{
+    if (!out) return fail(FSG_EINVAL, "out is NULL");
+    int rc = check_params(g, prm, B);
+    if (rc) return rc;
+    default_sched(g, B, out);
+    return FSG_OK;
+}
+
+int fsg_sim_workspace_size(const fsg_graph *g_, const fsg_params *prm, int64_t B,
+                           const fsg_schedule *sched, size_t *bytes)
+{
+    try {
+        if (!bytes) return fail(FSG_EINVAL, "bytes is NULL");
+        int rc = check_params(g_, prm, B);
+        if (rc) return rc;
+        fsg_graph *g = const_cast<fsg_graph *>(g_);
+        Sched s;
+        rc = resolve_sched(g, B, sched, &s);
+        if (rc) return rc;
+        const Plan &p = get_plan(g, s.heavy, s.tile_edges);
+        Layout L;
+        layout(g, prm, B, s, p, &L);
+        *bytes = L.total;
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seeds, int64_t n_seeds,
+                 int64_t B, int64_t replicate_offset, uint64_t rng_key, const fsg_schedule *sched,
+                 void *dev_ws, size_t ws_bytes, uint8_t *final_states, uint32_t *infected_counts,
+                 fsg_run_info *info, void *stream)
+{
+    try {
+        int rc = check_params(g_, prm, B);
+        if (rc) return rc;
+        fsg_graph *g = const_cast<fsg_graph *>(g_);
+        if (!g->bound) return fail(FSG_EINVAL, "graph is not bound to device memory");
+        if (replicate_offset < 0 || replicate_offset + B > ((int64_t)1 << 34))
+            return fail(FSG_EINVAL, "replicate_offset + B must lie in [0, 2^34]");
+        if (n_seeds < 0 || (n_seeds > 0 && !seeds)) return fail(FSG_EINVAL, "bad seed array");
+        for (int64_t i = 0; i < n_seeds; ++i)
+            if (seeds[i] < 0 || (int64_t)seeds[i] >= g->n)
+                return fail(FSG_EINVAL, "seed out of range at index " + std::to_string(i));
+        Sched s;
+        rc = resolve_sched(g, B, sched, &s);
+        if (rc) return rc;
+        const Plan &p = get_plan(g, s.heavy, s.tile_edges);
+        Layout L;
+        layout(g, prm, B, s, p, &L);
+        if (!dev_ws || ws_bytes < L.total) return fail(FSG_EWORKSPACE, "simulation workspace too small");
+        if (((uintptr_t)dev_ws & 255) != 0) return fail(FSG_EWORKSPACE, "workspace not 256-byte aligned");
+        hipStream_t st = (hipStream_t)stream;
+        char *base = (char *)dev_ws;
+        const int kind = model_kind(prm->model);
+        uint64_t *pl[3] = {(uint64_t *)(base + L.planes[0]), (uint64_t *)(base + L.planes[1]),
+                           L.n_planes > 2 ? (uint64_t *)(base + L.planes[2]) : nullptr};
+        // plane roles: IC {F0, F1, A}; epidemic {h0, h1, r}; LT {act0, act1}
+        uint32_t *flags = (uint32_t *)(base + L.flags);
+        const int ring = s.sync + 1;
+
+        // ---- uploads
+        std::vector<uint32_t> tinf = {0u};
+        if (kind == kKindEpidemic) tinf = infection_table(prm->beta, g->max_indeg);
+        std::vector<uint32_t> edge_t;
+        if (prm->model == FSG_IC && prm->ic_prob == FSG_IC_PER_EDGE) {
+            edge_t.resize((size_t)g->nnz);
+            for (int64_t e = 0; e < g->nnz; ++e) edge_t[(size_t)e] = threshold_of(prm->edge_p[e]);
+        }
+        auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+            if (bytes == 0) return hipSuccess;
+            return hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, st);
+        };
+        HIP_TRY(up(L.tiles, p.tiles.data(), p.tiles.size() * 4));
+        HIP_TRY(up(L.heavy_rows, p.heavy_rows.data(), p.heavy_rows.size() * 4));
+        HIP_TRY(up(L.heavy_seg, p.heavy_seg.data(), p.heavy_seg.size() * 4));
+        HIP_TRY(up(L.seg_row, p.seg_row.data(), p.seg_row.size() * 4));
+        HIP_TRY(up(L.seg_e0, p.seg_e0.data(), p.seg_e0.size() * 4));
+        HIP_TRY(up(L.seg_e1, p.seg_e1.data(), p.seg_e1.size() * 4));
+        HIP_TRY(up(L.tinf, tinf.data(), tinf.size() * 4));
+        HIP_TRY(up(L.edge_t, edge_t.data(), edge_t.size() * 4));
+
+        // ---- initial states: everything 0, seeds 1 in every replicate
+        for (int i = 0; i < L.n_planes; ++i) HIP_TRY(launch_fill64(pl[i], L.plane_words, 0ull, st));
+        HIP_TRY(launch_fill32(flags, ring, 0u, st));
+        int32_t *dseeds = (int32_t *)(base + L.seeds);
+        for (int64_t i0 = 0; i0 < n_seeds; i0 += L.n_seed_stage) {
+            const int64_t cnt = std::min<int64_t>(L.n_seed_stage, n_seeds - i0);
+            HIP_TRY(hipMemcpyAsync(dseeds, seeds + i0, (size_t)cnt * 4, hipMemcpyHostToDevice, st));
+            uint64_t *second = kind == kKindIC ? pl[2] : nullptr;  // IC: A too
+            HIP_TRY(launch_seed(pl[0], second, dseeds, cnt, (int32_t)L.W, B, flags, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+
+        // ---- step loop
+        StepArgs a;
+        memset(&a, 0, sizeof(a));
+        a.ptr = g->d_ptr;
+        a.src = g->d_src;
+        a.n = (int32_t)g->n;
+        a.W = (int32_t)L.W;
+        a.B = B;
+        a.goff = (uint64_t)replicate_offset;
+        a.key0 = (uint32_t)rng_key;
+        a.key1 = (uint32_t)(rng_key >> 32);
+        a.aux = pl[2];
+        a.model = prm->model;
+        a.ic_prob = prm->ic_prob;
+        a.ic_t = threshold_of(prm->p);
+        a.edge_t = edge_t.empty() ? nullptr : (const uint32_t *)(base + L.edge_t);
+        a.tinf = (const uint32_t *)(base + L.tinf);
+        a.khat = (int32_t)L.n_tinf - 1;
+        a.trec = prm->model == FSG_SI ? 0u : threshold_of(prm->gamma);
+        a.G = s.G;
+        a.S = s.S;
+        a.lgG = s.lgG;
+        a.lgS = s.lgS;
+        a.heavy = s.heavy;
+        a.tiles = (const int32_t *)(base + L.tiles);
+        a.n_tiles = (int32_t)p.tiles.size() - 1;
+        a.seg_row = (const int32_t *)(base + L.seg_row);
+        a.seg_e0 = (const int32_t *)(base + L.seg_e0);
+        a.seg_e1 = (const int32_t *)(base + L.seg_e1);
+        a.n_seg = (int32_t)p.seg_row.size();
+        a.heavy_rows = (const int32_t *)(base + L.heavy_rows);
+        a.heavy_seg = (const int32_t *)(base + L.heavy_seg);
+        a.n_heavy = (int32_t)p.heavy_rows.size();
+        a.partial = (uint64_t *)(base + L.partial);
+        a.Lp = L.L;
+        a.flags = flags;
+        a.ring = ring;
+
+        const int64_t K = prm->max_steps < 0 ? g->n : prm->max_steps;
+        int64_t steps_run = 0;
+        bool absorbed = n_seeds == 0;
+        std::vector<uint32_t> hflags((size_t)ring);
+        EventPool ev;
+        if (s.timed) HIP_TRY(ev.init(2 * (size_t)s.sync));
+        double kernel_ms = 0.0;
+        int64_t timed_steps = 0;
+        int64_t t = 0;
+        while (!absorbed && t < K) {
+            const int64_t c = std::min<int64_t>(s.sync, K - t);
+            HIP_TRY(launch_ring_clear(flags, ring, (int32_t)(t % ring), st));
+            for (int64_t i = 1; i <= c; ++i) {
+                const int64_t step = t + i;
+                a.step = (uint32_t)step;
+                a.prev = pl[(step - 1) & 1];
+                a.next = pl[step & 1];
+                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
+                HIP_TRY(launch_step(a, kind, L.L, s.block, st));
+                if (a.n_heavy > 0) HIP_TRY(launch_combine(a, kind, s.block, st));
+                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
+            }
+            HIP_TRY(hipMemcpyAsync(hflags.data(), flags, (size_t)ring * 4, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (s.timed) {
+                for (int64_t i = 1; i <= c; ++i) {
+                    // steps after absorption return at once; count only live ones
+                    if (i > 1 && hflags[(size_t)((t + i - 1) % ring)] == 0u) break;
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, ev.e[2 * (i - 1)], ev.e[2 * (i - 1) + 1]));
+                    kernel_ms += ms;
+                    ++timed_steps;
+                }
+            }
+            steps_run = t + c;
+            for (int64_t i = 1; i <= c; ++i)
+                if (hflags[(size_t)((t + i) % ring)] == 0u) {
+                    steps_run = t + i;
+                    absorbed = true;
+                    break;
+                }
+            t += c;
+        }
+
+        // ---- outputs
+        if (final_states || infected_counts) {
+            FinArgs f;
+            f.n = (int32_t)g->n;
+            f.W = (int32_t)L.W;
+            f.G = (int)std::min<int64_t>(next_pow2(L.W), 64);
+            f.lgG = ilog2(f.G);
+            f.B = B;
+            f.model = prm->model;
+            f.one = pl[steps_run & 1];
+            f.two = kind == kKindLT ? nullptr : pl[2];
+            if (prm->model == FSG_SIS || prm->model == FSG_SI) f.two = nullptr;
+            f.states = final_states;
+            f.counts = infected_counts;
+            HIP_TRY(launch_finalize(f, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        if (info) {
+            info->steps_run = steps_run;
+            info->absorbed = absorbed ? 1 : 0;
+            info->reserved = 0;
+            info->step_kernel_ms = kernel_ms;
+            info->step_launches = timed_steps;
+        }
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+int fsg_philox4x32_10(const uint32_t *dev_ctr, uint32_t key0, uint32_t key1, uint32_t *dev_out,
+                      int64_t count, void *stream)
+{
+    if (count < 0 || (count > 0 && (!dev_ctr || !dev_out)))
+        return fail(FSG_EINVAL, "bad philox arguments");
+    HIP_TRY(launch_philox(dev_ctr, key0, key1, dev_out, count, (hipStream_t)stream));
+    return FSG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// fsg_internal.hpp -- structures shared by the host side of libfsg and its
+// kernel launchers.  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsg {
+
+enum Kind { kKindIC = 0, kKindEpidemic = 1, kKindLT = 2 };
+enum Model { kIC = 0, kSI = 1, kSIS = 2, kSIR = 3, kLT = 4 };
+enum IcProb { kIcUniform = 0, kIcWeightedCascade = 1, kIcPerEdge = 2 };
+
+// Everything one synchronous step needs.  Planes are uint64 [n][W]:
+//   IC:       prev/next = frontier F (double-buffered), aux = ever-active A
+//   SI/SIS/SIR: prev/next = infected h (double-buffered), aux = removed r
+//   LT:       prev/next = active (double-buffered), aux unused
+struct StepArgs {
+    const int32_t *ptr;  // [n+1]
+    const int32_t *src;  // [nnz]
+    int32_t n;
+    int32_t W;            // words per node: ceil(B / 64)
+    int64_t B;
+    uint64_t goff;        // replicate_offset
+    uint32_t key0, key1;
+    const uint64_t *prev;
+    uint64_t *next;
+    uint64_t *aux;
+    int32_t model;
+    int32_t ic_prob;
+    uint32_t ic_t;          // uniform IC threshold
+    const uint32_t *edge_t; // per-edge IC thresholds [nnz] or null
+    const uint32_t *tinf;   // infection thresholds by infected-neighbour count
+    int32_t khat;           // last index of tinf
+    uint32_t trec;          // recovery threshold
+    // schedule
+    int32_t G, S, lgG, lgS; // lanes per row: G over words, S over edges
+    int32_t heavy;          // rows with more in-edges are processed as segments
+    const int32_t *tiles;   // [n_tiles + 1] row boundaries
+    int32_t n_tiles;
+    // heavy rows cut into segments
+    const int32_t *seg_row, *seg_e0, *seg_e1;
+    int32_t n_seg;
+    const int32_t *heavy_rows, *heavy_seg;  // [n_heavy], [n_heavy + 1]
+    int32_t n_heavy;
+    uint64_t *partial;      // [n_seg][Lp][W]
+    int32_t Lp;             // counter planes per partial (1 for IC)
+    // absorption flags: flags[t % ring] = 1 iff some replicate still has a
+    // state-1 node after step t
+    uint32_t *flags;
+    int32_t ring;
+    uint32_t step;
+};
+
+struct FinArgs {
+    int32_t n, W, G, lgG;
+    int64_t B;
+    int32_t model;
+    const uint64_t *one;  // state-1 plane (F, h, active)
+    const uint64_t *two;  // state-2 plane (A for IC, r for SIR) or null
+    uint8_t *states;      // [n][B] or null
+    uint32_t *counts;     // [n] or null
+};
+
+// launchers (fsg_kernels.hip); return the hipError_t of the launch
+hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
+hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
+hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s);
+hipError_t launch_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t ns, int32_t W,
+                       int64_t B, uint32_t *flag0, hipStream_t s);
+hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_t s);
+hipError_t launch_combine(const StepArgs &a, int kind, int block, hipStream_t s);
+hipError_t launch_finalize(const FinArgs &f, hipStream_t s);
+hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
+                         int64_t count, hipStream_t s);
+int counter_planes_for(int64_t max_count);  // compile-time counter width to use
+
+}  // namespace fsg

@@ -1,0 +1,593 @@
+// fsg_kernels.hip -- the synchronous pull step of batched Monte Carlo
+// propagation for gfx950 (FS_GPlib, arxiv 2603.14895, Sec. 3.1: message
+// Eq. ms, aggregation Eq. agg, update Eq. updata; batched over replicates as
+// Eq. batch).
+//
+// Work decomposition.  A row v of the pull CSR lists the sources of the arcs
+// into v.  Rows are grouped into contiguous tiles of roughly equal in-edge
+// load (the target-node partition of Sec. 3.2 applied per workgroup).  Inside
+// a wave, G * S lanes own one row: G lanes over the row's replicate words
+// (64 replicates per uint64 word, so the G lanes of a neighbour gather read
+// 8*G contiguous bytes) and S lanes over its in-edge list.  Per-lane partial
+// results are merged with order-free operations (OR for cascades, integer
+// addition of bit-sliced counters for counts), so every schedule gives the
+// same bits.  Rows with more than `heavy` in-edges are cut into segments whose
+// partial results go to a workspace and are merged by k_combine.
+//
+// No MFMA here: the step is a sparse gather plus integer/ALU work.
+#include "fsg_device.hpp"
+#include "fsg_internal.hpp"
+
+namespace fsg {
+
+// ---------------------------------------------------------------- IC ----
+// Message of arc e = (u -> v) in replicate r: u newly active at t-1 and the
+// arc's one trial fires (the trial does not depend on t, and an arc is
+// consulted only once per replicate since u is newly active only once).
+// Aggregation: OR over arcs.  Update: 0 -> 1 on any message, 1 -> 2.
+__device__ __forceinline__ void ic_row_word(const StepArgs &a, int G, int S, bool valid, int v,
+                                            int w, int e0, int e1, uint32_t tv, int s, int seg,
+                                            bool &any)
+{
+    const int64_t idx = (int64_t)v * a.W + w;
+    const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
+    const uint64_t A = valid ? a.aux[idx] : ~0ull;
+    const uint64_t cand = valid ? (~A & tail_mask(w, a.B)) : 0ull;
+    uint64_t acc = 0;
+    if (cand) {
+        for (int e = e0 + s; e < e1; e += S) {
+            const int u = a.src[e];
+            uint64_t f = a.prev[(int64_t)u * a.W + w] & cand & ~acc;
+            if (!f) continue;
+            const uint32_t te = a.edge_t ? a.edge_t[e] : tv;
+            if (te == 0u) continue;
+            while (f) {
+                const int b = __builtin_ctzll(f);
+                const uint64_t gm = block_bits(gbase, b);
+                uint64_t bits = f & gm;
+                f &= ~gm;
+                if (te == kAlways) {
+                    acc |= bits;
+                    continue;
+                }
+                const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
+                const U4 o = philox10((uint32_t)e, blk, 0u, kDomIcEdge << 24, a.key0, a.key1);
+                while (bits) {
+                    const int bb = __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    if (pick(o, (uint32_t)((gbase + (uint64_t)bb) & 3u)) < te) acc |= 1ull << bb;
+                }
+            }
+        }
+    }
+    acc = or_reduce_lanes(acc, G, S);
+    if (!valid || s != 0) return;
+    if (seg >= 0) {
+        a.partial[(int64_t)seg * a.W + w] = acc;
+    } else {
+        a.next[idx] = acc;
+        a.aux[idx] = A | acc;
+        any |= acc != 0;
+    }
+}
+
+// ------------------------------------------------------ SI / SIS / SIR ----
+// Appendix A.1: the log-survival messages of the k infected in-neighbours sum
+// to k log(1-beta), so a susceptible node is infected with probability
+// 1 - (1-beta)^k; the k-indexed thresholds come from the host.  One draw per
+// (node, replicate, step) decides whichever transition the node's state
+// allows (infection if S, recovery if I).
+template <int LC>
+__device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool valid, int v,
+                                           int w, int64_t idx, uint64_t h, uint64_t r,
+                                           uint64_t sus, const uint64_t (&c)[LC], int s, bool &any)
+{
+    const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
+    const bool draw_rec = a.trec != 0u && a.trec != kAlways;
+    uint64_t need = sus & bs_nonzero<LC>(c);
+    if (draw_rec) need |= h;
+    need &= share_bits(gbase, s, S);
+    uint64_t inf = 0, rec = 0;
+    while (need) {
+        const int b = __builtin_ctzll(need);
+        const uint64_t gm = block_bits(gbase, b);
+        uint64_t bits = need & gm;
+        need &= ~gm;
+        const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
+        const U4 o = philox10((uint32_t)v, blk, a.step, kDomNodeStep << 24, a.key0, a.key1);
+        while (bits) {
+            const int bb = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const uint32_t u = pick(o, (uint32_t)((gbase + (uint64_t)bb) & 3u));
+            const uint64_t bit = 1ull << bb;
+            if (h & bit) {
+                if (fires(u, a.trec)) rec |= bit;
+            } else {
+                uint32_t k = bs_get<LC>(c, bb);
+                if (k > (uint32_t)a.khat) k = (uint32_t)a.khat;
+                if (fires(u, a.tinf[k])) inf |= bit;
+            }
+        }
+    }
+    inf = or_reduce_lanes(inf, G, S);
+    rec = or_reduce_lanes(rec, G, S);
+    if (a.trec == kAlways) rec = h;
+    if (!valid || s != 0) return;
+    const uint64_t nh = (h & ~rec) | inf;
+    const uint64_t nr = (a.model == kSIS) ? r : (r | rec);
+    a.next[idx] = nh;
+    a.aux[idx] = nr;
+    any |= nh != 0;
+}
+
+template <int L>
+__device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bool valid, int v,
+                                             int w, int e0, int e1, int s, int seg, bool &any)
+{
+    const int64_t idx = (int64_t)v * a.W + w;
+    const uint64_t h = valid ? a.prev[idx] : 0ull;
+    const uint64_t r = valid ? a.aux[idx] : 0ull;
+    const uint64_t sus = valid ? (~(h | r) & tail_mask(w, a.B)) : 0ull;
+    uint64_t c[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) c[l] = 0;
+    if (sus) {
+        for (int e = e0 + s; e < e1; e += S) {
+            const uint64_t x = a.prev[(int64_t)a.src[e] * a.W + w] & sus;
+            if (x) bs_add1<L>(c, x);
+        }
+    }
+    bs_reduce_lanes<L>(c, G, S);
+    if (seg >= 0) {
+        if (valid && s == 0) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) a.partial[((int64_t)seg * L + l) * a.W + w] = c[l];
+        }
+        return;
+    }
+    epi_decide<L>(a, G, S, valid, v, w, idx, h, r, sus, c, s, any);
+}
+
+// ---------------------------------------------------------------- LT ----
+// In-weights 1/indeg and threshold U/2^32 drawn once per (node, replicate):
+// v activates once c active in-neighbours satisfy c >= ceil(U indeg / 2^32)
+// (and c >= 1).
+template <int LC>
+__device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool valid, int v,
+                                          int w, int64_t idx, uint64_t act, uint64_t inact,
+                                          uint32_t indeg, const uint64_t (&c)[LC], int s,
+                                          bool &any)
+{
+    const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
+    uint64_t cand = inact & bs_nonzero<LC>(c) & share_bits(gbase, s, S);
+    uint64_t nw = 0;
+    while (cand) {
+        const int b = __builtin_ctzll(cand);
+        const uint64_t gm = block_bits(gbase, b);
+        uint64_t bits = cand & gm;
+        cand &= ~gm;
+        const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
+        const U4 o = philox10((uint32_t)v, blk, 0u, kDomLtThresh << 24, a.key0, a.key1);
+        while (bits) {
+            const int bb = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const uint64_t u = pick(o, (uint32_t)((gbase + (uint64_t)bb) & 3u));
+            uint64_t need = (u * (uint64_t)indeg + 0xFFFFFFFFull) >> 32;
+            if (need < 1) need = 1;
+            if ((uint64_t)bs_get<LC>(c, bb) >= need) nw |= 1ull << bb;
+        }
+    }
+    nw = or_reduce_lanes(nw, G, S);
+    if (!valid || s != 0) return;
+    a.next[idx] = act | nw;
+    any |= nw != 0;
+}
+
+template <int L>
+__device__ __forceinline__ void lt_row_word(const StepArgs &a, int G, int S, bool valid, int v,
+                                            int w, int e0, int e1, uint32_t indeg, int s, int seg,
+                                            bool &any)
+{
+    const int64_t idx = (int64_t)v * a.W + w;
+    const uint64_t act = valid ? a.prev[idx] : 0ull;
+    const uint64_t inact = valid ? (~act & tail_mask(w, a.B)) : 0ull;
+    uint64_t c[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) c[l] = 0;
+    if (inact) {
+        for (int e = e0 + s; e < e1; e += S) {
+            const uint64_t x = a.prev[(int64_t)a.src[e] * a.W + w] & inact;
+            if (x) bs_add1<L>(c, x);
+        }
+    }
+    bs_reduce_lanes<L>(c, G, S);
+    if (seg >= 0) {
+        if (valid && s == 0) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) a.partial[((int64_t)seg * L + l) * a.W + w] = c[l];
+        }
+        return;
+    }
+    lt_decide<L>(a, G, S, valid, v, w, idx, act, inact, indeg, c, s, any);
+}
+
+__device__ __forceinline__ uint32_t wc_threshold(uint32_t indeg)
+{
+    // weighted cascade p = 1/indeg: floor(2^32 / indeg), 1 -> always
+    return indeg <= 1u ? kAlways : (uint32_t)(0x100000000ull / (uint64_t)indeg);
+}
+
+template <int KIND, int L>
+__device__ __forceinline__ void row_word(const StepArgs &a, int G, int S, bool valid, int v, int w,
+                                         int e0, int e1, uint32_t indeg, int s, int seg, bool &any)
+{
+    if (KIND == kKindIC) {
+        uint32_t tv = a.ic_t;
+        if (a.ic_prob == kIcWeightedCascade) tv = wc_threshold(indeg);
+        ic_row_word(a, G, S, valid, v, w, e0, e1, tv, s, seg, any);
+    } else if (KIND == kKindEpidemic) {
+        epi_row_word<L>(a, G, S, valid, v, w, e0, e1, s, seg, any);
+    } else {
+        lt_row_word<L>(a, G, S, valid, v, w, e0, e1, indeg, s, seg, any);
+    }
+}
+
+// One synchronous step t = a.step.  Blocks [0, n_tiles) own light tiles;
+// the rest own heavy-row segments (one per row slot).
+template <int KIND, int L>
+__global__ void __launch_bounds__(1024) k_step(StepArgs a)
+{
+    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // nothing left to change
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int G = a.G, S = a.S;
+    const int lgGS = a.lgG + a.lgS;
+    const int rpw = 64 >> lgGS;
+    const int slot = lane >> lgGS;
+    const int s = (lane >> a.lgG) & (S - 1);
+    const int gw = lane & (G - 1);
+    bool any = false;
+    const int bid = blockIdx.x;
+    if (bid < a.n_tiles) {
+        const int t0 = a.tiles[bid], t1 = a.tiles[bid + 1];
+        for (int rb = t0 + wave * rpw; rb < t1; rb += nwaves * rpw) {
+            const int v = rb + slot;
+            bool act = v < t1;
+            int e0 = 0, e1 = 0;
+            if (act) {
+                e0 = a.ptr[v];
+                e1 = a.ptr[v + 1];
+                if (e1 - e0 > a.heavy) act = false;
+            }
+            for (int w0 = 0; w0 < a.W; w0 += G) {
+                const int w = w0 + gw;
+                row_word<KIND, L>(a, G, S, act && w < a.W, v, w < a.W ? w : 0, e0, e1,
+                                  (uint32_t)(e1 - e0), s, -1, any);
+            }
+        }
+    } else {
+        const int seg = (bid - a.n_tiles) * nwaves * rpw + wave * rpw + slot;
+        const bool act = seg < a.n_seg;
+        int v = 0, e0 = 0, e1 = 0;
+        uint32_t indeg = 0;
+        if (act) {
+            v = a.seg_row[seg];
+            e0 = a.seg_e0[seg];
+            e1 = a.seg_e1[seg];
+            indeg = (uint32_t)(a.ptr[v + 1] - a.ptr[v]);
+        }
+        for (int w0 = 0; w0 < a.W; w0 += G) {
+            const int w = w0 + gw;
+            row_word<KIND, L>(a, G, S, act && w < a.W, v, w < a.W ? w : 0, e0, e1, indeg, s,
+                              act ? seg : 0, any);
+        }
+    }
+    if (__ballot(any) != 0ull && lane == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+// Merge of the segment partials of each heavy row, then the same update as
+// a light row.  G lanes per row over words, no edge split.
+template <int KIND, int LP>
+__global__ void __launch_bounds__(256) k_combine(StepArgs a)
+{
+    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
+    constexpr int LC = 32;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int G = a.G;
+    const int rpw = 64 >> a.lgG;
+    const int slot = lane >> a.lgG;
+    const int gw = lane & (G - 1);
+    const int j = (blockIdx.x * nwaves + wave) * rpw + slot;
+    const bool act = j < a.n_heavy;
+    const int v = act ? a.heavy_rows[j] : 0;
+    const int sg0 = act ? a.heavy_seg[j] : 0, sg1 = act ? a.heavy_seg[j + 1] : 0;
+    bool any = false;
+    for (int w0 = 0; w0 < a.W; w0 += G) {
+        const int w = w0 + gw;
+        const bool valid = act && w < a.W;
+        const int ww = w < a.W ? w : 0;
+        const int64_t idx = (int64_t)v * a.W + ww;
+        if (KIND == kKindIC) {
+            uint64_t acc = 0;
+            if (valid)
+                for (int sg = sg0; sg < sg1; ++sg) acc |= a.partial[(int64_t)sg * a.W + ww];
+            if (valid) {
+                const uint64_t A = a.aux[idx];
+                acc &= ~A;
+                a.next[idx] = acc;
+                a.aux[idx] = A | acc;
+                any |= acc != 0;
+            }
+        } else {
+            uint64_t c[LC];
+#pragma unroll
+            for (int l = 0; l < LC; ++l) c[l] = 0;
+            if (valid) {
+                for (int sg = sg0; sg < sg1; ++sg) {
+                    uint64_t d[LC];
+#pragma unroll
+                    for (int l = 0; l < LC; ++l)
+                        d[l] = (l < LP) ? a.partial[((int64_t)sg * LP + l) * a.W + ww] : 0ull;
+                    bs_add<LC>(c, d);
+                }
+            }
+            if (KIND == kKindEpidemic) {
+                const uint64_t h = valid ? a.prev[idx] : 0ull;
+                const uint64_t r = valid ? a.aux[idx] : 0ull;
+                const uint64_t sus = valid ? (~(h | r) & tail_mask(ww, a.B)) : 0ull;
+#pragma unroll
+                for (int l = 0; l < LC; ++l) c[l] &= sus;
+                epi_decide<LC>(a, G, 1, valid, v, ww, idx, h, r, sus, c, 0, any);
+            } else {
+                const uint64_t act_w = valid ? a.prev[idx] : 0ull;
+                const uint64_t inact = valid ? (~act_w & tail_mask(ww, a.B)) : 0ull;
+#pragma unroll
+                for (int l = 0; l < LC; ++l) c[l] &= inact;
+                const uint32_t indeg = act ? (uint32_t)(a.ptr[v + 1] - a.ptr[v]) : 0u;
+                lt_decide<LC>(a, G, 1, valid, v, ww, idx, act_w, inact, indeg, c, 0, any);
+            }
+        }
+    }
+    if (__ballot(any) != 0ull && lane == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+// ------------------------------------------------------- init / output ----
+
+__global__ void k_fill64(uint64_t *p, int64_t count, uint64_t value)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_fill32(uint32_t *p, int64_t count, uint32_t value)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// Clears every absorption flag of the ring except slot `keep` (the step
+// before the next chunk).
+__global__ void k_ring_clear(uint32_t *flags, int32_t ring, int32_t keep)
+{
+    for (int i = threadIdx.x; i < ring; i += blockDim.x)
+        if (i != keep) flags[i] = 0u;
+}
+
+// Seeds are in state 1 in every replicate (Algorithm 1, initial states).
+__global__ void k_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t ns, int32_t W,
+                       int64_t B, uint32_t *flag0)
+{
+    const int64_t total = ns * W;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = i / W;
+        const int w = (int)(i - k * W);
+        const int64_t idx = (int64_t)seeds[k] * W + w;
+        const uint64_t m = tail_mask(w, B);
+        p1[idx] = m;
+        if (p2) p2[idx] = m;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ns > 0) flag0[0] = 1u;
+}
+
+// Packed planes -> uint8 states [n][B] and per-node counts.
+__global__ void __launch_bounds__(256) k_finalize(FinArgs f)
+{
+    const int lane = threadIdx.x & 63;
+    const int G = f.G;
+    const int rpw = 64 >> f.lgG;
+    const int gw = lane & (G - 1);
+    const int64_t gwave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave_total = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t rb = gwave * rpw; rb < f.n; rb += nwave_total * rpw) {
+        const int64_t v = rb + (lane >> f.lgG);
+        const bool act = v < f.n;
+        uint32_t cnt = 0;
+        for (int w0 = 0; w0 < f.W; w0 += G) {
+            const int w = w0 + gw;
+            if (!act || w >= f.W) continue;
+            const int64_t idx = v * f.W + w;
+            const uint64_t tail = tail_mask(w, f.B);
+            const uint64_t one = f.one[idx] & tail;
+            const uint64_t two = f.two ? (f.two[idx] & tail) : 0ull;
+            cnt += (uint32_t)__popcll(f.model == kSIS ? one : (one | two));
+            if (!f.states) continue;
+            uint8_t *dst = f.states + v * f.B + 64ll * w;
+            const int64_t nb = f.B - 64ll * w < 64 ? f.B - 64ll * w : 64;
+            if (nb == 64 && (f.B & 15) == 0) {
+                uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t wd[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        uint32_t x = 0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int bit = q * 16 + k * 4 + j;
+                            const uint32_t s1 = (uint32_t)(one >> bit) & 1u;
+                            const uint32_t s2 = (uint32_t)(two >> bit) & 1u;
+                            x |= (s1 | ((s2 & ~s1) << 1)) << (8 * j);
+                        }
+                        wd[k] = x;
+                    }
+                    d4[q] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+                }
+            } else {
+                for (int j = 0; j < nb; ++j) {
+                    const uint32_t s1 = (uint32_t)(one >> j) & 1u;
+                    const uint32_t s2 = (uint32_t)(two >> j) & 1u;
+                    dst[j] = (uint8_t)(s1 | ((s2 & ~s1) << 1));
+                }
+            }
+        }
+        for (int off = 1; off < G; off <<= 1) cnt += __shfl_xor(cnt, off, 64);
+        if (act && gw == 0 && f.counts) f.counts[v] = cnt;
+    }
+}
+
+__global__ void k_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
+                         int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const U4 o = philox10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+        out[4 * i] = o.x;
+        out[4 * i + 1] = o.y;
+        out[4 * i + 2] = o.z;
+        out[4 * i + 3] = o.w;
+    }
+}
+
+// ------------------------------------------------------------ launchers ----
+
+static unsigned grid_for(int64_t work, int block)
+{
+    int64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill64, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill32, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ring_clear, dim3(1), dim3(256), 0, s, flags, ring, keep);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t ns, int32_t W,
+                       int64_t B, uint32_t *flag0, hipStream_t s)
+{
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seed, dim3(grid_for(ns * W, 256)), dim3(256), 0, s, p1, p2, seeds, ns, W,
+                       B, flag0);
+    return hipGetLastError();
+}
+
+int counter_planes_for(int64_t max_count)
+{
+    int bits = 1;
+    while (bits < 32 && (max_count >> bits) != 0) ++bits;
+    if (bits <= 2) return 2;
+    if (bits <= 4) return 4;
+    if (bits <= 8) return 8;
+    if (bits <= 12) return 12;
+    return 16;
+}
+
+template <int KIND>
+static hipError_t step_kind(const StepArgs &a, int L, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (KIND == kKindIC) {
+        hipLaunchKernelGGL((k_step<KIND, 1>), grid, block, 0, s, a);
+        return hipGetLastError();
+    }
+    switch (L) {
+    case 2: hipLaunchKernelGGL((k_step<KIND, 2>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_step<KIND, 4>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_step<KIND, 8>), grid, block, 0, s, a); break;
+    case 12: hipLaunchKernelGGL((k_step<KIND, 12>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_step<KIND, 16>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_t s)
+{
+    const int rows_per_block = (block / 64) * (64 >> (a.lgG + a.lgS));
+    const int seg_blocks = (a.n_seg + rows_per_block - 1) / rows_per_block;
+    const int64_t nblocks = (int64_t)a.n_tiles + seg_blocks;
+    if (nblocks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nblocks), blk((unsigned)block);
+    if (kind == kKindIC) return step_kind<kKindIC>(a, 1, grid, blk, s);
+    if (kind == kKindEpidemic) return step_kind<kKindEpidemic>(a, L, grid, blk, s);
+    return step_kind<kKindLT>(a, L, grid, blk, s);
+}
+
+hipError_t launch_combine(const StepArgs &a, int kind, int /*block*/, hipStream_t s)
+{
+    if (a.n_heavy <= 0) return hipSuccess;
+    const int rows_per_block = 4 * (64 >> a.lgG);
+    const dim3 grid((unsigned)((a.n_heavy + rows_per_block - 1) / rows_per_block)), blk(256);
+    if (kind == kKindIC) {
+        hipLaunchKernelGGL((k_combine<kKindIC, 1>), grid, blk, 0, s, a);
+        return hipGetLastError();
+    }
+#define FSG_COMBINE(K)                                                              \
+    switch (a.Lp) {                                                                 \
+    case 2: hipLaunchKernelGGL((k_combine<K, 2>), grid, blk, 0, s, a); break;       \
+    case 4: hipLaunchKernelGGL((k_combine<K, 4>), grid, blk, 0, s, a); break;       \
+    case 8: hipLaunchKernelGGL((k_combine<K, 8>), grid, blk, 0, s, a); break;       \
+    case 12: hipLaunchKernelGGL((k_combine<K, 12>), grid, blk, 0, s, a); break;     \
+    case 16: hipLaunchKernelGGL((k_combine<K, 16>), grid, blk, 0, s, a); break;     \
+    default: return hipErrorInvalidValue;                                           \
+    }
+    if (kind == kKindEpidemic) {
+        FSG_COMBINE(kKindEpidemic)
+    } else {
+        FSG_COMBINE(kKindLT)
+    }
+#undef FSG_COMBINE
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinArgs &f, hipStream_t s)
+{
+    const int64_t waves = ((int64_t)f.n * f.G + 63) / 64;
+    int64_t blocks = (waves + 3) / 4;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
+                         int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox, dim3(grid_for(count, 256)), dim3(256), 0, s, ctr, k0, k1, out,
+                       count);
+    return hipGetLastError();
+}
+
+}  // namespace fsg

@@ -1,0 +1,285 @@
+"""Python binding of libfsg (declarations in include/fsg.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library.  PyTorch supplies device memory (workspaces and outputs) and the
+stream.  If the shared library is missing this module raises on import of the
+library -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsg.so")
+
+FSG_OK, FSG_EINVAL, FSG_ENOMEM, FSG_EDEVICE, FSG_EUNSUPPORTED, FSG_EWORKSPACE = 0, -1, -2, -3, -4, -5
+FSG_IC, FSG_SI, FSG_SIS, FSG_SIR, FSG_LT = 0, 1, 2, 3, 4
+FSG_IC_UNIFORM, FSG_IC_WEIGHTED_CASCADE, FSG_IC_PER_EDGE = 0, 1, 2
+MODELS = {"ic": FSG_IC, "si": FSG_SI, "sis": FSG_SIS, "sir": FSG_SIR, "lt": FSG_LT}
+IC_PROBS = {"uniform": FSG_IC_UNIFORM, "weighted_cascade": FSG_IC_WEIGHTED_CASCADE,
+            "per_edge": FSG_IC_PER_EDGE}
+
+
+class FsgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfsg error {code}: {msg}")
+        self.code = code
+
+
+class fsg_params(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("ic_prob", ctypes.c_int32), ("p", ctypes.c_double),
+                ("edge_p", ctypes.c_void_p), ("beta", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+
+
+class fsg_run_info(ctypes.Structure):
+    _fields_ = [("steps_run", ctypes.c_int64), ("absorbed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("step_kernel_ms", ctypes.c_double),
+                ("step_launches", ctypes.c_int64)]
+
+
+class fsg_schedule(ctypes.Structure):
+    _fields_ = [("row_lanes", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("tile_edges", ctypes.c_int32), ("heavy_threshold", ctypes.c_int32),
+                ("steps_per_sync", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+_VP, _I64, _I32, _U32, _U64, _SZ = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t)
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "fsg_abi_version": (ctypes.c_int, []),
+    "fsg_last_error": (ctypes.c_char_p, []),
+    "fsg_graph_create": (ctypes.c_int, [_I64, _I64, _VP, _VP, ctypes.POINTER(_VP)]),
+    "fsg_graph_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
+    "fsg_graph_bind": (ctypes.c_int, [_VP, _VP, _SZ, _VP]),
+    "fsg_graph_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                       ctypes.POINTER(_I64)]),
+    "fsg_graph_destroy": (ctypes.c_int, [_VP]),
+    "fsg_default_schedule": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _I64,
+                                            ctypes.POINTER(fsg_schedule)]),
+    "fsg_sim_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _I64,
+                                              ctypes.POINTER(fsg_schedule), ctypes.POINTER(_SZ)]),
+    "fsg_simulate": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _I64, _U64,
+                                    ctypes.POINTER(fsg_schedule), _VP, _SZ, _VP, _VP,
+                                    ctypes.POINTER(fsg_run_info), _VP]),
+    "fsg_philox4x32_10": (ctypes.c_int, [_VP, _U32, _U32, _VP, _I64, _VP]),
+    "fsg_plan_row_tiles": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I64, _VP, ctypes.POINTER(_I64)]),
+}
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def lib():
+    """Load libfsg.so (built in-tree by paper_2603_14895_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2603_14895_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != FSG_OK:
+        raise FsgError(rc, lib().fsg_last_error().decode())
+
+
+# ---------------------------------------------------------------- raw calls --
+
+def fsg_abi_version() -> int:
+    return lib().fsg_abi_version()
+
+
+def fsg_last_error() -> str:
+    return lib().fsg_last_error().decode()
+
+
+def fsg_graph_create(n, nnz, in_ptr_addr, in_src_addr) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().fsg_graph_create(n, nnz, in_ptr_addr, in_src_addr, ctypes.byref(h)))
+    return h.value
+
+
+def fsg_graph_workspace_size(g) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().fsg_graph_workspace_size(g, ctypes.byref(b)))
+    return b.value
+
+
+def fsg_graph_bind(g, dev_ws, ws_bytes, stream=None):
+    _check(lib().fsg_graph_bind(g, dev_ws, ws_bytes, stream))
+
+
+def fsg_graph_stats(g):
+    n, nnz, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fsg_graph_stats(g, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(d)))
+    return n.value, nnz.value, d.value
+
+
+def fsg_graph_destroy(g):
+    _check(lib().fsg_graph_destroy(g))
+
+
+def fsg_default_schedule(g, prm: fsg_params, B) -> fsg_schedule:
+    s = fsg_schedule()
+    _check(lib().fsg_default_schedule(g, ctypes.byref(prm), B, ctypes.byref(s)))
+    return s
+
+
+def fsg_sim_workspace_size(g, prm: fsg_params, B, sched: Optional[fsg_schedule]) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().fsg_sim_workspace_size(g, ctypes.byref(prm), B,
+                                        ctypes.byref(sched) if sched is not None else None,
+                                        ctypes.byref(b)))
+    return b.value
+
+
+def fsg_simulate(g, prm, seeds_addr, n_seeds, B, replicate_offset, rng_key, sched, dev_ws,
+                 ws_bytes, states_addr, counts_addr, stream=None) -> fsg_run_info:
+    info = fsg_run_info()
+    _check(lib().fsg_simulate(g, ctypes.byref(prm), seeds_addr, n_seeds, B, replicate_offset,
+                              rng_key & (2**64 - 1),
+                              ctypes.byref(sched) if sched is not None else None,
+                              dev_ws, ws_bytes, states_addr, counts_addr, ctypes.byref(info),
+                              stream))
+    return info
+
+
+def fsg_philox4x32_10(dev_ctr, key0, key1, dev_out, count, stream=None):
+    _check(lib().fsg_philox4x32_10(dev_ctr, key0, key1, dev_out, count, stream))
+
+
+def fsg_plan_row_tiles(in_ptr: np.ndarray, heavy: int, row_cost: int, n_parts: int) -> np.ndarray:
+    in_ptr = np.ascontiguousarray(in_ptr, dtype=np.int64)
+    n = in_ptr.size - 1
+    out = np.empty(n + 2, dtype=np.int64)
+    cnt = ctypes.c_int64()
+    _check(lib().fsg_plan_row_tiles(in_ptr.ctypes.data, n, heavy, row_cost, n_parts,
+                                    out.ctypes.data, ctypes.byref(cnt)))
+    return out[: cnt.value + 1].copy()
+
+
+# ---------------------------------------------------- torch-backed helpers --
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ws(nbytes: int, device):
+    import torch
+    # +256 so the workspace can be aligned to 256 bytes
+    t = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    addr = t.data_ptr()
+    return t, (addr + 255) & ~255
+
+
+def make_params(model, *, p=0.0, ic_prob="uniform", edge_p=None, beta=0.0, gamma=0.0,
+                max_steps=-1):
+    prm = fsg_params()
+    prm.model = MODELS[model] if isinstance(model, str) else int(model)
+    prm.ic_prob = IC_PROBS[ic_prob] if isinstance(ic_prob, str) else int(ic_prob)
+    prm.p = float(p)
+    prm.beta = float(beta)
+    prm.gamma = float(gamma)
+    prm.max_steps = int(max_steps)
+    keep = None
+    if edge_p is not None:
+        keep = np.ascontiguousarray(edge_p, dtype=np.float64)
+        prm.edge_p = keep.ctypes.data
+    return prm, keep
+
+
+def make_schedule(d: Optional[dict]) -> Optional[fsg_schedule]:
+    if d is None:
+        return None
+    s = fsg_schedule()
+    for k, v in d.items():
+        setattr(s, k, int(v))
+    return s
+
+
+class DeviceGraph:
+    """A graph bound to device memory owned by a torch tensor."""
+
+    def __init__(self, ptr, src, device="cuda"):
+        ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        self.n = ptr.size - 1
+        self.nnz = src.size
+        self.handle = fsg_graph_create(self.n, self.nnz, ptr.ctypes.data,
+                                       src.ctypes.data if src.size else None)
+        nbytes = fsg_graph_workspace_size(self.handle)
+        self._ws, addr = _ws(nbytes, device)
+        fsg_graph_bind(self.handle, addr, nbytes, _stream_ptr())
+        self.device = device
+
+    def stats(self):
+        return fsg_graph_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            fsg_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Simulation:
+    """Workspace and outputs for repeated fsg_simulate calls on one graph."""
+
+    def __init__(self, graph: DeviceGraph, model, B: int, schedule: Optional[dict] = None,
+                 want_states: bool = True, want_counts: bool = True, **params):
+        import torch
+        self.graph = graph
+        self.B = int(B)
+        self.prm, self._keep = make_params(model, **params)
+        self.sched = make_schedule(schedule)
+        self.ws_bytes = fsg_sim_workspace_size(graph.handle, self.prm, self.B, self.sched)
+        self._ws, self.ws_addr = _ws(self.ws_bytes, graph.device)
+        self.states = (torch.empty((graph.n, self.B), dtype=torch.uint8, device=graph.device)
+                       if want_states else None)
+        self.counts = (torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+                       if want_counts else None)
+
+    def run(self, seeds, rng_key: int, replicate_offset: int = 0, stream=None) -> fsg_run_info:
+        seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        return fsg_simulate(self.graph.handle, self.prm, seeds.ctypes.data if seeds.size else None,
+                            seeds.size, self.B, int(replicate_offset), int(rng_key), self.sched,
+                            self.ws_addr, self.ws_bytes,
+                            self.states.data_ptr() if self.states is not None else None,
+                            self.counts.data_ptr() if self.counts is not None else None,
+                            _stream_ptr(stream))
+
+
+def simulate(graph: DeviceGraph, model, seeds, B, rng_key, *, replicate_offset=0, schedule=None,
+             want_states=True, **params):
+    """One call: returns (states [n,B] uint8 cuda tensor or None, counts [n] int32 tensor,
+    steps_run, absorbed)."""
+    sim = Simulation(graph, model, B, schedule=schedule, want_states=want_states, **params)
+    info = sim.run(seeds, rng_key, replicate_offset)
+    return sim.states, sim.counts, int(info.steps_run), int(info.absorbed)

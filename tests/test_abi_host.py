@@ -1,0 +1,125 @@
+"""Host-side tests of the C-ABI (no GPU needed): the library loads, exports
+every symbol the header declares, validates its arguments before touching the
+device, and its row-tile planner keeps the load-balance bound of the paper's
+target-node partition (Sec. 3.2, Proposition "Load Balance Guarantee")."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2603_14895_amd import fsg
+from paper_2603_14895_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsg.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(fsg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported():
+    lib = fsg.lib()
+    names = _declared()
+    assert "fsg_simulate" in names and "fsg_graph_create" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding wraps every declared call
+    assert set(names) <= set(fsg.exported_names())
+    assert fsg.fsg_abi_version() == 1
+
+
+def _graph(n=50, seed=1):
+    gr = W.chung_lu(n, 4.0, 2.5, seed)
+    return gr.numpy()
+
+
+def test_graph_create_validation():
+    ptr, src = _graph()
+    n, nnz = ptr.size - 1, src.size
+    h = fsg.fsg_graph_create(n, nnz, ptr.ctypes.data, src.ctypes.data)
+    assert fsg.fsg_graph_stats(h)[:2] == (n, nnz)
+    fsg.fsg_graph_destroy(h)
+    bad_src = src.copy()
+    bad_src[3] = n
+    with pytest.raises(fsg.FsgError) as e:
+        fsg.fsg_graph_create(n, nnz, ptr.ctypes.data, bad_src.ctypes.data)
+    assert e.value.code == fsg.FSG_EINVAL and "out of range" in str(e.value)
+    bad_ptr = ptr.copy()
+    bad_ptr[5], bad_ptr[6] = bad_ptr[6], bad_ptr[5] - 1
+    with pytest.raises(fsg.FsgError):
+        fsg.fsg_graph_create(n, nnz, bad_ptr.ctypes.data, src.ctypes.data)
+    with pytest.raises(fsg.FsgError) as e:
+        fsg.fsg_graph_create(0, 0, ptr.ctypes.data, None)
+    assert e.value.code == fsg.FSG_EINVAL
+    with pytest.raises(fsg.FsgError) as e:
+        fsg.fsg_graph_create(n, nnz + 1, ptr.ctypes.data, src.ctypes.data)
+    assert e.value.code == fsg.FSG_EINVAL
+    with pytest.raises(fsg.FsgError) as e:
+        fsg.fsg_graph_create(n, 2**31, ptr.ctypes.data, src.ctypes.data)
+    assert e.value.code == fsg.FSG_EUNSUPPORTED
+
+
+def test_params_validation_before_any_launch():
+    ptr, src = _graph()
+    n, nnz = ptr.size - 1, src.size
+    h = fsg.fsg_graph_create(n, nnz, ptr.ctypes.data, src.ctypes.data)
+    try:
+        cases = [
+            (dict(model="sir", beta=0.1, gamma=0.1, max_steps=-1), 10, fsg.FSG_EINVAL),
+            (dict(model="sir", beta=float("nan"), gamma=0.1, max_steps=5), 10, fsg.FSG_EINVAL),
+            (dict(model="sis", beta=0.1, gamma=1.5, max_steps=5), 10, fsg.FSG_EINVAL),
+            (dict(model="ic", p=-0.1), 10, fsg.FSG_EINVAL),
+            (dict(model="ic", p=0.1), 0, fsg.FSG_EINVAL),
+            (dict(model="ic", ic_prob="per_edge"), 10, fsg.FSG_EINVAL),
+        ]
+        for kw, B, code in cases:
+            prm, _ = fsg.make_params(**kw)
+            with pytest.raises(fsg.FsgError) as e:
+                fsg.fsg_sim_workspace_size(h, prm, B, None)
+            assert e.value.code == code, kw
+        prm, _ = fsg.make_params("ic", ic_prob="per_edge", edge_p=np.full(nnz, 2.0))
+        with pytest.raises(fsg.FsgError):
+            fsg.fsg_sim_workspace_size(h, prm, 10, None)
+        # bad schedules
+        prm, _ = fsg.make_params("ic", p=0.1)
+        for sd in [dict(row_lanes=3), dict(block_threads=96), dict(heavy_threshold=70000),
+                   dict(steps_per_sync=-2)]:
+            with pytest.raises(fsg.FsgError):
+                fsg.fsg_sim_workspace_size(h, prm, 10, fsg.make_schedule(sd))
+        ws = fsg.fsg_sim_workspace_size(h, prm, 100, None)
+        assert ws > 0 and ws % 256 == 0
+        # an unbound graph, bad seeds and small workspaces are refused on the host
+        seeds = np.array([1, 2], dtype=np.int32)
+        with pytest.raises(fsg.FsgError) as e:
+            fsg.fsg_simulate(h, prm, seeds.ctypes.data, 2, 100, 0, 1, None, None, 0, None, None)
+        assert e.value.code == fsg.FSG_EINVAL and "bound" in str(e.value)
+    finally:
+        fsg.fsg_graph_destroy(h)
+
+
+@pytest.mark.parametrize("heavy", [10**9, 40])
+@pytest.mark.parametrize("parts", [1, 3, 17, 64, 500])
+def test_row_tiles_load_balance_bound(heavy, parts):
+    """Every part's load is within w_max of the ideal W/d, parts are
+    contiguous, non-empty and cover all rows."""
+    gr = W.chung_lu(3000, 12.0, 2.5, 5)
+    ptr, _ = gr.numpy()
+    row_cost = 4
+    b = fsg.fsg_plan_row_tiles(ptr, heavy, row_cost, parts)
+    d = np.diff(ptr)
+    w = np.where(d > heavy, 0, d) + row_cost
+    assert b[0] == 0 and b[-1] == gr.n and (np.diff(b) > 0).all()
+    assert len(b) - 1 <= parts
+    loads = np.array([w[b[i]:b[i + 1]].sum() for i in range(len(b) - 1)])
+    total, wmax = w.sum(), w.max()
+    if len(loads) == parts:
+        assert (np.abs(loads - total / parts) < wmax).all()
+    else:
+        # parts that would be empty are dropped; each load still stays below
+        # the ideal plus one row
+        assert (loads < total / parts + wmax).all()
+    assert loads.sum() == total

@@ -1,0 +1,169 @@
+"""Parity of the HIP path with the CPU oracle, bit for bit: final states,
+per-node counts, steps run and absorption, on the same seeded inputs.
+
+Sizes are chosen so the oracle finishes in seconds while spanning many tiles,
+heavy-row segments and ragged replicate tails; the full-size SIR workload is
+checked on replicates the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_14895_amd import workloads as W
+from tests.gpu_util import assert_same, gpu_run, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_14895_amd import fsg
+    fsg.lib()
+
+
+def _both(gnp, model, seeds, B, key, what, **kw):
+    log(f"[parity] {what} model={model} B={B} kw={ {k: v for k, v in kw.items() if k != 'edge_p'} }")
+    g = gpu_run(gnp, model, seeds, B, key, **kw)
+    kw.pop("schedule", None)
+    r = oracle_run(gnp, model, seeds, B, key, **kw)
+    assert_same(g, r, what)
+    return g
+
+
+def test_device_philox_matches_kat_and_oracle():
+    import torch
+    from paper_2603_14895_amd import fsg
+    kat = [([0, 0, 0, 0], [0, 0]), ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2),
+           ([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0])]
+    for ctr, key in kat:
+        c = torch.tensor(np.array(ctr, dtype=np.uint32).view(np.int32), device="cuda")
+        o = torch.empty(4, dtype=torch.int32, device="cuda")
+        fsg.fsg_philox4x32_10(c.data_ptr(), key[0], key[1], o.data_ptr(), 1)
+        torch.cuda.synchronize()
+        assert list(o.cpu().numpy().view(np.uint32)) == oracle.philox4x32_10(ctr, key)
+    rng = np.random.default_rng(5)
+    ctr = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    c = torch.tensor(ctr.view(np.int32).ravel(), device="cuda")
+    o = torch.empty(4096 * 4, dtype=torch.int32, device="cuda")
+    fsg.fsg_philox4x32_10(c.data_ptr(), 0x1234, 0xABCD, o.data_ptr(), 4096)
+    torch.cuda.synchronize()
+    got = o.cpu().numpy().view(np.uint32).reshape(-1, 4)
+    for i in range(0, 4096, 97):
+        assert list(got[i]) == oracle.philox4x32_10(list(ctr[i]), [0x1234, 0xABCD])
+
+
+def test_c1_ic_erdos_renyi_full():
+    c = W.config_c1()
+    gnp = c["graph"].numpy()
+    _both(gnp, "ic", c["seeds"], c["B"], c["rng_key"], "c1", p=c["p"], max_steps=-1)
+
+
+@pytest.mark.parametrize("ic_prob", ["uniform", "weighted_cascade", "per_edge"])
+@pytest.mark.parametrize("B,offset", [(64, 0), (130, 3), (1, 7)])
+def test_ic_variants(ic_prob, B, offset):
+    gr = W.chung_lu(6000, 8.0, 2.5, 31)
+    gnp = gr.numpy()
+    ep = np.random.default_rng(4).uniform(0.0, 0.4, size=gr.nnz) if ic_prob == "per_edge" else None
+    seeds = W.uniform_seeds(gr.n, 20, 32)
+    _both(gnp, "ic", seeds, B, 0x1CE0 + B, f"ic-{ic_prob}", p=0.12, ic_prob=ic_prob, edge_p=ep,
+          replicate_offset=offset, max_steps=-1)
+
+
+@pytest.mark.parametrize("model", ["sir", "sis", "si"])
+@pytest.mark.parametrize("B", [1024, 100])
+def test_epidemics(model, B):
+    gr = W.chung_lu(3000, 20.0, 2.5, 41)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 30, 42)
+    _both(gnp, model, seeds, B, 0x5125 + B, model, beta=0.02, gamma=0.1, max_steps=40,
+          replicate_offset=2 if B == 100 else 0)
+
+
+@pytest.mark.parametrize("B", [200, 64])
+def test_lt(B):
+    gr = W.chung_lu(5000, 10.0, 2.5, 51)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 50, 52)
+    _both(gnp, "lt", seeds, B, 0x17 + B, "lt", max_steps=-1, replicate_offset=1)
+
+
+@pytest.mark.parametrize("model", ["ic", "sir", "lt", "sis"])
+@pytest.mark.parametrize("sched", [
+    dict(row_lanes=1, block_threads=64, tile_edges=64, heavy_threshold=16),
+    dict(row_lanes=4, block_threads=1024, tile_edges=100000, heavy_threshold=40),
+    dict(row_lanes=64, block_threads=128, tile_edges=500, heavy_threshold=7, steps_per_sync=1),
+    dict(row_lanes=16, block_threads=512, tile_edges=3000, heavy_threshold=65535, steps_per_sync=64),
+])
+def test_schedules_and_heavy_rows(model, sched):
+    """Every schedule -- lanes per row, block size, tile size, heavy-row cut
+    (forcing many segments), host sync cadence -- gives identical bits."""
+    gr = W.chung_lu(2500, 15.0, 2.5, 61)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 10, 62)
+    K = -1 if model in ("ic", "lt") else 25
+    _both(gnp, model, seeds, 300, 0xAB, f"sched-{sched}", p=0.1, beta=0.05, gamma=0.2,
+          max_steps=K, schedule=sched, replicate_offset=9)
+
+
+def test_edge_cases():
+    # self-loops, repeated arcs, isolated nodes, an in-star hub
+    edges = [(0, 1), (0, 1), (1, 1), (1, 2), (2, 3), (3, 1), (5, 5)] + [(i, 6) for i in range(7, 40)]
+    gr = W.from_edges(45, edges)
+    gnp = gr.numpy()
+    for model in ["ic", "sir", "si", "sis", "lt"]:
+        for seeds, K in [([0, 7, 8, 0], 12), ([], 12), ([0, 3], 0), ([44], 5)]:
+            for B in (1, 63, 65, 128):
+                kw = dict(p=0.5, beta=0.4, gamma=0.3, max_steps=K)
+                if model in ("ic", "lt") and K == 12:
+                    kw["max_steps"] = -1
+                _both(gnp, model, np.array(seeds, dtype=np.int32), B, 99 + B, f"edge-{model}",
+                      **kw)
+    # single node, no arcs
+    gnp = W.from_edges(1, []).numpy()
+    for model in ["ic", "sir", "lt"]:
+        _both(gnp, model, np.array([0], dtype=np.int32), 70, 5, "n1", p=1.0, beta=1.0,
+              gamma=1.0, max_steps=3 if model == "sir" else -1)
+    # p = 1 and beta = 1 (the "always" sentinel), gamma = 1
+    gr = W.chung_lu(500, 6.0, 2.5, 71)
+    gnp = gr.numpy()
+    _both(gnp, "ic", np.array([3], dtype=np.int32), 77, 1, "p1", p=1.0, max_steps=-1)
+    _both(gnp, "sir", np.array([3], dtype=np.int32), 77, 2, "beta1", beta=1.0, gamma=1.0,
+          max_steps=20)
+
+
+def test_replicate_split_and_repeat_invariance():
+    """Splitting a batch with replicate_offset and repeating a run change
+    nothing (counter-based draws keyed by the global replicate index)."""
+    gr = W.chung_lu(4000, 12.0, 2.5, 81)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 40, 82)
+    kw = dict(beta=0.03, gamma=0.1, max_steps=50)
+    full = gpu_run(gnp, "sir", seeds, 256, 0xFEED, **kw)
+    a = gpu_run(gnp, "sir", seeds, 101, 0xFEED, **kw)
+    b = gpu_run(gnp, "sir", seeds, 155, 0xFEED, replicate_offset=101, **kw)
+    assert (np.concatenate([a[0], b[0]], axis=1) == full[0]).all()
+    again = gpu_run(gnp, "sir", seeds, 256, 0xFEED, schedule=dict(row_lanes=8), **kw)
+    assert (again[0] == full[0]).all() and (again[1] == full[1]).all()
+
+
+def test_c2_full_size_sampled_replicates():
+    """The SIR workload at full size (Chung-Lu n = 10^6, mean degree 20,
+    B = 1024, 200 steps) in the default schedule: replicates the oracle
+    computes one by one, including ones whose generator block straddles a
+    word boundary, match bit for bit; counts equal the states' tallies."""
+    c = W.config_c2()
+    gr = c["graph"]
+    gnp = gr.numpy()
+    log(f"[parity] c2 full n={gr.n} nnz={gr.nnz}")
+    st, cnt, steps, absorbed = gpu_run(gnp, "sir", c["seeds"], c["B"], c["rng_key"],
+                                       beta=c["beta"], gamma=c["gamma"], max_steps=c["max_steps"])
+    assert (((st == 1) | (st == 2)).sum(axis=1) == cnt).all()
+    for r0 in (0, 61, 1021):
+        rs, _, _, _ = oracle_run(gnp, "sir", c["seeds"], 3, c["rng_key"], replicate_offset=r0,
+                                 beta=c["beta"], gamma=c["gamma"], max_steps=c["max_steps"],
+                                 want_states=True)
+        assert (st[:, r0:r0 + 3] == rs).all(), r0
+    log(f"[parity] c2 steps={steps} absorbed={absorbed} attack={(cnt.sum() / (gr.n * c['B'])):.4f}")
