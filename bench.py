@@ -31,11 +31,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_step(model: str, n: int, nnz: int, B: int) -> float:
-    """Bytes one pull step must move if every array is touched once per use:
-    sources 4 B/arc, row pointers 4 B/row, the gathered neighbour word group
-    8 W B/arc, and the node's own planes (IC: read A, write A and F;
-    SIR-family: read h, r, write h, r; LT: read and write the active plane)."""
+def algorithmic_bytes_per_step(model: str, n: int, nnz: int, B: int, edge_parallel: bool) -> float:
+    """Bytes one pull step must move if every array is touched once per use.
+
+    Row-group kernel: sources 4 B/arc, row pointers 4 B/row, the gathered
+    neighbour word group 8 W B/arc, and the node's own planes (IC: read A,
+    write A and F; SIR-family: read h, r, write h, r; LT: read and write the
+    active plane).
+    Edge-parallel IC kernel (B <= 64): sources 4 B/arc, row pointers 4 B/row
+    and one read of the N-bit frontier bitmap; the frontier words of the few
+    frontier arcs and the rows that change are not counted."""
+    if edge_parallel:
+        return 4.0 * nnz + 4.0 * (n + 1) + n / 8.0
     W = (B + 63) // 64
     own = {"ic": 24, "lt": 16}.get(model, 32) * W
     return 4.0 * nnz + 8.0 * W * nnz + 4.0 * (n + 1) + own * n
@@ -63,31 +70,37 @@ def params_of(c):
 
 
 def cpu_baseline(c, ptr, src, target_seconds: float):
-    """The oracle as it stands on a bounded sample of the same workload:
-    `threads` replicates (one per host thread), same graph, seeds, key and
-    step cap.  Rate in replicate-edge updates per second."""
+    """The oracle as it stands on a bounded sample of the same workload: a
+    subset of the replicates (a multiple of the host thread count, sized to
+    roughly `target_seconds`), same graph, seeds, key and step cap.  Rate in
+    replicate-edge updates per second."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    R = threads
-    t0 = time.perf_counter()
-    kw = params_of(c)
-    okw = dict(kw)
+    okw = dict(params_of(c))
     if "ic_prob" in okw:
         from paper_2603_14895_amd import fsg
         okw["ic_prob"] = fsg.IC_PROBS[okw["ic_prob"]]
-    if c["model"] == "ic" and ptr.size > 50_000_000:
-        # the plain loop nest is far too slow at web scale: the live-edge BFS
-        # oracle computes the same final states
-        _, _, _, steps, _ = oracle.ic_live_edge(ptr, src, c["seeds"], R, c["rng_key"],
-                                                want_states=False, nthreads=threads, **okw)
-        kind = "oracle-live-edge-bfs"
-    else:
-        _, _, steps, _ = oracle.simulate(c["model"], ptr, src, c["seeds"], R, c["rng_key"],
-                                         want_states=False, nthreads=threads, **okw)
-        kind = "oracle"
-    dt = time.perf_counter() - t0
-    nnz = src.size
-    rate = nnz * R * steps / dt
+
+    def run(R):
+        t0 = time.perf_counter()
+        if c["model"] == "ic" and ptr.size > 50_000_000:
+            # the plain loop nest is far too slow at web scale: the live-edge
+            # BFS oracle computes the same final states
+            _, _, _, steps, _ = oracle.ic_live_edge(ptr, src, c["seeds"], R, c["rng_key"],
+                                                    want_states=False, nthreads=threads, **okw)
+            kind = "oracle-live-edge-bfs"
+        else:
+            _, _, steps, _ = oracle.simulate(c["model"], ptr, src, c["seeds"], R, c["rng_key"],
+                                             want_states=False, nthreads=threads, **okw)
+            kind = "oracle"
+        return time.perf_counter() - t0, steps, kind
+
+    R = min(threads, c["B"])
+    dt, steps, kind = run(R)
+    if dt < target_seconds / 2 and R < c["B"] and kind == "oracle":
+        R = min(c["B"], R * max(1, int(round(target_seconds / max(dt, 1e-3)))))
+        dt, steps, kind = run(R)
+    rate = src.size * R * steps / dt
     return {"value": rate, "unit": "replicate-edge updates/s", "cores": threads, "kind": kind,
             "sample": f"{R} replicates (of B={c['B']}) x {steps} steps on the full graph, "
                       f"{dt:.1f} s"}
@@ -103,6 +116,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--schedule", default=None, help="JSON dict of fsg_schedule fields")
     ap.add_argument("--no-states", action="store_true", help="counts only (no [n][B] output)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -117,6 +132,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        xa = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+        xb = torch.empty_like(xa)
+        torch.cuda.synchronize()
+        xb.copy_(xa)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {nb} bytes read + {nb} bytes written")
+        del xa, xb
     t0 = time.perf_counter()
     c = make_workload(args.workload)
     gr = c["graph"]
@@ -157,11 +181,15 @@ def main():
         f"steps_run={steps_seen}, mean counted fraction {attack:.4f}")
 
     avg_kernel_ms = kernel_ms / max(launches, 1)
-    abytes = algorithmic_bytes_per_step(c["model"], ptr.size - 1, src.size, c["B"])
+    used = fsg.fsg_default_schedule(dg.handle, sim.prm, c["B"]).as_dict()
+    used.update({k: v for k, v in sched.items() if v})
+    edge_parallel = used.get("kernel_variant") == 2
+    abytes = algorithmic_bytes_per_step(c["model"], ptr.size - 1, src.size, c["B"], edge_parallel)
     achieved = abytes / (avg_kernel_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": "k_step (pull step; heavy-row combine included)",
+                "kernel": ("k_ic_edge1 (edge-parallel IC step; bitmap clear included)"
+                           if edge_parallel else "k_step (pull step; heavy-row combine included)"),
                 "avg_launch_ms": round(avg_kernel_ms, 5), "launches": launches,
                 "algorithmic_bytes_per_launch": abytes}
     cpu = None

@@ -111,7 +111,11 @@ typedef struct {
  *   steps_per_sync synchronous steps launched between host polls of the
  *                  absorption flags.
  *   time_kernels   1: time every pull step with HIP events (reported in
- *                  fsg_run_info); 0: no timing. */
+ *                  fsg_run_info); 0: no timing.
+ *   kernel_variant 0: the library picks; 1: row-group pull kernel (any
+ *                  model and B); 2: edge-parallel IC kernel with a frontier
+ *                  bitmap (IC with B <= 64 only, else FSG_EINVAL).  With
+ *                  variant 2, row_lanes and block_threads are not used. */
 typedef struct {
     int32_t row_lanes;
     int32_t block_threads;
@@ -119,7 +123,8 @@ typedef struct {
     int32_t heavy_threshold;
     int32_t steps_per_sync;
     int32_t time_kernels;
-    int32_t reserved[2];
+    int32_t kernel_variant;
+    int32_t reserved;
 } fsg_schedule;
 
 /* Library version of this header (FSG_ABI_VERSION). */

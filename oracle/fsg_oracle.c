@@ -37,6 +37,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -44,6 +45,10 @@
 #endif
 
 #define ORC_ALWAYS 0xFFFFFFFFu
+
+/* When set, the live-edge BFS reports each finished replicate on stderr. */
+static int orc_verbose = 0;
+void orc_set_verbose(int on) { orc_verbose = on; }
 
 enum { ORC_IC = 0, ORC_SI = 1, ORC_SIS = 2, ORC_SIR = 3, ORC_LT = 4 };
 enum { ORC_IC_UNIFORM = 0, ORC_IC_WEIGHTED_CASCADE = 1, ORC_IC_PER_EDGE = 2 };
@@ -397,6 +402,11 @@ int orc_ic_live_edge(int ic_prob, double p, const double *edge_p, int64_t max_st
                     }
             }
             for (int64_t i = 0; i < tail; ++i) dist[queue[i]] = -1;
+            if (orc_verbose) {
+                fprintf(stderr, "[oracle] live-edge replicate %lld: %lld reached, depth %lld\n",
+                        (long long)g, (long long)tail, (long long)dmax);
+                fflush(stderr);
+            }
         }
         if (counts) {
 #ifdef _OPENMP

@@ -68,6 +68,8 @@ def _load():
             ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), ctypes.c_int]
         lib.orc_ic_live_edge.restype = ctypes.c_int
+        lib.orc_set_verbose.argtypes = [ctypes.c_int]
+        lib.orc_set_verbose.restype = None
         _lib = lib
     return _lib
 
@@ -142,9 +144,10 @@ def simulate(model, ptr, src, seeds, B, rng_key, *, p=0.0, ic_prob=IC_UNIFORM, e
 
 def ic_live_edge(ptr, src, seeds, B, rng_key, *, p=0.0, ic_prob=IC_UNIFORM, edge_p=None,
                  max_steps=-1, replicate_offset=0, want_states=True, want_dist=False,
-                 nthreads=0):
+                 nthreads=0, verbose=False):
     """IC via BFS in the live-edge graph.  Returns (states, counts, dist, steps_run, absorbed)."""
     lib = _load()
+    lib.orc_set_verbose(1 if verbose else 0)
     ptr, src = _csr(ptr, src)
     n = ptr.size - 1
     seeds = np.ascontiguousarray(seeds, dtype=np.int32)

@@ -80,7 +80,7 @@ int ilog2(int64_t x)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
-    std::vector<int32_t> tiles;      // row boundaries of non-empty tiles
+    std::vector<int32_t> tiles;      // (row_begin, row_end) pairs; no heavy rows inside
     std::vector<int32_t> heavy_rows; // rows with indeg > heavy
     std::vector<int32_t> heavy_seg;  // [n_heavy + 1] first segment of each heavy row
     std::vector<int32_t> seg_row, seg_e0, seg_e1;
@@ -177,8 +177,26 @@ const Plan &get_plan(fsg_graph *g, int64_t heavy, int64_t tile_edges)
     std::vector<int64_t> b((size_t)n + 2);
     int64_t nt = 0;
     fsg_plan_row_tiles(ptr, n, heavy, kRowCost, parts, b.data(), &nt);
-    p.tiles.resize((size_t)nt + 1);
-    for (int64_t i = 0; i <= nt; ++i) p.tiles[(size_t)i] = (int32_t)b[(size_t)i];
+    // heavy rows are cut out of the parts (their segments are separate work
+    // items) and no tile holds more than kMaxTileRows rows
+    for (int64_t i = 0; i < nt; ++i) {
+        int64_t r = b[(size_t)i];
+        const int64_t end = b[(size_t)i + 1];
+        while (r < end) {
+            while (r < end && ptr[r + 1] - ptr[r] > heavy) ++r;
+            int64_t q = r;
+            while (q < end && q - r < kMaxTileRows && ptr[q + 1] - ptr[q] <= heavy) ++q;
+            if (q > r) {
+                p.tiles.push_back((int32_t)r);
+                p.tiles.push_back((int32_t)q);
+            }
+            r = q;
+        }
+    }
+    if (p.tiles.empty()) {  // every row heavy: one empty tile keeps the grid valid
+        p.tiles.push_back(0);
+        p.tiles.push_back(0);
+    }
     return g->plans.emplace(key, std::move(p)).first->second;
 }
 
@@ -220,30 +238,43 @@ int check_params(const fsg_graph *g, const fsg_params *prm, int64_t B)
 
 struct Sched {
     int G, S, lgG, lgS, block, tile_edges, heavy, sync, timed;
+    bool edge1;  // edge-parallel IC kernel
 };
 
-void default_sched(const fsg_graph *g, int64_t B, fsg_schedule *o)
+void default_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_schedule *o)
 {
     const int64_t W = (B + 63) / 64;
     memset(o, 0, sizeof(*o));
-    o->row_lanes = W >= 16 ? 64 : 16;
+    // lanes over words first; an edge split only for narrow batches
+    o->row_lanes = (int32_t)std::max<int64_t>(16, std::min<int64_t>(next_pow2(W), 64));
     o->block_threads = 256;
     o->tile_edges = 4096;
-    o->heavy_threshold = 2048;
+    o->heavy_threshold = 1024;
     o->steps_per_sync = 16;
+    o->kernel_variant = (prm->model == FSG_IC && W == 1) ? 2 : 1;
+    if (o->kernel_variant == 2) {
+        o->tile_edges = 8192;
+        o->heavy_threshold = 8192;
+    }
     (void)g;
 }
 
-int resolve_sched(const fsg_graph *g, int64_t B, const fsg_schedule *in, Sched *s)
+int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fsg_schedule *in,
+                  Sched *s)
 {
     fsg_schedule d;
-    default_sched(g, B, &d);
+    default_sched(g, prm, B, &d);
     fsg_schedule u = in ? *in : d;
     if (u.row_lanes == 0) u.row_lanes = d.row_lanes;
     if (u.block_threads == 0) u.block_threads = d.block_threads;
     if (u.tile_edges == 0) u.tile_edges = d.tile_edges;
     if (u.heavy_threshold == 0) u.heavy_threshold = d.heavy_threshold;
     if (u.steps_per_sync == 0) u.steps_per_sync = d.steps_per_sync;
+    if (u.kernel_variant == 0) u.kernel_variant = d.kernel_variant;
+    if (u.kernel_variant < 1 || u.kernel_variant > 2)
+        return fail(FSG_EINVAL, "kernel_variant must be 0, 1 or 2");
+    if (u.kernel_variant == 2 && !(prm->model == FSG_IC && B <= 64))
+        return fail(FSG_EINVAL, "kernel_variant 2 needs IC with B <= 64");
     if (u.row_lanes < 1 || u.row_lanes > 64 || (u.row_lanes & (u.row_lanes - 1)))
         return fail(FSG_EINVAL, "row_lanes must be a power of two in [1, 64]");
     if (u.block_threads < 64 || u.block_threads > 1024 || (u.block_threads & (u.block_threads - 1)))
@@ -264,6 +295,7 @@ int resolve_sched(const fsg_graph *g, int64_t B, const fsg_schedule *in, Sched *
     s->heavy = u.heavy_threshold;
     s->sync = u.steps_per_sync;
     s->timed = u.time_kernels != 0;
+    s->edge1 = u.kernel_variant == 2;
     return FSG_OK;
 }
 
@@ -271,7 +303,8 @@ struct Layout {
     size_t planes[3];
     int n_planes;
     size_t flags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
-        seeds, total;
+        seeds, bm[2], sum[2], total;
+    int sum_shift, sum_words;
     int64_t W, plane_words, n_tinf, n_seed_stage;
     int L;
 };
@@ -331,6 +364,21 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
     if (prm->model == FSG_IC && prm->ic_prob == FSG_IC_PER_EDGE)
         off = align256(off + (size_t)g->nnz * 4);
     L->seeds = off; off = align256(off + (size_t)L->n_seed_stage * 4);
+    L->bm[0] = L->bm[1] = L->sum[0] = L->sum[1] = 0;
+    L->sum_shift = 0;
+    L->sum_words = 0;
+    if (s.edge1) {
+        const size_t bmb = (size_t)((g->n + 31) / 32) * 4;
+        L->bm[0] = off; off = align256(off + bmb);
+        L->bm[1] = off; off = align256(off + bmb);
+        // coarsest summary that fits the kernel's LDS copy, at least 512 nodes a bit
+        int sh = 9;
+        while ((((g->n - 1) >> sh) >> 5) + 1 > kSumWords) ++sh;
+        L->sum_shift = sh;
+        L->sum_words = (int)((((g->n - 1) >> sh) >> 5) + 1);
+        L->sum[0] = off; off = align256(off + (size_t)L->sum_words * 4);
+        L->sum[1] = off; off = align256(off + (size_t)L->sum_words * 4);
+    }
     L->total = off;
     return FSG_OK;
 }
@@ -384,7 +432,8 @@ int fsg_graph_create(int64_t n, int64_t nnz, const int64_t *in_ptr, const int32_
 int fsg_graph_workspace_size(const fsg_graph *g, size_t *bytes)
 {
     if (!g || !bytes) return fail(FSG_EINVAL, "NULL argument");
-    *bytes = align256((size_t)(g->n + 1) * 4) + align256((size_t)std::max<int64_t>(g->nnz, 1) * 4);
+    // sources are padded by 16 bytes: kernels read them with 16-byte loads
+    *bytes = align256((size_t)(g->n + 1) * 4) + align256((size_t)std::max<int64_t>(g->nnz, 1) * 4 + 16);
     return FSG_OK;
 }
 
@@ -436,7 +485,7 @@ int fsg_default_schedule(const fsg_graph *g, const fsg_params *prm, int64_t B, f
     if (!out) return fail(FSG_EINVAL, "out is NULL");
     int rc = check_params(g, prm, B);
     if (rc) return rc;
-    default_sched(g, B, out);
+    default_sched(g, prm, B, out);
     return FSG_OK;
 }
 
@@ -449,7 +498,7 @@ int fsg_sim_workspace_size(const fsg_graph *g_, const fsg_params *prm, int64_t B
         if (rc) return rc;
         fsg_graph *g = const_cast<fsg_graph *>(g_);
         Sched s;
-        rc = resolve_sched(g, B, sched, &s);
+        rc = resolve_sched(g, prm, B, sched, &s);
         if (rc) return rc;
         const Plan &p = get_plan(g, s.heavy, s.tile_edges);
         Layout L;
@@ -478,7 +527,7 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
             if (seeds[i] < 0 || (int64_t)seeds[i] >= g->n)
                 return fail(FSG_EINVAL, "seed out of range at index " + std::to_string(i));
         Sched s;
-        rc = resolve_sched(g, B, sched, &s);
+        rc = resolve_sched(g, prm, B, sched, &s);
         if (rc) return rc;
         const Plan &p = get_plan(g, s.heavy, s.tile_edges);
         Layout L;
@@ -518,12 +567,22 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         // ---- initial states: everything 0, seeds 1 in every replicate
         for (int i = 0; i < L.n_planes; ++i) HIP_TRY(launch_fill64(pl[i], L.plane_words, 0ull, st));
         HIP_TRY(launch_fill32(flags, ring, 0u, st));
+        uint32_t *bm[2] = {nullptr, nullptr}, *sum[2] = {nullptr, nullptr};
+        if (s.edge1) {
+            for (int i = 0; i < 2; ++i) {
+                bm[i] = (uint32_t *)(base + L.bm[i]);
+                sum[i] = (uint32_t *)(base + L.sum[i]);
+                HIP_TRY(launch_fill32(bm[i], (g->n + 31) / 32, 0u, st));
+                HIP_TRY(launch_fill32(sum[i], L.sum_words, 0u, st));
+            }
+        }
         int32_t *dseeds = (int32_t *)(base + L.seeds);
         for (int64_t i0 = 0; i0 < n_seeds; i0 += L.n_seed_stage) {
             const int64_t cnt = std::min<int64_t>(L.n_seed_stage, n_seeds - i0);
             HIP_TRY(hipMemcpyAsync(dseeds, seeds + i0, (size_t)cnt * 4, hipMemcpyHostToDevice, st));
             uint64_t *second = kind == kKindIC ? pl[2] : nullptr;  // IC: A too
-            HIP_TRY(launch_seed(pl[0], second, dseeds, cnt, (int32_t)L.W, B, flags, st));
+            HIP_TRY(launch_seed(pl[0], second, dseeds, cnt, (int32_t)L.W, B, flags, bm[0], sum[0],
+                                L.sum_shift, st));
             HIP_TRY(hipStreamSynchronize(st));
         }
         HIP_TRY(hipStreamSynchronize(st));
@@ -553,7 +612,7 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         a.lgS = s.lgS;
         a.heavy = s.heavy;
         a.tiles = (const int32_t *)(base + L.tiles);
-        a.n_tiles = (int32_t)p.tiles.size() - 1;
+        a.n_tiles = (int32_t)(p.tiles.size() / 2);
         a.seg_row = (const int32_t *)(base + L.seg_row);
         a.seg_e0 = (const int32_t *)(base + L.seg_e0);
         a.seg_e1 = (const int32_t *)(base + L.seg_e1);
@@ -565,6 +624,15 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         a.Lp = L.L;
         a.flags = flags;
         a.ring = ring;
+        a.sum_shift = L.sum_shift;
+        a.sum_words = L.sum_words;
+        int edge_grid = 0;
+        if (s.edge1) {
+            int dev = 0, ncu = 0;
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+            edge_grid = 3 * std::max(ncu, 1);  // ~41 KB of LDS a block: three per CU
+        }
 
         const int64_t K = prm->max_steps < 0 ? g->n : prm->max_steps;
         int64_t steps_run = 0;
@@ -584,8 +652,17 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
                 a.prev = pl[(step - 1) & 1];
                 a.next = pl[step & 1];
                 if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
-                HIP_TRY(launch_step(a, kind, L.L, s.block, st));
-                if (a.n_heavy > 0) HIP_TRY(launch_combine(a, kind, s.block, st));
+                if (s.edge1) {
+                    a.bm_prev = bm[(step - 1) & 1];
+                    a.bm_next = bm[step & 1];
+                    a.sum_prev = sum[(step - 1) & 1];
+                    a.sum_next = sum[step & 1];
+                    HIP_TRY(launch_ic_clear(a, st));
+                    HIP_TRY(launch_ic_edge1(a, edge_grid, s.block, st));
+                } else {
+                    HIP_TRY(launch_step(a, kind, L.L, s.block, st));
+                    if (a.n_heavy > 0) HIP_TRY(launch_combine(a, kind, s.block, st));
+                }
                 if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
             }
             HIP_TRY(hipMemcpyAsync(hflags.data(), flags, (size_t)ring * 4, hipMemcpyDeviceToHost, st));
@@ -613,6 +690,7 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         // ---- outputs
         if (final_states || infected_counts) {
             FinArgs f;
+            memset(&f, 0, sizeof(f));
             f.n = (int32_t)g->n;
             f.W = (int32_t)L.W;
             f.G = (int)std::min<int64_t>(next_pow2(L.W), 64);
@@ -624,6 +702,7 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
             if (prm->model == FSG_SIS || prm->model == FSG_SI) f.two = nullptr;
             f.states = final_states;
             f.counts = infected_counts;
+            f.bm = s.edge1 ? bm[steps_run & 1] : nullptr;
             HIP_TRY(launch_finalize(f, st));
             HIP_TRY(hipStreamSynchronize(st));
         }

@@ -125,6 +125,45 @@ __device__ __forceinline__ uint64_t bs_nonzero(const uint64_t (&c)[L])
     return m;
 }
 
+// Masks of the replicates whose count is 1, 2 or 3 (the common case), so
+// most per-replicate counts are read with a select instead of L extractions.
+struct SmallCounts {
+    uint64_t m1, m2, m3;
+};
+
+template <int L>
+__device__ __forceinline__ SmallCounts bs_small(const uint64_t (&c)[L])
+{
+    uint64_t rest = 0;
+#pragma unroll
+    for (int l = 2; l < L; ++l) rest |= c[l];
+    const uint64_t c0 = c[0], c1 = L > 1 ? c[1] : 0ull;
+    return SmallCounts{c0 & ~c1 & ~rest, ~c0 & c1 & ~rest, c0 & c1 & ~rest};
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t bs_get_fast(const uint64_t (&c)[L], const SmallCounts &sm, int b)
+{
+    if ((sm.m1 >> b) & 1ull) return 1u;
+    if ((sm.m2 >> b) & 1ull) return 2u;
+    if ((sm.m3 >> b) & 1ull) return 3u;
+    return bs_get<L>(c, b);
+}
+
+// The four bits of x that belong to the generator block starting at bit gs
+// (gs in [-3, 63]; bits outside the word read as 0), as a nibble.
+__device__ __forceinline__ uint32_t nibble_at(uint64_t x, int gs)
+{
+    return (uint32_t)((gs >= 0 ? (x >> gs) : (x << (-gs))) & 0xFull);
+}
+
+// A nibble placed back at the block position gs.
+__device__ __forceinline__ uint64_t nibble_to_word(uint32_t nib, int gs)
+{
+    const uint64_t x = (uint64_t)(nib & 0xFu);
+    return gs >= 0 ? (x << gs) : (x >> (-gs));
+}
+
 // Sum of the counters held by the lanes lane ^ k*G, k < S (butterfly over
 // the edge-split lanes); every lane of the group ends with the total.
 template <int L>

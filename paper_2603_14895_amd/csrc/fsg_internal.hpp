@@ -8,6 +8,11 @@
 namespace fsg {
 
 enum Kind { kKindIC = 0, kKindEpidemic = 1, kKindLT = 2 };
+
+// Rows a tile may hold (the edge-parallel kernel stages them in LDS).
+constexpr int kMaxTileRows = 2048;
+// Words of the frontier summary the edge-parallel kernel keeps in LDS.
+constexpr int kSumWords = 4096;
 enum Model { kIC = 0, kSI = 1, kSIS = 2, kSIR = 3, kLT = 4 };
 enum IcProb { kIcUniform = 0, kIcWeightedCascade = 1, kIcPerEdge = 2 };
 
@@ -45,6 +50,17 @@ struct StepArgs {
     int32_t n_heavy;
     uint64_t *partial;      // [n_seg][Lp][W]
     int32_t Lp;             // counter planes per partial (1 for IC)
+    // frontier bitmaps of the edge-parallel IC kernel: bit u of bm_prev is set
+    // iff node u has a newly active replicate after step t-1 (prev is only
+    // meaningful where it is set); bm_next is cleared before step t
+    const uint32_t *bm_prev;
+    uint32_t *bm_next;
+    // summaries of the bitmaps: bit i set iff some node u with u >> sum_shift
+    // == i has its bitmap bit set (staged in LDS by the edge-parallel kernel)
+    const uint32_t *sum_prev;
+    uint32_t *sum_next;
+    int32_t sum_shift;
+    int32_t sum_words;
     // absorption flags: flags[t % ring] = 1 iff some replicate still has a
     // state-1 node after step t
     uint32_t *flags;
@@ -58,6 +74,7 @@ struct FinArgs {
     int32_t model;
     const uint64_t *one;  // state-1 plane (F, h, active)
     const uint64_t *two;  // state-2 plane (A for IC, r for SIR) or null
+    const uint32_t *bm;   // when set, `one` is valid only for nodes whose bit is set
     uint8_t *states;      // [n][B] or null
     uint32_t *counts;     // [n] or null
 };
@@ -67,7 +84,10 @@ hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t
 hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s);
 hipError_t launch_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t ns, int32_t W,
-                       int64_t B, uint32_t *flag0, hipStream_t s);
+                       int64_t B, uint32_t *flag0, uint32_t *bm, uint32_t *sum, int sum_shift,
+                       hipStream_t s);
+hipError_t launch_ic_edge1(const StepArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_ic_clear(const StepArgs &a, hipStream_t s);
 hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_t s);
 hipError_t launch_combine(const StepArgs &a, int kind, int block, hipStream_t s);
 hipError_t launch_finalize(const FinArgs &f, hipStream_t s);

@@ -18,47 +18,79 @@
 #include "fsg_device.hpp"
 #include "fsg_internal.hpp"
 
+#include <algorithm>
+
 namespace fsg {
+
+// Infection thresholds staged in LDS by the step kernel (k = 0 .. kTinfLds-1).
+constexpr int kTinfLds = 2048;
+
+// Threshold of k infected neighbours: LDS copy when staged, global otherwise.
+__device__ __forceinline__ uint32_t tinf_at(const StepArgs &a, const uint32_t *tl, int tl_n,
+                                            uint32_t k)
+{
+    if (k > (uint32_t)a.khat) k = (uint32_t)a.khat;
+    return (int)k < tl_n ? tl[k] : a.tinf[k];
+}
 
 // ---------------------------------------------------------------- IC ----
 // Message of arc e = (u -> v) in replicate r: u newly active at t-1 and the
 // arc's one trial fires (the trial does not depend on t, and an arc is
 // consulted only once per replicate since u is newly active only once).
 // Aggregation: OR over arcs.  Update: 0 -> 1 on any message, 1 -> 2.
+__device__ __forceinline__ void ic_edge(const StepArgs &a, int e, uint64_t f, uint64_t gbase,
+                                        uint32_t tv, uint64_t &acc)
+{
+    if (!f) return;
+    const uint32_t te = a.edge_t ? a.edge_t[e] : tv;
+    if (te == 0u) return;
+    if (te == kAlways) {
+        acc |= f;
+        return;
+    }
+    while (f) {
+        const int b = __builtin_ctzll(f);
+        const int gs = b - (int)((gbase + (uint64_t)b) & 3u);  // block's first bit
+        const uint64_t gm = block_bits(gbase, b);
+        const uint64_t bits = f & gm;
+        f &= ~gm;
+        const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
+        const U4 o = philox10((uint32_t)e, blk, 0u, kDomIcEdge << 24, a.key0, a.key1);
+        const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int bb = gs + j;
+            if (bb < 0 || bb > 63) continue;
+            if (((bits >> bb) & 1ull) && ou[j] < te) acc |= 1ull << bb;
+        }
+    }
+}
+
 __device__ __forceinline__ void ic_row_word(const StepArgs &a, int G, int S, bool valid, int v,
                                             int w, int e0, int e1, uint32_t tv, int s, int seg,
                                             bool &any)
 {
     const int64_t idx = (int64_t)v * a.W + w;
+    const int64_t W = a.W;
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
     const uint64_t A = valid ? a.aux[idx] : ~0ull;
     const uint64_t cand = valid ? (~A & tail_mask(w, a.B)) : 0ull;
     uint64_t acc = 0;
     if (cand) {
-        for (int e = e0 + s; e < e1; e += S) {
-            const int u = a.src[e];
-            uint64_t f = a.prev[(int64_t)u * a.W + w] & cand & ~acc;
-            if (!f) continue;
-            const uint32_t te = a.edge_t ? a.edge_t[e] : tv;
-            if (te == 0u) continue;
-            while (f) {
-                const int b = __builtin_ctzll(f);
-                const uint64_t gm = block_bits(gbase, b);
-                uint64_t bits = f & gm;
-                f &= ~gm;
-                if (te == kAlways) {
-                    acc |= bits;
-                    continue;
-                }
-                const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
-                const U4 o = philox10((uint32_t)e, blk, 0u, kDomIcEdge << 24, a.key0, a.key1);
-                while (bits) {
-                    const int bb = __builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    if (pick(o, (uint32_t)((gbase + (uint64_t)bb) & 3u)) < te) acc |= 1ull << bb;
-                }
-            }
+        int e = e0 + s;
+        // four independent gathers in flight per lane
+        for (; e + 3 * S < e1; e += 4 * S) {
+            const int u0 = a.src[e], u1 = a.src[e + S], u2 = a.src[e + 2 * S],
+                      u3 = a.src[e + 3 * S];
+            const uint64_t f0 = a.prev[(int64_t)u0 * W + w], f1 = a.prev[(int64_t)u1 * W + w],
+                           f2 = a.prev[(int64_t)u2 * W + w], f3 = a.prev[(int64_t)u3 * W + w];
+            ic_edge(a, e, f0 & cand & ~acc, gbase, tv, acc);
+            ic_edge(a, e + S, f1 & cand & ~acc, gbase, tv, acc);
+            ic_edge(a, e + 2 * S, f2 & cand & ~acc, gbase, tv, acc);
+            ic_edge(a, e + 3 * S, f3 & cand & ~acc, gbase, tv, acc);
         }
+        for (; e < e1; e += S)
+            ic_edge(a, e, a.prev[(int64_t)a.src[e] * W + w] & cand & ~acc, gbase, tv, acc);
     }
     acc = or_reduce_lanes(acc, G, S);
     if (!valid || s != 0) return;
@@ -71,6 +103,25 @@ __device__ __forceinline__ void ic_row_word(const StepArgs &a, int G, int S, boo
     }
 }
 
+// Bit-sliced count of the in-neighbours whose word has a bit of `mask` set,
+// per replicate: four independent gathers in flight per lane.
+template <int L>
+__device__ __forceinline__ void count_edges(const StepArgs &a, int e, int e1, int S, int w,
+                                            uint64_t mask, uint64_t (&c)[L])
+{
+    const int64_t W = a.W;
+    for (; e + 3 * S < e1; e += 4 * S) {
+        const int u0 = a.src[e], u1 = a.src[e + S], u2 = a.src[e + 2 * S], u3 = a.src[e + 3 * S];
+        const uint64_t x0 = a.prev[(int64_t)u0 * W + w], x1 = a.prev[(int64_t)u1 * W + w],
+                       x2 = a.prev[(int64_t)u2 * W + w], x3 = a.prev[(int64_t)u3 * W + w];
+        bs_add1<L>(c, x0 & mask);
+        bs_add1<L>(c, x1 & mask);
+        bs_add1<L>(c, x2 & mask);
+        bs_add1<L>(c, x3 & mask);
+    }
+    for (; e < e1; e += S) bs_add1<L>(c, a.prev[(int64_t)a.src[e] * W + w] & mask);
+}
+
 // ------------------------------------------------------ SI / SIS / SIR ----
 // Appendix A.1: the log-survival messages of the k infected in-neighbours sum
 // to k log(1-beta), so a susceptible node is infected with probability
@@ -80,34 +131,50 @@ __device__ __forceinline__ void ic_row_word(const StepArgs &a, int G, int S, boo
 template <int LC>
 __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool valid, int v,
                                            int w, int64_t idx, uint64_t h, uint64_t r,
-                                           uint64_t sus, const uint64_t (&c)[LC], int s, bool &any)
+                                           uint64_t sus, const uint64_t (&c)[LC], int s,
+                                           uint64_t share, const uint32_t *tl, int tl_n,
+                                           bool &any)
 {
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
     const bool draw_rec = a.trec != 0u && a.trec != kAlways;
     uint64_t need = sus & bs_nonzero<LC>(c);
     if (draw_rec) need |= h;
-    need &= share_bits(gbase, s, S);
+    need &= share;
+    const SmallCounts sm = bs_small<LC>(c);
+    const uint64_t big = sus & ~(sm.m1 | sm.m2 | sm.m3) & bs_nonzero<LC>(c);  // k >= 4
+    const uint32_t t1 = tinf_at(a, tl, tl_n, 1u), t2 = tinf_at(a, tl, tl_n, 2u),
+                   t3 = tinf_at(a, tl, tl_n, 3u);
+    const uint32_t trec = a.trec;
     uint64_t inf = 0, rec = 0;
     while (need) {
         const int b = __builtin_ctzll(need);
-        const uint64_t gm = block_bits(gbase, b);
-        uint64_t bits = need & gm;
-        need &= ~gm;
+        const int gs = b - (int)((gbase + (uint64_t)b) & 3u);  // first bit of the block
         const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
+        const uint32_t nn = nibble_at(need, gs);
+        need &= ~nibble_to_word(0xFu, gs);
         const U4 o = philox10((uint32_t)v, blk, a.step, kDomNodeStep << 24, a.key0, a.key1);
-        while (bits) {
-            const int bb = __builtin_ctzll(bits);
-            bits &= bits - 1;
-            const uint32_t u = pick(o, (uint32_t)((gbase + (uint64_t)bb) & 3u));
-            const uint64_t bit = 1ull << bb;
-            if (h & bit) {
-                if (fires(u, a.trec)) rec |= bit;
-            } else {
-                uint32_t k = bs_get<LC>(c, bb);
-                if (k > (uint32_t)a.khat) k = (uint32_t)a.khat;
-                if (fires(u, a.tinf[k])) inf |= bit;
-            }
+        const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
+        const uint32_t nh = nibble_at(h, gs), n1 = nibble_at(sm.m1, gs),
+                       n2 = nibble_at(sm.m2, gs), n3 = nibble_at(sm.m3, gs),
+                       nb = nibble_at(big, gs);
+        uint32_t tb[4] = {0u, 0u, 0u, 0u};
+        if (nb) {  // rare: a replicate of this block has four or more infected neighbours
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if ((nb >> j) & 1u) tb[j] = tinf_at(a, tl, tl_n, bs_get<LC>(c, gs + j));
         }
+        uint32_t fi = 0, fr = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool isI = (nh >> j) & 1u;
+            uint32_t t = ((n1 >> j) & 1u) ? t1 : (((n2 >> j) & 1u) ? t2 : (((n3 >> j) & 1u) ? t3 : tb[j]));
+            t = isI ? trec : t;
+            const uint32_t f = (((nn >> j) & 1u) && fires(ou[j], t)) ? 1u : 0u;
+            fi |= (isI ? 0u : f) << j;
+            fr |= (isI ? f : 0u) << j;
+        }
+        inf |= nibble_to_word(fi, gs);
+        rec |= nibble_to_word(fr, gs);
     }
     inf = or_reduce_lanes(inf, G, S);
     rec = or_reduce_lanes(rec, G, S);
@@ -122,7 +189,9 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
 
 template <int L>
 __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bool valid, int v,
-                                             int w, int e0, int e1, int s, int seg, bool &any)
+                                             int w, int e0, int e1, int s, int seg,
+                                             uint64_t share, const uint32_t *tl, int tl_n,
+                                             bool &any)
 {
     const int64_t idx = (int64_t)v * a.W + w;
     const uint64_t h = valid ? a.prev[idx] : 0ull;
@@ -131,12 +200,7 @@ __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bo
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
-    if (sus) {
-        for (int e = e0 + s; e < e1; e += S) {
-            const uint64_t x = a.prev[(int64_t)a.src[e] * a.W + w] & sus;
-            if (x) bs_add1<L>(c, x);
-        }
-    }
+    if (sus) count_edges<L>(a, e0 + s, e1, S, w, sus, c);
     bs_reduce_lanes<L>(c, G, S);
     if (seg >= 0) {
         if (valid && s == 0) {
@@ -145,7 +209,7 @@ __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bo
         }
         return;
     }
-    epi_decide<L>(a, G, S, valid, v, w, idx, h, r, sus, c, s, any);
+    epi_decide<L>(a, G, S, valid, v, w, idx, h, r, sus, c, s, share, tl, tl_n, any);
 }
 
 // ---------------------------------------------------------------- LT ----
@@ -156,26 +220,33 @@ template <int LC>
 __device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool valid, int v,
                                           int w, int64_t idx, uint64_t act, uint64_t inact,
                                           uint32_t indeg, const uint64_t (&c)[LC], int s,
-                                          bool &any)
+                                          uint64_t share, bool &any)
 {
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
-    uint64_t cand = inact & bs_nonzero<LC>(c) & share_bits(gbase, s, S);
+    uint64_t cand = inact & bs_nonzero<LC>(c) & share;
+    const SmallCounts sm = bs_small<LC>(c);
     uint64_t nw = 0;
     while (cand) {
         const int b = __builtin_ctzll(cand);
-        const uint64_t gm = block_bits(gbase, b);
-        uint64_t bits = cand & gm;
-        cand &= ~gm;
+        const int gs = b - (int)((gbase + (uint64_t)b) & 3u);
         const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
+        const uint32_t nc = nibble_at(cand, gs);
+        cand &= ~nibble_to_word(0xFu, gs);
         const U4 o = philox10((uint32_t)v, blk, 0u, kDomLtThresh << 24, a.key0, a.key1);
-        while (bits) {
-            const int bb = __builtin_ctzll(bits);
-            bits &= bits - 1;
-            const uint64_t u = pick(o, (uint32_t)((gbase + (uint64_t)bb) & 3u));
-            uint64_t need = (u * (uint64_t)indeg + 0xFFFFFFFFull) >> 32;
-            if (need < 1) need = 1;
-            if ((uint64_t)bs_get<LC>(c, bb) >= need) nw |= 1ull << bb;
+        const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
+        const uint32_t n1 = nibble_at(sm.m1, gs), n2 = nibble_at(sm.m2, gs),
+                       n3 = nibble_at(sm.m3, gs);
+        uint32_t fa = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!((nc >> j) & 1u)) continue;
+            uint32_t k = ((n1 >> j) & 1u) ? 1u : (((n2 >> j) & 1u) ? 2u : (((n3 >> j) & 1u) ? 3u : 0u));
+            if (k == 0u) k = bs_get<LC>(c, gs + j);  // four or more active neighbours
+            // c >= 1 here, so max(1, need) = need
+            const uint64_t need = ((uint64_t)ou[j] * (uint64_t)indeg + 0xFFFFFFFFull) >> 32;
+            if ((uint64_t)k >= need) fa |= 1u << j;
         }
+        nw |= nibble_to_word(fa, gs);
     }
     nw = or_reduce_lanes(nw, G, S);
     if (!valid || s != 0) return;
@@ -186,7 +257,7 @@ __device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool 
 template <int L>
 __device__ __forceinline__ void lt_row_word(const StepArgs &a, int G, int S, bool valid, int v,
                                             int w, int e0, int e1, uint32_t indeg, int s, int seg,
-                                            bool &any)
+                                            uint64_t share, bool &any)
 {
     const int64_t idx = (int64_t)v * a.W + w;
     const uint64_t act = valid ? a.prev[idx] : 0ull;
@@ -194,12 +265,7 @@ __device__ __forceinline__ void lt_row_word(const StepArgs &a, int G, int S, boo
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
-    if (inact) {
-        for (int e = e0 + s; e < e1; e += S) {
-            const uint64_t x = a.prev[(int64_t)a.src[e] * a.W + w] & inact;
-            if (x) bs_add1<L>(c, x);
-        }
-    }
+    if (inact) count_edges<L>(a, e0 + s, e1, S, w, inact, c);
     bs_reduce_lanes<L>(c, G, S);
     if (seg >= 0) {
         if (valid && s == 0) {
@@ -208,7 +274,7 @@ __device__ __forceinline__ void lt_row_word(const StepArgs &a, int G, int S, boo
         }
         return;
     }
-    lt_decide<L>(a, G, S, valid, v, w, idx, act, inact, indeg, c, s, any);
+    lt_decide<L>(a, G, S, valid, v, w, idx, act, inact, indeg, c, s, share, any);
 }
 
 __device__ __forceinline__ uint32_t wc_threshold(uint32_t indeg)
@@ -219,25 +285,38 @@ __device__ __forceinline__ uint32_t wc_threshold(uint32_t indeg)
 
 template <int KIND, int L>
 __device__ __forceinline__ void row_word(const StepArgs &a, int G, int S, bool valid, int v, int w,
-                                         int e0, int e1, uint32_t indeg, int s, int seg, bool &any)
+                                         int e0, int e1, uint32_t indeg, int s, int seg,
+                                         uint64_t share_fixed, const uint32_t *tl, int tl_n,
+                                         bool &any)
 {
+    // draws of lane s: generator blocks congruent to s mod S; for S <= 16 the
+    // pattern repeats every word, otherwise it depends on the word
+    const uint64_t share =
+        S <= 16 ? share_fixed : share_bits(a.goff + 64ull * (uint64_t)w, s, S);
     if (KIND == kKindIC) {
         uint32_t tv = a.ic_t;
         if (a.ic_prob == kIcWeightedCascade) tv = wc_threshold(indeg);
         ic_row_word(a, G, S, valid, v, w, e0, e1, tv, s, seg, any);
     } else if (KIND == kKindEpidemic) {
-        epi_row_word<L>(a, G, S, valid, v, w, e0, e1, s, seg, any);
+        epi_row_word<L>(a, G, S, valid, v, w, e0, e1, s, seg, share, tl, tl_n, any);
     } else {
-        lt_row_word<L>(a, G, S, valid, v, w, e0, e1, indeg, s, seg, any);
+        lt_row_word<L>(a, G, S, valid, v, w, e0, e1, indeg, s, seg, share, any);
     }
 }
 
-// One synchronous step t = a.step.  Blocks [0, n_tiles) own light tiles;
-// the rest own heavy-row segments (one per row slot).
+// One synchronous step t = a.step.  The first blocks own heavy-row segments
+// (one per row slot; long, so they start first), the rest own light tiles.
 template <int KIND, int L>
 __global__ void __launch_bounds__(1024) k_step(StepArgs a)
 {
     if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // nothing left to change
+    __shared__ uint32_t s_tinf[KIND == kKindEpidemic ? kTinfLds : 1];
+    int tl_n = 0;
+    if (KIND == kKindEpidemic) {
+        tl_n = a.khat + 1 < kTinfLds ? a.khat + 1 : kTinfLds;
+        for (int i = threadIdx.x; i < tl_n; i += blockDim.x) s_tinf[i] = a.tinf[i];
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -247,10 +326,14 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
     const int slot = lane >> lgGS;
     const int s = (lane >> a.lgG) & (S - 1);
     const int gw = lane & (G - 1);
+    const uint64_t share_fixed = S <= 16 ? share_bits(a.goff, s, S) : 0ull;
     bool any = false;
+    const int rows_per_block = nwaves * rpw;
+    const int seg_blocks = (a.n_seg + rows_per_block - 1) / rows_per_block;
     const int bid = blockIdx.x;
-    if (bid < a.n_tiles) {
-        const int t0 = a.tiles[bid], t1 = a.tiles[bid + 1];
+    if (bid >= seg_blocks) {
+        const int tile = bid - seg_blocks;
+        const int t0 = a.tiles[2 * tile], t1 = a.tiles[2 * tile + 1];
         for (int rb = t0 + wave * rpw; rb < t1; rb += nwaves * rpw) {
             const int v = rb + slot;
             bool act = v < t1;
@@ -263,11 +346,11 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
             for (int w0 = 0; w0 < a.W; w0 += G) {
                 const int w = w0 + gw;
                 row_word<KIND, L>(a, G, S, act && w < a.W, v, w < a.W ? w : 0, e0, e1,
-                                  (uint32_t)(e1 - e0), s, -1, any);
+                                  (uint32_t)(e1 - e0), s, -1, share_fixed, s_tinf, tl_n, any);
             }
         }
     } else {
-        const int seg = (bid - a.n_tiles) * nwaves * rpw + wave * rpw + slot;
+        const int seg = bid * rows_per_block + wave * rpw + slot;
         const bool act = seg < a.n_seg;
         int v = 0, e0 = 0, e1 = 0;
         uint32_t indeg = 0;
@@ -280,7 +363,7 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
         for (int w0 = 0; w0 < a.W; w0 += G) {
             const int w = w0 + gw;
             row_word<KIND, L>(a, G, S, act && w < a.W, v, w < a.W ? w : 0, e0, e1, indeg, s,
-                              act ? seg : 0, any);
+                              act ? seg : 0, share_fixed, s_tinf, tl_n, any);
         }
     }
     if (__ballot(any) != 0ull && lane == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
@@ -340,18 +423,193 @@ __global__ void __launch_bounds__(256) k_combine(StepArgs a)
                 const uint64_t sus = valid ? (~(h | r) & tail_mask(ww, a.B)) : 0ull;
 #pragma unroll
                 for (int l = 0; l < LC; ++l) c[l] &= sus;
-                epi_decide<LC>(a, G, 1, valid, v, ww, idx, h, r, sus, c, 0, any);
+                epi_decide<LC>(a, G, 1, valid, v, ww, idx, h, r, sus, c, 0, ~0ull, nullptr, 0,
+                               any);
             } else {
                 const uint64_t act_w = valid ? a.prev[idx] : 0ull;
                 const uint64_t inact = valid ? (~act_w & tail_mask(ww, a.B)) : 0ull;
 #pragma unroll
                 for (int l = 0; l < LC; ++l) c[l] &= inact;
                 const uint32_t indeg = act ? (uint32_t)(a.ptr[v + 1] - a.ptr[v]) : 0u;
-                lt_decide<LC>(a, G, 1, valid, v, ww, idx, act_w, inact, indeg, c, 0, any);
+                lt_decide<LC>(a, G, 1, valid, v, ww, idx, act_w, inact, indeg, c, 0, ~0ull, any);
             }
         }
     }
     if (__ballot(any) != 0ull && lane == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+// ------------------------------------------- IC, one word per node ----
+// Edge-parallel variant for B <= 64 (W = 1): a block streams the in-edge
+// range of its tile four arcs per thread with 16-byte loads, tests each source
+// against the frontier bitmap (N bits, cache-resident), and only for a
+// frontier source finds the target row (binary search over the tile's row
+// pointers in LDS), gathers the source word and runs the arc's trials; fired
+// replicate bits are OR-ed into the row's LDS word.  Only rows that change
+// are written.  Heavy rows come as segments whose blocks OR into the row's
+// global words directly (cleared before the step by k_ic_clear).
+__device__ __forceinline__ uint32_t ic_threshold(const StepArgs &a, uint32_t indeg)
+{
+    return a.ic_prob == kIcWeightedCascade ? wc_threshold(indeg) : a.ic_t;
+}
+
+__device__ __forceinline__ bool in_frontier(const uint32_t *bm, int u)
+{
+    return (bm[u >> 5] >> (u & 31)) & 1u;
+}
+
+// Frontier test of source u: the LDS summary first, the global bitmap only
+// when the summary bit is set.
+__device__ __forceinline__ bool frontier_hit(const StepArgs &a, const uint32_t *s_sum, int u)
+{
+    const int i = u >> a.sum_shift;
+    if (!((s_sum[i >> 5] >> (i & 31)) & 1u)) return false;
+    return in_frontier(a.bm_prev, u);
+}
+
+__device__ __forceinline__ void mark_frontier(const StepArgs &a, int v)
+{
+    atomicOr(&a.bm_next[v >> 5], 1u << (v & 31));
+    const int i = v >> a.sum_shift;
+    atomicOr(&a.sum_next[i >> 5], 1u << (i & 31));
+}
+
+// Persistent blocks: block b takes work items b, b + grid, ... where items
+// [0, n_seg) are heavy-row segments and the rest are light tiles.
+__global__ void __launch_bounds__(1024) k_ic_edge1(StepArgs a)
+{
+    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
+    __shared__ int32_t s_ptr[kMaxTileRows + 1];
+    __shared__ unsigned long long s_new[kMaxTileRows];
+    __shared__ uint32_t s_sum[kSumWords];
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+    const uint64_t tail = tail_mask(0, a.B);
+    const uint64_t gbase = a.goff;
+    for (int i = tid; i < a.sum_words; i += nt) s_sum[i] = a.sum_prev[i];
+    bool any = false;
+    const int n_items = a.n_seg + a.n_tiles;
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        __syncthreads();  // LDS of the previous item is no longer in use
+        if (item < a.n_seg) {
+            const int sg = item;
+            const int v = a.seg_row[sg], e0 = a.seg_e0[sg], e1 = a.seg_e1[sg];
+            const uint32_t tv = ic_threshold(a, (uint32_t)(a.ptr[v + 1] - a.ptr[v]));
+            if (tid == 0) s_new[0] = 0ull;
+            __syncthreads();
+            const uint64_t cand = ~a.aux[v] & tail;
+            uint64_t acc = 0;
+            if (cand) {
+                int e = e0 + tid;
+                for (; e + 3 * nt < e1; e += 4 * nt) {  // four independent probes in flight
+                    int us[4];
+                    bool hit[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) us[j] = a.src[e + j * nt];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) hit[j] = frontier_hit(a, s_sum, us[j]);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (hit[j])
+                            ic_edge(a, e + j * nt, a.prev[us[j]] & cand & ~acc, gbase, tv, acc);
+                }
+                for (; e < e1; e += nt) {
+                    const int u = a.src[e];
+                    if (frontier_hit(a, s_sum, u))
+                        ic_edge(a, e, a.prev[u] & cand & ~acc, gbase, tv, acc);
+                }
+            }
+            for (int off = 1; off < 64; off <<= 1) acc |= __shfl_xor(acc, off, 64);
+            if (lane == 0 && acc) atomicOr(&s_new[0], (unsigned long long)acc);
+            __syncthreads();
+            if (tid == 0) {
+                const uint64_t nf = s_new[0];
+                if (nf) {
+                    atomicOr((unsigned long long *)&a.next[v], (unsigned long long)nf);
+                    atomicOr((unsigned long long *)&a.aux[v], (unsigned long long)nf);
+                    mark_frontier(a, v);
+                    any = true;
+                }
+            }
+            continue;
+        }
+        const int tile = item - a.n_seg;
+        const int r0 = a.tiles[2 * tile], r1 = a.tiles[2 * tile + 1];
+        const int nr = r1 - r0;
+        for (int i = tid; i <= nr; i += nt) s_ptr[i] = a.ptr[r0 + i];
+        for (int i = tid; i < nr; i += nt) s_new[i] = 0ull;
+        __syncthreads();
+        const int E0 = s_ptr[0], E1 = s_ptr[nr];
+        // each thread owns 4 chunks of 4 consecutive arcs per pass: four
+        // 16-byte source loads, then sixteen frontier tests, all in flight
+        constexpr int kChunks = 4;
+        for (int base = E0 & ~3; base < E1; base += 4 * kChunks * nt) {
+            int us[4 * kChunks];
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const int eb = base + 4 * (c * nt + tid);
+                int4 q = make_int4(0, 0, 0, 0);
+                if (eb < E1) q = *reinterpret_cast<const int4 *>(a.src + eb);
+                us[4 * c] = q.x;
+                us[4 * c + 1] = q.y;
+                us[4 * c + 2] = q.z;
+                us[4 * c + 3] = q.w;
+            }
+            uint32_t hit = 0;
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int e = base + 4 * (c * nt + tid) + j;
+                    if (e >= E0 && e < E1 && frontier_hit(a, s_sum, us[4 * c + j]))
+                        hit |= 1u << (4 * c + j);
+                }
+            }
+            while (hit) {
+                const int k = __builtin_ctz(hit);
+                hit &= hit - 1;
+                const int c = k >> 2, j = k & 3;
+                const int e = base + 4 * (c * nt + tid) + j;
+                int lo = 0, hi = nr - 1;  // last row whose first edge is <= e
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_ptr[mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                const int v = r0 + lo;
+                const uint64_t cand = ~a.aux[v] & tail;
+                uint64_t acc = 0;
+                ic_edge(a, e, a.prev[us[k]] & cand, gbase,
+                        ic_threshold(a, (uint32_t)(s_ptr[lo + 1] - s_ptr[lo])), acc);
+                if (acc) atomicOr(&s_new[lo], (unsigned long long)acc);
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < nr; i += nt) {
+            const uint64_t nf = s_new[i];
+            if (nf) {
+                const int v = r0 + i;
+                a.next[v] = nf;
+                a.aux[v] |= nf;
+                mark_frontier(a, v);
+                any = true;
+            }
+        }
+    }
+    if (__ballot(any) != 0ull && lane == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+// Before a step of the edge-parallel kernel: clear the next frontier bitmap,
+// its summary, and the next-frontier words of heavy rows (their segments OR
+// into them).
+__global__ void k_ic_clear(StepArgs a)
+{
+    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
+    const int64_t nw = ((int64_t)a.n + 31) >> 5;
+    const int64_t work = nw > a.n_heavy ? nw : a.n_heavy;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < work;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < nw) a.bm_next[i] = 0u;
+        if (i < a.sum_words) a.sum_next[i] = 0u;
+        if (i < a.n_heavy) a.next[a.heavy_rows[i]] = 0ull;
+    }
 }
 
 // ------------------------------------------------------- init / output ----
@@ -380,7 +638,7 @@ __global__ void k_ring_clear(uint32_t *flags, int32_t ring, int32_t keep)
 
 // Seeds are in state 1 in every replicate (Algorithm 1, initial states).
 __global__ void k_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t ns, int32_t W,
-                       int64_t B, uint32_t *flag0)
+                       int64_t B, uint32_t *flag0, uint32_t *bm, uint32_t *sum, int sum_shift)
 {
     const int64_t total = ns * W;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -391,6 +649,11 @@ __global__ void k_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t
         const uint64_t m = tail_mask(w, B);
         p1[idx] = m;
         if (p2) p2[idx] = m;
+        if (bm && w == 0) {
+            const int u = seeds[k];
+            atomicOr(&bm[u >> 5], 1u << (u & 31));
+            atomicOr(&sum[(u >> sum_shift) >> 5], 1u << ((u >> sum_shift) & 31));
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && ns > 0) flag0[0] = 1u;
 }
@@ -413,7 +676,8 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
             if (!act || w >= f.W) continue;
             const int64_t idx = v * f.W + w;
             const uint64_t tail = tail_mask(w, f.B);
-            const uint64_t one = f.one[idx] & tail;
+            const bool live = !f.bm || ((f.bm[v >> 5] >> (v & 31)) & 1u);
+            const uint64_t one = live ? (f.one[idx] & tail) : 0ull;
             const uint64_t two = f.two ? (f.two[idx] & tail) : 0ull;
             cnt += (uint32_t)__popcll(f.model == kSIS ? one : (one | two));
             if (!f.states) continue;
@@ -495,11 +759,12 @@ hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStr
 }
 
 hipError_t launch_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t ns, int32_t W,
-                       int64_t B, uint32_t *flag0, hipStream_t s)
+                       int64_t B, uint32_t *flag0, uint32_t *bm, uint32_t *sum, int sum_shift,
+                       hipStream_t s)
 {
     if (ns <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_seed, dim3(grid_for(ns * W, 256)), dim3(256), 0, s, p1, p2, seeds, ns, W,
-                       B, flag0);
+                       B, flag0, bm, sum, sum_shift);
     return hipGetLastError();
 }
 
@@ -517,10 +782,6 @@ int counter_planes_for(int64_t max_count)
 template <int KIND>
 static hipError_t step_kind(const StepArgs &a, int L, dim3 grid, dim3 block, hipStream_t s)
 {
-    if (KIND == kKindIC) {
-        hipLaunchKernelGGL((k_step<KIND, 1>), grid, block, 0, s, a);
-        return hipGetLastError();
-    }
     switch (L) {
     case 2: hipLaunchKernelGGL((k_step<KIND, 2>), grid, block, 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_step<KIND, 4>), grid, block, 0, s, a); break;
@@ -539,7 +800,10 @@ hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_
     const int64_t nblocks = (int64_t)a.n_tiles + seg_blocks;
     if (nblocks <= 0) return hipSuccess;
     const dim3 grid((unsigned)nblocks), blk((unsigned)block);
-    if (kind == kKindIC) return step_kind<kKindIC>(a, 1, grid, blk, s);
+    if (kind == kKindIC) {
+        hipLaunchKernelGGL((k_step<kKindIC, 1>), grid, blk, 0, s, a);
+        return hipGetLastError();
+    }
     if (kind == kKindEpidemic) return step_kind<kKindEpidemic>(a, L, grid, blk, s);
     return step_kind<kKindLT>(a, L, grid, blk, s);
 }
@@ -568,6 +832,22 @@ hipError_t launch_combine(const StepArgs &a, int kind, int /*block*/, hipStream_
         FSG_COMBINE(kKindLT)
     }
 #undef FSG_COMBINE
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_edge1(const StepArgs &a, int grid, int block, hipStream_t s)
+{
+    const int64_t items = (int64_t)a.n_seg + a.n_tiles;
+    if (items <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>(items, grid);
+    hipLaunchKernelGGL(k_ic_edge1, dim3((unsigned)g), dim3((unsigned)block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_clear(const StepArgs &a, hipStream_t s)
+{
+    const int64_t work = std::max<int64_t>(((int64_t)a.n + 31) >> 5, a.n_heavy);
+    hipLaunchKernelGGL(k_ic_clear, dim3(grid_for(work, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

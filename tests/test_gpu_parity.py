@@ -167,3 +167,38 @@ def test_c2_full_size_sampled_replicates():
                                  want_states=True)
         assert (st[:, r0:r0 + 3] == rs).all(), r0
     log(f"[parity] c2 steps={steps} absorbed={absorbed} attack={(cnt.sum() / (gr.n * c['B'])):.4f}")
+
+
+@pytest.mark.parametrize("ic_prob", ["uniform", "weighted_cascade", "per_edge"])
+@pytest.mark.parametrize("sched", [
+    dict(kernel_variant=2),
+    dict(kernel_variant=2, tile_edges=300, heavy_threshold=50),
+    dict(kernel_variant=2, tile_edges=100000, heavy_threshold=3, steps_per_sync=1),
+])
+@pytest.mark.parametrize("B,offset,K", [(64, 0, -1), (37, 5, -1), (64, 2, 3)])
+def test_ic_edge_parallel(ic_prob, sched, B, offset, K):
+    """The edge-parallel IC kernel (one word per node, frontier bitmap) gives
+    the oracle's bits, including a step cap that leaves a live frontier."""
+    gr = W.chung_lu(7000, 9.0, 2.5, 91)
+    gnp = gr.numpy()
+    ep = np.random.default_rng(9).uniform(0.0, 0.5, size=gr.nnz) if ic_prob == "per_edge" else None
+    seeds = W.uniform_seeds(gr.n, 25, 92)
+    _both(gnp, "ic", seeds, B, 0xED6E + B, f"ic-edge-{ic_prob}", p=0.15, ic_prob=ic_prob,
+          edge_p=ep, replicate_offset=offset, max_steps=K, schedule=sched)
+
+
+def test_ic_rmat_weighted_cascade_vs_live_edge_bfs():
+    """R-MAT (scale 18, edge factor 16, duplicates and self-loops kept),
+    weighted cascade, 50 seeds, B = 64: the GPU matches the live-edge BFS
+    oracle bit for bit, for both kernel variants."""
+    gr = W.rmat(18, 16, 0.57, 0.19, 0.19, 1234)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 50, 1235)
+    key = 0xC4C4C4C4
+    rs, rc, _, rsteps, rabs = oracle.ic_live_edge(gnp[0], gnp[1], seeds, 64, key,
+                                                 ic_prob=oracle.IC_WEIGHTED_CASCADE, nthreads=16)
+    for var in (2, 1):
+        g = gpu_run(gnp, "ic", seeds, 64, key, ic_prob="weighted_cascade",
+                    schedule=dict(kernel_variant=var))
+        assert_same(g, (rs, rc, rsteps, rabs), f"rmat18-variant{var}")
+    log(f"[parity] rmat18 steps={rsteps} spread={rc.sum() / 64:.1f}")
