@@ -193,6 +193,62 @@ int fsg_simulate(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds
                  void *dev_ws, size_t ws_bytes, uint8_t *final_states, uint32_t *infected_counts,
                  fsg_run_info *info, void *stream);
 
+/* ---- Batches: many jobs (graphs, models, seed sets, B) in one launch per
+ * synchronous step (Definition "Batched Monte Carlo Method" applied across
+ * jobs as well as replicates).  Every launch is a persistent work-queue
+ * kernel whose blocks dequeue the tiles and heavy-row segments of all live
+ * jobs; a chunk of steps is captured once in a hipGraph and replayed until
+ * every job is absorbed or at its step cap.  Each job's results are
+ * bit-identical to fsg_simulate on the same arguments. */
+typedef struct fsg_plan fsg_plan;
+
+typedef struct {
+    const fsg_graph *g;         /* bound graph                                      */
+    fsg_params prm;
+    const int32_t *seeds;       /* host, read by fsg_batch_run                      */
+    int64_t n_seeds;
+    int64_t B;
+    int64_t replicate_offset;
+    uint64_t rng_key;
+    fsg_schedule sched;         /* zeros = defaults; kernel_variant must be 0 or 1   */
+    uint8_t *final_states;      /* device [n][B] or NULL                            */
+    uint32_t *infected_counts;  /* device [n] or NULL                               */
+} fsg_job;
+
+/* Plans a batch of 1 <= n_jobs <= 1024 jobs (each validated as by
+ * fsg_simulate) and reports the device workspace it needs.  steps_per_sync
+ * (>= 1) is the number of steps per captured graph.  The jobs array is
+ * copied; the seed arrays it points to must stay valid until
+ * fsg_batch_run returns.  Errors: FSG_EINVAL, FSG_EUNSUPPORTED, FSG_ENOMEM. */
+int fsg_batch_plan(const fsg_job *jobs, int32_t n_jobs, int32_t steps_per_sync, fsg_plan **out,
+                   size_t *ws_bytes);
+
+/* Runs the batch with caller workspace dev_ws (256-byte aligned, at least
+ * ws_bytes of fsg_batch_plan).  infos: host [n_jobs] or NULL; total_ms:
+ * host, device time of all captured step chunks (HIP events on `stream`),
+ * or NULL.  Returns after the work has completed.
+ * Errors: FSG_EINVAL, FSG_EWORKSPACE, FSG_EDEVICE. */
+int fsg_batch_run(fsg_plan *plan, void *dev_ws, size_t ws_bytes, fsg_run_info *infos,
+                  double *total_ms, void *stream);
+
+int fsg_plan_destroy(fsg_plan *plan);
+
+/* ---- Autotuner: times short runs (tune_steps steps from the seeds, kernel
+ * time per step from HIP events) of candidate schedules -- lanes per row,
+ * tile size, heavy-row cut, block size, kernel variant -- and returns the
+ * fastest.  batch_only = 1 restricts the search to schedules the batched
+ * launch accepts.  cache_path (nullable): a text file of earlier results
+ * keyed by graph size, in-degree maximum, model and B; a hit returns without
+ * running anything.  dev_ws: at least fsg_autotune_workspace_size bytes.
+ * best_ms / default_ms (nullable): measured ms per step of the winner and of
+ * the library default. */
+int fsg_autotune_workspace_size(const fsg_graph *g, const fsg_params *prm, int64_t B,
+                                int32_t batch_only, size_t *bytes);
+int fsg_autotune(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t n_seeds,
+                 int64_t B, uint64_t rng_key, int32_t tune_steps, int32_t batch_only,
+                 const char *cache_path, void *dev_ws, size_t ws_bytes, fsg_schedule *best,
+                 double *best_ms, double *default_ms, void *stream);
+
 /* Row-tile planner (host only; Sec. 3.2, Definition "Target-Node-Based
  * Partitioning via Longest Processing Time Heuristic", kept in CSR order so
  * every part is a contiguous row range).  Row v weighs

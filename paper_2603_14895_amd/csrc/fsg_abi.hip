@@ -6,7 +6,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <fstream>
+#include <sstream>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <tuple>
@@ -385,6 +389,171 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
 
 }  // namespace
 
+namespace {
+
+int validate_run(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t n_seeds,
+                 int64_t B, int64_t replicate_offset)
+{
+    int rc = check_params(g, prm, B);
+    if (rc) return rc;
+    if (!g->bound) return fail(FSG_EINVAL, "graph is not bound to device memory");
+    if (replicate_offset < 0 || replicate_offset + B > ((int64_t)1 << 34))
+        return fail(FSG_EINVAL, "replicate_offset + B must lie in [0, 2^34]");
+    if (n_seeds < 0 || (n_seeds > 0 && !seeds)) return fail(FSG_EINVAL, "bad seed array");
+    for (int64_t i = 0; i < n_seeds; ++i)
+        if (seeds[i] < 0 || (int64_t)seeds[i] >= g->n)
+            return fail(FSG_EINVAL, "seed out of range at index " + std::to_string(i));
+    return FSG_OK;
+}
+
+// One job on the device: its planes, tables and launch arguments.
+struct Job {
+    StepArgs a;
+    Layout L;
+    Sched s;
+    int kind = 0;
+    int ring = 0;
+    int64_t K = 0;
+    int64_t n = 0;
+    int64_t B = 0;
+    int model = 0;
+    uint64_t *pl[3] = {nullptr, nullptr, nullptr};
+    uint32_t *bm[2] = {nullptr, nullptr};
+    uint32_t *sum[2] = {nullptr, nullptr};
+};
+
+// Uploads the job's tables into `base`, clears its planes and seeds them
+// (every replicate starts with the seeds in state 1).  `flags` is the job's
+// absorption ring.  Returns after the stream has drained.
+int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t n_seeds,
+              int64_t B, int64_t replicate_offset, uint64_t rng_key, const Sched &s,
+              const Plan &p, const Layout &L, char *base, uint32_t *flags, hipStream_t st,
+              Job *jb)
+{
+    const int kind = model_kind(prm->model);
+    jb->L = L;
+    jb->s = s;
+    jb->kind = kind;
+    jb->ring = s.sync + 1;
+    jb->K = prm->max_steps < 0 ? g->n : prm->max_steps;
+    jb->n = g->n;
+    jb->B = B;
+    jb->model = prm->model;
+    // plane roles: IC {F0, F1, A}; epidemic {h0, h1, r}; LT {act0, act1}
+    for (int i = 0; i < 3; ++i)
+        jb->pl[i] = i < L.n_planes ? (uint64_t *)(base + L.planes[i]) : nullptr;
+    const int ring = jb->ring;
+
+    std::vector<uint32_t> tinf = {0u};
+    if (kind == kKindEpidemic) tinf = infection_table(prm->beta, g->max_indeg);
+    std::vector<uint32_t> edge_t;
+    if (prm->model == FSG_IC && prm->ic_prob == FSG_IC_PER_EDGE) {
+        edge_t.resize((size_t)g->nnz);
+        for (int64_t e = 0; e < g->nnz; ++e) edge_t[(size_t)e] = threshold_of(prm->edge_p[e]);
+    }
+    auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    HIP_TRY(up(L.tiles, p.tiles.data(), p.tiles.size() * 4));
+    HIP_TRY(up(L.heavy_rows, p.heavy_rows.data(), p.heavy_rows.size() * 4));
+    HIP_TRY(up(L.heavy_seg, p.heavy_seg.data(), p.heavy_seg.size() * 4));
+    HIP_TRY(up(L.seg_row, p.seg_row.data(), p.seg_row.size() * 4));
+    HIP_TRY(up(L.seg_e0, p.seg_e0.data(), p.seg_e0.size() * 4));
+    HIP_TRY(up(L.seg_e1, p.seg_e1.data(), p.seg_e1.size() * 4));
+    HIP_TRY(up(L.tinf, tinf.data(), tinf.size() * 4));
+    HIP_TRY(up(L.edge_t, edge_t.data(), edge_t.size() * 4));
+
+    for (int i = 0; i < L.n_planes; ++i) HIP_TRY(launch_fill64(jb->pl[i], L.plane_words, 0ull, st));
+    HIP_TRY(launch_fill32(flags, ring, 0u, st));
+    if (s.edge1) {
+        for (int i = 0; i < 2; ++i) {
+            jb->bm[i] = (uint32_t *)(base + L.bm[i]);
+            jb->sum[i] = (uint32_t *)(base + L.sum[i]);
+            HIP_TRY(launch_fill32(jb->bm[i], (g->n + 31) / 32, 0u, st));
+            HIP_TRY(launch_fill32(jb->sum[i], L.sum_words, 0u, st));
+        }
+    }
+    int32_t *dseeds = (int32_t *)(base + L.seeds);
+    for (int64_t i0 = 0; i0 < n_seeds; i0 += L.n_seed_stage) {
+        const int64_t cnt = std::min<int64_t>(L.n_seed_stage, n_seeds - i0);
+        HIP_TRY(hipMemcpyAsync(dseeds, seeds + i0, (size_t)cnt * 4, hipMemcpyHostToDevice, st));
+        uint64_t *second = kind == kKindIC ? jb->pl[2] : nullptr;  // IC: A too
+        HIP_TRY(launch_seed(jb->pl[0], second, dseeds, cnt, (int32_t)L.W, B, flags, jb->bm[0],
+                            jb->sum[0], L.sum_shift, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));  // tables above are host temporaries
+
+    StepArgs &a = jb->a;
+    memset(&a, 0, sizeof(a));
+    a.ptr = g->d_ptr;
+    a.src = g->d_src;
+    a.n = (int32_t)g->n;
+    a.W = (int32_t)L.W;
+    a.B = B;
+    a.goff = (uint64_t)replicate_offset;
+    a.key0 = (uint32_t)rng_key;
+    a.key1 = (uint32_t)(rng_key >> 32);
+    a.prev = jb->pl[0];
+    a.next = jb->pl[1];
+    a.aux = jb->pl[2];
+    a.model = prm->model;
+    a.ic_prob = prm->ic_prob;
+    a.ic_t = threshold_of(prm->p);
+    a.edge_t = edge_t.empty() ? nullptr : (const uint32_t *)(base + L.edge_t);
+    a.tinf = (const uint32_t *)(base + L.tinf);
+    a.khat = (int32_t)L.n_tinf - 1;
+    a.trec = prm->model == FSG_SI ? 0u : threshold_of(prm->gamma);
+    a.G = s.G;
+    a.S = s.S;
+    a.lgG = s.lgG;
+    a.lgS = s.lgS;
+    a.heavy = s.heavy;
+    a.tiles = (const int32_t *)(base + L.tiles);
+    a.n_tiles = (int32_t)(p.tiles.size() / 2);
+    a.seg_row = (const int32_t *)(base + L.seg_row);
+    a.seg_e0 = (const int32_t *)(base + L.seg_e0);
+    a.seg_e1 = (const int32_t *)(base + L.seg_e1);
+    a.n_seg = (int32_t)p.seg_row.size();
+    a.heavy_rows = (const int32_t *)(base + L.heavy_rows);
+    a.heavy_seg = (const int32_t *)(base + L.heavy_seg);
+    a.n_heavy = (int32_t)p.heavy_rows.size();
+    a.partial = (uint64_t *)(base + L.partial);
+    a.Lp = L.L;
+    a.flags = flags;
+    a.ring = ring;
+    a.sum_shift = L.sum_shift;
+    a.sum_words = L.sum_words;
+    return FSG_OK;
+}
+
+// Packed planes of the step `steps_run` -> uint8 states and counts.
+int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32_t *counts,
+                 hipStream_t st)
+{
+    if (!final_states && !counts) return FSG_OK;
+    FinArgs f;
+    memset(&f, 0, sizeof(f));
+    f.n = (int32_t)jb.n;
+    f.W = (int32_t)jb.L.W;
+    f.G = (int)std::min<int64_t>(next_pow2(jb.L.W), 64);
+    f.lgG = ilog2(f.G);
+    f.B = jb.B;
+    f.model = jb.model;
+    f.one = jb.pl[steps_run & 1];
+    f.two = jb.kind == kKindLT ? nullptr : jb.pl[2];
+    if (jb.model == FSG_SIS || jb.model == FSG_SI) f.two = nullptr;
+    f.states = final_states;
+    f.counts = counts;
+    f.bm = jb.s.edge1 ? jb.bm[steps_run & 1] : nullptr;
+    HIP_TRY(launch_finalize(f, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return FSG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int fsg_abi_version(void) { return FSG_ABI_VERSION; }
@@ -516,16 +685,9 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
                  fsg_run_info *info, void *stream)
 {
     try {
-        int rc = check_params(g_, prm, B);
-        if (rc) return rc;
         fsg_graph *g = const_cast<fsg_graph *>(g_);
-        if (!g->bound) return fail(FSG_EINVAL, "graph is not bound to device memory");
-        if (replicate_offset < 0 || replicate_offset + B > ((int64_t)1 << 34))
-            return fail(FSG_EINVAL, "replicate_offset + B must lie in [0, 2^34]");
-        if (n_seeds < 0 || (n_seeds > 0 && !seeds)) return fail(FSG_EINVAL, "bad seed array");
-        for (int64_t i = 0; i < n_seeds; ++i)
-            if (seeds[i] < 0 || (int64_t)seeds[i] >= g->n)
-                return fail(FSG_EINVAL, "seed out of range at index " + std::to_string(i));
+        int rc = validate_run(g, prm, seeds, n_seeds, B, replicate_offset);
+        if (rc) return rc;
         Sched s;
         rc = resolve_sched(g, prm, B, sched, &s);
         if (rc) return rc;
@@ -535,97 +697,15 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         if (!dev_ws || ws_bytes < L.total) return fail(FSG_EWORKSPACE, "simulation workspace too small");
         if (((uintptr_t)dev_ws & 255) != 0) return fail(FSG_EWORKSPACE, "workspace not 256-byte aligned");
         hipStream_t st = (hipStream_t)stream;
+        Job jb;
         char *base = (char *)dev_ws;
-        const int kind = model_kind(prm->model);
-        uint64_t *pl[3] = {(uint64_t *)(base + L.planes[0]), (uint64_t *)(base + L.planes[1]),
-                           L.n_planes > 2 ? (uint64_t *)(base + L.planes[2]) : nullptr};
-        // plane roles: IC {F0, F1, A}; epidemic {h0, h1, r}; LT {act0, act1}
-        uint32_t *flags = (uint32_t *)(base + L.flags);
-        const int ring = s.sync + 1;
-
-        // ---- uploads
-        std::vector<uint32_t> tinf = {0u};
-        if (kind == kKindEpidemic) tinf = infection_table(prm->beta, g->max_indeg);
-        std::vector<uint32_t> edge_t;
-        if (prm->model == FSG_IC && prm->ic_prob == FSG_IC_PER_EDGE) {
-            edge_t.resize((size_t)g->nnz);
-            for (int64_t e = 0; e < g->nnz; ++e) edge_t[(size_t)e] = threshold_of(prm->edge_p[e]);
-        }
-        auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
-            if (bytes == 0) return hipSuccess;
-            return hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, st);
-        };
-        HIP_TRY(up(L.tiles, p.tiles.data(), p.tiles.size() * 4));
-        HIP_TRY(up(L.heavy_rows, p.heavy_rows.data(), p.heavy_rows.size() * 4));
-        HIP_TRY(up(L.heavy_seg, p.heavy_seg.data(), p.heavy_seg.size() * 4));
-        HIP_TRY(up(L.seg_row, p.seg_row.data(), p.seg_row.size() * 4));
-        HIP_TRY(up(L.seg_e0, p.seg_e0.data(), p.seg_e0.size() * 4));
-        HIP_TRY(up(L.seg_e1, p.seg_e1.data(), p.seg_e1.size() * 4));
-        HIP_TRY(up(L.tinf, tinf.data(), tinf.size() * 4));
-        HIP_TRY(up(L.edge_t, edge_t.data(), edge_t.size() * 4));
-
-        // ---- initial states: everything 0, seeds 1 in every replicate
-        for (int i = 0; i < L.n_planes; ++i) HIP_TRY(launch_fill64(pl[i], L.plane_words, 0ull, st));
-        HIP_TRY(launch_fill32(flags, ring, 0u, st));
-        uint32_t *bm[2] = {nullptr, nullptr}, *sum[2] = {nullptr, nullptr};
-        if (s.edge1) {
-            for (int i = 0; i < 2; ++i) {
-                bm[i] = (uint32_t *)(base + L.bm[i]);
-                sum[i] = (uint32_t *)(base + L.sum[i]);
-                HIP_TRY(launch_fill32(bm[i], (g->n + 31) / 32, 0u, st));
-                HIP_TRY(launch_fill32(sum[i], L.sum_words, 0u, st));
-            }
-        }
-        int32_t *dseeds = (int32_t *)(base + L.seeds);
-        for (int64_t i0 = 0; i0 < n_seeds; i0 += L.n_seed_stage) {
-            const int64_t cnt = std::min<int64_t>(L.n_seed_stage, n_seeds - i0);
-            HIP_TRY(hipMemcpyAsync(dseeds, seeds + i0, (size_t)cnt * 4, hipMemcpyHostToDevice, st));
-            uint64_t *second = kind == kKindIC ? pl[2] : nullptr;  // IC: A too
-            HIP_TRY(launch_seed(pl[0], second, dseeds, cnt, (int32_t)L.W, B, flags, bm[0], sum[0],
-                                L.sum_shift, st));
-            HIP_TRY(hipStreamSynchronize(st));
-        }
-        HIP_TRY(hipStreamSynchronize(st));
-
-        // ---- step loop
-        StepArgs a;
-        memset(&a, 0, sizeof(a));
-        a.ptr = g->d_ptr;
-        a.src = g->d_src;
-        a.n = (int32_t)g->n;
-        a.W = (int32_t)L.W;
-        a.B = B;
-        a.goff = (uint64_t)replicate_offset;
-        a.key0 = (uint32_t)rng_key;
-        a.key1 = (uint32_t)(rng_key >> 32);
-        a.aux = pl[2];
-        a.model = prm->model;
-        a.ic_prob = prm->ic_prob;
-        a.ic_t = threshold_of(prm->p);
-        a.edge_t = edge_t.empty() ? nullptr : (const uint32_t *)(base + L.edge_t);
-        a.tinf = (const uint32_t *)(base + L.tinf);
-        a.khat = (int32_t)L.n_tinf - 1;
-        a.trec = prm->model == FSG_SI ? 0u : threshold_of(prm->gamma);
-        a.G = s.G;
-        a.S = s.S;
-        a.lgG = s.lgG;
-        a.lgS = s.lgS;
-        a.heavy = s.heavy;
-        a.tiles = (const int32_t *)(base + L.tiles);
-        a.n_tiles = (int32_t)(p.tiles.size() / 2);
-        a.seg_row = (const int32_t *)(base + L.seg_row);
-        a.seg_e0 = (const int32_t *)(base + L.seg_e0);
-        a.seg_e1 = (const int32_t *)(base + L.seg_e1);
-        a.n_seg = (int32_t)p.seg_row.size();
-        a.heavy_rows = (const int32_t *)(base + L.heavy_rows);
-        a.heavy_seg = (const int32_t *)(base + L.heavy_seg);
-        a.n_heavy = (int32_t)p.heavy_rows.size();
-        a.partial = (uint64_t *)(base + L.partial);
-        a.Lp = L.L;
-        a.flags = flags;
-        a.ring = ring;
-        a.sum_shift = L.sum_shift;
-        a.sum_words = L.sum_words;
+        rc = setup_job(g, prm, seeds, n_seeds, B, replicate_offset, rng_key, s, p, L, base,
+                       (uint32_t *)(base + L.flags), st, &jb);
+        if (rc) return rc;
+        StepArgs &a = jb.a;
+        const int kind = jb.kind;
+        const int ring = jb.ring;
+        uint32_t *flags = a.flags;
         int edge_grid = 0;
         if (s.edge1) {
             int dev = 0, ncu = 0;
@@ -634,7 +714,8 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
             edge_grid = 3 * std::max(ncu, 1);  // ~41 KB of LDS a block: three per CU
         }
 
-        const int64_t K = prm->max_steps < 0 ? g->n : prm->max_steps;
+        // ---- step loop: chunks of `sync` steps, then a poll of the flags
+        const int64_t K = jb.K;
         int64_t steps_run = 0;
         bool absorbed = n_seeds == 0;
         std::vector<uint32_t> hflags((size_t)ring);
@@ -649,18 +730,18 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
             for (int64_t i = 1; i <= c; ++i) {
                 const int64_t step = t + i;
                 a.step = (uint32_t)step;
-                a.prev = pl[(step - 1) & 1];
-                a.next = pl[step & 1];
+                a.prev = jb.pl[(step - 1) & 1];
+                a.next = jb.pl[step & 1];
                 if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
                 if (s.edge1) {
-                    a.bm_prev = bm[(step - 1) & 1];
-                    a.bm_next = bm[step & 1];
-                    a.sum_prev = sum[(step - 1) & 1];
-                    a.sum_next = sum[step & 1];
+                    a.bm_prev = jb.bm[(step - 1) & 1];
+                    a.bm_next = jb.bm[step & 1];
+                    a.sum_prev = jb.sum[(step - 1) & 1];
+                    a.sum_next = jb.sum[step & 1];
                     HIP_TRY(launch_ic_clear(a, st));
                     HIP_TRY(launch_ic_edge1(a, edge_grid, s.block, st));
                 } else {
-                    HIP_TRY(launch_step(a, kind, L.L, s.block, st));
+                    HIP_TRY(launch_step(a, kind, jb.L.L, s.block, st));
                     if (a.n_heavy > 0) HIP_TRY(launch_combine(a, kind, s.block, st));
                 }
                 if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
@@ -686,26 +767,8 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
                 }
             t += c;
         }
-
-        // ---- outputs
-        if (final_states || infected_counts) {
-            FinArgs f;
-            memset(&f, 0, sizeof(f));
-            f.n = (int32_t)g->n;
-            f.W = (int32_t)L.W;
-            f.G = (int)std::min<int64_t>(next_pow2(L.W), 64);
-            f.lgG = ilog2(f.G);
-            f.B = B;
-            f.model = prm->model;
-            f.one = pl[steps_run & 1];
-            f.two = kind == kKindLT ? nullptr : pl[2];
-            if (prm->model == FSG_SIS || prm->model == FSG_SI) f.two = nullptr;
-            f.states = final_states;
-            f.counts = infected_counts;
-            f.bm = s.edge1 ? bm[steps_run & 1] : nullptr;
-            HIP_TRY(launch_finalize(f, st));
-            HIP_TRY(hipStreamSynchronize(st));
-        }
+        rc = finalize_job(jb, steps_run, final_states, infected_counts, st);
+        if (rc) return rc;
         if (info) {
             info->steps_run = steps_run;
             info->absorbed = absorbed ? 1 : 0;
@@ -726,6 +789,429 @@ int fsg_philox4x32_10(const uint32_t *dev_ctr, uint32_t key0, uint32_t key1, uin
         return fail(FSG_EINVAL, "bad philox arguments");
     HIP_TRY(launch_philox(dev_ctr, key0, key1, dev_out, count, (hipStream_t)stream));
     return FSG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct fsg_plan {
+    std::vector<fsg_job> jobs;
+    std::vector<Sched> sched;
+    std::vector<const Plan *> plans;
+    std::vector<Layout> layouts;
+    std::vector<size_t> job_off;  // workspace offset of each job
+    size_t ctl_off = 0, total = 0;
+    int sync = 16;
+};
+
+namespace {
+
+int resolve_batch_sched(const fsg_job &j, Sched *s)
+{
+    fsg_schedule u = j.sched;
+    if (u.kernel_variant == 2) return fail(FSG_EINVAL, "batched jobs use kernel_variant 0 or 1");
+    u.kernel_variant = 1;
+    u.block_threads = kBatchBlock;
+    return resolve_sched(j.g, &j.prm, j.B, &u, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fsg_batch_plan(const fsg_job *jobs, int32_t n_jobs, int32_t steps_per_sync, fsg_plan **out,
+                   size_t *ws_bytes)
+{
+    try {
+        if (!out || !ws_bytes) return fail(FSG_EINVAL, "NULL output");
+        *out = nullptr;
+        if (!jobs || n_jobs < 1 || n_jobs > kMaxBatchJobs)
+            return fail(FSG_EINVAL, "n_jobs must be in [1, 1024]");
+        if (steps_per_sync < 1 || steps_per_sync > 4096)
+            return fail(FSG_EINVAL, "steps_per_sync must be in [1, 4096]");
+        std::unique_ptr<fsg_plan> pl(new fsg_plan);
+        pl->sync = steps_per_sync;
+        size_t off = 0;
+        for (int32_t i = 0; i < n_jobs; ++i) {
+            const fsg_job &j = jobs[i];
+            fsg_graph *g = const_cast<fsg_graph *>(j.g);
+            int rc = validate_run(g, &j.prm, j.seeds, j.n_seeds, j.B, j.replicate_offset);
+            if (rc) return fail(rc, "job " + std::to_string(i) + ": " + g_err);
+            Sched s;
+            rc = resolve_batch_sched(j, &s);
+            if (rc) return fail(rc, "job " + std::to_string(i) + ": " + g_err);
+            s.sync = steps_per_sync;
+            const Plan &p = get_plan(g, s.heavy, s.tile_edges);
+            Layout L;
+            layout(g, &j.prm, j.B, s, p, &L);
+            pl->jobs.push_back(j);
+            pl->sched.push_back(s);
+            pl->plans.push_back(&p);
+            pl->layouts.push_back(L);
+            pl->job_off.push_back(off);
+            off = align256(off + L.total);
+        }
+        pl->ctl_off = off;
+        const size_t n = (size_t)n_jobs, ring = (size_t)steps_per_sync + 1;
+        off = align256(off + n * sizeof(StepArgs));       // job table
+        off = align256(off + (n + 1) * 4 * 2 + n * 4 * 2);  // item_off, comb_off, code, max_step
+        off = align256(off + 16);                           // queue[2], cur_step
+        off = align256(off + n * ring * 4);                 // flag rings
+        pl->total = off;
+        *ws_bytes = off;
+        *out = pl.release();
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+int fsg_plan_destroy(fsg_plan *plan)
+{
+    delete plan;
+    return FSG_OK;
+}
+
+int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *infos,
+                  double *total_ms, void *stream)
+{
+    try {
+        if (!pl) return fail(FSG_EINVAL, "plan is NULL");
+        if (!dev_ws || ws_bytes < pl->total) return fail(FSG_EWORKSPACE, "batch workspace too small");
+        if (((uintptr_t)dev_ws & 255) != 0) return fail(FSG_EWORKSPACE, "workspace not 256-byte aligned");
+        hipStream_t st = (hipStream_t)stream;
+        char *base = (char *)dev_ws;
+        const int n = (int)pl->jobs.size();
+        const int ring = pl->sync + 1;
+        // control area
+        char *ctl = base + pl->ctl_off;
+        StepArgs *d_jobs = (StepArgs *)ctl;
+        char *q = ctl + align256((size_t)n * sizeof(StepArgs));
+        int32_t *d_item_off = (int32_t *)q;
+        int32_t *d_comb_off = d_item_off + (n + 1);
+        int32_t *d_code = d_comb_off + (n + 1);
+        int32_t *d_max_step = d_code + n;
+        q += align256((size_t)(n + 1) * 4 * 2 + (size_t)n * 4 * 2);
+        uint32_t *d_queue = (uint32_t *)q;
+        uint32_t *d_step = d_queue + 2;
+        q += align256(16);
+        uint32_t *d_flags = (uint32_t *)q;
+
+        std::vector<Job> jb((size_t)n);
+        std::vector<StepArgs> h_jobs((size_t)n);
+        std::vector<int32_t> item_off((size_t)n + 1, 0), comb_off((size_t)n + 1, 0),
+            code((size_t)n), max_step((size_t)n);
+        bool any_heavy = false;
+        for (int i = 0; i < n; ++i) {
+            const fsg_job &j = pl->jobs[(size_t)i];
+            fsg_graph *g = const_cast<fsg_graph *>(j.g);
+            int rc = setup_job(g, &j.prm, j.seeds, j.n_seeds, j.B, j.replicate_offset, j.rng_key,
+                               pl->sched[(size_t)i], *pl->plans[(size_t)i], pl->layouts[(size_t)i],
+                               base + pl->job_off[(size_t)i], d_flags + (size_t)i * ring, st,
+                               &jb[(size_t)i]);
+            if (rc) return rc;
+            const StepArgs &a = jb[(size_t)i].a;
+            h_jobs[(size_t)i] = a;  // prev/next hold planes 0 and 1
+            item_off[(size_t)i + 1] = item_off[(size_t)i] + step_blocks(a, kBatchBlock);
+            const int rows_per_combine = 4 * (64 >> a.lgG);
+            comb_off[(size_t)i + 1] =
+                comb_off[(size_t)i] + (a.n_heavy + rows_per_combine - 1) / rows_per_combine;
+            any_heavy |= a.n_heavy > 0;
+            code[(size_t)i] = jb[(size_t)i].kind * 32 + (jb[(size_t)i].kind == kKindIC ? 1 : a.Lp);
+            max_step[(size_t)i] = (int32_t)std::min<int64_t>(jb[(size_t)i].K, 0x7FFFFFFF);
+        }
+        HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs.data(), (size_t)n * sizeof(StepArgs), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_item_off, item_off.data(), item_off.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_comb_off, comb_off.data(), comb_off.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_code, code.data(), code.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_max_step, max_step.data(), max_step.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_fill32(d_queue, 2, 0u, st));
+        HIP_TRY(launch_fill32(d_step, 1, 1u, st));
+        HIP_TRY(hipStreamSynchronize(st));
+
+        BatchCtl c;
+        c.jobs = d_jobs;
+        c.item_off = d_item_off;
+        c.comb_off = d_comb_off;
+        c.code = d_code;
+        c.max_step = d_max_step;
+        c.n_jobs = n;
+        c.ring = ring;
+        c.queue = d_queue;
+        c.cur_step = d_step;
+        int dev = 0, ncu = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        const int grid = std::max(1, std::min(4 * std::max(ncu, 1), item_off[(size_t)n]));
+        const int cgrid = std::max(1, std::min(2 * std::max(ncu, 1), comb_off[(size_t)n]));
+
+        // capture one chunk of steps in a graph on a private stream
+        struct Cap {
+            hipStream_t s = nullptr;
+            hipGraph_t g = nullptr;
+            hipGraphExec_t e = nullptr;
+            ~Cap()
+            {
+                if (e) (void)hipGraphExecDestroy(e);
+                if (g) (void)hipGraphDestroy(g);
+                if (s) (void)hipStreamDestroy(s);
+            }
+        } cap;
+        HIP_TRY(hipStreamCreateWithFlags(&cap.s, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < pl->sync; ++i) {
+            hipError_t e1 = launch_batch_step(c, grid, cap.s);
+            hipError_t e2 = any_heavy ? launch_batch_combine(c, cgrid, cap.s) : hipSuccess;
+            hipError_t e3 = launch_batch_advance(c, cap.s);
+            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+                hipGraph_t dummy = nullptr;
+                (void)hipStreamEndCapture(cap.s, &dummy);
+                if (dummy) (void)hipGraphDestroy(dummy);
+                return fail(FSG_EDEVICE, std::string("batched launch capture failed: ") +
+                                             hipGetErrorString(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
+            }
+        }
+        HIP_TRY(hipStreamEndCapture(cap.s, &cap.g));
+        HIP_TRY(hipGraphInstantiate(&cap.e, cap.g, nullptr, nullptr, 0));
+
+        std::vector<uint32_t> hf((size_t)n * ring);
+        std::vector<int64_t> steps_run((size_t)n, 0);
+        std::vector<int> done((size_t)n, 0), absorbed((size_t)n, 0);
+        int remaining = 0;
+        for (int i = 0; i < n; ++i) {
+            const fsg_job &j = pl->jobs[(size_t)i];
+            if (j.n_seeds == 0 || jb[(size_t)i].K == 0) {
+                done[(size_t)i] = 1;
+                absorbed[(size_t)i] = j.n_seeds == 0;
+            } else {
+                ++remaining;
+            }
+        }
+        EventPool ev;
+        HIP_TRY(ev.init(2));
+        double kernel_ms = 0.0;
+        int64_t t0 = 0;
+        while (remaining > 0) {
+            HIP_TRY(hipEventRecord(ev.e[0], st));
+            HIP_TRY(hipGraphLaunch(cap.e, st));
+            HIP_TRY(hipEventRecord(ev.e[1], st));
+            HIP_TRY(hipMemcpyAsync(hf.data(), d_flags, hf.size() * 4, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+            kernel_ms += ms;
+            for (int i = 0; i < n; ++i) {
+                if (done[(size_t)i]) continue;
+                const uint32_t *f = hf.data() + (size_t)i * ring;
+                for (int k = 1; k <= pl->sync; ++k) {
+                    const int64_t t = t0 + k;
+                    if (f[t % ring] == 0u) {
+                        done[(size_t)i] = 1;
+                        absorbed[(size_t)i] = 1;
+                        steps_run[(size_t)i] = t;
+                        break;
+                    }
+                    if (t == jb[(size_t)i].K) {
+                        done[(size_t)i] = 1;
+                        steps_run[(size_t)i] = t;
+                        break;
+                    }
+                }
+                if (done[(size_t)i]) --remaining;
+            }
+            t0 += pl->sync;
+        }
+        for (int i = 0; i < n; ++i) {
+            const fsg_job &j = pl->jobs[(size_t)i];
+            int rc = finalize_job(jb[(size_t)i], steps_run[(size_t)i], j.final_states,
+                                  j.infected_counts, st);
+            if (rc) return rc;
+            if (infos) {
+                infos[i].steps_run = steps_run[(size_t)i];
+                infos[i].absorbed = absorbed[(size_t)i];
+                infos[i].reserved = 0;
+                infos[i].step_kernel_ms = 0.0;
+                infos[i].step_launches = 0;
+            }
+        }
+        if (total_ms) *total_ms = kernel_ms;
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------- autotuner
+
+namespace {
+
+std::vector<fsg_schedule> candidates(const fsg_graph *g, const fsg_params *prm, int64_t B,
+                                     bool batch_only)
+{
+    std::vector<fsg_schedule> out;
+    const int64_t W = (B + 63) / 64;
+    const int gmax = (int)std::min<int64_t>(next_pow2(W), 64);
+    auto add = [&](int lanes, int block, int tile, int heavy, int variant) {
+        fsg_schedule s;
+        memset(&s, 0, sizeof(s));
+        s.row_lanes = lanes;
+        s.block_threads = block;
+        s.tile_edges = tile;
+        s.heavy_threshold = heavy;
+        s.steps_per_sync = 16;
+        s.kernel_variant = variant;
+        out.push_back(s);
+    };
+    if (!batch_only && prm->model == FSG_IC && W == 1) {
+        for (int block : {256, 512, 1024})
+            for (int tile : {8192, 16384, 32768})
+                for (int heavy : {8192, 32768}) add(16, block, tile, heavy, 2);
+    }
+    std::vector<int> lanes;
+    for (int l = gmax; l <= 64; l *= 2) lanes.push_back(l);
+    if (gmax < 16 && std::find(lanes.begin(), lanes.end(), 16) == lanes.end()) lanes.push_back(16);
+    for (int l : lanes)
+        for (int block : batch_only ? std::vector<int>{kBatchBlock} : std::vector<int>{256, 512})
+            for (int tile : {2048, 4096, 16384})
+                for (int heavy : {512, 1024, 4096}) add(l, block, tile, heavy, 1);
+    (void)g;
+    return out;
+}
+
+std::string tune_key(const fsg_graph *g, const fsg_params *prm, int64_t B, bool batch_only)
+{
+    std::ostringstream k;
+    k << "n=" << g->n << ",nnz=" << g->nnz << ",dmax=" << g->max_indeg << ",model=" << prm->model
+      << ",icp=" << prm->ic_prob << ",B=" << B << ",batch=" << (batch_only ? 1 : 0);
+    return k.str();
+}
+
+bool cache_lookup(const char *path, const std::string &key, fsg_schedule *out, double *ms)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        fsg_schedule s;
+        memset(&s, 0, sizeof(s));
+        double m = 0;
+        if (!(is >> k >> s.row_lanes >> s.block_threads >> s.tile_edges >> s.heavy_threshold >>
+              s.steps_per_sync >> s.kernel_variant >> m))
+            continue;
+        if (k == key) {  // the last entry for a key wins
+            *out = s;
+            *ms = m;
+            found = true;
+        }
+    }
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const fsg_schedule &s, double ms)
+{
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << s.row_lanes << " " << s.block_threads << " " << s.tile_edges << " "
+      << s.heavy_threshold << " " << s.steps_per_sync << " " << s.kernel_variant << " " << ms
+      << "\n";
+}
+
+}  // namespace
+
+extern "C" {
+
+int fsg_autotune_workspace_size(const fsg_graph *g_, const fsg_params *prm, int64_t B,
+                                int32_t batch_only, size_t *bytes)
+{
+    try {
+        if (!bytes) return fail(FSG_EINVAL, "bytes is NULL");
+        int rc = check_params(g_, prm, B);
+        if (rc) return rc;
+        size_t best = 0;
+        fsg_schedule d;
+        default_sched(g_, prm, B, &d);
+        std::vector<fsg_schedule> cs = candidates(g_, prm, B, batch_only != 0);
+        cs.push_back(d);
+        for (const fsg_schedule &s : cs) {
+            size_t b = 0;
+            rc = fsg_sim_workspace_size(g_, prm, B, &s, &b);
+            if (rc) return rc;
+            best = std::max(best, b);
+        }
+        *bytes = best;
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+int fsg_autotune(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t n_seeds,
+                 int64_t B, uint64_t rng_key, int32_t tune_steps, int32_t batch_only,
+                 const char *cache_path, void *dev_ws, size_t ws_bytes, fsg_schedule *best,
+                 double *best_ms, double *default_ms, void *stream)
+{
+    try {
+        if (!best) return fail(FSG_EINVAL, "best is NULL");
+        if (tune_steps < 1) return fail(FSG_EINVAL, "tune_steps must be >= 1");
+        int rc = check_params(g, prm, B);
+        if (rc) return rc;
+        const std::string key = tune_key(g, prm, B, batch_only != 0);
+        double cached_ms = 0;
+        if (cache_lookup(cache_path, key, best, &cached_ms)) {
+            if (best_ms) *best_ms = cached_ms;
+            if (default_ms) *default_ms = -1.0;
+            return FSG_OK;
+        }
+        fsg_params tp = *prm;
+        tp.max_steps = prm->max_steps < 0 ? tune_steps : std::min<int64_t>(prm->max_steps, tune_steps);
+        auto time_one = [&](const fsg_schedule &s0, double *ms) -> int {
+            fsg_schedule s = s0;
+            s.time_kernels = 1;
+            s.steps_per_sync = std::max(1, std::min(tune_steps, 64));
+            fsg_run_info info;
+            int r = fsg_simulate(g, &tp, seeds, n_seeds, B, 0, rng_key, &s, dev_ws, ws_bytes,
+                                 nullptr, nullptr, &info, stream);
+            if (r) return r;
+            *ms = info.step_launches > 0 ? info.step_kernel_ms / (double)info.step_launches : 1e30;
+            return FSG_OK;
+        };
+        fsg_schedule d;
+        default_sched(g, prm, B, &d);
+        if (batch_only) {
+            d.kernel_variant = 1;
+            d.block_threads = kBatchBlock;
+        }
+        double dms = 0;
+        rc = time_one(d, &dms);  // also a warm-up of the code objects
+        if (rc) return rc;
+        rc = time_one(d, &dms);
+        if (rc) return rc;
+        fsg_schedule win = d;
+        double wms = dms;
+        for (const fsg_schedule &s : candidates(g, prm, B, batch_only != 0)) {
+            double ms = 0;
+            rc = time_one(s, &ms);
+            if (rc) return rc;
+            if (ms < wms) {
+                wms = ms;
+                win = s;
+            }
+        }
+        win.time_kernels = 0;
+        *best = win;
+        if (best_ms) *best_ms = wms;
+        if (default_ms) *default_ms = dms;
+        cache_store(cache_path, key, win, wms);
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
 }
 
 }  // extern "C"

@@ -79,6 +79,24 @@ struct FinArgs {
     uint32_t *counts;     // [n] or null
 };
 
+// Many jobs in one launch per synchronous step.  Each job keeps its own
+// StepArgs (prev/next hold its planes 0 and 1; step is filled in by the
+// kernel from *cur_step).  Work items are the step blocks of every job
+// (prefix item_off) and the heavy-row combine groups (prefix comb_off).
+constexpr int kMaxBatchJobs = 1024;
+
+struct BatchCtl {
+    const StepArgs *jobs;     // [n_jobs]
+    const int32_t *item_off;  // [n_jobs + 1]
+    const int32_t *comb_off;  // [n_jobs + 1]
+    const int32_t *code;      // [n_jobs]: kind * 32 + counter planes
+    const int32_t *max_step;  // [n_jobs]
+    int32_t n_jobs;
+    int32_t ring;
+    uint32_t *queue;          // [2] dequeue counters (step items, combine items)
+    uint32_t *cur_step;       // the step the next launch executes
+};
+
 // launchers (fsg_kernels.hip); return the hipError_t of the launch
 hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
@@ -94,5 +112,10 @@ hipError_t launch_finalize(const FinArgs &f, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
                          int64_t count, hipStream_t s);
 int counter_planes_for(int64_t max_count);  // compile-time counter width to use
+int step_blocks(const StepArgs &a, int block);  // blocks of one job's pull step
+hipError_t launch_batch_step(const BatchCtl &c, int grid, hipStream_t s);
+hipError_t launch_batch_combine(const BatchCtl &c, int grid, hipStream_t s);
+hipError_t launch_batch_advance(const BatchCtl &c, hipStream_t s);
+constexpr int kBatchBlock = 256;  // block size of the batched kernels
 
 }  // namespace fsg

@@ -304,19 +304,13 @@ __device__ __forceinline__ void row_word(const StepArgs &a, int G, int S, bool v
     }
 }
 
-// One synchronous step t = a.step.  The first blocks own heavy-row segments
-// (one per row slot; long, so they start first), the rest own light tiles.
+// Work of one block of the pull step: block `bid` < seg_blocks owns heavy-row
+// segments (one per row slot; long, so they start first), the rest own light
+// tiles.  Returns through `any` whether a state-1 node remains.
 template <int KIND, int L>
-__global__ void __launch_bounds__(1024) k_step(StepArgs a)
+__device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uint32_t *tl,
+                                           int tl_n, bool &any)
 {
-    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // nothing left to change
-    __shared__ uint32_t s_tinf[KIND == kKindEpidemic ? kTinfLds : 1];
-    int tl_n = 0;
-    if (KIND == kKindEpidemic) {
-        tl_n = a.khat + 1 < kTinfLds ? a.khat + 1 : kTinfLds;
-        for (int i = threadIdx.x; i < tl_n; i += blockDim.x) s_tinf[i] = a.tinf[i];
-        __syncthreads();
-    }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -327,10 +321,8 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
     const int s = (lane >> a.lgG) & (S - 1);
     const int gw = lane & (G - 1);
     const uint64_t share_fixed = S <= 16 ? share_bits(a.goff, s, S) : 0ull;
-    bool any = false;
     const int rows_per_block = nwaves * rpw;
     const int seg_blocks = (a.n_seg + rows_per_block - 1) / rows_per_block;
-    const int bid = blockIdx.x;
     if (bid >= seg_blocks) {
         const int tile = bid - seg_blocks;
         const int t0 = a.tiles[2 * tile], t1 = a.tiles[2 * tile + 1];
@@ -346,7 +338,7 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
             for (int w0 = 0; w0 < a.W; w0 += G) {
                 const int w = w0 + gw;
                 row_word<KIND, L>(a, G, S, act && w < a.W, v, w < a.W ? w : 0, e0, e1,
-                                  (uint32_t)(e1 - e0), s, -1, share_fixed, s_tinf, tl_n, any);
+                                  (uint32_t)(e1 - e0), s, -1, share_fixed, tl, tl_n, any);
             }
         }
     } else {
@@ -363,18 +355,34 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
         for (int w0 = 0; w0 < a.W; w0 += G) {
             const int w = w0 + gw;
             row_word<KIND, L>(a, G, S, act && w < a.W, v, w < a.W ? w : 0, e0, e1, indeg, s,
-                              act ? seg : 0, share_fixed, s_tinf, tl_n, any);
+                              act ? seg : 0, share_fixed, tl, tl_n, any);
         }
     }
-    if (__ballot(any) != 0ull && lane == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
 }
 
-// Merge of the segment partials of each heavy row, then the same update as
-// a light row.  G lanes per row over words, no edge split.
-template <int KIND, int LP>
-__global__ void __launch_bounds__(256) k_combine(StepArgs a)
+// One synchronous step t = a.step of one job.
+template <int KIND, int L>
+__global__ void __launch_bounds__(1024) k_step(StepArgs a)
 {
-    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
+    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // nothing left to change
+    __shared__ uint32_t s_tinf[KIND == kKindEpidemic ? kTinfLds : 1];
+    int tl_n = 0;
+    if (KIND == kKindEpidemic) {
+        tl_n = a.khat + 1 < kTinfLds ? a.khat + 1 : kTinfLds;
+        for (int i = threadIdx.x; i < tl_n; i += blockDim.x) s_tinf[i] = a.tinf[i];
+        __syncthreads();
+    }
+    bool any = false;
+    step_block<KIND, L>(a, blockIdx.x, s_tinf, tl_n, any);
+    if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+// Merge of the segment partials of heavy row group `bid` (rows_per_block
+// heavy rows), then the same update as a light row.  G lanes per row over
+// words, no edge split.
+template <int KIND, int LP>
+__device__ __forceinline__ void combine_block(const StepArgs &a, int bid, bool &any)
+{
     constexpr int LC = 32;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -383,11 +391,10 @@ __global__ void __launch_bounds__(256) k_combine(StepArgs a)
     const int rpw = 64 >> a.lgG;
     const int slot = lane >> a.lgG;
     const int gw = lane & (G - 1);
-    const int j = (blockIdx.x * nwaves + wave) * rpw + slot;
+    const int j = (bid * nwaves + wave) * rpw + slot;
     const bool act = j < a.n_heavy;
     const int v = act ? a.heavy_rows[j] : 0;
     const int sg0 = act ? a.heavy_seg[j] : 0, sg1 = act ? a.heavy_seg[j + 1] : 0;
-    bool any = false;
     for (int w0 = 0; w0 < a.W; w0 += G) {
         const int w = w0 + gw;
         const bool valid = act && w < a.W;
@@ -435,7 +442,15 @@ __global__ void __launch_bounds__(256) k_combine(StepArgs a)
             }
         }
     }
-    if (__ballot(any) != 0ull && lane == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+template <int KIND, int LP>
+__global__ void __launch_bounds__(256) k_combine(StepArgs a)
+{
+    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
+    bool any = false;
+    combine_block<KIND, LP>(a, blockIdx.x, any);
+    if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
 }
 
 // ------------------------------------------- IC, one word per node ----
@@ -609,6 +624,129 @@ __global__ void k_ic_clear(StepArgs a)
         if (i < nw) a.bm_next[i] = 0u;
         if (i < a.sum_words) a.sum_next[i] = 0u;
         if (i < a.n_heavy) a.next[a.heavy_rows[i]] = 0ull;
+    }
+}
+
+// ------------------------------------------------------------ batches ----
+// One launch per synchronous step for every job of a batch: persistent
+// blocks dequeue work items from one counter across all jobs (so jobs of very
+// different sizes share the chip), find the job by binary search over the
+// item prefix (LDS), skip jobs that are absorbed or past their step cap, and
+// run the job's own pull-step block.  Ordering between steps comes from the
+// kernel boundaries; the host captures a chunk of steps in a hipGraph.
+
+__device__ __forceinline__ int find_job(const int32_t *off, int n_jobs, int item)
+{
+    int lo = 0, hi = n_jobs - 1;  // last job whose first item is <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ StepArgs job_at_step(const BatchCtl &c, int j, uint32_t t)
+{
+    StepArgs a = c.jobs[j];
+    const uint64_t *p0 = a.prev;
+    uint64_t *p1 = a.next;
+    a.prev = (t & 1u) ? p0 : p1;   // state of step t-1
+    a.next = (t & 1u) ? p1 : const_cast<uint64_t *>(p0);
+    a.step = t;
+    return a;
+}
+
+__device__ __forceinline__ bool job_live(const BatchCtl &c, const StepArgs &a, int j, uint32_t t)
+{
+    return t <= (uint32_t)c.max_step[j] && a.flags[(t - 1) % (uint32_t)a.ring] != 0u;
+}
+
+__global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchCtl c)
+{
+    __shared__ int32_t s_off[kMaxBatchJobs + 1];
+    __shared__ int s_item;
+    const uint32_t t = *c.cur_step;
+    for (int i = threadIdx.x; i <= c.n_jobs; i += blockDim.x) s_off[i] = c.item_off[i];
+    __syncthreads();
+    const int total = s_off[c.n_jobs];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&c.queue[0], 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int j = __builtin_amdgcn_readfirstlane(find_job(s_off, c.n_jobs, item));
+        const StepArgs a = job_at_step(c, j, t);
+        if (!job_live(c, a, j, t)) continue;
+        const int local = item - s_off[j];
+        bool any = false;
+        switch (c.code[j]) {
+        case kKindIC * 32 + 1: step_block<kKindIC, 1>(a, local, nullptr, 0, any); break;
+        case kKindEpidemic * 32 + 2: step_block<kKindEpidemic, 2>(a, local, nullptr, 0, any); break;
+        case kKindEpidemic * 32 + 4: step_block<kKindEpidemic, 4>(a, local, nullptr, 0, any); break;
+        case kKindEpidemic * 32 + 8: step_block<kKindEpidemic, 8>(a, local, nullptr, 0, any); break;
+        case kKindEpidemic * 32 + 12: step_block<kKindEpidemic, 12>(a, local, nullptr, 0, any); break;
+        case kKindEpidemic * 32 + 16: step_block<kKindEpidemic, 16>(a, local, nullptr, 0, any); break;
+        case kKindLT * 32 + 2: step_block<kKindLT, 2>(a, local, nullptr, 0, any); break;
+        case kKindLT * 32 + 4: step_block<kKindLT, 4>(a, local, nullptr, 0, any); break;
+        case kKindLT * 32 + 8: step_block<kKindLT, 8>(a, local, nullptr, 0, any); break;
+        case kKindLT * 32 + 12: step_block<kKindLT, 12>(a, local, nullptr, 0, any); break;
+        case kKindLT * 32 + 16: step_block<kKindLT, 16>(a, local, nullptr, 0, any); break;
+        default: break;
+        }
+        if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[t % (uint32_t)a.ring] = 1u;
+    }
+}
+
+__global__ void __launch_bounds__(kBatchBlock) k_batch_combine(BatchCtl c)
+{
+    __shared__ int32_t s_off[kMaxBatchJobs + 1];
+    __shared__ int s_item;
+    const uint32_t t = *c.cur_step;
+    for (int i = threadIdx.x; i <= c.n_jobs; i += blockDim.x) s_off[i] = c.comb_off[i];
+    __syncthreads();
+    const int total = s_off[c.n_jobs];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&c.queue[1], 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int j = __builtin_amdgcn_readfirstlane(find_job(s_off, c.n_jobs, item));
+        const StepArgs a = job_at_step(c, j, t);
+        if (!job_live(c, a, j, t)) continue;
+        const int local = item - s_off[j];
+        bool any = false;
+        switch (c.code[j]) {
+        case kKindIC * 32 + 1: combine_block<kKindIC, 1>(a, local, any); break;
+        case kKindEpidemic * 32 + 2: combine_block<kKindEpidemic, 2>(a, local, any); break;
+        case kKindEpidemic * 32 + 4: combine_block<kKindEpidemic, 4>(a, local, any); break;
+        case kKindEpidemic * 32 + 8: combine_block<kKindEpidemic, 8>(a, local, any); break;
+        case kKindEpidemic * 32 + 12: combine_block<kKindEpidemic, 12>(a, local, any); break;
+        case kKindEpidemic * 32 + 16: combine_block<kKindEpidemic, 16>(a, local, any); break;
+        case kKindLT * 32 + 2: combine_block<kKindLT, 2>(a, local, any); break;
+        case kKindLT * 32 + 4: combine_block<kKindLT, 4>(a, local, any); break;
+        case kKindLT * 32 + 8: combine_block<kKindLT, 8>(a, local, any); break;
+        case kKindLT * 32 + 12: combine_block<kKindLT, 12>(a, local, any); break;
+        case kKindLT * 32 + 16: combine_block<kKindLT, 16>(a, local, any); break;
+        default: break;
+        }
+        if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[t % (uint32_t)a.ring] = 1u;
+    }
+}
+
+// End of step t: clear every job's flag slot for step t+1, reset the
+// dequeue counters and advance the step.
+__global__ void k_batch_advance(BatchCtl c)
+{
+    const uint32_t t = *c.cur_step;
+    for (int j = threadIdx.x; j < c.n_jobs; j += blockDim.x)
+        c.jobs[j].flags[(t + 1) % (uint32_t)c.ring] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c.queue[0] = 0u;
+        c.queue[1] = 0u;
+        *c.cur_step = t + 1;
     }
 }
 
@@ -848,6 +986,30 @@ hipError_t launch_ic_clear(const StepArgs &a, hipStream_t s)
 {
     const int64_t work = std::max<int64_t>(((int64_t)a.n + 31) >> 5, a.n_heavy);
     hipLaunchKernelGGL(k_ic_clear, dim3(grid_for(work, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int step_blocks(const StepArgs &a, int block)
+{
+    const int rows_per_block = (block / 64) * (64 >> (a.lgG + a.lgS));
+    return (a.n_seg + rows_per_block - 1) / rows_per_block + a.n_tiles;
+}
+
+hipError_t launch_batch_step(const BatchCtl &c, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_step, dim3((unsigned)grid), dim3(kBatchBlock), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_combine(const BatchCtl &c, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_combine, dim3((unsigned)grid), dim3(kBatchBlock), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(const BatchCtl &c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(256), 0, s, c);
     return hipGetLastError();
 }
 

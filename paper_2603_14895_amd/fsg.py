@@ -52,6 +52,14 @@ class fsg_schedule(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
+class fsg_job(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("prm", fsg_params), ("seeds", ctypes.c_void_p),
+                ("n_seeds", ctypes.c_int64), ("B", ctypes.c_int64),
+                ("replicate_offset", ctypes.c_int64), ("rng_key", ctypes.c_uint64),
+                ("sched", fsg_schedule), ("final_states", ctypes.c_void_p),
+                ("infected_counts", ctypes.c_void_p)]
+
+
 _lib = None
 _VP, _I64, _I32, _U32, _U64, _SZ = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t)
@@ -75,6 +83,17 @@ _SIGS = {
                                     ctypes.POINTER(fsg_run_info), _VP]),
     "fsg_philox4x32_10": (ctypes.c_int, [_VP, _U32, _U32, _VP, _I64, _VP]),
     "fsg_plan_row_tiles": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I64, _VP, ctypes.POINTER(_I64)]),
+    "fsg_batch_plan": (ctypes.c_int, [ctypes.POINTER(fsg_job), _I32, _I32, ctypes.POINTER(_VP),
+                                      ctypes.POINTER(_SZ)]),
+    "fsg_batch_run": (ctypes.c_int, [_VP, _VP, _SZ, ctypes.POINTER(fsg_run_info),
+                                     ctypes.POINTER(ctypes.c_double), _VP]),
+    "fsg_plan_destroy": (ctypes.c_int, [_VP]),
+    "fsg_autotune_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _I64, _I32,
+                                                   ctypes.POINTER(_SZ)]),
+    "fsg_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _U64, _I32,
+                                    _I32, ctypes.c_char_p, _VP, _SZ, ctypes.POINTER(fsg_schedule),
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), _VP]),
 }
 
 
@@ -176,6 +195,43 @@ def fsg_plan_row_tiles(in_ptr: np.ndarray, heavy: int, row_cost: int, n_parts: i
     _check(lib().fsg_plan_row_tiles(in_ptr.ctypes.data, n, heavy, row_cost, n_parts,
                                     out.ctypes.data, ctypes.byref(cnt)))
     return out[: cnt.value + 1].copy()
+
+
+def fsg_batch_plan(jobs_array, n_jobs, steps_per_sync):
+    h = ctypes.c_void_p()
+    nb = ctypes.c_size_t()
+    _check(lib().fsg_batch_plan(jobs_array, n_jobs, steps_per_sync, ctypes.byref(h),
+                                ctypes.byref(nb)))
+    return h.value, nb.value
+
+
+def fsg_batch_run(plan, dev_ws, ws_bytes, n_jobs, stream=None):
+    infos = (fsg_run_info * n_jobs)()
+    total = ctypes.c_double()
+    _check(lib().fsg_batch_run(plan, dev_ws, ws_bytes, infos, ctypes.byref(total), stream))
+    return list(infos), total.value
+
+
+def fsg_plan_destroy(plan):
+    _check(lib().fsg_plan_destroy(plan))
+
+
+def fsg_autotune_workspace_size(g, prm, B, batch_only):
+    b = ctypes.c_size_t()
+    _check(lib().fsg_autotune_workspace_size(g, ctypes.byref(prm), B, int(batch_only),
+                                             ctypes.byref(b)))
+    return b.value
+
+
+def fsg_autotune(g, prm, seeds_addr, n_seeds, B, rng_key, tune_steps, batch_only, cache_path,
+                 dev_ws, ws_bytes, stream=None):
+    best = fsg_schedule()
+    bms, dms = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fsg_autotune(g, ctypes.byref(prm), seeds_addr, n_seeds, B, rng_key & (2**64 - 1),
+                              tune_steps, int(batch_only),
+                              cache_path.encode() if cache_path else None, dev_ws, ws_bytes,
+                              ctypes.byref(best), ctypes.byref(bms), ctypes.byref(dms), stream))
+    return best, bms.value, dms.value
 
 
 # ---------------------------------------------------- torch-backed helpers --
@@ -283,3 +339,74 @@ def simulate(graph: DeviceGraph, model, seeds, B, rng_key, *, replicate_offset=0
     sim = Simulation(graph, model, B, schedule=schedule, want_states=want_states, **params)
     info = sim.run(seeds, rng_key, replicate_offset)
     return sim.states, sim.counts, int(info.steps_run), int(info.absorbed)
+
+
+def autotune(graph: DeviceGraph, model, seeds, B, rng_key, *, tune_steps=12, batch_only=False,
+             cache_path=None, **params):
+    """Runs the library's autotuner; returns (schedule dict, best ms/step, default ms/step)."""
+    prm, keep = make_params(model, **params)
+    nb = fsg_autotune_workspace_size(graph.handle, prm, int(B), batch_only)
+    ws, addr = _ws(nb, graph.device)
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+    best, bms, dms = fsg_autotune(graph.handle, prm, seeds.ctypes.data if seeds.size else None,
+                                  seeds.size, int(B), int(rng_key), int(tune_steps), batch_only,
+                                  cache_path, addr, nb, _stream_ptr())
+    del ws, keep
+    return best.as_dict(), bms, dms
+
+
+class Batch:
+    """Several jobs in one batched run (fsg_batch_plan / fsg_batch_run).
+
+    Each job is a dict: graph (DeviceGraph), model, seeds, B, rng_key and
+    model parameters, optionally replicate_offset and schedule."""
+
+    PARAM_KEYS = ("p", "ic_prob", "edge_p", "beta", "gamma", "max_steps")
+
+    def __init__(self, jobs, steps_per_sync=16, want_states=True, want_counts=True):
+        import torch
+        self.n = len(jobs)
+        self._keep = []
+        arr = (fsg_job * self.n)()
+        self.states, self.counts = [], []
+        for i, j in enumerate(jobs):
+            g = j["graph"]
+            prm, keep = make_params(j["model"], **{k: j[k] for k in self.PARAM_KEYS if k in j})
+            seeds = np.ascontiguousarray(j["seeds"], dtype=np.int32)
+            self._keep += [keep, seeds]
+            st = (torch.empty((g.n, j["B"]), dtype=torch.uint8, device=g.device)
+                  if want_states else None)
+            ct = torch.empty(g.n, dtype=torch.int32, device=g.device) if want_counts else None
+            self.states.append(st)
+            self.counts.append(ct)
+            a = arr[i]
+            a.g = g.handle
+            a.prm = prm
+            a.seeds = seeds.ctypes.data if seeds.size else None
+            a.n_seeds = seeds.size
+            a.B = int(j["B"])
+            a.replicate_offset = int(j.get("replicate_offset", 0))
+            a.rng_key = int(j["rng_key"]) & (2**64 - 1)
+            sc = make_schedule(j.get("schedule"))
+            if sc is not None:
+                a.sched = sc
+            a.final_states = st.data_ptr() if st is not None else None
+            a.infected_counts = ct.data_ptr() if ct is not None else None
+        self._arr = arr
+        self.plan, self.ws_bytes = fsg_batch_plan(arr, self.n, int(steps_per_sync))
+        self._ws, self.ws_addr = _ws(self.ws_bytes, jobs[0]["graph"].device)
+
+    def run(self, stream=None):
+        """Returns (list of fsg_run_info, total device ms of the step chunks)."""
+        return fsg_batch_run(self.plan, self.ws_addr, self.ws_bytes, self.n, _stream_ptr(stream))
+
+    def close(self):
+        if self.plan:
+            fsg_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -123,3 +123,24 @@ def test_row_tiles_load_balance_bound(heavy, parts):
         # the ideal plus one row
         assert (loads < total / parts + wmax).all()
     assert loads.sum() == total
+
+
+def test_batch_plan_validation():
+    ptr, src = _graph()
+    n, nnz = ptr.size - 1, src.size
+    h = fsg.fsg_graph_create(n, nnz, ptr.ctypes.data, src.ctypes.data)
+    try:
+        arr = (fsg.fsg_job * 1)()
+        prm, _ = fsg.make_params("ic", p=0.1)
+        arr[0].g = h
+        arr[0].prm = prm
+        arr[0].B = 10
+        with pytest.raises(fsg.FsgError) as e:
+            fsg.fsg_batch_plan(arr, 1, 8)  # graph not bound
+        assert e.value.code == fsg.FSG_EINVAL and "job 0" in str(e.value)
+        with pytest.raises(fsg.FsgError):
+            fsg.fsg_batch_plan(arr, 0, 8)
+        with pytest.raises(fsg.FsgError):
+            fsg.fsg_batch_plan(arr, 1, 0)
+    finally:
+        fsg.fsg_graph_destroy(h)

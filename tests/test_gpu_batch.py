@@ -1,0 +1,128 @@
+"""Batched launch and autotuner on the GPU: every job of a mixed batch gives
+the same bits as its solo run and as the oracle; tuned schedules change no
+result."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2603_14895_amd import workloads as W
+from tests.gpu_util import assert_same, gpu_run, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _params(j):
+    return {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps", "edge_p") if k in j}
+
+
+def _mixed_jobs():
+    rng = np.random.default_rng(11)
+    specs = [
+        ("ic", 2000, 8.0, 64, 0, dict(p=0.15, max_steps=-1), None),
+        ("sir", 3000, 12.0, 1024, 0, dict(beta=0.04, gamma=0.1, max_steps=30), None),
+        ("lt", 2500, 10.0, 100, 3, dict(max_steps=-1), None),
+        ("sis", 1500, 6.0, 63, 1, dict(beta=0.1, gamma=0.2, max_steps=25), None),
+        ("si", 1800, 5.0, 130, 0, dict(beta=0.05, max_steps=12), None),
+        ("ic", 4000, 15.0, 300, 7, dict(p=0.05, ic_prob="weighted_cascade", max_steps=-1),
+         dict(heavy_threshold=16, tile_edges=500)),
+        ("sir", 2200, 20.0, 200, 0, dict(beta=0.02, gamma=0.3, max_steps=40),
+         dict(row_lanes=4, heavy_threshold=30)),
+        ("lt", 3000, 18.0, 1, 0, dict(max_steps=-1), dict(heavy_threshold=12)),
+        ("ic", 1000, 10.0, 5, 0, dict(p=0.1, max_steps=2), None),
+        ("sir", 800, 8.0, 64, 0, dict(beta=0.3, gamma=0.3, max_steps=0), None),
+    ]
+    jobs = []
+    for i, (model, n, deg, B, off, prm, sched) in enumerate(specs):
+        gr = W.chung_lu(n, deg, 2.5, 700 + i)
+        k = int(rng.integers(1, 30))
+        seeds = W.uniform_seeds(gr.n, k, 800 + i) if i != 3 else np.array([], dtype=np.int32)
+        jobs.append(dict(gr=gr, model=model, B=B, replicate_offset=off, seeds=seeds,
+                         rng_key=0xBA7C0000 + i, schedule=sched, **prm))
+    return jobs
+
+
+def test_batch_equals_solo_and_oracle():
+    from paper_2603_14895_amd import fsg
+    jobs = _mixed_jobs()
+    dgs = [fsg.DeviceGraph(*j["gr"].numpy()) for j in jobs]
+    bj = [dict(graph=dg, **{k: v for k, v in j.items() if k != "gr"}) for dg, j in zip(dgs, jobs)]
+    for spsync in (5, 16):
+        batch = fsg.Batch(bj, steps_per_sync=spsync)
+        infos, total_ms = batch.run()
+        log(f"[batch] {len(jobs)} jobs, sync {spsync}: {total_ms:.2f} ms, "
+            f"steps {[int(x.steps_run) for x in infos]}")
+        for i, j in enumerate(jobs):
+            got = (batch.states[i].cpu().numpy(), batch.counts[i].cpu().numpy().astype(np.uint32),
+                   int(infos[i].steps_run), int(infos[i].absorbed))
+            gnp = j["gr"].numpy()
+            solo = gpu_run(gnp, j["model"], j["seeds"], j["B"], j["rng_key"],
+                           replicate_offset=j["replicate_offset"], schedule=j["schedule"],
+                           **_params(j))
+            assert_same(got, solo, f"job {i} batched vs solo")
+            ref = oracle_run(gnp, j["model"], j["seeds"], j["B"], j["rng_key"],
+                             replicate_offset=j["replicate_offset"], **_params(j))
+            assert_same(got, ref, f"job {i} batched vs oracle")
+        batch.close()
+
+
+def test_batch_mixed_workload_small():
+    """A reduced instance of the mixed batched workload (log-uniform sizes,
+    B and seed-set sizes; IC / SIR / LT), every job checked on sampled
+    replicates against the oracle and in full against its solo run."""
+    from paper_2603_14895_amd import fsg
+    specs = W.config_c3_jobs(n_jobs=9, n_hi=3e4, b_hi=700, seed_hi=100)
+    dgs, bj, grs = [], [], []
+    for sp in specs:
+        gr = W.build_c3_graph(sp)
+        grs.append(gr)
+        dg = fsg.DeviceGraph(*gr.numpy())
+        dgs.append(dg)
+        seeds = W.uniform_seeds(gr.n, sp["n_seeds"], sp["seed_seed"])
+        prm = {k: sp[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in sp}
+        bj.append(dict(graph=dg, model=sp["model"], B=sp["B"], seeds=seeds, rng_key=sp["key"], **prm))
+    batch = fsg.Batch(bj, steps_per_sync=16)
+    infos, total_ms = batch.run()
+    log(f"[batch] c3-small: {total_ms:.2f} ms")
+    for i, (gr, j) in enumerate(zip(grs, bj)):
+        gnp = gr.numpy()
+        prm = {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in j}
+        st = batch.states[i].cpu().numpy()
+        solo = gpu_run(gnp, j["model"], j["seeds"], j["B"], j["rng_key"], **prm)
+        got = (st, batch.counts[i].cpu().numpy().astype(np.uint32), int(infos[i].steps_run),
+               int(infos[i].absorbed))
+        assert_same(got, solo, f"c3-small job {i}")
+        r0 = j["B"] // 3
+        rs, _, _, _ = oracle_run(gnp, j["model"], j["seeds"], 2, j["rng_key"], replicate_offset=r0,
+                                 **prm)
+        assert (st[:, r0:r0 + 2] == rs).all(), i
+    batch.close()
+
+
+def test_autotune_and_cache():
+    from paper_2603_14895_amd import fsg
+    gr = W.chung_lu(20000, 20.0, 2.5, 901)
+    gnp = gr.numpy()
+    dg = fsg.DeviceGraph(*gnp)
+    seeds = W.uniform_seeds(gr.n, 200, 902)
+    kw = dict(beta=0.03, gamma=0.1, max_steps=30)
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "tune.txt")
+        best, bms, dms = fsg.autotune(dg, "sir", seeds, 512, 77, tune_steps=6, cache_path=cache, **kw)
+        log(f"[tune] best {best} {bms:.4f} ms vs default {dms:.4f} ms")
+        assert bms <= dms + 1e-9 and best["row_lanes"] >= 1
+        again, bms2, dms2 = fsg.autotune(dg, "sir", seeds, 512, 77, tune_steps=6, cache_path=cache, **kw)
+        assert again == best and dms2 < 0  # served from the cache
+        tuned = gpu_run(gnp, "sir", seeds, 512, 0x77, schedule=best, **kw)
+        plain = gpu_run(gnp, "sir", seeds, 512, 0x77, **kw)
+        assert_same(tuned, plain, "tuned vs default schedule")
+        bb, _, _ = fsg.autotune(dg, "ic", seeds, 64, 5, tune_steps=4, batch_only=True, p=0.05)
+        assert bb["kernel_variant"] == 1
