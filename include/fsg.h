@@ -249,6 +249,65 @@ int fsg_autotune(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds
                  const char *cache_path, void *dev_ws, size_t ws_bytes, fsg_schedule *best,
                  double *best_ms, double *default_ms, void *stream);
 
+/* ---- Learned surrogate of the SIR spread (message passing with learned
+ * message, aggregation = mean over in-neighbours, learned update; the
+ * structure of Eq. ms, Eq. agg, Eq. updata).  Per node v of seed set s:
+ *   x_v = [seed_v, 20 beta, log1p(indeg_v) / 8, 1, 0 x 12]
+ *   h1 = ReLU(W1 [x_v | mean x_u] + b1), h2, h3 likewise from h1, h2 (width 64)
+ *   p_v = sigmoid(wo . h3_v + bo), the predicted infection frequency of v.
+ * BF16 weights and activations, FP32 accumulation (MFMA), FP32 master
+ * weights and Adam moments.  Parameters: a flat FP32 vector of 18689 values
+ * in the order W1 [32][64], b1, W2 [128][64], b2, W3 [128][64], b3, wo [64],
+ * bo.  A network lives on the host until bound to caller device memory of
+ * fsg_gnn_state_size bytes; activations use a per-call workspace of
+ * fsg_gnn_workspace_size bytes.  All device pointers are caller-owned. */
+typedef struct fsg_gnn fsg_gnn;
+
+/* hidden must be 64 and layers 3 (FSG_EUNSUPPORTED otherwise); init_seed
+ * fixes the uniform Glorot initialisation of the weights (biases 0). */
+int fsg_gnn_create(int32_t hidden, int32_t layers, uint64_t init_seed, fsg_gnn **out);
+int fsg_gnn_destroy(fsg_gnn *g);
+int fsg_gnn_param_count(const fsg_gnn *g, int64_t *count);
+int fsg_gnn_state_size(const fsg_gnn *g, size_t *bytes);
+/* Uploads the initial parameters into dev_state (256-byte aligned) and
+ * zeroes the Adam moments.  Synchronous. */
+int fsg_gnn_bind(fsg_gnn *g, void *dev_state, size_t bytes, void *stream);
+/* Workspace of one forward or training call on `graph` for n_sets seed sets. */
+int fsg_gnn_workspace_size(const fsg_gnn *g, const fsg_graph *graph, int32_t n_sets,
+                           size_t *bytes);
+/* dev_mask: device uint8 [n_sets][n] (1 = seed); beta: host float [n_sets]
+ * in [0, 1]; dev_prob: device float [n_sets][n] receives p_v.  Synchronous. */
+int fsg_gnn_forward(fsg_gnn *g, const fsg_graph *graph, int32_t n_sets, const uint8_t *dev_mask,
+                    const float *beta, float *dev_prob, void *ws, size_t ws_bytes, void *stream);
+/* One step of mean binary cross-entropy against dev_target (device float
+ * [n_sets][n], per-node infection frequencies from Monte Carlo): forward,
+ * backward (the mean aggregation is transposed by pulling over `reverse`,
+ * the bound graph with every arc reversed), then, if apply_update, Adam with
+ * learning rate lr (beta1 0.9, beta2 0.999, eps 1e-8).  The gradient stays
+ * readable through fsg_gnn_get_grads; *loss (host, nullable) receives the
+ * mean loss.  Synchronous. */
+int fsg_gnn_train_step(fsg_gnn *g, const fsg_graph *graph, const fsg_graph *reverse,
+                       int32_t n_sets, const uint8_t *dev_mask, const float *beta,
+                       const float *dev_target, float lr, int32_t apply_update, float *loss,
+                       void *ws, size_t ws_bytes, void *stream);
+/* Host copies of the FP32 parameters / last gradient (n = parameter count). */
+int fsg_gnn_get_params(const fsg_gnn *g, float *out, int64_t n, void *stream);
+int fsg_gnn_set_params(fsg_gnn *g, const float *in, int64_t n, void *stream);
+int fsg_gnn_get_grads(const fsg_gnn *g, float *out, int64_t n, void *stream);
+/* Spread estimate of one SIR query with Monte Carlo fallback: the ensemble
+ * members predict sum_v p_v; uncertainty = (sample std / mean) over members.
+ * If it exceeds tau, the plain simulator runs B_fallback replicates
+ * (max_steps, rng_key) instead and its mean count is returned with
+ * *used_fallback = 1.  ws: fsg_gnn_workspace_size for n_sets = 1; sim_ws:
+ * fsg_sim_workspace_size for SIR with B_fallback; dev_counts: device uint32
+ * [n].  Synchronous. */
+int fsg_estimate_spread(fsg_gnn *const *members, int32_t n_members, const fsg_graph *graph,
+                        const int32_t *seeds, int64_t n_seeds, double beta, double gamma,
+                        int64_t max_steps, double tau, int64_t B_fallback, uint64_t rng_key,
+                        void *ws, size_t ws_bytes, void *sim_ws, size_t sim_ws_bytes,
+                        uint32_t *dev_counts, double *spread, double *uncertainty,
+                        int32_t *used_fallback, void *stream);
+
 /* Row-tile planner (host only; Sec. 3.2, Definition "Target-Node-Based
  * Partitioning via Longest Processing Time Heuristic", kept in CSR order so
  * every part is a contiguous row range).  Row v weighs

@@ -104,6 +104,24 @@ struct fsg_graph {
     std::map<std::tuple<int64_t, int64_t, int64_t>, Plan> plans;
 };
 
+namespace fsg {
+
+int set_error(int code, const char *msg) { return fail(code, msg); }
+
+bool graph_view(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg,
+                const int32_t **ptr, const int32_t **src)
+{
+    if (!g || !g->bound) return false;
+    *n = g->n;
+    *nnz = g->nnz;
+    *max_indeg = g->max_indeg;
+    *ptr = g->d_ptr;
+    *src = g->d_src;
+    return true;
+}
+
+}  // namespace fsg
+
 // Target-node partition by prefix sums (Sec. 3.2, Definition "Target-Node-
 // Based Partitioning"): node i with prefix load C_i goes to part
 // ceil(d C_i / W_total); here the nodes keep their CSR order so each part is
@@ -342,12 +360,9 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
     L->plane_words = g->n * L->W;
     L->n_planes = kind == kKindLT ? 2 : 3;
     L->L = kind == kKindIC ? 1 : counter_planes_for(std::max(p.max_light, p.max_seg));
-    if (kind == kKindEpidemic) {
-        const double beta = prm->beta;
-        L->n_tinf = (int64_t)infection_table(beta, g->max_indeg).size();
-    } else {
-        L->n_tinf = 1;
-    }
+    // room for the longest table (it stops early once it saturates), so the
+    // workspace size does not depend on beta
+    L->n_tinf = kind == kKindEpidemic ? g->max_indeg + 1 : 1;
     L->n_seed_stage = std::min<int64_t>(g->n, kSeedStage);
     size_t off = 0;
     for (int i = 0; i < L->n_planes; ++i) {
@@ -503,7 +518,7 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.ic_t = threshold_of(prm->p);
     a.edge_t = edge_t.empty() ? nullptr : (const uint32_t *)(base + L.edge_t);
     a.tinf = (const uint32_t *)(base + L.tinf);
-    a.khat = (int32_t)L.n_tinf - 1;
+    a.khat = (int32_t)tinf.size() - 1;
     a.trec = prm->model == FSG_SI ? 0u : threshold_of(prm->gamma);
     a.G = s.G;
     a.S = s.S;

@@ -1,0 +1,908 @@
+// fsg_gnn.hip -- learned surrogate of the Monte Carlo SIR spread: a
+// mean-aggregation message-passing network (the message / aggregate / update
+// structure of Eq. ms, Eq. agg, Eq. updata, here with learned functions),
+// BF16 weights and activations with FP32 accumulation on MFMA, trained on the
+// simulator's own Monte Carlo output by hand-written forward and backward
+// kernels and Adam.
+//
+// Network (per node v, per seed set s; R = n_sets * n rows):
+//   x_v  = [seed_v, 20 beta, log1p(indeg_v) / 8, 1, 0 ... 0]      (16 wide)
+//   h1_v = ReLU(W1 [x_v | mean_{u in N-(v)} x_u] + b1)            (32 -> 64)
+//   h2_v = ReLU(W2 [h1_v | mean h1_u] + b2)                        (128 -> 64)
+//   h3_v = ReLU(W3 [h2_v | mean h2_u] + b3)                        (128 -> 64)
+//   p_v  = sigmoid(wo . h3_v + bo)
+// Loss: mean binary cross-entropy against per-node infection frequencies.
+// A mean over an empty neighbourhood is 0.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fsg.h"
+#include "fsg_internal.hpp"
+
+namespace fsg {
+namespace gnn {
+
+constexpr int kF0 = 16;   // input features (padded)
+constexpr int kHid = 64;  // hidden width
+constexpr int kK1 = 2 * kF0, kK2 = 2 * kHid;
+// flat FP32 parameter layout
+constexpr int kW1 = 0, kB1 = kW1 + kK1 * kHid, kW2 = kB1 + kHid, kB2 = kW2 + kK2 * kHid,
+              kW3 = kB2 + kHid, kB3 = kW3 + kK2 * kHid, kWo = kB3 + kHid, kBo = kWo + kHid,
+              kP = kBo + 1;
+// BF16 copies of W1, W2, W3 ([K][64] row-major each)
+constexpr int kWb1 = 0, kWb2 = kWb1 + kK1 * kHid, kWb3 = kWb2 + kK2 * kHid,
+              kWbN = kWb3 + kK2 * kHid;
+constexpr int kPartBlocks = 512;  // fixed grid of reduction kernels (deterministic sums)
+constexpr int kDwRows = 1024;     // rows per block of the weight-gradient GEMM
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline uint16_t to_bf16(float f)
+{
+    union {
+        float f;
+        uint32_t u;
+    } x;
+    x.f = f;
+    if ((x.u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((x.u >> 16) | ((x.u & 0xFFFF) ? 0x40 : 0));
+    x.u += 0x7FFFu + ((x.u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(x.u >> 16);
+}
+
+__host__ __device__ inline float from_bf16(uint16_t h)
+{
+    union {
+        uint32_t u;
+        float f;
+    } x;
+    x.u = (uint32_t)h << 16;
+    return x.f;
+}
+
+// ------------------------------------------------------------- kernels ----
+
+// Input features of every (seed set, node) row into X1[:, 0:16].
+__global__ void k_input(uint16_t *X1, const uint8_t *mask, const float *beta, const int32_t *ptr,
+                        int32_t n, int32_t n_sets)
+{
+    const int64_t R = (int64_t)n * n_sets;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(r / n);
+        const int v = (int)(r - (int64_t)s * n);
+        const float d = (float)(ptr[v + 1] - ptr[v]);
+        uint16_t *x = X1 + r * kK1;
+        x[0] = to_bf16(mask[r] ? 1.f : 0.f);
+        x[1] = to_bf16(20.f * beta[s]);
+        x[2] = to_bf16(log1pf(d) * 0.125f);
+        x[3] = to_bf16(1.f);
+        for (int f = 4; f < kF0; ++f) x[f] = 0;
+    }
+}
+
+// Mean aggregation over in-neighbours (pull CSR), FP32 sums, BF16 result:
+// X[r][cout + f] = mean_{u in N-(v)} X[s*n + u][cin + f], f < d (d = 16 or 64).
+__global__ void __launch_bounds__(256) k_mean(uint16_t *X, int ld, int d, int cin, int cout,
+                                              const int32_t *ptr, const int32_t *src, int32_t n,
+                                              int32_t n_sets)
+{
+    const int lane = threadIdx.x & 63;
+    const int rows_per_wave = 64 / d;
+    const int f = lane % d;
+    const int64_t R = (int64_t)n * n_sets;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r0 = wave * rows_per_wave; r0 < R; r0 += nwave * rows_per_wave) {
+        const int64_t r = r0 + lane / d;
+        if (r >= R) continue;
+        const int s = (int)(r / n);
+        const int v = (int)(r - (int64_t)s * n);
+        const int e0 = ptr[v], e1 = ptr[v + 1];
+        const uint16_t *base = X + (int64_t)s * n * ld + cin + f;
+        float acc = 0.f;
+        int e = e0;
+        for (; e + 3 < e1; e += 4) {
+            const float a0 = from_bf16(base[(int64_t)src[e] * ld]);
+            const float a1 = from_bf16(base[(int64_t)src[e + 1] * ld]);
+            const float a2 = from_bf16(base[(int64_t)src[e + 2] * ld]);
+            const float a3 = from_bf16(base[(int64_t)src[e + 3] * ld]);
+            acc += (a0 + a1) + (a2 + a3);
+        }
+        for (; e < e1; ++e) acc += from_bf16(base[(int64_t)src[e] * ld]);
+        X[r * ld + cout + f] = to_bf16(e1 > e0 ? acc / (float)(e1 - e0) : 0.f);
+    }
+}
+
+// Transpose of the mean aggregation (backward): for row (s, u),
+// dH[r][f] = dX[r][f] + sum_{v : u in N-(v)} dX[s*n + v][64 + f] / indeg(v),
+// pulled over the out-arcs of u (the in-CSR of the reversed graph).
+__global__ void __launch_bounds__(256) k_mean_bwd(float *dH, const float *dX, const int32_t *ptr,
+                                                  const int32_t *rptr, const int32_t *rdst,
+                                                  int32_t n, int32_t n_sets)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t R = (int64_t)n * n_sets;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < R; r += nwave) {
+        const int s = (int)(r / n);
+        const int u = (int)(r - (int64_t)s * n);
+        const float *blk = dX + (int64_t)s * n * kK2 + kHid + lane;
+        float acc = dX[r * kK2 + lane];
+        for (int e = rptr[u]; e < rptr[u + 1]; ++e) {
+            const int v = rdst[e];
+            acc += blk[(int64_t)v * kK2] / (float)(ptr[v + 1] - ptr[v]);
+        }
+        dH[r * kHid + lane] = acc;
+    }
+}
+
+// Out[r][0:64] = act(A[r][0:K] . W[0:K][0:64] + bias) on MFMA (16x16x16 BF16,
+// FP32 accumulation).  One wave: 16 rows x 64 columns; block: 64 rows.
+// W staged in LDS.  relu: 1 -> ReLU and BF16 store to out16, 0 -> FP32 store
+// to out32 without bias.
+__global__ void __launch_bounds__(256) k_gemm_fwd(const uint16_t *A, int lda, int K,
+                                                  const uint16_t *Wb, const float *bias,
+                                                  uint16_t *out16, int ldo, int64_t R)
+{
+    __shared__ uint16_t sW[kK2 * kHid];
+    for (int i = threadIdx.x; i < K * kHid; i += blockDim.x) sW[i] = Wb[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int li = lane & 15, lk = lane >> 4;
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int64_t ra = r0 + li;
+    for (int kb = 0; kb < K; kb += 16) {
+        bf16x4 a = (bf16x4){0, 0, 0, 0};
+        if (ra < R) {
+            const uint16_t *pa = A + ra * lda + kb + 4 * lk;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = (short)pa[j];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            bf16x4 b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = (short)sW[(kb + 4 * lk + j) * kHid + t * 16 + li];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = r0 + 4 * lk + i;
+            const int col = t * 16 + li;
+            if (row < R) {
+                float v = acc[t][i] + bias[col];
+                out16[row * ldo + col] = to_bf16(v > 0.f ? v : 0.f);
+            }
+        }
+    }
+}
+
+// dX[r][0:K] = dZ[r][0:64] . W^T with W = [K][64]; FP32 out.  One wave:
+// 16 rows x K columns.
+__global__ void __launch_bounds__(256) k_gemm_dx(const uint16_t *dZ, const uint16_t *Wb, int K,
+                                                 float *dX, int64_t R)
+{
+    __shared__ uint16_t sW[kK2 * kHid];
+    for (int i = threadIdx.x; i < K * kHid; i += blockDim.x) sW[i] = Wb[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ntiles = K / 16;  // <= 8
+    f32x4 acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int64_t ra = r0 + li;
+#pragma unroll
+    for (int kb = 0; kb < kHid; kb += 16) {
+        bf16x4 a = (bf16x4){0, 0, 0, 0};
+        if (ra < R) {
+            const uint16_t *pa = dZ + ra * kHid + kb + 4 * lk;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = (short)pa[j];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t >= ntiles) break;
+            bf16x4 b;  // B[k][c] = W[c][k]
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = (short)sW[(t * 16 + li) * kHid + kb + 4 * lk + j];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        if (t >= ntiles) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = r0 + 4 * lk + i;
+            if (row < R) dX[row * K + t * 16 + li] = acc[t][i];
+        }
+    }
+}
+
+// Partial weight gradient of one block of kDwRows rows: part[blk][k][c] =
+// sum_rows X[row][k] dZ[row][c] on MFMA (the rows are the contraction).  Row
+// chunks of 64 are staged in LDS; wave w owns feature tiles w, w+4, ...
+__global__ void __launch_bounds__(256) k_gemm_dw(const uint16_t *X, int ldx, int K,
+                                                 const uint16_t *dZ, float *part, int64_t R)
+{
+    __shared__ uint16_t sX[64 * kK2];
+    __shared__ uint16_t sZ[64 * kHid];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int mtiles = K / 16;  // 2 or 8
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[m][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int64_t rb0 = (int64_t)blockIdx.x * kDwRows;
+    for (int64_t c0 = rb0; c0 < rb0 + kDwRows && c0 < R; c0 += 64) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * K; i += blockDim.x) {
+            const int rr = i / K, kk = i - rr * K;
+            sX[i] = (c0 + rr < R) ? X[(c0 + rr) * ldx + kk] : (uint16_t)0;
+        }
+        for (int i = threadIdx.x; i < 64 * kHid; i += blockDim.x) {
+            const int rr = i / kHid;
+            sZ[i] = (c0 + rr < R) ? dZ[(c0 + rr) * kHid + (i - rr * kHid)] : (uint16_t)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 64; ks += 16) {  // 16 rows per MFMA
+            bf16x4 b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[t][j] = (short)sZ[(ks + 4 * lk + j) * kHid + t * 16 + li];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int mt = wave + 4 * m;
+                if (mt >= mtiles) break;
+                bf16x4 a;  // A[feature][row] = X[row][feature]
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[j] = (short)sX[(ks + 4 * lk + j) * K + mt * 16 + li];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[m][t], 0, 0, 0);
+            }
+        }
+    }
+    float *pb = part + (int64_t)blockIdx.x * K * kHid;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int mt = wave + 4 * m;
+        if (mt >= mtiles) break;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pb[(mt * 16 + 4 * lk + i) * kHid + t * 16 + li] = acc[m][t][i];
+    }
+}
+
+// out[i] = scale * sum_b part[b][i] (fixed order).
+__global__ void k_reduce(const float *part, int nb, int len, float *out, float scale)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int b = 0; b < nb; ++b) s += part[(int64_t)b * len + i];
+        out[i] = s * scale;
+    }
+}
+
+// Output layer and loss.  p = sigmoid(wo . h3 + bo); with targets:
+// dz = (p - y) / R, dH3 = dz wo, and per-block partial sums of dz h3 (for
+// wo), dz (for bo) and the cross-entropy (stable form from the logit).
+__global__ void __launch_bounds__(256) k_head(const uint16_t *H3, const float *wo, const float *bo,
+                                              const float *y, float *prob, float *dH3,
+                                              float *part_wo, float *part_bo, float *part_loss,
+                                              int64_t R)
+{
+    __shared__ float s_wo[4][kHid];
+    __shared__ float s_b[4][2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float w = wo[lane];
+    const float b = bo[0];
+    float gw = 0.f, gb = 0.f, ls = 0.f;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < R; r += (int64_t)gridDim.x * 4) {
+        const float h = from_bf16(H3[r * kHid + lane]);
+        float z = h * w;
+        for (int off = 32; off >= 1; off >>= 1) z += __shfl_xor(z, off, 64);
+        z += b;
+        const float p = 1.f / (1.f + expf(-z));
+        if (lane == 0) prob[r] = p;
+        if (y) {
+            const float t = y[r];
+            const float dz = (p - t) / (float)R;
+            dH3[r * kHid + lane] = dz * w;
+            gw += dz * h;
+            gb += dz;
+            ls += fmaxf(z, 0.f) - z * t + log1pf(expf(-fabsf(z)));
+        }
+    }
+    if (!y) return;
+    s_wo[wave][lane] = gw;
+    if (lane == 0) {
+        s_b[wave][0] = gb;
+        s_b[wave][1] = ls;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        part_wo[blockIdx.x * kHid + lane] = s_wo[0][lane] + s_wo[1][lane] + s_wo[2][lane] + s_wo[3][lane];
+        if (lane == 0) {
+            part_bo[blockIdx.x] = s_b[0][0] + s_b[1][0] + s_b[2][0] + s_b[3][0];
+            part_loss[blockIdx.x] = s_b[0][1] + s_b[1][1] + s_b[2][1] + s_b[3][1];
+        }
+    }
+}
+
+// dZ = BF16(dH * [H > 0]) and per-block partial sums of dZ (bias gradient).
+__global__ void __launch_bounds__(256) k_dz(const float *dH, const uint16_t *H, int ldh,
+                                            uint16_t *dZ, float *part_b, int64_t R)
+{
+    __shared__ float s[4][kHid];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float acc = 0.f;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < R; r += (int64_t)gridDim.x * 4) {
+        const float g = from_bf16(H[r * ldh + lane]) > 0.f ? dH[r * kHid + lane] : 0.f;
+        const uint16_t gb = to_bf16(g);
+        dZ[r * kHid + lane] = gb;
+        acc += from_bf16(gb);
+    }
+    s[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) part_b[blockIdx.x * kHid + lane] = s[0][lane] + s[1][lane] + s[2][lane] + s[3][lane];
+}
+
+// Adam on the FP32 master parameters, then BF16 copies of W1..W3.
+__global__ void k_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, uint16_t *wb)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        if (i < kB1) wb[kWb1 + i] = to_bf16(pi);
+        else if (i >= kW2 && i < kB2) wb[kWb2 + (i - kW2)] = to_bf16(pi);
+        else if (i >= kW3 && i < kB3) wb[kWb3 + (i - kW3)] = to_bf16(pi);
+    }
+}
+
+__global__ void k_params_to_bf16(const float *p, uint16_t *wb)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kWbN; i += gridDim.x * blockDim.x) {
+        float x;
+        if (i < kWb2) x = p[kW1 + i];
+        else if (i < kWb3) x = p[kW2 + (i - kWb2)];
+        else x = p[kW3 + (i - kWb3)];
+        wb[i] = to_bf16(x);
+    }
+}
+
+// Sum of probabilities of each seed set (the predicted spread), fixed order.
+__global__ void k_set_sums(const float *prob, int32_t n, int32_t n_sets, float *out)
+{
+    __shared__ float s[256];
+    for (int set = blockIdx.x; set < n_sets; set += gridDim.x) {
+        float acc = 0.f;
+        for (int v = threadIdx.x; v < n; v += blockDim.x) acc += prob[(int64_t)set * n + v];
+        s[threadIdx.x] = acc;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[set] = s[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_mask_clear(uint8_t *mask, int32_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        mask[i] = 0;
+}
+
+__global__ void k_mask_set(uint8_t *mask, const int32_t *seeds, int64_t ns)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns;
+         i += (int64_t)gridDim.x * blockDim.x)
+        mask[seeds[i]] = 1;
+}
+
+}  // namespace gnn
+}  // namespace fsg
+
+using namespace fsg;
+using namespace fsg::gnn;
+
+// ------------------------------------------------------------------ host ----
+
+struct fsg_gnn {
+    int32_t hidden = kHid, layers = 3;
+    uint64_t seed = 0;
+    std::vector<float> init;
+    bool bound = false;
+    char *state = nullptr;  // device: params, m, v, grads (FP32 [P] each), BF16 weights
+    int64_t step = 0;
+    float last_loss = 0.f;
+    float *p() const { return (float *)state; }
+    float *m() const { return (float *)state + kP; }
+    float *v() const { return (float *)state + 2 * kP; }
+    float *g() const { return (float *)state + 3 * kP; }
+    uint16_t *wb() const { return (uint16_t *)((float *)state + 4 * kP); }
+};
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+#define GNN_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return set_error(FSG_EDEVICE, (std::string(#expr) + ": " + hipGetErrorString(e_)).c_str()); \
+    } while (0)
+
+unsigned grid_of(int64_t work, int block, int cap = 65536)
+{
+    int64_t g = (work + block - 1) / block;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// Workspace of one forward/backward pass over R rows.
+struct GnnWs {
+    size_t X1, X2, X3, H3, prob, dH, dH2, dZ, dX, part, pwo, pbo, ploss, beta, sums, mask, seeds,
+        total;
+};
+
+GnnWs gnn_layout(int64_t n, int32_t n_sets)
+{
+    GnnWs w;
+    const size_t R = (size_t)n * (size_t)n_sets;
+    const size_t dw_blocks = (R + kDwRows - 1) / kDwRows;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = al256(off + std::max<size_t>(bytes, 4));
+        return o;
+    };
+    w.X1 = take(R * kK1 * 2);
+    w.X2 = take(R * kK2 * 2);
+    w.X3 = take(R * kK2 * 2);
+    w.H3 = take(R * kHid * 2);
+    w.prob = take(R * 4);
+    w.dH = take(R * kHid * 4);
+    w.dH2 = take(R * kHid * 4);
+    w.dZ = take(R * kHid * 2);
+    w.dX = take(R * kK2 * 4);
+    w.part = take(std::max<size_t>(dw_blocks * kK2 * kHid, (size_t)kPartBlocks * kHid) * 4);
+    w.pwo = take((size_t)kPartBlocks * kHid * 4);
+    w.pbo = take((size_t)kPartBlocks * 4);
+    w.ploss = take((size_t)kPartBlocks * 4);
+    w.beta = take((size_t)n_sets * 4);
+    w.sums = take((size_t)n_sets * 4 + 4);
+    w.mask = take((size_t)n);
+    w.seeds = take((size_t)n * 4);
+    w.total = off;
+    return w;
+}
+
+uint64_t splitmix(uint64_t &x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct GraphView {
+    int64_t n = 0, nnz = 0, dmax = 0;
+    const int32_t *ptr = nullptr, *src = nullptr;
+};
+
+int view_of(const fsg_graph *g, GraphView *v, const char *what)
+{
+    if (!graph_view(g, &v->n, &v->nnz, &v->dmax, &v->ptr, &v->src))
+        return set_error(FSG_EINVAL, (std::string(what) + " is NULL or not bound").c_str());
+    return FSG_OK;
+}
+
+// Forward pass of all layers; probabilities into ws.prob (R rows).
+int forward_all(const fsg_gnn *gn, const GraphView &G, int32_t n_sets, const uint8_t *mask,
+                char *base, const GnnWs &w, hipStream_t st)
+{
+    const int64_t R = G.n * n_sets;
+    uint16_t *X1 = (uint16_t *)(base + w.X1), *X2 = (uint16_t *)(base + w.X2),
+             *X3 = (uint16_t *)(base + w.X3), *H3 = (uint16_t *)(base + w.H3);
+    const float *P = gn->p();
+    const uint16_t *Wb = gn->wb();
+    hipLaunchKernelGGL(k_input, dim3(grid_of(R, 256)), dim3(256), 0, st, X1, mask,
+                       (const float *)(base + w.beta), G.ptr, (int32_t)G.n, n_sets);
+    GNN_TRY(hipGetLastError());
+    const unsigned gm = grid_of(R * 64, 256);
+    hipLaunchKernelGGL(k_mean, dim3(grid_of(R * kF0, 256)), dim3(256), 0, st, X1, kK1, kF0, 0, kF0,
+                       G.ptr, G.src, (int32_t)G.n, n_sets);
+    GNN_TRY(hipGetLastError());
+    const unsigned gg = (unsigned)((R + 63) / 64);
+    hipLaunchKernelGGL(k_gemm_fwd, dim3(gg), dim3(256), 0, st, X1, kK1, kK1, Wb + kWb1, P + kB1, X2,
+                       kK2, R);
+    GNN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_mean, dim3(gm), dim3(256), 0, st, X2, kK2, kHid, 0, kHid, G.ptr, G.src,
+                       (int32_t)G.n, n_sets);
+    GNN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_gemm_fwd, dim3(gg), dim3(256), 0, st, X2, kK2, kK2, Wb + kWb2, P + kB2, X3,
+                       kK2, R);
+    GNN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_mean, dim3(gm), dim3(256), 0, st, X3, kK2, kHid, 0, kHid, G.ptr, G.src,
+                       (int32_t)G.n, n_sets);
+    GNN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_gemm_fwd, dim3(gg), dim3(256), 0, st, X3, kK2, kK2, Wb + kWb3, P + kB3, H3,
+                       kHid, R);
+    GNN_TRY(hipGetLastError());
+    return FSG_OK;
+}
+
+// Backward of one layer with input Xin (ld K) and output H (post-ReLU, ld
+// ldh): dZ from dH, bias and weight gradients into the gradient vector, and
+// (if dHin) the gradient of the layer input through W^T and the transposed
+// mean aggregation.
+int backward_layer(const fsg_gnn *gn, const GraphView &G, const GraphView &Gr, int32_t n_sets,
+                   char *base, const GnnWs &w, const uint16_t *Xin, int K, const uint16_t *H,
+                   int ldh, const float *dH, int wofs, int bofs, int wbofs, float *dHin,
+                   hipStream_t st)
+{
+    const int64_t R = G.n * n_sets;
+    uint16_t *dZ = (uint16_t *)(base + w.dZ);
+    float *part = (float *)(base + w.part);
+    float *grads = gn->g();
+    hipLaunchKernelGGL(k_dz, dim3(kPartBlocks), dim3(256), 0, st, dH, H, ldh, dZ, part, R);
+    GNN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, (const float *)part, kPartBlocks, kHid,
+                       grads + bofs, 1.f);
+    GNN_TRY(hipGetLastError());
+    const int nb = (int)((R + kDwRows - 1) / kDwRows);
+    hipLaunchKernelGGL(k_gemm_dw, dim3((unsigned)nb), dim3(256), 0, st, Xin, K, K,
+                       (const uint16_t *)dZ, part, R);
+    GNN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce, dim3(grid_of(K * kHid, 256)), dim3(256), 0, st, (const float *)part,
+                       nb, K * kHid, grads + wofs, 1.f);
+    GNN_TRY(hipGetLastError());
+    if (dHin) {
+        float *dX = (float *)(base + w.dX);
+        hipLaunchKernelGGL(k_gemm_dx, dim3((unsigned)((R + 63) / 64)), dim3(256), 0, st,
+                           (const uint16_t *)dZ, gn->wb() + wbofs, K, dX, R);
+        GNN_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_mean_bwd, dim3(grid_of(R * 64, 256)), dim3(256), 0, st, dHin,
+                           (const float *)dX, G.ptr, Gr.ptr, Gr.src, (int32_t)G.n, n_sets);
+        GNN_TRY(hipGetLastError());
+    }
+    return FSG_OK;
+}
+
+int check_ws(void *ws, size_t bytes, size_t need)
+{
+    if (!ws || bytes < need) return set_error(FSG_EWORKSPACE, "gnn workspace too small");
+    if (((uintptr_t)ws & 255) != 0) return set_error(FSG_EWORKSPACE, "workspace not 256-byte aligned");
+    return FSG_OK;
+}
+
+int upload_betas(const float *beta, int32_t n_sets, char *base, const GnnWs &w, hipStream_t st)
+{
+    for (int32_t i = 0; i < n_sets; ++i)
+        if (!(beta[i] >= 0.f && beta[i] <= 1.f)) return set_error(FSG_EINVAL, "beta outside [0, 1]");
+    GNN_TRY(hipMemcpyAsync(base + w.beta, beta, (size_t)n_sets * 4, hipMemcpyHostToDevice, st));
+    return FSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fsg_gnn_create(int32_t hidden, int32_t layers, uint64_t init_seed, fsg_gnn **out)
+{
+    try {
+        if (!out) return set_error(FSG_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (hidden != kHid || layers != 3)
+            return set_error(FSG_EUNSUPPORTED, "this build has hidden = 64 and 3 layers");
+        fsg_gnn *g = new fsg_gnn;
+        g->seed = init_seed;
+        g->init.assign(kP, 0.f);
+        uint64_t x = init_seed;
+        auto fill = [&](int off, int fan_in, int count) {  // uniform(-a, a), a = sqrt(6 / (fan_in + 64))
+            const float a = sqrtf(6.f / (float)(fan_in + kHid));
+            for (int i = 0; i < count; ++i) {
+                const double u = (double)(splitmix(x) >> 11) * (1.0 / 9007199254740992.0);
+                g->init[(size_t)(off + i)] = (float)((2.0 * u - 1.0) * a);
+            }
+        };
+        fill(kW1, kK1, kK1 * kHid);
+        fill(kW2, kK2, kK2 * kHid);
+        fill(kW3, kK2, kK2 * kHid);
+        fill(kWo, kHid, kHid);
+        *out = g;
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+int fsg_gnn_destroy(fsg_gnn *g)
+{
+    delete g;
+    return FSG_OK;
+}
+
+int fsg_gnn_param_count(const fsg_gnn *g, int64_t *count)
+{
+    if (!g || !count) return set_error(FSG_EINVAL, "NULL argument");
+    *count = kP;
+    return FSG_OK;
+}
+
+int fsg_gnn_state_size(const fsg_gnn *g, size_t *bytes)
+{
+    if (!g || !bytes) return set_error(FSG_EINVAL, "NULL argument");
+    *bytes = al256((size_t)4 * kP * 4 + (size_t)kWbN * 2);
+    return FSG_OK;
+}
+
+int fsg_gnn_bind(fsg_gnn *g, void *dev_state, size_t bytes, void *stream)
+{
+    if (!g) return set_error(FSG_EINVAL, "gnn is NULL");
+    size_t need = 0;
+    fsg_gnn_state_size(g, &need);
+    int rc = check_ws(dev_state, bytes, need);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    g->state = (char *)dev_state;
+    GNN_TRY(hipMemcpyAsync(g->p(), g->init.data(), (size_t)kP * 4, hipMemcpyHostToDevice, st));
+    GNN_TRY(hipMemsetAsync(g->m(), 0, (size_t)3 * kP * 4, st));
+    hipLaunchKernelGGL(k_params_to_bf16, dim3(grid_of(kWbN, 256)), dim3(256), 0, st,
+                       (const float *)g->p(), g->wb());
+    GNN_TRY(hipGetLastError());
+    GNN_TRY(hipStreamSynchronize(st));
+    g->bound = true;
+    g->step = 0;
+    return FSG_OK;
+}
+
+int fsg_gnn_workspace_size(const fsg_gnn *g, const fsg_graph *graph, int32_t n_sets, size_t *bytes)
+{
+    if (!g || !bytes) return set_error(FSG_EINVAL, "NULL argument");
+    GraphView G;
+    int rc = view_of(graph, &G, "graph");
+    if (rc) return rc;
+    if (n_sets < 1) return set_error(FSG_EINVAL, "n_sets must be >= 1");
+    if ((int64_t)n_sets * G.n > ((int64_t)1 << 31)) return set_error(FSG_EUNSUPPORTED, "n_sets * n above 2^31");
+    *bytes = gnn_layout(G.n, n_sets).total;
+    return FSG_OK;
+}
+
+int fsg_gnn_forward(fsg_gnn *g, const fsg_graph *graph, int32_t n_sets, const uint8_t *dev_mask,
+                    const float *beta, float *dev_prob, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!g || !g->bound) return set_error(FSG_EINVAL, "gnn is NULL or not bound");
+    GraphView G;
+    int rc = view_of(graph, &G, "graph");
+    if (rc) return rc;
+    if (n_sets < 1 || !dev_mask || !beta || !dev_prob) return set_error(FSG_EINVAL, "bad arguments");
+    const GnnWs w = gnn_layout(G.n, n_sets);
+    rc = check_ws(ws, ws_bytes, w.total);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    rc = upload_betas(beta, n_sets, base, w, st);
+    if (rc) return rc;
+    rc = forward_all(g, G, n_sets, dev_mask, base, w, st);
+    if (rc) return rc;
+    const int64_t R = G.n * n_sets;
+    hipLaunchKernelGGL(k_head, dim3(kPartBlocks), dim3(256), 0, st, (const uint16_t *)(base + w.H3),
+                       (const float *)(g->p() + kWo), (const float *)(g->p() + kBo),
+                       (const float *)nullptr, dev_prob, (float *)nullptr, (float *)nullptr,
+                       (float *)nullptr, (float *)nullptr, R);
+    GNN_TRY(hipGetLastError());
+    GNN_TRY(hipStreamSynchronize(st));
+    return FSG_OK;
+}
+
+int fsg_gnn_train_step(fsg_gnn *g, const fsg_graph *graph, const fsg_graph *reverse,
+                       int32_t n_sets, const uint8_t *dev_mask, const float *beta,
+                       const float *dev_target, float lr, int32_t apply_update, float *loss,
+                       void *ws, size_t ws_bytes, void *stream)
+{
+    if (!g || !g->bound) return set_error(FSG_EINVAL, "gnn is NULL or not bound");
+    GraphView G, Gr;
+    int rc = view_of(graph, &G, "graph");
+    if (rc) return rc;
+    rc = view_of(reverse, &Gr, "reverse graph");
+    if (rc) return rc;
+    if (Gr.n != G.n || Gr.nnz != G.nnz) return set_error(FSG_EINVAL, "reverse graph does not match");
+    if (n_sets < 1 || !dev_mask || !beta || !dev_target) return set_error(FSG_EINVAL, "bad arguments");
+    if (!(lr >= 0.f)) return set_error(FSG_EINVAL, "lr must be >= 0");
+    const GnnWs w = gnn_layout(G.n, n_sets);
+    rc = check_ws(ws, ws_bytes, w.total);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    rc = upload_betas(beta, n_sets, base, w, st);
+    if (rc) return rc;
+    rc = forward_all(g, G, n_sets, dev_mask, base, w, st);
+    if (rc) return rc;
+    const int64_t R = G.n * n_sets;
+    float *dH = (float *)(base + w.dH), *dH2 = (float *)(base + w.dH2);
+    float *grads = g->g();
+    hipLaunchKernelGGL(k_head, dim3(kPartBlocks), dim3(256), 0, st, (const uint16_t *)(base + w.H3),
+                       (const float *)(g->p() + kWo), (const float *)(g->p() + kBo), dev_target,
+                       (float *)(base + w.prob), dH, (float *)(base + w.pwo),
+                       (float *)(base + w.pbo), (float *)(base + w.ploss), R);
+    GNN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, (const float *)(base + w.pwo),
+                       kPartBlocks, kHid, grads + kWo, 1.f);
+    GNN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, (const float *)(base + w.pbo),
+                       kPartBlocks, 1, grads + kBo, 1.f);
+    GNN_TRY(hipGetLastError());
+    float *dloss = (float *)(base + w.sums);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, (const float *)(base + w.ploss),
+                       kPartBlocks, 1, dloss, 1.f / (float)R);
+    GNN_TRY(hipGetLastError());
+    const uint16_t *X1 = (const uint16_t *)(base + w.X1), *X2 = (const uint16_t *)(base + w.X2),
+                   *X3 = (const uint16_t *)(base + w.X3), *H3 = (const uint16_t *)(base + w.H3);
+    // layer 3: input X3 = [h2 | mean h2], output h3
+    rc = backward_layer(g, G, Gr, n_sets, base, w, X3, kK2, H3, kHid, dH, kW3, kB3, kWb3, dH2, st);
+    if (rc) return rc;
+    // layer 2: output h2 = X3[:, 0:64]
+    rc = backward_layer(g, G, Gr, n_sets, base, w, X2, kK2, X3, kK2, dH2, kW2, kB2, kWb2, dH, st);
+    if (rc) return rc;
+    // layer 1: output h1 = X2[:, 0:64]; no gradient to the inputs
+    rc = backward_layer(g, G, Gr, n_sets, base, w, X1, kK1, X2, kK2, dH, kW1, kB1, kWb1, nullptr, st);
+    if (rc) return rc;
+    if (apply_update) {
+        g->step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f - powf(b1, (float)g->step), c2 = 1.f - powf(b2, (float)g->step);
+        hipLaunchKernelGGL(k_adam, dim3(grid_of(kP, 256)), dim3(256), 0, st, g->p(),
+                           (const float *)grads, g->m(), g->v(), (int)kP, lr, b1, b2, 1e-8f, c1, c2,
+                           g->wb());
+        GNN_TRY(hipGetLastError());
+    }
+    float hl = 0.f;
+    GNN_TRY(hipMemcpyAsync(&hl, dloss, 4, hipMemcpyDeviceToHost, st));
+    GNN_TRY(hipStreamSynchronize(st));
+    g->last_loss = hl;
+    if (loss) *loss = hl;
+    return FSG_OK;
+}
+
+int fsg_gnn_get_params(const fsg_gnn *g, float *out, int64_t n, void *stream)
+{
+    if (!g || !g->bound || !out || n != kP) return set_error(FSG_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    GNN_TRY(hipMemcpyAsync(out, g->p(), (size_t)kP * 4, hipMemcpyDeviceToHost, st));
+    GNN_TRY(hipStreamSynchronize(st));
+    return FSG_OK;
+}
+
+int fsg_gnn_set_params(fsg_gnn *g, const float *in, int64_t n, void *stream)
+{
+    if (!g || !g->bound || !in || n != kP) return set_error(FSG_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    GNN_TRY(hipMemcpyAsync(g->p(), in, (size_t)kP * 4, hipMemcpyHostToDevice, st));
+    GNN_TRY(hipMemsetAsync(g->m(), 0, (size_t)2 * kP * 4, st));
+    hipLaunchKernelGGL(k_params_to_bf16, dim3(grid_of(kWbN, 256)), dim3(256), 0, st,
+                       (const float *)g->p(), g->wb());
+    GNN_TRY(hipGetLastError());
+    GNN_TRY(hipStreamSynchronize(st));
+    g->step = 0;
+    return FSG_OK;
+}
+
+int fsg_gnn_get_grads(const fsg_gnn *g, float *out, int64_t n, void *stream)
+{
+    if (!g || !g->bound || !out || n != kP) return set_error(FSG_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    GNN_TRY(hipMemcpyAsync(out, g->g(), (size_t)kP * 4, hipMemcpyDeviceToHost, st));
+    GNN_TRY(hipStreamSynchronize(st));
+    return FSG_OK;
+}
+
+int fsg_estimate_spread(fsg_gnn *const *members, int32_t n_members, const fsg_graph *graph,
+                        const int32_t *seeds, int64_t n_seeds, double beta, double gamma,
+                        int64_t max_steps, double tau, int64_t B_fallback, uint64_t rng_key,
+                        void *ws, size_t ws_bytes, void *sim_ws, size_t sim_ws_bytes,
+                        uint32_t *dev_counts, double *spread, double *uncertainty,
+                        int32_t *used_fallback, void *stream)
+{
+    if (!members || n_members < 1 || !spread || !uncertainty || !used_fallback)
+        return set_error(FSG_EINVAL, "bad arguments");
+    GraphView G;
+    int rc = view_of(graph, &G, "graph");
+    if (rc) return rc;
+    if (n_seeds < 0 || (n_seeds > 0 && !seeds)) return set_error(FSG_EINVAL, "bad seed array");
+    for (int64_t i = 0; i < n_seeds; ++i)
+        if (seeds[i] < 0 || seeds[i] >= G.n) return set_error(FSG_EINVAL, "seed out of range");
+    const GnnWs w = gnn_layout(G.n, 1);
+    rc = check_ws(ws, ws_bytes, w.total);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    uint8_t *mask = (uint8_t *)(base + w.mask);
+    int32_t *dseeds = (int32_t *)(base + w.seeds);
+    hipLaunchKernelGGL(k_mask_clear, dim3(grid_of(G.n, 256)), dim3(256), 0, st, mask, (int32_t)G.n);
+    GNN_TRY(hipGetLastError());
+    if (n_seeds > 0) {
+        GNN_TRY(hipMemcpyAsync(dseeds, seeds, (size_t)n_seeds * 4, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_mask_set, dim3(grid_of(n_seeds, 256)), dim3(256), 0, st, mask,
+                           (const int32_t *)dseeds, n_seeds);
+        GNN_TRY(hipGetLastError());
+    }
+    std::vector<double> sp((size_t)n_members);
+    const float fb = (float)beta;
+    for (int32_t m = 0; m < n_members; ++m) {
+        rc = fsg_gnn_forward(members[m], graph, 1, mask, &fb, (float *)(base + w.prob), ws,
+                             ws_bytes, stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_set_sums, dim3(1), dim3(256), 0, st, (const float *)(base + w.prob),
+                           (int32_t)G.n, 1, (float *)(base + w.sums));
+        GNN_TRY(hipGetLastError());
+        float s = 0.f;
+        GNN_TRY(hipMemcpyAsync(&s, base + w.sums, 4, hipMemcpyDeviceToHost, st));
+        GNN_TRY(hipStreamSynchronize(st));
+        sp[(size_t)m] = s;
+    }
+    double mean = 0, var = 0;
+    for (double x : sp) mean += x;
+    mean /= n_members;
+    for (double x : sp) var += (x - mean) * (x - mean);
+    var = n_members > 1 ? var / (n_members - 1) : 0.0;
+    const double unc = mean > 0 ? sqrt(var) / mean : 1e30;
+    *uncertainty = unc;
+    *used_fallback = 0;
+    *spread = mean;
+    if (unc > tau) {
+        if (B_fallback < 1 || !dev_counts) return set_error(FSG_EINVAL, "fallback needs B_fallback and counts");
+        fsg_params prm;
+        memset(&prm, 0, sizeof(prm));
+        prm.model = FSG_SIR;
+        prm.beta = beta;
+        prm.gamma = gamma;
+        prm.max_steps = max_steps;
+        fsg_run_info info;
+        rc = fsg_simulate(graph, &prm, seeds, n_seeds, B_fallback, 0, rng_key, nullptr, sim_ws,
+                          sim_ws_bytes, nullptr, dev_counts, &info, stream);
+        if (rc) return rc;
+        std::vector<uint32_t> cnt((size_t)G.n);
+        GNN_TRY(hipMemcpyAsync(cnt.data(), dev_counts, (size_t)G.n * 4, hipMemcpyDeviceToHost, st));
+        GNN_TRY(hipStreamSynchronize(st));
+        double tot = 0;
+        for (uint32_t c : cnt) tot += c;
+        *spread = tot / (double)B_fallback;
+        *used_fallback = 1;
+    }
+    return FSG_OK;
+}
+
+}  // extern "C"

@@ -5,7 +5,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct fsg_graph;
+
 namespace fsg {
+
+// Host helpers shared by the translation units (fsg_abi.hip).
+int set_error(int code, const char *msg);  // records the message, returns code
+// Device view of a graph; false if it is not bound.
+bool graph_view(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg,
+                const int32_t **ptr, const int32_t **src);
 
 enum Kind { kKindIC = 0, kKindEpidemic = 1, kKindLT = 2 };
 

@@ -88,6 +88,24 @@ _SIGS = {
     "fsg_batch_run": (ctypes.c_int, [_VP, _VP, _SZ, ctypes.POINTER(fsg_run_info),
                                      ctypes.POINTER(ctypes.c_double), _VP]),
     "fsg_plan_destroy": (ctypes.c_int, [_VP]),
+    "fsg_gnn_create": (ctypes.c_int, [_I32, _I32, _U64, ctypes.POINTER(_VP)]),
+    "fsg_gnn_destroy": (ctypes.c_int, [_VP]),
+    "fsg_gnn_param_count": (ctypes.c_int, [_VP, ctypes.POINTER(_I64)]),
+    "fsg_gnn_state_size": (ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
+    "fsg_gnn_bind": (ctypes.c_int, [_VP, _VP, _SZ, _VP]),
+    "fsg_gnn_workspace_size": (ctypes.c_int, [_VP, _VP, _I32, ctypes.POINTER(_SZ)]),
+    "fsg_gnn_forward": (ctypes.c_int, [_VP, _VP, _I32, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "fsg_gnn_train_step": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP, _VP, _VP, ctypes.c_float, _I32,
+                                          ctypes.POINTER(ctypes.c_float), _VP, _SZ, _VP]),
+    "fsg_gnn_get_params": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
+    "fsg_gnn_set_params": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
+    "fsg_gnn_get_grads": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
+    "fsg_estimate_spread": (ctypes.c_int, [_VP, _I32, _VP, _VP, _I64, ctypes.c_double,
+                                           ctypes.c_double, _I64, ctypes.c_double, _I64, _U64,
+                                           _VP, _SZ, _VP, _SZ, _VP,
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(_I32), _VP]),
     "fsg_autotune_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _I64, _I32,
                                                    ctypes.POINTER(_SZ)]),
     "fsg_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _U64, _I32,
@@ -410,3 +428,117 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class GNN:
+    """One member of the surrogate ensemble (fsg_gnn_*): parameters and Adam
+    state in a torch device buffer, activations in a per-call workspace."""
+
+    def __init__(self, init_seed: int, device="cuda"):
+        import torch
+        h = ctypes.c_void_p()
+        _check(lib().fsg_gnn_create(64, 3, int(init_seed) & (2**64 - 1), ctypes.byref(h)))
+        self.handle = h.value
+        cnt = ctypes.c_int64()
+        _check(lib().fsg_gnn_param_count(self.handle, ctypes.byref(cnt)))
+        self.n_params = cnt.value
+        nb = ctypes.c_size_t()
+        _check(lib().fsg_gnn_state_size(self.handle, ctypes.byref(nb)))
+        self._state, addr = _ws(nb.value, device)
+        _check(lib().fsg_gnn_bind(self.handle, addr, nb.value, _stream_ptr()))
+        self.device = device
+        self._wss = {}
+
+    def _workspace(self, graph: DeviceGraph, n_sets: int):
+        key = (graph.handle, n_sets)
+        if key not in self._wss:
+            nb = ctypes.c_size_t()
+            _check(lib().fsg_gnn_workspace_size(self.handle, graph.handle, int(n_sets),
+                                                ctypes.byref(nb)))
+            t, addr = _ws(nb.value, self.device)
+            self._wss = {key: (t, addr, nb.value)}  # keep one workspace at a time
+        return self._wss[key]
+
+    def forward(self, graph: DeviceGraph, masks, betas):
+        """masks: uint8 cuda tensor [n_sets, n]; betas: sequence of floats.
+        Returns probabilities [n_sets, n] (float32 cuda tensor)."""
+        import torch
+        n_sets = int(masks.shape[0])
+        _, addr, nb = self._workspace(graph, n_sets)
+        bet = np.ascontiguousarray(betas, dtype=np.float32)
+        prob = torch.empty(masks.shape, dtype=torch.float32, device=self.device)
+        _check(lib().fsg_gnn_forward(self.handle, graph.handle, n_sets, masks.data_ptr(),
+                                     bet.ctypes.data, prob.data_ptr(), addr, nb, _stream_ptr()))
+        return prob
+
+    def train_step(self, graph: DeviceGraph, reverse: DeviceGraph, masks, betas, targets,
+                   lr: float, update: bool = True) -> float:
+        n_sets = int(masks.shape[0])
+        _, addr, nb = self._workspace(graph, n_sets)
+        bet = np.ascontiguousarray(betas, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(lib().fsg_gnn_train_step(self.handle, graph.handle, reverse.handle, n_sets,
+                                        masks.data_ptr(), bet.ctypes.data, targets.data_ptr(),
+                                        float(lr), int(update), ctypes.byref(loss), addr, nb,
+                                        _stream_ptr()))
+        return loss.value
+
+    def get_params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().fsg_gnn_get_params(self.handle, out.ctypes.data, self.n_params, _stream_ptr()))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().fsg_gnn_set_params(self.handle, p.ctypes.data, self.n_params, _stream_ptr()))
+
+    def get_grads(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().fsg_gnn_get_grads(self.handle, out.ctypes.data, self.n_params, _stream_ptr()))
+        return out
+
+    def close(self):
+        if self.handle:
+            _check(lib().fsg_gnn_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SpreadEstimator:
+    """fsg_estimate_spread: ensemble prediction of the SIR spread with Monte
+    Carlo fallback when the members disagree by more than tau."""
+
+    def __init__(self, members, graph: DeviceGraph, gamma: float, max_steps: int,
+                 B_fallback: int, tau: float):
+        import torch
+        self.members = members
+        self.graph = graph
+        self.gamma, self.max_steps, self.B, self.tau = gamma, int(max_steps), int(B_fallback), tau
+        self._arr = (ctypes.c_void_p * len(members))(*[m.handle for m in members])
+        nb = ctypes.c_size_t()
+        _check(lib().fsg_gnn_workspace_size(members[0].handle, graph.handle, 1, ctypes.byref(nb)))
+        self._ws, self.ws_addr = _ws(nb.value, graph.device)
+        self.ws_bytes = nb.value
+        prm, _ = make_params("sir", beta=0.5, gamma=gamma, max_steps=max_steps)
+        self.sim_bytes = fsg_sim_workspace_size(graph.handle, prm, self.B, None)
+        self._sim, self.sim_addr = _ws(self.sim_bytes, graph.device)
+        self.counts = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+
+    def estimate(self, seeds, beta: float, rng_key: int, tau=None):
+        """Returns (spread, uncertainty, used_fallback)."""
+        seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        sp, un, fb = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _check(lib().fsg_estimate_spread(self._arr, len(self.members), self.graph.handle,
+                                         seeds.ctypes.data if seeds.size else None, seeds.size,
+                                         float(beta), float(self.gamma), self.max_steps,
+                                         float(self.tau if tau is None else tau), self.B,
+                                         int(rng_key) & (2**64 - 1), self.ws_addr, self.ws_bytes,
+                                         self.sim_addr, self.sim_bytes, self.counts.data_ptr(),
+                                         ctypes.byref(sp), ctypes.byref(un), ctypes.byref(fb),
+                                         _stream_ptr()))
+        return sp.value, un.value, bool(fb.value)

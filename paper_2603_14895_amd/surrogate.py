@@ -1,0 +1,129 @@
+"""Learned surrogate of the Monte Carlo SIR spread: training data from the
+simulator itself, ensemble training, uncertainty threshold and evaluation
+with Monte Carlo fallback.
+
+Orchestration only: labels come from the batched simulator (fsg_batch_run),
+the network's forward, backward and Adam steps are the library's kernels
+(fsg_gnn_*), and every fallback is a plain fsg_simulate call.  The plain
+simulator is also the judge of the surrogate's error.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import List, Sequence
+
+import numpy as np
+
+from . import fsg
+
+
+def log(*a):
+    import sys
+    print(*a, file=sys.stderr, flush=True)
+
+
+def seed_sets(n: int, count: int, rng: np.random.Generator, max_size: int = 1000):
+    """Seed sets of size round(exp U(0, ln max_size)), uniform without replacement."""
+    out = []
+    for _ in range(count):
+        k = max(1, int(round(math.exp(rng.uniform(0.0, math.log(max_size))))))
+        out.append(np.sort(rng.choice(n, size=min(k, n), replace=False)).astype(np.int32))
+    return out
+
+
+def masks_of(sets: Sequence[np.ndarray], n: int, device="cuda"):
+    import torch
+    m = torch.zeros((len(sets), n), dtype=torch.uint8)
+    for i, s in enumerate(sets):
+        m[i, torch.as_tensor(s, dtype=torch.int64)] = 1
+    return m.to(device)
+
+
+def mc_frequencies(graph: fsg.DeviceGraph, sets, betas, gamma: float, max_steps: int, B: int,
+                   key_base: int, jobs_per_batch: int = 128):
+    """Per-node infection frequencies (ever infected / B) of every seed set,
+    from batched runs of the simulator.  Returns (float32 cuda tensor
+    [len(sets), n], spreads as numpy [len(sets)], device ms)."""
+    import torch
+    n = graph.n
+    out = torch.empty((len(sets), n), dtype=torch.float32, device=graph.device)
+    total_ms = 0.0
+    for b0 in range(0, len(sets), jobs_per_batch):
+        idx = range(b0, min(len(sets), b0 + jobs_per_batch))
+        jobs = [dict(graph=graph, model="sir", B=B, seeds=sets[i], rng_key=key_base + i,
+                     beta=float(betas[i]), gamma=gamma, max_steps=max_steps) for i in idx]
+        batch = fsg.Batch(jobs, steps_per_sync=16, want_states=False)
+        _, ms = batch.run()
+        total_ms += ms
+        for k, i in enumerate(idx):
+            out[i] = batch.counts[k].to(torch.float32) / B
+        batch.close()
+    return out, out.sum(dim=1).cpu().numpy().astype(np.float64), total_ms
+
+
+class Ensemble:
+    """M independently initialised members trained on the same data in
+    different orders."""
+
+    def __init__(self, members: int = 4, seed: int = 1, device="cuda"):
+        self.members = [fsg.GNN(seed * 1000 + i, device) for i in range(members)]
+
+    def train(self, data, epochs: int, sets_per_step: int, lr: float, seed: int = 0,
+              progress_every: int = 1):
+        """data: list of (graph, reverse, masks, betas, targets) per training
+        graph.  Returns the mean loss of each epoch per member."""
+        hist = []
+        for mi, net in enumerate(self.members):
+            rng = np.random.default_rng(seed * 7919 + mi)
+            losses = []
+            for ep in range(epochs):
+                batches = []
+                for gi, (_, _, masks, _, _) in enumerate(data):
+                    order = rng.permutation(masks.shape[0])
+                    for s0 in range(0, len(order), sets_per_step):
+                        batches.append((gi, order[s0:s0 + sets_per_step]))
+                rng.shuffle(batches)
+                tot = 0.0
+                for gi, sel in batches:
+                    g, rev, masks, betas, targets = data[gi]
+                    import torch
+                    si = torch.as_tensor(sel, device=masks.device)
+                    tot += net.train_step(g, rev, masks[si].contiguous(), [betas[j] for j in sel],
+                                          targets[si].contiguous(), lr)
+                losses.append(tot / len(batches))
+                if progress_every and (ep + 1) % progress_every == 0:
+                    log(f"[surrogate] member {mi} epoch {ep + 1}/{epochs}: loss {losses[-1]:.5f}")
+            hist.append(losses)
+        return hist
+
+    def predict_spreads(self, graph: fsg.DeviceGraph, masks, betas, sets_per_call: int = 8):
+        """Predicted spread (sum of p_v) of every member for every seed set:
+        numpy [M, n_sets]."""
+        out = np.zeros((len(self.members), masks.shape[0]))
+        for mi, net in enumerate(self.members):
+            for s0 in range(0, masks.shape[0], sets_per_call):
+                sl = slice(s0, min(masks.shape[0], s0 + sets_per_call))
+                p = net.forward(graph, masks[sl].contiguous(), list(betas[sl]))
+                out[mi, sl] = p.sum(dim=1).double().cpu().numpy()
+        return out
+
+
+def uncertainty(pred: np.ndarray):
+    """Mean spread and relative sample std across members, per query."""
+    mean = pred.mean(axis=0)
+    std = pred.std(axis=0, ddof=1) if pred.shape[0] > 1 else np.zeros_like(mean)
+    return mean, std / np.maximum(mean, 1e-12)
+
+
+def calibrate_tau(mean, unc, ref, max_rel_err: float):
+    """Largest threshold tau such that every calibration query with
+    uncertainty <= tau has relative error <= max_rel_err."""
+    err = np.abs(mean - ref) / np.maximum(ref, 1e-12)
+    order = np.argsort(unc)
+    tau = -1.0
+    for i in order:
+        if err[i] > max_rel_err:
+            break
+        tau = unc[i]
+    return float(tau)

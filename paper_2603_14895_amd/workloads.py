@@ -70,6 +70,15 @@ def pull_csr(n: int, src: torch.Tensor, dst: torch.Tensor, name: str = "") -> Gr
     return Graph(n, ptr, src_sorted.contiguous(), name)
 
 
+def reverse_graph(graph: Graph) -> Graph:
+    """The same arcs reversed, as a pull CSR: row u lists the targets v of
+    the arcs u -> v of ``graph`` (its out-adjacency)."""
+    n = graph.n
+    dst = torch.repeat_interleave(torch.arange(n, device=graph.ptr.device),
+                                  graph.ptr[1:] - graph.ptr[:-1])
+    return pull_csr(n, dst, graph.src.to(torch.int64), graph.name + "_rev")
+
+
 def from_edges(n: int, edges, name: str = "") -> Graph:
     """Small hand-written graphs: ``edges`` is a list of (u, v) arcs."""
     if len(edges) == 0:

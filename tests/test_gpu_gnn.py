@@ -1,0 +1,94 @@
+"""The surrogate's hand-written kernels against its FP64 oracle on the same
+BF16-rounded parameters and inputs: forward probabilities, the full gradient
+of the loss, a decreasing training loss, and the spread estimator's fallback
+to the plain simulator."""
+import numpy as np
+import pytest
+
+from oracle import gnn as OG
+from paper_2603_14895_amd import workloads as W
+from tests.gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_14895_amd import fsg
+    gr = W.chung_lu(400, 8.0, 2.5, 4242)
+    rev = W.reverse_graph(gr)
+    g = fsg.DeviceGraph(*gr.numpy())
+    gr_ = fsg.DeviceGraph(*rev.numpy())
+    rng = np.random.default_rng(7)
+    n = gr.n
+    masks = (rng.random((3, n)) < 0.05).astype(np.uint8)
+    betas = [0.012, 0.03, 0.047]
+    ys = rng.random((3, n)).astype(np.float32)
+    params = OG.glorot(11).astype(np.float32)
+    return dict(fsg=fsg, gr=gr, g=g, rev=gr_, masks=masks, betas=betas, ys=ys, params=params)
+
+
+def test_forward_matches_oracle(setup):
+    import torch
+    S = setup
+    net = S["fsg"].GNN(1)
+    net.set_params(S["params"])
+    prob = net.forward(S["g"], torch.tensor(S["masks"], device="cuda"), S["betas"]).cpu().numpy()
+    ptr, src = S["gr"].numpy()
+    for s in range(3):
+        ref, _ = OG.forward(S["params"].astype(np.float64), ptr, src, S["masks"][s].astype(float),
+                            S["betas"][s], bf=True)
+        err = np.abs(prob[s] - ref)
+        log(f"[gnn] forward set {s}: max abs err {err.max():.2e}, mean {err.mean():.2e}")
+        assert err.max() < 2e-2 and err.mean() < 2e-3
+
+
+def test_gradient_matches_oracle(setup):
+    import torch
+    S = setup
+    net = S["fsg"].GNN(2)
+    net.set_params(S["params"])
+    loss = net.train_step(S["g"], S["rev"], torch.tensor(S["masks"], device="cuda"), S["betas"],
+                          torch.tensor(S["ys"], device="cuda"), 0.0, update=False)
+    gg = net.get_grads().astype(np.float64)
+    ptr, src = S["gr"].numpy()
+    rl, rg = OG.loss_and_grad(S["params"].astype(np.float64), ptr, src,
+                              [m.astype(float) for m in S["masks"]], S["betas"],
+                              [y.astype(float) for y in S["ys"]], bf=True)
+    cos = float(gg @ rg / (np.linalg.norm(gg) * np.linalg.norm(rg)))
+    big = np.abs(rg) > 1e-3 * np.abs(rg).max()
+    rel = np.abs(gg - rg)[big] / np.abs(rg)[big]
+    log(f"[gnn] loss gpu {loss:.6f} oracle {rl:.6f}; grad cosine {cos:.6f}, "
+        f"rel err median {np.median(rel):.2e} p99 {np.quantile(rel, 0.99):.2e} max {rel.max():.2e}")
+    assert abs(loss - rl) < 1e-4 * max(1.0, abs(rl))
+    assert cos >= 0.999
+    assert np.quantile(rel, 0.99) < 5e-2 and np.median(rel) < 1e-2
+
+
+def test_training_reduces_loss(setup):
+    import torch
+    S = setup
+    net = S["fsg"].GNN(3)
+    m = torch.tensor(S["masks"], device="cuda")
+    y = torch.tensor(S["ys"] * 0.0 + S["masks"] * 0.9 + 0.05, device="cuda", dtype=torch.float32)
+    losses = [net.train_step(S["g"], S["rev"], m, S["betas"], y, 3e-3) for _ in range(60)]
+    log(f"[gnn] loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.7 * losses[0]
+
+
+def test_estimator_fallback_is_plain_mc(setup):
+    S = setup
+    fsg = S["fsg"]
+    members = [fsg.GNN(10 + i) for i in range(3)]
+    est = fsg.SpreadEstimator(members, S["g"], gamma=0.1, max_steps=40, B_fallback=256, tau=0.0)
+    seeds = np.array([3, 17, 99], dtype=np.int32)
+    sp, unc, fb = est.estimate(seeds, 0.04, 1234, tau=-1.0)
+    assert fb
+    _, cnt, _, _ = fsg.simulate(S["g"], "sir", seeds, 256, 1234, beta=0.04, gamma=0.1,
+                                max_steps=40, want_states=False)
+    assert abs(sp - float(cnt.sum().item()) / 256) < 1e-9
+    sp2, unc2, fb2 = est.estimate(seeds, 0.04, 1234, tau=1e30)
+    assert not fb2 and unc2 == pytest.approx(unc)
