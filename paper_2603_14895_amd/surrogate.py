@@ -70,14 +70,17 @@ class Ensemble:
         self.members = [fsg.GNN(seed * 1000 + i, device) for i in range(members)]
 
     def train(self, data, epochs: int, sets_per_step: int, lr: float, seed: int = 0,
-              progress_every: int = 1):
+              progress_every: int = 1, final_lr_fraction: float = 0.1):
         """data: list of (graph, reverse, masks, betas, targets) per training
-        graph.  Returns the mean loss of each epoch per member."""
+        graph.  The learning rate decays geometrically from lr to
+        lr * final_lr_fraction over the epochs.  Returns the mean loss of each
+        epoch per member."""
         hist = []
         for mi, net in enumerate(self.members):
             rng = np.random.default_rng(seed * 7919 + mi)
             losses = []
             for ep in range(epochs):
+                lr_ep = lr * final_lr_fraction ** (ep / max(1, epochs - 1))
                 batches = []
                 for gi, (_, _, masks, _, _) in enumerate(data):
                     order = rng.permutation(masks.shape[0])
@@ -90,7 +93,7 @@ class Ensemble:
                     import torch
                     si = torch.as_tensor(sel, device=masks.device)
                     tot += net.train_step(g, rev, masks[si].contiguous(), [betas[j] for j in sel],
-                                          targets[si].contiguous(), lr)
+                                          targets[si].contiguous(), lr_ep)
                 losses.append(tot / len(batches))
                 if progress_every and (ep + 1) % progress_every == 0:
                     log(f"[surrogate] member {mi} epoch {ep + 1}/{epochs}: loss {losses[-1]:.5f}")
