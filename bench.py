@@ -12,6 +12,9 @@ Workloads (synthetic stand-ins for the paper's datasets):
       gamma 0.1, 1% seeds, B=1024, 200 steps            (default)
   c1  IC on directed G(1000, mean out-degree 10), p 0.1, B=100
   c4  IC weighted cascade on R-MAT scale 26, edge factor 16, B=64
+  c5  learned surrogate: GNN trained on simulator labels (Chung-Lu n=1e5,
+      4 graphs x 500 seed sets x 1024 replicates), evaluated on 2 unseen
+      graphs x 100 queries against 4096-replicate Monte Carlo
   c3  64 mixed jobs (Chung-Lu n log-uniform in [1e4, 2e6], mean degree
       U(5, 50); IC p=0.05 / SIR beta 0.03 gamma 0.1 / LT; B log-uniform in
       [64, 4096]; 1-1000 seeds) in one batched, graph-captured launch per step
@@ -28,6 +31,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; counter records are valid only for it."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_14895_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter record (FETCH_SIZE and WRITE_SIZE, scaled by what the
+    same counters read for a plain copy of known size), or None when the
+    kernels changed since the record was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def log(*a):
@@ -114,7 +144,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--epochs", type=int, default=8, help="surrogate training epochs (c5)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the schedule(s) first with the library autotuner")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
@@ -122,9 +153,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--schedule", default=None, help="JSON dict of fsg_schedule fields")
     ap.add_argument("--no-states", action="store_true", help="counts only (no [n][B] output)")
+    ap.add_argument("--print-kernel-hash", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
+    if args.print_kernel_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(replicate sharding across GPUs is described in DESIGN.md); run with --gpus 1.",
@@ -149,6 +184,8 @@ def main():
         del xa, xb
     if args.workload == "c3":
         return bench_batch(args)
+    if args.workload == "c5":
+        return bench_surrogate(args)
     t0 = time.perf_counter()
     c = make_workload(args.workload)
     gr = c["graph"]
@@ -200,7 +237,8 @@ def main():
     abytes = algorithmic_bytes_per_step(c["model"], ptr.size - 1, src.size, c["B"], edge_parallel)
     achieved = abytes / (avg_kernel_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": measured_traffic(args.workload),
                 "kernel": ("k_ic_edge1 (edge-parallel IC step; bitmap clear included)"
                            if edge_parallel else "k_step (pull step; heavy-row combine included)"),
                 "avg_launch_ms": round(avg_kernel_ms, 5), "launches": launches,
@@ -299,6 +337,113 @@ def bench_batch(args):
                      "algorithmic_bytes_per_launch": abytes / max(1, max(steps_run))},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_surrogate(args):
+    """The learned surrogate end to end: labels, training, threshold,
+    evaluation against 4096-replicate Monte Carlo, timing of both."""
+    import numpy as np
+    import torch
+
+    from paper_2603_14895_amd import fsg
+    from paper_2603_14895_amd import surrogate as S
+    from paper_2603_14895_amd import workloads as Wl
+
+    n, gamma, K, B_lab, B_ref = 100_000, 0.1, 200, 1024, 4096
+    rng = np.random.default_rng(Wl.BASE_SEED + 5)
+    t0 = time.perf_counter()
+    data, lab_ms = [], 0.0
+    for gi in range(4):
+        gr = Wl.chung_lu(n, 20.0, 2.5, Wl.BASE_SEED + 50 + gi, device="cuda")
+        ptr, src = gr.numpy()
+        g = fsg.DeviceGraph(ptr, src)
+        rv = fsg.DeviceGraph(*Wl.reverse_graph(gr).numpy())
+        sets = S.seed_sets(n, 500, rng)
+        betas = rng.uniform(0.01, 0.05, size=len(sets))
+        y, sp, ms = S.mc_frequencies(g, sets, betas, gamma, K, B_lab, 1_000_000 * (gi + 1))
+        lab_ms += ms
+        data.append((g, rv, S.masks_of(sets, n), list(betas), y))
+        log(f"[bench] labels graph {gi}: 500 seed sets x {B_lab} replicates in {ms:.0f} ms device, "
+            f"mean spread {sp.mean() / n:.3f} n")
+    ens = S.Ensemble(4, seed=Wl.BASE_SEED % 1000)
+    t1 = time.perf_counter()
+    ens.train(data, epochs=args.epochs, sets_per_step=8, lr=3e-3, progress_every=1)
+    train_s = time.perf_counter() - t1
+    # held-out graphs: calibration on the first 50 queries of each, test on the rest
+    cal_m, cal_u, cal_r, tests = [], [], [], []
+    ref_ms = 0.0
+    for gi in range(2):
+        gr = Wl.chung_lu(n, 20.0, 2.5, Wl.BASE_SEED + 90 + gi, device="cuda")
+        g = fsg.DeviceGraph(*gr.numpy())
+        qs = S.seed_sets(n, 100, rng)
+        qb = rng.uniform(0.01, 0.05, size=len(qs))
+        _, ref, ms = S.mc_frequencies(g, qs, qb, gamma, K, B_ref, 7_000_000 * (gi + 1))
+        ref_ms += ms
+        mean, unc = S.uncertainty(ens.predict_spreads(g, S.masks_of(qs, n), qb))
+        cal_m += list(mean[:50]); cal_u += list(unc[:50]); cal_r += list(ref[:50])
+        tests.append((g, qs[50:], qb[50:], ref[50:]))
+        log(f"[bench] held-out graph {gi}: reference 100 x {B_ref} in {ms:.0f} ms device; "
+            f"surrogate median error {np.median(np.abs(mean - ref) / ref):.4f}")
+    tau = S.calibrate_tau(np.array(cal_m), np.array(cal_u), np.array(cal_r), 0.02)
+    acc_err, fb_err, t_sur, n_fb = [], [], [], 0
+    for g, qs, qb, ref in tests:
+        est = fsg.SpreadEstimator(ens.members, g, gamma=gamma, max_steps=K, B_fallback=1024, tau=tau)
+        for i in range(len(qs)):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            sp, u, fb = est.estimate(qs[i], qb[i], 31337 + i)
+            dt = time.perf_counter() - ta
+            (fb_err if fb else acc_err).append(abs(sp - ref[i]) / ref[i])
+            n_fb += int(fb)
+            if not fb:
+                t_sur.append(dt)
+    # plain Monte Carlo on the same GPU: 4096 replicates (the reference) and
+    # the smallest B matching the surrogate's accuracy
+    g, qs, qb, ref = tests[0]
+    def mc_cost(B, count=10):
+        errs, times = [], []
+        for i in range(count):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, cnt, _, _ = fsg.simulate(g, "sir", qs[i], B, 4242 + i, beta=qb[i], gamma=gamma,
+                                        max_steps=K, want_states=False)
+            s = float(cnt.sum().item()) / B
+            times.append(time.perf_counter() - ta)
+            errs.append(abs(s - ref[i]) / ref[i])
+        return float(np.mean(errs)), float(np.median(times))
+    e_sur = float(np.mean(acc_err)) if acc_err else float("nan")
+    t_s = float(np.median(t_sur)) if t_sur else float("nan")
+    e4096, t4096 = mc_cost(B_ref)
+    matched = None
+    for B in (16, 32, 64, 128, 256, 512, 1024, 2048):
+        e, t = mc_cost(B)
+        if e <= e_sur:
+            matched = (B, e, t)
+            break
+    out = {
+        "metric": "surrogate speed-up over 4096-replicate MC on accepted queries (spread err <= 2%)",
+        "value": t4096 / t_s if t_sur else None, "unit": "x",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(t_s * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 weights/activations, fp32 accumulate (MFMA)", "data": "synthetic",
+        "config": {"workload": "c5_surrogate_chunglu1e5", "n": n, "train_sets": 2000,
+                   "label_replicates": B_lab, "reference_replicates": B_ref, "epochs": args.epochs,
+                   "ensemble": 4, "tau": tau, "parallelism": "single GPU"},
+        "surrogate": {"accepted": len(acc_err), "fallback": n_fb, "acceptance": len(acc_err) / 100.0,
+                      "accepted_rel_err_mean": e_sur,
+                      "accepted_rel_err_max": float(np.max(acc_err)) if acc_err else None,
+                      "fallback_rel_err_mean": float(np.mean(fb_err)) if fb_err else None,
+                      "ms_per_query": t_s * 1e3, "mc4096_ms_per_query": t4096 * 1e3,
+                      "mc4096_rel_err_mean": e4096,
+                      "matched_accuracy_mc": ({"B": matched[0], "rel_err": matched[1],
+                                               "ms_per_query": matched[2] * 1e3,
+                                               "speedup": matched[2] / t_s} if matched else None),
+                      "label_device_ms": lab_ms, "train_seconds": train_s,
+                      "reference_device_ms": ref_ms},
+        "roofline": None, "cpu_baseline": None,
+    }
+    log(f"[bench] c5 done in {time.perf_counter() - t0:.1f}s")
     print(json.dumps(out), flush=True)
 
 

@@ -321,8 +321,9 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
     const int s = (lane >> a.lgG) & (S - 1);
     const int gw = lane & (G - 1);
     const uint64_t share_fixed = S <= 16 ? share_bits(a.goff, s, S) : 0ull;
-    const int rows_per_block = nwaves * rpw;
-    const int seg_blocks = (a.n_seg + rows_per_block - 1) / rows_per_block;
+    // heavy-row segments take a whole wave each: G lanes over words, the
+    // other 64 / G lanes over the segment's arcs
+    const int seg_blocks = (a.n_seg + nwaves - 1) / nwaves;
     if (bid >= seg_blocks) {
         const int tile = bid - seg_blocks;
         const int t0 = a.tiles[2 * tile], t1 = a.tiles[2 * tile + 1];
@@ -342,7 +343,10 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
             }
         }
     } else {
-        const int seg = bid * rows_per_block + wave * rpw + slot;
+        const int Ss = 64 >> a.lgG;  // edge lanes of a segment
+        const int ss = lane >> a.lgG;
+        const uint64_t share_seg = Ss <= 16 ? share_bits(a.goff, ss, Ss) : 0ull;
+        const int seg = bid * nwaves + wave;
         const bool act = seg < a.n_seg;
         int v = 0, e0 = 0, e1 = 0;
         uint32_t indeg = 0;
@@ -354,8 +358,8 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
         }
         for (int w0 = 0; w0 < a.W; w0 += G) {
             const int w = w0 + gw;
-            row_word<KIND, L>(a, G, S, act && w < a.W, v, w < a.W ? w : 0, e0, e1, indeg, s,
-                              act ? seg : 0, share_fixed, tl, tl_n, any);
+            row_word<KIND, L>(a, G, Ss, act && w < a.W, v, w < a.W ? w : 0, e0, e1, indeg, ss,
+                              act ? seg : 0, share_seg, tl, tl_n, any);
         }
     }
 }
@@ -933,9 +937,7 @@ static hipError_t step_kind(const StepArgs &a, int L, dim3 grid, dim3 block, hip
 
 hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_t s)
 {
-    const int rows_per_block = (block / 64) * (64 >> (a.lgG + a.lgS));
-    const int seg_blocks = (a.n_seg + rows_per_block - 1) / rows_per_block;
-    const int64_t nblocks = (int64_t)a.n_tiles + seg_blocks;
+    const int64_t nblocks = step_blocks(a, block);
     if (nblocks <= 0) return hipSuccess;
     const dim3 grid((unsigned)nblocks), blk((unsigned)block);
     if (kind == kKindIC) {
@@ -991,8 +993,8 @@ hipError_t launch_ic_clear(const StepArgs &a, hipStream_t s)
 
 int step_blocks(const StepArgs &a, int block)
 {
-    const int rows_per_block = (block / 64) * (64 >> (a.lgG + a.lgS));
-    return (a.n_seg + rows_per_block - 1) / rows_per_block + a.n_tiles;
+    const int waves = block / 64;  // one heavy-row segment per wave
+    return (a.n_seg + waves - 1) / waves + a.n_tiles;
 }
 
 hipError_t launch_batch_step(const BatchCtl &c, int grid, hipStream_t s)
