@@ -239,8 +239,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": measured_traffic(args.workload),
-                "kernel": ("k_ic_edge1 (edge-parallel IC step; bitmap clear included)"
-                           if edge_parallel else "k_step (pull step; heavy-row combine included)"),
+                "kernel": "k_ic_edge1" if edge_parallel else "k_step",
                 "avg_launch_ms": round(avg_kernel_ms, 5), "launches": launches,
                 "algorithmic_bytes_per_launch": abytes}
     cpu = None

@@ -87,8 +87,10 @@ typedef struct {
  * loop that stops once no replicate has a state-1 node, or at max_steps).
  * absorbed: 1 iff no replicate ends with a state-1 node.
  * step_kernel_ms, step_launches: when the schedule asks for kernel timing,
- * the summed device time of the pull-step kernels (HIP events recorded on the
- * call's stream around each step) and the number of steps timed; else 0. */
+ * the summed device time of the pull-step kernel (HIP events recorded on the
+ * call's stream right around its launch in every step that did work; the
+ * heavy-row combine and the frontier clear are not included) and the number
+ * of steps timed; else 0. */
 typedef struct {
     int64_t steps_run;
     int32_t absorbed;

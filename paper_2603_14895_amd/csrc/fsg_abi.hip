@@ -526,6 +526,8 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.lgG = s.lgG;
     a.lgS = s.lgS;
     a.heavy = s.heavy;
+    a.fast32 = (g->n < ((int64_t)1 << 24) && g->n * L.W < ((int64_t)1 << 29) &&
+                g->nnz < ((int64_t)1 << 30)) ? 1 : 0;
     a.tiles = (const int32_t *)(base + L.tiles);
     a.n_tiles = (int32_t)(p.tiles.size() / 2);
     a.seg_row = (const int32_t *)(base + L.seg_row);
@@ -748,19 +750,23 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
                 a.step = (uint32_t)step;
                 a.prev = jb.pl[(step - 1) & 1];
                 a.next = jb.pl[step & 1];
-                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
+                // timed: the dominant kernel of the step alone (the pull step,
+                // without the bitmap clear or the heavy-row combine)
                 if (s.edge1) {
                     a.bm_prev = jb.bm[(step - 1) & 1];
                     a.bm_next = jb.bm[step & 1];
                     a.sum_prev = jb.sum[(step - 1) & 1];
                     a.sum_next = jb.sum[step & 1];
                     HIP_TRY(launch_ic_clear(a, st));
+                    if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
                     HIP_TRY(launch_ic_edge1(a, edge_grid, s.block, st));
+                    if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
                 } else {
+                    if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
                     HIP_TRY(launch_step(a, kind, jb.L.L, s.block, st));
+                    if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
                     if (a.n_heavy > 0) HIP_TRY(launch_combine(a, kind, s.block, st));
                 }
-                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
             }
             HIP_TRY(hipMemcpyAsync(hflags.data(), flags, (size_t)ring * 4, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));

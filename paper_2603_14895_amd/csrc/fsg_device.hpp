@@ -94,6 +94,34 @@ __device__ __forceinline__ void bs_add1(uint64_t (&c)[L], uint64_t x)
     }
 }
 
+// Four one-bit addends at once with carry-save adders: two full adders at
+// level 0, one at level 1, and a ripple from level 2 only when a carry
+// reaches it (a full adder: s = a ^ b ^ x, carry = (a & b) | (x & (a ^ b))).
+template <int L>
+__device__ __forceinline__ void bs_add4(uint64_t (&c)[L], uint64_t x0, uint64_t x1, uint64_t x2,
+                                        uint64_t x3)
+{
+    uint64_t u = c[0] ^ x0;
+    const uint64_t k1a = (c[0] & x0) | (u & x1);
+    uint64_t s0 = u ^ x1;
+    u = s0 ^ x2;
+    const uint64_t k1b = (s0 & x2) | (u & x3);
+    c[0] = u ^ x3;
+    if (L == 1) return;
+    u = c[1] ^ k1a;
+    uint64_t k2 = (c[1] & k1a) | (u & k1b);
+    c[1] = u ^ k1b;
+    if (k2) {
+#pragma unroll
+        for (int l = 2; l < L; ++l) {
+            const uint64_t t = c[l] & k2;
+            c[l] ^= k2;
+            k2 = t;
+            if (!k2) break;
+        }
+    }
+}
+
 template <int L>
 __device__ __forceinline__ void bs_add(uint64_t (&c)[L], const uint64_t (&d)[L])
 {
@@ -123,6 +151,18 @@ __device__ __forceinline__ uint64_t bs_nonzero(const uint64_t (&c)[L])
 #pragma unroll
     for (int l = 0; l < L; ++l) m |= c[l];
     return m;
+}
+
+// Loads through a uniform base and a 32-bit byte offset (the compiler then
+// uses scalar-base addressing with a 32-bit vector offset).
+__device__ __forceinline__ uint64_t ld64_off32(const uint64_t *base, uint32_t idx)
+{
+    return *reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(base) + (idx << 3));
+}
+
+__device__ __forceinline__ int ld32_off32(const int32_t *base, uint32_t idx)
+{
+    return *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(base) + (idx << 2));
 }
 
 // Masks of the replicates whose count is 1, 2 or 3 (the common case), so

@@ -76,7 +76,28 @@ __device__ __forceinline__ void ic_row_word(const StepArgs &a, int G, int S, boo
     const uint64_t A = valid ? a.aux[idx] : ~0ull;
     const uint64_t cand = valid ? (~A & tail_mask(w, a.B)) : 0ull;
     uint64_t acc = 0;
-    if (cand) {
+    if (cand && a.fast32) {
+        const uint32_t Wu = (uint32_t)a.W, ww = (uint32_t)w;
+        int e = e0 + s;
+        for (; e + 3 * S < e1; e += 4 * S) {
+            const uint32_t u0 = (uint32_t)ld32_off32(a.src, (uint32_t)e);
+            const uint32_t u1 = (uint32_t)ld32_off32(a.src, (uint32_t)(e + S));
+            const uint32_t u2 = (uint32_t)ld32_off32(a.src, (uint32_t)(e + 2 * S));
+            const uint32_t u3 = (uint32_t)ld32_off32(a.src, (uint32_t)(e + 3 * S));
+            const uint64_t f0 = ld64_off32(a.prev, __umul24(u0, Wu) + ww);
+            const uint64_t f1 = ld64_off32(a.prev, __umul24(u1, Wu) + ww);
+            const uint64_t f2 = ld64_off32(a.prev, __umul24(u2, Wu) + ww);
+            const uint64_t f3 = ld64_off32(a.prev, __umul24(u3, Wu) + ww);
+            ic_edge(a, e, f0 & cand & ~acc, gbase, tv, acc);
+            ic_edge(a, e + S, f1 & cand & ~acc, gbase, tv, acc);
+            ic_edge(a, e + 2 * S, f2 & cand & ~acc, gbase, tv, acc);
+            ic_edge(a, e + 3 * S, f3 & cand & ~acc, gbase, tv, acc);
+        }
+        for (; e < e1; e += S) {
+            const uint32_t u = (uint32_t)ld32_off32(a.src, (uint32_t)e);
+            ic_edge(a, e, ld64_off32(a.prev, __umul24(u, Wu) + ww) & cand & ~acc, gbase, tv, acc);
+        }
+    } else if (cand) {
         int e = e0 + s;
         // four independent gathers in flight per lane
         for (; e + 3 * S < e1; e += 4 * S) {
@@ -104,20 +125,38 @@ __device__ __forceinline__ void ic_row_word(const StepArgs &a, int G, int S, boo
 }
 
 // Bit-sliced count of the in-neighbours whose word has a bit of `mask` set,
-// per replicate: four independent gathers in flight per lane.
+// per replicate: four independent gathers in flight per lane, folded in with
+// carry-save adders.  The fast path addresses sources and planes with 32-bit
+// offsets from uniform bases and 24-bit index products.
 template <int L>
 __device__ __forceinline__ void count_edges(const StepArgs &a, int e, int e1, int S, int w,
                                             uint64_t mask, uint64_t (&c)[L])
 {
+    if (a.fast32) {
+        const uint32_t W = (uint32_t)a.W, ww = (uint32_t)w;
+        for (; e + 3 * S < e1; e += 4 * S) {
+            const uint32_t u0 = (uint32_t)ld32_off32(a.src, (uint32_t)e);
+            const uint32_t u1 = (uint32_t)ld32_off32(a.src, (uint32_t)(e + S));
+            const uint32_t u2 = (uint32_t)ld32_off32(a.src, (uint32_t)(e + 2 * S));
+            const uint32_t u3 = (uint32_t)ld32_off32(a.src, (uint32_t)(e + 3 * S));
+            const uint64_t x0 = ld64_off32(a.prev, __umul24(u0, W) + ww);
+            const uint64_t x1 = ld64_off32(a.prev, __umul24(u1, W) + ww);
+            const uint64_t x2 = ld64_off32(a.prev, __umul24(u2, W) + ww);
+            const uint64_t x3 = ld64_off32(a.prev, __umul24(u3, W) + ww);
+            bs_add4<L>(c, x0 & mask, x1 & mask, x2 & mask, x3 & mask);
+        }
+        for (; e < e1; e += S) {
+            const uint32_t u = (uint32_t)ld32_off32(a.src, (uint32_t)e);
+            bs_add1<L>(c, ld64_off32(a.prev, __umul24(u, W) + ww) & mask);
+        }
+        return;
+    }
     const int64_t W = a.W;
     for (; e + 3 * S < e1; e += 4 * S) {
         const int u0 = a.src[e], u1 = a.src[e + S], u2 = a.src[e + 2 * S], u3 = a.src[e + 3 * S];
         const uint64_t x0 = a.prev[(int64_t)u0 * W + w], x1 = a.prev[(int64_t)u1 * W + w],
                        x2 = a.prev[(int64_t)u2 * W + w], x3 = a.prev[(int64_t)u3 * W + w];
-        bs_add1<L>(c, x0 & mask);
-        bs_add1<L>(c, x1 & mask);
-        bs_add1<L>(c, x2 & mask);
-        bs_add1<L>(c, x3 & mask);
+        bs_add4<L>(c, x0 & mask, x1 & mask, x2 & mask, x3 & mask);
     }
     for (; e < e1; e += S) bs_add1<L>(c, a.prev[(int64_t)a.src[e] * W + w] & mask);
 }
