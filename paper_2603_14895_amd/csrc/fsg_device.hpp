@@ -22,6 +22,31 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
+// Three-input bitwise functions in one gfx950 instruction per 32 bits
+// (truth tables: 0x96 = a ^ b ^ c, 0xE8 = majority).  The builtin returns a
+// signed int: it goes through uint32_t before any widening.
+__device__ __forceinline__ uint32_t xor3_32(uint32_t a, uint32_t b, uint32_t c)
+{
+    return (uint32_t)__builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ uint32_t maj3_32(uint32_t a, uint32_t b, uint32_t c)
+{
+    return (uint32_t)__builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+
+__device__ __forceinline__ uint64_t xor3(uint64_t a, uint64_t b, uint64_t c)
+{
+    return (uint64_t)xor3_32((uint32_t)a, (uint32_t)b, (uint32_t)c) |
+           ((uint64_t)xor3_32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)) << 32);
+}
+
+__device__ __forceinline__ uint64_t maj3(uint64_t a, uint64_t b, uint64_t c)
+{
+    return (uint64_t)maj3_32((uint32_t)a, (uint32_t)b, (uint32_t)c) |
+           ((uint64_t)maj3_32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)) << 32);
+}
+
 __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                        uint32_t k0, uint32_t k1)
 {
@@ -29,8 +54,8 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     for (int i = 0; i < 10; ++i) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3_32((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3_32((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -96,21 +121,18 @@ __device__ __forceinline__ void bs_add1(uint64_t (&c)[L], uint64_t x)
 
 // Four one-bit addends at once with carry-save adders: two full adders at
 // level 0, one at level 1, and a ripple from level 2 only when a carry
-// reaches it (a full adder: s = a ^ b ^ x, carry = (a & b) | (x & (a ^ b))).
+// reaches it (a full adder: sum = a ^ b ^ x, carry = majority(a, b, x)).
 template <int L>
 __device__ __forceinline__ void bs_add4(uint64_t (&c)[L], uint64_t x0, uint64_t x1, uint64_t x2,
                                         uint64_t x3)
 {
-    uint64_t u = c[0] ^ x0;
-    const uint64_t k1a = (c[0] & x0) | (u & x1);
-    uint64_t s0 = u ^ x1;
-    u = s0 ^ x2;
-    const uint64_t k1b = (s0 & x2) | (u & x3);
-    c[0] = u ^ x3;
+    const uint64_t s0 = xor3(c[0], x0, x1);
+    const uint64_t k1a = maj3(c[0], x0, x1);
+    c[0] = xor3(s0, x2, x3);
     if (L == 1) return;
-    u = c[1] ^ k1a;
-    uint64_t k2 = (c[1] & k1a) | (u & k1b);
-    c[1] = u ^ k1b;
+    const uint64_t k1b = maj3(s0, x2, x3);
+    uint64_t k2 = maj3(c[1], k1a, k1b);
+    c[1] = xor3(c[1], k1a, k1b);
     if (k2) {
 #pragma unroll
         for (int l = 2; l < L; ++l) {
@@ -129,9 +151,8 @@ __device__ __forceinline__ void bs_add(uint64_t (&c)[L], const uint64_t (&d)[L])
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         const uint64_t a = c[l], b = d[l];
-        const uint64_t s = a ^ b;
-        c[l] = s ^ carry;
-        carry = (a & b) | (carry & s);
+        c[l] = xor3(a, b, carry);
+        carry = maj3(a, b, carry);
     }
 }
 

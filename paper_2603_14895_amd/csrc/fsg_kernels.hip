@@ -124,13 +124,14 @@ __device__ __forceinline__ void ic_row_word(const StepArgs &a, int G, int S, boo
     }
 }
 
-// Bit-sliced count of the in-neighbours whose word has a bit of `mask` set,
-// per replicate: four independent gathers in flight per lane, folded in with
-// carry-save adders.  The fast path addresses sources and planes with 32-bit
-// offsets from uniform bases and 24-bit index products.
+// Bit-sliced count of the in-neighbours whose word has the replicate's bit
+// set: four independent gathers in flight per lane, folded in with carry-save
+// adders.  Counts are kept for every replicate of the word; callers use them
+// only under their own state mask.  The fast path addresses sources and
+// planes with 32-bit offsets from uniform bases and 24-bit index products.
 template <int L>
 __device__ __forceinline__ void count_edges(const StepArgs &a, int e, int e1, int S, int w,
-                                            uint64_t mask, uint64_t (&c)[L])
+                                            uint64_t (&c)[L])
 {
     if (a.fast32) {
         const uint32_t W = (uint32_t)a.W, ww = (uint32_t)w;
@@ -143,22 +144,21 @@ __device__ __forceinline__ void count_edges(const StepArgs &a, int e, int e1, in
             const uint64_t x1 = ld64_off32(a.prev, __umul24(u1, W) + ww);
             const uint64_t x2 = ld64_off32(a.prev, __umul24(u2, W) + ww);
             const uint64_t x3 = ld64_off32(a.prev, __umul24(u3, W) + ww);
-            bs_add4<L>(c, x0 & mask, x1 & mask, x2 & mask, x3 & mask);
+            bs_add4<L>(c, x0, x1, x2, x3);
         }
         for (; e < e1; e += S) {
             const uint32_t u = (uint32_t)ld32_off32(a.src, (uint32_t)e);
-            bs_add1<L>(c, ld64_off32(a.prev, __umul24(u, W) + ww) & mask);
+            bs_add1<L>(c, ld64_off32(a.prev, __umul24(u, W) + ww));
         }
         return;
     }
     const int64_t W = a.W;
     for (; e + 3 * S < e1; e += 4 * S) {
         const int u0 = a.src[e], u1 = a.src[e + S], u2 = a.src[e + 2 * S], u3 = a.src[e + 3 * S];
-        const uint64_t x0 = a.prev[(int64_t)u0 * W + w], x1 = a.prev[(int64_t)u1 * W + w],
-                       x2 = a.prev[(int64_t)u2 * W + w], x3 = a.prev[(int64_t)u3 * W + w];
-        bs_add4<L>(c, x0 & mask, x1 & mask, x2 & mask, x3 & mask);
+        bs_add4<L>(c, a.prev[(int64_t)u0 * W + w], a.prev[(int64_t)u1 * W + w],
+                   a.prev[(int64_t)u2 * W + w], a.prev[(int64_t)u3 * W + w]);
     }
-    for (; e < e1; e += S) bs_add1<L>(c, a.prev[(int64_t)a.src[e] * W + w] & mask);
+    for (; e < e1; e += S) bs_add1<L>(c, a.prev[(int64_t)a.src[e] * W + w]);
 }
 
 // ------------------------------------------------------ SI / SIS / SIR ----
@@ -167,53 +167,138 @@ __device__ __forceinline__ void count_edges(const StepArgs &a, int e, int e1, in
 // 1 - (1-beta)^k; the k-indexed thresholds come from the host.  One draw per
 // (node, replicate, step) decides whichever transition the node's state
 // allows (infection if S, recovery if I).
+// Draw classes of the aligned decision path: code = b0 | b1 << 1 | b2 << 2
+// per replicate, with 1, 2, 3 = that many infected in-neighbours, 4 = four
+// or more (threshold from the exact count), 5 = infected with a recovery draw.
+// The table maps a code to its threshold (0 for codes that never fire here).
+constexpr int kCodeTable = 8;
+
+__device__ __forceinline__ uint32_t code_threshold(const StepArgs &a, int code)
+{
+    switch (code) {
+    case 1: case 2: case 3: return a.tinf[code < a.khat ? code : a.khat];
+    case 5: return a.trec;
+    default: return 0u;
+    }
+}
+
+// Spread the four bits of a nibble to bit 0 of the four bytes of a word.
+__device__ __forceinline__ uint32_t spread4(uint32_t n, uint32_t mul, uint32_t mask)
+{
+    return __umul24(n, mul) & mask;
+}
+
 template <int LC>
 __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool valid, int v,
                                            int w, int64_t idx, uint64_t h, uint64_t r,
                                            uint64_t sus, const uint64_t (&c)[LC], int s,
                                            uint64_t share, const uint32_t *tl, int tl_n,
-                                           bool &any)
+                                           const uint32_t *tcode, bool &any)
 {
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
     const bool draw_rec = a.trec != 0u && a.trec != kAlways;
-    uint64_t need = sus & bs_nonzero<LC>(c);
-    if (draw_rec) need |= h;
-    need &= share;
-    const SmallCounts sm = bs_small<LC>(c);
-    const uint64_t big = sus & ~(sm.m1 | sm.m2 | sm.m3) & bs_nonzero<LC>(c);  // k >= 4
-    const uint32_t t1 = tinf_at(a, tl, tl_n, 1u), t2 = tinf_at(a, tl, tl_n, 2u),
-                   t3 = tinf_at(a, tl, tl_n, 3u);
     const uint32_t trec = a.trec;
     uint64_t inf = 0, rec = 0;
-    while (need) {
-        const int b = __builtin_ctzll(need);
-        const int gs = b - (int)((gbase + (uint64_t)b) & 3u);  // first bit of the block
-        const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
-        const uint32_t nn = nibble_at(need, gs);
-        need &= ~nibble_to_word(0xFu, gs);
-        const U4 o = philox10((uint32_t)v, blk, a.step, kDomNodeStep << 24, a.key0, a.key1);
-        const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
-        const uint32_t nh = nibble_at(h, gs), n1 = nibble_at(sm.m1, gs),
-                       n2 = nibble_at(sm.m2, gs), n3 = nibble_at(sm.m3, gs),
-                       nb = nibble_at(big, gs);
-        uint32_t tb[4] = {0u, 0u, 0u, 0u};
-        if (nb) {  // rare: a replicate of this block has four or more infected neighbours
+    if (tcode != nullptr && (a.goff & 3u) == 0u) {
+        // generator blocks are nibbles of the word: one draw per block with
+        // any replicate that needs one, the class of each replicate read from
+        // three bit planes, its threshold from the code table
+        uint64_t rest = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if ((nb >> j) & 1u) tb[j] = tinf_at(a, tl, tl_n, bs_get<LC>(c, gs + j));
-        }
-        uint32_t fi = 0, fr = 0;
+        for (int l = 2; l < LC; ++l) rest |= c[l];
+        const uint64_t ninf = sus & share & (c[0] | c[1] | rest);  // k >= 1
+        const uint64_t m1 = c[0] & ~c[1] & ~rest, m2 = ~c[0] & c[1] & ~rest,
+                       m3 = c[0] & c[1] & ~rest;
+        const uint32_t t1 = tcode[1], t2 = tcode[2], t3 = tcode[3];
+        uint64_t always = 0;  // classes whose threshold always fires
+        if (t1 == kAlways) always |= m1;
+        if (t2 == kAlways) always |= m2;
+        if (t3 == kAlways) always |= m3;
+        always &= ninf;
+        const uint64_t ndraw = ninf & ~always;
+        const uint64_t nrec = draw_rec ? (h & share) : 0ull;
+        const uint64_t B0 = (ndraw & c[0] & ~rest) | nrec;
+        const uint64_t B1 = ndraw & c[1] & ~rest;
+        const uint64_t B2 = (ndraw & rest) | nrec;
+        uint64_t need = ndraw | nrec;
+        uint64_t fire = 0;
+        const uint32_t blk0 = (uint32_t)(gbase >> 2);
+        while (need) {
+            const int b = __builtin_ctzll(need);
+            const int gs = b & ~3;
+            need &= ~(0xFull << gs);
+            const bool hi = gs >= 32;
+            const uint32_t sh = (uint32_t)gs & 31u;
+            const uint32_t n0 = ((hi ? (uint32_t)(B0 >> 32) : (uint32_t)B0) >> sh) & 0xFu;
+            const uint32_t n1 = ((hi ? (uint32_t)(B1 >> 32) : (uint32_t)B1) >> sh) & 0xFu;
+            const uint32_t n2 = ((hi ? (uint32_t)(B2 >> 32) : (uint32_t)B2) >> sh) & 0xFu;
+            // byte j of T = 4 * code of replicate j (a byte offset into the table)
+            const uint32_t T = spread4(n0, 0x810204u, 0x04040404u) |
+                               (spread4(n1, 0x204081u, 0x01010101u) << 3) |
+                               (spread4(n2, 0x204081u, 0x01010101u) << 4);
+            const char *tb = reinterpret_cast<const char *>(tcode);
+            const uint32_t q0 = *reinterpret_cast<const uint32_t *>(tb + (T & 0xFFu));
+            const uint32_t q1 = *reinterpret_cast<const uint32_t *>(tb + ((T >> 8) & 0xFFu));
+            const uint32_t q2 = *reinterpret_cast<const uint32_t *>(tb + ((T >> 16) & 0xFFu));
+            const uint32_t q3 = *reinterpret_cast<const uint32_t *>(tb + (T >> 24));
+            const U4 o = philox10((uint32_t)v, blk0 + ((uint32_t)gs >> 2), a.step,
+                                  kDomNodeStep << 24, a.key0, a.key1);
+            uint32_t f = (o.w < q3) ? 1u : 0u;
+            f = f + f + ((o.z < q2) ? 1u : 0u);
+            f = f + f + ((o.y < q1) ? 1u : 0u);
+            f = f + f + ((o.x < q0) ? 1u : 0u);
+            const uint32_t nb = n2 & ~n0;  // four or more infected neighbours
+            if (nb) {
+                const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool isI = (nh >> j) & 1u;
-            uint32_t t = ((n1 >> j) & 1u) ? t1 : (((n2 >> j) & 1u) ? t2 : (((n3 >> j) & 1u) ? t3 : tb[j]));
-            t = isI ? trec : t;
-            const uint32_t f = (((nn >> j) & 1u) && fires(ou[j], t)) ? 1u : 0u;
-            fi |= (isI ? 0u : f) << j;
-            fr |= (isI ? f : 0u) << j;
+                for (int j = 0; j < 4; ++j)
+                    if ((nb >> j) & 1u)
+                        f |= (fires(ou[j], tinf_at(a, tl, tl_n, bs_get<LC>(c, gs + j))) ? 1u : 0u)
+                             << j;
+            }
+            fire |= (uint64_t)f << gs;
         }
-        inf |= nibble_to_word(fi, gs);
-        rec |= nibble_to_word(fr, gs);
+        inf = (fire & ~h) | always;
+        rec = fire & h;
+    } else {
+        uint64_t need = sus & bs_nonzero<LC>(c);
+        if (draw_rec) need |= h;
+        need &= share;
+        const SmallCounts sm = bs_small<LC>(c);
+        const uint64_t big = sus & ~(sm.m1 | sm.m2 | sm.m3) & bs_nonzero<LC>(c);  // k >= 4
+        const uint32_t t1 = tinf_at(a, tl, tl_n, 1u), t2 = tinf_at(a, tl, tl_n, 2u),
+                       t3 = tinf_at(a, tl, tl_n, 3u);
+        while (need) {
+            const int b = __builtin_ctzll(need);
+            const int gs = b - (int)((gbase + (uint64_t)b) & 3u);  // first bit of the block
+            const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
+            const uint32_t nn = nibble_at(need, gs);
+            need &= ~nibble_to_word(0xFu, gs);
+            const U4 o = philox10((uint32_t)v, blk, a.step, kDomNodeStep << 24, a.key0, a.key1);
+            const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
+            const uint32_t nh = nibble_at(h, gs), n1 = nibble_at(sm.m1, gs),
+                           n2 = nibble_at(sm.m2, gs), n3 = nibble_at(sm.m3, gs),
+                           nb = nibble_at(big, gs);
+            uint32_t tb[4] = {0u, 0u, 0u, 0u};
+            if (nb) {  // a replicate of this block has four or more infected neighbours
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if ((nb >> j) & 1u) tb[j] = tinf_at(a, tl, tl_n, bs_get<LC>(c, gs + j));
+            }
+            uint32_t fi = 0, fr = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool isI = (nh >> j) & 1u;
+                uint32_t t = ((n1 >> j) & 1u) ? t1
+                                              : (((n2 >> j) & 1u) ? t2 : (((n3 >> j) & 1u) ? t3 : tb[j]));
+                t = isI ? trec : t;
+                const uint32_t f = (((nn >> j) & 1u) && fires(ou[j], t)) ? 1u : 0u;
+                fi |= (isI ? 0u : f) << j;
+                fr |= (isI ? f : 0u) << j;
+            }
+            inf |= nibble_to_word(fi, gs);
+            rec |= nibble_to_word(fr, gs);
+        }
     }
     inf = or_reduce_lanes(inf, G, S);
     rec = or_reduce_lanes(rec, G, S);
@@ -230,7 +315,7 @@ template <int L>
 __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bool valid, int v,
                                              int w, int e0, int e1, int s, int seg,
                                              uint64_t share, const uint32_t *tl, int tl_n,
-                                             bool &any)
+                                             const uint32_t *tcode, bool &any)
 {
     const int64_t idx = (int64_t)v * a.W + w;
     const uint64_t h = valid ? a.prev[idx] : 0ull;
@@ -239,7 +324,7 @@ __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bo
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
-    if (sus) count_edges<L>(a, e0 + s, e1, S, w, sus, c);
+    if (sus) count_edges<L>(a, e0 + s, e1, S, w, c);
     bs_reduce_lanes<L>(c, G, S);
     if (seg >= 0) {
         if (valid && s == 0) {
@@ -248,7 +333,7 @@ __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bo
         }
         return;
     }
-    epi_decide<L>(a, G, S, valid, v, w, idx, h, r, sus, c, s, share, tl, tl_n, any);
+    epi_decide<L>(a, G, S, valid, v, w, idx, h, r, sus, c, s, share, tl, tl_n, tcode, any);
 }
 
 // ---------------------------------------------------------------- LT ----
@@ -304,7 +389,7 @@ __device__ __forceinline__ void lt_row_word(const StepArgs &a, int G, int S, boo
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
-    if (inact) count_edges<L>(a, e0 + s, e1, S, w, inact, c);
+    if (inact) count_edges<L>(a, e0 + s, e1, S, w, c);
     bs_reduce_lanes<L>(c, G, S);
     if (seg >= 0) {
         if (valid && s == 0) {
@@ -326,6 +411,7 @@ template <int KIND, int L>
 __device__ __forceinline__ void row_word(const StepArgs &a, int G, int S, bool valid, int v, int w,
                                          int e0, int e1, uint32_t indeg, int s, int seg,
                                          uint64_t share_fixed, const uint32_t *tl, int tl_n,
+                                         const uint32_t *tcode,
                                          bool &any)
 {
     // draws of lane s: generator blocks congruent to s mod S; for S <= 16 the
@@ -337,7 +423,7 @@ __device__ __forceinline__ void row_word(const StepArgs &a, int G, int S, bool v
         if (a.ic_prob == kIcWeightedCascade) tv = wc_threshold(indeg);
         ic_row_word(a, G, S, valid, v, w, e0, e1, tv, s, seg, any);
     } else if (KIND == kKindEpidemic) {
-        epi_row_word<L>(a, G, S, valid, v, w, e0, e1, s, seg, share, tl, tl_n, any);
+        epi_row_word<L>(a, G, S, valid, v, w, e0, e1, s, seg, share, tl, tl_n, tcode, any);
     } else {
         lt_row_word<L>(a, G, S, valid, v, w, e0, e1, indeg, s, seg, share, any);
     }
@@ -348,7 +434,7 @@ __device__ __forceinline__ void row_word(const StepArgs &a, int G, int S, bool v
 // tiles.  Returns through `any` whether a state-1 node remains.
 template <int KIND, int L>
 __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uint32_t *tl,
-                                           int tl_n, bool &any)
+                                           int tl_n, const uint32_t *tcode, bool &any)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -378,7 +464,7 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
             for (int w0 = 0; w0 < a.W; w0 += G) {
                 const int w = w0 + gw;
                 row_word<KIND, L>(a, G, S, act && w < a.W, v, w < a.W ? w : 0, e0, e1,
-                                  (uint32_t)(e1 - e0), s, -1, share_fixed, tl, tl_n, any);
+                                  (uint32_t)(e1 - e0), s, -1, share_fixed, tl, tl_n, tcode, any);
             }
         }
     } else {
@@ -398,7 +484,7 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
         for (int w0 = 0; w0 < a.W; w0 += G) {
             const int w = w0 + gw;
             row_word<KIND, L>(a, G, Ss, act && w < a.W, v, w < a.W ? w : 0, e0, e1, indeg, ss,
-                              act ? seg : 0, share_seg, tl, tl_n, any);
+                              act ? seg : 0, share_seg, tl, tl_n, tcode, any);
         }
     }
 }
@@ -409,14 +495,16 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
 {
     if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // nothing left to change
     __shared__ uint32_t s_tinf[KIND == kKindEpidemic ? kTinfLds : 1];
+    __shared__ uint32_t s_code[kCodeTable];
     int tl_n = 0;
     if (KIND == kKindEpidemic) {
         tl_n = a.khat + 1 < kTinfLds ? a.khat + 1 : kTinfLds;
         for (int i = threadIdx.x; i < tl_n; i += blockDim.x) s_tinf[i] = a.tinf[i];
+        if (threadIdx.x < kCodeTable) s_code[threadIdx.x] = code_threshold(a, threadIdx.x);
         __syncthreads();
     }
     bool any = false;
-    step_block<KIND, L>(a, blockIdx.x, s_tinf, tl_n, any);
+    step_block<KIND, L>(a, blockIdx.x, s_tinf, tl_n, s_code, any);
     if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
 }
 
@@ -424,7 +512,8 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
 // heavy rows), then the same update as a light row.  G lanes per row over
 // words, no edge split.
 template <int KIND, int LP>
-__device__ __forceinline__ void combine_block(const StepArgs &a, int bid, bool &any)
+__device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const uint32_t *tcode,
+                                              bool &any)
 {
     constexpr int LC = 32;
     const int lane = threadIdx.x & 63;
@@ -474,7 +563,7 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, bool &
 #pragma unroll
                 for (int l = 0; l < LC; ++l) c[l] &= sus;
                 epi_decide<LC>(a, G, 1, valid, v, ww, idx, h, r, sus, c, 0, ~0ull, nullptr, 0,
-                               any);
+                               tcode, any);
             } else {
                 const uint64_t act_w = valid ? a.prev[idx] : 0ull;
                 const uint64_t inact = valid ? (~act_w & tail_mask(ww, a.B)) : 0ull;
@@ -491,8 +580,13 @@ template <int KIND, int LP>
 __global__ void __launch_bounds__(256) k_combine(StepArgs a)
 {
     if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
+    __shared__ uint32_t s_code[kCodeTable];
+    if (KIND == kKindEpidemic) {
+        if (threadIdx.x < kCodeTable) s_code[threadIdx.x] = code_threshold(a, threadIdx.x);
+        __syncthreads();
+    }
     bool any = false;
-    combine_block<KIND, LP>(a, blockIdx.x, any);
+    combine_block<KIND, LP>(a, blockIdx.x, s_code, any);
     if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
 }
 
@@ -708,6 +802,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchCtl c)
 {
     __shared__ int32_t s_off[kMaxBatchJobs + 1];
     __shared__ int s_item;
+    __shared__ uint32_t s_code[kCodeTable];
     const uint32_t t = *c.cur_step;
     for (int i = threadIdx.x; i <= c.n_jobs; i += blockDim.x) s_off[i] = c.item_off[i];
     __syncthreads();
@@ -722,19 +817,23 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchCtl c)
         const StepArgs a = job_at_step(c, j, t);
         if (!job_live(c, a, j, t)) continue;
         const int local = item - s_off[j];
+        if (c.code[j] / 32 == kKindEpidemic) {  // block-uniform
+            if (threadIdx.x < kCodeTable) s_code[threadIdx.x] = code_threshold(a, threadIdx.x);
+            __syncthreads();
+        }
         bool any = false;
         switch (c.code[j]) {
-        case kKindIC * 32 + 1: step_block<kKindIC, 1>(a, local, nullptr, 0, any); break;
-        case kKindEpidemic * 32 + 2: step_block<kKindEpidemic, 2>(a, local, nullptr, 0, any); break;
-        case kKindEpidemic * 32 + 4: step_block<kKindEpidemic, 4>(a, local, nullptr, 0, any); break;
-        case kKindEpidemic * 32 + 8: step_block<kKindEpidemic, 8>(a, local, nullptr, 0, any); break;
-        case kKindEpidemic * 32 + 12: step_block<kKindEpidemic, 12>(a, local, nullptr, 0, any); break;
-        case kKindEpidemic * 32 + 16: step_block<kKindEpidemic, 16>(a, local, nullptr, 0, any); break;
-        case kKindLT * 32 + 2: step_block<kKindLT, 2>(a, local, nullptr, 0, any); break;
-        case kKindLT * 32 + 4: step_block<kKindLT, 4>(a, local, nullptr, 0, any); break;
-        case kKindLT * 32 + 8: step_block<kKindLT, 8>(a, local, nullptr, 0, any); break;
-        case kKindLT * 32 + 12: step_block<kKindLT, 12>(a, local, nullptr, 0, any); break;
-        case kKindLT * 32 + 16: step_block<kKindLT, 16>(a, local, nullptr, 0, any); break;
+        case kKindIC * 32 + 1: step_block<kKindIC, 1>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 2: step_block<kKindEpidemic, 2>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 4: step_block<kKindEpidemic, 4>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 8: step_block<kKindEpidemic, 8>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 12: step_block<kKindEpidemic, 12>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 16: step_block<kKindEpidemic, 16>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 2: step_block<kKindLT, 2>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 4: step_block<kKindLT, 4>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 8: step_block<kKindLT, 8>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 12: step_block<kKindLT, 12>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 16: step_block<kKindLT, 16>(a, local, nullptr, 0, s_code, any); break;
         default: break;
         }
         if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[t % (uint32_t)a.ring] = 1u;
@@ -745,6 +844,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_combine(BatchCtl c)
 {
     __shared__ int32_t s_off[kMaxBatchJobs + 1];
     __shared__ int s_item;
+    __shared__ uint32_t s_code[kCodeTable];
     const uint32_t t = *c.cur_step;
     for (int i = threadIdx.x; i <= c.n_jobs; i += blockDim.x) s_off[i] = c.comb_off[i];
     __syncthreads();
@@ -759,19 +859,23 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_combine(BatchCtl c)
         const StepArgs a = job_at_step(c, j, t);
         if (!job_live(c, a, j, t)) continue;
         const int local = item - s_off[j];
+        if (c.code[j] / 32 == kKindEpidemic) {  // block-uniform
+            if (threadIdx.x < kCodeTable) s_code[threadIdx.x] = code_threshold(a, threadIdx.x);
+            __syncthreads();
+        }
         bool any = false;
         switch (c.code[j]) {
-        case kKindIC * 32 + 1: combine_block<kKindIC, 1>(a, local, any); break;
-        case kKindEpidemic * 32 + 2: combine_block<kKindEpidemic, 2>(a, local, any); break;
-        case kKindEpidemic * 32 + 4: combine_block<kKindEpidemic, 4>(a, local, any); break;
-        case kKindEpidemic * 32 + 8: combine_block<kKindEpidemic, 8>(a, local, any); break;
-        case kKindEpidemic * 32 + 12: combine_block<kKindEpidemic, 12>(a, local, any); break;
-        case kKindEpidemic * 32 + 16: combine_block<kKindEpidemic, 16>(a, local, any); break;
-        case kKindLT * 32 + 2: combine_block<kKindLT, 2>(a, local, any); break;
-        case kKindLT * 32 + 4: combine_block<kKindLT, 4>(a, local, any); break;
-        case kKindLT * 32 + 8: combine_block<kKindLT, 8>(a, local, any); break;
-        case kKindLT * 32 + 12: combine_block<kKindLT, 12>(a, local, any); break;
-        case kKindLT * 32 + 16: combine_block<kKindLT, 16>(a, local, any); break;
+        case kKindIC * 32 + 1: combine_block<kKindIC, 1>(a, local, s_code, any); break;
+        case kKindEpidemic * 32 + 2: combine_block<kKindEpidemic, 2>(a, local, s_code, any); break;
+        case kKindEpidemic * 32 + 4: combine_block<kKindEpidemic, 4>(a, local, s_code, any); break;
+        case kKindEpidemic * 32 + 8: combine_block<kKindEpidemic, 8>(a, local, s_code, any); break;
+        case kKindEpidemic * 32 + 12: combine_block<kKindEpidemic, 12>(a, local, s_code, any); break;
+        case kKindEpidemic * 32 + 16: combine_block<kKindEpidemic, 16>(a, local, s_code, any); break;
+        case kKindLT * 32 + 2: combine_block<kKindLT, 2>(a, local, s_code, any); break;
+        case kKindLT * 32 + 4: combine_block<kKindLT, 4>(a, local, s_code, any); break;
+        case kKindLT * 32 + 8: combine_block<kKindLT, 8>(a, local, s_code, any); break;
+        case kKindLT * 32 + 12: combine_block<kKindLT, 12>(a, local, s_code, any); break;
+        case kKindLT * 32 + 16: combine_block<kKindLT, 16>(a, local, s_code, any); break;
         default: break;
         }
         if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[t % (uint32_t)a.ring] = 1u;
