@@ -358,7 +358,8 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
 {
     const int kind = model_kind(prm->model);
     L->W = (B + 63) / 64;
-    L->plane_words = g->n * L->W;
+    // one extra all-zero row (index n): gathers of padding lanes read it
+    L->plane_words = (g->n + 1) * L->W;
     L->n_planes = kind == kKindLT ? 2 : 3;
     L->L = kind == kKindIC ? 1 : counter_planes_for(std::max(p.max_light, p.max_seg));
     // room for the longest table (it stops early once it saturates), so the
@@ -526,8 +527,8 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.lgG = s.lgG;
     a.lgS = s.lgS;
     a.heavy = s.heavy;
-    a.fast32 = (g->n < ((int64_t)1 << 24) && g->n * L.W < ((int64_t)1 << 29) &&
-                g->nnz < ((int64_t)1 << 30)) ? 1 : 0;
+    a.fast32 = (g->n + 1 < (1 << 24) && L.W < (1 << 21) && (g->n + 1) * L.W < (1 << 29) &&
+                g->nnz < (1 << 30)) ? 1 : 0;
     a.tiles = (const int32_t *)(base + L.tiles);
     a.n_tiles = (int32_t)(p.tiles.size() / 2);
     a.seg_row = (const int32_t *)(base + L.seg_row);

@@ -105,6 +105,14 @@ __device__ __forceinline__ uint64_t share_bits(uint64_t gbase, int s, int S)
     return m;
 }
 
+// Value of lane J of the caller's 16-lane row (DPP row broadcast); every lane
+// of the row must be active.
+template <int J>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x150 + J, 0xF, 0xF, false);
+}
+
 // ---- bit-sliced counters: c[l] holds bit l of 64 per-replicate counts ----
 
 template <int L>

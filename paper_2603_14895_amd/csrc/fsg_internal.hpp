@@ -49,7 +49,7 @@ struct StepArgs {
     // schedule
     int32_t G, S, lgG, lgS; // lanes per row: G over words, S over edges
     int32_t heavy;          // rows with more in-edges are processed as segments
-    int32_t fast32;         // n < 2^24, n*W < 2^29 and nnz < 2^30: 32-bit offsets
+    int32_t fast32;         // n+1 < 2^24, W < 2^21, (n+1)*W < 2^29, nnz < 2^30: 32-bit offsets
     const int32_t *tiles;   // [n_tiles + 1] row boundaries
     int32_t n_tiles;
     // heavy rows cut into segments

@@ -161,6 +161,55 @@ __device__ __forceinline__ void count_edges(const StepArgs &a, int e, int e1, in
     for (; e < e1; e += S) bs_add1<L>(c, a.prev[(int64_t)a.src[e] * W + w]);
 }
 
+// The same count when a row owns whole 16-lane rows of the wave (G >= 16,
+// S = 1) and 32-bit offsets apply: the 16 lanes load 16 consecutive sources
+// of their row with one vector load (the next chunk's load issued before the
+// current chunk's gathers), and each source reaches every lane of the row by a
+// DPP row broadcast; the gathers then go out eight at a time without waiting
+// on index loads.  Positions past the row's end carry source n, whose plane
+// row is all zero, as does every position of a lane whose word needs no
+// count.  All 64 lanes of the wave must call this together.
+template <int L>
+__device__ __forceinline__ void count_edges_bcast(const StepArgs &a, int G, bool valid, int e0,
+                                                  int e1, int w, bool need, uint64_t (&c)[L])
+{
+    const int lr = (int)(threadIdx.x & 15u);
+    int dmax = 0;  // longest valid row of the wave (word 0 of a row is valid iff the row is)
+    const int d = valid ? e1 - e0 : 0;
+    for (int l = 0; l < 64; l += G) dmax = max(dmax, __builtin_amdgcn_readlane(d, l));
+    if (dmax == 0 || __ballot(need) == 0ull) return;
+    const uint32_t W8 = (uint32_t)a.W * 8u, w8 = (uint32_t)w * 8u, zero = (uint32_t)a.n;
+    const char *prev = reinterpret_cast<const char *>(a.prev);
+    auto src_at = [&](int base) -> uint32_t {
+        const int e = e0 + base + lr;
+        return e < e1 ? (uint32_t)ld32_off32(a.src, (uint32_t)e) : zero;
+    };
+    auto word = [&](uint32_t u) -> uint64_t {
+        return *reinterpret_cast<const uint64_t *>(prev + __umul24(need ? u : zero, W8) + w8);
+    };
+    uint32_t cur = src_at(0);
+    for (int base = 0; base < dmax; base += 16) {
+        const uint32_t nxt = base + 16 < dmax ? src_at(base + 16) : zero;
+        {
+            const uint64_t x0 = word(row_bcast<0>(cur)), x1 = word(row_bcast<1>(cur)),
+                           x2 = word(row_bcast<2>(cur)), x3 = word(row_bcast<3>(cur)),
+                           x4 = word(row_bcast<4>(cur)), x5 = word(row_bcast<5>(cur)),
+                           x6 = word(row_bcast<6>(cur)), x7 = word(row_bcast<7>(cur));
+            bs_add4<L>(c, x0, x1, x2, x3);
+            bs_add4<L>(c, x4, x5, x6, x7);
+        }
+        if (dmax - base > 8) {
+            const uint64_t x0 = word(row_bcast<8>(cur)), x1 = word(row_bcast<9>(cur)),
+                           x2 = word(row_bcast<10>(cur)), x3 = word(row_bcast<11>(cur)),
+                           x4 = word(row_bcast<12>(cur)), x5 = word(row_bcast<13>(cur)),
+                           x6 = word(row_bcast<14>(cur)), x7 = word(row_bcast<15>(cur));
+            bs_add4<L>(c, x0, x1, x2, x3);
+            bs_add4<L>(c, x4, x5, x6, x7);
+        }
+        cur = nxt;
+    }
+}
+
 // ------------------------------------------------------ SI / SIS / SIR ----
 // Appendix A.1: the log-survival messages of the k infected in-neighbours sum
 // to k log(1-beta), so a susceptible node is infected with probability
@@ -324,7 +373,10 @@ __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bo
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
-    if (sus) count_edges<L>(a, e0 + s, e1, S, w, c);
+    if (S == 1 && G >= 16 && a.fast32)
+        count_edges_bcast<L>(a, G, valid, e0, e1, w, sus != 0ull, c);
+    else if (sus)
+        count_edges<L>(a, e0 + s, e1, S, w, c);
     bs_reduce_lanes<L>(c, G, S);
     if (seg >= 0) {
         if (valid && s == 0) {
@@ -389,7 +441,10 @@ __device__ __forceinline__ void lt_row_word(const StepArgs &a, int G, int S, boo
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
-    if (inact) count_edges<L>(a, e0 + s, e1, S, w, c);
+    if (S == 1 && G >= 16 && a.fast32)
+        count_edges_bcast<L>(a, G, valid, e0, e1, w, inact != 0ull, c);
+    else if (inact)
+        count_edges<L>(a, e0 + s, e1, S, w, c);
     bs_reduce_lanes<L>(c, G, S);
     if (seg >= 0) {
         if (valid && s == 0) {
