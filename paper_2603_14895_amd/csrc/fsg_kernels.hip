@@ -664,12 +664,18 @@ __device__ __forceinline__ bool in_frontier(const uint32_t *bm, int u)
     return (bm[u >> 5] >> (u & 31)) & 1u;
 }
 
+// Summary bit of source u's group of 2^sum_shift nodes (LDS copy).
+__device__ __forceinline__ bool summary_hit(const StepArgs &a, const uint32_t *s_sum, int u)
+{
+    const int i = u >> a.sum_shift;
+    return (s_sum[i >> 5] >> (i & 31)) & 1u;
+}
+
 // Frontier test of source u: the LDS summary first, the global bitmap only
 // when the summary bit is set.
 __device__ __forceinline__ bool frontier_hit(const StepArgs &a, const uint32_t *s_sum, int u)
 {
-    const int i = u >> a.sum_shift;
-    if (!((s_sum[i >> 5] >> (i & 31)) & 1u)) return false;
+    if (!summary_hit(a, s_sum, u)) return false;
     return in_frontier(a.bm_prev, u);
 }
 
@@ -711,8 +717,12 @@ __global__ void __launch_bounds__(1024) k_ic_edge1(StepArgs a)
                     bool hit[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) us[j] = a.src[e + j * nt];
+                    uint32_t bw[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) hit[j] = frontier_hit(a, s_sum, us[j]);
+                    for (int j = 0; j < 4; ++j)
+                        bw[j] = summary_hit(a, s_sum, us[j]) ? a.bm_prev[us[j] >> 5] : 0u;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) hit[j] = (bw[j] >> (us[j] & 31)) & 1u;
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         if (hit[j])
@@ -760,15 +770,30 @@ __global__ void __launch_bounds__(1024) k_ic_edge1(StepArgs a)
                 us[4 * c + 2] = q.z;
                 us[4 * c + 3] = q.w;
             }
-            uint32_t hit = 0;
+            // summary tests first; then every bitmap word a summary hit needs
+            // is loaded at once, so a pass waits on global memory at most once
+            uint32_t cand = 0;
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int e = base + 4 * (c * nt + tid) + j;
-                    if (e >= E0 && e < E1 && frontier_hit(a, s_sum, us[4 * c + j]))
-                        hit |= 1u << (4 * c + j);
+                    if (e >= E0 && e < E1 && summary_hit(a, s_sum, us[4 * c + j]))
+                        cand |= 1u << (4 * c + j);
                 }
+            }
+            // when any lane of the wave has a candidate, every slot loads its
+            // bitmap word (word 0 where the slot is no candidate) in one
+            // branch-free run, so the pass waits on these loads once
+            uint32_t hit = 0;
+            if (__ballot(cand != 0u) != 0ull) {
+                uint32_t bw[4 * kChunks];
+#pragma unroll
+                for (int k = 0; k < 4 * kChunks; ++k)
+                    bw[k] = a.bm_prev[((cand >> k) & 1u) ? ((uint32_t)us[k] >> 5) : 0u];
+#pragma unroll
+                for (int k = 0; k < 4 * kChunks; ++k)
+                    hit |= (((cand >> k) & 1u) & (bw[k] >> ((uint32_t)us[k] & 31u))) << k;
             }
             while (hit) {
                 const int k = __builtin_ctz(hit);
