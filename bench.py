@@ -71,11 +71,11 @@ def algorithmic_bytes_per_step(model: str, n: int, nnz: int, B: int, edge_parall
     neighbour word group 8 W B/arc, and the node's own planes (IC: read A,
     write A and F; SIR-family: read h, r, write h, r; LT: read and write the
     active plane).
-    Edge-parallel IC kernel (B <= 64): sources 4 B/arc, row pointers 4 B/row
-    and one read of the N-bit frontier bitmap; the frontier words of the few
-    frontier arcs and the rows that change are not counted."""
+    Edge-parallel IC kernel (B <= 64): sources 4 B/arc and one read of the
+    N-bit frontier bitmap; the target rows, degrees and words of the few
+    frontier arcs are not counted."""
     if edge_parallel:
-        return 4.0 * nnz + 4.0 * (n + 1) + n / 8.0
+        return 4.0 * nnz + n / 8.0
     W = (B + 63) // 64
     own = {"ic": 24, "lt": 16}.get(model, 32) * W
     return 4.0 * nnz + 8.0 * W * nnz + 4.0 * (n + 1) + own * n
@@ -239,7 +239,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": measured_traffic(args.workload),
-                "kernel": "k_ic_edge1" if edge_parallel else "k_step",
+                "kernel": "k_ic_stream" if edge_parallel else "k_step",
                 "avg_launch_ms": round(avg_kernel_ms, 5), "launches": launches,
                 "algorithmic_bytes_per_launch": abytes}
     cpu = None

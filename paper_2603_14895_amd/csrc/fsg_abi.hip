@@ -101,6 +101,7 @@ struct fsg_graph {
     bool bound = false;
     int32_t *d_ptr = nullptr;
     int32_t *d_src = nullptr;
+    int32_t *d_dst = nullptr;  // target row of every arc (built on the device at bind)
     std::map<std::tuple<int64_t, int64_t, int64_t>, Plan> plans;
 };
 
@@ -392,8 +393,8 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
         const size_t bmb = (size_t)((g->n + 31) / 32) * 4;
         L->bm[0] = off; off = align256(off + bmb);
         L->bm[1] = off; off = align256(off + bmb);
-        // coarsest summary that fits the kernel's LDS copy, at least 512 nodes a bit
-        int sh = 9;
+        // coarsest summary that fits the kernel's LDS copy, at least 256 nodes a bit
+        int sh = 8;
         while ((((g->n - 1) >> sh) >> 5) + 1 > kSumWords) ++sh;
         L->sum_shift = sh;
         L->sum_words = (int)((((g->n - 1) >> sh) >> 5) + 1);
@@ -542,6 +543,8 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.Lp = L.L;
     a.flags = flags;
     a.ring = ring;
+    a.dst = g->d_dst;
+    a.nnz = g->nnz;
     a.sum_shift = L.sum_shift;
     a.sum_words = L.sum_words;
     return FSG_OK;
@@ -620,8 +623,10 @@ int fsg_graph_create(int64_t n, int64_t nnz, const int64_t *in_ptr, const int32_
 int fsg_graph_workspace_size(const fsg_graph *g, size_t *bytes)
 {
     if (!g || !bytes) return fail(FSG_EINVAL, "NULL argument");
-    // sources are padded by 16 bytes: kernels read them with 16-byte loads
-    *bytes = align256((size_t)(g->n + 1) * 4) + align256((size_t)std::max<int64_t>(g->nnz, 1) * 4 + 16);
+    // sources are padded by 16 bytes: kernels read them with 16-byte loads;
+    // then the target row of every arc
+    *bytes = align256((size_t)(g->n + 1) * 4) + align256((size_t)std::max<int64_t>(g->nnz, 1) * 4 + 16) +
+             align256((size_t)std::max<int64_t>(g->nnz, 1) * 4);
     return FSG_OK;
 }
 
@@ -638,13 +643,16 @@ int fsg_graph_bind(fsg_graph *g, void *dev_ws, size_t ws_bytes, void *stream)
         char *base = (char *)dev_ws;
         int32_t *dptr = (int32_t *)base;
         int32_t *dsrc = (int32_t *)(base + align256((size_t)(g->n + 1) * 4));
+        int32_t *ddst = (int32_t *)((char *)dsrc + align256((size_t)std::max<int64_t>(g->nnz, 1) * 4 + 16));
         std::vector<int32_t> p32(g->ptr.begin(), g->ptr.end());
         HIP_TRY(hipMemcpyAsync(dptr, p32.data(), p32.size() * 4, hipMemcpyHostToDevice, s));
         if (g->nnz > 0)
             HIP_TRY(hipMemcpyAsync(dsrc, g->src_host, (size_t)g->nnz * 4, hipMemcpyHostToDevice, s));
+        if (g->nnz > 0) HIP_TRY(launch_expand_rows(dptr, g->n, ddst, s));
         HIP_TRY(hipStreamSynchronize(s));
         g->d_ptr = dptr;
         g->d_src = dsrc;
+        g->d_dst = ddst;
         g->bound = true;
         g->src_host = nullptr;
         return FSG_OK;
@@ -730,7 +738,7 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
             int dev = 0, ncu = 0;
             HIP_TRY(hipGetDevice(&dev));
             HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-            edge_grid = 3 * std::max(ncu, 1);  // ~41 KB of LDS a block: three per CU
+            edge_grid = 4 * std::max(ncu, 1);  // 32 KB of LDS a block: four per CU
         }
 
         // ---- step loop: chunks of `sync` steps, then a poll of the flags
@@ -760,7 +768,7 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
                     a.sum_next = jb.sum[step & 1];
                     HIP_TRY(launch_ic_clear(a, st));
                     if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
-                    HIP_TRY(launch_ic_edge1(a, edge_grid, s.block, st));
+                    HIP_TRY(launch_ic_stream(a, edge_grid, s.block, st));
                     if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
                 } else {
                     if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));

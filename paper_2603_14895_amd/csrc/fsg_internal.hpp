@@ -17,10 +17,10 @@ bool graph_view(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg
 
 enum Kind { kKindIC = 0, kKindEpidemic = 1, kKindLT = 2 };
 
-// Rows a tile may hold (the edge-parallel kernel stages them in LDS).
+// Rows a tile may hold.
 constexpr int kMaxTileRows = 2048;
 // Words of the frontier summary the edge-parallel kernel keeps in LDS.
-constexpr int kSumWords = 4096;
+constexpr int kSumWords = 8192;
 enum Model { kIC = 0, kSI = 1, kSIS = 2, kSIR = 3, kLT = 4 };
 enum IcProb { kIcUniform = 0, kIcWeightedCascade = 1, kIcPerEdge = 2 };
 
@@ -31,6 +31,8 @@ enum IcProb { kIcUniform = 0, kIcWeightedCascade = 1, kIcPerEdge = 2 };
 struct StepArgs {
     const int32_t *ptr;  // [n+1]
     const int32_t *src;  // [nnz]
+    const int32_t *dst;  // [nnz] target row of every arc (edge-parallel IC kernel)
+    int64_t nnz;
     int32_t n;
     int32_t W;            // words per node: ceil(B / 64)
     int64_t B;
@@ -113,7 +115,8 @@ hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStr
 hipError_t launch_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t ns, int32_t W,
                        int64_t B, uint32_t *flag0, uint32_t *bm, uint32_t *sum, int sum_shift,
                        hipStream_t s);
-hipError_t launch_ic_edge1(const StepArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_ic_stream(const StepArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_expand_rows(const int32_t *ptr, int64_t n, int32_t *dst, hipStream_t s);
 hipError_t launch_ic_clear(const StepArgs &a, hipStream_t s);
 hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_t s);
 hipError_t launch_combine(const StepArgs &a, int kind, int block, hipStream_t s);

@@ -646,22 +646,19 @@ __global__ void __launch_bounds__(256) k_combine(StepArgs a)
 }
 
 // ------------------------------------------- IC, one word per node ----
-// Edge-parallel variant for B <= 64 (W = 1): a block streams the in-edge
-// range of its tile four arcs per thread with 16-byte loads, tests each source
-// against the frontier bitmap (N bits, cache-resident), and only for a
-// frontier source finds the target row (binary search over the tile's row
-// pointers in LDS), gathers the source word and runs the arc's trials; fired
-// replicate bits are OR-ed into the row's LDS word.  Only rows that change
-// are written.  Heavy rows come as segments whose blocks OR into the row's
-// global words directly (cleared before the step by k_ic_clear).
+// Edge-parallel variant for B <= 64 (W = 1): persistent blocks stream the
+// whole arc array once per step, four 16-byte source loads per thread per
+// pass, and test each source against the frontier: first the summary (one bit
+// per 2^sum_shift nodes, in LDS), then, for summary hits, the frontier bitmap
+// (N bits, cache-resident).  Only a frontier arc reads its target row (the
+// arc's entry of dst), gathers the source word, runs the arc's trials and ORs
+// fired replicates into the target's words with atomics; the target joins the
+// next frontier.  The step has no tiles and no block barriers, and it reads
+// neither the row pointers (except a frontier arc's target degree under the
+// weighted cascade) nor the words of rows that do not change.
 __device__ __forceinline__ uint32_t ic_threshold(const StepArgs &a, uint32_t indeg)
 {
     return a.ic_prob == kIcWeightedCascade ? wc_threshold(indeg) : a.ic_t;
-}
-
-__device__ __forceinline__ bool in_frontier(const uint32_t *bm, int u)
-{
-    return (bm[u >> 5] >> (u & 31)) & 1u;
 }
 
 // Summary bit of source u's group of 2^sum_shift nodes (LDS copy).
@@ -671,14 +668,6 @@ __device__ __forceinline__ bool summary_hit(const StepArgs &a, const uint32_t *s
     return (s_sum[i >> 5] >> (i & 31)) & 1u;
 }
 
-// Frontier test of source u: the LDS summary first, the global bitmap only
-// when the summary bit is set.
-__device__ __forceinline__ bool frontier_hit(const StepArgs &a, const uint32_t *s_sum, int u)
-{
-    if (!summary_hit(a, s_sum, u)) return false;
-    return in_frontier(a.bm_prev, u);
-}
-
 __device__ __forceinline__ void mark_frontier(const StepArgs &a, int v)
 {
     atomicOr(&a.bm_next[v >> 5], 1u << (v & 31));
@@ -686,161 +675,103 @@ __device__ __forceinline__ void mark_frontier(const StepArgs &a, int v)
     atomicOr(&a.sum_next[i >> 5], 1u << (i & 31));
 }
 
-// Persistent blocks: block b takes work items b, b + grid, ... where items
-// [0, n_seg) are heavy-row segments and the rest are light tiles.
-__global__ void __launch_bounds__(1024) k_ic_edge1(StepArgs a)
+__global__ void __launch_bounds__(1024) k_ic_stream(StepArgs a)
 {
     if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
-    __shared__ int32_t s_ptr[kMaxTileRows + 1];
-    __shared__ unsigned long long s_new[kMaxTileRows];
     __shared__ uint32_t s_sum[kSumWords];
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+    for (int i = threadIdx.x; i < a.sum_words; i += blockDim.x) s_sum[i] = a.sum_prev[i];
+    __syncthreads();
     const uint64_t tail = tail_mask(0, a.B);
     const uint64_t gbase = a.goff;
-    for (int i = tid; i < a.sum_words; i += nt) s_sum[i] = a.sum_prev[i];
+    const int64_t nnz = a.nnz;
+    // pass: chunk c of thread t covers arcs base + c*stride .. +3
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+    constexpr int kChunks = 4;
     bool any = false;
-    const int n_items = a.n_seg + a.n_tiles;
-    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
-        __syncthreads();  // LDS of the previous item is no longer in use
-        if (item < a.n_seg) {
-            const int sg = item;
-            const int v = a.seg_row[sg], e0 = a.seg_e0[sg], e1 = a.seg_e1[sg];
-            const uint32_t tv = ic_threshold(a, (uint32_t)(a.ptr[v + 1] - a.ptr[v]));
-            if (tid == 0) s_new[0] = 0ull;
-            __syncthreads();
-            const uint64_t cand = ~a.aux[v] & tail;
+    for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; base < nnz;
+         base += stride * kChunks) {
+        int us[4 * kChunks];
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const int64_t eb = base + c * stride;
+            int4 q = make_int4(0, 0, 0, 0);
+            if (eb < nnz) q = *reinterpret_cast<const int4 *>(a.src + eb);  // sources padded by 16 B
+            us[4 * c] = q.x;
+            us[4 * c + 1] = q.y;
+            us[4 * c + 2] = q.z;
+            us[4 * c + 3] = q.w;
+        }
+        uint32_t cand = 0;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (base + c * stride + j < nnz && summary_hit(a, s_sum, us[4 * c + j]))
+                    cand |= 1u << (4 * c + j);
+        }
+        // when any lane of the wave has a candidate, every slot loads its
+        // bitmap word (word 0 where the slot is no candidate) in one
+        // branch-free run, so the pass waits on these loads once
+        uint32_t hit = 0;
+        if (__ballot(cand != 0u) != 0ull) {
+            uint32_t bw[4 * kChunks];
+#pragma unroll
+            for (int k = 0; k < 4 * kChunks; ++k)
+                bw[k] = a.bm_prev[((cand >> k) & 1u) ? ((uint32_t)us[k] >> 5) : 0u];
+#pragma unroll
+            for (int k = 0; k < 4 * kChunks; ++k)
+                hit |= (((cand >> k) & 1u) & (bw[k] >> ((uint32_t)us[k] & 31u))) << k;
+        }
+        while (hit) {
+            const int k = __builtin_ctz(hit);
+            hit &= hit - 1;
+            const int64_t e = base + (k >> 2) * stride + (k & 3);
+            const int u = us[k];
+            const int v = a.dst[e];
+            const uint32_t tv = a.edge_t ? 0u : ic_threshold(a, (uint32_t)(a.ptr[v + 1] - a.ptr[v]));
+            const uint64_t cand_r = ~a.aux[v] & tail;
             uint64_t acc = 0;
-            if (cand) {
-                int e = e0 + tid;
-                for (; e + 3 * nt < e1; e += 4 * nt) {  // four independent probes in flight
-                    int us[4];
-                    bool hit[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) us[j] = a.src[e + j * nt];
-                    uint32_t bw[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        bw[j] = summary_hit(a, s_sum, us[j]) ? a.bm_prev[us[j] >> 5] : 0u;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) hit[j] = (bw[j] >> (us[j] & 31)) & 1u;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (hit[j])
-                            ic_edge(a, e + j * nt, a.prev[us[j]] & cand & ~acc, gbase, tv, acc);
-                }
-                for (; e < e1; e += nt) {
-                    const int u = a.src[e];
-                    if (frontier_hit(a, s_sum, u))
-                        ic_edge(a, e, a.prev[u] & cand & ~acc, gbase, tv, acc);
-                }
-            }
-            for (int off = 1; off < 64; off <<= 1) acc |= __shfl_xor(acc, off, 64);
-            if (lane == 0 && acc) atomicOr(&s_new[0], (unsigned long long)acc);
-            __syncthreads();
-            if (tid == 0) {
-                const uint64_t nf = s_new[0];
-                if (nf) {
-                    atomicOr((unsigned long long *)&a.next[v], (unsigned long long)nf);
-                    atomicOr((unsigned long long *)&a.aux[v], (unsigned long long)nf);
-                    mark_frontier(a, v);
-                    any = true;
-                }
-            }
-            continue;
-        }
-        const int tile = item - a.n_seg;
-        const int r0 = a.tiles[2 * tile], r1 = a.tiles[2 * tile + 1];
-        const int nr = r1 - r0;
-        for (int i = tid; i <= nr; i += nt) s_ptr[i] = a.ptr[r0 + i];
-        for (int i = tid; i < nr; i += nt) s_new[i] = 0ull;
-        __syncthreads();
-        const int E0 = s_ptr[0], E1 = s_ptr[nr];
-        // each thread owns 4 chunks of 4 consecutive arcs per pass: four
-        // 16-byte source loads, then sixteen frontier tests, all in flight
-        constexpr int kChunks = 4;
-        for (int base = E0 & ~3; base < E1; base += 4 * kChunks * nt) {
-            int us[4 * kChunks];
-#pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
-                const int eb = base + 4 * (c * nt + tid);
-                int4 q = make_int4(0, 0, 0, 0);
-                if (eb < E1) q = *reinterpret_cast<const int4 *>(a.src + eb);
-                us[4 * c] = q.x;
-                us[4 * c + 1] = q.y;
-                us[4 * c + 2] = q.z;
-                us[4 * c + 3] = q.w;
-            }
-            // summary tests first; then every bitmap word a summary hit needs
-            // is loaded at once, so a pass waits on global memory at most once
-            uint32_t cand = 0;
-#pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int e = base + 4 * (c * nt + tid) + j;
-                    if (e >= E0 && e < E1 && summary_hit(a, s_sum, us[4 * c + j]))
-                        cand |= 1u << (4 * c + j);
-                }
-            }
-            // when any lane of the wave has a candidate, every slot loads its
-            // bitmap word (word 0 where the slot is no candidate) in one
-            // branch-free run, so the pass waits on these loads once
-            uint32_t hit = 0;
-            if (__ballot(cand != 0u) != 0ull) {
-                uint32_t bw[4 * kChunks];
-#pragma unroll
-                for (int k = 0; k < 4 * kChunks; ++k)
-                    bw[k] = a.bm_prev[((cand >> k) & 1u) ? ((uint32_t)us[k] >> 5) : 0u];
-#pragma unroll
-                for (int k = 0; k < 4 * kChunks; ++k)
-                    hit |= (((cand >> k) & 1u) & (bw[k] >> ((uint32_t)us[k] & 31u))) << k;
-            }
-            while (hit) {
-                const int k = __builtin_ctz(hit);
-                hit &= hit - 1;
-                const int c = k >> 2, j = k & 3;
-                const int e = base + 4 * (c * nt + tid) + j;
-                int lo = 0, hi = nr - 1;  // last row whose first edge is <= e
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_ptr[mid] <= e) lo = mid; else hi = mid - 1;
-                }
-                const int v = r0 + lo;
-                const uint64_t cand = ~a.aux[v] & tail;
-                uint64_t acc = 0;
-                ic_edge(a, e, a.prev[us[k]] & cand, gbase,
-                        ic_threshold(a, (uint32_t)(s_ptr[lo + 1] - s_ptr[lo])), acc);
-                if (acc) atomicOr(&s_new[lo], (unsigned long long)acc);
-            }
-        }
-        __syncthreads();
-        for (int i = tid; i < nr; i += nt) {
-            const uint64_t nf = s_new[i];
-            if (nf) {
-                const int v = r0 + i;
-                a.next[v] = nf;
-                a.aux[v] |= nf;
+            ic_edge(a, (int)e, a.prev[u] & cand_r, gbase, tv, acc);
+            if (acc) {
+                atomicOr((unsigned long long *)&a.next[v], (unsigned long long)acc);
+                atomicOr((unsigned long long *)&a.aux[v], (unsigned long long)acc);
                 mark_frontier(a, v);
                 any = true;
             }
         }
     }
-    if (__ballot(any) != 0ull && lane == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+    if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
 }
 
-// Before a step of the edge-parallel kernel: clear the next frontier bitmap,
-// its summary, and the next-frontier words of heavy rows (their segments OR
-// into them).
+// Target row of every arc: one thread per row (grid-stride), used once when
+// a graph is bound.
+__global__ void k_expand_rows(const int32_t *ptr, int64_t n, int32_t *dst)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        for (int e = ptr[v]; e < ptr[v + 1]; ++e) dst[e] = (int32_t)v;
+}
+
+// Before a step of the edge-parallel kernel: the next-frontier bitmap still
+// holds the frontier of two steps back, whose words in the next plane are the
+// only nonzero ones there; zero those words (the step ORs into them), then
+// clear the bitmap and its summary.
 __global__ void k_ic_clear(StepArgs a)
 {
     if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
     const int64_t nw = ((int64_t)a.n + 31) >> 5;
-    const int64_t work = nw > a.n_heavy ? nw : a.n_heavy;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < work;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
          i += (int64_t)gridDim.x * blockDim.x) {
-        if (i < nw) a.bm_next[i] = 0u;
+        uint32_t x = a.bm_next[i];
+        if (x) {
+            a.bm_next[i] = 0u;
+            while (x) {
+                const int b = __builtin_ctz(x);
+                x &= x - 1u;
+                a.next[i * 32 + b] = 0ull;
+            }
+        }
         if (i < a.sum_words) a.sum_next[i] = 0u;
-        if (i < a.n_heavy) a.next[a.heavy_rows[i]] = 0ull;
     }
 }
 
@@ -1198,19 +1129,26 @@ hipError_t launch_combine(const StepArgs &a, int kind, int /*block*/, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_ic_edge1(const StepArgs &a, int grid, int block, hipStream_t s)
+hipError_t launch_ic_stream(const StepArgs &a, int grid, int block, hipStream_t s)
 {
-    const int64_t items = (int64_t)a.n_seg + a.n_tiles;
-    if (items <= 0) return hipSuccess;
-    const int64_t g = std::min<int64_t>(items, grid);
-    hipLaunchKernelGGL(k_ic_edge1, dim3((unsigned)g), dim3((unsigned)block), 0, s, a);
+    if (a.nnz <= 0) return hipSuccess;
+    const int64_t need = (a.nnz + 4 * (int64_t)block - 1) / (4 * (int64_t)block);
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>(need, grid));
+    hipLaunchKernelGGL(k_ic_stream, dim3((unsigned)g), dim3((unsigned)block), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_ic_clear(const StepArgs &a, hipStream_t s)
 {
-    const int64_t work = std::max<int64_t>(((int64_t)a.n + 31) >> 5, a.n_heavy);
+    const int64_t work = ((int64_t)a.n + 31) >> 5;
     hipLaunchKernelGGL(k_ic_clear, dim3(grid_for(work, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_rows(const int32_t *ptr, int64_t n, int32_t *dst, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, ptr, n, dst);
     return hipGetLastError();
 }
 
