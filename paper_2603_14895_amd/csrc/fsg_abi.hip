@@ -102,6 +102,8 @@ struct fsg_graph {
     int32_t *d_ptr = nullptr;
     int32_t *d_src = nullptr;
     int32_t *d_dst = nullptr;  // target row of every arc (built on the device at bind)
+    std::vector<int32_t> wide;  // rows with more than kWideRow in-arcs
+    int32_t *d_wide = nullptr;
     std::map<std::tuple<int64_t, int64_t, int64_t>, Plan> plans;
 };
 
@@ -110,9 +112,11 @@ namespace fsg {
 int set_error(int code, const char *msg) { return fail(code, msg); }
 
 bool graph_view(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg,
-                const int32_t **ptr, const int32_t **src)
+                const int32_t **ptr, const int32_t **src, const int32_t **wide, int64_t *n_wide)
 {
     if (!g || !g->bound) return false;
+    *wide = g->d_wide;
+    *n_wide = (int64_t)g->wide.size();
     *n = g->n;
     *nnz = g->nnz;
     *max_indeg = g->max_indeg;
@@ -610,6 +614,8 @@ int fsg_graph_create(int64_t n, int64_t nnz, const int64_t *in_ptr, const int32_
         g->nnz = nnz;
         g->max_indeg = dmax;
         g->ptr.assign(in_ptr, in_ptr + n + 1);
+        for (int64_t v = 0; v < n; ++v)
+            if (in_ptr[v + 1] - in_ptr[v] > kWideRow) g->wide.push_back((int32_t)v);
         g->src_host = in_src;
         *out = g;
         return FSG_OK;
@@ -626,7 +632,7 @@ int fsg_graph_workspace_size(const fsg_graph *g, size_t *bytes)
     // sources are padded by 16 bytes: kernels read them with 16-byte loads;
     // then the target row of every arc
     *bytes = align256((size_t)(g->n + 1) * 4) + align256((size_t)std::max<int64_t>(g->nnz, 1) * 4 + 16) +
-             align256((size_t)std::max<int64_t>(g->nnz, 1) * 4);
+             align256((size_t)std::max<int64_t>(g->nnz, 1) * 4) + align256((g->wide.size() + 1) * 4);
     return FSG_OK;
 }
 
@@ -644,6 +650,9 @@ int fsg_graph_bind(fsg_graph *g, void *dev_ws, size_t ws_bytes, void *stream)
         int32_t *dptr = (int32_t *)base;
         int32_t *dsrc = (int32_t *)(base + align256((size_t)(g->n + 1) * 4));
         int32_t *ddst = (int32_t *)((char *)dsrc + align256((size_t)std::max<int64_t>(g->nnz, 1) * 4 + 16));
+        int32_t *dwide = (int32_t *)((char *)ddst + align256((size_t)std::max<int64_t>(g->nnz, 1) * 4));
+        if (!g->wide.empty())
+            HIP_TRY(hipMemcpyAsync(dwide, g->wide.data(), g->wide.size() * 4, hipMemcpyHostToDevice, s));
         std::vector<int32_t> p32(g->ptr.begin(), g->ptr.end());
         HIP_TRY(hipMemcpyAsync(dptr, p32.data(), p32.size() * 4, hipMemcpyHostToDevice, s));
         if (g->nnz > 0)
@@ -653,6 +662,7 @@ int fsg_graph_bind(fsg_graph *g, void *dev_ws, size_t ws_bytes, void *stream)
         g->d_ptr = dptr;
         g->d_src = dsrc;
         g->d_dst = ddst;
+        g->d_wide = dwide;
         g->bound = true;
         g->src_host = nullptr;
         return FSG_OK;

@@ -41,6 +41,7 @@ constexpr int kWb1 = 0, kWb2 = kWb1 + kK1 * kHid, kWb3 = kWb2 + kK2 * kHid,
               kWbN = kWb3 + kK2 * kHid;
 constexpr int kPartBlocks = 512;  // fixed grid of reduction kernels (deterministic sums)
 constexpr int kDwRows = 1024;     // rows per block of the weight-gradient GEMM
+constexpr int kMaxMembers = 64;   // ensemble members one spread estimate may combine
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -90,58 +91,217 @@ __global__ void k_input(uint16_t *X1, const uint8_t *mask, const float *beta, co
 
 // Mean aggregation over in-neighbours (pull CSR), FP32 sums, BF16 result:
 // X[r][cout + f] = mean_{u in N-(v)} X[s*n + u][cin + f], f < d (d = 16 or 64).
+// One wave per row.  A lane covers 4 features (one 8-byte load per
+// neighbour), so d/4 lanes cover a neighbour row and the wave has 64/(d/4)
+// neighbour rows in flight per load; neighbour indices arrive 64 at a time
+// with one coalesced load and reach the lanes by shuffle.  The lane groups'
+// partial sums are added at the end (fixed order).
 __global__ void __launch_bounds__(256) k_mean(uint16_t *X, int ld, int d, int cin, int cout,
                                               const int32_t *ptr, const int32_t *src, int32_t n,
                                               int32_t n_sets)
 {
     const int lane = threadIdx.x & 63;
-    const int rows_per_wave = 64 / d;
-    const int f = lane % d;
+    const int lg = d >> 2, ng = 64 / lg;
+    const int gi = lane / lg, li = lane - gi * lg;
     const int64_t R = (int64_t)n * n_sets;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t r0 = wave * rows_per_wave; r0 < R; r0 += nwave * rows_per_wave) {
-        const int64_t r = r0 + lane / d;
-        if (r >= R) continue;
+    for (int64_t r = wave; r < R; r += nwave) {
         const int s = (int)(r / n);
         const int v = (int)(r - (int64_t)s * n);
-        const int e0 = ptr[v], e1 = ptr[v + 1];
-        const uint16_t *base = X + (int64_t)s * n * ld + cin + f;
-        float acc = 0.f;
-        int e = e0;
-        for (; e + 3 < e1; e += 4) {
-            const float a0 = from_bf16(base[(int64_t)src[e] * ld]);
-            const float a1 = from_bf16(base[(int64_t)src[e + 1] * ld]);
-            const float a2 = from_bf16(base[(int64_t)src[e + 2] * ld]);
-            const float a3 = from_bf16(base[(int64_t)src[e + 3] * ld]);
-            acc += (a0 + a1) + (a2 + a3);
+        const int e0 = ptr[v], e1 = ptr[v + 1], deg = e1 - e0;
+        if (deg > kWideRow) continue;  // k_mean_wide
+        const uint16_t *base = X + (int64_t)s * n * ld + cin + 4 * li;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        for (int c0 = 0; c0 < deg; c0 += 64) {
+            const int cnt = min(64, deg - c0);
+            const int my = lane < cnt ? src[e0 + c0 + lane] : 0;
+            for (int k0 = 0; k0 < cnt; k0 += 2 * ng) {
+                const int ka = k0 + gi, kb = k0 + ng + gi;
+                const int ua = __shfl(my, ka & 63, 64), ub = __shfl(my, kb & 63, 64);
+                uint2 qa = make_uint2(0u, 0u), qb = make_uint2(0u, 0u);
+                if (ka < cnt) qa = *reinterpret_cast<const uint2 *>(base + (int64_t)ua * ld);
+                if (kb < cnt) qb = *reinterpret_cast<const uint2 *>(base + (int64_t)ub * ld);
+                a0 += from_bf16((uint16_t)qa.x) + from_bf16((uint16_t)qb.x);
+                a1 += from_bf16((uint16_t)(qa.x >> 16)) + from_bf16((uint16_t)(qb.x >> 16));
+                a2 += from_bf16((uint16_t)qa.y) + from_bf16((uint16_t)qb.y);
+                a3 += from_bf16((uint16_t)(qa.y >> 16)) + from_bf16((uint16_t)(qb.y >> 16));
+            }
         }
-        for (; e < e1; ++e) acc += from_bf16(base[(int64_t)src[e] * ld]);
-        X[r * ld + cout + f] = to_bf16(e1 > e0 ? acc / (float)(e1 - e0) : 0.f);
+        for (int off = lg; off < 64; off <<= 1) {
+            a0 += __shfl_xor(a0, off, 64);
+            a1 += __shfl_xor(a1, off, 64);
+            a2 += __shfl_xor(a2, off, 64);
+            a3 += __shfl_xor(a3, off, 64);
+        }
+        if (gi == 0) {
+            const float inv = deg > 0 ? 1.f / (float)deg : 0.f;
+            uint2 o;
+            o.x = (uint32_t)to_bf16(a0 * inv) | ((uint32_t)to_bf16(a1 * inv) << 16);
+            o.y = (uint32_t)to_bf16(a2 * inv) | ((uint32_t)to_bf16(a3 * inv) << 16);
+            *reinterpret_cast<uint2 *>(X + r * ld + cout + 4 * li) = o;
+        }
     }
 }
 
 // Transpose of the mean aggregation (backward): for row (s, u),
 // dH[r][f] = dX[r][f] + sum_{v : u in N-(v)} dX[s*n + v][64 + f] / indeg(v),
-// pulled over the out-arcs of u (the in-CSR of the reversed graph).
+// pulled over the out-arcs of u (the in-CSR of the reversed graph).  One wave
+// per row: 16 lanes (one float4 each) per neighbour row, four rows in flight.
 __global__ void __launch_bounds__(256) k_mean_bwd(float *dH, const float *dX, const int32_t *ptr,
                                                   const int32_t *rptr, const int32_t *rdst,
                                                   int32_t n, int32_t n_sets)
 {
     const int lane = threadIdx.x & 63;
+    const int gi = lane >> 4, li = lane & 15;
     const int64_t R = (int64_t)n * n_sets;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t r = wave; r < R; r += nwave) {
         const int s = (int)(r / n);
         const int u = (int)(r - (int64_t)s * n);
-        const float *blk = dX + (int64_t)s * n * kK2 + kHid + lane;
-        float acc = dX[r * kK2 + lane];
-        for (int e = rptr[u]; e < rptr[u + 1]; ++e) {
-            const int v = rdst[e];
-            acc += blk[(int64_t)v * kK2] / (float)(ptr[v + 1] - ptr[v]);
+        const int e0 = rptr[u], deg = rptr[u + 1] - e0;
+        if (deg > kWideRow) continue;  // k_mean_bwd_wide
+        const float *blk = dX + (int64_t)s * n * kK2 + kHid + 4 * li;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int c0 = 0; c0 < deg; c0 += 64) {
+            const int cnt = min(64, deg - c0);
+            const int my = lane < cnt ? rdst[e0 + c0 + lane] : 0;
+            for (int k0 = 0; k0 < cnt; k0 += 4) {
+                const int k = k0 + gi;
+                const int v = __shfl(my, k & 63, 64);
+                if (k < cnt) {
+                    const float4 q = *reinterpret_cast<const float4 *>(blk + (int64_t)v * kK2);
+                    const float w = 1.f / (float)(ptr[v + 1] - ptr[v]);
+                    acc.x += q.x * w;
+                    acc.y += q.y * w;
+                    acc.z += q.z * w;
+                    acc.w += q.w * w;
+                }
+            }
         }
-        dH[r * kHid + lane] = acc;
+        for (int off = 16; off < 64; off <<= 1) {
+            acc.x += __shfl_xor(acc.x, off, 64);
+            acc.y += __shfl_xor(acc.y, off, 64);
+            acc.z += __shfl_xor(acc.z, off, 64);
+            acc.w += __shfl_xor(acc.w, off, 64);
+        }
+        if (gi == 0) {
+            const float4 self = *reinterpret_cast<const float4 *>(dX + r * kK2 + 4 * li);
+            *reinterpret_cast<float4 *>(dH + r * kHid + 4 * li) =
+                make_float4(self.x + acc.x, self.y + acc.y, self.z + acc.z, self.w + acc.w);
+        }
+    }
+}
+
+// The same aggregations for rows with more than kWideRow arcs: one block of
+// kWideThreads per (seed set, wide row); wave w takes the w-th contiguous
+// slice of the row's arcs, and the waves' sums are added in wave order.
+constexpr int kWideThreads = 1024;
+constexpr int kWideWaves = kWideThreads / 64;
+
+__global__ void __launch_bounds__(kWideThreads) k_mean_wide(uint16_t *X, int ld, int d, int cin,
+                                                            int cout, const int32_t *ptr,
+                                                            const int32_t *src, int32_t n,
+                                                            const int32_t *wide, int32_t n_wide)
+{
+    __shared__ float s_part[kWideWaves][kHid];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lg = d >> 2, ng = 64 / lg;
+    const int gi = lane / lg, li = lane - gi * lg;
+    const int s = blockIdx.x / n_wide;
+    const int v = wide[blockIdx.x - s * n_wide];
+    const int e0 = ptr[v], deg = ptr[v + 1] - e0;
+    const int per = (deg + kWideWaves - 1) / kWideWaves;
+    const int lo = min(deg, wv * per), hi = min(deg, lo + per);
+    const uint16_t *base = X + (int64_t)s * n * ld + cin + 4 * li;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    for (int c0 = lo; c0 < hi; c0 += 64) {
+        const int cnt = min(64, hi - c0);
+        const int my = lane < cnt ? src[e0 + c0 + lane] : 0;
+        for (int k0 = 0; k0 < cnt; k0 += 2 * ng) {
+            const int ka = k0 + gi, kb = k0 + ng + gi;
+            const int ua = __shfl(my, ka & 63, 64), ub = __shfl(my, kb & 63, 64);
+            uint2 qa = make_uint2(0u, 0u), qb = make_uint2(0u, 0u);
+            if (ka < cnt) qa = *reinterpret_cast<const uint2 *>(base + (int64_t)ua * ld);
+            if (kb < cnt) qb = *reinterpret_cast<const uint2 *>(base + (int64_t)ub * ld);
+            a0 += from_bf16((uint16_t)qa.x) + from_bf16((uint16_t)qb.x);
+            a1 += from_bf16((uint16_t)(qa.x >> 16)) + from_bf16((uint16_t)(qb.x >> 16));
+            a2 += from_bf16((uint16_t)qa.y) + from_bf16((uint16_t)qb.y);
+            a3 += from_bf16((uint16_t)(qa.y >> 16)) + from_bf16((uint16_t)(qb.y >> 16));
+        }
+    }
+    for (int off = lg; off < 64; off <<= 1) {
+        a0 += __shfl_xor(a0, off, 64);
+        a1 += __shfl_xor(a1, off, 64);
+        a2 += __shfl_xor(a2, off, 64);
+        a3 += __shfl_xor(a3, off, 64);
+    }
+    if (gi == 0) {
+        s_part[wv][4 * li] = a0;
+        s_part[wv][4 * li + 1] = a1;
+        s_part[wv][4 * li + 2] = a2;
+        s_part[wv][4 * li + 3] = a3;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < d) {
+        float acc = 0.f;
+        for (int w = 0; w < kWideWaves; ++w) acc += s_part[w][threadIdx.x];
+        X[((int64_t)s * n + v) * ld + cout + threadIdx.x] = to_bf16(acc / (float)deg);
+    }
+}
+
+__global__ void __launch_bounds__(kWideThreads) k_mean_bwd_wide(float *dH, const float *dX,
+                                                                const int32_t *ptr,
+                                                                const int32_t *rptr,
+                                                                const int32_t *rdst, int32_t n,
+                                                                const int32_t *wide,
+                                                                int32_t n_wide)
+{
+    __shared__ float s_part[kWideWaves][kHid];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gi = lane >> 4, li = lane & 15;
+    const int s = blockIdx.x / n_wide;
+    const int u = wide[blockIdx.x - s * n_wide];
+    const int e0 = rptr[u], deg = rptr[u + 1] - e0;
+    const int per = (deg + kWideWaves - 1) / kWideWaves;
+    const int lo = min(deg, wv * per), hi = min(deg, lo + per);
+    const float *blk = dX + (int64_t)s * n * kK2 + kHid + 4 * li;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int c0 = lo; c0 < hi; c0 += 64) {
+        const int cnt = min(64, hi - c0);
+        const int my = lane < cnt ? rdst[e0 + c0 + lane] : 0;
+        for (int k0 = 0; k0 < cnt; k0 += 4) {
+            const int k = k0 + gi;
+            const int v = __shfl(my, k & 63, 64);
+            if (k < cnt) {
+                const float4 q = *reinterpret_cast<const float4 *>(blk + (int64_t)v * kK2);
+                const float w = 1.f / (float)(ptr[v + 1] - ptr[v]);
+                acc.x += q.x * w;
+                acc.y += q.y * w;
+                acc.z += q.z * w;
+                acc.w += q.w * w;
+            }
+        }
+    }
+    for (int off = 16; off < 64; off <<= 1) {
+        acc.x += __shfl_xor(acc.x, off, 64);
+        acc.y += __shfl_xor(acc.y, off, 64);
+        acc.z += __shfl_xor(acc.z, off, 64);
+        acc.w += __shfl_xor(acc.w, off, 64);
+    }
+    if (gi == 0) {
+        s_part[wv][4 * li] = acc.x;
+        s_part[wv][4 * li + 1] = acc.y;
+        s_part[wv][4 * li + 2] = acc.z;
+        s_part[wv][4 * li + 3] = acc.w;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kHid) {
+        const int64_t r = (int64_t)s * n + u;
+        float a = dX[r * kK2 + threadIdx.x];
+        for (int w = 0; w < kWideWaves; ++w) a += s_part[w][threadIdx.x];
+        dH[r * kHid + threadIdx.x] = a;
     }
 }
 
@@ -399,16 +559,19 @@ __global__ void k_params_to_bf16(const float *p, uint16_t *wb)
     }
 }
 
-// Sum of probabilities of each seed set (the predicted spread), fixed order.
-__global__ void k_set_sums(const float *prob, int32_t n, int32_t n_sets, float *out)
+// Sum of probabilities of each seed set (the predicted spread), fixed order;
+// one block of kSumThreads per set.
+constexpr int kSumThreads = 1024;
+__global__ void __launch_bounds__(kSumThreads) k_set_sums(const float *prob, int32_t n,
+                                                          int32_t n_sets, float *out)
 {
-    __shared__ float s[256];
+    __shared__ float s[kSumThreads];
     for (int set = blockIdx.x; set < n_sets; set += gridDim.x) {
         float acc = 0.f;
         for (int v = threadIdx.x; v < n; v += blockDim.x) acc += prob[(int64_t)set * n + v];
         s[threadIdx.x] = acc;
         __syncthreads();
-        for (int off = 128; off > 0; off >>= 1) {
+        for (int off = kSumThreads / 2; off > 0; off >>= 1) {
             if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
             __syncthreads();
         }
@@ -502,7 +665,7 @@ GnnWs gnn_layout(int64_t n, int32_t n_sets)
     w.pbo = take((size_t)kPartBlocks * 4);
     w.ploss = take((size_t)kPartBlocks * 4);
     w.beta = take((size_t)n_sets * 4);
-    w.sums = take((size_t)n_sets * 4 + 4);
+    w.sums = take((size_t)std::max<int32_t>(n_sets, kMaxMembers) * 4);
     w.mask = take((size_t)n);
     w.seeds = take((size_t)n * 4);
     w.total = off;
@@ -518,14 +681,31 @@ uint64_t splitmix(uint64_t &x)
 }
 
 struct GraphView {
-    int64_t n = 0, nnz = 0, dmax = 0;
-    const int32_t *ptr = nullptr, *src = nullptr;
+    int64_t n = 0, nnz = 0, dmax = 0, n_wide = 0;
+    const int32_t *ptr = nullptr, *src = nullptr, *wide = nullptr;
 };
 
 int view_of(const fsg_graph *g, GraphView *v, const char *what)
 {
-    if (!graph_view(g, &v->n, &v->nnz, &v->dmax, &v->ptr, &v->src))
+    if (!graph_view(g, &v->n, &v->nnz, &v->dmax, &v->ptr, &v->src, &v->wide, &v->n_wide))
         return set_error(FSG_EINVAL, (std::string(what) + " is NULL or not bound").c_str());
+    return FSG_OK;
+}
+
+// Mean aggregation of one layer: light rows one wave each, wide rows one
+// block each.
+int mean_agg(uint16_t *X, int ld, int d, const GraphView &G, int32_t n_sets, hipStream_t st)
+{
+    const int64_t R = G.n * n_sets;
+    hipLaunchKernelGGL(k_mean, dim3(grid_of(R * 64, 256)), dim3(256), 0, st, X, ld, d, 0, d,
+                       G.ptr, G.src, (int32_t)G.n, n_sets);
+    GNN_TRY(hipGetLastError());
+    if (G.n_wide > 0) {
+        hipLaunchKernelGGL(k_mean_wide, dim3((unsigned)(G.n_wide * n_sets)), dim3(kWideThreads), 0,
+                           st, X, ld, d, 0, d, G.ptr, G.src, (int32_t)G.n, G.wide,
+                           (int32_t)G.n_wide);
+        GNN_TRY(hipGetLastError());
+    }
     return FSG_OK;
 }
 
@@ -541,23 +721,19 @@ int forward_all(const fsg_gnn *gn, const GraphView &G, int32_t n_sets, const uin
     hipLaunchKernelGGL(k_input, dim3(grid_of(R, 256)), dim3(256), 0, st, X1, mask,
                        (const float *)(base + w.beta), G.ptr, (int32_t)G.n, n_sets);
     GNN_TRY(hipGetLastError());
-    const unsigned gm = grid_of(R * 64, 256);
-    hipLaunchKernelGGL(k_mean, dim3(grid_of(R * kF0, 256)), dim3(256), 0, st, X1, kK1, kF0, 0, kF0,
-                       G.ptr, G.src, (int32_t)G.n, n_sets);
-    GNN_TRY(hipGetLastError());
+    int rc = mean_agg(X1, kK1, kF0, G, n_sets, st);
+    if (rc) return rc;
     const unsigned gg = (unsigned)((R + 63) / 64);
     hipLaunchKernelGGL(k_gemm_fwd, dim3(gg), dim3(256), 0, st, X1, kK1, kK1, Wb + kWb1, P + kB1, X2,
                        kK2, R);
     GNN_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_mean, dim3(gm), dim3(256), 0, st, X2, kK2, kHid, 0, kHid, G.ptr, G.src,
-                       (int32_t)G.n, n_sets);
-    GNN_TRY(hipGetLastError());
+    rc = mean_agg(X2, kK2, kHid, G, n_sets, st);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_gemm_fwd, dim3(gg), dim3(256), 0, st, X2, kK2, kK2, Wb + kWb2, P + kB2, X3,
                        kK2, R);
     GNN_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_mean, dim3(gm), dim3(256), 0, st, X3, kK2, kHid, 0, kHid, G.ptr, G.src,
-                       (int32_t)G.n, n_sets);
-    GNN_TRY(hipGetLastError());
+    rc = mean_agg(X3, kK2, kHid, G, n_sets, st);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_gemm_fwd, dim3(gg), dim3(256), 0, st, X3, kK2, kK2, Wb + kWb3, P + kB3, H3,
                        kHid, R);
     GNN_TRY(hipGetLastError());
@@ -597,6 +773,12 @@ int backward_layer(const fsg_gnn *gn, const GraphView &G, const GraphView &Gr, i
         hipLaunchKernelGGL(k_mean_bwd, dim3(grid_of(R * 64, 256)), dim3(256), 0, st, dHin,
                            (const float *)dX, G.ptr, Gr.ptr, Gr.src, (int32_t)G.n, n_sets);
         GNN_TRY(hipGetLastError());
+        if (Gr.n_wide > 0) {
+            hipLaunchKernelGGL(k_mean_bwd_wide, dim3((unsigned)(Gr.n_wide * n_sets)),
+                               dim3(kWideThreads), 0, st, dHin, (const float *)dX, G.ptr, Gr.ptr,
+                               Gr.src, (int32_t)G.n, Gr.wide, (int32_t)Gr.n_wide);
+            GNN_TRY(hipGetLastError());
+        }
     }
     return FSG_OK;
 }
@@ -701,7 +883,12 @@ int fsg_gnn_workspace_size(const fsg_gnn *g, const fsg_graph *graph, int32_t n_s
     return FSG_OK;
 }
 
-int fsg_gnn_forward(fsg_gnn *g, const fsg_graph *graph, int32_t n_sets, const uint8_t *dev_mask,
+}  // extern "C"
+
+namespace fsg {
+namespace gnn {
+// Forward pass into dev_prob, enqueued on the stream without waiting.
+int forward_enqueue(fsg_gnn *g, const fsg_graph *graph, int32_t n_sets, const uint8_t *dev_mask,
                     const float *beta, float *dev_prob, void *ws, size_t ws_bytes, void *stream)
 {
     if (!g || !g->bound) return set_error(FSG_EINVAL, "gnn is NULL or not bound");
@@ -724,7 +911,20 @@ int fsg_gnn_forward(fsg_gnn *g, const fsg_graph *graph, int32_t n_sets, const ui
                        (const float *)nullptr, dev_prob, (float *)nullptr, (float *)nullptr,
                        (float *)nullptr, (float *)nullptr, R);
     GNN_TRY(hipGetLastError());
-    GNN_TRY(hipStreamSynchronize(st));
+    return FSG_OK;
+}
+}  // namespace gnn
+}  // namespace fsg
+
+extern "C" {
+
+int fsg_gnn_forward(fsg_gnn *g, const fsg_graph *graph, int32_t n_sets, const uint8_t *dev_mask,
+                    const float *beta, float *dev_prob, void *ws, size_t ws_bytes, void *stream)
+{
+    const int rc = fsg::gnn::forward_enqueue(g, graph, n_sets, dev_mask, beta, dev_prob, ws,
+                                             ws_bytes, stream);
+    if (rc) return rc;
+    GNN_TRY(hipStreamSynchronize((hipStream_t)stream));
     return FSG_OK;
 }
 
@@ -836,8 +1036,9 @@ int fsg_estimate_spread(fsg_gnn *const *members, int32_t n_members, const fsg_gr
                         uint32_t *dev_counts, double *spread, double *uncertainty,
                         int32_t *used_fallback, void *stream)
 {
-    if (!members || n_members < 1 || !spread || !uncertainty || !used_fallback)
-        return set_error(FSG_EINVAL, "bad arguments");
+    if (!members || n_members < 1 || n_members > kMaxMembers || !spread || !uncertainty ||
+        !used_fallback)
+        return set_error(FSG_EINVAL, "bad arguments (1 <= n_members <= 64)");
     GraphView G;
     int rc = view_of(graph, &G, "graph");
     if (rc) return rc;
@@ -859,20 +1060,21 @@ int fsg_estimate_spread(fsg_gnn *const *members, int32_t n_members, const fsg_gr
                            (const int32_t *)dseeds, n_seeds);
         GNN_TRY(hipGetLastError());
     }
-    std::vector<double> sp((size_t)n_members);
+    // every member's spread into the device sums, then one copy
+    float *sums = (float *)(base + w.sums);
     const float fb = (float)beta;
     for (int32_t m = 0; m < n_members; ++m) {
-        rc = fsg_gnn_forward(members[m], graph, 1, mask, &fb, (float *)(base + w.prob), ws,
+        rc = forward_enqueue(members[m], graph, 1, mask, &fb, (float *)(base + w.prob), ws,
                              ws_bytes, stream);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_set_sums, dim3(1), dim3(256), 0, st, (const float *)(base + w.prob),
-                           (int32_t)G.n, 1, (float *)(base + w.sums));
+        hipLaunchKernelGGL(k_set_sums, dim3(1), dim3(kSumThreads), 0, st,
+                           (const float *)(base + w.prob), (int32_t)G.n, 1, sums + m);
         GNN_TRY(hipGetLastError());
-        float s = 0.f;
-        GNN_TRY(hipMemcpyAsync(&s, base + w.sums, 4, hipMemcpyDeviceToHost, st));
-        GNN_TRY(hipStreamSynchronize(st));
-        sp[(size_t)m] = s;
     }
+    float hs[kMaxMembers];
+    GNN_TRY(hipMemcpyAsync(hs, sums, (size_t)n_members * 4, hipMemcpyDeviceToHost, st));
+    GNN_TRY(hipStreamSynchronize(st));
+    std::vector<double> sp(hs, hs + n_members);
     double mean = 0, var = 0;
     for (double x : sp) mean += x;
     mean /= n_members;

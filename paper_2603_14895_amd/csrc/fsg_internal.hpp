@@ -13,7 +13,11 @@ namespace fsg {
 int set_error(int code, const char *msg);  // records the message, returns code
 // Device view of a graph; false if it is not bound.
 bool graph_view(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg,
-                const int32_t **ptr, const int32_t **src);
+                const int32_t **ptr, const int32_t **src, const int32_t **wide, int64_t *n_wide);
+
+// Rows with more in-arcs than this are aggregated by a whole block (their
+// list is built when a graph is bound).
+constexpr int kWideRow = 256;
 
 enum Kind { kKindIC = 0, kKindEpidemic = 1, kKindLT = 2 };
 

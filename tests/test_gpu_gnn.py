@@ -12,13 +12,29 @@ from tests.gpu_util import log
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def setup():
+def _hub_graph():
+    """Chung-Lu background plus hub nodes with 300-1500 in- and out-arcs, so
+    the block-per-row aggregation paths (rows above 256 arcs) run too."""
+    rng = np.random.default_rng(99)
+    base = W.chung_lu(1500, 6.0, 2.5, 4343)
+    ptr, src = base.numpy()
+    dst = np.repeat(np.arange(base.n), np.diff(ptr))
+    edges = set(zip(src.tolist(), dst.tolist()))
+    for hub, k in ((3, 300), (77, 700), (1234, 1499)):
+        for u in rng.choice(base.n, size=k, replace=False).tolist():
+            if u != hub:
+                edges.add((u, hub))
+                edges.add((hub, u))
+    return W.from_edges(base.n, sorted(edges), "hubs")
+
+
+@pytest.fixture(scope="module", params=["small", "hubs"])
+def setup(request):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2603_14895_amd import fsg
-    gr = W.chung_lu(400, 8.0, 2.5, 4242)
+    gr = W.chung_lu(400, 8.0, 2.5, 4242) if request.param == "small" else _hub_graph()
     rev = W.reverse_graph(gr)
     g = fsg.DeviceGraph(*gr.numpy())
     gr_ = fsg.DeviceGraph(*rev.numpy())
