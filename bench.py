@@ -352,7 +352,7 @@ def bench_surrogate(args):
     n, gamma, K, B_lab, B_ref = 100_000, 0.1, 200, 1024, 4096
     rng = np.random.default_rng(Wl.BASE_SEED + 5)
     t0 = time.perf_counter()
-    data, lab_ms = [], 0.0
+    data, lab_ms, train_sets = [], 0.0, []
     for gi in range(4):
         gr = Wl.chung_lu(n, 20.0, 2.5, Wl.BASE_SEED + 50 + gi, device="cuda")
         ptr, src = gr.numpy()
@@ -363,31 +363,48 @@ def bench_surrogate(args):
         y, sp, ms = S.mc_frequencies(g, sets, betas, gamma, K, B_lab, 1_000_000 * (gi + 1))
         lab_ms += ms
         data.append((g, rv, S.masks_of(sets, n), list(betas), y))
+        train_sets.append(sets)
         log(f"[bench] labels graph {gi}: 500 seed sets x {B_lab} replicates in {ms:.0f} ms device, "
             f"mean spread {sp.mean() / n:.3f} n")
     ens = S.Ensemble(4, seed=Wl.BASE_SEED % 1000)
     t1 = time.perf_counter()
     ens.train(data, epochs=args.epochs, sets_per_step=8, lr=3e-3, progress_every=1)
     train_s = time.perf_counter() - t1
-    # held-out graphs: calibration on the first 50 queries of each, test on the rest
-    cal_m, cal_u, cal_r, tests = [], [], [], []
+    # spread calibration fitted on the training queries' simulator labels
+    tr_pred, tr_lab, tr_beta, tr_k = [], [], [], []
+    for (g, rv, masks, betas, y), sets in zip(data, train_sets):
+        tr_pred.append(ens.predict_spreads(g, masks, np.array(betas)).mean(axis=0))
+        tr_lab.append(y.sum(dim=1).double().cpu().numpy())
+        tr_beta += list(betas)
+        tr_k += [len(x) for x in sets]
+    coef = S.fit_calibration(np.concatenate(tr_pred), np.concatenate(tr_lab), tr_beta, tr_k)
+    # held-out graphs: the gate is calibrated on the first 50 queries of each,
+    # the rest are the test queries
+    cal_s, cal_u, cal_r, cal_k, tests = [], [], [], [], []
     ref_ms = 0.0
     for gi in range(2):
         gr = Wl.chung_lu(n, 20.0, 2.5, Wl.BASE_SEED + 90 + gi, device="cuda")
         g = fsg.DeviceGraph(*gr.numpy())
         qs = S.seed_sets(n, 100, rng)
         qb = rng.uniform(0.01, 0.05, size=len(qs))
+        qk = np.array([len(np.unique(x)) for x in qs])
         _, ref, ms = S.mc_frequencies(g, qs, qb, gamma, K, B_ref, 7_000_000 * (gi + 1))
         ref_ms += ms
         mean, unc = S.uncertainty(ens.predict_spreads(g, S.masks_of(qs, n), qb))
-        cal_m += list(mean[:50]); cal_u += list(unc[:50]); cal_r += list(ref[:50])
+        cal = S.apply_calibration(mean, qb, qk, coef)
+        cal_s += list(cal[:50]); cal_u += list(unc[:50]); cal_r += list(ref[:50])
+        cal_k += list(qk[:50])
         tests.append((g, qs[50:], qb[50:], ref[50:]))
         log(f"[bench] held-out graph {gi}: reference 100 x {B_ref} in {ms:.0f} ms device; "
-            f"surrogate median error {np.median(np.abs(mean - ref) / ref):.4f}")
-    tau = S.calibrate_tau(np.array(cal_m), np.array(cal_u), np.array(cal_r), 0.02)
-    acc_err, fb_err, t_sur, n_fb = [], [], [], 0
+            f"median error raw {np.median(np.abs(mean - ref) / ref):.4f}, "
+            f"calibrated {np.median(np.abs(cal - ref) / ref):.4f}")
+    gate = S.calibrate_gate(cal_s, cal_u, cal_r, cal_k, 0.02)
+    gate["calib"] = list(coef)
+    tau = gate["tau"]
+    acc_err, fb_err, t_sur, n_fb, accepted = [], [], [], 0, []
     for g, qs, qb, ref in tests:
-        est = fsg.SpreadEstimator(ens.members, g, gamma=gamma, max_steps=K, B_fallback=1024, tau=tau)
+        est = fsg.SpreadEstimator(ens.members, g, gamma=gamma, max_steps=K, B_fallback=1024,
+                                  gate=gate)
         for i in range(len(qs)):
             torch.cuda.synchronize()
             ta = time.perf_counter()
@@ -397,25 +414,28 @@ def bench_surrogate(args):
             n_fb += int(fb)
             if not fb:
                 t_sur.append(dt)
-    # plain Monte Carlo on the same GPU: 4096 replicates (the reference) and
-    # the smallest B matching the surrogate's accuracy
-    g, qs, qb, ref = tests[0]
-    def mc_cost(B, count=10):
+                accepted.append((g, qs[i], qb[i], ref[i]))
+    # plain Monte Carlo on the same GPU and the same accepted queries: 4096
+    # replicates (the reference's cost) and the smallest B whose mean error
+    # matches the surrogate's
+    def mc_cost(B, count=20):
         errs, times = [], []
-        for i in range(count):
+        for i, (g, q, b, r) in enumerate(accepted[:count]):
             torch.cuda.synchronize()
             ta = time.perf_counter()
-            _, cnt, _, _ = fsg.simulate(g, "sir", qs[i], B, 4242 + i, beta=qb[i], gamma=gamma,
+            _, cnt, _, _ = fsg.simulate(g, "sir", q, B, 4242 + i, beta=b, gamma=gamma,
                                         max_steps=K, want_states=False)
             s = float(cnt.sum().item()) / B
             times.append(time.perf_counter() - ta)
-            errs.append(abs(s - ref[i]) / ref[i])
+            errs.append(abs(s - r) / r)
         return float(np.mean(errs)), float(np.median(times))
     e_sur = float(np.mean(acc_err)) if acc_err else float("nan")
     t_s = float(np.median(t_sur)) if t_sur else float("nan")
-    e4096, t4096 = mc_cost(B_ref)
+    e4096, t4096 = mc_cost(B_ref) if accepted else (float("nan"), float("nan"))
     matched = None
-    for B in (16, 32, 64, 128, 256, 512, 1024, 2048):
+    for B in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096):
+        if not accepted:
+            break
         e, t = mc_cost(B)
         if e <= e_sur:
             matched = (B, e, t)
@@ -428,7 +448,8 @@ def bench_surrogate(args):
         "dtype": "bf16 weights/activations, fp32 accumulate (MFMA)", "data": "synthetic",
         "config": {"workload": "c5_surrogate_chunglu1e5", "n": n, "train_sets": 2000,
                    "label_replicates": B_lab, "reference_replicates": B_ref, "epochs": args.epochs,
-                   "ensemble": 4, "tau": tau, "parallelism": "single GPU"},
+                   "ensemble": 4, "tau": tau, "min_seeds": gate["min_seeds"],
+                   "calibration": [round(float(c), 6) for c in coef], "parallelism": "single GPU"},
         "surrogate": {"accepted": len(acc_err), "fallback": n_fb, "acceptance": len(acc_err) / 100.0,
                       "accepted_rel_err_mean": e_sur,
                       "accepted_rel_err_max": float(np.max(acc_err)) if acc_err else None,

@@ -296,19 +296,35 @@ int fsg_gnn_train_step(fsg_gnn *g, const fsg_graph *graph, const fsg_graph *reve
 int fsg_gnn_get_params(const fsg_gnn *g, float *out, int64_t n, void *stream);
 int fsg_gnn_set_params(fsg_gnn *g, const float *in, int64_t n, void *stream);
 int fsg_gnn_get_grads(const fsg_gnn *g, float *out, int64_t n, void *stream);
+/* Acceptance gate and spread calibration of the surrogate (fitted by the
+ * caller on simulator labels of training queries and on a held-out split). */
+#define FSG_CALIB_TERMS 9
+typedef struct {
+    double tau;         /* fall back when the members' relative std exceeds tau */
+    int64_t min_seeds;  /* fall back for seed sets with fewer distinct nodes */
+    int32_t calibrated; /* 1: the ensemble mean is multiplied by exp(sum_i calib[i] f_i) */
+    int32_t reserved;   /* 0 */
+    /* f = [1, x, x^2, x^3, 1/k, x/k, 1/k^2, ln k, x ln k] with x = 20 beta and
+     * k the number of distinct seeds */
+    double calib[FSG_CALIB_TERMS];
+} fsg_spread_gate;
+
 /* Spread estimate of one SIR query with Monte Carlo fallback: the ensemble
- * members predict sum_v p_v; uncertainty = (sample std / mean) over members.
- * If it exceeds tau, the plain simulator runs B_fallback replicates
- * (max_steps, rng_key) instead and its mean count is returned with
- * *used_fallback = 1.  ws: fsg_gnn_workspace_size for n_sets = 1; sim_ws:
- * fsg_sim_workspace_size for SIR with B_fallback; dev_counts: device uint32
- * [n].  Synchronous. */
+ * members predict sum_v p_v; uncertainty = (sample std / mean) over
+ * members.  The estimate is the members' mean, calibrated if the gate says
+ * so.  If uncertainty > gate->tau or the seed set has fewer than
+ * gate->min_seeds distinct nodes, the plain simulator runs B_fallback
+ * replicates (max_steps, rng_key) instead and its mean count is returned
+ * with *used_fallback = 1.  An empty seed set gives spread 0.  ws:
+ * fsg_gnn_workspace_size for n_sets = 1; sim_ws: fsg_sim_workspace_size for
+ * SIR with B_fallback; dev_counts: device uint32 [n]; 1 <= n_members <= 64.
+ * Synchronous. */
 int fsg_estimate_spread(fsg_gnn *const *members, int32_t n_members, const fsg_graph *graph,
                         const int32_t *seeds, int64_t n_seeds, double beta, double gamma,
-                        int64_t max_steps, double tau, int64_t B_fallback, uint64_t rng_key,
-                        void *ws, size_t ws_bytes, void *sim_ws, size_t sim_ws_bytes,
-                        uint32_t *dev_counts, double *spread, double *uncertainty,
-                        int32_t *used_fallback, void *stream);
+                        int64_t max_steps, const fsg_spread_gate *gate, int64_t B_fallback,
+                        uint64_t rng_key, void *ws, size_t ws_bytes, void *sim_ws,
+                        size_t sim_ws_bytes, uint32_t *dev_counts, double *spread,
+                        double *uncertainty, int32_t *used_fallback, void *stream);
 
 /* Row-tile planner (host only; Sec. 3.2, Definition "Target-Node-Based
  * Partitioning via Longest Processing Time Heuristic", kept in CSR order so

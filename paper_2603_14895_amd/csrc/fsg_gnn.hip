@@ -1031,20 +1031,29 @@ int fsg_gnn_get_grads(const fsg_gnn *g, float *out, int64_t n, void *stream)
 
 int fsg_estimate_spread(fsg_gnn *const *members, int32_t n_members, const fsg_graph *graph,
                         const int32_t *seeds, int64_t n_seeds, double beta, double gamma,
-                        int64_t max_steps, double tau, int64_t B_fallback, uint64_t rng_key,
-                        void *ws, size_t ws_bytes, void *sim_ws, size_t sim_ws_bytes,
-                        uint32_t *dev_counts, double *spread, double *uncertainty,
-                        int32_t *used_fallback, void *stream)
+                        int64_t max_steps, const fsg_spread_gate *gate, int64_t B_fallback,
+                        uint64_t rng_key, void *ws, size_t ws_bytes, void *sim_ws,
+                        size_t sim_ws_bytes, uint32_t *dev_counts, double *spread,
+                        double *uncertainty, int32_t *used_fallback, void *stream)
 {
-    if (!members || n_members < 1 || n_members > kMaxMembers || !spread || !uncertainty ||
-        !used_fallback)
-        return set_error(FSG_EINVAL, "bad arguments (1 <= n_members <= 64)");
+    if (!members || n_members < 1 || n_members > kMaxMembers || !gate || !spread ||
+        !uncertainty || !used_fallback)
+        return set_error(FSG_EINVAL, "bad arguments (1 <= n_members <= 64, gate not NULL)");
     GraphView G;
     int rc = view_of(graph, &G, "graph");
     if (rc) return rc;
     if (n_seeds < 0 || (n_seeds > 0 && !seeds)) return set_error(FSG_EINVAL, "bad seed array");
     for (int64_t i = 0; i < n_seeds; ++i)
         if (seeds[i] < 0 || seeds[i] >= G.n) return set_error(FSG_EINVAL, "seed out of range");
+    std::vector<int32_t> distinct(seeds, seeds + n_seeds);
+    std::sort(distinct.begin(), distinct.end());
+    const int64_t k = std::unique(distinct.begin(), distinct.end()) - distinct.begin();
+    *used_fallback = 0;
+    *uncertainty = 0.0;
+    if (k == 0) {  // nothing is ever infected
+        *spread = 0.0;
+        return FSG_OK;
+    }
     const GnnWs w = gnn_layout(G.n, 1);
     rc = check_ws(ws, ws_bytes, w.total);
     if (rc) return rc;
@@ -1082,9 +1091,16 @@ int fsg_estimate_spread(fsg_gnn *const *members, int32_t n_members, const fsg_gr
     var = n_members > 1 ? var / (n_members - 1) : 0.0;
     const double unc = mean > 0 ? sqrt(var) / mean : 1e30;
     *uncertainty = unc;
-    *used_fallback = 0;
     *spread = mean;
-    if (unc > tau) {
+    if (gate->calibrated) {
+        const double x = 20.0 * beta, kd = (double)k, lk = log(kd);
+        const double f[FSG_CALIB_TERMS] = {1.0, x, x * x, x * x * x, 1.0 / kd, x / kd,
+                                           1.0 / (kd * kd), lk, x * lk};
+        double z = 0.0;
+        for (int i = 0; i < FSG_CALIB_TERMS; ++i) z += gate->calib[i] * f[i];
+        *spread = mean * exp(z);
+    }
+    if (unc > gate->tau || k < gate->min_seeds) {
         if (B_fallback < 1 || !dev_counts) return set_error(FSG_EINVAL, "fallback needs B_fallback and counts");
         fsg_params prm;
         memset(&prm, 0, sizeof(prm));

@@ -52,6 +52,29 @@ class fsg_schedule(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
+CALIB_TERMS = 9
+
+
+class fsg_spread_gate(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("min_seeds", ctypes.c_int64),
+                ("calibrated", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("calib", ctypes.c_double * CALIB_TERMS)]
+
+
+def make_gate(tau: float = float("inf"), min_seeds: int = 0, calib=None) -> fsg_spread_gate:
+    g = fsg_spread_gate()
+    g.tau = float(tau)
+    g.min_seeds = int(min_seeds)
+    g.calibrated = 0 if calib is None else 1
+    if calib is not None:
+        c = [float(x) for x in calib]
+        if len(c) != CALIB_TERMS:
+            raise ValueError(f"calibration needs {CALIB_TERMS} coefficients")
+        for i, x in enumerate(c):
+            g.calib[i] = x
+    return g
+
+
 class fsg_job(ctypes.Structure):
     _fields_ = [("g", ctypes.c_void_p), ("prm", fsg_params), ("seeds", ctypes.c_void_p),
                 ("n_seeds", ctypes.c_int64), ("B", ctypes.c_int64),
@@ -101,11 +124,11 @@ _SIGS = {
     "fsg_gnn_set_params": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "fsg_gnn_get_grads": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "fsg_estimate_spread": (ctypes.c_int, [_VP, _I32, _VP, _VP, _I64, ctypes.c_double,
-                                           ctypes.c_double, _I64, ctypes.c_double, _I64, _U64,
-                                           _VP, _SZ, _VP, _SZ, _VP,
+                                           ctypes.c_double, _I64, ctypes.POINTER(fsg_spread_gate),
+                                           _I64, _U64, _VP, _SZ, _VP, _SZ, _VP,
                                            ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double),
-                                           ctypes.POINTER(_I32), _VP]),
+                                           ctypes.POINTER(ctypes.c_int32), _VP]),
     "fsg_autotune_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _I64, _I32,
                                                    ctypes.POINTER(_SZ)]),
     "fsg_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _U64, _I32,
@@ -510,15 +533,20 @@ class GNN:
 
 
 class SpreadEstimator:
-    """fsg_estimate_spread: ensemble prediction of the SIR spread with Monte
-    Carlo fallback when the members disagree by more than tau."""
+    """fsg_estimate_spread: ensemble prediction of the SIR spread, calibrated
+    and gated (``gate``: dict with tau, min_seeds, calib), with Monte Carlo
+    fallback for queries the gate rejects."""
 
     def __init__(self, members, graph: DeviceGraph, gamma: float, max_steps: int,
-                 B_fallback: int, tau: float):
+                 B_fallback: int, gate=None, tau=None):
         import torch
         self.members = members
         self.graph = graph
-        self.gamma, self.max_steps, self.B, self.tau = gamma, int(max_steps), int(B_fallback), tau
+        self.gamma, self.max_steps, self.B = gamma, int(max_steps), int(B_fallback)
+        gate = dict(gate or {})
+        if tau is not None:
+            gate["tau"] = tau
+        self.gate = gate
         self._arr = (ctypes.c_void_p * len(members))(*[m.handle for m in members])
         nb = ctypes.c_size_t()
         _check(lib().fsg_gnn_workspace_size(members[0].handle, graph.handle, 1, ctypes.byref(nb)))
@@ -532,11 +560,15 @@ class SpreadEstimator:
     def estimate(self, seeds, beta: float, rng_key: int, tau=None):
         """Returns (spread, uncertainty, used_fallback)."""
         seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        gd = dict(self.gate)
+        if tau is not None:
+            gd["tau"] = tau
+        gate = make_gate(**gd)
         sp, un, fb = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
         _check(lib().fsg_estimate_spread(self._arr, len(self.members), self.graph.handle,
                                          seeds.ctypes.data if seeds.size else None, seeds.size,
                                          float(beta), float(self.gamma), self.max_steps,
-                                         float(self.tau if tau is None else tau), self.B,
+                                         ctypes.byref(gate), self.B,
                                          int(rng_key) & (2**64 - 1), self.ws_addr, self.ws_bytes,
                                          self.sim_addr, self.sim_bytes, self.counts.data_ptr(),
                                          ctypes.byref(sp), ctypes.byref(un), ctypes.byref(fb),

@@ -119,6 +119,58 @@ def uncertainty(pred: np.ndarray):
     return mean, std / np.maximum(mean, 1e-12)
 
 
+def calib_features(beta, k):
+    """Terms of the spread calibration, per query: [1, x, x^2, x^3, 1/k, x/k,
+    1/k^2, ln k, x ln k] with x = 20 beta and k the number of distinct seeds
+    (the same terms fsg_estimate_spread evaluates)."""
+    x = 20.0 * np.asarray(beta, dtype=np.float64)
+    k = np.maximum(np.asarray(k, dtype=np.float64), 1.0)
+    lk = np.log(k)
+    return np.stack([np.ones_like(x), x, x * x, x ** 3, 1.0 / k, x / k, 1.0 / (k * k), lk, x * lk],
+                    axis=-1)
+
+
+def fit_calibration(pred_mean, label, beta, k, min_seeds: int = 5):
+    """Least-squares fit of ln(label / prediction) on the calibration terms,
+    over training queries with at least min_seeds seeds; returns the
+    coefficient vector (the calibrated spread is prediction * exp(f . c))."""
+    pred_mean, label = np.asarray(pred_mean, np.float64), np.asarray(label, np.float64)
+    k = np.asarray(k)
+    sel = (k >= min_seeds) & (pred_mean > 0) & (label > 0)
+    A = calib_features(np.asarray(beta)[sel], k[sel])
+    coef, *_ = np.linalg.lstsq(A, np.log(label[sel] / pred_mean[sel]), rcond=None)
+    return coef
+
+
+def apply_calibration(pred_mean, beta, k, coef):
+    return np.asarray(pred_mean, np.float64) * np.exp(calib_features(beta, k) @ np.asarray(coef))
+
+
+def calibrate_gate(spread, unc, ref, k, max_rel_err: float, min_seeds_floor: int = 5,
+                   quantile: float = 0.9, quantile_frac: float = 0.25, tau_slack: float = 2.0,
+                   min_queries: int = 10):
+    """Acceptance gate from held-out calibration queries (calibrated spread,
+    member uncertainty, Monte Carlo reference, seed count).
+
+    min_seeds is the smallest seed count k0 >= min_seeds_floor such that the
+    calibration queries with at least k0 seeds (at least min_queries of them)
+    have their `quantile` error below quantile_frac * max_rel_err and their
+    largest error below max_rel_err; tau is tau_slack times the largest
+    member uncertainty among them (a guard against queries unlike the
+    calibration set).  No such k0: everything falls back.  Returns
+    dict(tau, min_seeds)."""
+    spread, unc, ref, k = (np.asarray(a, np.float64) for a in (spread, unc, ref, k))
+    err = np.abs(spread - ref) / np.maximum(ref, 1e-12)
+    for k0 in sorted(set(int(x) for x in k if x >= min_seeds_floor)):
+        sel = k >= k0
+        if sel.sum() < min_queries:
+            break
+        if np.quantile(err[sel], quantile) <= quantile_frac * max_rel_err and \
+                err[sel].max() <= max_rel_err:
+            return dict(tau=float(tau_slack * unc[sel].max()), min_seeds=int(k0))
+    return dict(tau=-1.0, min_seeds=int(k.max()) + 1)
+
+
 def calibrate_tau(mean, unc, ref, max_rel_err: float):
     """Largest threshold tau such that every calibration query with
     uncertainty <= tau has relative error <= max_rel_err."""
