@@ -195,6 +195,34 @@ int fsg_simulate(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds
                  void *dev_ws, size_t ws_bytes, uint8_t *final_states, uint32_t *infected_counts,
                  fsg_run_info *info, void *stream);
 
+/* Stateful stepping (the paper's run_iteration / run_iterations: steps that
+ * continue from the current state, Sec. 3.3 "Basic Workflow").  Because
+ * every draw is keyed by (unit, replicate, step), a run cut into any number
+ * of session steps gives bit for bit what one fsg_simulate call gives.
+ * fsg_session_begin validates and seeds like fsg_simulate (same workspace,
+ * fsg_sim_workspace_size) and keeps pointers into dev_ws, which must stay
+ * valid until fsg_session_end; synchronous.  Calls on one session must not
+ * overlap. */
+typedef struct fsg_session fsg_session;
+int fsg_session_begin(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds,
+                      int64_t n_seeds, int64_t B, int64_t replicate_offset, uint64_t rng_key,
+                      const fsg_schedule *sched, void *dev_ws, size_t ws_bytes, void *stream,
+                      fsg_session **out);
+/* Runs up to n_steps further steps (fewer once the run is absorbed or
+ * reaches prm->max_steps).  dev_tally (device uint64 [n_steps][2], or NULL):
+ * row i receives, for the state after the i-th step of this call, the number
+ * of (node, replicate) pairs in state 1 and in state 2 (state 0 is the rest
+ * of n * B); rows of steps not run repeat the final state's tally.  info:
+ * steps_run = steps executed since begin, absorbed.  Synchronous. */
+int fsg_session_step(fsg_session *s, int64_t n_steps, uint64_t *dev_tally, fsg_run_info *info,
+                     void *stream);
+/* The current state: states (device uint8 [n][B] or NULL), counts (device
+ * uint32 [n] or NULL, as fsg_simulate) and its tally (device uint64 [2] or
+ * NULL).  Synchronous. */
+int fsg_session_read(fsg_session *s, uint8_t *states, uint32_t *counts, uint64_t *dev_tally,
+                     void *stream);
+int fsg_session_end(fsg_session *s);
+
 /* ---- Batches: many jobs (graphs, models, seed sets, B) in one launch per
  * synchronous step (Definition "Batched Monte Carlo Method" applied across
  * jobs as well as replicates).  Every launch is a persistent work-queue

@@ -578,7 +578,158 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
     return FSG_OK;
 }
 
+// A run in progress: the job on the caller's workspace, its schedule, and
+// how far it has got.
+struct Session {
+    Job jb;
+    int edge_grid = 0;
+    int64_t steps_run = 0;  // steps executed so far
+    bool absorbed = false;
+    double kernel_ms = 0.0;
+    int64_t timed_steps = 0;
+};
+
+int begin_session(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t n_seeds,
+                  int64_t B, int64_t replicate_offset, uint64_t rng_key, const fsg_schedule *sched,
+                  void *dev_ws, size_t ws_bytes, hipStream_t st, Session *ss)
+{
+    int rc = validate_run(g, prm, seeds, n_seeds, B, replicate_offset);
+    if (rc) return rc;
+    Sched s;
+    rc = resolve_sched(g, prm, B, sched, &s);
+    if (rc) return rc;
+    const Plan &p = get_plan(g, s.heavy, s.tile_edges);
+    Layout L;
+    layout(g, prm, B, s, p, &L);
+    if (!dev_ws || ws_bytes < L.total) return fail(FSG_EWORKSPACE, "simulation workspace too small");
+    if (((uintptr_t)dev_ws & 255) != 0) return fail(FSG_EWORKSPACE, "workspace not 256-byte aligned");
+    char *base = (char *)dev_ws;
+    rc = setup_job(g, prm, seeds, n_seeds, B, replicate_offset, rng_key, s, p, L, base,
+                   (uint32_t *)(base + L.flags), st, &ss->jb);
+    if (rc) return rc;
+    ss->edge_grid = 0;
+    if (s.edge1) {
+        int dev = 0, ncu = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        ss->edge_grid = 4 * std::max(ncu, 1);  // 32 KB of LDS a block: four per CU
+    }
+    ss->steps_run = 0;
+    ss->absorbed = n_seeds == 0;
+    ss->kernel_ms = 0.0;
+    ss->timed_steps = 0;
+    return FSG_OK;
+}
+
+// Tally arguments for the state after step `step` (0: the current state,
+// no absorption check).
+FinArgs tally_args(const Session &ss, unsigned long long *out, uint32_t step)
+{
+    const Job &jb = ss.jb;
+    const int64_t t = step ? (int64_t)step : ss.steps_run;
+    FinArgs f;
+    memset(&f, 0, sizeof(f));
+    f.n = (int32_t)jb.n;
+    f.W = (int32_t)jb.L.W;
+    f.B = jb.B;
+    f.model = jb.model;
+    f.one = jb.pl[t & 1];
+    f.two = jb.kind == kKindLT ? nullptr : jb.pl[2];
+    if (jb.model == FSG_SIS || jb.model == FSG_SI) f.two = nullptr;
+    f.bm = jb.s.edge1 ? jb.bm[t & 1] : nullptr;
+    f.tally = out;
+    f.flags = step ? jb.a.flags : nullptr;
+    f.ring = jb.ring;
+    f.step = step;
+    return f;
+}
+
+void fill_info(const Session &ss, fsg_run_info *info)
+{
+    info->steps_run = ss.steps_run;
+    info->absorbed = ss.absorbed ? 1 : 0;
+    info->reserved = 0;
+    info->step_kernel_ms = ss.kernel_ms;
+    info->step_launches = ss.timed_steps;
+}
+
+// Up to n_more further steps (never past the job's step cap), in chunks of
+// `sync` steps with one poll of the absorption flags per chunk.  With
+// dev_tally, row i receives the state tally after the i-th step of this call.
+int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
+{
+    Job &jb = ss.jb;
+    const Sched &s = jb.s;
+    StepArgs &a = jb.a;
+    const int kind = jb.kind;
+    const int ring = jb.ring;
+    uint32_t *flags = a.flags;
+    const int64_t t_begin = ss.steps_run;
+    const int64_t K = std::min<int64_t>(jb.K, t_begin + n_more);
+    std::vector<uint32_t> hflags((size_t)ring);
+    EventPool ev;
+    if (s.timed) HIP_TRY(ev.init(2 * (size_t)s.sync));
+    int64_t t = t_begin;
+    while (!ss.absorbed && t < K) {
+        const int64_t c = std::min<int64_t>(s.sync, K - t);
+        HIP_TRY(launch_ring_clear(flags, ring, (int32_t)(t % ring), st));
+        for (int64_t i = 1; i <= c; ++i) {
+            const int64_t step = t + i;
+            a.step = (uint32_t)step;
+            a.prev = jb.pl[(step - 1) & 1];
+            a.next = jb.pl[step & 1];
+            // timed: the dominant kernel of the step alone (the pull step,
+            // without the bitmap clear or the heavy-row combine)
+            if (s.edge1) {
+                a.bm_prev = jb.bm[(step - 1) & 1];
+                a.bm_next = jb.bm[step & 1];
+                a.sum_prev = jb.sum[(step - 1) & 1];
+                a.sum_next = jb.sum[step & 1];
+                HIP_TRY(launch_ic_clear(a, st));
+                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
+                HIP_TRY(launch_ic_stream(a, ss.edge_grid, s.block, st));
+                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
+            } else {
+                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
+                HIP_TRY(launch_step(a, kind, jb.L.L, s.block, st));
+                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
+                if (a.n_heavy > 0) HIP_TRY(launch_combine(a, kind, s.block, st));
+            }
+            if (dev_tally) {
+                FinArgs f = tally_args(ss, (unsigned long long *)dev_tally + 2 * (step - t_begin - 1),
+                                       (uint32_t)step);
+                HIP_TRY(launch_tally(f, st));
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(hflags.data(), flags, (size_t)ring * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (s.timed) {
+            for (int64_t i = 1; i <= c; ++i) {
+                // steps after absorption return at once; count only live ones
+                if (i > 1 && hflags[(size_t)((t + i - 1) % ring)] == 0u) break;
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev.e[2 * (i - 1)], ev.e[2 * (i - 1) + 1]));
+                ss.kernel_ms += ms;
+                ++ss.timed_steps;
+            }
+        }
+        ss.steps_run = t + c;
+        for (int64_t i = 1; i <= c; ++i)
+            if (hflags[(size_t)((t + i) % ring)] == 0u) {
+                ss.steps_run = t + i;
+                ss.absorbed = true;
+                break;
+            }
+        t += c;
+    }
+    return FSG_OK;
+}
+
 }  // namespace
+
+struct fsg_session {
+    Session s;
+};
 
 extern "C" {
 
@@ -722,105 +873,88 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
                  fsg_run_info *info, void *stream)
 {
     try {
-        fsg_graph *g = const_cast<fsg_graph *>(g_);
-        int rc = validate_run(g, prm, seeds, n_seeds, B, replicate_offset);
+        Session ss;
+        int rc = begin_session(const_cast<fsg_graph *>(g_), prm, seeds, n_seeds, B,
+                               replicate_offset, rng_key, sched, dev_ws, ws_bytes,
+                               (hipStream_t)stream, &ss);
         if (rc) return rc;
-        Sched s;
-        rc = resolve_sched(g, prm, B, sched, &s);
+        rc = run_steps(ss, ss.jb.K, nullptr, (hipStream_t)stream);
         if (rc) return rc;
-        const Plan &p = get_plan(g, s.heavy, s.tile_edges);
-        Layout L;
-        layout(g, prm, B, s, p, &L);
-        if (!dev_ws || ws_bytes < L.total) return fail(FSG_EWORKSPACE, "simulation workspace too small");
-        if (((uintptr_t)dev_ws & 255) != 0) return fail(FSG_EWORKSPACE, "workspace not 256-byte aligned");
-        hipStream_t st = (hipStream_t)stream;
-        Job jb;
-        char *base = (char *)dev_ws;
-        rc = setup_job(g, prm, seeds, n_seeds, B, replicate_offset, rng_key, s, p, L, base,
-                       (uint32_t *)(base + L.flags), st, &jb);
+        rc = finalize_job(ss.jb, ss.steps_run, final_states, infected_counts, (hipStream_t)stream);
         if (rc) return rc;
-        StepArgs &a = jb.a;
-        const int kind = jb.kind;
-        const int ring = jb.ring;
-        uint32_t *flags = a.flags;
-        int edge_grid = 0;
-        if (s.edge1) {
-            int dev = 0, ncu = 0;
-            HIP_TRY(hipGetDevice(&dev));
-            HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-            edge_grid = 4 * std::max(ncu, 1);  // 32 KB of LDS a block: four per CU
-        }
-
-        // ---- step loop: chunks of `sync` steps, then a poll of the flags
-        const int64_t K = jb.K;
-        int64_t steps_run = 0;
-        bool absorbed = n_seeds == 0;
-        std::vector<uint32_t> hflags((size_t)ring);
-        EventPool ev;
-        if (s.timed) HIP_TRY(ev.init(2 * (size_t)s.sync));
-        double kernel_ms = 0.0;
-        int64_t timed_steps = 0;
-        int64_t t = 0;
-        while (!absorbed && t < K) {
-            const int64_t c = std::min<int64_t>(s.sync, K - t);
-            HIP_TRY(launch_ring_clear(flags, ring, (int32_t)(t % ring), st));
-            for (int64_t i = 1; i <= c; ++i) {
-                const int64_t step = t + i;
-                a.step = (uint32_t)step;
-                a.prev = jb.pl[(step - 1) & 1];
-                a.next = jb.pl[step & 1];
-                // timed: the dominant kernel of the step alone (the pull step,
-                // without the bitmap clear or the heavy-row combine)
-                if (s.edge1) {
-                    a.bm_prev = jb.bm[(step - 1) & 1];
-                    a.bm_next = jb.bm[step & 1];
-                    a.sum_prev = jb.sum[(step - 1) & 1];
-                    a.sum_next = jb.sum[step & 1];
-                    HIP_TRY(launch_ic_clear(a, st));
-                    if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
-                    HIP_TRY(launch_ic_stream(a, edge_grid, s.block, st));
-                    if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
-                } else {
-                    if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
-                    HIP_TRY(launch_step(a, kind, jb.L.L, s.block, st));
-                    if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
-                    if (a.n_heavy > 0) HIP_TRY(launch_combine(a, kind, s.block, st));
-                }
-            }
-            HIP_TRY(hipMemcpyAsync(hflags.data(), flags, (size_t)ring * 4, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            if (s.timed) {
-                for (int64_t i = 1; i <= c; ++i) {
-                    // steps after absorption return at once; count only live ones
-                    if (i > 1 && hflags[(size_t)((t + i - 1) % ring)] == 0u) break;
-                    float ms = 0.f;
-                    HIP_TRY(hipEventElapsedTime(&ms, ev.e[2 * (i - 1)], ev.e[2 * (i - 1) + 1]));
-                    kernel_ms += ms;
-                    ++timed_steps;
-                }
-            }
-            steps_run = t + c;
-            for (int64_t i = 1; i <= c; ++i)
-                if (hflags[(size_t)((t + i) % ring)] == 0u) {
-                    steps_run = t + i;
-                    absorbed = true;
-                    break;
-                }
-            t += c;
-        }
-        rc = finalize_job(jb, steps_run, final_states, infected_counts, st);
-        if (rc) return rc;
-        if (info) {
-            info->steps_run = steps_run;
-            info->absorbed = absorbed ? 1 : 0;
-            info->reserved = 0;
-            info->step_kernel_ms = kernel_ms;
-            info->step_launches = timed_steps;
-        }
+        if (info) fill_info(ss, info);
         return FSG_OK;
     } catch (const std::bad_alloc &) {
         return fail(FSG_ENOMEM, "host allocation failed");
     }
+}
+
+int fsg_session_begin(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds,
+                      int64_t n_seeds, int64_t B, int64_t replicate_offset, uint64_t rng_key,
+                      const fsg_schedule *sched, void *dev_ws, size_t ws_bytes, void *stream,
+                      fsg_session **out)
+{
+    try {
+        if (!out) return fail(FSG_EINVAL, "out is NULL");
+        *out = nullptr;
+        std::unique_ptr<fsg_session> ss(new fsg_session);
+        int rc = begin_session(const_cast<fsg_graph *>(g), prm, seeds, n_seeds, B, replicate_offset,
+                               rng_key, sched, dev_ws, ws_bytes, (hipStream_t)stream, &ss->s);
+        if (rc) return rc;
+        *out = ss.release();
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+int fsg_session_step(fsg_session *ss, int64_t n_steps, uint64_t *dev_tally, fsg_run_info *info,
+                     void *stream)
+{
+    try {
+        if (!ss) return fail(FSG_EINVAL, "session is NULL");
+        if (n_steps < 0) return fail(FSG_EINVAL, "n_steps must be >= 0");
+        Session &s = ss->s;
+        const hipStream_t st = (hipStream_t)stream;
+        const int64_t t0 = s.steps_run;
+        int rc = run_steps(s, n_steps, dev_tally, st);
+        if (rc) return rc;
+        if (dev_tally) {
+            // rows of steps that were not run (absorbed, or past max_steps)
+            // repeat the final state's tally
+            for (int64_t i = s.steps_run - t0; i < n_steps; ++i) {
+                FinArgs f = tally_args(s, (unsigned long long *)dev_tally + 2 * i, 0u);
+                HIP_TRY(launch_tally(f, st));
+            }
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        if (info) fill_info(s, info);
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+int fsg_session_read(fsg_session *ss, uint8_t *states, uint32_t *counts, uint64_t *dev_tally,
+                     void *stream)
+{
+    if (!ss) return fail(FSG_EINVAL, "session is NULL");
+    const Session &s = ss->s;
+    const hipStream_t st = (hipStream_t)stream;
+    int rc = finalize_job(s.jb, s.steps_run, states, counts, st);
+    if (rc) return rc;
+    if (dev_tally) {
+        FinArgs f = tally_args(s, (unsigned long long *)dev_tally, 0u);
+        HIP_TRY(launch_tally(f, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return FSG_OK;
+}
+
+int fsg_session_end(fsg_session *ss)
+{
+    delete ss;
+    return FSG_OK;
 }
 
 int fsg_philox4x32_10(const uint32_t *dev_ctr, uint32_t key0, uint32_t key1, uint32_t *dev_out,

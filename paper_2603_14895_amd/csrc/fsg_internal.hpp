@@ -92,6 +92,14 @@ struct FinArgs {
     const uint32_t *bm;   // when set, `one` is valid only for nodes whose bit is set
     uint8_t *states;      // [n][B] or null
     uint32_t *counts;     // [n] or null
+    // tally of the state after a step: out[0] = #(node, replicate) in state
+    // 1, out[1] = # in state 2; when the step did no work (the job was
+    // already absorbed; flag of step - 1 clear) the previous row out[-2..-1]
+    // is copied instead
+    unsigned long long *tally;
+    const uint32_t *flags;  // absorption ring, or null (always a live step)
+    int32_t ring;
+    uint32_t step;
 };
 
 // Many jobs in one launch per synchronous step.  Each job keeps its own
@@ -125,6 +133,7 @@ hipError_t launch_ic_clear(const StepArgs &a, hipStream_t s);
 hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_t s);
 hipError_t launch_combine(const StepArgs &a, int kind, int block, hipStream_t s);
 hipError_t launch_finalize(const FinArgs &f, hipStream_t s);
+hipError_t launch_tally(const FinArgs &f, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
                          int64_t count, hipStream_t s);
 int counter_planes_for(int64_t max_count);  // compile-time counter width to use

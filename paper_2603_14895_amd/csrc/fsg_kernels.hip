@@ -255,9 +255,9 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
         uint64_t rest = 0;
 #pragma unroll
         for (int l = 2; l < LC; ++l) rest |= c[l];
-        const uint64_t ninf = sus & share & (c[0] | c[1] | rest);  // k >= 1
-        const uint64_t m1 = c[0] & ~c[1] & ~rest, m2 = ~c[0] & c[1] & ~rest,
-                       m3 = c[0] & c[1] & ~rest;
+        const uint64_t c0 = c[0], c1 = LC > 1 ? c[LC > 1 ? 1 : 0] : 0ull;
+        const uint64_t ninf = sus & share & (c0 | c1 | rest);  // k >= 1
+        const uint64_t m1 = c0 & ~c1 & ~rest, m2 = ~c0 & c1 & ~rest, m3 = c0 & c1 & ~rest;
         const uint32_t t1 = tcode[1], t2 = tcode[2], t3 = tcode[3];
         uint64_t always = 0;  // classes whose threshold always fires
         if (t1 == kAlways) always |= m1;
@@ -266,8 +266,8 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
         always &= ninf;
         const uint64_t ndraw = ninf & ~always;
         const uint64_t nrec = draw_rec ? (h & share) : 0ull;
-        const uint64_t B0 = (ndraw & c[0] & ~rest) | nrec;
-        const uint64_t B1 = ndraw & c[1] & ~rest;
+        const uint64_t B0 = (ndraw & c0 & ~rest) | nrec;
+        const uint64_t B1 = ndraw & c1 & ~rest;
         const uint64_t B2 = (ndraw & rest) | nrec;
         uint64_t need = ndraw | nrec;
         uint64_t fire = 0;
@@ -399,9 +399,53 @@ __device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool 
                                           uint64_t share, bool &any)
 {
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
+    uint64_t nw = 0;
+    if ((a.goff & 3u) == 0u) {
+        // aligned generator blocks, branch-free per block: c = c0 + 2 c1
+        // when no higher plane is set; v activates iff c 2^32 >= U indeg,
+        // i.e. iff c > hi or (c == hi and lo == 0) for U indeg = hi 2^32 + lo.
+        // Replicates whose every in-neighbour is active (c == indeg) always
+        // activate and need no draw.
+        uint64_t rest = 0;
+#pragma unroll
+        for (int l = 2; l < LC; ++l) rest |= c[l];
+        const uint64_t c0 = c[0], c1 = LC > 1 ? c[LC > 1 ? 1 : 0] : 0ull;
+        const uint64_t cand = inact & share & (c0 | c1 | rest);
+        uint64_t full = cand;  // c == indeg, plane by plane
+#pragma unroll
+        for (int l = 0; l < LC; ++l) full &= ((indeg >> l) & 1u) ? c[l] : ~c[l];
+        if (((uint64_t)indeg >> LC) != 0ull) full = 0;  // c < 2^LC <= indeg
+        uint64_t need = cand & ~full;
+        uint64_t fire = 0;
+        const uint32_t blk0 = (uint32_t)(gbase >> 2);
+        while (need) {
+            const int b = __builtin_ctzll(need);
+            const int gs = b & ~3;
+            const bool hi32 = gs >= 32;
+            const uint32_t sh = (uint32_t)gs & 31u;
+            const uint32_t nn = ((hi32 ? (uint32_t)(need >> 32) : (uint32_t)need) >> sh) & 0xFu;
+            need &= ~(0xFull << gs);
+            const uint32_t n0 = ((hi32 ? (uint32_t)(c0 >> 32) : (uint32_t)c0) >> sh) & 0xFu;
+            const uint32_t n1 = ((hi32 ? (uint32_t)(c1 >> 32) : (uint32_t)c1) >> sh) & 0xFu;
+            const uint32_t nr = ((hi32 ? (uint32_t)(rest >> 32) : (uint32_t)rest) >> sh) & 0xFu;
+            const U4 o = philox10((uint32_t)v, blk0 + ((uint32_t)gs >> 2), 0u, kDomLtThresh << 24,
+                                  a.key0, a.key1);
+            const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
+            uint32_t f = 0;
+#pragma unroll
+            for (int j = 3; j >= 0; --j) {
+                uint32_t k = ((n0 >> j) & 1u) + 2u * ((n1 >> j) & 1u);
+                if ((nr >> j) & 1u) k = bs_get<LC>(c, gs + j);  // four or more active
+                const uint64_t prod = (uint64_t)ou[j] * (uint64_t)indeg;
+                const uint32_t ph = (uint32_t)(prod >> 32), pl = (uint32_t)prod;
+                f = f + f + ((k > ph || (k == ph && pl == 0u)) ? 1u : 0u);
+            }
+            fire |= (uint64_t)(f & nn) << gs;
+        }
+        nw = fire | full;
+    } else {
     uint64_t cand = inact & bs_nonzero<LC>(c) & share;
     const SmallCounts sm = bs_small<LC>(c);
-    uint64_t nw = 0;
     while (cand) {
         const int b = __builtin_ctzll(cand);
         const int gs = b - (int)((gbase + (uint64_t)b) & 3u);
@@ -423,6 +467,7 @@ __device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool 
             if ((uint64_t)k >= need) fa |= 1u << j;
         }
         nw |= nibble_to_word(fa, gs);
+    }
     }
     nw = or_reduce_lanes(nw, G, S);
     if (!valid || s != 0) return;
@@ -1011,6 +1056,43 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
     }
 }
 
+// State tally after a step (per-step trajectories): popcounts of the state
+// planes summed over nodes and replicates; integer atomics, so the totals are
+// exact and independent of the order.
+__global__ void __launch_bounds__(256) k_tally(FinArgs f)
+{
+    if (f.flags && f.step > 1u && f.flags[(f.step - 1u) % (uint32_t)f.ring] == 0u) {
+        if (blockIdx.x == 0 && threadIdx.x < 2) f.tally[threadIdx.x] = f.tally[(int)threadIdx.x - 2];
+        return;
+    }
+    unsigned long long c1 = 0, c2 = 0;
+    const int64_t words = (int64_t)f.n * f.W;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / f.W;
+        const int w = (int)(i - v * f.W);
+        const uint64_t tail = tail_mask(w, f.B);
+        const bool live = !f.bm || ((f.bm[v >> 5] >> (v & 31)) & 1u);
+        const uint64_t one = live ? (f.one[i] & tail) : 0ull;
+        const uint64_t two = f.two ? (f.two[i] & tail & ~one) : 0ull;
+        c1 += (unsigned long long)__popcll(one);
+        c2 += (unsigned long long)__popcll(two);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        c1 += __shfl_xor(c1, off, 64);
+        c2 += __shfl_xor(c2, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (c1) atomicAdd(&f.tally[0], c1);
+        if (c2) atomicAdd(&f.tally[1], c2);
+    }
+}
+
+__global__ void k_tally_clear(unsigned long long *t)
+{
+    if (threadIdx.x < 2) t[threadIdx.x] = 0ull;
+}
+
 __global__ void k_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
                          int64_t count)
 {
@@ -1183,6 +1265,14 @@ hipError_t launch_finalize(const FinArgs &f, hipStream_t s)
     if (blocks < 1) blocks = 1;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_tally(const FinArgs &f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tally_clear, dim3(1), dim3(64), 0, s, f.tally);
+    const int64_t words = (int64_t)f.n * f.W;
+    hipLaunchKernelGGL(k_tally, dim3(grid_for(words, 256)), dim3(256), 0, s, f);
     return hipGetLastError();
 }
 

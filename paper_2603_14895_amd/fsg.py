@@ -104,6 +104,12 @@ _SIGS = {
     "fsg_simulate": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _I64, _U64,
                                     ctypes.POINTER(fsg_schedule), _VP, _SZ, _VP, _VP,
                                     ctypes.POINTER(fsg_run_info), _VP]),
+    "fsg_session_begin": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _I64,
+                                         _U64, ctypes.POINTER(fsg_schedule), _VP, _SZ, _VP,
+                                         ctypes.POINTER(_VP)]),
+    "fsg_session_step": (ctypes.c_int, [_VP, _I64, _VP, ctypes.POINTER(fsg_run_info), _VP]),
+    "fsg_session_read": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "fsg_session_end": (ctypes.c_int, [_VP]),
     "fsg_philox4x32_10": (ctypes.c_int, [_VP, _U32, _U32, _VP, _I64, _VP]),
     "fsg_plan_row_tiles": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I64, _VP, ctypes.POINTER(_I64)]),
     "fsg_batch_plan": (ctypes.c_int, [ctypes.POINTER(fsg_job), _I32, _I32, ctypes.POINTER(_VP),
@@ -371,6 +377,67 @@ class Simulation:
                             self.states.data_ptr() if self.states is not None else None,
                             self.counts.data_ptr() if self.counts is not None else None,
                             _stream_ptr(stream))
+
+
+class Session:
+    """fsg_session_*: a run that advances step by step from its current state
+    (the paper's run_iteration / run_iterations), with per-step state tallies."""
+
+    def __init__(self, graph: DeviceGraph, model, seeds, B: int, rng_key: int, *,
+                 replicate_offset: int = 0, schedule: Optional[dict] = None, stream=None,
+                 **params):
+        import torch
+        self.graph = graph
+        self.B = int(B)
+        self.prm, self._keep = make_params(model, **params)
+        self.sched = make_schedule(schedule)
+        self.ws_bytes = fsg_sim_workspace_size(graph.handle, self.prm, self.B, self.sched)
+        self._ws, self.ws_addr = _ws(self.ws_bytes, graph.device)
+        seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().fsg_session_begin(graph.handle, ctypes.byref(self.prm),
+                                       seeds.ctypes.data if seeds.size else None, seeds.size,
+                                       self.B, int(replicate_offset), int(rng_key) & (2**64 - 1),
+                                       ctypes.byref(self.sched) if self.sched is not None else None,
+                                       self.ws_addr, self.ws_bytes,
+                                       _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h.value
+        self._torch = torch
+
+    def step(self, n_steps: int = 1, tally: bool = False, stream=None):
+        """Advances up to n_steps; returns (fsg_run_info, tally [n_steps, 2] uint64
+        numpy array or None)."""
+        torch = self._torch
+        out = torch.zeros((max(1, int(n_steps)), 2), dtype=torch.int64,
+                          device=self.graph.device) if tally else None
+        info = fsg_run_info()
+        _check(lib().fsg_session_step(self.handle, int(n_steps),
+                                      out.data_ptr() if out is not None else None,
+                                      ctypes.byref(info), _stream_ptr(stream)))
+        return info, (out[:int(n_steps)].cpu().numpy().astype(np.uint64) if tally else None)
+
+    def read(self, want_states: bool = True, stream=None):
+        """Current (states [n,B] uint8 tensor or None, counts [n] int32 tensor,
+        tally (state-1 pairs, state-2 pairs))."""
+        torch = self._torch
+        st = (torch.empty((self.graph.n, self.B), dtype=torch.uint8, device=self.graph.device)
+              if want_states else None)
+        cnt = torch.empty(self.graph.n, dtype=torch.int32, device=self.graph.device)
+        t = torch.zeros(2, dtype=torch.int64, device=self.graph.device)
+        _check(lib().fsg_session_read(self.handle, st.data_ptr() if st is not None else None,
+                                      cnt.data_ptr(), t.data_ptr(), _stream_ptr(stream)))
+        return st, cnt, tuple(int(x) for x in t.cpu().tolist())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fsg_session_end(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def simulate(graph: DeviceGraph, model, seeds, B, rng_key, *, replicate_offset=0, schedule=None,
