@@ -17,6 +17,13 @@
  *     an infected node recovers with probability gamma;
  *   - SIS / SI (Table tab:29s names them; semantics are the SIR rule with
  *     recovery back to S, resp. no recovery);
+ *   - SEIR(DT) / SEIS(DT) (named in Table tab:29s, validated in the
+ *     comparison tables of the appendix, not defined by equations there):
+ *     the SIR rule with a latent state E between S and I.  A susceptible node
+ *     with k infectious in-neighbours becomes E with probability
+ *     1 - (1-beta)^k, E becomes I with probability alpha, I becomes R (SEIS:
+ *     S) with probability gamma; one draw per node, replicate and step decides
+ *     whichever transition the node's state allows, as for SIR;
  *   - independent cascade (Table tab:29s; Kempe et al. cited in Sec. 2): every
  *     newly active node gets one chance per out-arc to activate its target;
  *   - linear threshold with in-weights 1/indeg and U(0,1) thresholds.
@@ -50,7 +57,7 @@
 static int orc_verbose = 0;
 void orc_set_verbose(int on) { orc_verbose = on; }
 
-enum { ORC_IC = 0, ORC_SI = 1, ORC_SIS = 2, ORC_SIR = 3, ORC_LT = 4 };
+enum { ORC_IC = 0, ORC_SI = 1, ORC_SIS = 2, ORC_SIR = 3, ORC_LT = 4, ORC_SEIR = 5, ORC_SEIS = 6 };
 enum { ORC_IC_UNIFORM = 0, ORC_IC_WEIGHTED_CASCADE = 1, ORC_IC_PER_EDGE = 2 };
 enum { ORC_DOM_IC_EDGE = 1, ORC_DOM_NODE_STEP = 2, ORC_DOM_LT_THRESH = 3 };
 
@@ -144,7 +151,10 @@ typedef struct {
     uint64_t rng_key;
     const uint32_t *tinf; /* [max_indeg + 1] */
     uint32_t trec;
+    uint32_t talpha; /* SEIR / SEIS: E -> I */
 } orc_problem;
+
+static int is_latent_model(int model) { return model == ORC_SEIR || model == ORC_SEIS; }
 
 /* Threshold of in-edge e of node v for IC. */
 static uint32_t ic_edge_threshold(const orc_problem *P, int64_t v, int64_t e)
@@ -156,12 +166,16 @@ static uint32_t ic_edge_threshold(const orc_problem *P, int64_t v, int64_t e)
     return orc_thr(1.0 / (double)indeg);
 }
 
-/* States for every model: 0 = S / inactive, 1 = I / newly active,
- * 2 = R / active since an earlier step.  LT reports 1 for both 1 and 2. */
-static int has_one(const uint8_t *x, int64_t n)
+/* States: IC, SI, SIS, SIR, LT: 0 = S / inactive, 1 = I / newly active,
+ * 2 = R / active since an earlier step (LT reports 1 for both 1 and 2).
+ * SEIR, SEIS: 0 = S, 1 = E, 2 = I, 3 = R.  A run goes on while some node is
+ * in a state that can still change others or itself: 1, or for SEIR / SEIS
+ * E or I. */
+static int has_one(const orc_problem *P, const uint8_t *x, int64_t n)
 {
+    const int latent = is_latent_model(P->model);
     for (int64_t v = 0; v < n; ++v)
-        if (x[v] == 1) return 1;
+        if (x[v] == 1 || (latent && x[v] == 2)) return 1;
     return 0;
 }
 
@@ -197,6 +211,18 @@ static void one_step(const orc_problem *P, uint64_t g, uint32_t t, const uint8_t
                 /* active-weight c / indeg reaches the threshold U / 2^32 */
                 if (c >= 1 && ((uint64_t)c << 32) >= U * (uint64_t)indeg) yv = 1;
             }
+        } else if (is_latent_model(P->model)) { /* SEIR, SEIS */
+            uint32_t U = orc_draw(P->rng_key, ORC_DOM_NODE_STEP, (uint64_t)v, g, t);
+            if (xv == 0) {
+                int64_t k = 0;
+                for (int64_t e = e0; e < e1; ++e)
+                    if (x[P->src[e]] == 2) ++k;
+                if (k > 0 && fires(U, P->tinf[k])) yv = 1;
+            } else if (xv == 1) {
+                if (fires(U, P->talpha)) yv = 2;
+            } else if (xv == 2) {
+                if (fires(U, P->trec)) yv = (P->model == ORC_SEIS) ? 0 : 3;
+            }
         } else { /* SI, SIS, SIR */
             uint32_t U = orc_draw(P->rng_key, ORC_DOM_NODE_STEP, (uint64_t)v, g, t);
             if (xv == 0) {
@@ -217,9 +243,10 @@ static int64_t run_replicate(const orc_problem *P, uint64_t g, const int32_t *se
                              uint8_t *x, uint8_t *y)
 {
     memset(x, 0, (size_t)P->n);
-    for (int64_t i = 0; i < n_seeds; ++i) x[seeds[i]] = 1;
+    /* seeds start infectious: state 1, for SEIR / SEIS state 2 (I) */
+    for (int64_t i = 0; i < n_seeds; ++i) x[seeds[i]] = is_latent_model(P->model) ? 2 : 1;
     int64_t t = 0;
-    while ((P->max_steps < 0 || t < P->max_steps) && has_one(x, P->n)) {
+    while ((P->max_steps < 0 || t < P->max_steps) && has_one(P, x, P->n)) {
         ++t;
         one_step(P, g, (uint32_t)t, x, y);
         memcpy(x, y, (size_t)P->n);
@@ -244,13 +271,13 @@ static int64_t max_indegree(int64_t n, const int64_t *ptr)
  * Returns 0, or -1 on invalid arguments.
  */
 int orc_simulate(int model, int ic_prob, double p, const double *edge_p, double beta, double gamma,
-                 int64_t max_steps, int64_t n, const int64_t *ptr, const int32_t *src,
+                 double alpha, int64_t max_steps, int64_t n, const int64_t *ptr, const int32_t *src,
                  const int32_t *seeds, int64_t n_seeds, int64_t B, int64_t replicate_offset,
                  uint64_t rng_key, uint8_t *states, uint32_t *counts, int64_t *steps_run,
                  int32_t *absorbed, int nthreads)
 {
-    if (n < 1 || B < 0 || model < ORC_IC || model > ORC_LT) return -1;
-    if ((model == ORC_SI || model == ORC_SIS || model == ORC_SIR) && max_steps < 0) return -1;
+    if (n < 1 || B < 0 || model < ORC_IC || model > ORC_SEIS) return -1;
+    if (model != ORC_IC && model != ORC_LT && max_steps < 0) return -1;
     for (int64_t i = 0; i < n_seeds; ++i)
         if (seeds[i] < 0 || seeds[i] >= n) return -1;
 
@@ -258,8 +285,9 @@ int orc_simulate(int model, int ic_prob, double p, const double *edge_p, double 
     uint32_t *tinf = (uint32_t *)calloc((size_t)(dmax + 1), sizeof(uint32_t));
     orc_sir_table(beta, dmax + 1, tinf);
     orc_problem P = {model, ic_prob, p, beta, (model == ORC_SI) ? 0.0 : gamma, edge_p, max_steps,
-                     n, ptr, src, rng_key, tinf, 0};
+                     n, ptr, src, rng_key, tinf, 0, 0};
     P.trec = orc_thr(P.gamma);
+    P.talpha = orc_thr(alpha);
 
     int64_t smax = 0;
     int any_one = 0;
@@ -278,14 +306,17 @@ int orc_simulate(int model, int ic_prob, double p, const double *edge_p, double 
         for (int64_t r = 0; r < B; ++r) {
             int64_t t = run_replicate(&P, (uint64_t)(replicate_offset + r), seeds, n_seeds, x, y);
             if (t > smax) smax = t;
-            if (has_one(x, n)) any_one = 1;
+            if (has_one(&P, x, n)) any_one = 1;
             for (int64_t v = 0; v < n; ++v) {
                 uint8_t s = x[v];
                 uint8_t out = (model == ORC_LT) ? (uint8_t)(s != 0) : s;
                 if (states) states[v * B + r] = out;
                 /* counted: IC ever active; SIR/SI ever infected; SIS infected
-                 * at the end; LT active */
-                int counted = (model == ORC_SIS) ? (s == 1) : (s != 0);
+                 * at the end; LT active; SEIR ever exposed; SEIS exposed or
+                 * infectious at the end */
+                int counted = (model == ORC_SIS)    ? (s == 1)
+                              : (model == ORC_SEIS) ? (s == 1 || s == 2)
+                                                    : (s != 0);
                 cnt[v] += (uint32_t)counted;
             }
         }
@@ -340,7 +371,7 @@ int orc_ic_live_edge(int ic_prob, double p, const double *edge_p, int64_t max_st
             oeid[pos] = e;
         }
     free(fill);
-    orc_problem P = {ORC_IC, ic_prob, p, 0.0, 0.0, edge_p, max_steps, n, ptr, src, rng_key, NULL, 0};
+    orc_problem P = {ORC_IC, ic_prob, p, 0.0, 0.0, edge_p, max_steps, n, ptr, src, rng_key, NULL, 0, 0};
 
     int64_t smax = 0;
     int any_one = 0;

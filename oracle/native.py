@@ -14,10 +14,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fsg_oracle.c")
 _LIB = os.path.join(_HERE, "libfsg_oracle.so")
 
-IC, SI, SIS, SIR, LT = 0, 1, 2, 3, 4
+IC, SI, SIS, SIR, LT, SEIR, SEIS = 0, 1, 2, 3, 4, 5, 6
 IC_UNIFORM, IC_WEIGHTED_CASCADE, IC_PER_EDGE = 0, 1, 2
 DOM_IC_EDGE, DOM_NODE_STEP, DOM_LT_THRESH = 1, 2, 3
-MODEL_NAMES = {"ic": IC, "si": SI, "sis": SIS, "sir": SIR, "lt": LT}
+MODEL_NAMES = {"ic": IC, "si": SI, "sis": SIS, "sir": SIR, "lt": LT, "seir": SEIR, "seis": SEIS}
 
 
 def build(force: bool = True) -> str:
@@ -57,8 +57,9 @@ def _load():
         lib.orc_sir_table.restype = None
         lib.orc_simulate.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_double,
-            ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
-            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+            ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_uint64,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
             ctypes.POINTER(ctypes.c_int32), ctypes.c_int]
         lib.orc_simulate.restype = ctypes.c_int
@@ -117,8 +118,8 @@ def _csr(ptr, src):
 
 
 def simulate(model, ptr, src, seeds, B, rng_key, *, p=0.0, ic_prob=IC_UNIFORM, edge_p=None,
-             beta=0.0, gamma=0.0, max_steps=-1, replicate_offset=0, want_states=True,
-             nthreads=0):
+             beta=0.0, gamma=0.0, alpha=0.0, max_steps=-1, replicate_offset=0,
+             want_states=True, nthreads=0):
     """Plain batched simulation.  Returns (states [n,B] uint8 or None, counts [n] uint32,
     steps_run, absorbed)."""
     lib = _load()
@@ -133,7 +134,7 @@ def simulate(model, ptr, src, seeds, B, rng_key, *, p=0.0, ic_prob=IC_UNIFORM, e
     steps = ctypes.c_int64(0)
     absorbed = ctypes.c_int32(0)
     rc = lib.orc_simulate(model, ic_prob, float(p), _ptr(ep), float(beta), float(gamma),
-                          int(max_steps), n, _ptr(ptr), _ptr(src), _ptr(seeds), seeds.size,
+                          float(alpha), int(max_steps), n, _ptr(ptr), _ptr(src), _ptr(seeds), seeds.size,
                           int(B), int(replicate_offset), int(rng_key) & (2**64 - 1),
                           _ptr(states), _ptr(counts), ctypes.byref(steps),
                           ctypes.byref(absorbed), int(nthreads))

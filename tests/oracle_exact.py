@@ -143,6 +143,51 @@ def epidemic_exact_marginals(n, ptr, src, seeds, beta, gamma, steps, sis=False):
     return marg
 
 
+def latent_exact_marginals(n, ptr, src, seeds, beta, alpha, gamma, steps, seis=False):
+    """Exact synchronous SEIR / SEIS Markov chain on all 4^n joint states
+    (states 0 S, 1 E, 2 I, 3 R; seeds start in I).
+
+    Given the previous joint state every node moves independently:
+    S -> E with probability 1 - (1-beta)^k, k = number of in-arcs from
+    nodes in I; E -> I with probability alpha; I -> R (SEIS: I -> S) with
+    probability gamma; R stays.  Returns P[x_v = s] after ``steps`` steps as
+    an array [n, 4]."""
+    rows = [[int(src[e]) for e in range(ptr[v], ptr[v + 1])] for v in range(n)]
+    x0 = [0] * n
+    for s in seeds:
+        x0[s] = 2
+    dist = {tuple(x0): 1.0}
+    for _ in range(steps):
+        nxt = {}
+        for x, mass in dist.items():
+            per_node = []
+            for v in range(n):
+                if x[v] == 0:
+                    k = sum(1 for u in rows[v] if x[u] == 2)
+                    q = 1.0 - (1.0 - beta) ** k
+                    per_node.append([(0, 1.0 - q), (1, q)])
+                elif x[v] == 1:
+                    per_node.append([(1, 1.0 - alpha), (2, alpha)])
+                elif x[v] == 2:
+                    per_node.append([(2, 1.0 - gamma), (0 if seis else 3, gamma)])
+                else:
+                    per_node.append([(3, 1.0)])
+            for combo in itertools.product(*per_node):
+                w = mass
+                for _, q in combo:
+                    w *= q
+                if w == 0.0:
+                    continue
+                y = tuple(s for s, _ in combo)
+                nxt[y] = nxt.get(y, 0.0) + w
+        dist = nxt
+    marg = np.zeros((n, 4))
+    for x, mass in dist.items():
+        for v in range(n):
+            marg[v, x[v]] += mass
+    return marg
+
+
 def zscore(freq, p, B):
     """Binomial z-score of an observed frequency against an exact probability."""
     var = max(p * (1.0 - p), 1e-12) / B

@@ -310,6 +310,71 @@ def test_epidemic_exact_markov_chain(model, case):
             assert abs(X.zscore(f, marg[v, s], B)) < ZMAX, (v, s, f, marg[v, s])
 
 
+# ---------------------------------------------------- SEIR / SEIS pins --
+
+@pytest.mark.parametrize("model", ["seir", "seis"])
+@pytest.mark.parametrize("case", [0, 1])
+def test_latent_exact_markov_chain(model, case):
+    """Per-node marginals of the four states after K steps equal those of the
+    exact synchronous SEIR / SEIS chain over all 4^n joint states."""
+    rng = np.random.default_rng(150 + case)
+    n = 5
+    edges = [(int(rng.integers(n)), int(rng.integers(n))) for _ in range(9)] + [(0, 1), (1, 0)]
+    gr = W.from_edges(n, edges)
+    ptr, src = gr.numpy()
+    beta, alpha, gamma, K, B = 0.4, 0.5, 0.3, 5, 40000
+    marg = X.latent_exact_marginals(n, ptr, src, [0], beta, alpha, gamma, K,
+                                    seis=(model == "seis"))
+    st, _, _, _ = oracle.simulate(model, ptr, src, [0], B, 0x5E1 + case, beta=beta,
+                                  alpha=alpha, gamma=gamma, max_steps=K)
+    for v in range(n):
+        for s in range(4):
+            f = (st[v] == s).mean()
+            assert abs(X.zscore(f, marg[v, s], B)) < ZMAX, (v, s, f, marg[v, s])
+
+
+def test_seir_single_edge_closed_form():
+    """Arc 0 -> 1, seed 0 infectious: node 1 is ever exposed with probability
+    beta / (1 - (1-beta)(1-gamma)) (the seed transmits with probability beta
+    in every step it is still infectious); with K large every exposed node
+    ends recovered."""
+    gr = W.from_edges(2, [(0, 1)])
+    ptr, src = gr.numpy()
+    beta, alpha, gamma, B = 0.3, 0.4, 0.2, 100000
+    T = beta / (1.0 - (1.0 - beta) * (1.0 - gamma))
+    st, cnt, steps, absorbed = oracle.simulate("seir", ptr, src, [0], B, 0x5E2, beta=beta,
+                                               alpha=alpha, gamma=gamma, max_steps=400)
+    assert absorbed == 1
+    assert abs(X.zscore(cnt[1] / B, T, B)) < ZMAX
+    assert set(np.unique(st[1]).tolist()) <= {0, 3} and (st[0] == 3).all()
+    assert (cnt[1] == (st[1] == 3).sum())
+
+
+def test_seir_no_infection_decay():
+    """beta = 0: nobody is exposed; a seed is still infectious after K steps
+    with probability (1-gamma)^K."""
+    gr = W.from_edges(3, [(0, 1), (1, 2), (0, 2)])
+    ptr, src = gr.numpy()
+    gamma, K, B = 0.15, 6, 100000
+    st, _, _, _ = oracle.simulate("seir", ptr, src, [0], B, 0x5E3, beta=0.0, alpha=0.5,
+                                  gamma=gamma, max_steps=K)
+    assert abs(X.zscore((st[0] == 2).mean(), (1 - gamma) ** K, B)) < ZMAX
+    assert (st[1:] == 0).all()
+
+
+def test_seir_deterministic_latency():
+    """beta = alpha = 1, gamma = 0 on a path: hop d is exposed at step 2d - 1
+    and infectious from step 2d on (one step in E)."""
+    gr = W.from_edges(5, [(0, 1), (1, 2), (2, 3), (3, 4)])
+    ptr, src = gr.numpy()
+    for K in range(9):
+        st, _, _, _ = oracle.simulate("seir", ptr, src, [0], 3, 7, beta=1.0, alpha=1.0,
+                                      gamma=0.0, max_steps=K)
+        for d in range(5):
+            want = 2 if (d == 0 or K >= 2 * d) else (1 if K == 2 * d - 1 else 0)
+            assert (st[d] == want).all(), (K, d, st[d], want)
+
+
 # -------------------------------------------------------------- LT pins --
 
 @pytest.mark.parametrize("case", [0, 1, 2])
