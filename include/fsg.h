@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FSG_ABI_VERSION 1
+#define FSG_ABI_VERSION 2
 
 /* status codes */
 #define FSG_OK 0
@@ -60,6 +60,8 @@ extern "C" {
 #define FSG_SIS 2 /* SIS: recovery returns the node to S                        */
 #define FSG_SIR 3 /* SIR: 0 S, 1 I, 2 R                                         */
 #define FSG_LT 4  /* linear threshold, in-weights 1/indeg, thresholds U(0,1)    */
+#define FSG_SEIR 5 /* SEIR(DT): 0 S, 1 E (latent), 2 I, 3 R                     */
+#define FSG_SEIS 6 /* SEIS(DT): SEIR with recovery back to S                    */
 
 /* IC edge probability */
 #define FSG_IC_UNIFORM 0          /* p for every arc                         */
@@ -72,7 +74,14 @@ typedef struct fsg_graph fsg_graph;
  * max_steps: step cap K >= 0.  For IC and LT a negative value means "until
  * absorption" (at most n steps can change anything).  SI, SIS, SIR require
  * K >= 0.  p, beta, gamma, edge_p[] must lie in [0, 1] and not be NaN.
- * For SI, gamma is ignored (no recovery). */
+ * For SI, gamma is ignored (no recovery).
+ * SEIR / SEIS (named in Table tab:29s; the paper gives no equations, so
+ * this is the discrete-time SIR rule with a latent state): a susceptible
+ * node with k infectious in-neighbours becomes E with probability
+ * 1 - (1-beta)^k, E becomes I with probability alpha, I becomes R (SEIS: S)
+ * with probability gamma, one draw per node, replicate and step; seeds
+ * start infectious; they require K >= 0.  alpha must lie in [0, 1] and is
+ * ignored by the other models. */
 typedef struct {
     int32_t model;
     int32_t ic_prob;
@@ -81,11 +90,13 @@ typedef struct {
     double beta;
     double gamma;
     int64_t max_steps;
+    double alpha; /* SEIR / SEIS: per-step probability of E -> I */
 } fsg_params;
 
 /* steps_run: number of synchronous steps executed (the batch shares one
- * loop that stops once no replicate has a state-1 node, or at max_steps).
- * absorbed: 1 iff no replicate ends with a state-1 node.
+ * loop that stops once no replicate has a state-1 node -- for SEIR / SEIS
+ * no node in E or I -- or at max_steps).
+ * absorbed: 1 iff no replicate ends with such a node.
  * step_kernel_ms, step_launches: when the schedule asks for kernel timing,
  * the summed device time of the pull-step kernel (HIP events recorded on the
  * call's stream right around its launch in every step that did work; the
@@ -176,15 +187,18 @@ int fsg_sim_workspace_size(const fsg_graph *g, const fsg_params *prm, int64_t B,
 /* Batched Monte Carlo propagation (Algorithm 1 run as Eq. batch): B >= 1
  * replicates with global indices replicate_offset + r, r < B
  * (replicate_offset >= 0, replicate_offset + B <= 2^34), every replicate
- * starting with the seed set in state 1 and everything else in state 0.
+ * starting with the seed set in state 1 (SEIR / SEIS: state 2, I) and
+ * everything else in state 0.
  * seeds: host int32 [n_seeds], each in [0, n); duplicates are ignored and an
  * empty set is valid (nothing happens).
  * Outputs (device, either may be NULL):
  *   final_states [n][B] uint8, final_states[v*B + r] = state of node v in
- *     replicate r (IC 0/1/2, SIR 0/1/2, SI and SIS 0/1, LT 0/1);
+ *     replicate r (IC 0/1/2, SIR 0/1/2, SI and SIS 0/1, LT 0/1,
+ *     SEIR 0/1/2/3, SEIS 0/1/2);
  *   infected_counts [n] uint32, the number of replicates in which v is
  *     counted: ever active (IC), ever infected (SI, SIR), infected at the
- *     end (SIS), active (LT).
+ *     end (SIS), active (LT), ever exposed (SEIR), exposed or infectious at
+ *     the end (SEIS).
  * info (host, may be NULL) receives steps_run and absorbed.
  * The graph must be bound.  dev_ws: at least fsg_sim_workspace_size bytes,
  * 256-byte aligned; its contents on entry do not matter.  The call returns
@@ -209,15 +223,15 @@ int fsg_session_begin(const fsg_graph *g, const fsg_params *prm, const int32_t *
                       const fsg_schedule *sched, void *dev_ws, size_t ws_bytes, void *stream,
                       fsg_session **out);
 /* Runs up to n_steps further steps (fewer once the run is absorbed or
- * reaches prm->max_steps).  dev_tally (device uint64 [n_steps][2], or NULL):
+ * reaches prm->max_steps).  dev_tally (device uint64 [n_steps][3], or NULL):
  * row i receives, for the state after the i-th step of this call, the number
- * of (node, replicate) pairs in state 1 and in state 2 (state 0 is the rest
- * of n * B); rows of steps not run repeat the final state's tally.  info:
+ * of (node, replicate) pairs in states 1, 2 and 3 (state 0 is the rest of
+ * n * B); rows of steps not run repeat the final state's tally.  info:
  * steps_run = steps executed since begin, absorbed.  Synchronous. */
 int fsg_session_step(fsg_session *s, int64_t n_steps, uint64_t *dev_tally, fsg_run_info *info,
                      void *stream);
 /* The current state: states (device uint8 [n][B] or NULL), counts (device
- * uint32 [n] or NULL, as fsg_simulate) and its tally (device uint64 [2] or
+ * uint32 [n] or NULL, as fsg_simulate) and its tally (device uint64 [3] or
  * NULL).  Synchronous. */
 int fsg_session_read(fsg_session *s, uint8_t *states, uint32_t *counts, uint64_t *dev_tally,
                      void *stream);

@@ -238,11 +238,13 @@ int check_params(const fsg_graph *g, const fsg_params *prm, int64_t B)
 {
     if (!g) return fail(FSG_EINVAL, "graph is NULL");
     if (!prm) return fail(FSG_EINVAL, "params is NULL");
-    if (prm->model < FSG_IC || prm->model > FSG_LT) return fail(FSG_EINVAL, "unknown model");
+    if (prm->model < FSG_IC || prm->model > FSG_SEIS) return fail(FSG_EINVAL, "unknown model");
     if (B < 1) return fail(FSG_EINVAL, "B must be >= 1");
     if (B > (int64_t)1 << 31) return fail(FSG_EUNSUPPORTED, "B above 2^31");
-    const bool epi = prm->model == FSG_SI || prm->model == FSG_SIS || prm->model == FSG_SIR;
-    if (epi && prm->max_steps < 0) return fail(FSG_EINVAL, "SI/SIS/SIR need max_steps >= 0");
+    const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS;
+    const bool epi = prm->model == FSG_SI || prm->model == FSG_SIS || prm->model == FSG_SIR || latent;
+    if (epi && prm->max_steps < 0)
+        return fail(FSG_EINVAL, "SI/SIS/SIR/SEIR/SEIS need max_steps >= 0");
     if (prm->max_steps > 0x7FFFFFFF) return fail(FSG_EUNSUPPORTED, "max_steps above 2^31-1");
     if (prm->model == FSG_IC) {
         if (prm->ic_prob < FSG_IC_UNIFORM || prm->ic_prob > FSG_IC_PER_EDGE)
@@ -259,6 +261,7 @@ int check_params(const fsg_graph *g, const fsg_params *prm, int64_t B)
         if (bad_prob(prm->beta)) return fail(FSG_EINVAL, "beta must be in [0, 1]");
         if (prm->model != FSG_SI && bad_prob(prm->gamma))
             return fail(FSG_EINVAL, "gamma must be in [0, 1]");
+        if (latent && bad_prob(prm->alpha)) return fail(FSG_EINVAL, "alpha must be in [0, 1]");
     }
     return FSG_OK;
 }
@@ -328,7 +331,7 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
 }
 
 struct Layout {
-    size_t planes[3];
+    size_t planes[4];
     int n_planes;
     size_t flags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
         seeds, bm[2], sum[2], total;
@@ -365,7 +368,8 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
     L->W = (B + 63) / 64;
     // one extra all-zero row (index n): gathers of padding lanes read it
     L->plane_words = (g->n + 1) * L->W;
-    L->n_planes = kind == kKindLT ? 2 : 3;
+    const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS;
+    L->n_planes = kind == kKindLT ? 2 : (latent ? 4 : 3);
     L->L = kind == kKindIC ? 1 : counter_planes_for(std::max(p.max_light, p.max_seg));
     // room for the longest table (it stops early once it saturates), so the
     // workspace size does not depend on beta
@@ -439,7 +443,7 @@ struct Job {
     int64_t n = 0;
     int64_t B = 0;
     int model = 0;
-    uint64_t *pl[3] = {nullptr, nullptr, nullptr};
+    uint64_t *pl[4] = {nullptr, nullptr, nullptr, nullptr};
     uint32_t *bm[2] = {nullptr, nullptr};
     uint32_t *sum[2] = {nullptr, nullptr};
 };
@@ -461,8 +465,9 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     jb->n = g->n;
     jb->B = B;
     jb->model = prm->model;
-    // plane roles: IC {F0, F1, A}; epidemic {h0, h1, r}; LT {act0, act1}
-    for (int i = 0; i < 3; ++i)
+    // plane roles: IC {F0, F1, A}; epidemic {h0, h1, r}, SEIR / SEIS also
+    // the latent plane e; LT {act0, act1}
+    for (int i = 0; i < 4; ++i)
         jb->pl[i] = i < L.n_planes ? (uint64_t *)(base + L.planes[i]) : nullptr;
     const int ring = jb->ring;
 
@@ -527,6 +532,9 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.tinf = (const uint32_t *)(base + L.tinf);
     a.khat = (int32_t)tinf.size() - 1;
     a.trec = prm->model == FSG_SI ? 0u : threshold_of(prm->gamma);
+    const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS;
+    a.talpha = latent ? threshold_of(prm->alpha) : 0u;
+    a.lat = latent ? jb->pl[3] : nullptr;
     a.G = s.G;
     a.S = s.S;
     a.lgG = s.lgG;
@@ -569,7 +577,8 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
     f.model = jb.model;
     f.one = jb.pl[steps_run & 1];
     f.two = jb.kind == kKindLT ? nullptr : jb.pl[2];
-    if (jb.model == FSG_SIS || jb.model == FSG_SI) f.two = nullptr;
+    if (jb.model == FSG_SIS || jb.model == FSG_SI || jb.model == FSG_SEIS) f.two = nullptr;
+    f.three = jb.pl[3];
     f.states = final_states;
     f.counts = counts;
     f.bm = jb.s.edge1 ? jb.bm[steps_run & 1] : nullptr;
@@ -635,7 +644,8 @@ FinArgs tally_args(const Session &ss, unsigned long long *out, uint32_t step)
     f.model = jb.model;
     f.one = jb.pl[t & 1];
     f.two = jb.kind == kKindLT ? nullptr : jb.pl[2];
-    if (jb.model == FSG_SIS || jb.model == FSG_SI) f.two = nullptr;
+    if (jb.model == FSG_SIS || jb.model == FSG_SI || jb.model == FSG_SEIS) f.two = nullptr;
+    f.three = jb.pl[3];
     f.bm = jb.s.edge1 ? jb.bm[t & 1] : nullptr;
     f.tally = out;
     f.flags = step ? jb.a.flags : nullptr;
@@ -696,7 +706,7 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 if (a.n_heavy > 0) HIP_TRY(launch_combine(a, kind, s.block, st));
             }
             if (dev_tally) {
-                FinArgs f = tally_args(ss, (unsigned long long *)dev_tally + 2 * (step - t_begin - 1),
+                FinArgs f = tally_args(ss, (unsigned long long *)dev_tally + 3 * (step - t_begin - 1),
                                        (uint32_t)step);
                 HIP_TRY(launch_tally(f, st));
             }
@@ -923,7 +933,7 @@ int fsg_session_step(fsg_session *ss, int64_t n_steps, uint64_t *dev_tally, fsg_
             // rows of steps that were not run (absorbed, or past max_steps)
             // repeat the final state's tally
             for (int64_t i = s.steps_run - t0; i < n_steps; ++i) {
-                FinArgs f = tally_args(s, (unsigned long long *)dev_tally + 2 * i, 0u);
+                FinArgs f = tally_args(s, (unsigned long long *)dev_tally + 3 * i, 0u);
                 HIP_TRY(launch_tally(f, st));
             }
             HIP_TRY(hipStreamSynchronize(st));

@@ -25,7 +25,7 @@ enum Kind { kKindIC = 0, kKindEpidemic = 1, kKindLT = 2 };
 constexpr int kMaxTileRows = 2048;
 // Words of the frontier summary the edge-parallel kernel keeps in LDS.
 constexpr int kSumWords = 8192;
-enum Model { kIC = 0, kSI = 1, kSIS = 2, kSIR = 3, kLT = 4 };
+enum Model { kIC = 0, kSI = 1, kSIS = 2, kSIR = 3, kLT = 4, kSEIR = 5, kSEIS = 6 };
 enum IcProb { kIcUniform = 0, kIcWeightedCascade = 1, kIcPerEdge = 2 };
 
 // Everything one synchronous step needs.  Planes are uint64 [n][W]:
@@ -52,6 +52,8 @@ struct StepArgs {
     const uint32_t *tinf;   // infection thresholds by infected-neighbour count
     int32_t khat;           // last index of tinf
     uint32_t trec;          // recovery threshold
+    uint32_t talpha;        // SEIR / SEIS: E -> I threshold
+    uint64_t *lat;          // SEIR / SEIS: latent (E) plane [n][W], updated in place; else null
     // schedule
     int32_t G, S, lgG, lgS; // lanes per row: G over words, S over edges
     int32_t heavy;          // rows with more in-edges are processed as segments
@@ -88,14 +90,15 @@ struct FinArgs {
     int64_t B;
     int32_t model;
     const uint64_t *one;  // state-1 plane (F, h, active)
-    const uint64_t *two;  // state-2 plane (A for IC, r for SIR) or null
+    const uint64_t *two;  // state-2 plane (A for IC, r for SIR and SEIR) or null
+    const uint64_t *three;  // latent plane (SEIR / SEIS) or null
     const uint32_t *bm;   // when set, `one` is valid only for nodes whose bit is set
     uint8_t *states;      // [n][B] or null
     uint32_t *counts;     // [n] or null
-    // tally of the state after a step: out[0] = #(node, replicate) in state
-    // 1, out[1] = # in state 2; when the step did no work (the job was
-    // already absorbed; flag of step - 1 clear) the previous row out[-2..-1]
-    // is copied instead
+    // tally of the state after a step: out[s-1] = #(node, replicate) in
+    // state s, s = 1, 2, 3; when the step did no work (the job was already
+    // absorbed; flag of step - 1 clear) the previous row out[-3..-1] is
+    // copied instead
     unsigned long long *tally;
     const uint32_t *flags;  // absorption ring, or null (always a live step)
     int32_t ring;

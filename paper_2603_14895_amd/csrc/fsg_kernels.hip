@@ -218,8 +218,9 @@ __device__ __forceinline__ void count_edges_bcast(const StepArgs &a, int G, bool
 // allows (infection if S, recovery if I).
 // Draw classes of the aligned decision path: code = b0 | b1 << 1 | b2 << 2
 // per replicate, with 1, 2, 3 = that many infected in-neighbours, 4 = four
-// or more (threshold from the exact count), 5 = infected with a recovery draw.
-// The table maps a code to its threshold (0 for codes that never fire here).
+// or more (threshold from the exact count), 5 = infected with a recovery
+// draw, 6 = latent (SEIR / SEIS) with an E -> I draw.  The table maps a code
+// to its threshold (0 for codes that never fire here).
 constexpr int kCodeTable = 8;
 
 __device__ __forceinline__ uint32_t code_threshold(const StepArgs &a, int code)
@@ -227,6 +228,7 @@ __device__ __forceinline__ uint32_t code_threshold(const StepArgs &a, int code)
     switch (code) {
     case 1: case 2: case 3: return a.tinf[code < a.khat ? code : a.khat];
     case 5: return a.trec;
+    case 6: return a.talpha;
     default: return 0u;
     }
 }
@@ -239,15 +241,16 @@ __device__ __forceinline__ uint32_t spread4(uint32_t n, uint32_t mul, uint32_t m
 
 template <int LC>
 __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool valid, int v,
-                                           int w, int64_t idx, uint64_t h, uint64_t r,
+                                           int w, int64_t idx, uint64_t h, uint64_t r, uint64_t e,
                                            uint64_t sus, const uint64_t (&c)[LC], int s,
                                            uint64_t share, const uint32_t *tl, int tl_n,
                                            const uint32_t *tcode, bool &any)
 {
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
     const bool draw_rec = a.trec != 0u && a.trec != kAlways;
-    const uint32_t trec = a.trec;
-    uint64_t inf = 0, rec = 0;
+    const bool draw_lat = a.talpha != 0u && a.talpha != kAlways;
+    const uint32_t trec = a.trec, tlat = a.talpha;
+    uint64_t inf = 0, rec = 0, act = 0;  // S -> I or E, I -> R or S, E -> I
     if (tcode != nullptr && (a.goff & 3u) == 0u) {
         // generator blocks are nibbles of the word: one draw per block with
         // any replicate that needs one, the class of each replicate read from
@@ -266,10 +269,11 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
         always &= ninf;
         const uint64_t ndraw = ninf & ~always;
         const uint64_t nrec = draw_rec ? (h & share) : 0ull;
+        const uint64_t nlat = draw_lat ? (e & share) : 0ull;
         const uint64_t B0 = (ndraw & c0 & ~rest) | nrec;
-        const uint64_t B1 = ndraw & c1 & ~rest;
-        const uint64_t B2 = (ndraw & rest) | nrec;
-        uint64_t need = ndraw | nrec;
+        const uint64_t B1 = (ndraw & c1 & ~rest) | nlat;
+        const uint64_t B2 = (ndraw & rest) | nrec | nlat;
+        uint64_t need = ndraw | nrec | nlat;
         uint64_t fire = 0;
         const uint32_t blk0 = (uint32_t)(gbase >> 2);
         while (need) {
@@ -296,7 +300,7 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
             f = f + f + ((o.z < q2) ? 1u : 0u);
             f = f + f + ((o.y < q1) ? 1u : 0u);
             f = f + f + ((o.x < q0) ? 1u : 0u);
-            const uint32_t nb = n2 & ~n0;  // four or more infected neighbours
+            const uint32_t nb = n2 & ~n0 & ~n1;  // code 4: four or more infected neighbours
             if (nb) {
                 const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
@@ -307,11 +311,13 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
             }
             fire |= (uint64_t)f << gs;
         }
-        inf = (fire & ~h) | always;
+        inf = (fire & ~h & ~e) | always;
         rec = fire & h;
+        act = fire & e;
     } else {
         uint64_t need = sus & bs_nonzero<LC>(c);
         if (draw_rec) need |= h;
+        if (draw_lat) need |= e;
         need &= share;
         const SmallCounts sm = bs_small<LC>(c);
         const uint64_t big = sus & ~(sm.m1 | sm.m2 | sm.m3) & bs_nonzero<LC>(c);  // k >= 4
@@ -325,7 +331,7 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
             need &= ~nibble_to_word(0xFu, gs);
             const U4 o = philox10((uint32_t)v, blk, a.step, kDomNodeStep << 24, a.key0, a.key1);
             const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
-            const uint32_t nh = nibble_at(h, gs), n1 = nibble_at(sm.m1, gs),
+            const uint32_t nh = nibble_at(h, gs), ne = nibble_at(e, gs), n1 = nibble_at(sm.m1, gs),
                            n2 = nibble_at(sm.m2, gs), n3 = nibble_at(sm.m3, gs),
                            nb = nibble_at(big, gs);
             uint32_t tb[4] = {0u, 0u, 0u, 0u};
@@ -334,25 +340,38 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
                 for (int j = 0; j < 4; ++j)
                     if ((nb >> j) & 1u) tb[j] = tinf_at(a, tl, tl_n, bs_get<LC>(c, gs + j));
             }
-            uint32_t fi = 0, fr = 0;
+            uint32_t fi = 0, fr = 0, fe = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const bool isI = (nh >> j) & 1u;
+                const bool isI = (nh >> j) & 1u, isE = (ne >> j) & 1u;
                 uint32_t t = ((n1 >> j) & 1u) ? t1
                                               : (((n2 >> j) & 1u) ? t2 : (((n3 >> j) & 1u) ? t3 : tb[j]));
-                t = isI ? trec : t;
+                t = isI ? trec : (isE ? tlat : t);
                 const uint32_t f = (((nn >> j) & 1u) && fires(ou[j], t)) ? 1u : 0u;
-                fi |= (isI ? 0u : f) << j;
+                fi |= ((isI || isE) ? 0u : f) << j;
                 fr |= (isI ? f : 0u) << j;
+                fe |= (isE ? f : 0u) << j;
             }
             inf |= nibble_to_word(fi, gs);
             rec |= nibble_to_word(fr, gs);
+            act |= nibble_to_word(fe, gs);
         }
     }
     inf = or_reduce_lanes(inf, G, S);
     rec = or_reduce_lanes(rec, G, S);
+    act = or_reduce_lanes(act, G, S);
     if (a.trec == kAlways) rec = h;
+    if (a.talpha == kAlways) act = e;
     if (!valid || s != 0) return;
+    if (a.lat) {  // SEIR / SEIS: infection leads to E, E -> I
+        const uint64_t nh = (h & ~rec) | act;
+        const uint64_t ne = (e & ~act) | inf;
+        a.next[idx] = nh;
+        a.lat[idx] = ne;
+        if (a.model == kSEIR) a.aux[idx] = r | rec;
+        any |= (nh | ne) != 0;
+        return;
+    }
     const uint64_t nh = (h & ~rec) | inf;
     const uint64_t nr = (a.model == kSIS) ? r : (r | rec);
     a.next[idx] = nh;
@@ -369,7 +388,8 @@ __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bo
     const int64_t idx = (int64_t)v * a.W + w;
     const uint64_t h = valid ? a.prev[idx] : 0ull;
     const uint64_t r = valid ? a.aux[idx] : 0ull;
-    const uint64_t sus = valid ? (~(h | r) & tail_mask(w, a.B)) : 0ull;
+    const uint64_t e = (valid && a.lat) ? a.lat[idx] : 0ull;
+    const uint64_t sus = valid ? (~(h | r | e) & tail_mask(w, a.B)) : 0ull;
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
@@ -385,7 +405,7 @@ __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bo
         }
         return;
     }
-    epi_decide<L>(a, G, S, valid, v, w, idx, h, r, sus, c, s, share, tl, tl_n, tcode, any);
+    epi_decide<L>(a, G, S, valid, v, w, idx, h, r, e, sus, c, s, share, tl, tl_n, tcode, any);
 }
 
 // ---------------------------------------------------------------- LT ----
@@ -659,10 +679,11 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
             if (KIND == kKindEpidemic) {
                 const uint64_t h = valid ? a.prev[idx] : 0ull;
                 const uint64_t r = valid ? a.aux[idx] : 0ull;
-                const uint64_t sus = valid ? (~(h | r) & tail_mask(ww, a.B)) : 0ull;
+                const uint64_t e = (valid && a.lat) ? a.lat[idx] : 0ull;
+                const uint64_t sus = valid ? (~(h | r | e) & tail_mask(ww, a.B)) : 0ull;
 #pragma unroll
                 for (int l = 0; l < LC; ++l) c[l] &= sus;
-                epi_decide<LC>(a, G, 1, valid, v, ww, idx, h, r, sus, c, 0, ~0ull, nullptr, 0,
+                epi_decide<LC>(a, G, 1, valid, v, ww, idx, h, r, e, sus, c, 0, ~0ull, nullptr, 0,
                                tcode, any);
             } else {
                 const uint64_t act_w = valid ? a.prev[idx] : 0ull;
@@ -1020,8 +1041,12 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
             const bool live = !f.bm || ((f.bm[v >> 5] >> (v & 31)) & 1u);
             const uint64_t one = live ? (f.one[idx] & tail) : 0ull;
             const uint64_t two = f.two ? (f.two[idx] & tail) : 0ull;
-            cnt += (uint32_t)__popcll(f.model == kSIS ? one : (one | two));
+            const uint64_t three = f.three ? (f.three[idx] & tail) : 0ull;
+            cnt += (uint32_t)__popcll(f.model == kSIS ? one : (one | two | three));
             if (!f.states) continue;
+            // state codes: with a latent plane E 1, I 2, R 3 (the planes are
+            // disjoint); else 1 for the first plane, 2 for the second only
+            const uint32_t m1 = f.three ? 2u : 1u, m2 = f.three ? 3u : 2u;
             uint8_t *dst = f.states + v * f.B + 64ll * w;
             const int64_t nb = f.B - 64ll * w < 64 ? f.B - 64ll * w : 64;
             if (nb == 64 && (f.B & 15) == 0) {
@@ -1036,8 +1061,9 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
                         for (int j = 0; j < 4; ++j) {
                             const int bit = q * 16 + k * 4 + j;
                             const uint32_t s1 = (uint32_t)(one >> bit) & 1u;
-                            const uint32_t s2 = (uint32_t)(two >> bit) & 1u;
-                            x |= (s1 | ((s2 & ~s1) << 1)) << (8 * j);
+                            const uint32_t s2 = (uint32_t)(two >> bit) & 1u & ~s1;
+                            const uint32_t s3 = (uint32_t)(three >> bit) & 1u;
+                            x |= (s1 * m1 + s2 * m2 + s3) << (8 * j);
                         }
                         wd[k] = x;
                     }
@@ -1046,8 +1072,9 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
             } else {
                 for (int j = 0; j < nb; ++j) {
                     const uint32_t s1 = (uint32_t)(one >> j) & 1u;
-                    const uint32_t s2 = (uint32_t)(two >> j) & 1u;
-                    dst[j] = (uint8_t)(s1 | ((s2 & ~s1) << 1));
+                    const uint32_t s2 = (uint32_t)(two >> j) & 1u & ~s1;
+                    const uint32_t s3 = (uint32_t)(three >> j) & 1u;
+                    dst[j] = (uint8_t)(s1 * m1 + s2 * m2 + s3);
                 }
             }
         }
@@ -1062,10 +1089,10 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
 __global__ void __launch_bounds__(256) k_tally(FinArgs f)
 {
     if (f.flags && f.step > 1u && f.flags[(f.step - 1u) % (uint32_t)f.ring] == 0u) {
-        if (blockIdx.x == 0 && threadIdx.x < 2) f.tally[threadIdx.x] = f.tally[(int)threadIdx.x - 2];
+        if (blockIdx.x == 0 && threadIdx.x < 3) f.tally[threadIdx.x] = f.tally[(int)threadIdx.x - 3];
         return;
     }
-    unsigned long long c1 = 0, c2 = 0;
+    unsigned long long c1 = 0, c2 = 0, c3 = 0;
     const int64_t words = (int64_t)f.n * f.W;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -1075,22 +1102,31 @@ __global__ void __launch_bounds__(256) k_tally(FinArgs f)
         const bool live = !f.bm || ((f.bm[v >> 5] >> (v & 31)) & 1u);
         const uint64_t one = live ? (f.one[i] & tail) : 0ull;
         const uint64_t two = f.two ? (f.two[i] & tail & ~one) : 0ull;
-        c1 += (unsigned long long)__popcll(one);
-        c2 += (unsigned long long)__popcll(two);
+        const uint64_t three = f.three ? (f.three[i] & tail) : 0ull;
+        if (f.three) {  // E 1, I 2, R 3
+            c1 += (unsigned long long)__popcll(three);
+            c2 += (unsigned long long)__popcll(one);
+            c3 += (unsigned long long)__popcll(two);
+        } else {
+            c1 += (unsigned long long)__popcll(one);
+            c2 += (unsigned long long)__popcll(two);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         c1 += __shfl_xor(c1, off, 64);
         c2 += __shfl_xor(c2, off, 64);
+        c3 += __shfl_xor(c3, off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         if (c1) atomicAdd(&f.tally[0], c1);
         if (c2) atomicAdd(&f.tally[1], c2);
+        if (c3) atomicAdd(&f.tally[2], c3);
     }
 }
 
 __global__ void k_tally_clear(unsigned long long *t)
 {
-    if (threadIdx.x < 2) t[threadIdx.x] = 0ull;
+    if (threadIdx.x < 3) t[threadIdx.x] = 0ull;
 }
 
 __global__ void k_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,

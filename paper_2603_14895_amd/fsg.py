@@ -17,9 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfsg.so")
 
 FSG_OK, FSG_EINVAL, FSG_ENOMEM, FSG_EDEVICE, FSG_EUNSUPPORTED, FSG_EWORKSPACE = 0, -1, -2, -3, -4, -5
-FSG_IC, FSG_SI, FSG_SIS, FSG_SIR, FSG_LT = 0, 1, 2, 3, 4
+FSG_IC, FSG_SI, FSG_SIS, FSG_SIR, FSG_LT, FSG_SEIR, FSG_SEIS = 0, 1, 2, 3, 4, 5, 6
 FSG_IC_UNIFORM, FSG_IC_WEIGHTED_CASCADE, FSG_IC_PER_EDGE = 0, 1, 2
-MODELS = {"ic": FSG_IC, "si": FSG_SI, "sis": FSG_SIS, "sir": FSG_SIR, "lt": FSG_LT}
+MODELS = {"ic": FSG_IC, "si": FSG_SI, "sis": FSG_SIS, "sir": FSG_SIR, "lt": FSG_LT,
+          "seir": FSG_SEIR, "seis": FSG_SEIS}
 IC_PROBS = {"uniform": FSG_IC_UNIFORM, "weighted_cascade": FSG_IC_WEIGHTED_CASCADE,
             "per_edge": FSG_IC_PER_EDGE}
 
@@ -33,7 +34,8 @@ class FsgError(RuntimeError):
 class fsg_params(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("ic_prob", ctypes.c_int32), ("p", ctypes.c_double),
                 ("edge_p", ctypes.c_void_p), ("beta", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+                ("gamma", ctypes.c_double), ("max_steps", ctypes.c_int64),
+                ("alpha", ctypes.c_double)]
 
 
 class fsg_run_info(ctypes.Structure):
@@ -298,7 +300,7 @@ def _ws(nbytes: int, device):
 
 
 def make_params(model, *, p=0.0, ic_prob="uniform", edge_p=None, beta=0.0, gamma=0.0,
-                max_steps=-1):
+                max_steps=-1, alpha=0.0):
     prm = fsg_params()
     prm.model = MODELS[model] if isinstance(model, str) else int(model)
     prm.ic_prob = IC_PROBS[ic_prob] if isinstance(ic_prob, str) else int(ic_prob)
@@ -306,6 +308,7 @@ def make_params(model, *, p=0.0, ic_prob="uniform", edge_p=None, beta=0.0, gamma
     prm.beta = float(beta)
     prm.gamma = float(gamma)
     prm.max_steps = int(max_steps)
+    prm.alpha = float(alpha)
     keep = None
     if edge_p is not None:
         keep = np.ascontiguousarray(edge_p, dtype=np.float64)
@@ -405,10 +408,10 @@ class Session:
         self._torch = torch
 
     def step(self, n_steps: int = 1, tally: bool = False, stream=None):
-        """Advances up to n_steps; returns (fsg_run_info, tally [n_steps, 2] uint64
-        numpy array or None)."""
+        """Advances up to n_steps; returns (fsg_run_info, tally [n_steps, 3] uint64
+        numpy array -- pairs in states 1, 2, 3 after each step -- or None)."""
         torch = self._torch
-        out = torch.zeros((max(1, int(n_steps)), 2), dtype=torch.int64,
+        out = torch.zeros((max(1, int(n_steps)), 3), dtype=torch.int64,
                           device=self.graph.device) if tally else None
         info = fsg_run_info()
         _check(lib().fsg_session_step(self.handle, int(n_steps),
@@ -418,12 +421,12 @@ class Session:
 
     def read(self, want_states: bool = True, stream=None):
         """Current (states [n,B] uint8 tensor or None, counts [n] int32 tensor,
-        tally (state-1 pairs, state-2 pairs))."""
+        tally (pairs in states 1, 2, 3))."""
         torch = self._torch
         st = (torch.empty((self.graph.n, self.B), dtype=torch.uint8, device=self.graph.device)
               if want_states else None)
         cnt = torch.empty(self.graph.n, dtype=torch.int32, device=self.graph.device)
-        t = torch.zeros(2, dtype=torch.int64, device=self.graph.device)
+        t = torch.zeros(3, dtype=torch.int64, device=self.graph.device)
         _check(lib().fsg_session_read(self.handle, st.data_ptr() if st is not None else None,
                                       cnt.data_ptr(), t.data_ptr(), _stream_ptr(stream)))
         return st, cnt, tuple(int(x) for x in t.cpu().tolist())
@@ -469,7 +472,7 @@ class Batch:
     Each job is a dict: graph (DeviceGraph), model, seeds, B, rng_key and
     model parameters, optionally replicate_offset and schedule."""
 
-    PARAM_KEYS = ("p", "ic_prob", "edge_p", "beta", "gamma", "max_steps")
+    PARAM_KEYS = ("p", "ic_prob", "edge_p", "beta", "gamma", "max_steps", "alpha")
 
     def __init__(self, jobs, steps_per_sync=16, want_states=True, want_counts=True):
         import torch

@@ -29,7 +29,8 @@ def test_header_symbols_exported():
         assert hasattr(lib, name), name
     # the binding wraps every declared call
     assert set(names) <= set(fsg.exported_names())
-    assert fsg.fsg_abi_version() == 1
+    want = int(re.search(r"#define FSG_ABI_VERSION (\d+)", open(HEADER).read()).group(1))
+    assert fsg.fsg_abi_version() == want
 
 
 def _graph(n=50, seed=1):

@@ -21,7 +21,8 @@ def _cuda():
 
 
 def _params(j):
-    return {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps", "edge_p") if k in j}
+    return {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "alpha", "max_steps", "edge_p")
+            if k in j}
 
 
 def _mixed_jobs():
@@ -39,6 +40,9 @@ def _mixed_jobs():
         ("lt", 3000, 18.0, 1, 0, dict(max_steps=-1), dict(heavy_threshold=12)),
         ("ic", 1000, 10.0, 5, 0, dict(p=0.1, max_steps=2), None),
         ("sir", 800, 8.0, 64, 0, dict(beta=0.3, gamma=0.3, max_steps=0), None),
+        ("seir", 2400, 14.0, 700, 0, dict(beta=0.04, alpha=0.3, gamma=0.1, max_steps=35), None),
+        ("seis", 1700, 9.0, 90, 1, dict(beta=0.08, alpha=0.4, gamma=0.25, max_steps=20),
+         dict(heavy_threshold=25)),
     ]
     jobs = []
     for i, (model, n, deg, B, off, prm, sched) in enumerate(specs):

@@ -82,6 +82,30 @@ def test_epidemics(model, B):
           replicate_offset=2 if B == 100 else 0)
 
 
+@pytest.mark.parametrize("model", ["seir", "seis"])
+@pytest.mark.parametrize("B,offset", [(1024, 0), (100, 2), (300, 0)])
+def test_latent_epidemics(model, B, offset):
+    """SEIR / SEIS: the aligned decision path (offset 0) and the general one
+    (offset 2), one word per row and sixteen."""
+    gr = W.chung_lu(3000, 20.0, 2.5, 45)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 30, 46)
+    _both(gnp, model, seeds, B, 0x5E1A + B, model, beta=0.03, alpha=0.25, gamma=0.1,
+          max_steps=50, replicate_offset=offset)
+
+
+@pytest.mark.parametrize("model", ["seir", "seis"])
+def test_latent_always_and_never(model):
+    """alpha = 1 (every latent node turns infectious next step, no draw) and
+    alpha = 0 (latent forever), beta = 1."""
+    gr = W.chung_lu(800, 8.0, 2.5, 47)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 4, 48)
+    for alpha, beta in ((1.0, 0.2), (0.0, 1.0), (0.5, 1.0)):
+        _both(gnp, model, seeds, 192, 0x5E1B, f"{model} alpha={alpha}", beta=beta,
+              alpha=alpha, gamma=0.3, max_steps=20)
+
+
 @pytest.mark.parametrize("B", [200, 64])
 def test_lt(B):
     gr = W.chung_lu(5000, 10.0, 2.5, 51)
@@ -90,7 +114,7 @@ def test_lt(B):
     _both(gnp, "lt", seeds, B, 0x17 + B, "lt", max_steps=-1, replicate_offset=1)
 
 
-@pytest.mark.parametrize("model", ["ic", "sir", "lt", "sis"])
+@pytest.mark.parametrize("model", ["ic", "sir", "lt", "sis", "seir"])
 @pytest.mark.parametrize("sched", [
     dict(row_lanes=1, block_threads=64, tile_edges=64, heavy_threshold=16),
     dict(row_lanes=4, block_threads=1024, tile_edges=100000, heavy_threshold=40),
@@ -105,7 +129,7 @@ def test_schedules_and_heavy_rows(model, sched):
     seeds = W.uniform_seeds(gr.n, 10, 62)
     K = -1 if model in ("ic", "lt") else 25
     _both(gnp, model, seeds, 300, 0xAB, f"sched-{sched}", p=0.1, beta=0.05, gamma=0.2,
-          max_steps=K, schedule=sched, replicate_offset=9)
+          alpha=0.3, max_steps=K, schedule=sched, replicate_offset=9)
 
 
 def test_edge_cases():
@@ -113,10 +137,10 @@ def test_edge_cases():
     edges = [(0, 1), (0, 1), (1, 1), (1, 2), (2, 3), (3, 1), (5, 5)] + [(i, 6) for i in range(7, 40)]
     gr = W.from_edges(45, edges)
     gnp = gr.numpy()
-    for model in ["ic", "sir", "si", "sis", "lt"]:
+    for model in ["ic", "sir", "si", "sis", "lt", "seir", "seis"]:
         for seeds, K in [([0, 7, 8, 0], 12), ([], 12), ([0, 3], 0), ([44], 5)]:
             for B in (1, 63, 65, 128):
-                kw = dict(p=0.5, beta=0.4, gamma=0.3, max_steps=K)
+                kw = dict(p=0.5, beta=0.4, gamma=0.3, alpha=0.6, max_steps=K)
                 if model in ("ic", "lt") and K == 12:
                     kw["max_steps"] = -1
                 _both(gnp, model, np.array(seeds, dtype=np.int32), B, 99 + B, f"edge-{model}",
@@ -132,6 +156,8 @@ def test_edge_cases():
     _both(gnp, "ic", np.array([3], dtype=np.int32), 77, 1, "p1", p=1.0, max_steps=-1)
     _both(gnp, "sir", np.array([3], dtype=np.int32), 77, 2, "beta1", beta=1.0, gamma=1.0,
           max_steps=20)
+    _both(gnp, "seir", np.array([3], dtype=np.int32), 77, 3, "seir-all-1", beta=1.0, alpha=1.0,
+          gamma=1.0, max_steps=20)
 
 
 def test_replicate_split_and_repeat_invariance():

@@ -26,6 +26,7 @@ CASES = [
     ("lt", 2000, 10.0, 300, 0, dict(max_steps=-1), None),
     ("sir", 1800, 15.0, 256, 0, dict(beta=0.05, gamma=0.2, max_steps=25),
      dict(heavy_threshold=20, row_lanes=4)),
+    ("seir", 2000, 12.0, 512, 0, dict(beta=0.05, alpha=0.3, gamma=0.15, max_steps=40), None),
 ]
 
 
@@ -59,7 +60,7 @@ def test_session_resume_is_exact(case):
     assert_same(got, whole, f"case {case} stepped vs one call")
 
 
-@pytest.mark.parametrize("case", [0, 2, 4])
+@pytest.mark.parametrize("case", [0, 2, 4, 6])
 def test_session_tallies_match_oracle(case):
     """Tally after each step == (#state-1, #state-2) of the oracle's states at
     that step (the oracle run with max_steps = t)."""
@@ -73,17 +74,20 @@ def test_session_tallies_match_oracle(case):
     T = 12
     g = fsg.DeviceGraph(*gnp)
     p = dict(prm)
-    p["max_steps"] = T if model != "lt" and model != "ic" else -1
+    p["max_steps"] = T if model not in ("lt", "ic") else -1
     ss = fsg.Session(g, model, seeds, B, key, replicate_offset=off, **p)
     _, _, t0 = ss.read(want_states=False)
-    assert t0 == (len(np.unique(seeds)) * B, 0)  # step 0: the seeds, in state 1 everywhere
+    seed_state = 2 if model in ("seir", "seis") else 1  # step 0: the seeds, infectious
+    want0 = [0, 0, 0]
+    want0[seed_state - 1] = len(np.unique(seeds)) * B
+    assert t0 == tuple(want0)
     info, tal = ss.step(T, tally=True)
     ss.close()
     for t in range(1, T + 1):
         q = dict(prm)
         q["max_steps"] = t
         rs, _, rsteps, _ = oracle_run(gnp, model, seeds, B, key, replicate_offset=off, **q)
-        want = (int((rs == 1).sum()), int((rs == 2).sum()))
+        want = (int((rs == 1).sum()), int((rs == 2).sum()), int((rs == 3).sum()))
         assert tuple(int(x) for x in tal[t - 1]) == want, (t, tal[t - 1], want, rsteps)
     log(f"[session] {model}: tallies of {T} steps match the oracle "
         f"(steps run {int(info.steps_run)}, absorbed {int(info.absorbed)})")
