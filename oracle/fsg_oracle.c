@@ -26,7 +26,10 @@
  *     whichever transition the node's state allows, as for SIR;
  *   - independent cascade (Table tab:29s; Kempe et al. cited in Sec. 2): every
  *     newly active node gets one chance per out-arc to activate its target;
- *   - linear threshold with in-weights 1/indeg and U(0,1) thresholds.
+ *   - linear threshold with in-weights 1/indeg and U(0,1) thresholds;
+ *   - the Hegselmann-Krause opinion model as the micro-implementation of
+ *     Appendix A.2 (strict |h_i - h_j| < eps; a node with no eps-neighbour
+ *     keeps its opinion), in FP32 with the in-arcs summed in CSR order.
  *
  * Randomness is passed in as a fixed counter-based generator so the result is
  * a deterministic function of the inputs:
@@ -462,4 +465,63 @@ void orc_draw_many(uint64_t rng_key, uint32_t dom, const uint64_t *unit, const u
                    const uint32_t *step, int64_t count, uint32_t *out)
 {
     for (int64_t i = 0; i < count; ++i) out[i] = orc_draw(rng_key, dom, unit[i], g[i], step[i]);
+}
+
+
+/*
+ * Hegselmann-Krause (Appendix A.2): per replicate r and step, every node i
+ * sums the opinions h_j of the in-neighbours j (arcs j -> i, CSR order, with
+ * multiplicity) with |h_i - h_j| < eps and counts them; the new opinion is
+ * the sum divided by the count, or the old opinion when the count is 0.
+ * FP32 throughout (IEEE single, round to nearest), no contraction.
+ * h: [n][B] row-major, initial opinions on entry, final ones on return.
+ * The loop stops after max_steps steps or after a step that changed no
+ * opinion in any replicate; *steps_run counts the steps executed (the last,
+ * unchanged one included), *converged = 1 iff it stopped on no change.
+ */
+int orc_hk(float eps, int64_t max_steps, int64_t n, const int64_t *ptr, const int32_t *src,
+           int64_t B, float *h, int64_t *steps_run, int32_t *converged, int nthreads)
+{
+    if (n < 1 || B < 0 || max_steps < 0) return -1;
+    float *x = (float *)malloc((size_t)n * (size_t)B * sizeof(float));
+    float *y = (float *)malloc((size_t)n * (size_t)B * sizeof(float));
+    memcpy(x, h, (size_t)n * (size_t)B * sizeof(float));
+    int64_t t = 0;
+    int changed = 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    while (t < max_steps && changed) {
+        ++t;
+        changed = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(| : changed)
+#endif
+        for (int64_t r = 0; r < B; ++r) {
+            for (int64_t v = 0; v < n; ++v) {
+                const float hv = x[v * B + r];
+                float mc = 0.0f;
+                int64_t mv = 0;
+                for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e) {
+                    const float hj = x[(int64_t)src[e] * B + r];
+                    if (fabsf(hv - hj) < eps) {
+                        mc += hj;
+                        ++mv;
+                    }
+                }
+                const float nv = mv > 0 ? mc / (float)mv : hv;
+                y[v * B + r] = nv;
+                if (nv != hv) changed = 1;
+            }
+        }
+        float *tmp = x;
+        x = y;
+        y = tmp;
+    }
+    memcpy(h, x, (size_t)n * (size_t)B * sizeof(float));
+    free(x);
+    free(y);
+    if (steps_run) *steps_run = t;
+    if (converged) *converged = !changed;
+    return 0;
 }

@@ -69,6 +69,11 @@ def _load():
             ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), ctypes.c_int]
         lib.orc_ic_live_edge.restype = ctypes.c_int
+        lib.orc_hk.argtypes = [ctypes.c_float, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.c_int]
+        lib.orc_hk.restype = ctypes.c_int
         lib.orc_set_verbose.argtypes = [ctypes.c_int]
         lib.orc_set_verbose.restype = None
         _lib = lib
@@ -165,3 +170,21 @@ def ic_live_edge(ptr, src, seeds, B, rng_key, *, p=0.0, ic_prob=IC_UNIFORM, edge
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return states, counts, dist, int(steps.value), int(absorbed.value)
+
+
+def hk(ptr, src, h0, eps, max_steps, nthreads=0):
+    """Hegselmann-Krause from opinions h0 [n, B] (float32).  Returns (h [n, B]
+    float32, steps_run, converged)."""
+    lib = _load()
+    ptr, src = _csr(ptr, src)
+    n = ptr.size - 1
+    h = np.ascontiguousarray(h0, dtype=np.float32).copy()
+    assert h.shape[0] == n
+    B = h.shape[1]
+    steps = ctypes.c_int64(0)
+    conv = ctypes.c_int32(0)
+    rc = lib.orc_hk(float(np.float32(eps)), int(max_steps), n, _ptr(ptr), _ptr(src), B, _ptr(h),
+                    ctypes.byref(steps), ctypes.byref(conv), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return h, int(steps.value), int(conv.value)

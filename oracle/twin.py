@@ -123,3 +123,36 @@ def simulate(model, ptr, src, seeds, B, rng_key, *, p=0.0, ic_prob=0, edge_p=Non
             states[v][r] = out
             counts[v] += int(x[v] == 1) if model == SIS else int(x[v] != 0)
     return states, counts, steps_run, int(not any_one)
+
+
+def hk(ptr, src, h0, eps, max_steps):
+    """Hegselmann-Krause (Appendix A.2) on IEEE single scalars: h0 is a list
+    of B-long lists of floats (node-major); returns (h, steps_run,
+    converged) like the C oracle."""
+    import numpy as np
+    f32 = np.float32
+    e = f32(eps)
+    n = len(ptr) - 1
+    x = [[f32(v) for v in row] for row in h0]
+    B = len(x[0]) if n else 0
+    t, changed = 0, True
+    while t < max_steps and changed:
+        t += 1
+        changed = False
+        y = []
+        for v in range(n):
+            row = []
+            for r in range(B):
+                hv = x[v][r]
+                num, cnt = f32(0.0), 0
+                for k in range(ptr[v], ptr[v + 1]):
+                    hj = x[src[k]][r]
+                    if abs(f32(hv - hj)) < e:
+                        num = f32(num + hj)
+                        cnt += 1
+                new = f32(num / f32(cnt)) if cnt else hv
+                changed |= bool(new != hv)
+                row.append(new)
+            y.append(row)
+        x = y
+    return x, t, int(not changed)

@@ -188,6 +188,13 @@ def uniform_seeds(n: int, k: int, seed: int) -> np.ndarray:
     return torch.randperm(n, generator=g)[:k].to(torch.int32).numpy()
 
 
+def uniform_opinions(n: int, B: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Initial opinions of the Hegselmann-Krause model: float32 [n, B], each
+    independent and uniform on [lo, hi) (the opinion interval is [-1, 1])."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(n, B)).astype(np.float32)
+
+
 def top_indegree_seeds(graph: Graph, k: int) -> np.ndarray:
     """Degree-centrality seeds as in the paper's usage example (Listing 1):
     the k nodes of largest in-degree; ties broken by node id."""

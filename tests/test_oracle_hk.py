@@ -1,0 +1,138 @@
+"""Pins of the oracle's Hegselmann-Krause update (Appendix A.2: strict
+|h_i - h_j| < eps over the in-neighbours, their mean, no eps-neighbour keeps
+the opinion) against closed forms, special cases and invariants, and against
+the pure-Python twin on tiny graphs."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import twin
+from paper_2603_14895_amd import workloads as W
+
+F = np.float32
+
+
+def _run(edges, n, h0, eps, K):
+    ptr, src = W.from_edges(n, edges).numpy()
+    h0 = np.asarray(h0, dtype=np.float32)
+    if h0.ndim == 1:
+        h0 = h0[:, None]
+    return oracle.hk(ptr, src, h0, eps, K)
+
+
+def test_complete_digraph_one_step_closed_form():
+    """Complete digraph without self-loops, eps above every gap: each node
+    moves to the mean of the other n-1 opinions, (S - h_i) / (n - 1)."""
+    n = 9
+    rng = np.random.default_rng(5)
+    h0 = rng.uniform(-1, 1, n).astype(np.float32)
+    edges = [(j, i) for i in range(n) for j in range(n) if i != j]
+    h, steps, conv = _run(edges, n, h0, 2.5, 1)
+    S = float(h0.astype(np.float64).sum())
+    want = (S - h0.astype(np.float64)) / (n - 1)
+    assert steps == 1 and conv == 0
+    assert np.max(np.abs(h[:, 0] - want)) < 1e-6
+
+
+def test_eps_zero_and_isolated_nodes_keep_their_opinion():
+    n = 6
+    h0 = np.linspace(-0.9, 0.8, n).astype(np.float32)
+    edges = [(j, i) for i in range(4) for j in range(4) if i != j]  # 4, 5 isolated
+    h, steps, conv = _run(edges, n, h0, 0.0, 10)
+    assert steps == 1 and conv == 1 and (h[:, 0] == h0).all()
+    h, _, _ = _run(edges, n, h0, 3.0, 1)
+    assert h[4, 0] == h0[4] and h[5, 0] == h0[5]
+    assert (h[:4, 0] != h0[:4]).all()
+
+
+def test_strict_inequality_at_eps():
+    """Two nodes listening to each other at distance exactly eps do not move
+    (the comparison is strict); at the next float above eps they swap every
+    step and never settle."""
+    edges = [(0, 1), (1, 0)]
+    h, steps, conv = _run(edges, 2, [0.25, 0.75], 0.5, 7)
+    assert steps == 1 and conv == 1 and list(h[:, 0]) == [0.25, 0.75]
+    eps_up = float(np.nextafter(F(0.5), F(1.0)))
+    h, steps, conv = _run(edges, 2, [0.25, 0.75], eps_up, 7)
+    assert steps == 7 and conv == 0 and list(h[:, 0]) == [0.75, 0.25]
+    h, _, _ = _run(edges, 2, [0.25, 0.75], eps_up, 6)
+    assert list(h[:, 0]) == [0.25, 0.75]
+
+
+def test_direction_multiplicity_and_eps_filter():
+    """In-star: leaves 1..4 -> centre 0, leaf 1 twice.  Leaves have no
+    in-arcs and keep their opinions; the centre takes the mean over the arcs
+    whose source lies within eps, counting the repeated arc twice."""
+    h0 = [0.0, 0.125, 0.25, -0.375, 0.875]
+    edges = [(1, 0), (2, 0), (1, 0), (3, 0), (4, 0)]
+    h, _, _ = _run(edges, 5, h0, 0.5, 1)
+    assert list(h[1:, 0]) == h0[1:]
+    assert h[0, 0] == F((0.125 + 0.25 + 0.125 - 0.375) / 4)
+    # the transposed graph (centre -> leaves) moves the leaves instead
+    h, _, _ = _run([(v, u) for u, v in edges], 5, h0, 0.5, 1)
+    assert h[0, 0] == 0.0 and h[1, 0] == 0.0 and h[4, 0] == F(0.875)
+
+
+def test_consensus_and_clusters_with_self_loops():
+    """Classic bounded-confidence facts (self-loops give each node its own
+    opinion as in the original model): on a complete graph with eps above
+    the spread, one step reaches the mean and the next changes nothing; two
+    groups further apart than eps settle at their own means."""
+    n = 8
+    h0 = np.array([-0.5, -0.25, 0.0, 0.125, 0.25, 0.375, 0.5, 0.75], np.float32)
+    edges = [(j, i) for i in range(n) for j in range(n)]
+    h, steps, conv = _run(edges, n, h0, 1.5, 20)
+    assert steps == 2 and conv == 1
+    assert (h[:, 0] == F(h0.astype(np.float64).mean())).all()
+    a = np.array([-0.875, -0.75, -0.625, -0.5], np.float32)
+    b = np.array([0.5, 0.625, 0.75, 1.0], np.float32)
+    h0 = np.concatenate([a, b])
+    h, steps, conv = _run(edges, n, h0, 0.6, 20)
+    assert conv == 1
+    assert (h[:4, 0] == F(a.astype(np.float64).mean())).all()
+    assert (h[4:, 0] == F(b.astype(np.float64).mean())).all()
+
+
+def test_opinions_stay_in_the_hull_of_their_neighbours():
+    """Every new opinion is a mean of eps-neighbours' opinions, so it lies
+    between their smallest and largest value; the global range never grows."""
+    gr = W.chung_lu(300, 8.0, 2.5, 77)
+    ptr, src = gr.numpy()
+    h0 = W.uniform_opinions(300, 4, 78)
+    eps = 0.4
+    h1, _, _ = oracle.hk(ptr, src, h0, eps, 1)
+    for r in range(4):
+        for v in range(300):
+            nb = h0[src[ptr[v]:ptr[v + 1]], r]
+            nb = nb[np.abs(h0[v, r] - nb) < F(eps)]
+            if nb.size == 0:
+                assert h1[v, r] == h0[v, r]
+            else:
+                assert nb.min() <= h1[v, r] <= nb.max()
+    hK, _, _ = oracle.hk(ptr, src, h0, eps, 50)
+    assert hK.min() >= h0.min() and hK.max() <= h0.max()
+
+
+def test_replicates_are_independent():
+    gr = W.chung_lu(200, 6.0, 2.5, 31)
+    ptr, src = gr.numpy()
+    h0 = W.uniform_opinions(200, 5, 32)
+    hb, _, _ = oracle.hk(ptr, src, h0, 0.3, 6)
+    for r in range(5):
+        h1, _, _ = oracle.hk(ptr, src, h0[:, r:r + 1], 0.3, 6)
+        assert (h1[:, 0] == hb[:, r]).all()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_twin_matches_c_oracle(seed):
+    rng = np.random.default_rng(900 + seed)
+    n = 12
+    edges = [(int(u), int(v)) for u, v in rng.integers(0, n, size=(40, 2))]
+    gr = W.from_edges(n, edges)
+    ptr, src = gr.numpy()
+    h0 = W.uniform_opinions(n, 3, 950 + seed)
+    for eps, K in ((0.3, 4), (0.8, 30), (2.5, 3)):
+        hc, sc, cc = oracle.hk(ptr, src, h0, eps, K)
+        ht, st, ct = twin.hk(list(ptr), list(src), h0.tolist(), eps, K)
+        assert (hc == np.array(ht, dtype=np.float32)).all()
+        assert (sc, cc) == (st, ct)
