@@ -18,6 +18,8 @@ Workloads (synthetic stand-ins for the paper's datasets):
   c3  64 mixed jobs (Chung-Lu n log-uniform in [1e4, 2e6], mean degree
       U(5, 50); IC p=0.05 / SIR beta 0.03 gamma 0.1 / LT; B log-uniform in
       [64, 4096]; 1-1000 seeds) in one batched, graph-captured launch per step
+  hk  Hegselmann-Krause opinion dynamics on the c2 graph, eps 0.32, B=256
+      uniform [-1, 1] initial opinion vectors, 20 steps (FP32 state)
 """
 from __future__ import annotations
 
@@ -144,7 +146,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "hk"])
     ap.add_argument("--epochs", type=int, default=8, help="surrogate training epochs (c5)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the schedule(s) first with the library autotuner")
@@ -186,6 +188,8 @@ def main():
         return bench_batch(args)
     if args.workload == "c5":
         return bench_surrogate(args)
+    if args.workload == "hk":
+        return bench_hk(args)
     t0 = time.perf_counter()
     c = make_workload(args.workload)
     gr = c["graph"]
@@ -256,6 +260,104 @@ def main():
         "config": {"workload": c["name"], "model": c["model"], "n": int(ptr.size - 1),
                    "nnz": int(src.size), "B": c["B"], "max_steps": c["max_steps"],
                    "steps_run": steps_seen[-1] if steps_seen else 0, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def hk_algorithmic_bytes(n: int, nnz: int, B: int) -> float:
+    """Bytes one Hegselmann-Krause step must move: the B opinions of every
+    arc's source (4 B each), the node's own opinions read and written, the
+    sources (4 B/arc) and row pointers (4 B/row)."""
+    return 4.0 * B * nnz + 8.0 * B * n + 4.0 * nnz + 4.0 * (n + 1)
+
+
+def bench_hk(args):
+    """Hegselmann-Krause opinion dynamics: one bench step = one fsg_hk call
+    (reset to the initial opinions, then up to max_steps synchronous steps)."""
+    import numpy as np
+    import torch
+
+    from paper_2603_14895_amd import fsg
+    from paper_2603_14895_amd import workloads as Wl
+
+    t0 = time.perf_counter()
+    c = Wl.config_hk()
+    ptr, src = c["graph"].numpy()
+    n, B, K, eps = ptr.size - 1, c["B"], c["max_steps"], c["eps"]
+    h0 = Wl.uniform_opinions(n, B, c["opinion_seed"])
+    log(f"[bench] workload {c['name']}: n={n} nnz={src.size} B={B} "
+        f"(generated in {time.perf_counter() - t0:.1f}s)")
+    c["graph"] = None
+    dg = fsg.DeviceGraph(ptr, src, device="cuda:0")
+    sched = json.loads(args.schedule) if args.schedule else {}
+    sched["time_kernels"] = 1
+    sc = fsg.make_schedule(sched)
+    h0d = torch.from_numpy(h0).to("cuda:0")
+    h = torch.empty_like(h0d)
+    counts = torch.empty(B, dtype=torch.int32, device="cuda:0")
+    nb = fsg.fsg_hk_workspace_size(dg.handle, B, sc)
+    ws, addr = fsg._ws(nb, "cuda:0")
+
+    def one():
+        h.copy_(h0d)
+        return fsg.fsg_hk(dg.handle, eps, K, B, h.data_ptr(), sc, addr, nb, 0.5, counts.data_ptr())
+
+    for i in range(args.warmup):
+        info = one()
+        log(f"[bench] warmup {i}: steps_run={info.steps_run} converged={info.absorbed}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    updates, kernel_ms, launches, steps_seen = 0.0, 0.0, 0, []
+    for i in range(args.steps):
+        info = one()
+        updates += float(src.size) * B * info.steps_run
+        kernel_ms += info.step_kernel_ms
+        launches += info.step_launches
+        steps_seen.append(int(info.steps_run))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    value = updates / dt
+    ms_per_step = dt * 1000.0 / args.steps
+    above = float(counts.sum().item()) / n / B
+    log(f"[bench] {args.steps} steps in {dt:.3f}s: {ms_per_step:.2f} ms/step, steps_run={steps_seen}, "
+        f"mean fraction of opinions above 0.5: {above:.4f}")
+    avg_kernel_ms = kernel_ms / max(launches, 1)
+    abytes = hk_algorithmic_bytes(n, src.size, B)
+    achieved = abytes / (avg_kernel_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": measured_traffic("hk"), "kernel": "k_hk_step",
+                "avg_launch_ms": round(avg_kernel_ms, 5), "launches": launches,
+                "algorithmic_bytes_per_launch": abytes}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        R, S = threads, 2
+        hs = np.ascontiguousarray(h0[:, :R])
+        t2 = time.perf_counter()
+        _, st, _ = oracle.hk(ptr, src, hs, eps, S, nthreads=threads)
+        dc = time.perf_counter() - t2
+        if dc < args.cpu_seconds / 2:
+            S = max(S, min(K, int(S * args.cpu_seconds / max(dc, 1e-3))))
+            t2 = time.perf_counter()
+            _, st, _ = oracle.hk(ptr, src, hs, eps, S, nthreads=threads)
+            dc = time.perf_counter() - t2
+        cpu = {"value": src.size * R * st / dc, "unit": "replicate-edge updates/s",
+               "cores": threads, "kind": "oracle",
+               "sample": f"{R} replicates (of B={B}) x {st} steps on the full graph, {dc:.1f} s"}
+        log(f"[bench] cpu baseline {cpu}")
+    del ws
+    out = {
+        "metric": "replicate-edge updates/s", "value": value, "unit": "replicate-edge updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": c["name"], "model": "hk", "n": int(n), "nnz": int(src.size), "B": B,
+                   "eps": eps, "max_steps": K, "steps_run": steps_seen[-1] if steps_seen else 0,
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -237,6 +237,41 @@ int fsg_session_read(fsg_session *s, uint8_t *states, uint32_t *counts, uint64_t
                      void *stream);
 int fsg_session_end(fsg_session *s);
 
+/* ---- Hegselmann-Krause opinion dynamics (Appendix A.2, "Micro-accelerated
+ * implementation of HK model").  Each of B replicates holds one FP32
+ * opinion per node; a synchronous step sends over every arc j -> i the pair
+ * (h_j, 1) if |h_i - h_j| < eps (strict) and (0, 0) otherwise; node i takes
+ * the sum of the first components divided by the sum of the second, and
+ * keeps h_i when that count is 0.  No randomness.
+ * Arithmetic: per (node, replicate) the passing opinions are added in IEEE
+ * single precision in in_src order (one rounding per addition, from +0.0),
+ * then divided once, rounding to nearest even, by the count; results are
+ * bit-reproducible.
+ *
+ * fsg_hk_workspace_size: device bytes fsg_hk needs for (graph, B, sched);
+ * sched may be NULL.
+ * fsg_hk: dev_h (device float [n][B], replicate fastest, 16-byte aligned)
+ * holds the initial opinions on entry and the final ones on return.  The
+ * run stops after max_steps >= 0 steps, or after the first step that
+ * changes no opinion in any replicate (the batch shares one loop).  eps
+ * must be finite and >= 0 (0: nothing ever moves).  sched (may be NULL):
+ * steps_per_sync (steps queued between host polls of the change flags,
+ * default 16, at most 256) and time_kernels are used, the other fields are
+ * ignored.  dev_counts (device uint32 [B], or NULL) receives, per
+ * replicate, the number of nodes whose final opinion exceeds act.  info
+ * (may be NULL): steps_run = steps executed (the unchanged last step
+ * included), absorbed = 1 iff the run stopped on a step with no change,
+ * step_kernel_ms / step_launches as fsg_simulate.  dev_ws: at least
+ * fsg_hk_workspace_size bytes, 256-byte aligned.  Synchronous on stream.
+ * Errors: FSG_EINVAL (graph not bound, B < 1, max_steps < 0, eps negative,
+ * NaN or infinite, act NaN), FSG_EWORKSPACE, FSG_EUNSUPPORTED
+ * (n * B / v >= 2^31 - 256, v = 4 if B % 4 == 0 else 1, or B >= 2^28),
+ * FSG_EDEVICE. */
+int fsg_hk_workspace_size(const fsg_graph *g, int64_t B, const fsg_schedule *sched, size_t *bytes);
+int fsg_hk(const fsg_graph *g, float eps, int64_t max_steps, int64_t B, float *dev_h,
+           const fsg_schedule *sched, void *dev_ws, size_t ws_bytes, float act,
+           uint32_t *dev_counts, fsg_run_info *info, void *stream);
+
 /* ---- Batches: many jobs (graphs, models, seed sets, B) in one launch per
  * synchronous step (Definition "Batched Monte Carlo Method" applied across
  * jobs as well as replicates).  Every launch is a persistent work-queue

@@ -479,6 +479,35 @@ void orc_draw_many(uint64_t rng_key, uint32_t dom, const uint64_t *unit, const u
  * opinion in any replicate; *steps_run counts the steps executed (the last,
  * unchanged one included), *converged = 1 iff it stopped on no change.
  */
+/* New opinion of node v in replicate r from the opinions x [n][B]. */
+static float hk_node(float eps, const int64_t *ptr, const int32_t *src, int64_t B, const float *x,
+                     int64_t v, int64_t r)
+{
+    const float hv = x[v * B + r];
+    float mc = 0.0f;
+    int64_t mv = 0;
+    for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e) {
+        const float hj = x[(int64_t)src[e] * B + r];
+        if (fabsf(hv - hj) < eps) {
+            mc += hj;
+            ++mv;
+        }
+    }
+    return mv > 0 ? mc / (float)mv : hv;
+}
+
+/* One step for the listed rows only: out[i][r] = new opinion of rows[i]. */
+int orc_hk_rows(float eps, int64_t n, const int64_t *ptr, const int32_t *src, int64_t B,
+                const float *x, const int64_t *rows, int64_t n_rows, float *out)
+{
+    if (n < 1 || B < 0) return -1;
+    for (int64_t i = 0; i < n_rows; ++i) {
+        if (rows[i] < 0 || rows[i] >= n) return -1;
+        for (int64_t r = 0; r < B; ++r) out[i * B + r] = hk_node(eps, ptr, src, B, x, rows[i], r);
+    }
+    return 0;
+}
+
 int orc_hk(float eps, int64_t max_steps, int64_t n, const int64_t *ptr, const int32_t *src,
            int64_t B, float *h, int64_t *steps_run, int32_t *converged, int nthreads)
 {
@@ -499,19 +528,9 @@ int orc_hk(float eps, int64_t max_steps, int64_t n, const int64_t *ptr, const in
 #endif
         for (int64_t r = 0; r < B; ++r) {
             for (int64_t v = 0; v < n; ++v) {
-                const float hv = x[v * B + r];
-                float mc = 0.0f;
-                int64_t mv = 0;
-                for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e) {
-                    const float hj = x[(int64_t)src[e] * B + r];
-                    if (fabsf(hv - hj) < eps) {
-                        mc += hj;
-                        ++mv;
-                    }
-                }
-                const float nv = mv > 0 ? mc / (float)mv : hv;
+                const float nv = hk_node(eps, ptr, src, B, x, v, r);
                 y[v * B + r] = nv;
-                if (nv != hv) changed = 1;
+                if (nv != x[v * B + r]) changed = 1;
             }
         }
         float *tmp = x;

@@ -74,6 +74,10 @@ def _load():
                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                ctypes.c_int]
         lib.orc_hk.restype = ctypes.c_int
+        lib.orc_hk_rows.argtypes = [ctypes.c_float, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        lib.orc_hk_rows.restype = ctypes.c_int
         lib.orc_set_verbose.argtypes = [ctypes.c_int]
         lib.orc_set_verbose.restype = None
         _lib = lib
@@ -188,3 +192,20 @@ def hk(ptr, src, h0, eps, max_steps, nthreads=0):
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return h, int(steps.value), int(conv.value)
+
+
+def hk_rows(ptr, src, h, eps, rows):
+    """One Hegselmann-Krause step of the listed rows from opinions h [n, B];
+    returns float32 [len(rows), B]."""
+    lib = _load()
+    ptr, src = _csr(ptr, src)
+    n = ptr.size - 1
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    assert h.shape[0] == n
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((rows.size, h.shape[1]), dtype=np.float32)
+    rc = lib.orc_hk_rows(float(np.float32(eps)), n, _ptr(ptr), _ptr(src), h.shape[1], _ptr(h),
+                         _ptr(rows), rows.size, _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out

@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsg.so")
-SOURCES = ["fsg_kernels.hip", "fsg_abi.hip", "fsg_gnn.hip"]
+SOURCES = ["fsg_kernels.hip", "fsg_abi.hip", "fsg_gnn.hip", "fsg_hk.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

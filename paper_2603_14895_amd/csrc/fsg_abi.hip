@@ -102,7 +102,7 @@ struct fsg_graph {
     int32_t *d_ptr = nullptr;
     int32_t *d_src = nullptr;
     int32_t *d_dst = nullptr;  // target row of every arc (built on the device at bind)
-    std::vector<int32_t> wide;  // rows with more than kWideRow in-arcs
+    std::vector<int32_t> wide;  // rows with more than kWideRow in-arcs, largest first
     int32_t *d_wide = nullptr;
     std::map<std::tuple<int64_t, int64_t, int64_t>, Plan> plans;
 };
@@ -777,6 +777,11 @@ int fsg_graph_create(int64_t n, int64_t nnz, const int64_t *in_ptr, const int32_
         g->ptr.assign(in_ptr, in_ptr + n + 1);
         for (int64_t v = 0; v < n; ++v)
             if (in_ptr[v + 1] - in_ptr[v] > kWideRow) g->wide.push_back((int32_t)v);
+        // largest rows first: kernels that give each wide row its own block
+        // then start the longest ones at the head of the grid
+        std::stable_sort(g->wide.begin(), g->wide.end(), [&](int32_t a, int32_t b) {
+            return in_ptr[a + 1] - in_ptr[a] > in_ptr[b + 1] - in_ptr[b];
+        });
         g->src_host = in_src;
         *out = g;
         return FSG_OK;

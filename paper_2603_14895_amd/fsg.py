@@ -137,6 +137,10 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int32), _VP]),
+    "fsg_hk_workspace_size": (ctypes.c_int, [_VP, _I64, ctypes.POINTER(fsg_schedule),
+                                             ctypes.POINTER(_SZ)]),
+    "fsg_hk": (ctypes.c_int, [_VP, ctypes.c_float, _I64, _I64, _VP, ctypes.POINTER(fsg_schedule),
+                              _VP, _SZ, ctypes.c_float, _VP, ctypes.POINTER(fsg_run_info), _VP]),
     "fsg_autotune_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _I64, _I32,
                                                    ctypes.POINTER(_SZ)]),
     "fsg_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _U64, _I32,
@@ -450,6 +454,42 @@ def simulate(graph: DeviceGraph, model, seeds, B, rng_key, *, replicate_offset=0
     sim = Simulation(graph, model, B, schedule=schedule, want_states=want_states, **params)
     info = sim.run(seeds, rng_key, replicate_offset)
     return sim.states, sim.counts, int(info.steps_run), int(info.absorbed)
+
+
+def fsg_hk_workspace_size(g, B, sched: Optional[fsg_schedule]) -> int:
+    out = _SZ(0)
+    _check(lib().fsg_hk_workspace_size(g, int(B), ctypes.byref(sched) if sched else None,
+                                       ctypes.byref(out)))
+    return out.value
+
+
+def fsg_hk(g, eps, max_steps, B, dev_h, sched, dev_ws, ws_bytes, act, dev_counts,
+           stream=None) -> fsg_run_info:
+    info = fsg_run_info()
+    _check(lib().fsg_hk(g, ctypes.c_float(eps), int(max_steps), int(B), dev_h,
+                        ctypes.byref(sched) if sched else None, dev_ws, ws_bytes,
+                        ctypes.c_float(act), dev_counts, ctypes.byref(info),
+                        stream if stream is not None else _stream_ptr()))
+    return info
+
+
+def hk(graph: DeviceGraph, h0, eps: float, max_steps: int, *, act: float = 0.5,
+       want_counts: bool = True, schedule=None):
+    """Hegselmann-Krause from opinions h0 ([n, B] float32, any device; copied).
+    Returns (h [n, B] float32 cuda tensor, counts [B] int32 tensor of nodes with
+    opinion > act or None, fsg_run_info)."""
+    import torch
+    h = torch.as_tensor(h0, dtype=torch.float32).to(graph.device).contiguous().clone()
+    assert h.dim() == 2 and h.shape[0] == graph.n
+    B = int(h.shape[1])
+    sched = make_schedule(schedule)
+    nb = fsg_hk_workspace_size(graph.handle, B, sched)
+    ws, addr = _ws(nb, graph.device)
+    counts = torch.empty(B, dtype=torch.int32, device=graph.device) if want_counts else None
+    info = fsg_hk(graph.handle, float(eps), int(max_steps), B, h.data_ptr(), sched, addr, nb,
+                  float(act), counts.data_ptr() if counts is not None else None)
+    del ws
+    return h, counts, info
 
 
 def autotune(graph: DeviceGraph, model, seeds, B, rng_key, *, tune_steps=12, batch_only=False,

@@ -236,6 +236,16 @@ def config_c2(device="cpu", n: int = 1_000_000, B: int = 1024, steps: int = 200)
                 max_steps=steps)
 
 
+def config_hk(device="cpu", n: int = 1_000_000, B: int = 256, steps: int = 20):
+    """Hegselmann-Krause on the same Chung-Lu graph as the SIR workload
+    (exponent 2.5, mean degree 20), eps = 0.32 (the paper's HK setting),
+    B = 256 replicates of uniform [-1, 1] initial opinions, 20 steps."""
+    s = BASE_SEED + 2
+    gr = chung_lu(n, 20.0, 2.5, s, device)
+    return dict(name=f"hk_chunglu{n}_eps0.32", graph=gr, model="hk", eps=0.32, B=B,
+                max_steps=steps, opinion_seed=s + 7)
+
+
 def config_c4(device="cpu", scale: int = 26, B: int = 64, edge_factor: int = 16):
     """Web-scale IC: R-MAT (a, b, c) = (0.57, 0.19, 0.19), weighted cascade
     p = 1/indeg(v), 50 uniform seeds, B = 64, to absorption."""

@@ -136,3 +136,12 @@ def test_twin_matches_c_oracle(seed):
         ht, st, ct = twin.hk(list(ptr), list(src), h0.tolist(), eps, K)
         assert (hc == np.array(ht, dtype=np.float32)).all()
         assert (sc, cc) == (st, ct)
+
+
+def test_row_step_equals_whole_step():
+    gr = W.chung_lu(400, 10.0, 2.5, 55)
+    ptr, src = gr.numpy()
+    h0 = W.uniform_opinions(400, 6, 56)
+    h1, _, _ = oracle.hk(ptr, src, h0, 0.32, 1)
+    rows = np.array([0, 5, 399, 17, 5])
+    assert (oracle.hk_rows(ptr, src, h0, 0.32, rows) == h1[rows]).all()
