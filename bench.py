@@ -36,12 +36,21 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the HIP sources; counter records are valid only for it."""
+# HIP sources each workload's dominant kernel is built and launched from
+KERNEL_SOURCES = {
+    "hk": ["fsg_hk.hip", "fsg_internal.hpp"],
+    "c5": ["fsg_gnn.hip", "fsg_internal.hpp"],
+}
+SIM_SOURCES = ["fsg_kernels.hip", "fsg_device.hpp", "fsg_internal.hpp", "fsg_abi.hip"]
+
+
+def kernel_source_hash(workload: str = "c2") -> str:
+    """Hash of the HIP sources behind a workload's kernels; a counter record
+    is valid only for the hash it was taken at."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_14895_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in sorted(KERNEL_SOURCES.get(workload, SIM_SOURCES)):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
@@ -57,7 +66,7 @@ def measured_traffic(workload: str):
             rec = json.load(f).get(workload)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash(workload):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -160,7 +169,7 @@ def main():
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.print_kernel_hash:
-        print(kernel_source_hash())
+        print(json.dumps({w: kernel_source_hash(w) for w in ("c1", "c2", "c3", "c4", "c5", "hk")}))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
