@@ -75,6 +75,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _finite(x):
+    """NaN / infinity -> None, recursively, so the line stays valid JSON."""
+    import math
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    if isinstance(x, dict):
+        return {k: _finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_finite(v) for v in x]
+    return x
+
+
+def emit(out: dict):
+    print(json.dumps(_finite(out), allow_nan=False), flush=True)
+
+
 def algorithmic_bytes_per_step(model: str, n: int, nnz: int, B: int, edge_parallel: bool) -> float:
     """Bytes one pull step must move if every array is touched once per use.
 
@@ -272,7 +288,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def hk_algorithmic_bytes(n: int, nnz: int, B: int) -> float:
@@ -370,7 +386,7 @@ def bench_hk(args):
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def bench_batch(args):
@@ -447,7 +463,7 @@ def bench_batch(args):
                      "algorithmic_bytes_per_launch": abytes / max(1, max(steps_run))},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def bench_surrogate(args):
@@ -575,7 +591,7 @@ def bench_surrogate(args):
         "roofline": None, "cpu_baseline": None,
     }
     log(f"[bench] c5 done in {time.perf_counter() - t0:.1f}s")
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def cpu_baseline_batch(specs, jobs, host, target_seconds):
