@@ -752,7 +752,7 @@ __global__ void __launch_bounds__(1024) k_ic_stream(StepArgs a)
     const int64_t nnz = a.nnz;
     // pass: chunk c of thread t covers arcs base + c*stride .. +3
     const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-    constexpr int kChunks = 4;
+    constexpr int kChunks = 8;  // 32 arcs in flight per thread and pass
     bool any = false;
     for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; base < nnz;
          base += stride * kChunks) {

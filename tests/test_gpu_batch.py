@@ -130,3 +130,45 @@ def test_autotune_and_cache():
         assert_same(tuned, plain, "tuned vs default schedule")
         bb, _, _ = fsg.autotune(dg, "ic", seeds, 64, 5, tune_steps=4, batch_only=True, p=0.05)
         assert bb["kernel_variant"] == 1
+
+
+def test_c3_full_size_every_job():
+    """The mixed batched workload at full size (64 jobs, 3.4e8 arcs) in the
+    launch configuration the benchmark times: every job equals its solo run
+    bit for bit (compared on the device), and two sampled replicates of every
+    job equal the oracle."""
+    import torch
+    from paper_2603_14895_amd import fsg
+    specs = W.config_c3_jobs()
+    jobs, host = [], []
+    for sp in specs:
+        gr = W.build_c3_graph(sp, device="cuda")
+        ptr, src = gr.numpy()
+        del gr
+        dg = fsg.DeviceGraph(ptr, src, device="cuda:0")
+        seeds = W.uniform_seeds(dg.n, sp["n_seeds"], sp["seed_seed"])
+        prm = {k: sp[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in sp}
+        jobs.append(dict(graph=dg, model=sp["model"], B=sp["B"], seeds=seeds, rng_key=sp["key"],
+                         **prm))
+        host.append((ptr, src))
+    log(f"[batch] c3 full: {len(jobs)} jobs, {sum(h[1].size for h in host)} arcs")
+    batch = fsg.Batch(jobs, steps_per_sync=16)
+    infos, total_ms = batch.run()
+    log(f"[batch] c3 full: {total_ms:.1f} ms device")
+    for i, (j, (ptr, src)) in enumerate(zip(jobs, host)):
+        prm = {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in j}
+        st, cnt, steps, absorbed = fsg.simulate(j["graph"], j["model"], j["seeds"], j["B"],
+                                                j["rng_key"], **prm)
+        assert torch.equal(batch.states[i], st), f"job {i} states differ from its solo run"
+        assert torch.equal(batch.counts[i], cnt), f"job {i} counts differ from its solo run"
+        assert (int(infos[i].steps_run), int(infos[i].absorbed)) == (steps, absorbed), i
+        del st, cnt
+        r0 = j["B"] // 3
+        rs, _, _, _ = oracle_run((ptr, src), j["model"], j["seeds"], 2, j["rng_key"],
+                                 replicate_offset=r0, **prm)
+        got = batch.states[i][:, r0:r0 + 2].cpu().numpy()
+        assert (got == rs).all(), f"job {i} ({j['model']}) sampled replicates differ from the oracle"
+    log(f"[batch] c3 full: all {len(jobs)} jobs match their solo runs and the oracle samples")
+    batch.close()
+    for j in jobs:
+        j["graph"].close()
