@@ -334,7 +334,7 @@ struct Layout {
     size_t planes[4];
     int n_planes;
     size_t flags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
-        seeds, bm[2], sum[2], total;
+        seeds, bm[2], sum[2], need, total;
     int sum_shift, sum_words;
     int64_t W, plane_words, n_tinf, n_seed_stage;
     int L;
@@ -394,6 +394,9 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
     if (prm->model == FSG_IC && prm->ic_prob == FSG_IC_PER_EDGE)
         off = align256(off + (size_t)g->nnz * 4);
     L->seeds = off; off = align256(off + (size_t)L->n_seed_stage * 4);
+    L->need = off;
+    if (kind == kKindLT)  // bit-sliced thresholds [n][L][W]
+        off = align256(off + (size_t)g->n * (size_t)L->L * (size_t)L->W * 8);
     L->bm[0] = L->bm[1] = L->sum[0] = L->sum[1] = 0;
     L->sum_shift = 0;
     L->sum_words = 0;
@@ -559,6 +562,12 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.nnz = g->nnz;
     a.sum_shift = L.sum_shift;
     a.sum_words = L.sum_words;
+    a.need = nullptr;
+    if (kind == kKindLT && g->n > 0) {
+        a.need = (uint64_t *)(base + L.need);
+        HIP_TRY(launch_lt_need(a, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
     return FSG_OK;
 }
 

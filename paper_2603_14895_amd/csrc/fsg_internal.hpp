@@ -67,6 +67,10 @@ struct StepArgs {
     int32_t n_heavy;
     uint64_t *partial;      // [n_seg][Lp][W]
     int32_t Lp;             // counter planes per partial (1 for IC)
+    // LT: each replicate's activation threshold max(1, ceil(U indeg / 2^32)),
+    // bit-sliced: plane p of node v at need[(v Lp + p) W + w], written for
+    // p < bitlen(indeg(v)) <= Lp once per run; null for the other models
+    uint64_t *need;
     // frontier bitmaps of the edge-parallel IC kernel: bit u of bm_prev is set
     // iff node u has a newly active replicate after step t-1 (prev is only
     // meaningful where it is set); bm_next is cleared before step t
@@ -133,6 +137,7 @@ hipError_t launch_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t
 hipError_t launch_ic_stream(const StepArgs &a, int grid, int block, hipStream_t s);
 hipError_t launch_expand_rows(const int32_t *ptr, int64_t n, int32_t *dst, hipStream_t s);
 hipError_t launch_ic_clear(const StepArgs &a, hipStream_t s);
+hipError_t launch_lt_need(const StepArgs &a, hipStream_t s);
 hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_t s);
 hipError_t launch_combine(const StepArgs &a, int kind, int block, hipStream_t s);
 hipError_t launch_finalize(const FinArgs &f, hipStream_t s);

@@ -416,11 +416,30 @@ template <int LC>
 __device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool valid, int v,
                                           int w, int64_t idx, uint64_t act, uint64_t inact,
                                           uint32_t indeg, const uint64_t (&c)[LC], int s,
-                                          uint64_t share, bool &any)
+                                          uint64_t share, bool use_need, bool &any)
 {
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
     uint64_t nw = 0;
-    if ((a.goff & 3u) == 0u) {
+    const int P = indeg ? 32 - __builtin_clz(indeg) : 0;  // planes of the stored thresholds
+    if (use_need && a.need != nullptr && P <= LC) {
+        // thresholds drawn once per run: v activates in replicate r iff
+        // c_r >= need_r, i.e. iff c - need does not borrow (the borrow chain
+        // runs plane by plane over all 64 replicates of the word)
+        uint64_t nz = 0;
+#pragma unroll
+        for (int l = 0; l < LC; ++l) nz |= c[l];
+        const uint64_t cand = inact & share & nz;
+        if (cand) {
+            const uint64_t *np = a.need + (int64_t)v * a.Lp * a.W + w;
+            uint64_t borrow = 0;
+#pragma unroll
+            for (int l = 0; l < LC; ++l) {
+                const uint64_t nl = l < P ? np[(int64_t)l * a.W] : 0ull;
+                borrow = maj3(~c[l], nl, borrow);
+            }
+            nw = cand & ~borrow;
+        }
+    } else if ((a.goff & 3u) == 0u) {
         // aligned generator blocks, branch-free per block: c = c0 + 2 c1
         // when no higher plane is set; v activates iff c 2^32 >= U indeg,
         // i.e. iff c > hi or (c == hi and lo == 0) for U indeg = hi 2^32 + lo.
@@ -518,7 +537,7 @@ __device__ __forceinline__ void lt_row_word(const StepArgs &a, int G, int S, boo
         }
         return;
     }
-    lt_decide<L>(a, G, S, valid, v, w, idx, act, inact, indeg, c, s, share, any);
+    lt_decide<L>(a, G, S, valid, v, w, idx, act, inact, indeg, c, s, share, true, any);
 }
 
 __device__ __forceinline__ uint32_t wc_threshold(uint32_t indeg)
@@ -691,7 +710,8 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
 #pragma unroll
                 for (int l = 0; l < LC; ++l) c[l] &= inact;
                 const uint32_t indeg = act ? (uint32_t)(a.ptr[v + 1] - a.ptr[v]) : 0u;
-                lt_decide<LC>(a, G, 1, valid, v, ww, idx, act_w, inact, indeg, c, 0, ~0ull, any);
+                lt_decide<LC>(a, G, 1, valid, v, ww, idx, act_w, inact, indeg, c, 0, ~0ull, false,
+                              any);
             }
         }
     }
@@ -807,6 +827,45 @@ __global__ void __launch_bounds__(1024) k_ic_stream(StepArgs a)
         }
     }
     if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+// LT thresholds of one run, bit-sliced (one thread per node word): replicate
+// g = goff + 64 w + b of node v gets need = max(1, ceil(U indeg / 2^32)) with
+// U = D(LT threshold, v, g, 0), the same draw the per-step path takes; v
+// activates iff its count of active in-neighbours reaches need.  Nodes
+// whose in-degree needs more planes than the counter has are left to the
+// per-step path (they are heavy rows, merged by the combine kernel).
+__global__ void k_lt_need(StepArgs a)
+{
+    const int64_t total = (int64_t)a.n * a.W;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int v = (int)(i / a.W);
+        const int w = (int)(i - (int64_t)v * a.W);
+        const uint32_t indeg = (uint32_t)(a.ptr[v + 1] - a.ptr[v]);
+        const int P = indeg ? 32 - __builtin_clz(indeg) : 0;
+        if (P == 0 || P > a.Lp) continue;
+        uint64_t pl[16];
+#pragma unroll
+        for (int p = 0; p < 16; ++p) pl[p] = 0;
+        const uint64_t g0 = a.goff + 64ull * (uint64_t)w;
+        U4 o = {0u, 0u, 0u, 0u};
+        for (int b = 0; b < 64; ++b) {
+            const uint64_t g = g0 + (uint64_t)b;
+            if (b == 0 || (g & 3u) == 0u)
+                o = philox10((uint32_t)v, (uint32_t)(g >> 2), 0u, kDomLtThresh << 24, a.key0, a.key1);
+            const uint32_t j = (uint32_t)g & 3u;
+            const uint32_t u = j == 0 ? o.x : j == 1 ? o.y : j == 2 ? o.z : o.w;
+            uint64_t need = ((uint64_t)u * (uint64_t)indeg + 0xFFFFFFFFull) >> 32;
+            need = need ? need : 1ull;
+#pragma unroll
+            for (int p = 0; p < 16; ++p) pl[p] |= ((need >> p) & 1ull) << b;
+        }
+        uint64_t *np = a.need + (int64_t)v * a.Lp * a.W + w;
+#pragma unroll
+        for (int p = 0; p < 16; ++p)
+            if (p < P) np[(int64_t)p * a.W] = pl[p];
+    }
 }
 
 // Target row of every arc: one thread per row (grid-stride), used once when
@@ -1163,6 +1222,13 @@ hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t
 {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill32, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_lt_need(const StepArgs &a, hipStream_t s)
+{
+    const int64_t total = (int64_t)a.n * a.W;
+    hipLaunchKernelGGL(k_lt_need, dim3(grid_for(total, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
