@@ -412,6 +412,8 @@ __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bo
 // In-weights 1/indeg and threshold U/2^32 drawn once per (node, replicate):
 // v activates once c active in-neighbours satisfy c >= ceil(U indeg / 2^32)
 // (and c >= 1).
+constexpr int kPlaneBlocks = 4;
+
 template <int LC>
 __device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool valid, int v,
                                           int w, int64_t idx, uint64_t act, uint64_t inact,
@@ -421,14 +423,22 @@ __device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool 
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
     uint64_t nw = 0;
     const int P = indeg ? 32 - __builtin_clz(indeg) : 0;  // planes of the stored thresholds
-    if (use_need && a.need != nullptr && P <= LC) {
-        // thresholds drawn once per run: v activates in replicate r iff
-        // c_r >= need_r, i.e. iff c - need does not borrow (the borrow chain
-        // runs plane by plane over all 64 replicates of the word)
-        uint64_t nz = 0;
+    uint64_t nz = 0;
 #pragma unroll
-        for (int l = 0; l < LC; ++l) nz |= c[l];
-        const uint64_t cand = inact & share & nz;
+    for (int l = 0; l < LC; ++l) nz |= c[l];
+    const uint64_t cand = inact & share & nz;
+    // Stored thresholds cost bitlen(indeg) word loads, a fresh draw one
+    // Philox call per 4-replicate block with a candidate: the wave reads the
+    // planes when some lane has more than kPlaneBlocks such blocks.
+    bool planes = false;
+    if (use_need && a.need != nullptr) {
+        uint64_t blk = cand | (cand >> 1) | (cand >> 2) | (cand >> 3);
+        blk &= 0x1111111111111111ull;
+        planes = __ballot(__popcll(blk) > kPlaneBlocks) != 0ull;
+    }
+    if (planes && P <= LC) {
+        // v activates in replicate r iff c_r >= need_r, i.e. iff c - need
+        // does not borrow (the chain runs plane by plane over the word)
         if (cand) {
             const uint64_t *np = a.need + (int64_t)v * a.Lp * a.W + w;
             uint64_t borrow = 0;
