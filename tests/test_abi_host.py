@@ -102,6 +102,22 @@ def test_params_validation_before_any_launch():
         fsg.fsg_graph_destroy(h)
 
 
+def test_hk_entry_points_refuse_unbound_graphs_on_the_host():
+    ptr, src = _graph()
+    n, nnz = ptr.size - 1, src.size
+    h = fsg.fsg_graph_create(n, nnz, ptr.ctypes.data, src.ctypes.data)
+    try:
+        for call in (lambda: fsg.fsg_hk_workspace_size(h, 8, None),
+                     lambda: fsg.fsg_hk(h, 0.3, 5, 8, None, None, None, 0, 0.5, None,
+                                        stream=ctypes.c_void_p(0)),
+                     lambda: fsg.fsg_hk_workspace_size(None, 8, None)):
+            with pytest.raises(fsg.FsgError) as e:
+                call()
+            assert e.value.code == fsg.FSG_EINVAL and "bound" in str(e.value)
+    finally:
+        fsg.fsg_graph_destroy(h)
+
+
 @pytest.mark.parametrize("heavy", [10**9, 40])
 @pytest.mark.parametrize("parts", [1, 3, 17, 64, 500])
 def test_row_tiles_load_balance_bound(heavy, parts):
