@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the schedule(s) first with the library autotuner")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
+    ap.add_argument("--tune-steps", type=int, default=8,
+                    help="steps per timed candidate in the autotuner (c3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--schedule", default=None, help="JSON dict of fsg_schedule fields")
@@ -418,7 +420,8 @@ def bench_batch(args):
         for j in jobs:
             prm = {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in j}
             best, bms, dms = fsg.autotune(j["graph"], j["model"], j["seeds"], j["B"], j["rng_key"],
-                                          tune_steps=8, batch_only=True, cache_path=args.tune_cache,
+                                          tune_steps=args.tune_steps, batch_only=True,
+                                          cache_path=args.tune_cache,
                                           **prm)
             j["schedule"] = best
         log(f"[bench] autotuned {len(jobs)} jobs in {time.perf_counter() - t1:.1f}s")
