@@ -312,8 +312,10 @@ int fsg_batch_run(fsg_plan *plan, void *dev_ws, size_t ws_bytes, fsg_run_info *i
 
 int fsg_plan_destroy(fsg_plan *plan);
 
-/* ---- Autotuner: times short runs (tune_steps steps from the seeds, kernel
- * time per step from HIP events) of candidate schedules -- lanes per row,
+/* ---- Autotuner: times short runs of candidate schedules (from the seeds,
+ * runs of tune_steps and 2 tune_steps steps with HIP events around each on
+ * `stream`; the cost per step is their difference over the extra steps, so
+ * the set-up is left out and every kernel of a step counts) -- lanes per row,
  * tile size, heavy-row cut, block size, kernel variant -- and returns the
  * fastest.  batch_only = 1 restricts the search to schedules the batched
  * launch accepts.  cache_path (nullable): a text file of earlier results

@@ -1370,17 +1370,40 @@ int fsg_autotune(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds
             if (default_ms) *default_ms = -1.0;
             return FSG_OK;
         }
-        fsg_params tp = *prm;
-        tp.max_steps = prm->max_steps < 0 ? tune_steps : std::min<int64_t>(prm->max_steps, tune_steps);
-        auto time_one = [&](const fsg_schedule &s0, double *ms) -> int {
-            fsg_schedule s = s0;
-            s.time_kernels = 1;
-            s.steps_per_sync = std::max(1, std::min(tune_steps, 64));
+        // Objective: device time of whole steps (pull step, heavy-row merge
+        // and frontier clear), from runs of K and 2K steps timed with HIP
+        // events on the stream; their difference leaves out the set-up.
+        hipStream_t st = (hipStream_t)stream;
+        EventPool ev;
+        HIP_TRY(ev.init(2));
+        auto run_for = [&](const fsg_schedule &s, int64_t k, double *ms, int64_t *steps) -> int {
+            fsg_params tp = *prm;
+            tp.max_steps = prm->max_steps < 0 ? k : std::min<int64_t>(prm->max_steps, k);
             fsg_run_info info;
+            HIP_TRY(hipEventRecord(ev.e[0], st));
             int r = fsg_simulate(g, &tp, seeds, n_seeds, B, 0, rng_key, &s, dev_ws, ws_bytes,
                                  nullptr, nullptr, &info, stream);
             if (r) return r;
-            *ms = info.step_launches > 0 ? info.step_kernel_ms / (double)info.step_launches : 1e30;
+            HIP_TRY(hipEventRecord(ev.e[1], st));
+            HIP_TRY(hipEventSynchronize(ev.e[1]));
+            float f = 0.f;
+            HIP_TRY(hipEventElapsedTime(&f, ev.e[0], ev.e[1]));
+            *ms = f;
+            *steps = info.steps_run;
+            return FSG_OK;
+        };
+        auto time_one = [&](const fsg_schedule &s0, double *ms) -> int {
+            fsg_schedule s = s0;
+            s.time_kernels = 0;
+            s.steps_per_sync = std::max(1, std::min(tune_steps, 64));
+            double t1 = 0, t2 = 0;
+            int64_t s1 = 0, s2 = 0;
+            int r = run_for(s, tune_steps, &t1, &s1);
+            if (r) return r;
+            r = run_for(s, 2 * (int64_t)tune_steps, &t2, &s2);
+            if (r) return r;
+            *ms = s2 > s1 ? std::max(0.0, t2 - t1) / (double)(s2 - s1)
+                          : (s2 > 0 ? t2 / (double)s2 : 1e30);
             return FSG_OK;
         };
         fsg_schedule d;
