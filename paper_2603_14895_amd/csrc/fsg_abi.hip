@@ -1116,7 +1116,7 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
             const StepArgs &a = jb[(size_t)i].a;
             h_jobs[(size_t)i] = a;  // prev/next hold planes 0 and 1
             item_off[(size_t)i + 1] = item_off[(size_t)i] + step_blocks(a, kBatchBlock);
-            const int rows_per_combine = 4 * (64 >> a.lgG);
+            const int rows_per_combine = (kBatchBlock / 64) * combine_rows_per_wave(a.lgG);
             comb_off[(size_t)i + 1] =
                 comb_off[(size_t)i] + (a.n_heavy + rows_per_combine - 1) / rows_per_combine;
             any_heavy |= a.n_heavy > 0;

@@ -151,4 +151,12 @@ hipError_t launch_batch_combine(const BatchCtl &c, int grid, hipStream_t s);
 hipError_t launch_batch_advance(const BatchCtl &c, hipStream_t s);
 constexpr int kBatchBlock = 256;  // block size of the batched kernels
 
+// Heavy rows merged per wave by the combine kernels: each row takes G word
+// lanes times min(64 / G, 16) segment lanes.
+__host__ __device__ inline int combine_rows_per_wave(int lgG)
+{
+    const int lanes = 64 >> lgG;
+    return lanes < 16 ? 1 : lanes / 16;
+}
+
 }  // namespace fsg

@@ -669,13 +669,20 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
     const int G = a.G;
-    const int rpw = 64 >> a.lgG;
-    const int slot = lane >> a.lgG;
+    // G lanes over words times S2 lanes over the row's segments (S2 <= 16,
+    // the widest split the draw-sharing masks cover), combine_rows_per_wave
+    // rows per wave; the segment lanes' counts are summed across lanes
+    const int lanes = 64 >> a.lgG;
+    const int S2 = lanes < 16 ? lanes : 16;
+    const int rpw = combine_rows_per_wave(a.lgG);
+    const int slot = lane / (G * S2);
+    const int ss = (lane >> a.lgG) % S2;
     const int gw = lane & (G - 1);
     const int j = (bid * nwaves + wave) * rpw + slot;
     const bool act = j < a.n_heavy;
     const int v = act ? a.heavy_rows[j] : 0;
     const int sg0 = act ? a.heavy_seg[j] : 0, sg1 = act ? a.heavy_seg[j + 1] : 0;
+    const uint64_t share = share_bits(a.goff, ss, S2);
     for (int w0 = 0; w0 < a.W; w0 += G) {
         const int w = w0 + gw;
         const bool valid = act && w < a.W;
@@ -684,8 +691,9 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
         if (KIND == kKindIC) {
             uint64_t acc = 0;
             if (valid)
-                for (int sg = sg0; sg < sg1; ++sg) acc |= a.partial[(int64_t)sg * a.W + ww];
-            if (valid) {
+                for (int sg = sg0 + ss; sg < sg1; sg += S2) acc |= a.partial[(int64_t)sg * a.W + ww];
+            acc = or_reduce_lanes(acc, G, S2);
+            if (valid && ss == 0) {
                 const uint64_t A = a.aux[idx];
                 acc &= ~A;
                 a.next[idx] = acc;
@@ -697,7 +705,7 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
 #pragma unroll
             for (int l = 0; l < LC; ++l) c[l] = 0;
             if (valid) {
-                for (int sg = sg0; sg < sg1; ++sg) {
+                for (int sg = sg0 + ss; sg < sg1; sg += S2) {
                     uint64_t d[LC];
 #pragma unroll
                     for (int l = 0; l < LC; ++l)
@@ -705,6 +713,7 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
                     bs_add<LC>(c, d);
                 }
             }
+            bs_reduce_lanes<LC>(c, G, S2);
             if (KIND == kKindEpidemic) {
                 const uint64_t h = valid ? a.prev[idx] : 0ull;
                 const uint64_t r = valid ? a.aux[idx] : 0ull;
@@ -712,7 +721,7 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
                 const uint64_t sus = valid ? (~(h | r | e) & tail_mask(ww, a.B)) : 0ull;
 #pragma unroll
                 for (int l = 0; l < LC; ++l) c[l] &= sus;
-                epi_decide<LC>(a, G, 1, valid, v, ww, idx, h, r, e, sus, c, 0, ~0ull, nullptr, 0,
+                epi_decide<LC>(a, G, S2, valid, v, ww, idx, h, r, e, sus, c, ss, share, nullptr, 0,
                                tcode, any);
             } else {
                 const uint64_t act_w = valid ? a.prev[idx] : 0ull;
@@ -720,7 +729,7 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
 #pragma unroll
                 for (int l = 0; l < LC; ++l) c[l] &= inact;
                 const uint32_t indeg = act ? (uint32_t)(a.ptr[v + 1] - a.ptr[v]) : 0u;
-                lt_decide<LC>(a, G, 1, valid, v, ww, idx, act_w, inact, indeg, c, 0, ~0ull, false,
+                lt_decide<LC>(a, G, S2, valid, v, ww, idx, act_w, inact, indeg, c, ss, share, false,
                               any);
             }
         }
@@ -1299,7 +1308,7 @@ hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_
 hipError_t launch_combine(const StepArgs &a, int kind, int /*block*/, hipStream_t s)
 {
     if (a.n_heavy <= 0) return hipSuccess;
-    const int rows_per_block = 4 * (64 >> a.lgG);
+    const int rows_per_block = 4 * combine_rows_per_wave(a.lgG);
     const dim3 grid((unsigned)((a.n_heavy + rows_per_block - 1) / rows_per_block)), blk(256);
     if (kind == kKindIC) {
         hipLaunchKernelGGL((k_combine<kKindIC, 1>), grid, blk, 0, s, a);
