@@ -190,8 +190,8 @@ def main():
         print(json.dumps({w: kernel_source_hash(w) for w in ("c1", "c2", "c3", "c4", "c5", "hk")}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(replicate sharding across GPUs is described in DESIGN.md); run with --gpus 1.",
+        print("bench.py measures one GPU: the library runs on a single GPU (replicates "
+              "would shard across GPUs by global replicate index); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
