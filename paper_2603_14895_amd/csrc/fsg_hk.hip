@@ -24,7 +24,7 @@
 //     (16-byte gathers of the source rows), else per (row, replicate),
 //     looping over the row's in-arcs with the next source indices in
 //     flight.
-// A step that changes no opinion clears its ring flag; the next step's
+// A step that changes no opinion leaves its ring flag clear; the next step's
 // kernel then returns at once, so several steps can be queued between host
 // polls.
 #include <hip/hip_runtime.h>
