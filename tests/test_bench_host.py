@@ -1,0 +1,44 @@
+"""Host-side checks of the benchmark script: it refuses more than one GPU
+with a message, its JSON output stays valid when a figure is not finite, and
+the algorithmic byte models match their definitions on small sizes."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_json_line_has_no_nan():
+    import bench
+    out = {"value": float("nan"), "roofline": {"frac": float("inf")}, "x": [1.0, float("-inf")]}
+    from io import StringIO
+    import contextlib
+    buf = StringIO()
+    with contextlib.redirect_stdout(buf):
+        bench.emit(out)
+    d = json.loads(buf.getvalue())
+    assert d == {"value": None, "roofline": {"frac": None}, "x": [1.0, None]}
+
+
+def test_byte_models():
+    import bench
+    n, nnz, B = 1000, 20000, 1024
+    W = 16
+    assert bench.algorithmic_bytes_per_step("sir", n, nnz, B, False) == \
+        4 * nnz + 8 * W * nnz + 4 * (n + 1) + 32 * W * n
+    assert bench.algorithmic_bytes_per_step("ic", n, nnz, 64, True) == 4 * nnz + n / 8
+    assert bench.hk_algorithmic_bytes(n, nnz, 256) == 4 * 256 * nnz + 8 * 256 * n + 4 * nnz + 4 * (n + 1)
+
+
+def test_kernel_hash_is_per_workload():
+    import bench
+    h = {w: bench.kernel_source_hash(w) for w in ("c2", "c4", "hk", "c5")}
+    assert h["c2"] == h["c4"] and h["hk"] != h["c2"] and h["c5"] != h["hk"]
