@@ -76,7 +76,62 @@ __device__ __forceinline__ void ic_row_word(const StepArgs &a, int G, int S, boo
     const uint64_t A = valid ? a.aux[idx] : ~0ull;
     const uint64_t cand = valid ? (~A & tail_mask(w, a.B)) : 0ull;
     uint64_t acc = 0;
-    if (cand && a.fast32) {
+    if (S == 1 && G >= 16 && a.fast32 && seg < 0) {
+        // 16 arcs of the row per pass: lane lr of each 16-lane DPP row loads
+        // source e0 + base + lr, the row's lanes receive them by row
+        // broadcast and gather their word of each; arcs past the row's end
+        // read the all-zero row n, so they never reach a trial
+        const int lr = (int)(threadIdx.x & 15u);
+        int dmax = 0;
+        const int d = valid ? e1 - e0 : 0;
+        for (int l = 0; l < 64; l += G) dmax = max(dmax, __builtin_amdgcn_readlane(d, l));
+        if (dmax > 0 && __ballot(cand != 0ull) != 0ull) {
+            const uint32_t W8 = (uint32_t)a.W * 8u, w8 = (uint32_t)w * 8u, zero = (uint32_t)a.n;
+            const char *prev = reinterpret_cast<const char *>(a.prev);
+            auto src_at = [&](int base) -> uint32_t {
+                const int e = e0 + base + lr;
+                return e < e1 ? (uint32_t)ld32_off32(a.src, (uint32_t)e) : zero;
+            };
+            auto word = [&](uint32_t u) -> uint64_t {
+                return *reinterpret_cast<const uint64_t *>(prev + __umul24(cand ? u : zero, W8) + w8);
+            };
+            uint32_t cur = src_at(0);
+            for (int base = 0; base < dmax; base += 16) {
+                const uint32_t nxt = base + 16 < dmax ? src_at(base + 16) : zero;
+                {
+                    const uint64_t x0 = word(row_bcast<0>(cur)), x1 = word(row_bcast<1>(cur)),
+                                   x2 = word(row_bcast<2>(cur)), x3 = word(row_bcast<3>(cur)),
+                                   x4 = word(row_bcast<4>(cur)), x5 = word(row_bcast<5>(cur)),
+                                   x6 = word(row_bcast<6>(cur)), x7 = word(row_bcast<7>(cur));
+                    const int eb = e0 + base;
+                    ic_edge(a, eb, x0 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 1, x1 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 2, x2 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 3, x3 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 4, x4 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 5, x5 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 6, x6 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 7, x7 & cand & ~acc, gbase, tv, acc);
+                }
+                if (dmax - base > 8) {
+                    const uint64_t x0 = word(row_bcast<8>(cur)), x1 = word(row_bcast<9>(cur)),
+                                   x2 = word(row_bcast<10>(cur)), x3 = word(row_bcast<11>(cur)),
+                                   x4 = word(row_bcast<12>(cur)), x5 = word(row_bcast<13>(cur)),
+                                   x6 = word(row_bcast<14>(cur)), x7 = word(row_bcast<15>(cur));
+                    const int eb = e0 + base + 8;
+                    ic_edge(a, eb, x0 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 1, x1 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 2, x2 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 3, x3 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 4, x4 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 5, x5 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 6, x6 & cand & ~acc, gbase, tv, acc);
+                    ic_edge(a, eb + 7, x7 & cand & ~acc, gbase, tv, acc);
+                }
+                cur = nxt;
+            }
+        }
+    } else if (cand && a.fast32) {
         const uint32_t Wu = (uint32_t)a.W, ww = (uint32_t)w;
         int e = e0 + s;
         for (; e + 3 * S < e1; e += 4 * S) {

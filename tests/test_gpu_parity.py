@@ -62,7 +62,7 @@ def test_c1_ic_erdos_renyi_full():
 
 
 @pytest.mark.parametrize("ic_prob", ["uniform", "weighted_cascade", "per_edge"])
-@pytest.mark.parametrize("B,offset", [(64, 0), (130, 3), (1, 7)])
+@pytest.mark.parametrize("B,offset", [(64, 0), (130, 3), (1, 7), (1024, 0), (1500, 5)])
 def test_ic_variants(ic_prob, B, offset):
     gr = W.chung_lu(6000, 8.0, 2.5, 31)
     gnp = gr.numpy()
