@@ -96,16 +96,14 @@ __global__ void k_input(uint16_t *X1, const uint8_t *mask, const float *beta, co
 // neighbour rows in flight per load; neighbour indices arrive 64 at a time
 // with one coalesced load and reach the lanes by shuffle.  The lane groups'
 // partial sums are added at the end (fixed order).
-__global__ void __launch_bounds__(256) k_mean(uint16_t *X, int ld, int d, int cin, int cout,
-                                              const int32_t *ptr, const int32_t *src, int32_t n,
-                                              int32_t n_sets)
+__device__ __forceinline__ void mean_light(uint16_t *X, int ld, int d, int cin, int cout,
+                                           const int32_t *ptr, const int32_t *src, int32_t n,
+                                           int32_t n_sets, int64_t wave, int64_t nwave)
 {
     const int lane = threadIdx.x & 63;
     const int lg = d >> 2, ng = 64 / lg;
     const int gi = lane / lg, li = lane - gi * lg;
     const int64_t R = (int64_t)n * n_sets;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t r = wave; r < R; r += nwave) {
         const int s = (int)(r / n);
         const int v = (int)(r - (int64_t)s * n);
@@ -200,17 +198,16 @@ __global__ void __launch_bounds__(256) k_mean_bwd(float *dH, const float *dX, co
 constexpr int kWideThreads = 1024;
 constexpr int kWideWaves = kWideThreads / 64;
 
-__global__ void __launch_bounds__(kWideThreads) k_mean_wide(uint16_t *X, int ld, int d, int cin,
-                                                            int cout, const int32_t *ptr,
-                                                            const int32_t *src, int32_t n,
-                                                            const int32_t *wide, int32_t n_wide)
+__device__ __forceinline__ void mean_wide(uint16_t *X, int ld, int d, int cin, int cout,
+                                          const int32_t *ptr, const int32_t *src, int32_t n,
+                                          const int32_t *wide, int32_t n_wide, int blk,
+                                          float (*s_part)[kHid])
 {
-    __shared__ float s_part[kWideWaves][kHid];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lg = d >> 2, ng = 64 / lg;
     const int gi = lane / lg, li = lane - gi * lg;
-    const int s = blockIdx.x / n_wide;
-    const int v = wide[blockIdx.x - s * n_wide];
+    const int s = blk / n_wide;
+    const int v = wide[blk - s * n_wide];
     const int e0 = ptr[v], deg = ptr[v + 1] - e0;
     const int per = (deg + kWideWaves - 1) / kWideWaves;
     const int lo = min(deg, wv * per), hi = min(deg, lo + per);
@@ -249,6 +246,26 @@ __global__ void __launch_bounds__(kWideThreads) k_mean_wide(uint16_t *X, int ld,
         for (int w = 0; w < kWideWaves; ++w) acc += s_part[w][threadIdx.x];
         X[((int64_t)s * n + v) * ld + cout + threadIdx.x] = to_bf16(acc / (float)deg);
     }
+}
+
+// Forward mean aggregation in one launch: the first n_wide * n_sets blocks
+// take the wide rows (largest first), the rest the other rows one wave each,
+// so the long rows run alongside the short ones.
+__global__ void __launch_bounds__(kWideThreads) k_mean_all(uint16_t *X, int ld, int d, int cin,
+                                                           int cout, const int32_t *ptr,
+                                                           const int32_t *src, int32_t n,
+                                                           int32_t n_sets, const int32_t *wide,
+                                                           int32_t n_wide)
+{
+    __shared__ float s_part[kWideWaves][kHid];
+    const int nwb = n_wide * n_sets;
+    if ((int)blockIdx.x < nwb) {
+        mean_wide(X, ld, d, cin, cout, ptr, src, n, wide, n_wide, (int)blockIdx.x, s_part);
+        return;
+    }
+    const int64_t wave = ((int64_t)(blockIdx.x - nwb) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)(gridDim.x - nwb) * blockDim.x) >> 6;
+    mean_light(X, ld, d, cin, cout, ptr, src, n, n_sets, wave, nwave);
 }
 
 __global__ void __launch_bounds__(kWideThreads) k_mean_bwd_wide(float *dH, const float *dX,
@@ -559,25 +576,39 @@ __global__ void k_params_to_bf16(const float *p, uint16_t *wb)
     }
 }
 
-// Sum of probabilities of each seed set (the predicted spread), fixed order;
-// one block of kSumThreads per set.
-constexpr int kSumThreads = 1024;
-__global__ void __launch_bounds__(kSumThreads) k_set_sums(const float *prob, int32_t n,
-                                                          int32_t n_sets, float *out)
+// Per-set sums of the node probabilities (the predicted spread) in a fixed
+// order: block b of set s
+// sums rows [b c, (b+1) c) of the set (c = ceil(n / kSumParts)) into
+// part[s][b]; k_set_final then adds the kSumParts partials of each set.
+constexpr int kSumParts = 128;
+
+__global__ void __launch_bounds__(256) k_set_part(const float *prob, int32_t n, float *part)
 {
-    __shared__ float s[kSumThreads];
-    for (int set = blockIdx.x; set < n_sets; set += gridDim.x) {
-        float acc = 0.f;
-        for (int v = threadIdx.x; v < n; v += blockDim.x) acc += prob[(int64_t)set * n + v];
-        s[threadIdx.x] = acc;
-        __syncthreads();
-        for (int off = kSumThreads / 2; off > 0; off >>= 1) {
-            if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[set] = s[0];
+    __shared__ float s[256];
+    const int set = blockIdx.x / kSumParts, b = blockIdx.x - set * kSumParts;
+    const int c = (n + kSumParts - 1) / kSumParts;
+    const int lo = min(n, b * c), hi = min(n, lo + c);
+    float acc = 0.f;
+    for (int v = lo + (int)threadIdx.x; v < hi; v += blockDim.x) acc += prob[(int64_t)set * n + v];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
     }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void __launch_bounds__(kSumParts) k_set_final(const float *part, float *out)
+{
+    __shared__ float s[kSumParts];
+    s[threadIdx.x] = part[blockIdx.x * kSumParts + threadIdx.x];
+    __syncthreads();
+    for (int off = kSumParts / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = s[0];
 }
 
 __global__ void k_mask_clear(uint8_t *mask, int32_t n)
@@ -697,15 +728,11 @@ int view_of(const fsg_graph *g, GraphView *v, const char *what)
 int mean_agg(uint16_t *X, int ld, int d, const GraphView &G, int32_t n_sets, hipStream_t st)
 {
     const int64_t R = G.n * n_sets;
-    hipLaunchKernelGGL(k_mean, dim3(grid_of(R * 64, 256)), dim3(256), 0, st, X, ld, d, 0, d,
-                       G.ptr, G.src, (int32_t)G.n, n_sets);
+    const unsigned nwb = (unsigned)(G.n_wide * n_sets);
+    hipLaunchKernelGGL(k_mean_all, dim3(nwb + grid_of(R * 64, kWideThreads)), dim3(kWideThreads), 0,
+                       st, X, ld, d, 0, d, G.ptr, G.src, (int32_t)G.n, n_sets, G.wide,
+                       (int32_t)G.n_wide);
     GNN_TRY(hipGetLastError());
-    if (G.n_wide > 0) {
-        hipLaunchKernelGGL(k_mean_wide, dim3((unsigned)(G.n_wide * n_sets)), dim3(kWideThreads), 0,
-                           st, X, ld, d, 0, d, G.ptr, G.src, (int32_t)G.n, G.wide,
-                           (int32_t)G.n_wide);
-        GNN_TRY(hipGetLastError());
-    }
     return FSG_OK;
 }
 
@@ -906,7 +933,10 @@ int forward_enqueue(fsg_gnn *g, const fsg_graph *graph, int32_t n_sets, const ui
     rc = forward_all(g, G, n_sets, dev_mask, base, w, st);
     if (rc) return rc;
     const int64_t R = G.n * n_sets;
-    hipLaunchKernelGGL(k_head, dim3(kPartBlocks), dim3(256), 0, st, (const uint16_t *)(base + w.H3),
+    // no gradient partials here, so one wave per row instead of the fixed
+    // grid the training pass needs for its deterministic sums
+    hipLaunchKernelGGL(k_head, dim3(grid_of(R * 64, 256)), dim3(256), 0, st,
+                       (const uint16_t *)(base + w.H3),
                        (const float *)(g->p() + kWo), (const float *)(g->p() + kBo),
                        (const float *)nullptr, dev_prob, (float *)nullptr, (float *)nullptr,
                        (float *)nullptr, (float *)nullptr, R);
@@ -1076,8 +1106,12 @@ int fsg_estimate_spread(fsg_gnn *const *members, int32_t n_members, const fsg_gr
         rc = forward_enqueue(members[m], graph, 1, mask, &fb, (float *)(base + w.prob), ws,
                              ws_bytes, stream);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_set_sums, dim3(1), dim3(kSumThreads), 0, st,
-                           (const float *)(base + w.prob), (int32_t)G.n, 1, sums + m);
+        float *part = (float *)(base + w.part);  // kSumParts floats (unused by the forward)
+        hipLaunchKernelGGL(k_set_part, dim3(kSumParts), dim3(256), 0, st,
+                           (const float *)(base + w.prob), (int32_t)G.n, part);
+        GNN_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_set_final, dim3(1), dim3(kSumParts), 0, st, (const float *)part,
+                           sums + m);
         GNN_TRY(hipGetLastError());
     }
     float hs[kMaxMembers];
