@@ -248,6 +248,24 @@ __device__ __forceinline__ void mean_wide(uint16_t *X, int ld, int d, int cin, i
     }
 }
 
+__global__ void __launch_bounds__(256) k_mean(uint16_t *X, int ld, int d, int cin, int cout,
+                                              const int32_t *ptr, const int32_t *src, int32_t n,
+                                              int32_t n_sets)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    mean_light(X, ld, d, cin, cout, ptr, src, n, n_sets, wave, nwave);
+}
+
+__global__ void __launch_bounds__(kWideThreads) k_mean_wide(uint16_t *X, int ld, int d, int cin,
+                                                            int cout, const int32_t *ptr,
+                                                            const int32_t *src, int32_t n,
+                                                            const int32_t *wide, int32_t n_wide)
+{
+    __shared__ float s_part[kWideWaves][kHid];
+    mean_wide(X, ld, d, cin, cout, ptr, src, n, wide, n_wide, (int)blockIdx.x, s_part);
+}
+
 // Forward mean aggregation in one launch: the first n_wide * n_sets blocks
 // take the wide rows (largest first), the rest the other rows one wave each,
 // so the long rows run alongside the short ones.
@@ -728,11 +746,24 @@ int view_of(const fsg_graph *g, GraphView *v, const char *what)
 int mean_agg(uint16_t *X, int ld, int d, const GraphView &G, int32_t n_sets, hipStream_t st)
 {
     const int64_t R = G.n * n_sets;
-    const unsigned nwb = (unsigned)(G.n_wide * n_sets);
-    hipLaunchKernelGGL(k_mean_all, dim3(nwb + grid_of(R * 64, kWideThreads)), dim3(kWideThreads), 0,
-                       st, X, ld, d, 0, d, G.ptr, G.src, (int32_t)G.n, n_sets, G.wide,
-                       (int32_t)G.n_wide);
+    if (n_sets == 1) {  // one query: the hubs overlap the short rows in one launch
+        const unsigned nwb = (unsigned)G.n_wide;
+        hipLaunchKernelGGL(k_mean_all, dim3(nwb + grid_of(R * 64, kWideThreads)),
+                           dim3(kWideThreads), 0, st, X, ld, d, 0, d, G.ptr, G.src, (int32_t)G.n,
+                           n_sets, G.wide, (int32_t)G.n_wide);
+        GNN_TRY(hipGetLastError());
+        return FSG_OK;
+    }
+    // many seed sets (training): short rows fill the GPU on their own
+    hipLaunchKernelGGL(k_mean, dim3(grid_of(R * 64, 256)), dim3(256), 0, st, X, ld, d, 0, d,
+                       G.ptr, G.src, (int32_t)G.n, n_sets);
     GNN_TRY(hipGetLastError());
+    if (G.n_wide > 0) {
+        hipLaunchKernelGGL(k_mean_wide, dim3((unsigned)(G.n_wide * n_sets)), dim3(kWideThreads), 0,
+                           st, X, ld, d, 0, d, G.ptr, G.src, (int32_t)G.n, G.wide,
+                           (int32_t)G.n_wide);
+        GNN_TRY(hipGetLastError());
+    }
     return FSG_OK;
 }
 
