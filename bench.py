@@ -176,8 +176,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the schedule(s) first with the library autotuner")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
-    ap.add_argument("--tune-steps", type=int, default=8,
-                    help="steps per timed candidate in the autotuner (c3)")
+    ap.add_argument("--tune-steps", type=int, default=0,
+                    help="autotuner window: runs of K and 2K steps per candidate; 0 = the "
+                         "workload's step cap (whole runs), or 64 for runs to absorption")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--schedule", default=None, help="JSON dict of fsg_schedule fields")
@@ -228,8 +229,9 @@ def main():
     dg = fsg.DeviceGraph(ptr, src, device="cuda:0")
     sched = json.loads(args.schedule) if args.schedule else {}
     if args.autotune:
+        ts = args.tune_steps or (c["max_steps"] if c["max_steps"] > 0 else 64)
         tuned, bms, dms = fsg.autotune(dg, c["model"], c["seeds"], c["B"], c["rng_key"],
-                                       cache_path=args.tune_cache, **params_of(c))
+                                       tune_steps=ts, cache_path=args.tune_cache, **params_of(c))
         log(f"[bench] autotuned {tuned}: {bms:.4f} ms/step vs default {dms:.4f}")
         sched.update({k: v for k, v in tuned.items() if v})
     sched["time_kernels"] = 1
@@ -420,7 +422,9 @@ def bench_batch(args):
         for j in jobs:
             prm = {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in j}
             best, bms, dms = fsg.autotune(j["graph"], j["model"], j["seeds"], j["B"], j["rng_key"],
-                                          tune_steps=args.tune_steps, batch_only=True,
+                                          tune_steps=args.tune_steps or
+                                          (prm["max_steps"] if prm.get("max_steps", -1) > 0 else 64),
+                                          batch_only=True,
                                           cache_path=args.tune_cache,
                                           **prm)
             j["schedule"] = best

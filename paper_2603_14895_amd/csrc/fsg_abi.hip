@@ -1340,7 +1340,8 @@ int fsg_autotune_workspace_size(const fsg_graph *g_, const fsg_params *prm, int6
         default_sched(g_, prm, B, &d);
         std::vector<fsg_schedule> cs = candidates(g_, prm, B, batch_only != 0);
         cs.push_back(d);
-        for (const fsg_schedule &s : cs) {
+        for (fsg_schedule s : cs) {
+            s.steps_per_sync = 64;  // the longest poll interval fsg_autotune uses
             size_t b = 0;
             rc = fsg_sim_workspace_size(g_, prm, B, &s, &b);
             if (rc) return rc;
