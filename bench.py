@@ -419,7 +419,7 @@ def bench_batch(args):
         f"{np.mean([j['B'] for j in jobs]):.0f} (built in {time.perf_counter() - t0:.1f}s)")
     if args.autotune:
         t1 = time.perf_counter()
-        for j in jobs:
+        for ji, j in enumerate(jobs):
             prm = {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in j}
             best, bms, dms = fsg.autotune(j["graph"], j["model"], j["seeds"], j["B"], j["rng_key"],
                                           tune_steps=args.tune_steps or
@@ -428,6 +428,8 @@ def bench_batch(args):
                                           cache_path=args.tune_cache,
                                           **prm)
             j["schedule"] = best
+            log(f"[bench] tuned job {ji + 1}/{len(jobs)} ({j['model']}): {bms:.4f} ms/step "
+                f"vs default {dms:.4f}")
         log(f"[bench] autotuned {len(jobs)} jobs in {time.perf_counter() - t1:.1f}s")
     batch = fsg.Batch(jobs, steps_per_sync=16, want_states=not args.no_states)
     log(f"[bench] batch workspace {batch.ws_bytes / 2**30:.2f} GiB")
