@@ -492,10 +492,14 @@ def hk(graph: DeviceGraph, h0, eps: float, max_steps: int, *, act: float = 0.5,
     return h, counts, info
 
 
-def autotune(graph: DeviceGraph, model, seeds, B, rng_key, *, tune_steps=12, batch_only=False,
+def autotune(graph: DeviceGraph, model, seeds, B, rng_key, *, tune_steps=None, batch_only=False,
              cache_path=None, **params):
-    """Runs the library's autotuner; returns (schedule dict, best ms/step, default ms/step)."""
+    """Runs the library's autotuner; returns (schedule dict, best ms/step, default ms/step).
+    tune_steps None: a window covering the run (the step cap, or 64 steps for runs to
+    absorption), since short windows from the seeds time only the run's early phase."""
     prm, keep = make_params(model, **params)
+    if tune_steps is None:
+        tune_steps = prm.max_steps if prm.max_steps > 0 else 64
     nb = fsg_autotune_workspace_size(graph.handle, prm, int(B), batch_only)
     ws, addr = _ws(nb, graph.device)
     seeds = np.ascontiguousarray(seeds, dtype=np.int32)
