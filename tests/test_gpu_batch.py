@@ -130,6 +130,12 @@ def test_autotune_and_cache():
         assert_same(tuned, plain, "tuned vs default schedule")
         bb, _, _ = fsg.autotune(dg, "ic", seeds, 64, 5, tune_steps=4, batch_only=True, p=0.05)
         assert bb["kernel_variant"] == 1
+        # windows longer than the poll interval cap (whole runs; the default window)
+        for ts in (200, None):
+            w, wms, dms3 = fsg.autotune(dg, "sir", seeds, 100, 78, tune_steps=ts, **kw)
+            assert wms <= dms3 + 1e-9 and wms > 0
+        w, _, _ = fsg.autotune(dg, "lt", seeds, 130, 79, tune_steps=100, max_steps=-1)
+        assert w["row_lanes"] >= 1
 
 
 def test_c3_full_size_every_job():
