@@ -333,7 +333,7 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
 struct Layout {
     size_t planes[4];
     int n_planes;
-    size_t flags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
+    size_t flags, wflags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
         seeds, bm[2], sum[2], need, total;
     int sum_shift, sum_words;
     int64_t W, plane_words, n_tinf, n_seed_stage;
@@ -382,6 +382,8 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
     }
     const int ring = s.sync + 1;
     L->flags = off; off = align256(off + (size_t)ring * 4);
+    L->wflags = off;  // per-word flags [ring + 1][W] when 16 < W <= 64
+    if (L->W > 16 && L->W <= 64) off = align256(off + (size_t)(ring + 1) * (size_t)L->W * 4);
     L->tiles = off; off = align256(off + p.tiles.size() * 4);
     L->heavy_rows = off; off = align256(off + (p.heavy_rows.size() + 1) * 4);
     L->heavy_seg = off; off = align256(off + p.heavy_seg.size() * 4);
@@ -496,6 +498,11 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
 
     for (int i = 0; i < L.n_planes; ++i) HIP_TRY(launch_fill64(jb->pl[i], L.plane_words, 0ull, st));
     HIP_TRY(launch_fill32(flags, ring, 0u, st));
+    uint32_t *wflags = (L.W > 16 && L.W <= 64) ? (uint32_t *)(base + L.wflags) : nullptr;
+    if (wflags) {  // every word is live before step 1 (slot 0); the others clear
+        HIP_TRY(launch_fill32(wflags, L.W, 1u, st));
+        HIP_TRY(launch_fill32(wflags + L.W, (int64_t)ring * L.W, 0u, st));
+    }
     if (s.edge1) {
         for (int i = 0; i < 2; ++i) {
             jb->bm[i] = (uint32_t *)(base + L.bm[i]);
@@ -558,6 +565,8 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.Lp = L.L;
     a.flags = flags;
     a.ring = ring;
+    a.wflags = wflags;
+    a.wring = ring + 1;
     a.dst = g->d_dst;
     a.nnz = g->nnz;
     a.sum_shift = L.sum_shift;
@@ -694,7 +703,7 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
     int64_t t = t_begin;
     while (!ss.absorbed && t < K) {
         const int64_t c = std::min<int64_t>(s.sync, K - t);
-        HIP_TRY(launch_ring_clear(flags, ring, (int32_t)(t % ring), st));
+        HIP_TRY(launch_ring_clear(flags, ring, (int32_t)(t % ring), st, a.wflags, a.W, a.wring, t));
         for (int64_t i = 1; i <= c; ++i) {
             const int64_t step = t + i;
             a.step = (uint32_t)step;

@@ -87,6 +87,13 @@ struct StepArgs {
     uint32_t *flags;
     int32_t ring;
     uint32_t step;
+    // the same flags per word of 64 replicates, [wring][W]: word w of slot
+    // t % wring is set iff the replicates of that word alone would set the
+    // flag above after step t.  Step t reads the slots of t-1 and t-2 and
+    // leaves out words clear in both.  Null unless 16 < W <= 64 (with fewer
+    // words a row's words take one pass of lanes anyway).
+    uint32_t *wflags;
+    int32_t wring;  // ring + 1 slots (step t must not clear t-1 or t-2)
 };
 
 struct FinArgs {
@@ -130,7 +137,9 @@ struct BatchCtl {
 // launchers (fsg_kernels.hip); return the hipError_t of the launch
 hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
-hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s);
+hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s,
+                             uint32_t *wflags = nullptr, int32_t W = 0, int32_t wring = 0,
+                             int64_t t = 0);
 hipError_t launch_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t ns, int32_t W,
                        int64_t B, uint32_t *flag0, uint32_t *bm, uint32_t *sum, int sum_shift,
                        hipStream_t s);

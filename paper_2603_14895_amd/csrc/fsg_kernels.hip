@@ -68,13 +68,13 @@ __device__ __forceinline__ void ic_edge(const StepArgs &a, int e, uint64_t f, ui
 
 __device__ __forceinline__ void ic_row_word(const StepArgs &a, int G, int S, bool valid, int v,
                                             int w, int e0, int e1, uint32_t tv, int s, int seg,
-                                            bool &any)
+                                            uint64_t lm, bool &any)
 {
     const int64_t idx = (int64_t)v * a.W + w;
     const int64_t W = a.W;
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
     const uint64_t A = valid ? a.aux[idx] : ~0ull;
-    const uint64_t cand = valid ? (~A & tail_mask(w, a.B)) : 0ull;
+    const uint64_t cand = valid ? (~A & tail_mask(w, a.B) & lm) : 0ull;
     uint64_t acc = 0;
     if (S == 1 && G >= 16 && a.fast32 && seg < 0) {
         // 16 arcs of the row per pass: lane lr of each 16-lane DPP row loads
@@ -438,13 +438,13 @@ template <int L>
 __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bool valid, int v,
                                              int w, int e0, int e1, int s, int seg,
                                              uint64_t share, const uint32_t *tl, int tl_n,
-                                             const uint32_t *tcode, bool &any)
+                                             const uint32_t *tcode, uint64_t lm, bool &any)
 {
     const int64_t idx = (int64_t)v * a.W + w;
     const uint64_t h = valid ? a.prev[idx] : 0ull;
     const uint64_t r = valid ? a.aux[idx] : 0ull;
     const uint64_t e = (valid && a.lat) ? a.lat[idx] : 0ull;
-    const uint64_t sus = valid ? (~(h | r | e) & tail_mask(w, a.B)) : 0ull;
+    const uint64_t sus = valid ? (~(h | r | e) & tail_mask(w, a.B) & lm) : 0ull;
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
@@ -582,11 +582,11 @@ __device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool 
 template <int L>
 __device__ __forceinline__ void lt_row_word(const StepArgs &a, int G, int S, bool valid, int v,
                                             int w, int e0, int e1, uint32_t indeg, int s, int seg,
-                                            uint64_t share, bool &any)
+                                            uint64_t share, uint64_t lm, bool &any)
 {
     const int64_t idx = (int64_t)v * a.W + w;
     const uint64_t act = valid ? a.prev[idx] : 0ull;
-    const uint64_t inact = valid ? (~act & tail_mask(w, a.B)) : 0ull;
+    const uint64_t inact = valid ? (~act & tail_mask(w, a.B) & lm) : 0ull;
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
@@ -615,7 +615,7 @@ template <int KIND, int L>
 __device__ __forceinline__ void row_word(const StepArgs &a, int G, int S, bool valid, int v, int w,
                                          int e0, int e1, uint32_t indeg, int s, int seg,
                                          uint64_t share_fixed, const uint32_t *tl, int tl_n,
-                                         const uint32_t *tcode,
+                                         const uint32_t *tcode, uint64_t lm,
                                          bool &any)
 {
     // draws of lane s: generator blocks congruent to s mod S; for S <= 16 the
@@ -625,12 +625,104 @@ __device__ __forceinline__ void row_word(const StepArgs &a, int G, int S, bool v
     if (KIND == kKindIC) {
         uint32_t tv = a.ic_t;
         if (a.ic_prob == kIcWeightedCascade) tv = wc_threshold(indeg);
-        ic_row_word(a, G, S, valid, v, w, e0, e1, tv, s, seg, any);
+        ic_row_word(a, G, S, valid, v, w, e0, e1, tv, s, seg, lm, any);
     } else if (KIND == kKindEpidemic) {
-        epi_row_word<L>(a, G, S, valid, v, w, e0, e1, s, seg, share, tl, tl_n, tcode, any);
+        epi_row_word<L>(a, G, S, valid, v, w, e0, e1, s, seg, share, tl, tl_n, tcode, lm, any);
     } else {
-        lt_row_word<L>(a, G, S, valid, v, w, e0, e1, indeg, s, seg, share, any);
+        lt_row_word<L>(a, G, S, valid, v, w, e0, e1, indeg, s, seg, share, lm, any);
     }
+}
+
+// Words a wave works on at step t = a.step.  A word whose flag is clear
+// after step t-1 cannot change at step t (no frontier, no infectious or
+// latent replicate, or no activation under fixed thresholds).  If its flag
+// after step t-2 is clear too, the state buffer step t writes already holds
+// the word's state (state t-2 = t-1 = t) and the word is left out; otherwise
+// it takes a pass with its candidates masked off, which copies it forward.
+// `any` lists the words worked on, `live` those with candidates; with word
+// flags, pass k gives lane gw the (k G + gw)-th word of `any`.
+struct WordMap {
+    uint64_t any, live;
+    int passes, count;
+    bool compact;
+};
+
+// All 64 lanes of the wave call this together.
+__device__ __forceinline__ WordMap word_map(const StepArgs &a, int G)
+{
+    WordMap m;
+    m.compact = a.wflags != nullptr;
+    if (!m.compact) {
+        m.any = m.live = ~0ull;
+        m.count = a.W;
+    } else {
+        const uint32_t t = a.step, wr = (uint32_t)a.wring;
+        const uint32_t *f1 = a.wflags + (size_t)((t - 1u) % wr) * (size_t)a.W;
+        const uint32_t *f2 = a.wflags + (size_t)((t + wr - 2u) % wr) * (size_t)a.W;
+        const int lane = (int)(threadIdx.x & 63u);
+        uint32_t x1 = 0u, x2 = 0u;
+        if (lane < a.W) {
+            x1 = f1[lane];
+            x2 = f2[lane];
+        }
+        m.live = __ballot(x1 != 0u);
+        m.any = __ballot((x1 | x2) != 0u);
+        m.count = __popcll(m.any);
+    }
+    m.passes = (m.count + G - 1) / G;
+    return m;
+}
+
+// Position of the j-th (from 0) set bit of m; j < popcount(m).
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int j)
+{
+    int pos = 0;
+    int c = __popc((uint32_t)m);
+    if (j >= c) {
+        j -= c;
+        m >>= 32;
+        pos = 32;
+    }
+    uint32_t x = (uint32_t)m;
+    c = __popc(x & 0xFFFFu);
+    if (j >= c) { j -= c; x >>= 16; pos += 16; }
+    c = __popc(x & 0xFFu);
+    if (j >= c) { j -= c; x >>= 8; pos += 8; }
+    c = __popc(x & 0xFu);
+    if (j >= c) { j -= c; x >>= 4; pos += 4; }
+    c = __popc(x & 0x3u);
+    if (j >= c) { j -= c; x >>= 2; pos += 2; }
+    if (j >= (int)(x & 1u)) pos += 1;
+    return pos;
+}
+
+// Word of lane gw in pass k, whether it exists, and its candidate mask.
+__device__ __forceinline__ int word_of(const WordMap &m, int k, int G, int gw, bool &ok,
+                                       uint64_t &lm)
+{
+    const int j = k * G + gw;
+    ok = j < m.count;
+    if (!m.compact) {
+        lm = ~0ull;
+        return ok ? j : 0;
+    }
+    const int w = ok ? nth_set_bit(m.any, j) : 0;
+    lm = ((m.live >> w) & 1ull) ? ~0ull : 0ull;
+    return w;
+}
+
+// Records the word flags of step a.step: lanes of one pass that share gw
+// share the word, so the ballot is folded onto its low G bits and lane gw
+// stores for its word.  All 64 lanes of the wave call this together.
+__device__ __forceinline__ void note_words(const StepArgs &a, int G, int w, bool ok, bool anyw)
+{
+    if (a.wflags == nullptr) return;
+    uint64_t m = __ballot(anyw);
+    if (m == 0ull) return;
+    for (int sh = 32; sh >= G; sh >>= 1) m |= m >> sh;
+    const int lane = (int)(threadIdx.x & 63u);
+    if (lane < G && ((m >> lane) & 1ull) && ok)
+        a.wflags[(size_t)(a.step % (uint32_t)a.wring) * (size_t)a.W + (size_t)w] = 1u;
 }
 
 // Work of one block of the pull step: block `bid` < seg_blocks owns heavy-row
@@ -643,21 +735,33 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
-    const int G = a.G, S = a.S;
-    const int lgGS = a.lgG + a.lgS;
-    const int rpw = 64 >> lgGS;
-    const int slot = lane >> lgGS;
-    const int s = (lane >> a.lgG) & (S - 1);
-    const int gw = lane & (G - 1);
-    const uint64_t share_fixed = S <= 16 ? share_bits(a.goff, s, S) : 0ull;
+    const int S = a.S;
+    const WordMap wm = word_map(a, a.G);
     // heavy-row segments take a whole wave each: G lanes over words, the
     // other 64 / G lanes over the segment's arcs
     const int seg_blocks = (a.n_seg + nwaves - 1) / nwaves;
     if (bid >= seg_blocks) {
+        // light rows: once fewer words are left than the row has word lanes,
+        // the row gets next_pow2(words) lanes (not below 16, which keeps the
+        // DPP source broadcast) and the wave takes more rows
+        int lgGe = a.lgG;
+        if (wm.compact) {
+            int lg = 0;
+            while ((1 << lg) < wm.count) ++lg;
+            const int lo = a.lgG < 4 ? a.lgG : 4;
+            lgGe = lg < lo ? lo : (lg > a.lgG ? a.lgG : lg);
+        }
+        const int Ge = 1 << lgGe;
+        const int rpwe = 64 >> (lgGe + a.lgS);
+        const int slote = lane >> (lgGe + a.lgS);
+        const int se = (lane >> lgGe) & (S - 1);
+        const int gwe = lane & (Ge - 1);
+        const uint64_t share_e = S <= 16 ? share_bits(a.goff, se, S) : 0ull;
+        const int passes = (wm.count + Ge - 1) / Ge;
         const int tile = bid - seg_blocks;
         const int t0 = a.tiles[2 * tile], t1 = a.tiles[2 * tile + 1];
-        for (int rb = t0 + wave * rpw; rb < t1; rb += nwaves * rpw) {
-            const int v = rb + slot;
+        for (int rb = t0 + wave * rpwe; rb < t1; rb += nwaves * rpwe) {
+            const int v = rb + slote;
             bool act = v < t1;
             int e0 = 0, e1 = 0;
             if (act) {
@@ -665,15 +769,31 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                 e1 = a.ptr[v + 1];
                 if (e1 - e0 > a.heavy) act = false;
             }
-            for (int w0 = 0; w0 < a.W; w0 += G) {
-                const int w = w0 + gw;
-                row_word<KIND, L>(a, G, S, act && w < a.W, v, w < a.W ? w : 0, e0, e1,
-                                  (uint32_t)(e1 - e0), s, -1, share_fixed, tl, tl_n, tcode, any);
+            for (int k = 0; k < passes; ++k) {
+                bool ok;
+                uint64_t lm;
+                const int w = word_of(wm, k, Ge, gwe, ok, lm);
+                bool anyw = false;
+                row_word<KIND, L>(a, Ge, S, act && ok, v, w, e0, e1, (uint32_t)(e1 - e0), se, -1,
+                                  share_e, tl, tl_n, tcode, lm, anyw);
+                note_words(a, Ge, w, ok, anyw);
+                any |= anyw;
             }
         }
     } else {
-        const int Ss = 64 >> a.lgG;  // edge lanes of a segment
-        const int ss = lane >> a.lgG;
+        // with fewer words left than word lanes, next_pow2(words) word lanes
+        // and the rest over the segment's arcs (a shorter chain per lane)
+        int lgGs = a.lgG;
+        if (wm.compact) {
+            int lg = 0;
+            while ((1 << lg) < wm.count) ++lg;
+            lgGs = lg > a.lgG ? a.lgG : lg;
+        }
+        const int Gs = 1 << lgGs;
+        const int Ss = 64 >> lgGs;  // edge lanes of a segment
+        const int ss = lane >> lgGs;
+        const int gws = lane & (Gs - 1);
+        const int passes = (wm.count + Gs - 1) / Gs;
         const uint64_t share_seg = Ss <= 16 ? share_bits(a.goff, ss, Ss) : 0ull;
         const int seg = bid * nwaves + wave;
         const bool act = seg < a.n_seg;
@@ -685,10 +805,12 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
             e1 = a.seg_e1[seg];
             indeg = (uint32_t)(a.ptr[v + 1] - a.ptr[v]);
         }
-        for (int w0 = 0; w0 < a.W; w0 += G) {
-            const int w = w0 + gw;
-            row_word<KIND, L>(a, G, Ss, act && w < a.W, v, w < a.W ? w : 0, e0, e1, indeg, ss,
-                              act ? seg : 0, share_seg, tl, tl_n, tcode, any);
+        for (int k = 0; k < passes; ++k) {
+            bool ok;
+            uint64_t lm;
+            const int w = word_of(wm, k, Gs, gws, ok, lm);
+            row_word<KIND, L>(a, Gs, Ss, act && ok, v, w, e0, e1, indeg, ss, act ? seg : 0,
+                              share_seg, tl, tl_n, tcode, lm, any);
         }
     }
 }
@@ -738,14 +860,17 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
     const int v = act ? a.heavy_rows[j] : 0;
     const int sg0 = act ? a.heavy_seg[j] : 0, sg1 = act ? a.heavy_seg[j + 1] : 0;
     const uint64_t share = share_bits(a.goff, ss, S2);
-    for (int w0 = 0; w0 < a.W; w0 += G) {
-        const int w = w0 + gw;
-        const bool valid = act && w < a.W;
-        const int ww = w < a.W ? w : 0;
+    const WordMap wm = word_map(a, G);
+    for (int k = 0; k < wm.passes; ++k) {
+        bool ok;
+        uint64_t lm;
+        const int ww = word_of(wm, k, G, gw, ok, lm);
+        const bool valid = act && ok;
         const int64_t idx = (int64_t)v * a.W + ww;
+        bool anyw = false;
         if (KIND == kKindIC) {
             uint64_t acc = 0;
-            if (valid)
+            if (valid && lm)
                 for (int sg = sg0 + ss; sg < sg1; sg += S2) acc |= a.partial[(int64_t)sg * a.W + ww];
             acc = or_reduce_lanes(acc, G, S2);
             if (valid && ss == 0) {
@@ -753,13 +878,13 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
                 acc &= ~A;
                 a.next[idx] = acc;
                 a.aux[idx] = A | acc;
-                any |= acc != 0;
+                anyw = acc != 0;
             }
         } else {
             uint64_t c[LC];
 #pragma unroll
             for (int l = 0; l < LC; ++l) c[l] = 0;
-            if (valid) {
+            if (valid && lm) {
                 for (int sg = sg0 + ss; sg < sg1; sg += S2) {
                     uint64_t d[LC];
 #pragma unroll
@@ -773,21 +898,23 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
                 const uint64_t h = valid ? a.prev[idx] : 0ull;
                 const uint64_t r = valid ? a.aux[idx] : 0ull;
                 const uint64_t e = (valid && a.lat) ? a.lat[idx] : 0ull;
-                const uint64_t sus = valid ? (~(h | r | e) & tail_mask(ww, a.B)) : 0ull;
+                const uint64_t sus = valid ? (~(h | r | e) & tail_mask(ww, a.B) & lm) : 0ull;
 #pragma unroll
                 for (int l = 0; l < LC; ++l) c[l] &= sus;
                 epi_decide<LC>(a, G, S2, valid, v, ww, idx, h, r, e, sus, c, ss, share, nullptr, 0,
-                               tcode, any);
+                               tcode, anyw);
             } else {
                 const uint64_t act_w = valid ? a.prev[idx] : 0ull;
-                const uint64_t inact = valid ? (~act_w & tail_mask(ww, a.B)) : 0ull;
+                const uint64_t inact = valid ? (~act_w & tail_mask(ww, a.B) & lm) : 0ull;
 #pragma unroll
                 for (int l = 0; l < LC; ++l) c[l] &= inact;
                 const uint32_t indeg = act ? (uint32_t)(a.ptr[v + 1] - a.ptr[v]) : 0u;
                 lt_decide<LC>(a, G, S2, valid, v, ww, idx, act_w, inact, indeg, c, ss, share, false,
-                              any);
+                              anyw);
             }
         }
+        note_words(a, G, ww, ok, anyw);
+        any |= anyw;
     }
 }
 
@@ -1099,6 +1226,13 @@ __global__ void k_batch_advance(BatchCtl c)
     const uint32_t t = *c.cur_step;
     for (int j = threadIdx.x; j < c.n_jobs; j += blockDim.x)
         c.jobs[j].flags[(t + 1) % (uint32_t)c.ring] = 0u;
+    for (int j = 0; j < c.n_jobs; ++j) {
+        uint32_t *wf = c.jobs[j].wflags;
+        if (wf == nullptr) continue;
+        const int W = c.jobs[j].W;
+        wf += (size_t)((t + 1) % (uint32_t)c.jobs[j].wring) * (size_t)W;
+        for (int i = threadIdx.x; i < W; i += blockDim.x) wf[i] = 0u;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         c.queue[0] = 0u;
@@ -1125,10 +1259,19 @@ __global__ void k_fill32(uint32_t *p, int64_t count, uint32_t value)
 
 // Clears every absorption flag of the ring except slot `keep` (the step
 // before the next chunk).
-__global__ void k_ring_clear(uint32_t *flags, int32_t ring, int32_t keep)
+// With word flags, the slots of steps t and t-1 are kept (the next step
+// reads both).
+__global__ void k_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, uint32_t *wflags,
+                             int32_t W, int32_t wring, int64_t t)
 {
     for (int i = threadIdx.x; i < ring; i += blockDim.x)
         if (i != keep) flags[i] = 0u;
+    if (wflags == nullptr) return;
+    const int64_t k1 = t % wring, k2 = (t + wring - 1) % wring;
+    for (int64_t i = threadIdx.x; i < (int64_t)wring * W; i += blockDim.x) {
+        const int64_t sl = i / W;
+        if (sl != k1 && sl != k2) wflags[i] = 0u;
+    }
 }
 
 // Seeds are in state 1 in every replicate (Algorithm 1, initial states).
@@ -1306,9 +1449,11 @@ hipError_t launch_lt_need(const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s)
+hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s,
+                             uint32_t *wflags, int32_t W, int32_t wring, int64_t t)
 {
-    hipLaunchKernelGGL(k_ring_clear, dim3(1), dim3(256), 0, s, flags, ring, keep);
+    hipLaunchKernelGGL(k_ring_clear, dim3(1), dim3(256), 0, s, flags, ring, keep, wflags, W,
+                       wring, t);
     return hipGetLastError();
 }
 

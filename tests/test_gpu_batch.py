@@ -43,6 +43,11 @@ def _mixed_jobs():
         ("seir", 2400, 14.0, 700, 0, dict(beta=0.04, alpha=0.3, gamma=0.1, max_steps=35), None),
         ("seis", 1700, 9.0, 90, 1, dict(beta=0.08, alpha=0.4, gamma=0.25, max_steps=20),
          dict(heavy_threshold=25)),
+        # more than 16 words per node: words that stopped changing are left out
+        ("lt", 1600, 12.0, 1100, 0, dict(max_steps=-1), dict(heavy_threshold=20)),
+        ("ic", 1500, 10.0, 1500, 2, dict(p=0.1, max_steps=-1), None),
+        ("sir", 1200, 10.0, 1300, 0, dict(beta=0.05, gamma=0.2, max_steps=40),
+         dict(row_lanes=16, heavy_threshold=24)),
     ]
     jobs = []
     for i, (model, n, deg, B, off, prm, sched) in enumerate(specs):

@@ -132,6 +132,34 @@ def test_schedules_and_heavy_rows(model, sched):
           alpha=0.3, max_steps=K, schedule=sched, replicate_offset=9)
 
 
+@pytest.mark.parametrize("model", ["ic", "sir", "lt", "seir"])
+@pytest.mark.parametrize("sched", [
+    None,
+    dict(row_lanes=16, heavy_threshold=20, steps_per_sync=1),
+    dict(row_lanes=64, block_threads=128, tile_edges=700, heavy_threshold=9, steps_per_sync=2),
+])
+def test_word_absorption_skip(model, sched):
+    """With more than 16 words per node, a word none of whose replicates can
+    change any more is left out of later steps (fewer lanes per row, more
+    rows per wave, more edge lanes per heavy segment): same bits as the
+    oracle, with heavy-row segments and the shortest host sync cadences (a
+    word-flag ring of three slots)."""
+    gr = W.chung_lu(1500, 12.0, 2.5, 71)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 3, 72)
+    K = -1 if model in ("ic", "lt") else 60
+    prm = dict(p=0.1, beta=0.05, gamma=0.2, alpha=0.3, max_steps=K)
+    B = 1100
+    g = _both(gnp, model, seeds, B, 0x3D0 + len(model), f"word-skip-{sched}", schedule=sched,
+              replicate_offset=4, **prm)
+    # the case is not vacuous: words stop changing at different steps
+    okw = {k: v for k, v in prm.items() if k != "max_steps"}
+    steps = [oracle_run(gnp, model, seeds, 64, 0x3D0 + len(model), replicate_offset=4 + 64 * w,
+                        max_steps=K, **okw)[2] for w in range(0, B // 64, 4)]
+    if model in ("ic", "lt"):
+        assert len(set(steps)) > 1 and min(steps) < g[2], steps
+
+
 def test_edge_cases():
     # self-loops, repeated arcs, isolated nodes, an in-star hub
     edges = [(0, 1), (0, 1), (1, 1), (1, 2), (2, 3), (3, 1), (5, 5)] + [(i, 6) for i in range(7, 40)]
