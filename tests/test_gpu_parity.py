@@ -160,6 +160,20 @@ def test_word_absorption_skip(model, sched):
         assert len(set(steps)) > 1 and min(steps) < g[2], steps
 
 
+@pytest.mark.parametrize("model", ["lt", "sir", "ic"])
+@pytest.mark.parametrize("B", [1025, 4096, 4097])
+def test_word_absorption_limits(model, B):
+    """Word flags start at 17 words per node (1025 replicates, a one-replicate
+    last word), end at 64 (4096 replicates: every lane of the wave holds a
+    word flag) and are off from 65: all three give the oracle's bits."""
+    gr = W.chung_lu(900, 10.0, 2.5, 81)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 2, 82)
+    K = -1 if model in ("ic", "lt") else 40
+    _both(gnp, model, seeds, B, 0x5EED + B, f"word-limits-{B}", p=0.1, beta=0.05, gamma=0.2,
+          max_steps=K, replicate_offset=1)
+
+
 def test_edge_cases():
     # self-loops, repeated arcs, isolated nodes, an in-star hub
     edges = [(0, 1), (0, 1), (1, 1), (1, 2), (2, 3), (3, 1), (5, 5)] + [(i, 6) for i in range(7, 40)]
