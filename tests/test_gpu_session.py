@@ -27,6 +27,10 @@ CASES = [
     ("sir", 1800, 15.0, 256, 0, dict(beta=0.05, gamma=0.2, max_steps=25),
      dict(heavy_threshold=20, row_lanes=4)),
     ("seir", 2000, 12.0, 512, 0, dict(beta=0.05, alpha=0.3, gamma=0.15, max_steps=40), None),
+    # more than 16 words per node: word flags kept across calls (two-step ring margin)
+    ("lt", 1500, 10.0, 1100, 0, dict(max_steps=-1), dict(steps_per_sync=2)),
+    ("sir", 1200, 12.0, 1300, 3, dict(beta=0.05, gamma=0.2, max_steps=60),
+     dict(steps_per_sync=1, heavy_threshold=20)),
 ]
 
 
@@ -58,6 +62,9 @@ def test_session_resume_is_exact(case):
     ss.close()
     log(f"[session] {model} B={B}: steps {got[2]} absorbed {got[3]}")
     assert_same(got, whole, f"case {case} stepped vs one call")
+    if B > 1024:
+        assert_same(got, oracle_run(gnp, model, seeds, B, key, replicate_offset=off, **prm),
+                    f"case {case} stepped vs oracle")
 
 
 @pytest.mark.parametrize("case", [0, 2, 4, 6])
