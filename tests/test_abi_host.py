@@ -102,6 +102,31 @@ def test_params_validation_before_any_launch():
         fsg.fsg_graph_destroy(h)
 
 
+def test_word_flag_ring_in_workspace():
+    """Jobs with 17 to 64 words per node carry a word-flag ring of
+    steps_per_sync + 2 slots of W flags; the others carry none.  Only the two
+    flag rings depend on steps_per_sync, so the workspace difference between
+    two cadences is the ring growth alone."""
+    ptr, src = _graph()
+    n, nnz = ptr.size - 1, src.size
+    h = fsg.fsg_graph_create(n, nnz, ptr.ctypes.data, src.ctypes.data)
+    try:
+        prm, _ = fsg.make_params("ic", p=0.1)
+
+        def a256(x):
+            return (x + 255) // 256 * 256
+
+        for W in (1, 2, 16, 17, 40, 64, 65):
+            B = 64 * W - (W > 1)  # a ragged last word
+            ws = [fsg.fsg_sim_workspace_size(h, prm, B, fsg.make_schedule(dict(steps_per_sync=k)))
+                  for k in (1, 9)]
+            job_ring = a256(10 * 4) - a256(2 * 4)
+            word_ring = a256(11 * W * 4) - a256(3 * W * 4) if 16 < W <= 64 else 0
+            assert ws[1] - ws[0] == job_ring + word_ring, W
+    finally:
+        fsg.fsg_graph_destroy(h)
+
+
 def test_hk_entry_points_refuse_unbound_graphs_on_the_host():
     ptr, src = _graph()
     n, nnz = ptr.size - 1, src.size
