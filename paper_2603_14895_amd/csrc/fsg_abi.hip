@@ -334,7 +334,7 @@ struct Layout {
     size_t planes[4];
     int n_planes;
     size_t flags, wflags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
-        seeds, bm[2], sum[2], need, total;
+        seeds, bm[2], sum[2], need, stamp, total;
     int sum_shift, sum_words;
     int64_t W, plane_words, n_tinf, n_seed_stage;
     int L;
@@ -399,6 +399,8 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
     L->need = off;
     if (kind == kKindLT)  // bit-sliced thresholds [n][L][W]
         off = align256(off + (size_t)g->n * (size_t)L->L * (size_t)L->W * 8);
+    L->stamp = off;
+    if (kind == kKindLT) off = align256(off + (size_t)g->n * 8);  // gain steps, two arrays
     L->bm[0] = L->bm[1] = L->sum[0] = L->sum[1] = 0;
     L->sum_shift = 0;
     L->sum_words = 0;
@@ -512,10 +514,12 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
         }
     }
     int32_t *dseeds = (int32_t *)(base + L.seeds);
+    if (kind == kKindLT) HIP_TRY(launch_fill32((uint32_t *)(base + L.stamp), 2 * g->n, 0xFFFFFFFFu, st));
     for (int64_t i0 = 0; i0 < n_seeds; i0 += L.n_seed_stage) {
         const int64_t cnt = std::min<int64_t>(L.n_seed_stage, n_seeds - i0);
         HIP_TRY(hipMemcpyAsync(dseeds, seeds + i0, (size_t)cnt * 4, hipMemcpyHostToDevice, st));
         uint64_t *second = kind == kKindIC ? jb->pl[2] : nullptr;  // IC: A too
+        if (kind == kKindLT) HIP_TRY(launch_stamp_seeds((uint32_t *)(base + L.stamp), dseeds, cnt, st));
         HIP_TRY(launch_seed(jb->pl[0], second, dseeds, cnt, (int32_t)L.W, B, flags, jb->bm[0],
                             jb->sum[0], L.sum_shift, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -572,6 +576,7 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.sum_shift = L.sum_shift;
     a.sum_words = L.sum_words;
     a.need = nullptr;
+    a.stamp = kind == kKindLT ? (uint32_t *)(base + L.stamp) : nullptr;
     if (kind == kKindLT && g->n > 0) {
         a.need = (uint64_t *)(base + L.need);
         HIP_TRY(launch_lt_need(a, st));

@@ -71,6 +71,11 @@ struct StepArgs {
     // bit-sliced: plane p of node v at need[(v Lp + p) W + w], written for
     // p < bitlen(indeg(v)) <= Lp once per run; null for the other models
     uint64_t *need;
+    // LT: [2][n], array t & 1 holds t for the nodes that gained an
+    // activation (any replicate) at step t; step t reads array (t-1) & 1,
+    // which no one writes during step t.  Seeds: 0 in array 0.  Null for
+    // the other models.
+    uint32_t *stamp;
     // frontier bitmaps of the edge-parallel IC kernel: bit u of bm_prev is set
     // iff node u has a newly active replicate after step t-1 (prev is only
     // meaningful where it is set); bm_next is cleared before step t
@@ -137,6 +142,7 @@ struct BatchCtl {
 // launchers (fsg_kernels.hip); return the hipError_t of the launch
 hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
+hipError_t launch_stamp_seeds(uint32_t *stamp, const int32_t *seeds, int64_t ns, hipStream_t s);
 hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s,
                              uint32_t *wflags = nullptr, int32_t W = 0, int32_t wring = 0,
                              int64_t t = 0);

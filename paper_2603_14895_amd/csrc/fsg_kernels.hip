@@ -576,6 +576,8 @@ __device__ __forceinline__ void lt_decide(const StepArgs &a, int G, int S, bool 
     nw = or_reduce_lanes(nw, G, S);
     if (!valid || s != 0) return;
     a.next[idx] = act | nw;
+    if (nw != 0ull && a.stamp != nullptr)
+        a.stamp[(size_t)(a.step & 1u) * (size_t)a.n + (size_t)v] = a.step;
     any |= nw != 0;
 }
 
@@ -760,6 +762,15 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
         const int passes = (wm.count + Ge - 1) / Ge;
         const int tile = bid - seg_blocks;
         const int t0 = a.tiles[2 * tile], t1 = a.tiles[2 * tile + 1];
+        // LT once at most half of the words are left: thresholds are fixed,
+        // so a row none of whose in-neighbours gained an activation at step
+        // t-1 has the counts it was last decided on and cannot activate; it
+        // takes the copy pass without counting (earlier, nearly every row
+        // has such a neighbour and the test would only add loads)
+        const bool fresh_test = KIND == kKindLT && a.stamp != nullptr && wm.compact &&
+                                wm.count * 2 <= a.W;
+        const int rl = 1 << (lgGe + a.lgS);  // lanes of a row
+        const uint64_t rowmask = (rl == 64 ? ~0ull : ((1ull << rl) - 1ull)) << (slote * rl);
         for (int rb = t0 + wave * rpwe; rb < t1; rb += nwaves * rpwe) {
             const int v = rb + slote;
             bool act = v < t1;
@@ -769,13 +780,22 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                 e1 = a.ptr[v + 1];
                 if (e1 - e0 > a.heavy) act = false;
             }
+            uint64_t rowlm = ~0ull;
+            if (fresh_test) {
+                const uint32_t *gained = a.stamp + (size_t)((a.step - 1u) & 1u) * (size_t)a.n;
+                bool f = false;
+                if (act)
+                    for (int e = e0 + (lane & (rl - 1)); e < e1 && !f; e += rl)
+                        f = gained[a.src[e]] == a.step - 1u;
+                if ((__ballot(f) & rowmask) == 0ull) rowlm = 0ull;
+            }
             for (int k = 0; k < passes; ++k) {
                 bool ok;
                 uint64_t lm;
                 const int w = word_of(wm, k, Ge, gwe, ok, lm);
                 bool anyw = false;
                 row_word<KIND, L>(a, Ge, S, act && ok, v, w, e0, e1, (uint32_t)(e1 - e0), se, -1,
-                                  share_e, tl, tl_n, tcode, lm, anyw);
+                                  share_e, tl, tl_n, tcode, lm & rowlm, anyw);
                 note_words(a, Ge, w, ok, anyw);
                 any |= anyw;
             }
@@ -1250,6 +1270,13 @@ __global__ void k_fill64(uint64_t *p, int64_t count, uint64_t value)
         p[i] = value;
 }
 
+__global__ void k_stamp_seeds(uint32_t *stamp, const int32_t *seeds, int64_t ns)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns;
+         i += (int64_t)gridDim.x * blockDim.x)
+        stamp[seeds[i]] = 0u;
+}
+
 __global__ void k_fill32(uint32_t *p, int64_t count, uint32_t value)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -1432,6 +1459,13 @@ hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t
 {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill64, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp_seeds(uint32_t *stamp, const int32_t *seeds, int64_t ns, hipStream_t s)
+{
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stamp_seeds, dim3(grid_for(ns, 256)), dim3(256), 0, s, stamp, seeds, ns);
     return hipGetLastError();
 }
 
