@@ -277,6 +277,9 @@ void default_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_sch
     memset(o, 0, sizeof(*o));
     // lanes over words first; an edge split only for narrow batches
     o->row_lanes = (int32_t)std::max<int64_t>(16, std::min<int64_t>(next_pow2(W), 64));
+    // SI-family rows of 33-48 words: three 16-lane passes fill 48 lane slots
+    // where one 64-lane pass leaves up to 31 idle through the draws
+    if (model_kind(prm->model) == kKindEpidemic && W > 32 && W <= 48) o->row_lanes = 16;
     o->block_threads = 256;
     o->tile_edges = 4096;
     o->heavy_threshold = 1024;
