@@ -4,8 +4,8 @@ with Monte Carlo fallback.
 
 Orchestration only: labels come from the batched simulator (fsg_batch_run),
 the network's forward, backward and Adam steps are the library's kernels
-(fsg_gnn_*), and every fallback is a plain fsg_simulate call.  The plain
-simulator is also the judge of the surrogate's error.
+(fsg_gnn_*), and every fallback is a plain fsg_simulate call.  The surrogate's
+error is measured against plain simulator runs.
 """
 from __future__ import annotations
 
