@@ -465,7 +465,8 @@ def bench_batch(args):
                    "B": [j["B"] for j in jobs], "steps_run": steps_run,
                    "autotuned": bool(args.autotune), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic("c3"),
                      "kernel": "k_batch_step + k_batch_combine (captured step chunks)",
                      "avg_launch_ms": round(dev_ms / args.steps / max(1, max(steps_run)), 5),
                      "launches": args.steps * max(steps_run),
