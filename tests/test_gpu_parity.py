@@ -174,6 +174,25 @@ def test_word_absorption_limits(model, B):
           max_steps=K, replicate_offset=1)
 
 
+def test_lt_row_test_on_long_tails():
+    """LT rows skip their count once at most half of the words are left and
+    none of their in-neighbours gained an activation at the step before.  A
+    directed path with a few random extra arcs makes cascades run for very
+    different lengths across replicates, so most words stop long before the
+    last one and the skip runs for many steps: same bits as the oracle."""
+    n = 700
+    rng = np.random.default_rng(91)
+    extra = rng.integers(0, n, size=(900, 2))
+    edges = [(i, i + 1) for i in range(n - 1)] + [(int(u), int(v)) for u, v in extra if u != v]
+    gnp = W.from_edges(n, edges).numpy()
+    seeds = np.array([0], dtype=np.int32)
+    B, key = 2600, 0x7A1
+    g = _both(gnp, "lt", seeds, B, key, "lt-long-tails", max_steps=-1, replicate_offset=8)
+    steps = [oracle_run(gnp, "lt", seeds, 64, key, replicate_offset=8 + 64 * w, max_steps=-1)[2]
+             for w in range(B // 64)]
+    assert sorted(steps)[len(steps) // 2] + 10 < g[2], (sorted(steps), g[2])
+
+
 def test_edge_cases():
     # self-loops, repeated arcs, isolated nodes, an in-star hub
     edges = [(0, 1), (0, 1), (1, 1), (1, 2), (2, 3), (3, 1), (5, 5)] + [(i, 6) for i in range(7, 40)]
