@@ -8,10 +8,12 @@ timed region.  The metric is replicate-edge updates per second:
 nnz * B * steps_run / wall time of the step.
 
 Workloads (synthetic stand-ins for the paper's datasets):
+  c4  IC weighted cascade on R-MAT scale 26 (2^26 nodes, edge factor 16,
+      2^30 arcs), 50 seeds, B=64, to absorption  (default: the largest
+      single-GPU configuration, the web-scale run of Sec. 5)
   c2  SIR on Chung-Lu n=1e6 (exponent 2.5, mean degree 20), beta 0.02,
-      gamma 0.1, 1% seeds, B=1024, 200 steps            (default)
+      gamma 0.1, 1% seeds, B=1024, 200 steps
   c1  IC on directed G(1000, mean out-degree 10), p 0.1, B=100
-  c4  IC weighted cascade on R-MAT scale 26, edge factor 16, B=64
   c5  learned surrogate: GNN trained on simulator labels (Chung-Lu n=1e5,
       4 graphs x 500 seed sets x 1024 replicates), evaluated on 2 unseen
       graphs x 100 queries against 4096-replicate Monte Carlo
@@ -129,13 +131,44 @@ def params_of(c):
     return dict(max_steps=c["max_steps"])
 
 
+def host_cpu():
+    """Host threads the oracle may use and what the host is: the CPUs this
+    process may run on (sched_getaffinity), capped by OMP_NUM_THREADS when it
+    is set (the host's CPU share per GPU), plus the CPU model name."""
+    try:
+        visible = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        visible = os.cpu_count() or 1
+    threads = visible
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    if share.isdigit() and int(share) > 0:
+        threads = min(threads, int(share))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"threads": max(1, threads), "visible_cpus": visible, "omp_num_threads": share or None,
+            "cpu_model": model}
+
+
+def cpu_fields(hc):
+    return {"cores": hc["threads"], "cpu_model": hc["cpu_model"],
+            "visible_cpus": hc["visible_cpus"], "omp_num_threads": hc["omp_num_threads"]}
+
+
 def cpu_baseline(c, ptr, src, target_seconds: float):
     """The oracle as it stands on a bounded sample of the same workload: a
     subset of the replicates (a multiple of the host thread count, sized to
     roughly `target_seconds`), same graph, seeds, key and step cap.  Rate in
     replicate-edge updates per second."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    hc = host_cpu()
+    threads = hc["threads"]
     okw = dict(params_of(c))
     if "ic_prob" in okw:
         from paper_2603_14895_amd import fsg
@@ -161,9 +194,39 @@ def cpu_baseline(c, ptr, src, target_seconds: float):
         R = min(c["B"], R * max(1, int(round(target_seconds / max(dt, 1e-3)))))
         dt, steps, kind = run(R)
     rate = src.size * R * steps / dt
-    return {"value": rate, "unit": "replicate-edge updates/s", "cores": threads, "kind": kind,
+    return {"value": rate, "unit": "replicate-edge updates/s", **cpu_fields(hc), "kind": kind,
             "sample": f"{R} replicates (of B={c['B']}) x {steps} steps on the full graph, "
                       f"{dt:.1f} s"}
+
+
+def frontier_arcs(dg, c, outdeg):
+    """Arcs whose source is in some replicate's frontier, per step of one IC
+    run (outside the timed region): the run is repeated with the stepping
+    interface, and after each step the nodes holding a newly active replicate
+    are summed by out-degree.  These are the arcs the frontier-bitmap kernel
+    must process; the rest of its source stream only confirms that a source
+    is not in the frontier."""
+    import numpy as np
+    import torch
+
+    from paper_2603_14895_amd import fsg
+    sess = fsg.Session(dg, c["model"], c["seeds"], c["B"], c["rng_key"], **params_of(c))
+    out = []
+    try:
+        seeds = torch.zeros(dg.n, dtype=torch.bool, device="cuda")
+        seeds[torch.from_numpy(np.asarray(c["seeds"], dtype=np.int64)).to("cuda")] = True
+        front = seeds
+        while True:
+            out.append(int(outdeg[front].sum().item()))
+            info, _ = sess.step(1)
+            st, _, _ = sess.read(want_states=True)
+            front = (st == 1).any(dim=1)
+            del st
+            if int(info.absorbed) or not bool(front.any().item()):
+                break
+    finally:
+        sess.close()
+    return out
 
 
 def main():
@@ -171,7 +234,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "hk"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "hk"])
     ap.add_argument("--epochs", type=int, default=8, help="surrogate training epochs (c5)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the schedule(s) first with the library autotuner")
@@ -180,6 +243,8 @@ def main():
                     help="autotuner window: runs of K and 2K steps per candidate; 0 = the "
                          "workload's step cap (whole runs), or 64 for runs to absorption")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-frontier", action="store_true",
+                    help="IC workloads: skip the per-step count of live frontier arcs")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--schedule", default=None, help="JSON dict of fsg_schedule fields")
     ap.add_argument("--no-states", action="store_true", help="counts only (no [n][B] output)")
@@ -275,6 +340,16 @@ def main():
                 "kernel": "k_ic_stream" if edge_parallel else "k_step",
                 "avg_launch_ms": round(avg_kernel_ms, 5), "launches": launches,
                 "algorithmic_bytes_per_launch": abytes}
+    frontier = None
+    if c["model"] == "ic" and not args.no_frontier:
+        outdeg = torch.bincount(torch.from_numpy(src).to("cuda"), minlength=ptr.size - 1)
+        live = frontier_arcs(dg, c, outdeg)
+        del outdeg
+        frontier = {"live_arcs_per_step": live,
+                    "live_arc_fraction_mean": round(float(np.mean(live)) / src.size, 6),
+                    "note": "arcs out of nodes with a newly active replicate, per step; the "
+                            "edge-parallel kernel reads every source to find them"}
+        log(f"[bench] live frontier arcs per step: {live}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -292,6 +367,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if frontier is not None:
+        out["frontier"] = frontier
     emit(out)
 
 
@@ -363,7 +440,8 @@ def bench_hk(args):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        threads = min(16, os.cpu_count() or 1)
+        hc = host_cpu()
+        threads = hc["threads"]
         R, S = threads, 2
         hs = np.ascontiguousarray(h0[:, :R])
         t2 = time.perf_counter()
@@ -375,7 +453,7 @@ def bench_hk(args):
             _, st, _ = oracle.hk(ptr, src, hs, eps, S, nthreads=threads)
             dc = time.perf_counter() - t2
         cpu = {"value": src.size * R * st / dc, "unit": "replicate-edge updates/s",
-               "cores": threads, "kind": "oracle",
+               **cpu_fields(hc), "kind": "oracle",
                "sample": f"{R} replicates (of B={B}) x {st} steps on the full graph, {dc:.1f} s"}
         log(f"[bench] cpu baseline {cpu}")
     del ws
@@ -605,10 +683,13 @@ def bench_surrogate(args):
 
 
 def cpu_baseline_batch(specs, jobs, host, target_seconds):
-    """The oracle on a bounded sample of the batch: two replicates of each
-    job in turn until about target_seconds have passed."""
+    """The oracle on a bounded sample of the batch: the jobs in turn, each
+    with as many replicates as the oracle has threads (it runs replicates in
+    parallel, so every thread has one), until about target_seconds have
+    passed."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    hc = host_cpu()
+    threads = hc["threads"]
     t0 = time.perf_counter()
     work, used = 0.0, 0
     for (ptr, src), j in zip(host, jobs):
@@ -616,15 +697,17 @@ def cpu_baseline_batch(specs, jobs, host, target_seconds):
         if "ic_prob" in j:
             from paper_2603_14895_amd import fsg
             prm["ic_prob"] = fsg.IC_PROBS[j["ic_prob"]]
-        _, _, steps, _ = oracle.simulate(j["model"], ptr, src, j["seeds"], 2, j["rng_key"],
+        R = min(threads, j["B"])
+        _, _, steps, _ = oracle.simulate(j["model"], ptr, src, j["seeds"], R, j["rng_key"],
                                          want_states=False, nthreads=threads, **prm)
-        work += float(src.size) * 2 * steps
+        work += float(src.size) * R * steps
         used += 1
         if time.perf_counter() - t0 > target_seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": work / dt, "unit": "replicate-edge updates/s", "cores": threads,
-            "kind": "oracle", "sample": f"2 replicates of each of the first {used} jobs, {dt:.1f} s"}
+    return {"value": work / dt, "unit": "replicate-edge updates/s", **cpu_fields(hc),
+            "kind": "oracle",
+            "sample": f"min({threads}, B) replicates of each of the first {used} jobs, {dt:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -42,3 +42,14 @@ def test_kernel_hash_is_per_workload():
     import bench
     h = {w: bench.kernel_source_hash(w) for w in ("c2", "c4", "hk", "c5")}
     assert h["c2"] == h["c4"] and h["hk"] != h["c2"] and h["c5"] != h["hk"]
+
+
+def test_host_cpu_record():
+    import bench
+    hc = bench.host_cpu()
+    assert hc["threads"] >= 1 and hc["threads"] <= hc["visible_cpus"]
+    if (os.environ.get("OMP_NUM_THREADS") or "").isdigit():
+        assert hc["threads"] <= int(os.environ["OMP_NUM_THREADS"])
+    assert isinstance(hc["cpu_model"], str) and hc["cpu_model"]
+    f = bench.cpu_fields(hc)
+    assert f["cores"] == hc["threads"]
