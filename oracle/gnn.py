@@ -16,6 +16,9 @@ Written in float64 with plain numpy.  With ``bf16=True`` the values are
 rounded to bfloat16 (round to nearest even) at the points where the GPU
 stores them in bfloat16: inputs, aggregates, post-ReLU activations, weights
 used by the products, and the pre-activation gradient fed to the products.
+
+The optimiser is Adam (Kingma and Ba, ICLR 2015) on single-precision master
+weights: ``adam_step``, every operation in single precision.
 """
 from __future__ import annotations
 
@@ -146,3 +149,56 @@ def glorot(seed):
         else:
             d[name] = rng.uniform(-0.1, 0.1, size=shape)
     return flatten(d)
+
+
+# ------------------------------------------------------------------ Adam --
+ADAM_BETA1, ADAM_BETA2, ADAM_EPS = 0.9, 0.999, 1e-8
+
+
+def adam_bias_correction(beta, t):
+    """1 - beta^t in single precision: beta^t of the single-precision beta,
+    rounded once to single precision, subtracted from 1 in single precision."""
+    b = np.float32(beta)
+    return np.float32(np.float32(1.0) - np.float32(np.float64(b) ** int(t)))
+
+
+def adam_step(params, m, v, grad, t, lr, beta1=ADAM_BETA1, beta2=ADAM_BETA2, eps=ADAM_EPS):
+    """Step t >= 1 of Adam (Kingma and Ba, ICLR 2015, Algorithm 1) on
+    single-precision master weights, every operation rounded to single
+    precision:
+
+        m = beta1 m + (1 - beta1) g
+        v = beta2 v + (1 - beta2) g^2
+        m_hat = m / (1 - beta1^t),  v_hat = v / (1 - beta2^t)
+        theta = theta - lr * (m_hat / (sqrt(v_hat) + eps))
+
+    Returns new (params, m, v) as float32 arrays; the inputs are not changed."""
+    f = np.float32
+    p = np.asarray(params, dtype=np.float32)
+    m = np.asarray(m, dtype=np.float32)
+    v = np.asarray(v, dtype=np.float32)
+    g = np.asarray(grad, dtype=np.float32)
+    b1, b2, e, a = f(beta1), f(beta2), f(eps), f(lr)
+    one = f(1.0)
+    m_new = (b1 * m + (one - b1) * g).astype(np.float32)
+    v_new = (b2 * v + (one - b2) * (g * g)).astype(np.float32)
+    c1 = adam_bias_correction(beta1, t)
+    c2 = adam_bias_correction(beta2, t)
+    m_hat = (m_new / c1).astype(np.float32)
+    v_hat = (v_new / c2).astype(np.float32)
+    upd = (m_hat / (np.sqrt(v_hat) + e)).astype(np.float32)
+    p_new = (p - a * upd).astype(np.float32)
+    return p_new, m_new, v_new
+
+
+def bf16_bits(x):
+    """bfloat16 bit patterns (uint16) of x rounded to nearest even through
+    float32 -- the BF16 weight copies the products use."""
+    return (bf16(x).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def weight_copies(params):
+    """BF16 bit patterns of W1, W2, W3 (row-major, in that order) of a flat
+    parameter vector."""
+    P = unflatten(params)
+    return np.concatenate([bf16_bits(P[k].astype(np.float32)).ravel() for k in ("W1", "W2", "W3")])
