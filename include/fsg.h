@@ -371,10 +371,27 @@ int fsg_gnn_train_step(fsg_gnn *g, const fsg_graph *graph, const fsg_graph *reve
                        int32_t n_sets, const uint8_t *dev_mask, const float *beta,
                        const float *dev_target, float lr, int32_t apply_update, float *loss,
                        void *ws, size_t ws_bytes, void *stream);
-/* Host copies of the FP32 parameters / last gradient (n = parameter count). */
+/* Host copies of the FP32 parameters / last gradient (n = parameter count).
+ * fsg_gnn_set_params also zeroes the Adam moments and the step count. */
 int fsg_gnn_get_params(const fsg_gnn *g, float *out, int64_t n, void *stream);
 int fsg_gnn_set_params(fsg_gnn *g, const float *in, int64_t n, void *stream);
 int fsg_gnn_get_grads(const fsg_gnn *g, float *out, int64_t n, void *stream);
+/* The optimiser step of fsg_gnn_train_step on its own: Adam (Kingma and Ba,
+ * ICLR 2015, Algorithm 1; beta1 0.9, beta2 0.999, eps 1e-8, learning rate
+ * lr >= 0) with step count t = previous t + 1, in FP32 on the master
+ * parameters:  m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ * p = p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), each operation
+ * rounded to FP32; then the BF16 weight copies are refreshed.  dev_grad:
+ * device float [parameter count], e.g. a gradient summed over several
+ * processes, or NULL for the gradient of the last training step.
+ * Synchronous.  Errors: FSG_EINVAL, FSG_EDEVICE. */
+int fsg_gnn_apply_update(fsg_gnn *g, const float *dev_grad, float lr, void *stream);
+/* Host copies of the optimiser state: Adam moments m and v (FP32 [n] each,
+ * n = parameter count), the BF16 weight copies the products read (uint16
+ * bit patterns of W1, W2, W3 in that order, row-major, 18432 values) and
+ * the step count t; every output may be NULL.  Synchronous. */
+int fsg_gnn_get_state(const fsg_gnn *g, float *m, float *v, uint16_t *wb, int64_t *step,
+                      int64_t n, void *stream);
 /* Acceptance gate and spread calibration of the surrogate (fitted by the
  * caller on simulator labels of training queries and on a held-out split). */
 #define FSG_CALIB_TERMS 9

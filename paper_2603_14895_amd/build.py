@@ -19,6 +19,9 @@ HIPCC_FLAGS = [
 ]
 
 
+IGNORED_HOST_NOTE = "'-packed-fp32-ops'"
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if c and os.path.exists(c):
@@ -32,7 +35,16 @@ def build(verbose: bool = False) -> str:
     cmd = [hipcc()] + HIPCC_FLAGS + srcs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    # hipcc hands the target-feature flag to the host pass too, whose target
+    # has no such feature and says so once per source; that line is dropped
+    # and every other compiler message is shown
+    lines = [ln for ln in r.stdout.splitlines()
+             if not (IGNORED_HOST_NOTE in ln and "not a recognized feature" in ln)]
+    if lines:
+        print("\n".join(lines), flush=True)
+    if r.returncode != 0:
+        raise subprocess.CalledProcessError(r.returncode, cmd)
     os.replace(tmp, LIB)
     return LIB
 

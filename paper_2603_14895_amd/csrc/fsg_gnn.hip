@@ -12,7 +12,10 @@
 //   h3_v = ReLU(W3 [h2_v | mean h2_u] + b3)                        (128 -> 64)
 //   p_v  = sigmoid(wo . h3_v + bo)
 // Loss: mean binary cross-entropy against per-node infection frequencies.
-// A mean over an empty neighbourhood is 0.
+// A mean over an empty neighbourhood is 0.  Every stored BF16 value of the
+// forward pass is its defining expression rounded once (to nearest even,
+// through FP32): the means exactly so (FP64 sums), the layer outputs up to
+// the FP32 rounding of the MFMA sums.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -79,18 +82,44 @@ __global__ void k_input(uint16_t *X1, const uint8_t *mask, const float *beta, co
          r += (int64_t)gridDim.x * blockDim.x) {
         const int s = (int)(r / n);
         const int v = (int)(r - (int64_t)s * n);
-        const float d = (float)(ptr[v + 1] - ptr[v]);
+        const int d = ptr[v + 1] - ptr[v];
         uint16_t *x = X1 + r * kK1;
         x[0] = to_bf16(mask[r] ? 1.f : 0.f);
         x[1] = to_bf16(20.f * beta[s]);
-        x[2] = to_bf16(log1pf(d) * 0.125f);
+        x[2] = to_bf16((float)(log1p((double)d) * 0.125));
         x[3] = to_bf16(1.f);
         for (int f = 4; f < kF0; ++f) x[f] = 0;
     }
 }
 
-// Mean aggregation over in-neighbours (pull CSR), FP32 sums, BF16 result:
+// Adds the four BF16 values packed in q to four FP64 sums (exactly: a BF16
+// value widens to FP64 without rounding).
+__device__ __forceinline__ void add_bf16x4(double &a0, double &a1, double &a2, double &a3,
+                                           uint2 q)
+{
+    a0 += (double)from_bf16((uint16_t)q.x);
+    a1 += (double)from_bf16((uint16_t)(q.x >> 16));
+    a2 += (double)from_bf16((uint16_t)q.y);
+    a3 += (double)from_bf16((uint16_t)(q.y >> 16));
+}
+
+// BF16 of sum / deg: FP64 quotient, rounded to FP32, then to BF16 (nearest
+// even at both steps); 0 for an empty neighbourhood.
+__device__ __forceinline__ uint16_t mean_bf16(double sum, int deg)
+{
+    return deg > 0 ? to_bf16((float)(sum / (double)deg)) : (uint16_t)0;
+}
+
+// Mean aggregation over in-neighbours (pull CSR), BF16 result:
 // X[r][cout + f] = mean_{u in N-(v)} X[s*n + u][cin + f], f < d (d = 16 or 64).
+// The BF16 neighbour values are added in FP64, which holds such a sum
+// exactly (8-bit significands: exact while the values span fewer than about
+// 2^40 and the row has fewer than 2^5 ... 2^31 entries), and divided by the
+// degree in FP64; the quotient goes to FP32 and then to BF16, both rounding
+// to nearest even.  The stored mean is therefore the exact mean rounded as
+// the definition rounds it, whatever the order of the additions.  (An FP32
+// sum scaled by a rounded 1/deg lands on the other side of a BF16 tie now and
+// then; those one-unit flips then reach every later layer.)
 // One wave per row.  A lane covers 4 features (one 8-byte load per
 // neighbour), so d/4 lanes cover a neighbour row and the wave has 64/(d/4)
 // neighbour rows in flight per load; neighbour indices arrive 64 at a time
@@ -110,7 +139,7 @@ __device__ __forceinline__ void mean_light(uint16_t *X, int ld, int d, int cin, 
         const int e0 = ptr[v], e1 = ptr[v + 1], deg = e1 - e0;
         if (deg > kWideRow) continue;  // k_mean_wide
         const uint16_t *base = X + (int64_t)s * n * ld + cin + 4 * li;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         for (int c0 = 0; c0 < deg; c0 += 64) {
             const int cnt = min(64, deg - c0);
             const int my = lane < cnt ? src[e0 + c0 + lane] : 0;
@@ -120,10 +149,8 @@ __device__ __forceinline__ void mean_light(uint16_t *X, int ld, int d, int cin, 
                 uint2 qa = make_uint2(0u, 0u), qb = make_uint2(0u, 0u);
                 if (ka < cnt) qa = *reinterpret_cast<const uint2 *>(base + (int64_t)ua * ld);
                 if (kb < cnt) qb = *reinterpret_cast<const uint2 *>(base + (int64_t)ub * ld);
-                a0 += from_bf16((uint16_t)qa.x) + from_bf16((uint16_t)qb.x);
-                a1 += from_bf16((uint16_t)(qa.x >> 16)) + from_bf16((uint16_t)(qb.x >> 16));
-                a2 += from_bf16((uint16_t)qa.y) + from_bf16((uint16_t)qb.y);
-                a3 += from_bf16((uint16_t)(qa.y >> 16)) + from_bf16((uint16_t)(qb.y >> 16));
+                add_bf16x4(a0, a1, a2, a3, qa);
+                add_bf16x4(a0, a1, a2, a3, qb);
             }
         }
         for (int off = lg; off < 64; off <<= 1) {
@@ -133,10 +160,9 @@ __device__ __forceinline__ void mean_light(uint16_t *X, int ld, int d, int cin, 
             a3 += __shfl_xor(a3, off, 64);
         }
         if (gi == 0) {
-            const float inv = deg > 0 ? 1.f / (float)deg : 0.f;
             uint2 o;
-            o.x = (uint32_t)to_bf16(a0 * inv) | ((uint32_t)to_bf16(a1 * inv) << 16);
-            o.y = (uint32_t)to_bf16(a2 * inv) | ((uint32_t)to_bf16(a3 * inv) << 16);
+            o.x = (uint32_t)mean_bf16(a0, deg) | ((uint32_t)mean_bf16(a1, deg) << 16);
+            o.y = (uint32_t)mean_bf16(a2, deg) | ((uint32_t)mean_bf16(a3, deg) << 16);
             *reinterpret_cast<uint2 *>(X + r * ld + cout + 4 * li) = o;
         }
     }
@@ -201,7 +227,7 @@ constexpr int kWideWaves = kWideThreads / 64;
 __device__ __forceinline__ void mean_wide(uint16_t *X, int ld, int d, int cin, int cout,
                                           const int32_t *ptr, const int32_t *src, int32_t n,
                                           const int32_t *wide, int32_t n_wide, int blk,
-                                          float (*s_part)[kHid])
+                                          double (*s_part)[kHid])
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lg = d >> 2, ng = 64 / lg;
@@ -212,7 +238,7 @@ __device__ __forceinline__ void mean_wide(uint16_t *X, int ld, int d, int cin, i
     const int per = (deg + kWideWaves - 1) / kWideWaves;
     const int lo = min(deg, wv * per), hi = min(deg, lo + per);
     const uint16_t *base = X + (int64_t)s * n * ld + cin + 4 * li;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (int c0 = lo; c0 < hi; c0 += 64) {
         const int cnt = min(64, hi - c0);
         const int my = lane < cnt ? src[e0 + c0 + lane] : 0;
@@ -222,10 +248,8 @@ __device__ __forceinline__ void mean_wide(uint16_t *X, int ld, int d, int cin, i
             uint2 qa = make_uint2(0u, 0u), qb = make_uint2(0u, 0u);
             if (ka < cnt) qa = *reinterpret_cast<const uint2 *>(base + (int64_t)ua * ld);
             if (kb < cnt) qb = *reinterpret_cast<const uint2 *>(base + (int64_t)ub * ld);
-            a0 += from_bf16((uint16_t)qa.x) + from_bf16((uint16_t)qb.x);
-            a1 += from_bf16((uint16_t)(qa.x >> 16)) + from_bf16((uint16_t)(qb.x >> 16));
-            a2 += from_bf16((uint16_t)qa.y) + from_bf16((uint16_t)qb.y);
-            a3 += from_bf16((uint16_t)(qa.y >> 16)) + from_bf16((uint16_t)(qb.y >> 16));
+            add_bf16x4(a0, a1, a2, a3, qa);
+            add_bf16x4(a0, a1, a2, a3, qb);
         }
     }
     for (int off = lg; off < 64; off <<= 1) {
@@ -242,9 +266,9 @@ __device__ __forceinline__ void mean_wide(uint16_t *X, int ld, int d, int cin, i
     }
     __syncthreads();
     if ((int)threadIdx.x < d) {
-        float acc = 0.f;
+        double acc = 0.0;
         for (int w = 0; w < kWideWaves; ++w) acc += s_part[w][threadIdx.x];
-        X[((int64_t)s * n + v) * ld + cout + threadIdx.x] = to_bf16(acc / (float)deg);
+        X[((int64_t)s * n + v) * ld + cout + threadIdx.x] = mean_bf16(acc, deg);
     }
 }
 
@@ -262,7 +286,7 @@ __global__ void __launch_bounds__(kWideThreads) k_mean_wide(uint16_t *X, int ld,
                                                             const int32_t *src, int32_t n,
                                                             const int32_t *wide, int32_t n_wide)
 {
-    __shared__ float s_part[kWideWaves][kHid];
+    __shared__ double s_part[kWideWaves][kHid];
     mean_wide(X, ld, d, cin, cout, ptr, src, n, wide, n_wide, (int)blockIdx.x, s_part);
 }
 
@@ -275,7 +299,7 @@ __global__ void __launch_bounds__(kWideThreads) k_mean_all(uint16_t *X, int ld, 
                                                            int32_t n_sets, const int32_t *wide,
                                                            int32_t n_wide)
 {
-    __shared__ float s_part[kWideWaves][kHid];
+    __shared__ double s_part[kWideWaves][kHid];
     const int nwb = n_wide * n_sets;
     if ((int)blockIdx.x < nwb) {
         mean_wide(X, ld, d, cin, cout, ptr, src, n, wide, n_wide, (int)blockIdx.x, s_part);
@@ -565,17 +589,23 @@ __global__ void __launch_bounds__(256) k_dz(const float *dH, const uint16_t *H, 
     if (wave == 0) part_b[blockIdx.x * kHid + lane] = s[0][lane] + s[1][lane] + s[2][lane] + s[3][lane];
 }
 
-// Adam on the FP32 master parameters, then BF16 copies of W1..W3.
+// Adam (Kingma and Ba, ICLR 2015, Algorithm 1) on the FP32 master
+// parameters, every operation rounded to FP32 (no contraction; division and
+// square root correctly rounded):
+//   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+//   p = p - lr (m / c1) / (sqrt(v / c2) + eps),  c1 = 1 - b1^t, c2 = 1 - b2^t,
+// then the BF16 copies of W1..W3.
 __global__ void k_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1,
                        float b2, float eps, float c1, float c2, uint16_t *wb)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const float gi = g[i];
         const float mi = b1 * m[i] + (1.f - b1) * gi;
-        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * (gi * gi);
         m[i] = mi;
         v[i] = vi;
-        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        const float upd = (mi / c1) / (sqrtf(vi / c2) + eps);
+        const float pi = p[i] - lr * upd;
         p[i] = pi;
         if (i < kB1) wb[kWb1 + i] = to_bf16(pi);
         else if (i >= kW2 && i < kB2) wb[kWb2 + (i - kW2)] = to_bf16(pi);
@@ -848,6 +878,19 @@ int check_ws(void *ws, size_t bytes, size_t need)
     return FSG_OK;
 }
 
+// One Adam step (step count t = ++g->step) with gradient grads (device [kP]).
+int adam_enqueue(fsg_gnn *g, const float *grads, float lr, hipStream_t st)
+{
+    g->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    // 1 - beta^t: beta^t rounded once to FP32 (powf is correctly rounded)
+    const float c1 = 1.f - powf(b1, (float)g->step), c2 = 1.f - powf(b2, (float)g->step);
+    hipLaunchKernelGGL(k_adam, dim3(grid_of(kP, 256)), dim3(256), 0, st, g->p(), grads, g->m(),
+                       g->v(), (int)kP, lr, b1, b2, 1e-8f, c1, c2, g->wb());
+    GNN_TRY(hipGetLastError());
+    return FSG_OK;
+}
+
 int upload_betas(const float *beta, int32_t n_sets, char *base, const GnnWs &w, hipStream_t st)
 {
     for (int32_t i = 0; i < n_sets; ++i)
@@ -1042,13 +1085,8 @@ int fsg_gnn_train_step(fsg_gnn *g, const fsg_graph *graph, const fsg_graph *reve
     rc = backward_layer(g, G, Gr, n_sets, base, w, X1, kK1, X2, kK2, dH, kW1, kB1, kWb1, nullptr, st);
     if (rc) return rc;
     if (apply_update) {
-        g->step += 1;
-        const float b1 = 0.9f, b2 = 0.999f;
-        const float c1 = 1.f - powf(b1, (float)g->step), c2 = 1.f - powf(b2, (float)g->step);
-        hipLaunchKernelGGL(k_adam, dim3(grid_of(kP, 256)), dim3(256), 0, st, g->p(),
-                           (const float *)grads, g->m(), g->v(), (int)kP, lr, b1, b2, 1e-8f, c1, c2,
-                           g->wb());
-        GNN_TRY(hipGetLastError());
+        rc = adam_enqueue(g, grads, lr, st);
+        if (rc) return rc;
     }
     float hl = 0.f;
     GNN_TRY(hipMemcpyAsync(&hl, dloss, 4, hipMemcpyDeviceToHost, st));
@@ -1087,6 +1125,30 @@ int fsg_gnn_get_grads(const fsg_gnn *g, float *out, int64_t n, void *stream)
     hipStream_t st = (hipStream_t)stream;
     GNN_TRY(hipMemcpyAsync(out, g->g(), (size_t)kP * 4, hipMemcpyDeviceToHost, st));
     GNN_TRY(hipStreamSynchronize(st));
+    return FSG_OK;
+}
+
+int fsg_gnn_apply_update(fsg_gnn *g, const float *dev_grad, float lr, void *stream)
+{
+    if (!g || !g->bound) return set_error(FSG_EINVAL, "gnn is NULL or not bound");
+    if (!(lr >= 0.f) || !(lr < INFINITY)) return set_error(FSG_EINVAL, "lr must be finite and >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    const int rc = adam_enqueue(g, dev_grad ? dev_grad : (const float *)g->g(), lr, st);
+    if (rc) return rc;
+    GNN_TRY(hipStreamSynchronize(st));
+    return FSG_OK;
+}
+
+int fsg_gnn_get_state(const fsg_gnn *g, float *m, float *v, uint16_t *wb, int64_t *step,
+                      int64_t n, void *stream)
+{
+    if (!g || !g->bound || n != kP) return set_error(FSG_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    if (m) GNN_TRY(hipMemcpyAsync(m, g->m(), (size_t)kP * 4, hipMemcpyDeviceToHost, st));
+    if (v) GNN_TRY(hipMemcpyAsync(v, g->v(), (size_t)kP * 4, hipMemcpyDeviceToHost, st));
+    if (wb) GNN_TRY(hipMemcpyAsync(wb, g->wb(), (size_t)kWbN * 2, hipMemcpyDeviceToHost, st));
+    GNN_TRY(hipStreamSynchronize(st));
+    if (step) *step = g->step;
     return FSG_OK;
 }
 

@@ -131,6 +131,8 @@ _SIGS = {
     "fsg_gnn_get_params": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "fsg_gnn_set_params": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "fsg_gnn_get_grads": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
+    "fsg_gnn_apply_update": (ctypes.c_int, [_VP, _VP, ctypes.c_float, _VP]),
+    "fsg_gnn_get_state": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(_I64), _I64, _VP]),
     "fsg_estimate_spread": (ctypes.c_int, [_VP, _I32, _VP, _VP, _I64, ctypes.c_double,
                                            ctypes.c_double, _I64, ctypes.POINTER(fsg_spread_gate),
                                            _I64, _U64, _VP, _SZ, _VP, _SZ, _VP,
@@ -633,6 +635,28 @@ class GNN:
         out = np.empty(self.n_params, dtype=np.float32)
         _check(lib().fsg_gnn_get_grads(self.handle, out.ctypes.data, self.n_params, _stream_ptr()))
         return out
+
+    def apply_update(self, grads, lr: float):
+        """One Adam step with the given gradient (float32 [n_params], host or
+        device) or, for None, the last training step's gradient."""
+        import torch
+        g = None
+        if grads is not None:
+            g = torch.as_tensor(np.ascontiguousarray(grads, dtype=np.float32)
+                                if not isinstance(grads, torch.Tensor) else grads)
+            g = g.to(device=self.device, dtype=torch.float32).contiguous()
+        _check(lib().fsg_gnn_apply_update(self.handle, g.data_ptr() if g is not None else None,
+                                          float(lr), _stream_ptr()))
+
+    def get_state(self):
+        """(m, v, BF16 weight copies as uint16, step count)."""
+        m = np.empty(self.n_params, dtype=np.float32)
+        v = np.empty(self.n_params, dtype=np.float32)
+        wb = np.empty(32 * 64 + 2 * 128 * 64, dtype=np.uint16)
+        t = ctypes.c_int64()
+        _check(lib().fsg_gnn_get_state(self.handle, m.ctypes.data, v.ctypes.data, wb.ctypes.data,
+                                       ctypes.byref(t), self.n_params, _stream_ptr()))
+        return m, v, wb, t.value
 
     def close(self):
         if self.handle:

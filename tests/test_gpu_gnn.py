@@ -59,7 +59,9 @@ def test_forward_matches_oracle(setup):
                             S["betas"][s], bf=True)
         err = np.abs(prob[s] - ref)
         log(f"[gnn] forward set {s}: max abs err {err.max():.2e}, mean {err.mean():.2e}")
-        assert err.max() < 2e-2 and err.mean() < 2e-3
+        # every BF16 activation is its definition rounded once, so only the
+        # FP32 head (and a rare MFMA-sum rounding at a BF16 tie) separates them
+        assert err.max() < 1e-3 and err.mean() < 1e-5
 
 
 def test_gradient_matches_oracle(setup):
@@ -81,7 +83,8 @@ def test_gradient_matches_oracle(setup):
         f"rel err median {np.median(rel):.2e} p99 {np.quantile(rel, 0.99):.2e} max {rel.max():.2e}")
     assert abs(loss - rl) < 1e-4 * max(1.0, abs(rl))
     assert cos >= 0.999
-    assert np.quantile(rel, 0.99) < 5e-2 and np.median(rel) < 1e-2
+    # elementwise on every entry above 1e-3 of the largest
+    assert rel.max() <= 2e-2, (np.nonzero(big)[0][np.argmax(rel)], rel.max())
 
 
 def test_training_reduces_loss(setup):
@@ -108,3 +111,73 @@ def test_estimator_fallback_is_plain_mc(setup):
     assert abs(sp - float(cnt.sum().item()) / 256) < 1e-9
     sp2, unc2, fb2 = est.estimate(seeds, 0.04, 1234, tau=1e30)
     assert not fb2 and unc2 == pytest.approx(unc)
+
+
+def test_adam_matches_oracle_bit_for_bit(setup):
+    """The optimiser step on seeded gradients (not from the network): FP32
+    parameters, both moments and the BF16 weight copies after each of three
+    steps equal the oracle's single-precision Adam bit for bit."""
+    S = setup
+    net = S["fsg"].GNN(4)
+    p = S["params"].copy()
+    net.set_params(p)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    rng = np.random.default_rng(2024)
+    for t, lr in enumerate((1e-3, 3e-3, 1e-3), start=1):
+        g = (rng.normal(size=p.size) * 10.0 ** rng.uniform(-9, 0, size=p.size)).astype(np.float32)
+        g[::97] = 0.0
+        net.apply_update(g, lr)
+        p, m, v = OG.adam_step(p, m, v, g, t, lr)
+        gp = net.get_params()
+        gm, gv, gwb, gt = net.get_state()
+        assert gt == t
+        for name, a, b in (("params", gp, p), ("m", gm, m), ("v", gv, v)):
+            bad = np.nonzero(a.view(np.uint32) != b.view(np.uint32))[0]
+            assert bad.size == 0, (t, name, bad[:5], a[bad[:5]], b[bad[:5]])
+        assert (gwb == OG.weight_copies(p)).all(), t
+
+
+def test_three_train_steps_match_oracle(setup):
+    """Three full training steps (forward, backward, Adam) against the oracle's
+    network and Adam.  Moments follow the gradient elementwise (the first
+    within 2e-2 of the same moment of |g|, the second within 4e-2 relative,
+    on entries above 1e-3 of the largest); a parameter whose three gradients are
+    all such entries moves as the oracle's does (Adam's step has size about lr
+    whatever the gradient's scale, so the bound is in units of lr); any other
+    parameter stays within its largest possible move, 3 lr."""
+    import torch
+    S = setup
+    net = S["fsg"].GNN(5)
+    p = S["params"].copy()
+    net.set_params(p)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    ptr, src = S["gr"].numpy()
+    masks_t = torch.tensor(S["masks"], device="cuda")
+    ys_t = torch.tensor(S["ys"], device="cuda")
+    lr = 1e-3
+    sure = np.ones(p.size, dtype=bool)
+    m_abs = np.zeros(p.size)  # the first moment of |g|: the scale of m without cancellation
+    for t in range(1, 4):
+        net.train_step(S["g"], S["rev"], masks_t, S["betas"], ys_t, lr)
+        _, rg = OG.loss_and_grad(p.astype(np.float64), ptr, src,
+                                 [mm.astype(float) for mm in S["masks"]], S["betas"],
+                                 [y.astype(float) for y in S["ys"]], bf=True)
+        big = np.abs(rg) > 1e-3 * np.abs(rg).max()
+        sure &= big
+        p, m, v = OG.adam_step(p, m, v, rg.astype(np.float32), t, lr)
+        m_abs = 0.9 * m_abs + 0.1 * np.abs(rg)
+        gp = net.get_params()
+        gm, gv, gwb, gt = net.get_state()
+        assert gt == t
+        mb = m_abs > 1e-3 * m_abs.max()
+        rel_m = np.abs(gm - m)[mb] / m_abs[mb]
+        vb = v > 1e-6 * v.max()
+        rel_v = np.abs(gv - v)[vb] / v[vb]
+        dp = np.abs(gp.astype(np.float64) - p)
+        log(f"[gnn] train step {t}: m rel max {rel_m.max():.2e}, v rel max {rel_v.max():.2e}, "
+            f"param diff max {dp[sure].max() / lr:.2e} lr (determined), {dp.max() / lr:.2e} lr (all)")
+        assert rel_m.max() <= 2e-2 and rel_v.max() <= 4e-2
+        assert dp[sure].max() <= 2e-2 * lr * t
+        assert dp.max() <= 2 * lr * t + 1e-7
