@@ -128,7 +128,14 @@ typedef struct {
  *   kernel_variant 0: the library picks; 1: row-group pull kernel (any
  *                  model and B); 2: edge-parallel IC kernel with a frontier
  *                  bitmap (IC with B <= 64 only, else FSG_EINVAL).  With
- *                  variant 2, row_lanes and block_threads are not used. */
+ *                  variant 2, row_lanes and block_threads are not used.
+ *   options        bit flags, 0 by default.  FSG_OPT_WIDE_OFFSETS: the
+ *                  row-group kernels address sources and state planes with
+ *                  64-bit offsets even where 32-bit ones suffice (they are
+ *                  used by themselves when n + 1 >= 2^24, ceil(B/64) >=
+ *                  2^21, (n + 1) ceil(B/64) >= 2^29 or nnz >= 2^30); the
+ *                  results are the same either way. */
+#define FSG_OPT_WIDE_OFFSETS 1
 typedef struct {
     int32_t row_lanes;
     int32_t block_threads;
@@ -137,7 +144,7 @@ typedef struct {
     int32_t steps_per_sync;
     int32_t time_kernels;
     int32_t kernel_variant;
-    int32_t reserved;
+    int32_t options;
 } fsg_schedule;
 
 /* Library version of this header (FSG_ABI_VERSION). */
@@ -149,14 +156,15 @@ const char *fsg_last_error(void);
 
 /* Graph (Sec. 2, Definitions "Graph" and "CSR"; update rule Eq. nodestate
  * pulls over in-neighbours N^-(v)).
- * n >= 1 nodes, nnz >= 0 arcs, nnz < 2^31.  in_ptr: host int64 [n+1],
+ * n >= 1 nodes, nnz >= 0 arcs, nnz <= 2^31 - 256 (arc indices and the
+ * few arcs kernels look past a row's end stay in int32).  in_ptr: host int64 [n+1],
  * in_ptr[0] = 0, non-decreasing, in_ptr[n] = nnz.  in_src: host int32
  * [nnz]; in_src[in_ptr[v] .. in_ptr[v+1]) are the sources u of the arcs
  * u -> v.  The edge id of an arc is its position in in_src.  Undirected
  * graphs store both arcs.  Self-loops and repeated arcs are allowed.
  * in_ptr is copied; in_src is borrowed until fsg_graph_bind returns.
  * Errors: FSG_EINVAL (NULL pointers, n < 1, a malformed CSR, a source out
- * of range), FSG_EUNSUPPORTED (nnz >= 2^31), FSG_ENOMEM. */
+ * of range), FSG_EUNSUPPORTED (nnz > 2^31 - 256, n > 2^31 - 2), FSG_ENOMEM. */
 int fsg_graph_create(int64_t n, int64_t nnz, const int64_t *in_ptr, const int32_t *in_src,
                      fsg_graph **out);
 

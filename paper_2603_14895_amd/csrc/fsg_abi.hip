@@ -3,9 +3,11 @@
 // Declarations and contracts: include/fsg.h.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <fstream>
 #include <sstream>
@@ -33,10 +35,44 @@ int fail(int code, const std::string &msg)
 
 #define HIP_TRY(expr)                                                                       \
     do {                                                                                    \
+        if (fsg::inject_device_fault())                                                     \
+            return fail(FSG_EDEVICE, std::string(#expr) + ": injected fault");              \
         hipError_t e_ = (expr);                                                             \
         if (e_ != hipSuccess)                                                               \
             return fail(FSG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
     } while (0)
+
+// FSG_FAULT_INJECT: the call numbers at which a guarded allocation or a
+// checked HIP call fails (0: never), parsed on first use.
+struct FaultPlan {
+    long alloc_at = 0, device_at = 0;
+    std::atomic<long> allocs{0}, devices{0};
+    FaultPlan()
+    {
+        const char *env = getenv("FSG_FAULT_INJECT");
+        if (!env) return;
+        std::string spec(env);
+        size_t pos = 0;
+        while (pos <= spec.size()) {
+            size_t end = spec.find(',', pos);
+            if (end == std::string::npos) end = spec.size();
+            const std::string item = spec.substr(pos, end - pos);
+            const size_t c = item.find(':');
+            if (c != std::string::npos) {
+                const long at = atol(item.c_str() + c + 1);
+                if (item.compare(0, c, "alloc") == 0) alloc_at = at;
+                if (item.compare(0, c, "device") == 0) device_at = at;
+            }
+            pos = end + 1;
+        }
+    }
+};
+
+FaultPlan &fault_plan()
+{
+    static FaultPlan plan;
+    return plan;
+}
 
 // Probability -> uint32 threshold (the Bernoulli fires iff t == 2^32-1 or
 // draw < t).  Scaling by 2^32 is exact in FP64.
@@ -83,6 +119,11 @@ int ilog2(int64_t x)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Largest arc count: arc indices are int32 in the kernels, which look up to
+// 4 * 64 positions past an index they hold (unrolled loads of the row-group
+// loops, lanes past a row's end), so every such position stays below 2^31.
+constexpr int64_t kMaxNnz = ((int64_t)1 << 31) - 256;
+
 struct Plan {
     std::vector<int32_t> tiles;      // (row_begin, row_end) pairs; no heavy rows inside
     std::vector<int32_t> heavy_rows; // rows with indeg > heavy
@@ -110,6 +151,18 @@ struct fsg_graph {
 namespace fsg {
 
 int set_error(int code, const char *msg) { return fail(code, msg); }
+
+void inject_alloc_fault()
+{
+    FaultPlan &f = fault_plan();
+    if (f.alloc_at > 0 && f.allocs.fetch_add(1) + 1 == f.alloc_at) throw std::bad_alloc();
+}
+
+bool inject_device_fault()
+{
+    FaultPlan &f = fault_plan();
+    return f.device_at > 0 && f.devices.fetch_add(1) + 1 == f.device_at;
+}
 
 bool graph_view(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg,
                 const int32_t **ptr, const int32_t **src, const int32_t **wide, int64_t *n_wide)
@@ -269,6 +322,7 @@ int check_params(const fsg_graph *g, const fsg_params *prm, int64_t B)
 struct Sched {
     int G, S, lgG, lgS, block, tile_edges, heavy, sync, timed;
     bool edge1;  // edge-parallel IC kernel
+    bool wide;   // 64-bit offsets in the row-group kernels even where 32-bit ones fit
 };
 
 void default_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_schedule *o)
@@ -330,6 +384,8 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
     s->sync = u.steps_per_sync;
     s->timed = u.time_kernels != 0;
     s->edge1 = u.kernel_variant == 2;
+    if (u.options & ~FSG_OPT_WIDE_OFFSETS) return fail(FSG_EINVAL, "unknown schedule option bits");
+    s->wide = (u.options & FSG_OPT_WIDE_OFFSETS) != 0;
     return FSG_OK;
 }
 
@@ -557,8 +613,8 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.lgG = s.lgG;
     a.lgS = s.lgS;
     a.heavy = s.heavy;
-    a.fast32 = (g->n + 1 < (1 << 24) && L.W < (1 << 21) && (g->n + 1) * L.W < (1 << 29) &&
-                g->nnz < (1 << 30)) ? 1 : 0;
+    a.fast32 = (!s.wide && g->n + 1 < (1 << 24) && L.W < (1 << 21) &&
+                (g->n + 1) * L.W < (1 << 29) && g->nnz < (1 << 30)) ? 1 : 0;
     a.tiles = (const int32_t *)(base + L.tiles);
     a.n_tiles = (int32_t)(p.tiles.size() / 2);
     a.seg_row = (const int32_t *)(base + L.seg_row);
@@ -785,7 +841,7 @@ int fsg_graph_create(int64_t n, int64_t nnz, const int64_t *in_ptr, const int32_
         if (n < 1) return fail(FSG_EINVAL, "n must be >= 1");
         if (n > 0x7FFFFFFF - 1) return fail(FSG_EUNSUPPORTED, "n above 2^31-2");
         if (nnz < 0) return fail(FSG_EINVAL, "nnz must be >= 0");
-        if (nnz >= ((int64_t)1 << 31)) return fail(FSG_EUNSUPPORTED, "nnz must be below 2^31");
+        if (nnz > kMaxNnz) return fail(FSG_EUNSUPPORTED, "nnz above 2^31 - 256");
         if (!in_ptr) return fail(FSG_EINVAL, "in_ptr is NULL");
         if (nnz > 0 && !in_src) return fail(FSG_EINVAL, "in_src is NULL");
         if (in_ptr[0] != 0) return fail(FSG_EINVAL, "in_ptr[0] must be 0");
@@ -799,6 +855,7 @@ int fsg_graph_create(int64_t n, int64_t nnz, const int64_t *in_ptr, const int32_
         for (int64_t e = 0; e < nnz; ++e)
             if (in_src[e] < 0 || (int64_t)in_src[e] >= n)
                 return fail(FSG_EINVAL, "in_src entry out of range at edge " + std::to_string(e));
+        fsg::inject_alloc_fault();
         fsg_graph *g = new fsg_graph;
         g->n = n;
         g->nnz = nnz;
@@ -1049,6 +1106,7 @@ int fsg_batch_plan(const fsg_job *jobs, int32_t n_jobs, int32_t steps_per_sync, 
             return fail(FSG_EINVAL, "n_jobs must be in [1, 1024]");
         if (steps_per_sync < 1 || steps_per_sync > 4096)
             return fail(FSG_EINVAL, "steps_per_sync must be in [1, 4096]");
+        fsg::inject_alloc_fault();
         std::unique_ptr<fsg_plan> pl(new fsg_plan);
         pl->sync = steps_per_sync;
         size_t off = 0;

@@ -702,6 +702,8 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 #define GNN_TRY(expr)                                                                 \
     do {                                                                              \
+        if (fsg::inject_device_fault())                                                       \
+            return set_error(FSG_EDEVICE, (std::string(#expr) + ": injected fault").c_str()); \
         hipError_t e_ = (expr);                                                       \
         if (e_ != hipSuccess)                                                         \
             return set_error(FSG_EDEVICE, (std::string(#expr) + ": " + hipGetErrorString(e_)).c_str()); \
@@ -910,6 +912,7 @@ int fsg_gnn_create(int32_t hidden, int32_t layers, uint64_t init_seed, fsg_gnn *
         *out = nullptr;
         if (hidden != kHid || layers != 3)
             return set_error(FSG_EUNSUPPORTED, "this build has hidden = 64 and 3 layers");
+        fsg::inject_alloc_fault();
         fsg_gnn *g = new fsg_gnn;
         g->seed = init_seed;
         g->init.assign(kP, 0.f);

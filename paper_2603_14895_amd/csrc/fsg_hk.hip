@@ -324,6 +324,8 @@ int view_of(const fsg_graph *g, View *v)
 
 #define HK_TRY(expr)                                                                          \
     do {                                                                                      \
+        if (fsg::inject_device_fault())                                                        \
+            return set_error(FSG_EDEVICE, (std::string(#expr) + ": injected fault").c_str());  \
         hipError_t e_ = (expr);                                                               \
         if (e_ != hipSuccess)                                                                 \
             return set_error(FSG_EDEVICE, (std::string(#expr) + ": " + hipGetErrorString(e_)).c_str()); \

@@ -11,6 +11,15 @@ namespace fsg {
 
 // Host helpers shared by the translation units (fsg_abi.hip).
 int set_error(int code, const char *msg);  // records the message, returns code
+
+// Fault injection for tests of the error paths, armed by the environment
+// variable FSG_FAULT_INJECT (read once per process): "alloc:N" makes the
+// N-th guarded host allocation fail (std::bad_alloc -> FSG_ENOMEM),
+// "device:N" makes the N-th checked HIP call report an error without
+// calling HIP (-> FSG_EDEVICE); both may be given, comma-separated.  Each
+// fires once.  Unset, both checks are a load and a compare.
+void inject_alloc_fault();  // throws std::bad_alloc when this allocation is to fail
+bool inject_device_fault(); // true when this checked HIP call is to fail
 // Device view of a graph; false if it is not bound.
 bool graph_view(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg,
                 const int32_t **ptr, const int32_t **src, const int32_t **wide, int64_t *n_wide);

@@ -48,10 +48,13 @@ class fsg_schedule(ctypes.Structure):
     _fields_ = [("row_lanes", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("tile_edges", ctypes.c_int32), ("heavy_threshold", ctypes.c_int32),
                 ("steps_per_sync", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
-                ("kernel_variant", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("kernel_variant", ctypes.c_int32), ("options", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+OPT_WIDE_OFFSETS = 1  # FSG_OPT_WIDE_OFFSETS
 
 
 CALIB_TERMS = 9

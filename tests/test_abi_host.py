@@ -64,6 +64,32 @@ def test_graph_create_validation():
     assert e.value.code == fsg.FSG_EUNSUPPORTED
 
 
+def test_arc_count_cap_is_refused_before_reading_arrays():
+    """nnz above 2^31 - 256 is refused up front (kernels keep arc indices in
+    int32 and look up to 256 positions past one); the arrays are not read."""
+    for nnz in (2**31 - 255, 2**31 - 1):
+        ptr = np.array([0, nnz], dtype=np.int64)
+        src = np.zeros(4, dtype=np.int32)
+        with pytest.raises(fsg.FsgError) as e:
+            fsg.fsg_graph_create(1, nnz, ptr.ctypes.data, src.ctypes.data)
+        assert e.value.code == fsg.FSG_EUNSUPPORTED and "2^31 - 256" in str(e.value)
+
+
+def test_schedule_options_validated():
+    ptr, src = _graph()
+    n, nnz = ptr.size - 1, src.size
+    h = fsg.fsg_graph_create(n, nnz, ptr.ctypes.data, src.ctypes.data)
+    try:
+        prm, _ = fsg.make_params("sir", beta=0.1, gamma=0.1, max_steps=5)
+        ok = fsg.make_schedule({"options": fsg.OPT_WIDE_OFFSETS})
+        assert fsg.fsg_sim_workspace_size(h, prm, 64, ok) > 0
+        with pytest.raises(fsg.FsgError) as e:
+            fsg.fsg_sim_workspace_size(h, prm, 64, fsg.make_schedule({"options": 6}))
+        assert e.value.code == fsg.FSG_EINVAL
+    finally:
+        fsg.fsg_graph_destroy(h)
+
+
 def test_params_validation_before_any_launch():
     ptr, src = _graph()
     n, nnz = ptr.size - 1, src.size
@@ -186,3 +212,64 @@ def test_batch_plan_validation():
             fsg.fsg_batch_plan(arr, 1, 0)
     finally:
         fsg.fsg_graph_destroy(h)
+
+
+def _run_injected(spec, code):
+    """Runs `code` in a fresh interpreter with FSG_FAULT_INJECT=spec (the
+    library reads it once per process) and returns its stdout lines."""
+    import subprocess
+    import sys
+    env = dict(os.environ, FSG_FAULT_INJECT=spec)
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    return r.stdout.split()
+
+
+_PRELUDE = """
+import numpy as np
+from paper_2603_14895_amd import fsg
+ptr = np.array([0, 1, 2, 4], dtype=np.int64)
+src = np.array([1, 2, 0, 1], dtype=np.int32)
+def create():
+    try:
+        return fsg.fsg_graph_create(3, 4, ptr.ctypes.data, src.ctypes.data), 0
+    except fsg.FsgError as e:
+        return None, e.code
+"""
+
+
+def test_fault_injection_host_allocation():
+    """FSG_FAULT_INJECT=alloc:2: the second guarded host allocation fails
+    with FSG_ENOMEM and a message; the calls before and after succeed."""
+    out = _run_injected("alloc:2", _PRELUDE + """
+g1, c1 = create()
+g2, c2 = create()
+msg = fsg.fsg_last_error()
+g3, c3 = create()
+print(c1, c2, c3, 'host' in msg and 'allocation' in msg)
+""")
+    assert out == ["0", str(fsg.FSG_ENOMEM), "0", "True"]
+
+
+def test_fault_injection_device_call():
+    """FSG_FAULT_INJECT=device:1: the first checked HIP call (the upload in
+    fsg_graph_bind) reports FSG_EDEVICE without calling HIP, so the path runs
+    on a host without a GPU; nothing is marked bound."""
+    out = _run_injected("device:1", _PRELUDE + """
+g, c = create()
+try:
+    fsg.fsg_graph_bind(g, 1 << 20, 1 << 20, None)
+    code = 0
+except fsg.FsgError as e:
+    code = e.code
+msg = fsg.fsg_last_error()
+prm, _ = fsg.make_params('ic', p=0.1)
+try:
+    fsg.fsg_sim_workspace_size(g, prm, 64, None)
+    sim = 0
+except fsg.FsgError as e:
+    sim = e.code
+print(code, 'injected' in msg, sim)
+""")
+    assert out[:2] == [str(fsg.FSG_EDEVICE), "True"]

@@ -133,6 +133,7 @@ def test_autotune_and_cache():
         tuned = gpu_run(gnp, "sir", seeds, 512, 0x77, schedule=best, **kw)
         plain = gpu_run(gnp, "sir", seeds, 512, 0x77, **kw)
         assert_same(tuned, plain, "tuned vs default schedule")
+        assert_same(tuned, oracle_run(gnp, "sir", seeds, 512, 0x77, **kw), "tuned vs oracle")
         bb, _, _ = fsg.autotune(dg, "ic", seeds, 64, 5, tune_steps=4, batch_only=True, p=0.05)
         assert bb["kernel_variant"] == 1
         # windows longer than the poll interval cap (whole runs; the default window)

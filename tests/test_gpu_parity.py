@@ -174,6 +174,26 @@ def test_word_absorption_limits(model, B):
           max_steps=K, replicate_offset=1)
 
 
+@pytest.mark.parametrize("model", ["ic", "sir", "lt", "seir", "sis"])
+@pytest.mark.parametrize("sched,B", [
+    (dict(options=1), 300),
+    (dict(options=1, row_lanes=1, block_threads=64, tile_edges=64, heavy_threshold=16), 300),
+    (dict(options=1, row_lanes=4, heavy_threshold=40, steps_per_sync=3), 64),
+    (dict(options=1, heavy_threshold=20, steps_per_sync=2), 1100),
+])
+def test_wide_offsets_path(model, sched, B):
+    """The 64-bit-offset branches of the row-group kernels (taken by
+    themselves only on graphs with n + 1 >= 2^24, (n + 1) W >= 2^29 or
+    nnz >= 2^30), forced on small graphs: every model, edge-split rows,
+    heavy-row segments and word absorption give the oracle's bits."""
+    gr = W.chung_lu(2500, 15.0, 2.5, 63)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 8, 64)
+    K = -1 if model in ("ic", "lt") else 30
+    _both(gnp, model, seeds, B, 0xA1DE + B, f"wide-{sched}", p=0.1, beta=0.05, gamma=0.2,
+          alpha=0.3, max_steps=K, schedule=sched, replicate_offset=5)
+
+
 def test_lt_row_test_on_long_tails():
     """LT rows skip their count once at most half of the words are left and
     none of their in-neighbours gained an activation at the step before.  A
@@ -254,6 +274,46 @@ def test_c2_full_size_sampled_replicates():
                                  want_states=True)
         assert (st[:, r0:r0 + 3] == rs).all(), r0
     log(f"[parity] c2 steps={steps} absorbed={absorbed} attack={(cnt.sum() / (gr.n * c['B'])):.4f}")
+
+
+def _million_arc_hub():
+    """A hub with 10^6 in-arcs (and 2000 out-arcs) on a sparse Chung-Lu
+    background of 1.1e6 nodes."""
+    import torch
+    n, hub = 1_100_000, 7
+    rng = np.random.default_rng(1717)
+    base = W.chung_lu(n, 4.0, 2.5, 1718)
+    bp, bs = base.numpy()
+    bdst = np.repeat(np.arange(n, dtype=np.int64), np.diff(bp))
+    srcs = rng.choice(n - 1, size=1_000_000, replace=False)
+    srcs = srcs + (srcs >= hub)  # every node but the hub
+    outs = rng.choice(n, size=2000, replace=False)
+    src = np.concatenate([bs.astype(np.int64), srcs, np.full(outs.size, hub)])
+    dst = np.concatenate([bdst, np.full(srcs.size, hub), outs])
+    gr = W.pull_csr(n, torch.from_numpy(src), torch.from_numpy(dst), "hub1e6")
+    assert int(gr.indeg()[hub]) >= 1_000_000
+    return gr, hub
+
+
+@pytest.mark.parametrize("model", ["sir", "lt", "seir", "ic"])
+def test_million_arc_hub_sampled_replicates(model):
+    """A row of 10^6 in-arcs (about a thousand heavy-row segments merged by
+    the combine kernel, counts far past the SIR table's saturation, LT
+    thresholds wider than the stored planes): replicates the oracle computes
+    one by one match bit for bit."""
+    gr, hub = _million_arc_hub()
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 3000, 1719)
+    B, key = 256, 0x4B1B
+    K = -1 if model in ("ic", "lt") else 25
+    kw = dict(p=0.05, beta=0.02, gamma=0.1, alpha=0.4, max_steps=K)
+    log(f"[parity] hub1e6 {model} n={gr.n} nnz={gr.nnz}")
+    st, cnt, steps, absorbed = gpu_run(gnp, model, seeds, B, key, **kw)
+    for r0 in (0, 125, 253):
+        rs, _, _, _ = oracle_run(gnp, model, seeds, 3, key, replicate_offset=r0, want_states=True,
+                                 **kw)
+        assert (st[:, r0:r0 + 3] == rs).all(), (model, r0)
+    log(f"[parity] hub1e6 {model}: steps={steps}, hub counted in {cnt[hub]} of {B}")
 
 
 @pytest.mark.parametrize("ic_prob", ["uniform", "weighted_cascade", "per_edge"])
