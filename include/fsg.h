@@ -217,6 +217,24 @@ int fsg_simulate(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds
                  void *dev_ws, size_t ws_bytes, uint8_t *final_states, uint32_t *infected_counts,
                  fsg_run_info *info, void *stream);
 
+/* fsg_simulate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same run, with the workspace taken from a static device array of
+ * fsg_simulate_noalloc_limit() bytes (64 MiB) that each GPU the library runs
+ * on holds until the process ends.  The call itself allocates no device
+ * memory (no hipMalloc, hipFree or allocating library routine); the caller
+ * still owns the bound graph and the outputs.  Kernel timing is not done
+ * (sched->time_kernels is ignored).  Every call on one GPU uses that GPU's
+ * one array, so calls that overlap on a GPU (other threads or streams)
+ * race; the array keeps the last call's contents, and a call clears what it
+ * needs.  Errors: as fsg_simulate, and FSG_EWORKSPACE when the run needs more
+ * workspace than the array holds (fsg_sim_workspace_size tells). */
+size_t fsg_simulate_noalloc_limit(void);
+int fsg_simulate_noalloc(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds,
+                         int64_t n_seeds, int64_t B, int64_t replicate_offset, uint64_t rng_key,
+                         const fsg_schedule *sched, uint8_t *final_states,
+                         uint32_t *infected_counts, fsg_run_info *info, void *stream);
+
 /* Stateful stepping (the paper's run_iteration / run_iterations: steps that
  * continue from the current state, Sec. 3.3 "Basic Workflow").  Because
  * every draw is keyed by (unit, replicate, step), a run cut into any number

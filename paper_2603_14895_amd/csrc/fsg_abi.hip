@@ -13,6 +13,7 @@
 #include <sstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -1056,6 +1057,75 @@ int fsg_session_end(fsg_session *ss)
 {
     delete ss;
     return FSG_OK;
+}
+
+}  // extern "C"
+
+// ---- fsg_simulate without a caller workspace: the workspace is a static
+// device array of kScratchBytes, one per GPU, held until the process ends.
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_at;  // device -> address of that device's copy of scratch
+
+// Device address of the current device's copy of scratch, looked up once per
+// device (the host-side name of the array is not a device address).
+int scratch_address(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_at.find(dev);
+    if (it == g_scratch_at.end()) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255) != 0) return fail(FSG_EDEVICE, "scratch array misplaced");
+        it = g_scratch_at.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return FSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fsg_simulate_noalloc_limit(void) { return kScratchBytes; }
+
+int fsg_simulate_noalloc(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds,
+                         int64_t n_seeds, int64_t B, int64_t replicate_offset, uint64_t rng_key,
+                         const fsg_schedule *sched, uint8_t *final_states,
+                         uint32_t *infected_counts, fsg_run_info *info, void *stream)
+{
+    try {
+        fsg_schedule s;
+        if (sched) {
+            s = *sched;
+        } else {
+            memset(&s, 0, sizeof(s));
+        }
+        s.time_kernels = 0;  // no HIP events
+        size_t need = 0;
+        int rc = fsg_sim_workspace_size(g, prm, B, &s, &need);
+        if (rc) return rc;
+        if (need > kScratchBytes)
+            return fail(FSG_EWORKSPACE, "this run needs " + std::to_string(need) +
+                                            " bytes of workspace; the static scratch holds " +
+                                            std::to_string(kScratchBytes));
+        void *ws = nullptr;
+        rc = scratch_address(&ws);
+        if (rc) return rc;
+        return fsg_simulate(g, prm, seeds, n_seeds, B, replicate_offset, rng_key, &s, ws,
+                            kScratchBytes, final_states, infected_counts, info, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
 }
 
 int fsg_philox4x32_10(const uint32_t *dev_ctr, uint32_t key0, uint32_t key1, uint32_t *dev_out,

@@ -109,6 +109,10 @@ _SIGS = {
     "fsg_simulate": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _I64, _U64,
                                     ctypes.POINTER(fsg_schedule), _VP, _SZ, _VP, _VP,
                                     ctypes.POINTER(fsg_run_info), _VP]),
+    "fsg_simulate_noalloc_limit": (_SZ, []),
+    "fsg_simulate_noalloc": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64,
+                                            _I64, _U64, ctypes.POINTER(fsg_schedule), _VP, _VP,
+                                            ctypes.POINTER(fsg_run_info), _VP]),
     "fsg_session_begin": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _I64,
                                          _U64, ctypes.POINTER(fsg_schedule), _VP, _SZ, _VP,
                                          ctypes.POINTER(_VP)]),
@@ -238,6 +242,16 @@ def fsg_simulate(g, prm, seeds_addr, n_seeds, B, replicate_offset, rng_key, sche
                               ctypes.byref(sched) if sched is not None else None,
                               dev_ws, ws_bytes, states_addr, counts_addr, ctypes.byref(info),
                               stream))
+    return info
+
+
+def fsg_simulate_noalloc(g, prm, seeds_addr, n_seeds, B, replicate_offset, rng_key, sched,
+                         states_addr, counts_addr, stream=None) -> fsg_run_info:
+    info = fsg_run_info()
+    _check(lib().fsg_simulate_noalloc(g, ctypes.byref(prm), seeds_addr, n_seeds, B,
+                                      replicate_offset, rng_key & (2**64 - 1),
+                                      ctypes.byref(sched) if sched is not None else None,
+                                      states_addr, counts_addr, ctypes.byref(info), stream))
     return info
 
 
