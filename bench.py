@@ -58,17 +58,20 @@ def kernel_source_hash(workload: str = "c2") -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, kernel: str = None):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter record (FETCH_SIZE and WRITE_SIZE, scaled by what the
     same counters read for a plain copy of known size), or None when the
-    kernels changed since the record was taken."""
+    kernels changed since the record was taken or the record is of another
+    kernel."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f).get(workload)
     except (OSError, ValueError):
         return None
     if not rec or rec.get("kernel_source_hash") != kernel_source_hash(workload):
+        return None
+    if kernel is not None and rec.get("kernel") != kernel:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -108,6 +111,18 @@ def algorithmic_bytes_per_step(model: str, n: int, nnz: int, B: int, edge_parall
     W = (B + 63) // 64
     own = {"ic": 24, "lt": 16}.get(model, 32) * W
     return 4.0 * nnz + 8.0 * W * nnz + 4.0 * (n + 1) + own * n
+
+
+def finalize_bytes(model: str, n: int, B: int, states: bool, bitmap: bool) -> float:
+    """Bytes the finalize kernel must move: per node the packed words it
+    reads (the state-1 plane, except where a frontier bitmap marks it empty;
+    the removed / ever-active plane for IC, SIR, SEIR; the latent plane for
+    SEIR, SEIS), the uint8 states it writes ([n][B], if asked) and the uint32
+    count; plus one read of the n-bit frontier bitmap."""
+    W = (B + 63) // 64
+    planes = (0 if bitmap else 1) + (1 if model in ("ic", "sir", "seir") else 0) + \
+        (1 if model in ("seir", "seis") else 0)
+    return n * (8.0 * W * planes + (B if states else 0) + 4.0) + (n / 8.0 if bitmap else 0.0)
 
 
 def make_workload(name: str):
@@ -245,6 +260,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-frontier", action="store_true",
                     help="IC workloads: skip the per-step count of live frontier arcs")
+    ap.add_argument("--no-out-adjacency", action="store_true",
+                    help="IC with B <= 64: do not bind the out-adjacency (streaming step only)")
+    ap.add_argument("--stream-reference", type=int, default=5,
+                    help="frontier-driven IC: also time this many runs of the streaming step")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--schedule", default=None, help="JSON dict of fsg_schedule fields")
     ap.add_argument("--no-states", action="store_true", help="counts only (no [n][B] output)")
@@ -291,7 +310,13 @@ def main():
         f"(generated in {time.perf_counter() - t0:.1f}s)")
     del gr
     c["graph"] = None
-    dg = fsg.DeviceGraph(ptr, src, device="cuda:0")
+    # IC with one word per node: the graph's out-adjacency too, so the
+    # frontier-driven step can push over the out-arcs of small frontiers
+    want_out = c["model"] == "ic" and c["B"] <= 64 and not args.no_out_adjacency
+    t_b = time.perf_counter()
+    dg = fsg.DeviceGraph(ptr, src, device="cuda:0", out=want_out)
+    log(f"[bench] graph bound{' with its out-adjacency' if want_out else ''} in "
+        f"{time.perf_counter() - t_b:.1f}s")
     sched = json.loads(args.schedule) if args.schedule else {}
     if args.autotune:
         ts = args.tune_steps or (c["max_steps"] if c["max_steps"] > 0 else 64)
@@ -310,7 +335,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     total_updates = 0.0
-    kernel_ms = 0.0
+    kernel_ms = fin_ms = setup_ms = 0.0
     launches = 0
     steps_seen = []
     for i in range(args.steps):
@@ -318,6 +343,8 @@ def main():
         total_updates += float(src.size) * c["B"] * info.steps_run
         kernel_ms += info.step_kernel_ms
         launches += info.step_launches
+        fin_ms += info.finalize_ms
+        setup_ms += info.setup_ms
         steps_seen.append(int(info.steps_run))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
@@ -328,18 +355,58 @@ def main():
     log(f"[bench] {args.steps} steps in {dt:.3f}s: {ms_per_step:.2f} ms/step, "
         f"steps_run={steps_seen}, mean counted fraction {attack:.4f}")
 
-    avg_kernel_ms = kernel_ms / max(launches, 1)
     used = fsg.fsg_default_schedule(dg.handle, sim.prm, c["B"]).as_dict()
     used.update({k: v for k, v in sched.items() if v})
-    edge_parallel = used.get("kernel_variant") == 2
-    abytes = algorithmic_bytes_per_step(c["model"], ptr.size - 1, src.size, c["B"], edge_parallel)
-    achieved = abytes / (avg_kernel_ms / 1e3) / 1e9
+    variant = used.get("kernel_variant")
+    n = ptr.size - 1
+    step_kernel = {3: "k_ic_front", 2: "k_ic_stream"}.get(variant, "k_step")
+    avg_kernel_ms = kernel_ms / max(launches, 1)
+    kernels = {step_kernel: {"avg_launch_ms": round(avg_kernel_ms, 5), "launches": launches,
+                             "ms_per_run": round(kernel_ms / args.steps, 4)},
+               "k_finalize": {"avg_launch_ms": round(fin_ms / args.steps, 5),
+                              "launches": args.steps if fin_ms > 0 else 0,
+                              "ms_per_run": round(fin_ms / args.steps, 4)},
+               "setup": {"ms_per_run": round(setup_ms / args.steps, 4),
+                         "note": "plane fills, table uploads and seeding, host gaps included"}}
+    log(f"[bench] device time per run: {json.dumps(kernels)}")
+    # the roofline of the kernel with the most device time per run
+    if fin_ms > kernel_ms:
+        abytes = finalize_bytes(c["model"], n, c["B"], not args.no_states, variant in (2, 3))
+        kname, avg_ms, nl = "k_finalize", fin_ms / args.steps, args.steps
+    else:
+        if variant == 3:
+            raise SystemExit("no byte model for the frontier-driven step as the dominant kernel")
+        abytes = algorithmic_bytes_per_step(c["model"], n, src.size, c["B"], variant == 2)
+        kname, avg_ms, nl = step_kernel, avg_kernel_ms, launches
+    achieved = abytes / (avg_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": measured_traffic(args.workload),
-                "kernel": "k_ic_stream" if edge_parallel else "k_step",
-                "avg_launch_ms": round(avg_kernel_ms, 5), "launches": launches,
+                "traffic": measured_traffic(args.workload, kname),
+                "kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": nl,
                 "algorithmic_bytes_per_launch": abytes}
+    stream_ref = None
+    if variant == 3 and args.stream_reference > 0:
+        # the same runs with the streaming step (every arc read every step),
+        # for comparison; not part of the value
+        ref = fsg.Simulation(dg, c["model"], c["B"], want_states=not args.no_states,
+                             schedule=dict(sched, kernel_variant=2), **params_of(c))
+        ref.run(c["seeds"], c["rng_key"])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        km, kl = 0.0, 0
+        for _ in range(args.stream_reference):
+            ri = ref.run(c["seeds"], c["rng_key"])
+            km += ri.step_kernel_ms
+            kl += ri.step_launches
+        torch.cuda.synchronize()
+        d2 = time.perf_counter() - t2
+        sb = algorithmic_bytes_per_step(c["model"], n, src.size, c["B"], True)
+        stream_ref = {"kernel": "k_ic_stream", "ms_per_run": round(d2 * 1e3 / args.stream_reference, 3),
+                      "value": float(src.size) * c["B"] * int(ri.steps_run) * args.stream_reference / d2,
+                      "avg_launch_ms": round(km / max(kl, 1), 5),
+                      "hbm_frac_algorithmic": round(sb / (km / max(kl, 1) / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+        log(f"[bench] streaming step for comparison: {stream_ref}")
+        del ref
     frontier = None
     if c["model"] == "ic" and not args.no_frontier:
         outdeg = torch.bincount(torch.from_numpy(src).to("cuda"), minlength=ptr.size - 1)
@@ -347,8 +414,9 @@ def main():
         del outdeg
         frontier = {"live_arcs_per_step": live,
                     "live_arc_fraction_mean": round(float(np.mean(live)) / src.size, 6),
-                    "note": "arcs out of nodes with a newly active replicate, per step; the "
-                            "edge-parallel kernel reads every source to find them"}
+                    "note": "arcs out of nodes with a newly active replicate, per step: the "
+                            "arcs the frontier-driven step pushes over; the streaming step "
+                            "reads every source to find them"}
         log(f"[bench] live frontier arcs per step: {live}")
     cpu = None
     if not args.no_cpu_baseline:
@@ -366,9 +434,13 @@ def main():
                    "steps_run": steps_seen[-1] if steps_seen else 0, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "runs_per_s": round(args.steps / dt, 3),
+        "kernels": kernels,
     }
     if frontier is not None:
         out["frontier"] = frontier
+    if stream_ref is not None:
+        out["streaming_step_reference"] = stream_ref
     emit(out)
 
 

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FSG_ABI_VERSION 2
+#define FSG_ABI_VERSION 3
 
 /* status codes */
 #define FSG_OK 0
@@ -101,13 +101,19 @@ typedef struct {
  * the summed device time of the pull-step kernel (HIP events recorded on the
  * call's stream right around its launch in every step that did work; the
  * heavy-row combine and the frontier clear are not included) and the number
- * of steps timed; else 0. */
+ * of steps timed; else 0.
+ * setup_ms: with kernel timing, the device time from the first to the last
+ * set-up operation (table uploads, plane fills, seeding; host work between
+ * them included); finalize_ms: the device time of the kernel that writes
+ * final_states and infected_counts (fsg_simulate only); else 0. */
 typedef struct {
     int64_t steps_run;
     int32_t absorbed;
     int32_t reserved;
     double step_kernel_ms;
     int64_t step_launches;
+    double setup_ms;
+    double finalize_ms;
 } fsg_run_info;
 
 /* Launch schedule of the pull step (what the autotuner searches).  A value
@@ -125,10 +131,18 @@ typedef struct {
  *                  absorption flags.
  *   time_kernels   1: time every pull step with HIP events (reported in
  *                  fsg_run_info); 0: no timing.
- *   kernel_variant 0: the library picks; 1: row-group pull kernel (any
- *                  model and B); 2: edge-parallel IC kernel with a frontier
- *                  bitmap (IC with B <= 64 only, else FSG_EINVAL).  With
- *                  variant 2, row_lanes and block_threads are not used.
+ *   kernel_variant 0: the library picks (3 for IC with B <= 64 on a graph
+ *                  with its out-adjacency bound, else 2 for IC with
+ *                  B <= 64, else 1); 1: row-group pull kernel (any model
+ *                  and B); 2: edge-parallel IC kernel with a frontier
+ *                  bitmap (IC with B <= 64 only, else FSG_EINVAL); 3:
+ *                  frontier-driven IC (IC with B <= 64 on a graph bound
+ *                  with fsg_graph_bind_out): each step pushes the trials of
+ *                  the previous step's frontier over its out-arcs while
+ *                  those are at most nnz / 16, and otherwise streams every
+ *                  arc as variant 2 does; same draws, same results.  With
+ *                  variants 2 and 3, row_lanes is not used, and variant 3
+ *                  launches blocks of 512 threads.
  *   options        bit flags, 0 by default.  FSG_OPT_WIDE_OFFSETS: the
  *                  row-group kernels address sources and state planes with
  *                  64-bit offsets even where 32-bit ones suffice (they are
@@ -176,6 +190,20 @@ int fsg_graph_workspace_size(const fsg_graph *g, size_t *bytes);
  * and untouched while the graph is used.  Synchronous on `stream`.
  * Errors: FSG_EWORKSPACE, FSG_EDEVICE. */
 int fsg_graph_bind(fsg_graph *g, void *dev_ws, size_t ws_bytes, void *stream);
+
+/* Out-adjacency of a bound graph, for the frontier-driven IC steps
+ * (kernel_variant 3): the arcs grouped by source, each with its target row
+ * and its edge id (its position in in_src), so a step can reach the out-arcs
+ * of the nodes that just became active without scanning every arc.  Built on
+ * the device from the bound sources (out-degrees, prefix sums on the host,
+ * placement); the order of arcs inside a source's group is unspecified and
+ * does not change any result.  dev_ws: at least fsg_graph_out_workspace_size
+ * bytes (4 (n + 1) + 8 nnz + 4 n, rounded up), 256-byte aligned, kept valid
+ * and untouched while the graph is used.  Synchronous on `stream`.
+ * Errors: FSG_EINVAL (graph NULL or not bound), FSG_EWORKSPACE,
+ * FSG_EDEVICE, FSG_ENOMEM. */
+int fsg_graph_out_workspace_size(const fsg_graph *g, size_t *bytes);
+int fsg_graph_bind_out(fsg_graph *g, void *dev_ws, size_t ws_bytes, void *stream);
 
 /* n, nnz and the largest in-degree; any output may be NULL. */
 int fsg_graph_stats(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg);

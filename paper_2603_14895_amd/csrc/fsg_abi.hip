@@ -146,6 +146,11 @@ struct fsg_graph {
     int32_t *d_dst = nullptr;  // target row of every arc (built on the device at bind)
     std::vector<int32_t> wide;  // rows with more than kWideRow in-arcs, largest first
     int32_t *d_wide = nullptr;
+    // out-adjacency (fsg_graph_bind_out): arcs grouped by source
+    bool has_out = false;
+    int32_t *d_optr = nullptr;
+    int2 *d_oarc = nullptr;
+    int64_t out_items = 0;  // sum over nodes of max(1, ceil(outdeg / kOutChunk))
     std::map<std::tuple<int64_t, int64_t, int64_t>, Plan> plans;
 };
 
@@ -322,7 +327,8 @@ int check_params(const fsg_graph *g, const fsg_params *prm, int64_t B)
 
 struct Sched {
     int G, S, lgG, lgS, block, tile_edges, heavy, sync, timed;
-    bool edge1;  // edge-parallel IC kernel
+    bool edge1;  // edge-parallel IC kernel (frontier bitmap and summary)
+    bool push;   // frontier-driven IC: work queues, push over out-arcs or stream
     bool wide;   // 64-bit offsets in the row-group kernels even where 32-bit ones fit
 };
 
@@ -339,13 +345,12 @@ void default_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_sch
     o->tile_edges = 4096;
     o->heavy_threshold = 1024;
     o->steps_per_sync = 16;
-    o->kernel_variant = (prm->model == FSG_IC && W == 1) ? 2 : 1;
-    if (o->kernel_variant == 2) {  // measured best on R-MAT scale 26 at B = 64
+    o->kernel_variant = (prm->model == FSG_IC && W == 1) ? (g && g->has_out ? 3 : 2) : 1;
+    if (o->kernel_variant >= 2) {  // measured best on R-MAT scale 26 at B = 64
         o->block_threads = 512;
         o->tile_edges = 16384;
         o->heavy_threshold = 32768;
     }
-    (void)g;
 }
 
 int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fsg_schedule *in,
@@ -360,10 +365,12 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
     if (u.heavy_threshold == 0) u.heavy_threshold = d.heavy_threshold;
     if (u.steps_per_sync == 0) u.steps_per_sync = d.steps_per_sync;
     if (u.kernel_variant == 0) u.kernel_variant = d.kernel_variant;
-    if (u.kernel_variant < 1 || u.kernel_variant > 2)
-        return fail(FSG_EINVAL, "kernel_variant must be 0, 1 or 2");
-    if (u.kernel_variant == 2 && !(prm->model == FSG_IC && B <= 64))
-        return fail(FSG_EINVAL, "kernel_variant 2 needs IC with B <= 64");
+    if (u.kernel_variant < 1 || u.kernel_variant > 3)
+        return fail(FSG_EINVAL, "kernel_variant must be 0, 1, 2 or 3");
+    if (u.kernel_variant >= 2 && !(prm->model == FSG_IC && B <= 64))
+        return fail(FSG_EINVAL, "kernel_variants 2 and 3 need IC with B <= 64");
+    if (u.kernel_variant == 3 && !g->has_out)
+        return fail(FSG_EINVAL, "kernel_variant 3 needs the graph's out-adjacency (fsg_graph_bind_out)");
     if (u.row_lanes < 1 || u.row_lanes > 64 || (u.row_lanes & (u.row_lanes - 1)))
         return fail(FSG_EINVAL, "row_lanes must be a power of two in [1, 64]");
     if (u.block_threads < 64 || u.block_threads > 1024 || (u.block_threads & (u.block_threads - 1)))
@@ -384,7 +391,9 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
     s->heavy = u.heavy_threshold;
     s->sync = u.steps_per_sync;
     s->timed = u.time_kernels != 0;
-    s->edge1 = u.kernel_variant == 2;
+    s->edge1 = u.kernel_variant >= 2;
+    s->push = u.kernel_variant == 3;
+    if (s->push) s->block = 512;
     if (u.options & ~FSG_OPT_WIDE_OFFSETS) return fail(FSG_EINVAL, "unknown schedule option bits");
     s->wide = (u.options & FSG_OPT_WIDE_OFFSETS) != 0;
     return FSG_OK;
@@ -394,7 +403,7 @@ struct Layout {
     size_t planes[4];
     int n_planes;
     size_t flags, wflags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
-        seeds, bm[2], sum[2], need, stamp, total;
+        seeds, bm[3], sum[3], need, stamp, queue[4], qctl, total;
     int sum_shift, sum_words;
     int64_t W, plane_words, n_tinf, n_seed_stage;
     int L;
@@ -429,7 +438,8 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
     // one extra all-zero row (index n): gathers of padding lanes read it
     L->plane_words = (g->n + 1) * L->W;
     const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS;
-    L->n_planes = kind == kKindLT ? 2 : (latent ? 4 : 3);
+    // frontier-driven IC keeps a third frontier plane (index 3)
+    L->n_planes = kind == kKindLT ? 2 : ((latent || s.push) ? 4 : 3);
     L->L = kind == kKindIC ? 1 : counter_planes_for(std::max(p.max_light, p.max_seg));
     // room for the longest table (it stops early once it saturates), so the
     // workspace size does not depend on beta
@@ -461,20 +471,35 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
         off = align256(off + (size_t)g->n * (size_t)L->L * (size_t)L->W * 8);
     L->stamp = off;
     if (kind == kKindLT) off = align256(off + (size_t)g->n * 8);  // gain steps, two arrays
-    L->bm[0] = L->bm[1] = L->sum[0] = L->sum[1] = 0;
+    for (int i = 0; i < 3; ++i) L->bm[i] = L->sum[i] = 0;
+    for (int i = 0; i < 4; ++i) L->queue[i] = 0;
+    L->qctl = 0;
     L->sum_shift = 0;
     L->sum_words = 0;
     if (s.edge1) {
+        const int nbuf = s.push ? 3 : 2;
         const size_t bmb = (size_t)((g->n + 31) / 32) * 4;
-        L->bm[0] = off; off = align256(off + bmb);
-        L->bm[1] = off; off = align256(off + bmb);
+        for (int i = 0; i < nbuf; ++i) {
+            L->bm[i] = off;
+            off = align256(off + bmb);
+        }
         // coarsest summary that fits the kernel's LDS copy, at least 256 nodes a bit
         int sh = 8;
         while ((((g->n - 1) >> sh) >> 5) + 1 > kSumWords) ++sh;
         L->sum_shift = sh;
         L->sum_words = (int)((((g->n - 1) >> sh) >> 5) + 1);
-        L->sum[0] = off; off = align256(off + (size_t)L->sum_words * 4);
-        L->sum[1] = off; off = align256(off + (size_t)L->sum_words * 4);
+        for (int i = 0; i < nbuf; ++i) {
+            L->sum[i] = off;
+            off = align256(off + (size_t)L->sum_words * 4);
+        }
+    }
+    if (s.push) {  // four queues of (node, chunk) items; counters: uint32 [4], uint64 [4]
+        for (int i = 0; i < 4; ++i) {
+            L->queue[i] = off;
+            off = align256(off + (size_t)std::max<int64_t>(g->out_items, 1) * 8);
+        }
+        L->qctl = off;
+        off = align256(off + 64);
     }
     L->total = off;
     return FSG_OK;
@@ -511,8 +536,21 @@ struct Job {
     int64_t B = 0;
     int model = 0;
     uint64_t *pl[4] = {nullptr, nullptr, nullptr, nullptr};
-    uint32_t *bm[2] = {nullptr, nullptr};
-    uint32_t *sum[2] = {nullptr, nullptr};
+    uint32_t *bm[3] = {nullptr, nullptr, nullptr};
+    uint32_t *sum[3] = {nullptr, nullptr, nullptr};
+    uint2 *queue[4] = {nullptr, nullptr, nullptr, nullptr};
+    // frontier plane (state 1) and its bitmap after step t: the planes
+    // alternate, or rotate over three in the frontier-driven IC path
+    static int mod3(int64_t t) { return (int)(((t % 3) + 3) % 3); }
+    uint64_t *front(int64_t t) const
+    {
+        return s.push ? pl[mod3(t) == 2 ? 3 : mod3(t)] : pl[t & 1];
+    }
+    uint32_t *front_bm(int64_t t) const
+    {
+        return s.edge1 ? (s.push ? bm[mod3(t)] : bm[t & 1]) : nullptr;
+    }
+    uint32_t *front_sum(int64_t t) const { return s.push ? sum[mod3(t)] : sum[t & 1]; }
 };
 
 // Uploads the job's tables into `base`, clears its planes and seeds them
@@ -558,7 +596,9 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     HIP_TRY(up(L.tinf, tinf.data(), tinf.size() * 4));
     HIP_TRY(up(L.edge_t, edge_t.data(), edge_t.size() * 4));
 
-    for (int i = 0; i < L.n_planes; ++i) HIP_TRY(launch_fill64(jb->pl[i], L.plane_words, 0ull, st));
+    // the planes lie back to back (256-byte aligned): one zeroing launch
+    HIP_TRY(launch_zero(base + L.planes[0],
+                        L.planes[L.n_planes - 1] + (size_t)L.plane_words * 8 - L.planes[0], st));
     HIP_TRY(launch_fill32(flags, ring, 0u, st));
     uint32_t *wflags = (L.W > 16 && L.W <= 64) ? (uint32_t *)(base + L.wflags) : nullptr;
     if (wflags) {  // every word is live before step 1 (slot 0); the others clear
@@ -566,12 +606,32 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
         HIP_TRY(launch_fill32(wflags + L.W, (int64_t)ring * L.W, 0u, st));
     }
     if (s.edge1) {
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < (s.push ? 3 : 2); ++i) {
             jb->bm[i] = (uint32_t *)(base + L.bm[i]);
             jb->sum[i] = (uint32_t *)(base + L.sum[i]);
             HIP_TRY(launch_fill32(jb->bm[i], (g->n + 31) / 32, 0u, st));
             HIP_TRY(launch_fill32(jb->sum[i], L.sum_words, 0u, st));
         }
+    }
+    uint32_t *qcnt = nullptr;
+    unsigned long long *qarcs = nullptr;
+    if (s.push) {
+        for (int i = 0; i < 4; ++i) jb->queue[i] = (uint2 *)(base + L.queue[i]);
+        qcnt = (uint32_t *)(base + L.qctl);
+        qarcs = (unsigned long long *)(base + L.qctl + 32);
+        HIP_TRY(launch_fill32(qcnt, 16, 0u, st));  // counters and arc sums of the four queues
+    }
+    StepArgs sq;  // seeds join the frontier of step 0 (queue 0)
+    memset(&sq, 0, sizeof(sq));
+    if (s.push) {
+        sq.bm_next = jb->bm[0];
+        sq.sum_next = jb->sum[0];
+        sq.sum_shift = L.sum_shift;
+        sq.optr = g->d_optr;
+        sq.q_out = jb->queue[0];
+        sq.qcnt = qcnt;
+        sq.qarcs = qarcs;
+        sq.qi_out = 0;
     }
     int32_t *dseeds = (int32_t *)(base + L.seeds);
     if (kind == kKindLT) HIP_TRY(launch_fill32((uint32_t *)(base + L.stamp), 2 * g->n, 0xFFFFFFFFu, st));
@@ -580,6 +640,7 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
         HIP_TRY(hipMemcpyAsync(dseeds, seeds + i0, (size_t)cnt * 4, hipMemcpyHostToDevice, st));
         uint64_t *second = kind == kKindIC ? jb->pl[2] : nullptr;  // IC: A too
         if (kind == kKindLT) HIP_TRY(launch_stamp_seeds((uint32_t *)(base + L.stamp), dseeds, cnt, st));
+        if (s.push) HIP_TRY(launch_seed_queue(sq, dseeds, cnt, st));
         HIP_TRY(launch_seed(jb->pl[0], second, dseeds, cnt, (int32_t)L.W, B, flags, jb->bm[0],
                             jb->sum[0], L.sum_shift, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -637,6 +698,16 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.sum_words = L.sum_words;
     a.need = nullptr;
     a.stamp = kind == kKindLT ? (uint32_t *)(base + L.stamp) : nullptr;
+    if (s.push) {
+        a.optr = g->d_optr;
+        a.oarc = g->d_oarc;
+        a.qcnt = qcnt;
+        a.qarcs = qarcs;
+        // push while the frontier's out-arcs are at most 1/16 of all arcs:
+        // a pushed arc costs a random read of its target's word and more
+        // address traffic than a streamed source (4 bytes)
+        a.push_limit = (unsigned long long)(g->nnz / 16);
+    }
     if (kind == kKindLT && g->n > 0) {
         a.need = (uint64_t *)(base + L.need);
         HIP_TRY(launch_lt_need(a, st));
@@ -647,7 +718,7 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
 
 // Packed planes of the step `steps_run` -> uint8 states and counts.
 int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32_t *counts,
-                 hipStream_t st)
+                 hipStream_t st, double *ms_out = nullptr)
 {
     if (!final_states && !counts) return FSG_OK;
     FinArgs f;
@@ -658,15 +729,26 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
     f.lgG = ilog2(f.G);
     f.B = jb.B;
     f.model = jb.model;
-    f.one = jb.pl[steps_run & 1];
+    f.one = jb.front(steps_run);
     f.two = jb.kind == kKindLT ? nullptr : jb.pl[2];
     if (jb.model == FSG_SIS || jb.model == FSG_SI || jb.model == FSG_SEIS) f.two = nullptr;
-    f.three = jb.pl[3];
+    f.three = jb.kind == kKindEpidemic ? jb.pl[3] : nullptr;
     f.states = final_states;
     f.counts = counts;
-    f.bm = jb.s.edge1 ? jb.bm[steps_run & 1] : nullptr;
+    f.bm = jb.front_bm(steps_run);
+    EventPool ev;
+    if (ms_out) {
+        HIP_TRY(ev.init(2));
+        HIP_TRY(hipEventRecord(ev.e[0], st));
+    }
     HIP_TRY(launch_finalize(f, st));
+    if (ms_out) HIP_TRY(hipEventRecord(ev.e[1], st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (ms_out) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+        *ms_out = ms;
+    }
     return FSG_OK;
 }
 
@@ -679,6 +761,7 @@ struct Session {
     bool absorbed = false;
     double kernel_ms = 0.0;
     int64_t timed_steps = 0;
+    double setup_ms = 0.0, finalize_ms = 0.0;
 };
 
 int begin_session(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t n_seeds,
@@ -696,9 +779,23 @@ int begin_session(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int
     if (!dev_ws || ws_bytes < L.total) return fail(FSG_EWORKSPACE, "simulation workspace too small");
     if (((uintptr_t)dev_ws & 255) != 0) return fail(FSG_EWORKSPACE, "workspace not 256-byte aligned");
     char *base = (char *)dev_ws;
+    EventPool ev;
+    if (s.timed) {
+        HIP_TRY(ev.init(2));
+        HIP_TRY(hipEventRecord(ev.e[0], st));
+    }
     rc = setup_job(g, prm, seeds, n_seeds, B, replicate_offset, rng_key, s, p, L, base,
                    (uint32_t *)(base + L.flags), st, &ss->jb);
     if (rc) return rc;
+    ss->setup_ms = 0.0;
+    ss->finalize_ms = 0.0;
+    if (s.timed) {
+        HIP_TRY(hipEventRecord(ev.e[1], st));
+        HIP_TRY(hipEventSynchronize(ev.e[1]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+        ss->setup_ms = ms;
+    }
     ss->edge_grid = 0;
     if (s.edge1) {
         int dev = 0, ncu = 0;
@@ -728,11 +825,11 @@ FinArgs tally_args(const Session &ss, unsigned long long *out, uint32_t step)
     f.W = (int32_t)jb.L.W;
     f.B = jb.B;
     f.model = jb.model;
-    f.one = jb.pl[t & 1];
+    f.one = jb.front(t);
     f.two = jb.kind == kKindLT ? nullptr : jb.pl[2];
     if (jb.model == FSG_SIS || jb.model == FSG_SI || jb.model == FSG_SEIS) f.two = nullptr;
-    f.three = jb.pl[3];
-    f.bm = jb.s.edge1 ? jb.bm[t & 1] : nullptr;
+    f.three = jb.kind == kKindEpidemic ? jb.pl[3] : nullptr;
+    f.bm = jb.front_bm(t);
     f.tally = out;
     f.flags = step ? jb.a.flags : nullptr;
     f.ring = jb.ring;
@@ -747,6 +844,8 @@ void fill_info(const Session &ss, fsg_run_info *info)
     info->reserved = 0;
     info->step_kernel_ms = ss.kernel_ms;
     info->step_launches = ss.timed_steps;
+    info->setup_ms = ss.setup_ms;
+    info->finalize_ms = ss.finalize_ms;
 }
 
 // Up to n_more further steps (never past the job's step cap), in chunks of
@@ -772,11 +871,29 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
         for (int64_t i = 1; i <= c; ++i) {
             const int64_t step = t + i;
             a.step = (uint32_t)step;
-            a.prev = jb.pl[(step - 1) & 1];
-            a.next = jb.pl[step & 1];
+            a.prev = jb.front(step - 1);
+            a.next = jb.front(step);
             // timed: the dominant kernel of the step alone (the pull step,
             // without the bitmap clear or the heavy-row combine)
-            if (s.edge1) {
+            if (s.push) {
+                a.bm_prev = jb.front_bm(step - 1);
+                a.bm_next = jb.front_bm(step);
+                a.sum_prev = jb.front_sum(step - 1);
+                a.sum_next = jb.front_sum(step);
+                a.f_clr = jb.front(step - 2);
+                a.bm_clr = jb.front_bm(step - 2);
+                a.sum_clr = jb.front_sum(step - 2);
+                a.qi_in = (int32_t)((step + 3) % 4);
+                a.qi_out = (int32_t)(step % 4);
+                a.qi_clr = (int32_t)((step + 2) % 4);
+                a.qi_rst = (int32_t)((step + 1) % 4);
+                a.q_in = jb.queue[a.qi_in];
+                a.q_out = jb.queue[a.qi_out];
+                a.q_clr = jb.queue[a.qi_clr];
+                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
+                HIP_TRY(launch_ic_front(a, ss.edge_grid, s.block, st));
+                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
+            } else if (s.edge1) {
                 a.bm_prev = jb.bm[(step - 1) & 1];
                 a.bm_next = jb.bm[step & 1];
                 a.sum_prev = jb.sum[(step - 1) & 1];
@@ -924,6 +1041,71 @@ int fsg_graph_bind(fsg_graph *g, void *dev_ws, size_t ws_bytes, void *stream)
     }
 }
 
+namespace {
+struct OutLayout {
+    size_t optr, oarc, cursor, total;
+};
+OutLayout out_layout(const fsg_graph *g)
+{
+    OutLayout o;
+    size_t off = 0;
+    o.optr = off; off = align256(off + (size_t)(g->n + 1) * 4);
+    o.oarc = off; off = align256(off + (size_t)std::max<int64_t>(g->nnz, 1) * 8);
+    o.cursor = off; off = align256(off + (size_t)g->n * 4);
+    o.total = off;
+    return o;
+}
+}  // namespace
+
+int fsg_graph_out_workspace_size(const fsg_graph *g, size_t *bytes)
+{
+    if (!g || !bytes) return fail(FSG_EINVAL, "NULL argument");
+    *bytes = out_layout(g).total;
+    return FSG_OK;
+}
+
+int fsg_graph_bind_out(fsg_graph *g, void *dev_ws, size_t ws_bytes, void *stream)
+{
+    try {
+        if (!g) return fail(FSG_EINVAL, "graph is NULL");
+        if (!g->bound) return fail(FSG_EINVAL, "graph is not bound to device memory");
+        const OutLayout o = out_layout(g);
+        if (!dev_ws || ws_bytes < o.total) return fail(FSG_EWORKSPACE, "out-adjacency workspace too small");
+        if (((uintptr_t)dev_ws & 255) != 0) return fail(FSG_EWORKSPACE, "workspace not 256-byte aligned");
+        hipStream_t s = (hipStream_t)stream;
+        char *base = (char *)dev_ws;
+        int32_t *optr = (int32_t *)(base + o.optr);
+        int2 *oarc = (int2 *)(base + o.oarc);
+        int32_t *cursor = (int32_t *)(base + o.cursor);
+        const int64_t n = g->n;
+        // out-degrees on the device, prefix sums on the host
+        HIP_TRY(launch_fill32((uint32_t *)cursor, n, 0u, s));
+        HIP_TRY(launch_out_count(g->d_src, g->nnz, cursor, s));
+        std::vector<int32_t> deg((size_t)n), p32((size_t)n + 1);
+        HIP_TRY(hipMemcpyAsync(deg.data(), cursor, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int64_t acc = 0, items = 0;
+        for (int64_t u = 0; u < n; ++u) {
+            p32[(size_t)u] = (int32_t)acc;
+            acc += deg[(size_t)u];
+            items += deg[(size_t)u] > kOutChunk ? (deg[(size_t)u] + kOutChunk - 1) / kOutChunk : 1;
+        }
+        p32[(size_t)n] = (int32_t)acc;
+        if (acc != g->nnz) return fail(FSG_EDEVICE, "out-degree count does not add up to nnz");
+        HIP_TRY(hipMemcpyAsync(optr, p32.data(), p32.size() * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(cursor, p32.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_out_fill(g->d_src, g->d_dst, g->nnz, cursor, oarc, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        g->d_optr = optr;
+        g->d_oarc = oarc;
+        g->out_items = items;
+        g->has_out = true;
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
 int fsg_graph_stats(const fsg_graph *g, int64_t *n, int64_t *nnz, int64_t *max_indeg)
 {
     if (!g) return fail(FSG_EINVAL, "graph is NULL");
@@ -982,7 +1164,8 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         if (rc) return rc;
         rc = run_steps(ss, ss.jb.K, nullptr, (hipStream_t)stream);
         if (rc) return rc;
-        rc = finalize_job(ss.jb, ss.steps_run, final_states, infected_counts, (hipStream_t)stream);
+        rc = finalize_job(ss.jb, ss.steps_run, final_states, infected_counts, (hipStream_t)stream,
+                          ss.jb.s.timed ? &ss.finalize_ms : nullptr);
         if (rc) return rc;
         if (info) fill_info(ss, info);
         return FSG_OK;
@@ -1156,7 +1339,7 @@ namespace {
 int resolve_batch_sched(const fsg_job &j, Sched *s)
 {
     fsg_schedule u = j.sched;
-    if (u.kernel_variant == 2) return fail(FSG_EINVAL, "batched jobs use kernel_variant 0 or 1");
+    if (u.kernel_variant >= 2) return fail(FSG_EINVAL, "batched jobs use kernel_variant 0 or 1");
     u.kernel_variant = 1;
     u.block_threads = kBatchBlock;
     return resolve_sched(j.g, &j.prm, j.B, &u, s);
@@ -1380,6 +1563,8 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
                 infos[i].reserved = 0;
                 infos[i].step_kernel_ms = 0.0;
                 infos[i].step_launches = 0;
+                infos[i].setup_ms = 0.0;
+                infos[i].finalize_ms = 0.0;
             }
         }
         if (total_ms) *total_ms = kernel_ms;
@@ -1413,6 +1598,7 @@ std::vector<fsg_schedule> candidates(const fsg_graph *g, const fsg_params *prm, 
         out.push_back(s);
     };
     if (!batch_only && prm->model == FSG_IC && W == 1) {
+        if (g->has_out) add(16, 512, 16384, 32768, 3);
         for (int block : {256, 512, 1024})
             for (int tile : {8192, 16384, 32768})
                 for (int heavy : {8192, 32768}) add(16, block, tile, heavy, 2);
@@ -1424,7 +1610,6 @@ std::vector<fsg_schedule> candidates(const fsg_graph *g, const fsg_params *prm, 
         for (int block : batch_only ? std::vector<int>{kBatchBlock} : std::vector<int>{256, 512})
             for (int tile : {2048, 4096, 16384})
                 for (int heavy : {512, 1024, 4096}) add(l, block, tile, heavy, 1);
-    (void)g;
     return out;
 }
 
@@ -1432,7 +1617,8 @@ std::string tune_key(const fsg_graph *g, const fsg_params *prm, int64_t B, bool 
 {
     std::ostringstream k;
     k << "n=" << g->n << ",nnz=" << g->nnz << ",dmax=" << g->max_indeg << ",model=" << prm->model
-      << ",icp=" << prm->ic_prob << ",B=" << B << ",batch=" << (batch_only ? 1 : 0);
+      << ",icp=" << prm->ic_prob << ",B=" << B << ",batch=" << (batch_only ? 1 : 0)
+      << ",out=" << (g->has_out ? 1 : 0);
     return k.str();
 }
 

@@ -477,6 +477,8 @@ int fsg_hk(const fsg_graph *g, float eps, int64_t max_steps, int64_t B, float *d
         info->reserved = 0;
         info->step_kernel_ms = kernel_ms;
         info->step_launches = launches;
+        info->setup_ms = 0.0;
+        info->finalize_ms = 0.0;
     }
     return FSG_OK;
 }

@@ -108,7 +108,31 @@ struct StepArgs {
     // words a row's words take one pass of lanes anyway).
     uint32_t *wflags;
     int32_t wring;  // ring + 1 slots (step t must not clear t-1 or t-2)
+    // frontier-driven IC (one word per node): the out-adjacency of the graph
+    // (oarc[optr[u] .. optr[u+1]) = (target row v, edge id e) of the arcs
+    // u -> v) and four queues of (node, chunk) work items, one per step mod 4.
+    // Every node that joins the frontier of step t is queued once, as
+    // max(1, ceil(outdeg / kOutChunk)) items.  Step t reads the queue of t-1,
+    // fills the queue of t, takes the nodes of the queue of t-2 out of their
+    // plane, bitmap and summary (f_clr, bm_clr, sum_clr: the buffers step
+    // t+1 writes), and resets the counters of the queue step t+1 fills.
+    // Frontier planes, bitmaps and summaries rotate over three buffers.
+    const int32_t *optr;
+    const int2 *oarc;
+    uint2 *q_in, *q_out, *q_clr;
+    uint32_t *qcnt;              // [4] items in each queue
+    unsigned long long *qarcs;   // [4] out-arcs of each queue's nodes
+    int32_t qi_in, qi_out, qi_clr, qi_rst;
+    uint64_t *f_clr;
+    uint32_t *bm_clr, *sum_clr;
+    // step t pushes over the out-arcs of the frontier of t-1 when they are at
+    // most this many, else it streams the sources of every arc
+    unsigned long long push_limit;
 };
+
+// Out-arcs per work item of the frontier-driven IC step (a multiple of 64:
+// every lane of the item's wave takes kOutChunk / 64 of them).
+constexpr int kOutChunk = 128;
 
 struct FinArgs {
     int32_t n, W, G, lgG;
@@ -150,6 +174,7 @@ struct BatchCtl {
 
 // launchers (fsg_kernels.hip); return the hipError_t of the launch
 hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);  // p 256-byte aligned
 hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_stamp_seeds(uint32_t *stamp, const int32_t *seeds, int64_t ns, hipStream_t s);
 hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s,
@@ -159,6 +184,11 @@ hipError_t launch_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t
                        int64_t B, uint32_t *flag0, uint32_t *bm, uint32_t *sum, int sum_shift,
                        hipStream_t s);
 hipError_t launch_ic_stream(const StepArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_ic_front(const StepArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_seed_queue(const StepArgs &a, const int32_t *seeds, int64_t ns, hipStream_t s);
+hipError_t launch_out_count(const int32_t *src, int64_t nnz, int32_t *cnt, hipStream_t s);
+hipError_t launch_out_fill(const int32_t *src, const int32_t *dst, int64_t nnz, int32_t *cursor,
+                           int2 *oarc, hipStream_t s);
 hipError_t launch_expand_rows(const int32_t *ptr, int64_t n, int32_t *dst, hipStream_t s);
 hipError_t launch_ic_clear(const StepArgs &a, hipStream_t s);
 hipError_t launch_lt_need(const StepArgs &a, hipStream_t s);

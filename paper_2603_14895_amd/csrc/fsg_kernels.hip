@@ -982,19 +982,38 @@ __device__ __forceinline__ void mark_frontier(const StepArgs &a, int v)
     atomicOr(&a.sum_next[i >> 5], 1u << (i & 31));
 }
 
-__global__ void __launch_bounds__(1024) k_ic_stream(StepArgs a)
+// Joins node v to the frontier of step t (its bit in the next bitmap; the
+// first thread to set the bit also sets the summary bit and, with a queue,
+// appends v's work items and adds its out-degree to the queue's arc count).
+template <bool Q>
+__device__ __forceinline__ void join_frontier(const StepArgs &a, int v)
 {
-    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
-    __shared__ uint32_t s_sum[kSumWords];
-    for (int i = threadIdx.x; i < a.sum_words; i += blockDim.x) s_sum[i] = a.sum_prev[i];
-    __syncthreads();
+    if (!Q) {
+        mark_frontier(a, v);
+        return;
+    }
+    const uint32_t bit = 1u << (v & 31);
+    const uint32_t old = atomicOr(&a.bm_next[v >> 5], bit);
+    if (old & bit) return;
+    const int i = v >> a.sum_shift;
+    atomicOr(&a.sum_next[i >> 5], 1u << (i & 31));
+    const int deg = a.optr[v + 1] - a.optr[v];
+    const uint32_t nch = deg > kOutChunk ? (uint32_t)((deg + kOutChunk - 1) / kOutChunk) : 1u;
+    const uint32_t at = atomicAdd(&a.qcnt[a.qi_out], nch);
+    for (uint32_t k = 0; k < nch; ++k) a.q_out[at + k] = make_uint2((uint32_t)v, k);
+    if (deg > 0) atomicAdd(&a.qarcs[a.qi_out], (unsigned long long)deg);
+}
+
+// One pass of the streaming step over the source array (see above).
+template <bool Q>
+__device__ __forceinline__ void ic_stream_pass(const StepArgs &a, const uint32_t *s_sum, bool &any)
+{
     const uint64_t tail = tail_mask(0, a.B);
     const uint64_t gbase = a.goff;
     const int64_t nnz = a.nnz;
     // pass: chunk c of thread t covers arcs base + c*stride .. +3
     const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
     constexpr int kChunks = 8;  // 32 arcs in flight per thread and pass
-    bool any = false;
     for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; base < nnz;
          base += stride * kChunks) {
         int us[4 * kChunks];
@@ -1042,12 +1061,136 @@ __global__ void __launch_bounds__(1024) k_ic_stream(StepArgs a)
             if (acc) {
                 atomicOr((unsigned long long *)&a.next[v], (unsigned long long)acc);
                 atomicOr((unsigned long long *)&a.aux[v], (unsigned long long)acc);
-                mark_frontier(a, v);
+                join_frontier<Q>(a, v);
                 any = true;
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(1024) k_ic_stream(StepArgs a)
+{
+    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
+    __shared__ uint32_t s_sum[kSumWords];
+    for (int i = threadIdx.x; i < a.sum_words; i += blockDim.x) s_sum[i] = a.sum_prev[i];
+    __syncthreads();
+    bool any = false;
+    ic_stream_pass<false>(a, s_sum, any);
     if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+// Push over the out-arcs of the frontier of t-1: one wave per work item
+// (a chunk of at most kOutChunk out-arcs of a frontier node u), lanes over
+// the chunk's arcs.  An arc u -> v with edge id e runs the same trials the
+// pull step would (keyed by e, threshold of v), for the replicates where u
+// is newly active and v is not yet active.
+__device__ __forceinline__ void ic_push_pass(const StepArgs &a, bool &any)
+{
+    const uint64_t tail = tail_mask(0, a.B);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nitems = a.qcnt[a.qi_in];
+    constexpr int kPer = kOutChunk / 64;  // arcs of an item per lane
+    for (int64_t i = wave; i < nitems; i += nwave) {
+        const uint2 it = a.q_in[i];
+        const int u = (int)it.x;
+        const int o_end = a.optr[u + 1];
+        const int o_beg = a.optr[u] + (int)it.y * kOutChunk;
+        const int o_lim = o_end - o_beg < kOutChunk ? o_end : o_beg + kOutChunk;
+        const uint64_t fu = a.prev[u] & tail;
+        // the lane's arcs and their targets' active words are all requested
+        // before any trial runs, so the item waits on two load latencies
+        int2 ve[kPer];
+        uint64_t av[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int j = o_beg + lane + 64 * k;
+            ve[k] = j < o_lim ? a.oarc[j] : make_int2(-1, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) av[k] = ve[k].x >= 0 ? a.aux[ve[k].x] : ~0ull;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int v = ve[k].x;
+            const uint64_t cand = fu & ~av[k];
+            if (!cand) continue;
+            const uint32_t tv = a.edge_t ? 0u : ic_threshold(a, (uint32_t)(a.ptr[v + 1] - a.ptr[v]));
+            uint64_t acc = 0;
+            ic_edge(a, ve[k].y, cand, a.goff, tv, acc);
+            if (acc) {
+                atomicOr((unsigned long long *)&a.next[v], (unsigned long long)acc);
+                atomicOr((unsigned long long *)&a.aux[v], (unsigned long long)acc);
+                join_frontier<true>(a, v);
+                any = true;
+            }
+        }
+    }
+}
+
+// One step of the frontier-driven IC path (see StepArgs): first the nodes of
+// the frontier of t-2 leave their plane, bitmap and summary (buffers step t
+// does not touch) and the counters of the queue of t+1 are reset; then the
+// frontier of t-1 is pushed over its out-arcs when it has at most
+// push_limit of them, else the step streams every source.  The choice
+// depends only on counts from step t-1, so every block makes the same one.
+__global__ void __launch_bounds__(512) k_ic_front(StepArgs a)
+{
+    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;
+    __shared__ uint32_t s_sum[kSumWords];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    const int64_t nclr = a.qcnt[a.qi_clr];
+    for (int64_t i = tid; i < nclr; i += nthr) {
+        const uint2 it = a.q_clr[i];
+        if (it.y == 0u) {
+            a.f_clr[it.x] = 0ull;
+            a.bm_clr[it.x >> 5] = 0u;  // every set bit of this bitmap is such a node
+        }
+    }
+    for (int64_t i = tid; i < a.sum_words; i += nthr) a.sum_clr[i] = 0u;
+    if (tid == 0) {
+        a.qcnt[a.qi_rst] = 0u;
+        a.qarcs[a.qi_rst] = 0ull;
+    }
+    bool any = false;
+    if (a.qarcs[a.qi_in] <= a.push_limit) {
+        ic_push_pass(a, any);
+    } else {
+        for (int i = threadIdx.x; i < a.sum_words; i += blockDim.x) s_sum[i] = a.sum_prev[i];
+        __syncthreads();
+        ic_stream_pass<true>(a, s_sum, any);
+    }
+    if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+// Seeds of a frontier-driven run: joined to the frontier of step 0 (bitmap,
+// summary, queue 0) once each, duplicates included.
+__global__ void k_seed_queue(StepArgs a, const int32_t *seeds, int64_t ns)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns;
+         i += (int64_t)gridDim.x * blockDim.x)
+        join_frontier<true>(a, seeds[i]);
+}
+
+// Out-adjacency of a bound graph: out-degrees, then every arc placed in its
+// source's range (any order inside a range: the steps that read it combine
+// with OR).
+__global__ void k_out_count(const int32_t *src, int64_t nnz, int32_t *cnt)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[src[e]], 1);
+}
+
+__global__ void k_out_fill(const int32_t *src, const int32_t *dst, int64_t nnz, int32_t *cursor,
+                           int2 *oarc)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int at = atomicAdd(&cursor[src[e]], 1);
+        oarc[at] = make_int2(dst[e], (int)e);
+    }
 }
 
 // LT thresholds of one run, bit-sliced (one thread per node word): replicate
@@ -1263,6 +1406,18 @@ __global__ void k_batch_advance(BatchCtl c)
 
 // ------------------------------------------------------- init / output ----
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Zeroes count16 16-byte words with non-temporal stores (the zeroed planes
+// are next touched a step or more later, sparsely).
+__global__ void k_zero16(u32x4 *p, int64_t count16)
+{
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count16;
+         i += (int64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(z, p + i);
+}
+
 __global__ void k_fill64(uint64_t *p, int64_t count, uint64_t value)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -1352,7 +1507,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
             const uint32_t m1 = f.three ? 2u : 1u, m2 = f.three ? 3u : 2u;
             uint8_t *dst = f.states + v * f.B + 64ll * w;
             const int64_t nb = f.B - 64ll * w < 64 ? f.B - 64ll * w : 64;
-            if (nb == 64 && (f.B & 15) == 0) {
+            if (nb == 64 && (f.B & 15) == 0 && ((uintptr_t)f.states & 15u) == 0) {
                 uint4 *d4 = reinterpret_cast<uint4 *>(dst);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -1383,6 +1538,73 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
         }
         for (int off = 1; off < G; off <<= 1) cnt += __shfl_xor(cnt, off, 64);
         if (act && gw == 0 && f.counts) f.counts[v] = cnt;
+    }
+}
+
+// The same when B = 64 W and W is a power of two up to 64 (so G = W and a
+// wave holds one word per lane): the uint8 states of a wave's 64 words form
+// one contiguous 4 KB block, and each store instruction writes 1 KB of it
+// (pass q, lane l: bytes 16 (64 q + l) .. +15 of the block, whose word is
+// held by lane 16 q + l / 4 and reaches lane l by shuffle), instead of 16
+// bytes at a 64-byte stride per lane.  Needs a 16-byte aligned state array.
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ void __launch_bounds__(256) k_finalize_dense(FinArgs f)
+{
+    const int lane = threadIdx.x & 63;
+    const int G = f.G;
+    const int rpw = 64 >> f.lgG;
+    const int64_t gwave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave_total = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint32_t m1 = f.three ? 2u : 1u, m2 = f.three ? 3u : 2u;
+    for (int64_t rb = gwave * rpw; rb < f.n; rb += nwave_total * rpw) {
+        const int64_t v = rb + (lane >> f.lgG);
+        const int w = lane & (G - 1);
+        const bool act = v < f.n;
+        uint64_t one = 0, two = 0, three = 0;
+        if (act) {
+            const int64_t idx = v * f.W + w;
+            const bool live = !f.bm || ((f.bm[v >> 5] >> (v & 31)) & 1u);
+            one = live ? f.one[idx] : 0ull;
+            two = f.two ? f.two[idx] : 0ull;
+            three = f.three ? f.three[idx] : 0ull;
+        }
+        uint32_t cnt = (uint32_t)__popcll(f.model == kSIS ? one : (one | two | three));
+        for (int off = 1; off < G; off <<= 1) cnt += __shfl_xor(cnt, off, 64);
+        if (act && w == 0 && f.counts) f.counts[v] = cnt;
+        if (!f.states) continue;
+        uint8_t *blk = f.states + rb * f.B;
+        const int64_t limit = (f.n - rb) * f.B;  // bytes of the block inside the array
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int src = 16 * q + (lane >> 2);
+            const uint64_t o1 = shfl64(one, src), o2 = shfl64(two, src), o3 = shfl64(three, src);
+            const int sh = 16 * (lane & 3);
+            uint32_t wd[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                uint32_t x = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int bit = sh + 4 * k + j;
+                    const uint32_t s1 = (uint32_t)(o1 >> bit) & 1u;
+                    const uint32_t s2 = (uint32_t)(o2 >> bit) & 1u & ~s1;
+                    const uint32_t s3 = (uint32_t)(o3 >> bit) & 1u;
+                    x |= (s1 * m1 + s2 * m2 + s3) << (8 * j);
+                }
+                wd[k] = x;
+            }
+            const int64_t byte = 16 * (64 * q + lane);
+            if (byte < limit) {
+                const u32x4 o = {wd[0], wd[1], wd[2], wd[3]};
+                __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(blk + byte));
+            }
+        }
     }
 }
 
@@ -1455,6 +1677,19 @@ static unsigned grid_for(int64_t work, int block)
     return (unsigned)g;
 }
 
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    // 16-byte words first (p is 256-byte aligned), the last 8 bytes if any
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 > 0) {
+        hipLaunchKernelGGL(k_zero16, dim3(grid_for(n16, 256)), dim3(256), 0, s, (u32x4 *)p, n16);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (bytes % 16 >= 8) return launch_fill64((uint64_t *)((char *)p + 16 * n16), 1, 0ull, s);
+    return hipSuccess;
+}
+
 hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
@@ -1488,6 +1723,39 @@ hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStr
 {
     hipLaunchKernelGGL(k_ring_clear, dim3(1), dim3(256), 0, s, flags, ring, keep, wflags, W,
                        wring, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_front(const StepArgs &a, int grid, int block, hipStream_t s)
+{
+    // enough blocks for the larger of the two passes (4 arcs a thread when
+    // streaming; a wave per work item when pushing), at most `grid`
+    const int64_t work = std::max<int64_t>((a.nnz + 3) / 4, (int64_t)a.n * 64);
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>((work + block - 1) / block, grid));
+    hipLaunchKernelGGL(k_ic_front, dim3((unsigned)g), dim3((unsigned)block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_queue(const StepArgs &a, const int32_t *seeds, int64_t ns, hipStream_t s)
+{
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seed_queue, dim3(grid_for(ns, 256)), dim3(256), 0, s, a, seeds, ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_out_count(const int32_t *src, int64_t nnz, int32_t *cnt, hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_out_count, dim3(grid_for(nnz, 256)), dim3(256), 0, s, src, nnz, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_out_fill(const int32_t *src, const int32_t *dst, int64_t nnz, int32_t *cursor,
+                           int2 *oarc, hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_out_fill, dim3(grid_for(nnz, 256)), dim3(256), 0, s, src, dst, nnz,
+                       cursor, oarc);
     return hipGetLastError();
 }
 
@@ -1619,7 +1887,12 @@ hipError_t launch_finalize(const FinArgs &f, hipStream_t s)
     int64_t blocks = (waves + 3) / 4;
     if (blocks < 1) blocks = 1;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, s, f);
+    const bool dense = f.G == f.W && f.B == 64ll * f.W &&
+                       ((uintptr_t)f.states & 15u) == 0;
+    if (dense)
+        hipLaunchKernelGGL(k_finalize_dense, dim3((unsigned)blocks), dim3(256), 0, s, f);
+    else
+        hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, s, f);
     return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ class fsg_params(ctypes.Structure):
 class fsg_run_info(ctypes.Structure):
     _fields_ = [("steps_run", ctypes.c_int64), ("absorbed", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("step_kernel_ms", ctypes.c_double),
-                ("step_launches", ctypes.c_int64)]
+                ("step_launches", ctypes.c_int64), ("setup_ms", ctypes.c_double),
+                ("finalize_ms", ctypes.c_double)]
 
 
 class fsg_schedule(ctypes.Structure):
@@ -99,6 +100,8 @@ _SIGS = {
     "fsg_graph_create": (ctypes.c_int, [_I64, _I64, _VP, _VP, ctypes.POINTER(_VP)]),
     "fsg_graph_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
     "fsg_graph_bind": (ctypes.c_int, [_VP, _VP, _SZ, _VP]),
+    "fsg_graph_out_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
+    "fsg_graph_bind_out": (ctypes.c_int, [_VP, _VP, _SZ, _VP]),
     "fsg_graph_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                        ctypes.POINTER(_I64)]),
     "fsg_graph_destroy": (ctypes.c_int, [_VP]),
@@ -349,9 +352,10 @@ def make_schedule(d: Optional[dict]) -> Optional[fsg_schedule]:
 
 
 class DeviceGraph:
-    """A graph bound to device memory owned by a torch tensor."""
+    """A graph bound to device memory owned by a torch tensor; with
+    ``out=True`` its out-adjacency too (frontier-driven IC steps)."""
 
-    def __init__(self, ptr, src, device="cuda"):
+    def __init__(self, ptr, src, device="cuda", out=False):
         ptr = np.ascontiguousarray(ptr, dtype=np.int64)
         src = np.ascontiguousarray(src, dtype=np.int32)
         self.n = ptr.size - 1
@@ -362,6 +366,16 @@ class DeviceGraph:
         self._ws, addr = _ws(nbytes, device)
         fsg_graph_bind(self.handle, addr, nbytes, _stream_ptr())
         self.device = device
+        self._out_ws = None
+        if out:
+            self.bind_out()
+
+    def bind_out(self):
+        """Builds the out-adjacency on the device (fsg_graph_bind_out)."""
+        nb = _SZ(0)
+        _check(lib().fsg_graph_out_workspace_size(self.handle, ctypes.byref(nb)))
+        self._out_ws, addr = _ws(nb.value, self.device)
+        _check(lib().fsg_graph_bind_out(self.handle, addr, nb.value, _stream_ptr()))
 
     def stats(self):
         return fsg_graph_stats(self.handle)

@@ -17,9 +17,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gpu_run(graph_np, model, seeds, B, key, *, schedule=None, replicate_offset=0, **kw):
+def gpu_run(graph_np, model, seeds, B, key, *, schedule=None, replicate_offset=0, out=False,
+            **kw):
     ptr, src = graph_np
-    g = fsg.DeviceGraph(ptr, src)
+    g = fsg.DeviceGraph(ptr, src, out=out)
     st, cnt, steps, absorbed = fsg.simulate(g, model, seeds, B, key,
                                             replicate_offset=replicate_offset,
                                             schedule=schedule, **kw)

@@ -36,6 +36,10 @@ def test_byte_models():
         4 * nnz + 8 * W * nnz + 4 * (n + 1) + 32 * W * n
     assert bench.algorithmic_bytes_per_step("ic", n, nnz, 64, True) == 4 * nnz + n / 8
     assert bench.hk_algorithmic_bytes(n, nnz, 256) == 4 * 256 * nnz + 8 * 256 * n + 4 * nnz + 4 * (n + 1)
+    # finalize: IC with a frontier bitmap reads the ever-active plane only
+    assert bench.finalize_bytes("ic", n, 64, True, True) == n * (8 + 64 + 4) + n / 8
+    assert bench.finalize_bytes("sir", n, 1024, True, False) == n * (8 * 16 * 2 + 1024 + 4)
+    assert bench.finalize_bytes("seir", n, 64, False, False) == n * (8 * 3 + 4)
 
 
 def test_kernel_hash_is_per_workload():

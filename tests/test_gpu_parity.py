@@ -28,6 +28,7 @@ def _both(gnp, model, seeds, B, key, what, **kw):
     log(f"[parity] {what} model={model} B={B} kw={ {k: v for k, v in kw.items() if k != 'edge_p'} }")
     g = gpu_run(gnp, model, seeds, B, key, **kw)
     kw.pop("schedule", None)
+    kw.pop("out", None)
     r = oracle_run(gnp, model, seeds, B, key, **kw)
     assert_same(g, r, what)
     return g
@@ -334,6 +335,42 @@ def test_ic_edge_parallel(ic_prob, sched, B, offset, K):
           edge_p=ep, replicate_offset=offset, max_steps=K, schedule=sched)
 
 
+def _out_hub_graph():
+    """Chung-Lu background plus a node with 5000 out-arcs (ten work items of
+    the frontier-driven step) and one with 600."""
+    rng = np.random.default_rng(93)
+    base = W.chung_lu(6000, 6.0, 2.5, 94)
+    bp, bs = base.numpy()
+    dst = np.repeat(np.arange(base.n), np.diff(bp))
+    edges = list(zip(bs.tolist(), dst.tolist()))
+    for hub, k in ((11, 5000), (4321, 600)):
+        edges += [(hub, int(v)) for v in rng.choice(base.n, size=k, replace=False) if v != hub]
+    return W.from_edges(base.n, edges, "outhub")
+
+
+@pytest.mark.parametrize("graph", ["chunglu", "outhub", "dense"])
+@pytest.mark.parametrize("ic_prob", ["uniform", "weighted_cascade", "per_edge"])
+@pytest.mark.parametrize("B,offset,K", [(64, 0, -1), (37, 5, -1), (64, 2, 3), (1, 0, -1)])
+def test_ic_frontier_driven(graph, ic_prob, B, offset, K):
+    """The frontier-driven IC step (kernel variant 3: work queues, pushes
+    over out-arcs while the frontier has few of them, streams every arc
+    otherwise) gives the oracle's bits: small frontiers (pushed), a node
+    whose out-arcs span many work items, frontiers large enough to switch a
+    run to streaming and back, ragged replicate counts, a step cap."""
+    if graph == "chunglu":
+        gr, p = W.chung_lu(7000, 9.0, 2.5, 95), 0.15
+    elif graph == "outhub":
+        gr, p = _out_hub_graph(), 0.2
+    else:
+        gr, p = W.erdos_renyi_directed(2000, 40.0, 96), 0.3
+    gnp = gr.numpy()
+    ep = np.random.default_rng(97).uniform(0.0, 0.5, size=gr.nnz) if ic_prob == "per_edge" else None
+    seeds = np.concatenate([W.uniform_seeds(gr.n, 12, 98), [11, 11]]).astype(np.int32)
+    _both(gnp, "ic", seeds, B, 0xF207 + B, f"ic-front-{graph}-{ic_prob}", p=p, ic_prob=ic_prob,
+          edge_p=ep, replicate_offset=offset, max_steps=K, out=True,
+          schedule=dict(kernel_variant=3, steps_per_sync=2 if K < 0 else 16))
+
+
 def test_ic_rmat_weighted_cascade_vs_live_edge_bfs():
     """R-MAT (scale 18, edge factor 16, duplicates and self-loops kept),
     weighted cascade, 50 seeds, B = 64: the GPU matches the live-edge BFS
@@ -344,8 +381,8 @@ def test_ic_rmat_weighted_cascade_vs_live_edge_bfs():
     key = 0xC4C4C4C4
     rs, rc, _, rsteps, rabs = oracle.ic_live_edge(gnp[0], gnp[1], seeds, 64, key,
                                                  ic_prob=oracle.IC_WEIGHTED_CASCADE, nthreads=16)
-    for var in (2, 1):
+    for var in (3, 2, 1):
         g = gpu_run(gnp, "ic", seeds, 64, key, ic_prob="weighted_cascade",
-                    schedule=dict(kernel_variant=var))
+                    schedule=dict(kernel_variant=var), out=var == 3)
         assert_same(g, (rs, rc, rsteps, rabs), f"rmat18-variant{var}")
     log(f"[parity] rmat18 steps={rsteps} spread={rc.sum() / 64:.1f}")

@@ -98,3 +98,37 @@ def test_session_tallies_match_oracle(case):
         assert tuple(int(x) for x in tal[t - 1]) == want, (t, tal[t - 1], want, rsteps)
     log(f"[session] {model}: tallies of {T} steps match the oracle "
         f"(steps run {int(info.steps_run)}, absorbed {int(info.absorbed)})")
+
+
+@pytest.mark.parametrize("B,off", [(64, 0), (50, 3)])
+def test_session_frontier_driven_ic(B, off):
+    """Frontier-driven IC (work queues over three rotating frontier planes):
+    a run cut into session pieces equals one call and the oracle, and the
+    per-step tallies equal the oracle's states counted at every step."""
+    from paper_2603_14895_amd import fsg
+    gr = W.chung_lu(5000, 9.0, 2.5, 931)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 9, 932)
+    key, prm = 0xF5E5, dict(p=0.12, max_steps=-1)
+    sched = dict(kernel_variant=3, steps_per_sync=3)
+    whole = gpu_run(gnp, "ic", seeds, B, key, replicate_offset=off, schedule=sched, out=True, **prm)
+    assert_same(whole, oracle_run(gnp, "ic", seeds, B, key, replicate_offset=off, **prm), "whole")
+    g = fsg.DeviceGraph(*gnp, out=True)
+    ss = fsg.Session(g, "ic", seeds, B, key, replicate_offset=off, schedule=sched, **prm)
+    tallies = []
+    for k in _pieces(10_000):
+        info, t = ss.step(k, tally=True)
+        tallies += [tuple(int(x) for x in row) for row in t]
+        if info.absorbed:
+            break
+    st, cnt, _ = ss.read()
+    got = (st.cpu().numpy(), cnt.cpu().numpy().astype(np.uint32), int(info.steps_run),
+           int(info.absorbed))
+    assert_same(got, whole, "frontier-driven session vs one call")
+    for step in range(1, min(len(tallies), whole[2]) + 1, 3):
+        rs, _, _, _ = oracle_run(gnp, "ic", seeds, B, key, replicate_offset=off, max_steps=step,
+                                 p=prm["p"])
+        want = tuple(int((rs == s).sum()) for s in (1, 2, 3))
+        assert tallies[step - 1] == want, step
+    ss.close()
+    g.close()

@@ -29,16 +29,23 @@ def test_c4_full_size_bit_exact():
     c["graph"] = None
     torch.cuda.empty_cache()
     log(f"[webscale] graph n={ptr.size - 1} nnz={src.size} in {time.time() - t0:.1f}s")
-    g = fsg.DeviceGraph(ptr, src)
-    sim = fsg.Simulation(g, "ic", c["B"], ic_prob="weighted_cascade", max_steps=-1)
-    info = sim.run(c["seeds"], c["rng_key"])
-    gst = sim.states.cpu().numpy()
-    gcnt = sim.counts.cpu().numpy().astype(np.uint32)
-    steps, absorbed = int(info.steps_run), int(info.absorbed)
-    del sim, g
+    g = fsg.DeviceGraph(ptr, src, out=True)
+    runs = {}
+    for var in (3, 2):  # frontier-driven (the default here), then the streaming step
+        sim = fsg.Simulation(g, "ic", c["B"], ic_prob="weighted_cascade", max_steps=-1,
+                             schedule=dict(kernel_variant=var))
+        info = sim.run(c["seeds"], c["rng_key"])
+        runs[var] = (sim.states.cpu().numpy(), sim.counts.cpu().numpy().astype(np.uint32),
+                     int(info.steps_run), int(info.absorbed))
+        del sim
+        log(f"[webscale] gpu variant {var}: steps={runs[var][2]} absorbed={runs[var][3]} "
+            f"spread={runs[var][1].sum() / c['B']:.1f} at {time.time() - t0:.1f}s")
+    del g
     torch.cuda.empty_cache()
-    log(f"[webscale] gpu steps={steps} absorbed={absorbed} spread={gcnt.sum() / c['B']:.1f} "
-        f"at {time.time() - t0:.1f}s")
+    assert (runs[3][0] == runs[2][0]).all() and (runs[3][1] == runs[2][1]).all()
+    assert runs[3][2:] == runs[2][2:]
+    gst, gcnt, steps, absorbed = runs[3]
+    del runs
     rs, rc, _, rsteps, rabs = oracle.ic_live_edge(ptr, src, c["seeds"], c["B"], c["rng_key"],
                                                  ic_prob=oracle.IC_WEIGHTED_CASCADE,
                                                  nthreads=NTHREADS, verbose=True)
