@@ -351,6 +351,10 @@ void default_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_sch
         o->tile_edges = 16384;
         o->heavy_threshold = 32768;
     }
+    // frontier-driven steps take microseconds, so a run's steps after
+    // absorption (up to a chunk's worth, each an early-exit launch) cost
+    // more than a poll: shorter chunks
+    if (o->kernel_variant == 3) o->steps_per_sync = 8;
 }
 
 int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fsg_schedule *in,
@@ -493,10 +497,10 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
             off = align256(off + (size_t)L->sum_words * 4);
         }
     }
-    if (s.push) {  // four queues of (node, chunk) items; counters: uint32 [4], uint64 [4]
+    if (s.push) {  // four queues of 16-byte items; counters: uint32 [4], uint64 [4]
         for (int i = 0; i < 4; ++i) {
             L->queue[i] = off;
-            off = align256(off + (size_t)std::max<int64_t>(g->out_items, 1) * 8);
+            off = align256(off + (size_t)std::max<int64_t>(g->out_items, 1) * 16);
         }
         L->qctl = off;
         off = align256(off + 64);
@@ -538,7 +542,8 @@ struct Job {
     uint64_t *pl[4] = {nullptr, nullptr, nullptr, nullptr};
     uint32_t *bm[3] = {nullptr, nullptr, nullptr};
     uint32_t *sum[3] = {nullptr, nullptr, nullptr};
-    uint2 *queue[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint4 *queue[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<uint32_t> tinf_h, edge_t_h;  // host tables the set-up uploads
     // frontier plane (state 1) and its bitmap after step t: the planes
     // alternate, or rotate over three in the frontier-driven IC path
     static int mod3(int64_t t) { return (int)(((t % 3) + 3) % 3); }
@@ -576,9 +581,13 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
         jb->pl[i] = i < L.n_planes ? (uint64_t *)(base + L.planes[i]) : nullptr;
     const int ring = jb->ring;
 
-    std::vector<uint32_t> tinf = {0u};
+    // host tables stay in the job until the run ends: the copies below are
+    // not waited for
+    std::vector<uint32_t> &tinf = jb->tinf_h;
+    tinf.assign(1, 0u);
     if (kind == kKindEpidemic) tinf = infection_table(prm->beta, g->max_indeg);
-    std::vector<uint32_t> edge_t;
+    std::vector<uint32_t> &edge_t = jb->edge_t_h;
+    edge_t.clear();
     if (prm->model == FSG_IC && prm->ic_prob == FSG_IC_PER_EDGE) {
         edge_t.resize((size_t)g->nnz);
         for (int64_t e = 0; e < g->nnz; ++e) edge_t[(size_t)e] = threshold_of(prm->edge_p[e]);
@@ -616,7 +625,7 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     uint32_t *qcnt = nullptr;
     unsigned long long *qarcs = nullptr;
     if (s.push) {
-        for (int i = 0; i < 4; ++i) jb->queue[i] = (uint2 *)(base + L.queue[i]);
+        for (int i = 0; i < 4; ++i) jb->queue[i] = (uint4 *)(base + L.queue[i]);
         qcnt = (uint32_t *)(base + L.qctl);
         qarcs = (unsigned long long *)(base + L.qctl + 32);
         HIP_TRY(launch_fill32(qcnt, 16, 0u, st));  // counters and arc sums of the four queues
@@ -643,9 +652,9 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
         if (s.push) HIP_TRY(launch_seed_queue(sq, dseeds, cnt, st));
         HIP_TRY(launch_seed(jb->pl[0], second, dseeds, cnt, (int32_t)L.W, B, flags, jb->bm[0],
                             jb->sum[0], L.sum_shift, st));
-        HIP_TRY(hipStreamSynchronize(st));
+        // the staging array is reused by the next chunk of seeds
+        if (i0 + cnt < n_seeds) HIP_TRY(hipStreamSynchronize(st));
     }
-    HIP_TRY(hipStreamSynchronize(st));  // tables above are host temporaries
 
     StepArgs &a = jb->a;
     memset(&a, 0, sizeof(a));

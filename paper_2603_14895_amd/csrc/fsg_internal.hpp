@@ -119,7 +119,7 @@ struct StepArgs {
     // Frontier planes, bitmaps and summaries rotate over three buffers.
     const int32_t *optr;
     const int2 *oarc;
-    uint2 *q_in, *q_out, *q_clr;
+    uint4 *q_in, *q_out, *q_clr;  // items (node, chunk, first arc, end of arcs)
     uint32_t *qcnt;              // [4] items in each queue
     unsigned long long *qarcs;   // [4] out-arcs of each queue's nodes
     int32_t qi_in, qi_out, qi_clr, qi_rst;
@@ -130,9 +130,9 @@ struct StepArgs {
     unsigned long long push_limit;
 };
 
-// Out-arcs per work item of the frontier-driven IC step (a multiple of 64:
-// every lane of the item's wave takes kOutChunk / 64 of them).
-constexpr int kOutChunk = 128;
+// Out-arcs per work item of the frontier-driven IC step (one per lane of
+// the item's wave).
+constexpr int kOutChunk = 64;
 
 struct FinArgs {
     int32_t n, W, G, lgG;

@@ -982,6 +982,15 @@ __device__ __forceinline__ void mark_frontier(const StepArgs &a, int v)
     atomicOr(&a.sum_next[i >> 5], 1u << (i & 31));
 }
 
+// Work item k of node v whose out-arcs are oarc[o0 .. o1): (v, k, first arc,
+// end of its arcs).
+__device__ __forceinline__ uint4 out_item(int v, uint32_t k, int o0, int o1)
+{
+    const int b = o0 + (int)k * kOutChunk;
+    const int e = o1 - b < kOutChunk ? o1 : b + kOutChunk;
+    return make_uint4((uint32_t)v, k, (uint32_t)b, (uint32_t)e);
+}
+
 // Joins node v to the frontier of step t (its bit in the next bitmap; the
 // first thread to set the bit also sets the summary bit and, with a queue,
 // appends v's work items and adds its out-degree to the queue's arc count).
@@ -997,11 +1006,63 @@ __device__ __forceinline__ void join_frontier(const StepArgs &a, int v)
     if (old & bit) return;
     const int i = v >> a.sum_shift;
     atomicOr(&a.sum_next[i >> 5], 1u << (i & 31));
-    const int deg = a.optr[v + 1] - a.optr[v];
+    const int o0 = a.optr[v], o1 = a.optr[v + 1];
+    const int deg = o1 - o0;
     const uint32_t nch = deg > kOutChunk ? (uint32_t)((deg + kOutChunk - 1) / kOutChunk) : 1u;
     const uint32_t at = atomicAdd(&a.qcnt[a.qi_out], nch);
-    for (uint32_t k = 0; k < nch; ++k) a.q_out[at + k] = make_uint2((uint32_t)v, k);
+    for (uint32_t k = 0; k < nch; ++k) a.q_out[at + k] = out_item(v, k, o0, o1);
     if (deg > 0) atomicAdd(&a.qarcs[a.qi_out], (unsigned long long)deg);
+}
+
+// Claims node v for the frontier of step t: sets its bit in the next bitmap
+// and returns true for the one thread that set it first (which then sets
+// the summary bit and must queue v).
+__device__ __forceinline__ bool claim_frontier(const StepArgs &a, int v)
+{
+    const uint32_t bit = 1u << (v & 31);
+    const uint32_t old = atomicOr(&a.bm_next[v >> 5], bit);
+    if (old & bit) return false;
+    const int i = v >> a.sum_shift;
+    atomicOr(&a.sum_next[i >> 5], 1u << (i & 31));
+    return true;
+}
+
+// Queues the nodes the lanes of a wave claimed (v < 0: none), called by all
+// 64 lanes together: one atomic add per wave reserves the items of all of
+// them (a shuffle scan gives each lane its offset) and one adds their
+// out-arcs; a node with more than 64 items has them written by the whole
+// wave.
+__device__ __forceinline__ void queue_claimed(const StepArgs &a, int v, int o0, int o1)
+{
+    const int lane = threadIdx.x & 63;
+    const int deg = v >= 0 ? o1 - o0 : 0;
+    const uint32_t nch = v < 0 ? 0u : (deg > kOutChunk ? (uint32_t)((deg + kOutChunk - 1) / kOutChunk) : 1u);
+    if (__ballot(nch != 0u) == 0ull) return;
+    uint32_t incl = nch;
+    unsigned long long arcs = (unsigned long long)deg;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t x = (uint32_t)__shfl_up((int)incl, off, 64);
+        if (lane >= off) incl += x;
+        arcs += __shfl_xor(arcs, off, 64);
+    }
+    uint32_t base = 0;
+    if (lane == 63) {
+        base = atomicAdd(&a.qcnt[a.qi_out], incl);
+        if (arcs) atomicAdd(&a.qarcs[a.qi_out], arcs);
+    }
+    base = (uint32_t)__shfl((int)base, 63, 64);
+    const uint32_t at = base + incl - nch;
+    if (nch <= 64u) {
+        for (uint32_t k = 0; k < nch; ++k) a.q_out[at + k] = out_item(v, k, o0, o1);
+    }
+    uint64_t big = __ballot(nch > 64u);
+    while (big) {
+        const int l = __builtin_ctzll(big);
+        big &= big - 1;
+        const int bv = __shfl(v, l, 64), b0 = __shfl(o0, l, 64), b1 = __shfl(o1, l, 64);
+        const uint32_t bat = (uint32_t)__shfl((int)at, l, 64), bn = (uint32_t)__shfl((int)nch, l, 64);
+        for (uint32_t k = (uint32_t)lane; k < bn; k += 64) a.q_out[bat + k] = out_item(bv, k, b0, b1);
+    }
 }
 
 // One pass of the streaming step over the source array (see above).
@@ -1091,40 +1152,45 @@ __device__ __forceinline__ void ic_push_pass(const StepArgs &a, bool &any)
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t nitems = a.qcnt[a.qi_in];
-    constexpr int kPer = kOutChunk / 64;  // arcs of an item per lane
+    const bool wc = a.ic_prob == kIcWeightedCascade && !a.edge_t;
     for (int64_t i = wave; i < nitems; i += nwave) {
-        const uint2 it = a.q_in[i];
+        // an item carries its arc range, so the chain of dependent loads
+        // is: item; arc and source word; target's active word, in-degree
+        // and out-arc range; then the trials and the atomics
+        const uint4 it = a.q_in[i];
         const int u = (int)it.x;
-        const int o_end = a.optr[u + 1];
-        const int o_beg = a.optr[u] + (int)it.y * kOutChunk;
-        const int o_lim = o_end - o_beg < kOutChunk ? o_end : o_beg + kOutChunk;
+        const int j = (int)it.z + lane;
+        const bool has = j < (int)it.w;
         const uint64_t fu = a.prev[u] & tail;
-        // the lane's arcs and their targets' active words are all requested
-        // before any trial runs, so the item waits on two load latencies
-        int2 ve[kPer];
-        uint64_t av[kPer];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int j = o_beg + lane + 64 * k;
-            ve[k] = j < o_lim ? a.oarc[j] : make_int2(-1, 0);
+        const int2 ve = has ? a.oarc[j] : make_int2(0, 0);
+        const int v = ve.x;
+        uint64_t av = ~0ull;
+        int p0 = 0, p1 = 0, o0 = 0, o1 = 0;
+        if (has) {
+            av = a.aux[v];
+            if (wc) {
+                p0 = a.ptr[v];
+                p1 = a.ptr[v + 1];
+            }
         }
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) av[k] = ve[k].x >= 0 ? a.aux[ve[k].x] : ~0ull;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int v = ve[k].x;
-            const uint64_t cand = fu & ~av[k];
-            if (!cand) continue;
-            const uint32_t tv = a.edge_t ? 0u : ic_threshold(a, (uint32_t)(a.ptr[v + 1] - a.ptr[v]));
+        const uint64_t cand = fu & ~av;
+        int claimed = -1;
+        if (cand) {
+            const uint32_t tv = a.edge_t ? 0u : (wc ? wc_threshold((uint32_t)(p1 - p0)) : a.ic_t);
             uint64_t acc = 0;
-            ic_edge(a, ve[k].y, cand, a.goff, tv, acc);
+            ic_edge(a, ve.y, cand, a.goff, tv, acc);
             if (acc) {
                 atomicOr((unsigned long long *)&a.next[v], (unsigned long long)acc);
                 atomicOr((unsigned long long *)&a.aux[v], (unsigned long long)acc);
-                join_frontier<true>(a, v);
+                if (claim_frontier(a, v)) {
+                    claimed = v;
+                    o0 = a.optr[v];
+                    o1 = a.optr[v + 1];
+                }
                 any = true;
             }
         }
+        queue_claimed(a, claimed, o0, o1);
     }
 }
 
@@ -1140,21 +1206,27 @@ __global__ void __launch_bounds__(512) k_ic_front(StepArgs a)
     __shared__ uint32_t s_sum[kSumWords];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    // when pushing, the clearing takes the threads after the push items'
+    // waves (still in the first blocks dispatched), so no thread's chain of
+    // loads holds both
+    const bool push = a.qarcs[a.qi_in] <= a.push_limit;
+    const int64_t skip = push ? (int64_t)a.qcnt[a.qi_in] * 64 : 0;
+    const int64_t rtid = (tid - skip + nthr) % nthr;
     const int64_t nclr = a.qcnt[a.qi_clr];
-    for (int64_t i = tid; i < nclr; i += nthr) {
-        const uint2 it = a.q_clr[i];
+    for (int64_t i = rtid; i < nclr; i += nthr) {
+        const uint4 it = a.q_clr[i];
         if (it.y == 0u) {
             a.f_clr[it.x] = 0ull;
             a.bm_clr[it.x >> 5] = 0u;  // every set bit of this bitmap is such a node
         }
     }
-    for (int64_t i = tid; i < a.sum_words; i += nthr) a.sum_clr[i] = 0u;
+    for (int64_t i = rtid; i < a.sum_words; i += nthr) a.sum_clr[i] = 0u;
     if (tid == 0) {
         a.qcnt[a.qi_rst] = 0u;
         a.qarcs[a.qi_rst] = 0ull;
     }
     bool any = false;
-    if (a.qarcs[a.qi_in] <= a.push_limit) {
+    if (push) {
         ic_push_pass(a, any);
     } else {
         for (int i = threadIdx.x; i < a.sum_words; i += blockDim.x) s_sum[i] = a.sum_prev[i];
@@ -1554,57 +1626,78 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t x, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Loads the packed words of lane's node word for the dense finalize.
+struct DenseWords {
+    uint64_t one, two, three;
+    bool act;
+};
+
+__device__ __forceinline__ DenseWords dense_words(const FinArgs &f, int64_t rb, int lane)
+{
+    DenseWords d = {0ull, 0ull, 0ull, false};
+    const int64_t v = rb + (lane >> f.lgG);
+    d.act = v < f.n;
+    if (d.act) {
+        const int64_t idx = v * f.W + (lane & (f.G - 1));
+        const bool live = !f.bm || ((f.bm[v >> 5] >> (v & 31)) & 1u);
+        d.one = live ? f.one[idx] : 0ull;
+        d.two = f.two ? f.two[idx] : 0ull;
+        d.three = f.three ? f.three[idx] : 0ull;
+    }
+    return d;
+}
+
+// Counts and states of one wave's 64 words (rows rb .. rb + 64 / G - 1).
+__device__ __forceinline__ void dense_out(const FinArgs &f, int64_t rb, int lane,
+                                          const DenseWords &d)
+{
+    const int G = f.G;
+    uint32_t cnt = (uint32_t)__popcll(f.model == kSIS ? d.one : (d.one | d.two | d.three));
+    for (int off = 1; off < G; off <<= 1) cnt += __shfl_xor(cnt, off, 64);
+    if (d.act && (lane & (G - 1)) == 0 && f.counts) f.counts[rb + (lane >> f.lgG)] = cnt;
+    if (!f.states) return;
+    // state byte = s1 m1 + s2 m2 + s3 (at most 3, so bytes never carry)
+    const uint32_t m1 = f.three ? 2u : 1u, m2 = f.three ? 3u : 2u;
+    uint8_t *blk = f.states + rb * f.B;
+    const int64_t limit = (f.n - rb) * f.B;  // bytes of the block inside the array
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int src = 16 * q + (lane >> 2);
+        const uint64_t o1 = shfl64(d.one, src), o2 = shfl64(d.two, src), o3 = shfl64(d.three, src);
+        const int sh = 16 * (lane & 3);
+        const uint32_t h1 = (uint32_t)(o1 >> sh) & 0xFFFFu, h2 = (uint32_t)(o2 >> sh) & 0xFFFFu & ~h1,
+                       h3 = (uint32_t)(o3 >> sh) & 0xFFFFu;
+        uint32_t wd[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t n1 = (h1 >> (4 * k)) & 0xFu, n2 = (h2 >> (4 * k)) & 0xFu,
+                           n3 = (h3 >> (4 * k)) & 0xFu;
+            wd[k] = spread4(n1, 0x204081u, 0x01010101u) * m1 +
+                    spread4(n2, 0x204081u, 0x01010101u) * m2 + spread4(n3, 0x204081u, 0x01010101u);
+        }
+        const int64_t byte = 16 * (64 * q + lane);
+        if (byte < limit) {
+            const u32x4 o = {wd[0], wd[1], wd[2], wd[3]};
+            __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(blk + byte));
+        }
+    }
+}
+
+// Two blocks of 64 words per pass, their loads issued before either's stores.
 __global__ void __launch_bounds__(256) k_finalize_dense(FinArgs f)
 {
     const int lane = threadIdx.x & 63;
-    const int G = f.G;
     const int rpw = 64 >> f.lgG;
     const int64_t gwave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwave_total = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const uint32_t m1 = f.three ? 2u : 1u, m2 = f.three ? 3u : 2u;
-    for (int64_t rb = gwave * rpw; rb < f.n; rb += nwave_total * rpw) {
-        const int64_t v = rb + (lane >> f.lgG);
-        const int w = lane & (G - 1);
-        const bool act = v < f.n;
-        uint64_t one = 0, two = 0, three = 0;
-        if (act) {
-            const int64_t idx = v * f.W + w;
-            const bool live = !f.bm || ((f.bm[v >> 5] >> (v & 31)) & 1u);
-            one = live ? f.one[idx] : 0ull;
-            two = f.two ? f.two[idx] : 0ull;
-            three = f.three ? f.three[idx] : 0ull;
-        }
-        uint32_t cnt = (uint32_t)__popcll(f.model == kSIS ? one : (one | two | three));
-        for (int off = 1; off < G; off <<= 1) cnt += __shfl_xor(cnt, off, 64);
-        if (act && w == 0 && f.counts) f.counts[v] = cnt;
-        if (!f.states) continue;
-        uint8_t *blk = f.states + rb * f.B;
-        const int64_t limit = (f.n - rb) * f.B;  // bytes of the block inside the array
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int src = 16 * q + (lane >> 2);
-            const uint64_t o1 = shfl64(one, src), o2 = shfl64(two, src), o3 = shfl64(three, src);
-            const int sh = 16 * (lane & 3);
-            uint32_t wd[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                uint32_t x = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int bit = sh + 4 * k + j;
-                    const uint32_t s1 = (uint32_t)(o1 >> bit) & 1u;
-                    const uint32_t s2 = (uint32_t)(o2 >> bit) & 1u & ~s1;
-                    const uint32_t s3 = (uint32_t)(o3 >> bit) & 1u;
-                    x |= (s1 * m1 + s2 * m2 + s3) << (8 * j);
-                }
-                wd[k] = x;
-            }
-            const int64_t byte = 16 * (64 * q + lane);
-            if (byte < limit) {
-                const u32x4 o = {wd[0], wd[1], wd[2], wd[3]};
-                __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(blk + byte));
-            }
-        }
+    const int64_t stride = nwave_total * rpw;
+    for (int64_t rb = gwave * rpw; rb < f.n; rb += 2 * stride) {
+        const DenseWords d0 = dense_words(f, rb, lane);
+        const bool two_blocks = rb + stride < f.n;
+        const DenseWords d1 = two_blocks ? dense_words(f, rb + stride, lane)
+                                         : DenseWords{0ull, 0ull, 0ull, false};
+        dense_out(f, rb, lane, d0);
+        if (two_blocks) dense_out(f, rb + stride, lane, d1);
     }
 }
 
