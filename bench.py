@@ -35,6 +35,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# Philox4x32-10 calls per second chip-wide: one call is 20 v_mad_u64_u32 (8
+# cycles per wave64 on a SIMD) and 20 v_bitop3_b32 (4 cycles) in the build's
+# ISA, 240 SIMD cycles per 64 calls; 1024 SIMDs (256 CUs x 4) at 2.4 GHz
+PEAK_PHILOX_CALLS = 1024 * 2.4e9 * 64 / 240.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -384,6 +388,32 @@ def main():
                 "traffic": measured_traffic(args.workload, kname),
                 "kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": nl,
                 "algorithmic_bytes_per_launch": abytes}
+    roofline_other = None
+    if c["model"] in ("sir", "sis", "si", "seir", "seis") and kname == "k_step":
+        # a counting run gives the generator calls per step: the arithmetic
+        # ceiling of the same launches
+        cnt_sim = fsg.Simulation(dg, c["model"], c["B"], want_states=False,
+                                 schedule=dict(sched, time_kernels=0,
+                                               options=fsg.OPT_COUNT_DRAWS), **params_of(c))
+        ci = cnt_sim.run(c["seeds"], c["rng_key"])
+        del cnt_sim
+        calls = int(ci.philox_calls) / max(int(ci.steps_run), 1)
+        rate = calls / (avg_kernel_ms / 1e3)
+        alu = {"bound": "alu", "achieved": rate, "peak": PEAK_PHILOX_CALLS,
+               "unit": "Philox4x32-10 calls/s", "frac": round(rate / PEAK_PHILOX_CALLS, 4),
+               "traffic": None, "kernel": "k_step", "avg_launch_ms": round(avg_kernel_ms, 5),
+               "launches": launches, "calls_per_launch": calls}
+        hbm_meas = roofline["traffic"] / (avg_kernel_ms / 1e3) / 1e9 / PEAK_HBM_GBS \
+            if roofline["traffic"] else None
+        roofline["frac_measured"] = round(hbm_meas, 4) if hbm_meas is not None else None
+        log(f"[bench] generator calls per step {calls:.4g}: {alu['frac']:.3f} of the ALU ceiling; "
+            f"HBM {roofline['frac']:.3f} (algorithmic), {hbm_meas} (counters)")
+        # the binding ceiling is the one the kernel comes closer to (HBM by
+        # its measured traffic when the counter record is current)
+        if alu["frac"] > (hbm_meas if hbm_meas is not None else roofline["frac"]):
+            roofline, roofline_other = alu, roofline
+        else:
+            roofline_other = alu
     stream_ref = None
     if variant == 3 and args.stream_reference > 0:
         # the same runs with the streaming step (every arc read every step),
@@ -441,6 +471,8 @@ def main():
         out["frontier"] = frontier
     if stream_ref is not None:
         out["streaming_step_reference"] = stream_ref
+    if roofline_other is not None:
+        out["roofline_other"] = roofline_other
     emit(out)
 
 

@@ -105,7 +105,10 @@ typedef struct {
  * setup_ms: with kernel timing, the device time from the first to the last
  * set-up operation (table uploads, plane fills, seeding; host work between
  * them included); finalize_ms: the device time of the kernel that writes
- * final_states and infected_counts (fsg_simulate only); else 0. */
+ * final_states and infected_counts (fsg_simulate only); else 0.
+ * philox_calls: with FSG_OPT_COUNT_DRAWS, the Philox4x32-10 calls of the
+ * SI-family decisions over the steps run (each call gives the draws of four
+ * consecutive replicates of one node and step); else 0. */
 typedef struct {
     int64_t steps_run;
     int32_t absorbed;
@@ -114,6 +117,7 @@ typedef struct {
     int64_t step_launches;
     double setup_ms;
     double finalize_ms;
+    int64_t philox_calls;
 } fsg_run_info;
 
 /* Launch schedule of the pull step (what the autotuner searches).  A value
@@ -148,8 +152,13 @@ typedef struct {
  *                  64-bit offsets even where 32-bit ones suffice (they are
  *                  used by themselves when n + 1 >= 2^24, ceil(B/64) >=
  *                  2^21, (n + 1) ceil(B/64) >= 2^29 or nnz >= 2^30); the
- *                  results are the same either way. */
+ *                  results are the same either way.  FSG_OPT_COUNT_DRAWS:
+ *                  count the generator calls of the SI / SIS / SIR / SEIR /
+ *                  SEIS decisions (reported in fsg_run_info.philox_calls;
+ *                  one wave-reduced atomic add per row pass, so it is for
+ *                  measurement runs, not timed ones). */
 #define FSG_OPT_WIDE_OFFSETS 1
+#define FSG_OPT_COUNT_DRAWS 2
 typedef struct {
     int32_t row_lanes;
     int32_t block_threads;

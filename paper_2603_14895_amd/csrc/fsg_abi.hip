@@ -330,6 +330,7 @@ struct Sched {
     bool edge1;  // edge-parallel IC kernel (frontier bitmap and summary)
     bool push;   // frontier-driven IC: work queues, push over out-arcs or stream
     bool wide;   // 64-bit offsets in the row-group kernels even where 32-bit ones fit
+    bool count;  // count the generator calls of the SI-family decisions
 };
 
 void default_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_schedule *o)
@@ -398,8 +399,10 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
     s->edge1 = u.kernel_variant >= 2;
     s->push = u.kernel_variant == 3;
     if (s->push) s->block = 512;
-    if (u.options & ~FSG_OPT_WIDE_OFFSETS) return fail(FSG_EINVAL, "unknown schedule option bits");
+    if (u.options & ~(FSG_OPT_WIDE_OFFSETS | FSG_OPT_COUNT_DRAWS))
+        return fail(FSG_EINVAL, "unknown schedule option bits");
     s->wide = (u.options & FSG_OPT_WIDE_OFFSETS) != 0;
+    s->count = (u.options & FSG_OPT_COUNT_DRAWS) != 0;
     return FSG_OK;
 }
 
@@ -407,7 +410,7 @@ struct Layout {
     size_t planes[4];
     int n_planes;
     size_t flags, wflags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
-        seeds, bm[3], sum[3], need, stamp, queue[4], qctl, total;
+        seeds, bm[3], sum[3], need, stamp, queue[4], qctl, draws, total;
     int sum_shift, sum_words;
     int64_t W, plane_words, n_tinf, n_seed_stage;
     int L;
@@ -497,6 +500,8 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
             off = align256(off + (size_t)L->sum_words * 4);
         }
     }
+    L->draws = off;  // generator-call counter (counting runs)
+    off = align256(off + 8);
     if (s.push) {  // four queues of 16-byte items; counters: uint32 [4], uint64 [4]
         for (int i = 0; i < 4; ++i) {
             L->queue[i] = off;
@@ -707,6 +712,11 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.sum_words = L.sum_words;
     a.need = nullptr;
     a.stamp = kind == kKindLT ? (uint32_t *)(base + L.stamp) : nullptr;
+    a.draws = nullptr;
+    if (s.count) {
+        a.draws = (unsigned long long *)(base + L.draws);
+        HIP_TRY(launch_fill64((uint64_t *)a.draws, 1, 0ull, st));
+    }
     if (s.push) {
         a.optr = g->d_optr;
         a.oarc = g->d_oarc;
@@ -771,6 +781,7 @@ struct Session {
     double kernel_ms = 0.0;
     int64_t timed_steps = 0;
     double setup_ms = 0.0, finalize_ms = 0.0;
+    int64_t philox_calls = 0;
 };
 
 int begin_session(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t n_seeds,
@@ -846,6 +857,17 @@ FinArgs tally_args(const Session &ss, unsigned long long *out, uint32_t step)
     return f;
 }
 
+// The generator-call counter of a counting run into the session.
+int read_draws(Session &ss, hipStream_t st)
+{
+    if (!ss.jb.a.draws) return FSG_OK;
+    unsigned long long calls = 0;
+    HIP_TRY(hipMemcpyAsync(&calls, ss.jb.a.draws, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    ss.philox_calls = (int64_t)calls;
+    return FSG_OK;
+}
+
 void fill_info(const Session &ss, fsg_run_info *info)
 {
     info->steps_run = ss.steps_run;
@@ -855,6 +877,7 @@ void fill_info(const Session &ss, fsg_run_info *info)
     info->step_launches = ss.timed_steps;
     info->setup_ms = ss.setup_ms;
     info->finalize_ms = ss.finalize_ms;
+    info->philox_calls = ss.philox_calls;
 }
 
 // Up to n_more further steps (never past the job's step cap), in chunks of
@@ -1176,6 +1199,8 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         rc = finalize_job(ss.jb, ss.steps_run, final_states, infected_counts, (hipStream_t)stream,
                           ss.jb.s.timed ? &ss.finalize_ms : nullptr);
         if (rc) return rc;
+        rc = read_draws(ss, (hipStream_t)stream);
+        if (rc) return rc;
         if (info) fill_info(ss, info);
         return FSG_OK;
     } catch (const std::bad_alloc &) {
@@ -1222,6 +1247,8 @@ int fsg_session_step(fsg_session *ss, int64_t n_steps, uint64_t *dev_tally, fsg_
             }
             HIP_TRY(hipStreamSynchronize(st));
         }
+        rc = read_draws(s, st);
+        if (rc) return rc;
         if (info) fill_info(s, info);
         return FSG_OK;
     } catch (const std::bad_alloc &) {
@@ -1574,6 +1601,7 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
                 infos[i].step_launches = 0;
                 infos[i].setup_ms = 0.0;
                 infos[i].finalize_ms = 0.0;
+                infos[i].philox_calls = 0;
             }
         }
         if (total_ms) *total_ms = kernel_ms;

@@ -479,6 +479,7 @@ int fsg_hk(const fsg_graph *g, float eps, int64_t max_steps, int64_t B, float *d
         info->step_launches = launches;
         info->setup_ms = 0.0;
         info->finalize_ms = 0.0;
+        info->philox_calls = 0;
     }
     return FSG_OK;
 }

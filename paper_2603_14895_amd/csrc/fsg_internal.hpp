@@ -128,6 +128,9 @@ struct StepArgs {
     // step t pushes over the out-arcs of the frontier of t-1 when they are at
     // most this many, else it streams the sources of every arc
     unsigned long long push_limit;
+    // when set, the SI-family decision code adds its Philox4x32-10 calls here
+    // (a counting run; normal runs leave it null)
+    unsigned long long *draws;
 };
 
 // Out-arcs per work item of the frontier-driven IC step (one per lane of

@@ -306,6 +306,7 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
     const bool draw_lat = a.talpha != 0u && a.talpha != kAlways;
     const uint32_t trec = a.trec, tlat = a.talpha;
     uint64_t inf = 0, rec = 0, act = 0;  // S -> I or E, I -> R or S, E -> I
+    uint32_t ncalls = 0;                 // generator calls of this lane
     if (tcode != nullptr && (a.goff & 3u) == 0u) {
         // generator blocks are nibbles of the word: one draw per block with
         // any replicate that needs one, the class of each replicate read from
@@ -351,6 +352,7 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
             const uint32_t q3 = *reinterpret_cast<const uint32_t *>(tb + (T >> 24));
             const U4 o = philox10((uint32_t)v, blk0 + ((uint32_t)gs >> 2), a.step,
                                   kDomNodeStep << 24, a.key0, a.key1);
+            ++ncalls;
             uint32_t f = (o.w < q3) ? 1u : 0u;
             f = f + f + ((o.z < q2) ? 1u : 0u);
             f = f + f + ((o.y < q1) ? 1u : 0u);
@@ -385,6 +387,7 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
             const uint32_t nn = nibble_at(need, gs);
             need &= ~nibble_to_word(0xFu, gs);
             const U4 o = philox10((uint32_t)v, blk, a.step, kDomNodeStep << 24, a.key0, a.key1);
+            ++ncalls;
             const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
             const uint32_t nh = nibble_at(h, gs), ne = nibble_at(e, gs), n1 = nibble_at(sm.m1, gs),
                            n2 = nibble_at(sm.m2, gs), n3 = nibble_at(sm.m3, gs),
@@ -411,6 +414,10 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
             rec |= nibble_to_word(fr, gs);
             act |= nibble_to_word(fe, gs);
         }
+    }
+    if (a.draws) {  // counting runs only (all 64 lanes are here together)
+        for (int off = 32; off >= 1; off >>= 1) ncalls += (uint32_t)__shfl_xor((int)ncalls, off, 64);
+        if ((threadIdx.x & 63) == 0 && ncalls) atomicAdd(a.draws, (unsigned long long)ncalls);
     }
     inf = or_reduce_lanes(inf, G, S);
     rec = or_reduce_lanes(rec, G, S);

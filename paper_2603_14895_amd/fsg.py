@@ -42,7 +42,7 @@ class fsg_run_info(ctypes.Structure):
     _fields_ = [("steps_run", ctypes.c_int64), ("absorbed", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("step_kernel_ms", ctypes.c_double),
                 ("step_launches", ctypes.c_int64), ("setup_ms", ctypes.c_double),
-                ("finalize_ms", ctypes.c_double)]
+                ("finalize_ms", ctypes.c_double), ("philox_calls", ctypes.c_int64)]
 
 
 class fsg_schedule(ctypes.Structure):
@@ -56,6 +56,7 @@ class fsg_schedule(ctypes.Structure):
 
 
 OPT_WIDE_OFFSETS = 1  # FSG_OPT_WIDE_OFFSETS
+OPT_COUNT_DRAWS = 2   # FSG_OPT_COUNT_DRAWS
 
 
 CALIB_TERMS = 9

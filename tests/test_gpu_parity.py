@@ -386,3 +386,44 @@ def test_ic_rmat_weighted_cascade_vs_live_edge_bfs():
                     schedule=dict(kernel_variant=var), out=var == 3)
         assert_same(g, (rs, rc, rsteps, rabs), f"rmat18-variant{var}")
     log(f"[parity] rmat18 steps={rsteps} spread={rc.sum() / 64:.1f}")
+
+
+@pytest.mark.parametrize("B,sched", [(256, None), (1024, dict(row_lanes=4, heavy_threshold=30))])
+def test_sir_generator_call_count(B, sched):
+    """The counting run (FSG_OPT_COUNT_DRAWS) reports as many Philox4x32-10
+    calls as the decision rule needs: at step t, one call per node and block
+    of four replicates (g >> 2) in which some replicate needs a draw -- a
+    susceptible one with k >= 1 infected in-neighbours (unless k <= 3 and
+    1 - (1-beta)^k rounds to "always"), or an infected one (gamma strictly
+    between 0 and 1) -- counted here from the oracle's states after each
+    step t - 1.  The states of the counting run equal the oracle's too."""
+    import scipy.sparse as sp
+    from paper_2603_14895_amd import fsg
+    gr = W.chung_lu(900, 12.0, 2.5, 1811)
+    ptr, src = gr.numpy()
+    n = gr.n
+    seeds = W.uniform_seeds(n, 12, 1812)
+    key, kw = 0xD8A7, dict(beta=0.06, gamma=0.25, max_steps=14)
+    opt = dict(sched or {}, options=fsg.OPT_COUNT_DRAWS, time_kernels=0)
+    g = fsg.DeviceGraph(ptr, src)
+    sim = fsg.Simulation(g, "sir", B, schedule=opt, **kw)
+    info = sim.run(seeds, key)
+    got = (sim.states.cpu().numpy(), sim.counts.cpu().numpy().astype(np.uint32),
+           int(info.steps_run), int(info.absorbed))
+    assert_same(got, oracle_run((ptr, src), "sir", seeds, B, key, **kw), "counting run")
+    dst = np.repeat(np.arange(n), np.diff(ptr))
+    A = sp.csr_matrix((np.ones(src.size, dtype=np.int64), (dst, src)), shape=(n, n))
+    table = oracle.sir_table(kw["beta"], int(np.diff(ptr).max()) + 1)
+    always = 0xFFFFFFFF
+    trec = oracle.thr(kw["gamma"])
+    want = 0
+    for t in range(1, int(info.steps_run) + 1):
+        prev, _, _, _ = oracle_run((ptr, src), "sir", seeds, B, key, beta=kw["beta"],
+                                   gamma=kw["gamma"], max_steps=t - 1)
+        k = A @ (prev == 1).astype(np.int64)
+        tk = table[np.minimum(k, table.size - 1)]
+        need_s = (prev == 0) & (k >= 1) & ~((k <= 3) & (tk == always))
+        need_i = (prev == 1) & (trec not in (0, always))
+        want += int((need_s | need_i).reshape(n, B // 4, 4).any(axis=2).sum())
+    log(f"[parity] generator calls B={B}: gpu {int(info.philox_calls)}, rule {want}")
+    assert int(info.philox_calls) == want
