@@ -18,8 +18,8 @@ vectors) are in ``tests/test_oracle_*.py``.
 """
 from . import native, twin  # noqa: F401
 from .native import (  # noqa: F401
-    IC, SI, SIS, SIR, LT,
+    IC, SI, SIS, SIR, LT, SEIR, SEIS, SWIR,
     IC_UNIFORM, IC_WEIGHTED_CASCADE, IC_PER_EDGE,
     DOM_IC_EDGE, DOM_NODE_STEP, DOM_LT_THRESH,
-    philox4x32_10, draw, draw_many, thr, sir_table, simulate, ic_live_edge, hk, hk_rows, build,
+    philox4x32_10, draw, draw_many, thr, sir_table, simulate, ic_live_edge, hk, whk, hk_rows, build,
 )

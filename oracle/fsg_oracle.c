@@ -60,7 +60,8 @@
 static int orc_verbose = 0;
 void orc_set_verbose(int on) { orc_verbose = on; }
 
-enum { ORC_IC = 0, ORC_SI = 1, ORC_SIS = 2, ORC_SIR = 3, ORC_LT = 4, ORC_SEIR = 5, ORC_SEIS = 6 };
+enum { ORC_IC = 0, ORC_SI = 1, ORC_SIS = 2, ORC_SIR = 3, ORC_LT = 4, ORC_SEIR = 5, ORC_SEIS = 6,
+       ORC_SWIR = 7 };
 enum { ORC_IC_UNIFORM = 0, ORC_IC_WEIGHTED_CASCADE = 1, ORC_IC_PER_EDGE = 2 };
 enum { ORC_DOM_IC_EDGE = 1, ORC_DOM_NODE_STEP = 2, ORC_DOM_LT_THRESH = 3 };
 
@@ -155,9 +156,15 @@ typedef struct {
     const uint32_t *tinf; /* [max_indeg + 1] */
     uint32_t trec;
     uint32_t talpha; /* SEIR / SEIS: E -> I */
+    /* SWIR: S -> I or W with k infectious in-neighbours, W -> I */
+    const uint32_t *t_si, *t_siw, *t_wi;
 } orc_problem;
 
-static int is_latent_model(int model) { return model == ORC_SEIR || model == ORC_SEIS; }
+/* Models whose states are 0 S, 1 E or W, 2 I, 3 R, with seeds starting in I. */
+static int is_latent_model(int model)
+{
+    return model == ORC_SEIR || model == ORC_SEIS || model == ORC_SWIR;
+}
 
 /* Threshold of in-edge e of node v for IC. */
 static uint32_t ic_edge_threshold(const orc_problem *P, int64_t v, int64_t e)
@@ -177,8 +184,13 @@ static uint32_t ic_edge_threshold(const orc_problem *P, int64_t v, int64_t e)
 static int has_one(const orc_problem *P, const uint8_t *x, int64_t n)
 {
     const int latent = is_latent_model(P->model);
-    for (int64_t v = 0; v < n; ++v)
-        if (x[v] == 1 || (latent && x[v] == 2)) return 1;
+    for (int64_t v = 0; v < n; ++v) {
+        if (P->model == ORC_SWIR) {  /* a weakened node alone changes nothing */
+            if (x[v] == 2) return 1;
+        } else if (x[v] == 1 || (latent && x[v] == 2)) {
+            return 1;
+        }
+    }
     return 0;
 }
 
@@ -213,6 +225,30 @@ static void one_step(const orc_problem *P, uint64_t g, uint32_t t, const uint8_t
                 uint64_t U = orc_draw(P->rng_key, ORC_DOM_LT_THRESH, (uint64_t)v, g, 0);
                 /* active-weight c / indeg reaches the threshold U / 2^32 */
                 if (c >= 1 && ((uint64_t)c << 32) >= U * (uint64_t)indeg) yv = 1;
+            }
+        } else if (P->model == ORC_SWIR) {
+            /* an infectious node is removed after one step; a susceptible
+             * node with k infectious in-neighbours becomes I with probability
+             * 1-(1-kappa)^k, else W with probability (1-kappa)^k -
+             * (1-kappa-mu)^k (one draw decides both); a weakened one becomes
+             * I with probability 1-(1-nu)^k */
+            if (xv == 2) {
+                yv = 3;
+            } else if (xv == 0 || xv == 1) {
+                int64_t k = 0;
+                for (int64_t e = e0; e < e1; ++e)
+                    if (x[P->src[e]] == 2) ++k;
+                if (k > 0) {
+                    uint32_t U = orc_draw(P->rng_key, ORC_DOM_NODE_STEP, (uint64_t)v, g, t);
+                    if (xv == 0) {
+                        if (fires(U, P->t_si[k]))
+                            yv = 2;
+                        else if (fires(U, P->t_siw[k]))
+                            yv = 1;
+                    } else if (fires(U, P->t_wi[k])) {
+                        yv = 2;
+                    }
+                }
             }
         } else if (is_latent_model(P->model)) { /* SEIR, SEIS */
             uint32_t U = orc_draw(P->rng_key, ORC_DOM_NODE_STEP, (uint64_t)v, g, t);
@@ -279,8 +315,9 @@ int orc_simulate(int model, int ic_prob, double p, const double *edge_p, double 
                  uint64_t rng_key, uint8_t *states, uint32_t *counts, int64_t *steps_run,
                  int32_t *absorbed, int nthreads)
 {
-    if (n < 1 || B < 0 || model < ORC_IC || model > ORC_SEIS) return -1;
-    if (model != ORC_IC && model != ORC_LT && max_steps < 0) return -1;
+    if (n < 1 || B < 0 || model < ORC_IC || model > ORC_SWIR) return -1;
+    if (model != ORC_IC && model != ORC_LT && model != ORC_SWIR && max_steps < 0) return -1;
+    if (model == ORC_SWIR && !(beta + alpha <= 1.0)) return -1;
     for (int64_t i = 0; i < n_seeds; ++i)
         if (seeds[i] < 0 || seeds[i] >= n) return -1;
 
@@ -288,9 +325,19 @@ int orc_simulate(int model, int ic_prob, double p, const double *edge_p, double 
     uint32_t *tinf = (uint32_t *)calloc((size_t)(dmax + 1), sizeof(uint32_t));
     orc_sir_table(beta, dmax + 1, tinf);
     orc_problem P = {model, ic_prob, p, beta, (model == ORC_SI) ? 0.0 : gamma, edge_p, max_steps,
-                     n, ptr, src, rng_key, tinf, 0, 0};
+                     n, ptr, src, rng_key, tinf, 0, 0, NULL, NULL, NULL};
     P.trec = orc_thr(P.gamma);
     P.talpha = orc_thr(alpha);
+    /* SWIR: kappa = beta (S -> I), mu = alpha (S -> W), nu = gamma (W -> I) */
+    uint32_t *t_siw = (uint32_t *)calloc((size_t)(dmax + 1), sizeof(uint32_t));
+    uint32_t *t_wi = (uint32_t *)calloc((size_t)(dmax + 1), sizeof(uint32_t));
+    if (model == ORC_SWIR) {
+        orc_sir_table(beta + alpha, dmax + 1, t_siw);
+        orc_sir_table(gamma, dmax + 1, t_wi);
+    }
+    P.t_si = tinf;
+    P.t_siw = t_siw;
+    P.t_wi = t_wi;
 
     int64_t smax = 0;
     int any_one = 0;
@@ -316,7 +363,7 @@ int orc_simulate(int model, int ic_prob, double p, const double *edge_p, double 
                 if (states) states[v * B + r] = out;
                 /* counted: IC ever active; SIR/SI ever infected; SIS infected
                  * at the end; LT active; SEIR ever exposed; SEIS exposed or
-                 * infectious at the end */
+                 * infectious at the end; SWIR ever weakened or infected */
                 int counted = (model == ORC_SIS)    ? (s == 1)
                               : (model == ORC_SEIS) ? (s == 1 || s == 2)
                                                     : (s != 0);
@@ -334,6 +381,8 @@ int orc_simulate(int model, int ic_prob, double p, const double *edge_p, double 
         free(x);
     }
     free(tinf);
+    free(t_siw);
+    free(t_wi);
     if (steps_run) *steps_run = smax;
     if (absorbed) *absorbed = !any_one;
     return 0;
@@ -374,7 +423,8 @@ int orc_ic_live_edge(int ic_prob, double p, const double *edge_p, int64_t max_st
             oeid[pos] = e;
         }
     free(fill);
-    orc_problem P = {ORC_IC, ic_prob, p, 0.0, 0.0, edge_p, max_steps, n, ptr, src, rng_key, NULL, 0, 0};
+    orc_problem P = {ORC_IC, ic_prob, p, 0.0, 0.0, edge_p, max_steps, n, ptr, src, rng_key, NULL, 0, 0,
+                     NULL, NULL, NULL};
 
     int64_t smax = 0;
     int any_one = 0;
@@ -481,6 +531,29 @@ void orc_draw_many(uint64_t rng_key, uint32_t dom, const uint64_t *unit, const u
  */
 /* New opinion of node v in replicate r from the opinions x [n][B]. */
 static float hk_node(float eps, const int64_t *ptr, const int32_t *src, int64_t B, const float *x,
+                     int64_t v, int64_t r);
+
+/* Weighted HK: node v moves the fraction mu of the way from its opinion h
+ * to the HK mean m of its eps-neighbourhood: (1 - mu) h + mu m, each product
+ * and the sum rounded to single precision; h itself when no in-neighbour is
+ * within eps.  mu = 1 is plain HK. */
+static float whk_node(float eps, float mu, const int64_t *ptr, const int32_t *src, int64_t B,
+                      const float *x, int64_t v, int64_t r)
+{
+    const float hv = x[v * B + r];
+    const float m = hk_node(eps, ptr, src, B, x, v, r);
+    if (mu == 1.0f) return m;
+    int any = 0;
+    for (int64_t e = ptr[v]; e < ptr[v + 1] && !any; ++e)
+        if (fabsf(hv - x[(int64_t)src[e] * B + r]) < eps) any = 1;
+    if (!any) return hv;
+    const float one_minus = 1.0f - mu;
+    volatile float a = one_minus * hv; /* no contraction */
+    volatile float b = mu * m;
+    return a + b;
+}
+
+static float hk_node(float eps, const int64_t *ptr, const int32_t *src, int64_t B, const float *x,
                      int64_t v, int64_t r)
 {
     const float hv = x[v * B + r];
@@ -508,10 +581,11 @@ int orc_hk_rows(float eps, int64_t n, const int64_t *ptr, const int32_t *src, in
     return 0;
 }
 
-int orc_hk(float eps, int64_t max_steps, int64_t n, const int64_t *ptr, const int32_t *src,
-           int64_t B, float *h, int64_t *steps_run, int32_t *converged, int nthreads)
+int orc_whk(float eps, float mu, int64_t max_steps, int64_t n, const int64_t *ptr,
+            const int32_t *src, int64_t B, float *h, int64_t *steps_run, int32_t *converged,
+            int nthreads)
 {
-    if (n < 1 || B < 0 || max_steps < 0) return -1;
+    if (n < 1 || B < 0 || max_steps < 0 || !(mu >= 0.0f && mu <= 1.0f)) return -1;
     float *x = (float *)malloc((size_t)n * (size_t)B * sizeof(float));
     float *y = (float *)malloc((size_t)n * (size_t)B * sizeof(float));
     memcpy(x, h, (size_t)n * (size_t)B * sizeof(float));
@@ -528,7 +602,7 @@ int orc_hk(float eps, int64_t max_steps, int64_t n, const int64_t *ptr, const in
 #endif
         for (int64_t r = 0; r < B; ++r) {
             for (int64_t v = 0; v < n; ++v) {
-                const float nv = hk_node(eps, ptr, src, B, x, v, r);
+                const float nv = whk_node(eps, mu, ptr, src, B, x, v, r);
                 y[v * B + r] = nv;
                 if (nv != x[v * B + r]) changed = 1;
             }
@@ -543,4 +617,10 @@ int orc_hk(float eps, int64_t max_steps, int64_t n, const int64_t *ptr, const in
     if (steps_run) *steps_run = t;
     if (converged) *converged = !changed;
     return 0;
+}
+
+int orc_hk(float eps, int64_t max_steps, int64_t n, const int64_t *ptr, const int32_t *src,
+           int64_t B, float *h, int64_t *steps_run, int32_t *converged, int nthreads)
+{
+    return orc_whk(eps, 1.0f, max_steps, n, ptr, src, B, h, steps_run, converged, nthreads);
 }

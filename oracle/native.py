@@ -14,10 +14,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fsg_oracle.c")
 _LIB = os.path.join(_HERE, "libfsg_oracle.so")
 
-IC, SI, SIS, SIR, LT, SEIR, SEIS = 0, 1, 2, 3, 4, 5, 6
+IC, SI, SIS, SIR, LT, SEIR, SEIS, SWIR = 0, 1, 2, 3, 4, 5, 6, 7
 IC_UNIFORM, IC_WEIGHTED_CASCADE, IC_PER_EDGE = 0, 1, 2
 DOM_IC_EDGE, DOM_NODE_STEP, DOM_LT_THRESH = 1, 2, 3
-MODEL_NAMES = {"ic": IC, "si": SI, "sis": SIS, "sir": SIR, "lt": LT, "seir": SEIR, "seis": SEIS}
+MODEL_NAMES = {"ic": IC, "si": SI, "sis": SIS, "sir": SIR, "lt": LT, "seir": SEIR, "seis": SEIS,
+               "swir": SWIR}
 
 
 def build(force: bool = True) -> str:
@@ -74,6 +75,11 @@ def _load():
                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                ctypes.c_int]
         lib.orc_hk.restype = ctypes.c_int
+        lib.orc_whk.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_int64, ctypes.c_int64,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.c_int]
+        lib.orc_whk.restype = ctypes.c_int
         lib.orc_hk_rows.argtypes = [ctypes.c_float, ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
@@ -189,6 +195,25 @@ def hk(ptr, src, h0, eps, max_steps, nthreads=0):
     conv = ctypes.c_int32(0)
     rc = lib.orc_hk(float(np.float32(eps)), int(max_steps), n, _ptr(ptr), _ptr(src), B, _ptr(h),
                     ctypes.byref(steps), ctypes.byref(conv), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return h, int(steps.value), int(conv.value)
+
+
+def whk(ptr, src, h0, eps, mu, max_steps, nthreads=0):
+    """Weighted Hegselmann-Krause: each node moves the fraction mu of the way
+    to its HK mean, (1 - mu) h + mu m in float32.  Returns (h, steps_run,
+    converged) as :func:`hk`."""
+    lib = _load()
+    ptr, src = _csr(ptr, src)
+    n = ptr.size - 1
+    h = np.ascontiguousarray(h0, dtype=np.float32).copy()
+    assert h.shape[0] == n
+    B = h.shape[1]
+    steps = ctypes.c_int64(0)
+    conv = ctypes.c_int32(0)
+    rc = lib.orc_whk(float(np.float32(eps)), float(np.float32(mu)), int(max_steps), n, _ptr(ptr),
+                     _ptr(src), B, _ptr(h), ctypes.byref(steps), ctypes.byref(conv), int(nthreads))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return h, int(steps.value), int(conv.value)

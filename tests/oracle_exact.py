@@ -192,3 +192,48 @@ def zscore(freq, p, B):
     """Binomial z-score of an observed frequency against an exact probability."""
     var = max(p * (1.0 - p), 1e-12) / B
     return (freq - p) / np.sqrt(var)
+
+
+def swir_exact_marginals(n, ptr, src, seeds, kappa, mu, nu, steps):
+    """Exact synchronous SWIR Markov chain on all 4^n joint states (states
+    0 S, 1 W, 2 I, 3 R; seeds start in I).
+
+    Given the previous joint state every node moves independently, with k
+    the number of in-arcs from nodes in I: S -> I with probability
+    1 - (1-kappa)^k, S -> W with probability (1-kappa)^k - (1-kappa-mu)^k;
+    W -> I with probability 1 - (1-nu)^k; I -> R; R stays.  Returns
+    P[x_v = s] after ``steps`` steps as an array [n, 4]."""
+    rows = [[int(src[e]) for e in range(ptr[v], ptr[v + 1])] for v in range(n)]
+    x0 = [0] * n
+    for s in seeds:
+        x0[s] = 2
+    dist = {tuple(x0): 1.0}
+    for _ in range(steps):
+        nxt = {}
+        for x, mass in dist.items():
+            per_node = []
+            for v in range(n):
+                k = sum(1 for u in rows[v] if x[u] == 2)
+                if x[v] == 0:
+                    pi = 1.0 - (1.0 - kappa) ** k
+                    pw = (1.0 - kappa) ** k - (1.0 - kappa - mu) ** k
+                    per_node.append([(0, 1.0 - pi - pw), (1, pw), (2, pi)])
+                elif x[v] == 1:
+                    q = 1.0 - (1.0 - nu) ** k
+                    per_node.append([(1, 1.0 - q), (2, q)])
+                else:
+                    per_node.append([(3, 1.0)])
+            for combo in itertools.product(*per_node):
+                w = mass
+                for _, q in combo:
+                    w *= q
+                if w == 0.0:
+                    continue
+                y = tuple(s for s, _ in combo)
+                nxt[y] = nxt.get(y, 0.0) + w
+        dist = nxt
+    marg = np.zeros((n, 4))
+    for x, mass in dist.items():
+        for v in range(n):
+            marg[v, x[v]] += mass
+    return marg

@@ -145,3 +145,62 @@ def test_row_step_equals_whole_step():
     h1, _, _ = oracle.hk(ptr, src, h0, 0.32, 1)
     rows = np.array([0, 5, 399, 17, 5])
     assert (oracle.hk_rows(ptr, src, h0, 0.32, rows) == h1[rows]).all()
+
+
+# ---- weighted HK: a node moves the fraction mu of the way to its HK mean
+
+
+def _run_w(edges, n, h0, eps, mu, K):
+    ptr, src = W.from_edges(n, edges).numpy()
+    h0 = np.asarray(h0, dtype=np.float32)
+    if h0.ndim == 1:
+        h0 = h0[:, None]
+    return oracle.whk(ptr, src, h0, eps, mu, K)
+
+
+@pytest.mark.parametrize("mu", [0.2, 0.5, 0.9])
+def test_whk_complete_digraph_one_step_closed_form(mu):
+    """Complete digraph without self-loops, eps above every gap: each node
+    moves to (1 - mu) h_i + mu (S - h_i) / (n - 1)."""
+    n = 9
+    rng = np.random.default_rng(15)
+    h0 = rng.uniform(-1, 1, n).astype(np.float32)
+    edges = [(j, i) for i in range(n) for j in range(n) if i != j]
+    h, steps, conv = _run_w(edges, n, h0, 2.5, mu, 1)
+    S = float(h0.astype(np.float64).sum())
+    h64 = h0.astype(np.float64)
+    mu64 = float(np.float32(mu))
+    want = (1 - mu64) * h64 + mu64 * (S - h64) / (n - 1)
+    assert steps == 1 and conv == 0
+    assert np.max(np.abs(h[:, 0] - want)) < 2e-6
+
+
+def test_whk_pair_contracts_geometrically():
+    """Two nodes with arcs both ways and eps above their gap: the gap shrinks
+    by the factor 1 - 2 mu every step, the mean stays."""
+    mu = 0.2
+    h0 = np.array([-0.15, 0.1], dtype=np.float32)
+    for K in range(1, 8):
+        h, steps, _ = _run_w([(0, 1), (1, 0)], 2, h0, 0.32, mu, K)
+        gap = float(h[1, 0]) - float(h[0, 0])
+        assert abs(gap - 0.25 * (1 - 2 * 0.2) ** K) < 1e-6 * K, (K, gap)
+        assert abs(float(h[:, 0].astype(np.float64).mean()) - (-0.025)) < 1e-6
+
+
+def test_whk_special_cases():
+    """mu = 0 moves nothing (the first step changes nothing, so the run
+    stops); mu = 1 is plain HK bit for bit; a node with no in-neighbour
+    within eps keeps its opinion; opinions stay in the hull of the start."""
+    rng = np.random.default_rng(16)
+    gr = W.chung_lu(300, 8.0, 2.5, 17)
+    ptr, src = gr.numpy()
+    h0 = rng.uniform(-1, 1, (gr.n, 5)).astype(np.float32)
+    h, steps, conv = oracle.whk(ptr, src, h0, 0.32, 0.0, 10)
+    assert (h == h0).all() and steps == 1 and conv == 1
+    a, sa, ca = oracle.whk(ptr, src, h0, 0.32, 1.0, 7)
+    b, sb, cb = oracle.hk(ptr, src, h0, 0.32, 7)
+    assert (a.view(np.uint32) == b.view(np.uint32)).all() and (sa, ca) == (sb, cb)
+    w, _, _ = oracle.whk(ptr, src, h0, 0.32, 0.2, 12)
+    assert (w.min(axis=0) >= h0.min(axis=0)).all() and (w.max(axis=0) <= h0.max(axis=0)).all()
+    lone, _, _ = _run_w([(0, 1)], 3, [0.0, 0.9, 0.5], 0.32, 0.5, 3)
+    assert lone[1, 0] == np.float32(0.9) and lone[2, 0] == np.float32(0.5)

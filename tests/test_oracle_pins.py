@@ -375,6 +375,85 @@ def test_seir_deterministic_latency():
             assert (st[d] == want).all(), (K, d, st[d], want)
 
 
+# ----------------------------------------------------------- SWIR pins --
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_swir_exact_markov_chain(case):
+    """Per-node marginals of S, W, I, R after K steps equal those of the
+    exact synchronous SWIR chain over all 4^n joint states (the weakened
+    state needs two infectious contacts in different steps, so a node reached
+    by two paths carries the nu term)."""
+    rng = np.random.default_rng(250 + case)
+    n = 5
+    edges = [(int(rng.integers(n)), int(rng.integers(n))) for _ in range(9)] + \
+        [(0, 1), (0, 2), (2, 1), (1, 3)]
+    gr = W.from_edges(n, edges)
+    ptr, src = gr.numpy()
+    kappa, mu, nu, K, B = 0.3, 0.35, 0.5, 4, 40000
+    marg = X.swir_exact_marginals(n, ptr, src, [0], kappa, mu, nu, K)
+    st, _, _, _ = oracle.simulate("swir", ptr, src, [0], B, 0x5A1 + case, beta=kappa, alpha=mu,
+                                  gamma=nu, max_steps=K)
+    for v in range(n):
+        for s in range(4):
+            f = (st[v] == s).mean()
+            assert abs(X.zscore(f, marg[v, s], B)) < ZMAX, (v, s, f, marg[v, s])
+
+
+def test_swir_without_weakening_is_sir_with_one_step_recovery():
+    """mu = 0: no node is ever weakened, and SWIR(kappa, 0, nu) is SIR with
+    beta = kappa and gamma = 1 (recovery after exactly one step) under the
+    same draws, bit for bit (SWIR's I and R are SIR's 1 and 2)."""
+    gr = W.chung_lu(400, 8.0, 2.5, 251)
+    ptr, src = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 6, 252)
+    a, ac, asteps, aab = oracle.simulate("swir", ptr, src, seeds, 96, 0x5A2, beta=0.2, alpha=0.0,
+                                         gamma=0.7, max_steps=-1)
+    b, bc, bsteps, bab = oracle.simulate("sir", ptr, src, seeds, 96, 0x5A2, beta=0.2, gamma=1.0,
+                                         max_steps=400)
+    assert (a != 1).all()
+    relabel = np.array([0, 2, 3], dtype=np.uint8)
+    assert (a == relabel[b]).all()
+    assert (ac == bc).all() and asteps == bsteps and aab == bab == 1
+
+
+def test_swir_single_edge_closed_form():
+    """Arc 0 -> 1, seed 0: the seed is removed after one step, so node 1 gets
+    one contact: it ends weakened with probability mu, removed (infected at
+    step 1) with probability kappa, susceptible otherwise; the run absorbs at
+    step 2 (or 1 when node 1 is not infected)."""
+    gr = W.from_edges(2, [(0, 1)])
+    ptr, src = gr.numpy()
+    kappa, mu, nu, B = 0.25, 0.4, 0.9, 100000
+    st, cnt, steps, absorbed = oracle.simulate("swir", ptr, src, [0], B, 0x5A3, beta=kappa,
+                                               alpha=mu, gamma=nu, max_steps=-1)
+    assert absorbed == 1 and steps == 2 and (st[0] == 3).all()
+    assert abs(X.zscore((st[1] == 1).mean(), mu, B)) < ZMAX
+    assert abs(X.zscore((st[1] == 3).mean(), kappa, B)) < ZMAX
+    assert cnt[1] == (st[1] != 0).sum()
+
+
+def test_swir_weakened_then_infected_closed_form():
+    """Seed 0 -> 1 and 0 -> 2 -> 1: node 1 is infected either at step 1
+    (kappa), or, if weakened at step 1 (mu) and node 2 infected at step 1
+    (kappa), at step 2 with nu; if still susceptible and node 2 infected, at
+    step 2 with kappa.  P[1 ever infected] = kappa + kappa (mu nu + (1 -
+    kappa - mu) kappa)."""
+    gr = W.from_edges(3, [(0, 1), (0, 2), (2, 1)])
+    ptr, src = gr.numpy()
+    kappa, mu, nu, B = 0.3, 0.3, 0.6, 200000
+    st, _, _, _ = oracle.simulate("swir", ptr, src, [0], B, 0x5A4, beta=kappa, alpha=mu,
+                                  gamma=nu, max_steps=-1)
+    want = kappa + kappa * (mu * nu + (1 - kappa - mu) * kappa)
+    assert abs(X.zscore((st[1] == 3).mean(), want, B)) < ZMAX
+
+
+def test_swir_refuses_kappa_plus_mu_above_one():
+    gr = W.from_edges(2, [(0, 1)])
+    ptr, src = gr.numpy()
+    with pytest.raises(ValueError):
+        oracle.simulate("swir", ptr, src, [0], 4, 1, beta=0.7, alpha=0.4, gamma=0.1, max_steps=3)
+
+
 # -------------------------------------------------------------- LT pins --
 
 @pytest.mark.parametrize("case", [0, 1, 2])
