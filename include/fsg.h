@@ -62,6 +62,7 @@ extern "C" {
 #define FSG_LT 4  /* linear threshold, in-weights 1/indeg, thresholds U(0,1)    */
 #define FSG_SEIR 5 /* SEIR(DT): 0 S, 1 E (latent), 2 I, 3 R                     */
 #define FSG_SEIS 6 /* SEIS(DT): SEIR with recovery back to S                    */
+#define FSG_SWIR 7 /* SWIR: 0 S, 1 W (weakened), 2 I, 3 R                      */
 
 /* IC edge probability */
 #define FSG_IC_UNIFORM 0          /* p for every arc                         */
@@ -81,7 +82,15 @@ typedef struct fsg_graph fsg_graph;
  * 1 - (1-beta)^k, E becomes I with probability alpha, I becomes R (SEIS: S)
  * with probability gamma, one draw per node, replicate and step; seeds
  * start infectious; they require K >= 0.  alpha must lie in [0, 1] and is
- * ignored by the other models. */
+ * ignored by the other models.
+ * SWIR (named in Table tab:29s and compared in Table tab:result with three
+ * parameters; the paper gives no rule, so this is a reading): kappa = beta,
+ * mu = alpha, nu = gamma, kappa + mu <= 1.  With k infected in-neighbours a
+ * susceptible node becomes I with probability 1 - (1-kappa)^k, else W with
+ * probability (1-kappa)^k - (1-kappa-mu)^k (one draw decides both), a
+ * weakened node becomes I with probability 1 - (1-nu)^k, and an infected
+ * node is removed after one step; seeds start infected; a negative K means
+ * "until no node is infected". */
 typedef struct {
     int32_t model;
     int32_t ic_prob;
@@ -239,11 +248,11 @@ int fsg_sim_workspace_size(const fsg_graph *g, const fsg_params *prm, int64_t B,
  * Outputs (device, either may be NULL):
  *   final_states [n][B] uint8, final_states[v*B + r] = state of node v in
  *     replicate r (IC 0/1/2, SIR 0/1/2, SI and SIS 0/1, LT 0/1,
- *     SEIR 0/1/2/3, SEIS 0/1/2);
+ *     SEIR 0/1/2/3, SEIS 0/1/2, SWIR 0/1/2/3);
  *   infected_counts [n] uint32, the number of replicates in which v is
  *     counted: ever active (IC), ever infected (SI, SIR), infected at the
  *     end (SIS), active (LT), ever exposed (SEIR), exposed or infectious at
- *     the end (SEIS).
+ *     the end (SEIS), ever weakened or infected (SWIR).
  * info (host, may be NULL) receives steps_run and absorbed.
  * The graph must be bound.  dev_ws: at least fsg_sim_workspace_size bytes,
  * 256-byte aligned; its contents on entry do not matter.  The call returns
@@ -334,6 +343,17 @@ int fsg_hk_workspace_size(const fsg_graph *g, int64_t B, const fsg_schedule *sch
 int fsg_hk(const fsg_graph *g, float eps, int64_t max_steps, int64_t B, float *dev_h,
            const fsg_schedule *sched, void *dev_ws, size_t ws_bytes, float act,
            uint32_t *dev_counts, fsg_run_info *info, void *stream);
+/* Weighted HK (named "WHK" in Table tab:29s, compared with the parameters
+ * (0.32, 0.2) in Table tab:result; the paper gives no rule, so this is a
+ * reading): each node moves the fraction mu in [0, 1] of the way from its
+ * opinion h to the HK mean m of its eps-neighbourhood, h' = (1 - mu) h +
+ * mu m (two products and a sum, each rounded to FP32, no contraction), and
+ * keeps h when no in-neighbour is within eps.  mu = 1 is fsg_hk; otherwise
+ * as fsg_hk (same workspace, flags, counts and errors, FSG_EINVAL for mu
+ * outside [0, 1]). */
+int fsg_whk(const fsg_graph *g, float eps, float mu, int64_t max_steps, int64_t B, float *dev_h,
+            const fsg_schedule *sched, void *dev_ws, size_t ws_bytes, float act,
+            uint32_t *dev_counts, fsg_run_info *info, void *stream);
 
 /* ---- Batches: many jobs (graphs, models, seed sets, B) in one launch per
  * synchronous step (Definition "Batched Monte Carlo Method" applied across

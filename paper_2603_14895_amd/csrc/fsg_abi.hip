@@ -297,12 +297,13 @@ int check_params(const fsg_graph *g, const fsg_params *prm, int64_t B)
 {
     if (!g) return fail(FSG_EINVAL, "graph is NULL");
     if (!prm) return fail(FSG_EINVAL, "params is NULL");
-    if (prm->model < FSG_IC || prm->model > FSG_SEIS) return fail(FSG_EINVAL, "unknown model");
+    if (prm->model < FSG_IC || prm->model > FSG_SWIR) return fail(FSG_EINVAL, "unknown model");
     if (B < 1) return fail(FSG_EINVAL, "B must be >= 1");
     if (B > (int64_t)1 << 31) return fail(FSG_EUNSUPPORTED, "B above 2^31");
-    const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS;
+    const bool swir = prm->model == FSG_SWIR;
+    const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS || swir;
     const bool epi = prm->model == FSG_SI || prm->model == FSG_SIS || prm->model == FSG_SIR || latent;
-    if (epi && prm->max_steps < 0)
+    if (epi && !swir && prm->max_steps < 0)
         return fail(FSG_EINVAL, "SI/SIS/SIR/SEIR/SEIS need max_steps >= 0");
     if (prm->max_steps > 0x7FFFFFFF) return fail(FSG_EUNSUPPORTED, "max_steps above 2^31-1");
     if (prm->model == FSG_IC) {
@@ -321,6 +322,8 @@ int check_params(const fsg_graph *g, const fsg_params *prm, int64_t B)
         if (prm->model != FSG_SI && bad_prob(prm->gamma))
             return fail(FSG_EINVAL, "gamma must be in [0, 1]");
         if (latent && bad_prob(prm->alpha)) return fail(FSG_EINVAL, "alpha must be in [0, 1]");
+        if (swir && !(prm->beta + prm->alpha <= 1.0))
+            return fail(FSG_EINVAL, "SWIR needs beta + alpha <= 1 (kappa + mu)");
     }
     return FSG_OK;
 }
@@ -444,13 +447,14 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
     L->W = (B + 63) / 64;
     // one extra all-zero row (index n): gathers of padding lanes read it
     L->plane_words = (g->n + 1) * L->W;
-    const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS;
+    const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS || prm->model == FSG_SWIR;
     // frontier-driven IC keeps a third frontier plane (index 3)
     L->n_planes = kind == kKindLT ? 2 : ((latent || s.push) ? 4 : 3);
     L->L = kind == kKindIC ? 1 : counter_planes_for(std::max(p.max_light, p.max_seg));
     // room for the longest table (it stops early once it saturates), so the
     // workspace size does not depend on beta
-    L->n_tinf = kind == kKindEpidemic ? g->max_indeg + 1 : 1;
+    // SWIR keeps three tables (S -> I, S -> I or W, W -> I) of that length
+    L->n_tinf = (kind == kKindEpidemic ? g->max_indeg + 1 : 1) * (prm->model == FSG_SWIR ? 3 : 1);
     L->n_seed_stage = std::min<int64_t>(g->n, kSeedStage);
     size_t off = 0;
     for (int i = 0; i < L->n_planes; ++i) {
@@ -591,6 +595,19 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     std::vector<uint32_t> &tinf = jb->tinf_h;
     tinf.assign(1, 0u);
     if (kind == kKindEpidemic) tinf = infection_table(prm->beta, g->max_indeg);
+    // SWIR: kappa = beta (S -> I), mu = alpha (S -> W), nu = gamma (W -> I);
+    // S -> I or W with 1 - (1 - kappa - mu)^k, the sum formed in FP64
+    const bool swir = prm->model == FSG_SWIR;
+    const size_t n_si = tinf.size();
+    size_t n_siw = 0, n_wi = 0;
+    if (swir) {
+        const std::vector<uint32_t> siw = infection_table(prm->beta + prm->alpha, g->max_indeg);
+        const std::vector<uint32_t> wi = infection_table(prm->gamma, g->max_indeg);
+        n_siw = siw.size();
+        n_wi = wi.size();
+        tinf.insert(tinf.end(), siw.begin(), siw.end());
+        tinf.insert(tinf.end(), wi.begin(), wi.end());
+    }
     std::vector<uint32_t> &edge_t = jb->edge_t_h;
     edge_t.clear();
     if (prm->model == FSG_IC && prm->ic_prob == FSG_IC_PER_EDGE) {
@@ -679,10 +696,14 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     a.ic_t = threshold_of(prm->p);
     a.edge_t = edge_t.empty() ? nullptr : (const uint32_t *)(base + L.edge_t);
     a.tinf = (const uint32_t *)(base + L.tinf);
-    a.khat = (int32_t)tinf.size() - 1;
+    a.khat = (int32_t)n_si - 1;
+    a.tsiw = swir ? a.tinf + n_si : nullptr;
+    a.twi = swir ? a.tinf + n_si + n_siw : nullptr;
+    a.khat_siw = swir ? (int32_t)n_siw - 1 : 0;
+    a.khat_wi = swir ? (int32_t)n_wi - 1 : 0;
     a.trec = prm->model == FSG_SI ? 0u : threshold_of(prm->gamma);
-    const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS;
-    a.talpha = latent ? threshold_of(prm->alpha) : 0u;
+    const bool latent = prm->model == FSG_SEIR || prm->model == FSG_SEIS || swir;
+    a.talpha = (latent && !swir) ? threshold_of(prm->alpha) : 0u;
     a.lat = latent ? jb->pl[3] : nullptr;
     a.G = s.G;
     a.S = s.S;

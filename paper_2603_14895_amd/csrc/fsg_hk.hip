@@ -59,6 +59,7 @@ struct Args {
     int64_t B;
     int64_t lanes;        // n * B / vec
     float eps;
+    float mu, omm;        // weighted HK: fraction moved towards the mean, and 1 - mu
     const float *x;       // opinions after the previous step
     float *y;             // opinions after this step
     uint32_t *flags;      // ring: 1 iff the step changed an opinion
@@ -82,9 +83,13 @@ __device__ __forceinline__ void take(float hv, float hj, float eps, float &mc, i
     mv += in ? 1 : 0;
 }
 
-__device__ __forceinline__ float settle(float hv, float mc, int mv)
+__device__ __forceinline__ float settle(const Args &a, float hv, float mc, int mv)
 {
-    return mv > 0 ? __fdiv_rn(mc, (float)mv) : hv;
+    if (mv == 0) return hv;
+    const float m = __fdiv_rn(mc, (float)mv);
+    // weighted HK: (1 - mu) h + mu m, two rounded products and a rounded sum
+    // (no contraction); mu = 1 is plain HK
+    return a.mu == 1.0f ? m : __fadd_rn(__fmul_rn(a.omm, hv), __fmul_rn(a.mu, m));
 }
 
 // ---- hub rows ---------------------------------------------------------------
@@ -189,7 +194,7 @@ __device__ void hub_row(const Args &a, float (*lds)[kTile][kCols])
         __syncthreads();
     }
     if (w == 0) {
-        const float nv = settle(hv, mc, mv);
+        const float nv = settle(a, hv, mc, mv);
         if (live) a.y[(int64_t)v * a.B + col] = nv;
         mark_changed(a, live && nv != hv);
     }
@@ -268,7 +273,7 @@ __device__ void light_row(const Args &a, int64_t idx)
 #pragma unroll
             for (int c = 0; c < VEC; ++c) {
                 const float h = Vec<VEC>::get(hv, c);
-                const float nv = settle(h, mc[c], mv[c]);
+                const float nv = settle(a, h, mc[c], mv[c]);
                 Vec<VEC>::set(out, c, nv);
                 ch |= nv != h;
             }
@@ -367,6 +372,14 @@ int fsg_hk(const fsg_graph *g, float eps, int64_t max_steps, int64_t B, float *d
            const fsg_schedule *sched, void *dev_ws, size_t ws_bytes, float act,
            uint32_t *dev_counts, fsg_run_info *info, void *stream)
 {
+    return fsg_whk(g, eps, 1.0f, max_steps, B, dev_h, sched, dev_ws, ws_bytes, act, dev_counts,
+                   info, stream);
+}
+
+int fsg_whk(const fsg_graph *g, float eps, float mu, int64_t max_steps, int64_t B, float *dev_h,
+            const fsg_schedule *sched, void *dev_ws, size_t ws_bytes, float act,
+            uint32_t *dev_counts, fsg_run_info *info, void *stream)
+{
     View G;
     int rc = view_of(g, &G);
     if (rc) return rc;
@@ -374,6 +387,7 @@ int fsg_hk(const fsg_graph *g, float eps, int64_t max_steps, int64_t B, float *d
     if (B < 1) return set_error(FSG_EINVAL, "B must be >= 1");
     if (max_steps < 0) return set_error(FSG_EINVAL, "max_steps must be >= 0");
     if (!(eps >= 0.0f) || isinf(eps)) return set_error(FSG_EINVAL, "eps must be finite and >= 0");
+    if (!(mu >= 0.0f && mu <= 1.0f)) return set_error(FSG_EINVAL, "mu must be in [0, 1]");
     if (isnan(act)) return set_error(FSG_EINVAL, "act is NaN");
     const int vec = (B % 4 == 0) ? 4 : 1;
     const int64_t lanes = G.n * (B / vec);
@@ -405,6 +419,8 @@ int fsg_hk(const fsg_graph *g, float eps, int64_t max_steps, int64_t B, float *d
     a.B = B;
     a.lanes = lanes;
     a.eps = eps;
+    a.mu = mu;
+    a.omm = 1.0f - mu;
     a.flags = flags;
     const int64_t grid = a.hub_blocks + (lanes + kBlock - 1) / kBlock;
 

@@ -34,7 +34,7 @@ enum Kind { kKindIC = 0, kKindEpidemic = 1, kKindLT = 2 };
 constexpr int kMaxTileRows = 2048;
 // Words of the frontier summary the edge-parallel kernel keeps in LDS.
 constexpr int kSumWords = 8192;
-enum Model { kIC = 0, kSI = 1, kSIS = 2, kSIR = 3, kLT = 4, kSEIR = 5, kSEIS = 6 };
+enum Model { kIC = 0, kSI = 1, kSIS = 2, kSIR = 3, kLT = 4, kSEIR = 5, kSEIS = 6, kSWIR = 7 };
 enum IcProb { kIcUniform = 0, kIcWeightedCascade = 1, kIcPerEdge = 2 };
 
 // Everything one synchronous step needs.  Planes are uint64 [n][W]:
@@ -62,7 +62,12 @@ struct StepArgs {
     int32_t khat;           // last index of tinf
     uint32_t trec;          // recovery threshold
     uint32_t talpha;        // SEIR / SEIS: E -> I threshold
-    uint64_t *lat;          // SEIR / SEIS: latent (E) plane [n][W], updated in place; else null
+    uint64_t *lat;          // SEIR / SEIS: latent (E) plane, SWIR: weakened (W) plane [n][W],
+                            // updated in place; else null
+    // SWIR: thresholds of S -> I or W and of W -> I by infected-neighbour
+    // count (tinf holds S -> I); each table stops where it saturates
+    const uint32_t *tsiw, *twi;
+    int32_t khat_siw, khat_wi;
     // schedule
     int32_t G, S, lgG, lgS; // lanes per row: G over words, S over edges
     int32_t heavy;          // rows with more in-edges are processed as segments

@@ -294,6 +294,62 @@ __device__ __forceinline__ uint32_t spread4(uint32_t n, uint32_t mul, uint32_t m
     return __umul24(n, mul) & mask;
 }
 
+// SWIR (states S, W weakened, I, R; a reading of the model the paper only
+// names): with k infected in-neighbours a susceptible replicate becomes I if
+// its draw fires against thr(1-(1-kappa)^k), else W if it fires against
+// thr(1-(1-kappa-mu)^k); a weakened one becomes I against thr(1-(1-nu)^k);
+// an infected one is removed after one step.  One draw per (node, replicate,
+// step), taken only where k >= 1; counts are exact per replicate here (the
+// model is off the hot path).  `wk` is the weakened plane.
+__device__ __forceinline__ uint32_t swir_table(const uint32_t *t, int32_t khat, uint32_t k)
+{
+    return t[k > (uint32_t)khat ? (uint32_t)khat : k];
+}
+
+template <int LC>
+__device__ __forceinline__ void swir_decide(const StepArgs &a, int G, int S, bool valid, int v,
+                                            int w, int64_t idx, uint64_t h, uint64_t r, uint64_t wk,
+                                            uint64_t sus, const uint64_t (&c)[LC], int s,
+                                            uint64_t share, bool &any)
+{
+    const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
+    uint64_t need = (sus | wk) & bs_nonzero<LC>(c) & share;
+    uint64_t toI = 0, toW = 0;
+    while (need) {
+        const int b = __builtin_ctzll(need);
+        const int gs = b - (int)((gbase + (uint64_t)b) & 3u);  // first bit of the block
+        const uint32_t blk = (uint32_t)((gbase + (uint64_t)b) >> 2);
+        const uint32_t nn = nibble_at(need, gs);
+        need &= ~nibble_to_word(0xFu, gs);
+        const U4 o = philox10((uint32_t)v, blk, a.step, kDomNodeStep << 24, a.key0, a.key1);
+        const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
+        const uint32_t ns = nibble_at(sus, gs);
+        uint32_t fi = 0, fw = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!((nn >> j) & 1u)) continue;
+            const uint32_t k = bs_get<LC>(c, gs + j);
+            if ((ns >> j) & 1u) {
+                if (fires(ou[j], swir_table(a.tinf, a.khat, k)))
+                    fi |= 1u << j;
+                else if (fires(ou[j], swir_table(a.tsiw, a.khat_siw, k)))
+                    fw |= 1u << j;
+            } else if (fires(ou[j], swir_table(a.twi, a.khat_wi, k))) {
+                fi |= 1u << j;
+            }
+        }
+        toI |= nibble_to_word(fi, gs);
+        toW |= nibble_to_word(fw, gs);
+    }
+    toI = or_reduce_lanes(toI, G, S);
+    toW = or_reduce_lanes(toW, G, S);
+    if (!valid || s != 0) return;
+    a.next[idx] = toI;               // infected for one step
+    a.lat[idx] = (wk & ~toI) | toW;
+    a.aux[idx] = r | h;              // removed after it
+    any |= toI != 0;
+}
+
 template <int LC>
 __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool valid, int v,
                                            int w, int64_t idx, uint64_t h, uint64_t r, uint64_t e,
@@ -301,6 +357,10 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
                                            uint64_t share, const uint32_t *tl, int tl_n,
                                            const uint32_t *tcode, bool &any)
 {
+    if (a.model == kSWIR) {
+        swir_decide<LC>(a, G, S, valid, v, w, idx, h, r, e, sus, c, s, share, any);
+        return;
+    }
     const uint64_t gbase = a.goff + 64ull * (uint64_t)w;
     const bool draw_rec = a.trec != 0u && a.trec != kAlways;
     const bool draw_lat = a.talpha != 0u && a.talpha != kAlways;
@@ -452,12 +512,14 @@ __device__ __forceinline__ void epi_row_word(const StepArgs &a, int G, int S, bo
     const uint64_t r = valid ? a.aux[idx] : 0ull;
     const uint64_t e = (valid && a.lat) ? a.lat[idx] : 0ull;
     const uint64_t sus = valid ? (~(h | r | e) & tail_mask(w, a.B) & lm) : 0ull;
+    // replicates whose decision needs the count (SWIR: weakened ones too)
+    const uint64_t counted = a.model == kSWIR ? (sus | (e & lm)) : sus;
     uint64_t c[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) c[l] = 0;
     if (S == 1 && G >= 16 && a.fast32)
-        count_edges_bcast<L>(a, G, valid, e0, e1, w, sus != 0ull, c);
-    else if (sus)
+        count_edges_bcast<L>(a, G, valid, e0, e1, w, counted != 0ull, c);
+    else if (counted)
         count_edges<L>(a, e0 + s, e1, S, w, c);
     bs_reduce_lanes<L>(c, G, S);
     if (seg >= 0) {
@@ -926,8 +988,9 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
                 const uint64_t r = valid ? a.aux[idx] : 0ull;
                 const uint64_t e = (valid && a.lat) ? a.lat[idx] : 0ull;
                 const uint64_t sus = valid ? (~(h | r | e) & tail_mask(ww, a.B) & lm) : 0ull;
+                const uint64_t counted = a.model == kSWIR ? (sus | (e & lm)) : sus;
 #pragma unroll
-                for (int l = 0; l < LC; ++l) c[l] &= sus;
+                for (int l = 0; l < LC; ++l) c[l] &= counted;
                 epi_decide<LC>(a, G, S2, valid, v, ww, idx, h, r, e, sus, c, ss, share, nullptr, 0,
                                tcode, anyw);
             } else {

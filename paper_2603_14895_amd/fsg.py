@@ -17,10 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfsg.so")
 
 FSG_OK, FSG_EINVAL, FSG_ENOMEM, FSG_EDEVICE, FSG_EUNSUPPORTED, FSG_EWORKSPACE = 0, -1, -2, -3, -4, -5
-FSG_IC, FSG_SI, FSG_SIS, FSG_SIR, FSG_LT, FSG_SEIR, FSG_SEIS = 0, 1, 2, 3, 4, 5, 6
+FSG_IC, FSG_SI, FSG_SIS, FSG_SIR, FSG_LT, FSG_SEIR, FSG_SEIS, FSG_SWIR = 0, 1, 2, 3, 4, 5, 6, 7
 FSG_IC_UNIFORM, FSG_IC_WEIGHTED_CASCADE, FSG_IC_PER_EDGE = 0, 1, 2
 MODELS = {"ic": FSG_IC, "si": FSG_SI, "sis": FSG_SIS, "sir": FSG_SIR, "lt": FSG_LT,
-          "seir": FSG_SEIR, "seis": FSG_SEIS}
+          "seir": FSG_SEIR, "seis": FSG_SEIS, "swir": FSG_SWIR}
 IC_PROBS = {"uniform": FSG_IC_UNIFORM, "weighted_cascade": FSG_IC_WEIGHTED_CASCADE,
             "per_edge": FSG_IC_PER_EDGE}
 
@@ -154,6 +154,9 @@ _SIGS = {
                                              ctypes.POINTER(_SZ)]),
     "fsg_hk": (ctypes.c_int, [_VP, ctypes.c_float, _I64, _I64, _VP, ctypes.POINTER(fsg_schedule),
                               _VP, _SZ, ctypes.c_float, _VP, ctypes.POINTER(fsg_run_info), _VP]),
+    "fsg_whk": (ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, _I64, _I64, _VP,
+                               ctypes.POINTER(fsg_schedule), _VP, _SZ, ctypes.c_float, _VP,
+                               ctypes.POINTER(fsg_run_info), _VP]),
     "fsg_autotune_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _I64, _I32,
                                                    ctypes.POINTER(_SZ)]),
     "fsg_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(fsg_params), _VP, _I64, _I64, _U64, _I32,
@@ -507,11 +510,22 @@ def fsg_hk(g, eps, max_steps, B, dev_h, sched, dev_ws, ws_bytes, act, dev_counts
     return info
 
 
+def fsg_whk(g, eps, mu, max_steps, B, dev_h, sched, dev_ws, ws_bytes, act, dev_counts,
+            stream=None) -> fsg_run_info:
+    info = fsg_run_info()
+    _check(lib().fsg_whk(g, ctypes.c_float(eps), ctypes.c_float(mu), int(max_steps), int(B),
+                         dev_h, ctypes.byref(sched) if sched else None, dev_ws, ws_bytes,
+                         ctypes.c_float(act), dev_counts, ctypes.byref(info),
+                         stream if stream is not None else _stream_ptr()))
+    return info
+
+
 def hk(graph: DeviceGraph, h0, eps: float, max_steps: int, *, act: float = 0.5,
-       want_counts: bool = True, schedule=None):
-    """Hegselmann-Krause from opinions h0 ([n, B] float32, any device; copied).
-    Returns (h [n, B] float32 cuda tensor, counts [B] int32 tensor of nodes with
-    opinion > act or None, fsg_run_info)."""
+       want_counts: bool = True, schedule=None, mu: float = 1.0):
+    """Hegselmann-Krause from opinions h0 ([n, B] float32, any device; copied);
+    with mu < 1 the weighted variant (fsg_whk).  Returns (h [n, B] float32 cuda
+    tensor, counts [B] int32 tensor of nodes with opinion > act or None,
+    fsg_run_info)."""
     import torch
     h = torch.as_tensor(h0, dtype=torch.float32).to(graph.device).contiguous().clone()
     assert h.dim() == 2 and h.shape[0] == graph.n
@@ -520,8 +534,8 @@ def hk(graph: DeviceGraph, h0, eps: float, max_steps: int, *, act: float = 0.5,
     nb = fsg_hk_workspace_size(graph.handle, B, sched)
     ws, addr = _ws(nb, graph.device)
     counts = torch.empty(B, dtype=torch.int32, device=graph.device) if want_counts else None
-    info = fsg_hk(graph.handle, float(eps), int(max_steps), B, h.data_ptr(), sched, addr, nb,
-                  float(act), counts.data_ptr() if counts is not None else None)
+    info = fsg_whk(graph.handle, float(eps), float(mu), int(max_steps), B, h.data_ptr(), sched,
+                   addr, nb, float(act), counts.data_ptr() if counts is not None else None)
     del ws
     return h, counts, info
 

@@ -48,6 +48,9 @@ def _mixed_jobs():
         ("ic", 1500, 10.0, 1500, 2, dict(p=0.1, max_steps=-1), None),
         ("sir", 1200, 10.0, 1300, 0, dict(beta=0.05, gamma=0.2, max_steps=40),
          dict(row_lanes=16, heavy_threshold=24)),
+        ("swir", 2000, 10.0, 500, 2, dict(beta=0.1, alpha=0.1, gamma=0.4, max_steps=-1), None),
+        ("swir", 1400, 16.0, 1090, 0, dict(beta=0.06, alpha=0.2, gamma=0.5, max_steps=-1),
+         dict(heavy_threshold=18)),
     ]
     jobs = []
     for i, (model, n, deg, B, off, prm, sched) in enumerate(specs):

@@ -166,3 +166,30 @@ def test_hk_full_size_first_step_sampled():
 def torch_equal(a, b):
     import torch
     return bool(torch.equal(a.view(torch.int32), b.view(torch.int32)))
+
+
+def _both_w(ptr, src, h0, eps, mu, K, act=0.5):
+    from paper_2603_14895_amd import fsg
+    g = fsg.DeviceGraph(ptr, src)
+    h, cnt, info = fsg.hk(g, h0, eps, K, act=act, mu=mu)
+    got = (h.cpu().numpy(), cnt.cpu().numpy(), int(info.steps_run), int(info.absorbed))
+    g.close()
+    rh, rsteps, rconv = oracle.whk(ptr, src, h0, eps, mu, K, nthreads=NTHREADS)
+    want = (rh, (rh > np.float32(act)).sum(axis=0).astype(np.int32), rsteps, rconv)
+    return got, want
+
+
+@pytest.mark.parametrize("mu", [0.2, 0.65, 0.0, 1.0])
+@pytest.mark.parametrize("B", [1, 64, 130])
+def test_whk_matches_oracle(mu, B):
+    """Weighted HK (each node moves the fraction mu towards its HK mean; the
+    parameters (0.32, 0.2) the paper compares): opinions bit for bit on a
+    graph with hub rows (block-per-row path) and ordinary rows, mu = 0 (no
+    move) and mu = 1 (plain HK) included."""
+    ptr, src = _hub_graph(91)
+    h0 = W.uniform_opinions(ptr.size - 1, B, 92 + B)
+    got, want = _both_w(ptr, src, h0, 0.32, mu, 15)
+    _same(got, want, f"whk mu={mu} B={B}")
+    if mu == 1.0:
+        hk_got, _ = _both(ptr, src, h0, 0.32, 15)
+        assert np.array_equal(hk_got[0].view(np.uint32), got[0].view(np.uint32))

@@ -427,3 +427,17 @@ def test_sir_generator_call_count(B, sched):
         want += int((need_s | need_i).reshape(n, B // 4, 4).any(axis=2).sum())
     log(f"[parity] generator calls B={B}: gpu {int(info.philox_calls)}, rule {want}")
     assert int(info.philox_calls) == want
+
+
+@pytest.mark.parametrize("B,offset,K", [(256, 0, -1), (100, 2, -1), (1100, 1, -1), (64, 0, 3)])
+@pytest.mark.parametrize("sched", [None, dict(row_lanes=4, heavy_threshold=25, steps_per_sync=2)])
+def test_swir(B, offset, K, sched):
+    """SWIR (susceptible, weakened, infected, removed): every state, count
+    and step count equal the oracle's, with word absorption (1100
+    replicates), unaligned generator blocks (offsets 1, 2), edge-split rows,
+    heavy-row segments and a step cap."""
+    gr = W.chung_lu(3000, 12.0, 2.5, 1901)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 15, 1902)
+    _both(gnp, "swir", seeds, B, 0x5A1E + B, f"swir-{sched}", beta=0.08, alpha=0.12, gamma=0.3,
+          max_steps=K, replicate_offset=offset, schedule=sched)

@@ -31,6 +31,7 @@ CASES = [
     ("lt", 1500, 10.0, 1100, 0, dict(max_steps=-1), dict(steps_per_sync=2)),
     ("sir", 1200, 12.0, 1300, 3, dict(beta=0.05, gamma=0.2, max_steps=60),
      dict(steps_per_sync=1, heavy_threshold=20)),
+    ("swir", 2000, 12.0, 700, 1, dict(beta=0.08, alpha=0.15, gamma=0.4, max_steps=-1), None),
 ]
 
 
