@@ -258,6 +258,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the schedule(s) first with the library autotuner")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
+    ap.add_argument("--tune-trials", type=int, default=32,
+                    help="c3: whole-batch trials of the batch autotuner")
     ap.add_argument("--tune-steps", type=int, default=0,
                     help="autotuner window: runs of K and 2K steps per candidate; 0 = the "
                          "workload's step cap (whole runs), or 64 for runs to absorption")
@@ -599,21 +601,15 @@ def bench_batch(args):
     tot_nnz = sum(h[1].size for h in host)
     log(f"[bench] c3: {len(jobs)} jobs, {tot_nnz} arcs, B mean "
         f"{np.mean([j['B'] for j in jobs]):.0f} (built in {time.perf_counter() - t0:.1f}s)")
-    if args.autotune:
-        t1 = time.perf_counter()
-        for ji, j in enumerate(jobs):
-            prm = {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in j}
-            best, bms, dms = fsg.autotune(j["graph"], j["model"], j["seeds"], j["B"], j["rng_key"],
-                                          tune_steps=args.tune_steps or
-                                          (prm["max_steps"] if prm.get("max_steps", -1) > 0 else 64),
-                                          batch_only=True,
-                                          cache_path=args.tune_cache,
-                                          **prm)
-            j["schedule"] = best
-            log(f"[bench] tuned job {ji + 1}/{len(jobs)} ({j['model']}): {bms:.4f} ms/step "
-                f"vs default {dms:.4f}")
-        log(f"[bench] autotuned {len(jobs)} jobs in {time.perf_counter() - t1:.1f}s")
     batch = fsg.Batch(jobs, steps_per_sync=16, want_states=not args.no_states)
+    tune = None
+    if args.autotune:
+        # the batch is tuned as a batch: whole runs scored by device time
+        t1 = time.perf_counter()
+        tune = batch.autotune(max_trials=args.tune_trials)
+        log(f"[bench] batch autotune: {tune['default_ms']:.1f} -> {tune['best_ms']:.1f} ms device "
+            f"in {tune['trials']} trials ({time.perf_counter() - t1:.1f}s); steps_per_sync "
+            f"{tune['steps_per_sync']}, blocks per CU {tune['blocks_per_cu']}")
     log(f"[bench] batch workspace {batch.ws_bytes / 2**30:.2f} GiB")
     for i in range(args.warmup):
         infos, ms = batch.run()
@@ -646,6 +642,8 @@ def bench_batch(args):
         "config": {"workload": "c3_mixed_batch_64_jobs", "jobs": len(jobs), "nnz_total": int(tot_nnz),
                    "B": [j["B"] for j in jobs], "steps_run": steps_run,
                    "autotuned": bool(args.autotune), "parallelism": "single GPU"},
+        "autotune": ({k: tune[k] for k in ("default_ms", "best_ms", "trials", "steps_per_sync",
+                                           "blocks_per_cu")} if tune else None),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic("c3"),

@@ -393,7 +393,34 @@ int fsg_batch_plan(const fsg_job *jobs, int32_t n_jobs, int32_t steps_per_sync, 
 int fsg_batch_run(fsg_plan *plan, void *dev_ws, size_t ws_bytes, fsg_run_info *infos,
                   double *total_ms, void *stream);
 
+/* Persistent blocks per compute unit of the batched step and merge kernels
+ * (default 4; at most 32).  Errors: FSG_EINVAL. */
+int fsg_batch_set_launch(fsg_plan *plan, int32_t blocks_per_cu);
+
 int fsg_plan_destroy(fsg_plan *plan);
+
+/* ---- Batch autotuner (the batch-size methodology of Tables tab:IC_batchsize
+ * and tab:SIR_batchsize applied to a whole batch): every trial plans and
+ * runs the whole batch and is scored by its device time (fsg_batch_run's
+ * total_ms), so a schedule that helps a job alone but costs the batch is
+ * not taken.  Coordinate descent from the jobs' own schedules over:
+ * steps_per_sync (16, 8, 32, 64), blocks per compute unit (4, 2, 8), then
+ * for each model class present (IC, SI family, LT) the lanes per row
+ * (default, 16, 32, 64), tile size (default, 2048, 8192 arcs) and heavy-row
+ * cut (default, 512, 2048), each applied to every job of the class.  The
+ * default is run twice (the first is a warm-up); at most max_trials trials.
+ * The jobs' outputs are written by every trial (the same bits each time).
+ * tuned: host [n_jobs] receives the jobs with their tuned schedules;
+ * steps_per_sync / blocks_per_cu: the tuned launch (give them to
+ * fsg_batch_plan / fsg_batch_set_launch); best_ms / default_ms: device ms
+ * of one batch run; trials_run: trials run.  dev_ws: at least
+ * fsg_batch_autotune_workspace_size bytes.  Synchronous.
+ * Errors: as fsg_batch_plan and fsg_batch_run. */
+int fsg_batch_autotune_workspace_size(const fsg_job *jobs, int32_t n_jobs, size_t *bytes);
+int fsg_batch_autotune(const fsg_job *jobs, int32_t n_jobs, int32_t max_trials, void *dev_ws,
+                       size_t ws_bytes, fsg_job *tuned, int32_t *steps_per_sync,
+                       int32_t *blocks_per_cu, double *best_ms, double *default_ms,
+                       int32_t *trials_run, void *stream);
 
 /* ---- Autotuner: times short runs of candidate schedules (from the seeds,
  * runs of tune_steps and 2 tune_steps steps with HIP events around each on

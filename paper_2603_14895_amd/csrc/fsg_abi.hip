@@ -1389,6 +1389,7 @@ struct fsg_plan {
     std::vector<size_t> job_off;  // workspace offset of each job
     size_t ctl_off = 0, total = 0;
     int sync = 16;
+    int blocks_per_cu = 4;  // persistent blocks of the batched kernels per compute unit
 };
 
 namespace {
@@ -1452,6 +1453,15 @@ int fsg_batch_plan(const fsg_job *jobs, int32_t n_jobs, int32_t steps_per_sync, 
     } catch (const std::bad_alloc &) {
         return fail(FSG_ENOMEM, "host allocation failed");
     }
+}
+
+int fsg_batch_set_launch(fsg_plan *plan, int32_t blocks_per_cu)
+{
+    if (!plan) return fail(FSG_EINVAL, "plan is NULL");
+    if (blocks_per_cu < 1 || blocks_per_cu > 32)
+        return fail(FSG_EINVAL, "blocks_per_cu must be in [1, 32]");
+    plan->blocks_per_cu = blocks_per_cu;
+    return FSG_OK;
 }
 
 int fsg_plan_destroy(fsg_plan *plan)
@@ -1530,7 +1540,8 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
         int dev = 0, ncu = 0;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        const int grid = std::max(1, std::min(4 * std::max(ncu, 1), item_off[(size_t)n]));
+        const int grid =
+            std::max(1, std::min(pl->blocks_per_cu * std::max(ncu, 1), item_off[(size_t)n]));
         const int cgrid = std::max(1, std::min(2 * std::max(ncu, 1), comb_off[(size_t)n]));
 
         // capture one chunk of steps in a graph on a private stream
@@ -1823,6 +1834,172 @@ int fsg_autotune(const fsg_graph *g, const fsg_params *prm, const int32_t *seeds
         if (best_ms) *best_ms = wms;
         if (default_ms) *default_ms = dms;
         cache_store(cache_path, key, win, wms);
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ batch autotuner ----
+// The batch is tuned as a batch: every trial plans and runs the whole batch
+// (all jobs to absorption or their caps) and is scored by its device time,
+// so a schedule that helps one job alone but costs the batch is not taken.
+namespace {
+
+struct BatchTrial {
+    std::vector<fsg_schedule> sched;  // per job
+    int sync = 16, blocks_per_cu = 4;
+};
+
+// Knob values tried per model class (0 keeps the library default).
+const int kTryLanes[] = {0, 16, 32, 64};
+const int kTryTile[] = {0, 2048, 8192};
+const int kTryHeavy[] = {0, 512, 2048};
+const int kTrySync[] = {16, 8, 32, 64};
+const int kTryBlocks[] = {4, 2, 8};
+
+int model_class(int model)
+{
+    const int k = model_kind(model);
+    return k == kKindIC ? 0 : (k == kKindLT ? 2 : 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fsg_batch_autotune_workspace_size(const fsg_job *jobs, int32_t n_jobs, size_t *bytes)
+{
+    try {
+        if (!jobs || !bytes || n_jobs < 1 || n_jobs > kMaxBatchJobs)
+            return fail(FSG_EINVAL, "bad arguments");
+        size_t best = 0;
+        std::vector<fsg_job> js(jobs, jobs + n_jobs);
+        for (int tile : kTryTile)
+            for (int heavy : kTryHeavy) {
+                for (auto &j : js) {
+                    j.sched.tile_edges = tile;
+                    j.sched.heavy_threshold = heavy;
+                }
+                fsg_plan *pl = nullptr;
+                size_t need = 0;
+                int rc = fsg_batch_plan(js.data(), n_jobs, 64, &pl, &need);
+                if (rc) return rc;
+                fsg_plan_destroy(pl);
+                best = std::max(best, need);
+            }
+        *bytes = best;
+        return FSG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FSG_ENOMEM, "host allocation failed");
+    }
+}
+
+int fsg_batch_autotune(const fsg_job *jobs, int32_t n_jobs, int32_t max_trials, void *dev_ws,
+                       size_t ws_bytes, fsg_job *tuned, int32_t *steps_per_sync,
+                       int32_t *blocks_per_cu, double *best_ms, double *default_ms,
+                       int32_t *trials_run, void *stream)
+{
+    try {
+        if (!jobs || !tuned || !steps_per_sync || !blocks_per_cu || n_jobs < 1 ||
+            n_jobs > kMaxBatchJobs)
+            return fail(FSG_EINVAL, "bad arguments");
+        if (max_trials < 1) return fail(FSG_EINVAL, "max_trials must be >= 1");
+        const std::vector<fsg_job> base(jobs, jobs + n_jobs);
+        int trials = 0;
+        auto run = [&](const BatchTrial &t, double *ms) -> int {
+            std::vector<fsg_job> js = base;
+            for (int i = 0; i < n_jobs; ++i) js[(size_t)i].sched = t.sched[(size_t)i];
+            fsg_plan *pl = nullptr;
+            size_t need = 0;
+            int rc = fsg_batch_plan(js.data(), n_jobs, t.sync, &pl, &need);
+            if (rc) return rc;
+            std::unique_ptr<fsg_plan, int (*)(fsg_plan *)> guard(pl, fsg_plan_destroy);
+            if (need > ws_bytes) return fail(FSG_EWORKSPACE, "batch autotune workspace too small");
+            pl->blocks_per_cu = t.blocks_per_cu;
+            double total = 0;
+            rc = fsg_batch_run(pl, dev_ws, ws_bytes, nullptr, &total, stream);
+            if (rc) return rc;
+            *ms = total;
+            ++trials;
+            return FSG_OK;
+        };
+        BatchTrial cur;
+        for (const auto &j : base) {
+            fsg_schedule s = j.sched;
+            s.time_kernels = 0;
+            cur.sched.push_back(s);
+        }
+        double cms = 0;
+        int rc = run(cur, &cms);  // warm-up
+        if (rc) return rc;
+        rc = run(cur, &cms);
+        if (rc) return rc;
+        const double dms = cms;
+        auto consider = [&](const BatchTrial &t) -> int {
+            if (trials >= max_trials) return FSG_OK;
+            double ms = 0;
+            int r = run(t, &ms);
+            if (r) return r;
+            if (ms < cms) {
+                cms = ms;
+                cur = t;
+            }
+            return FSG_OK;
+        };
+        // launch-level knobs, then per model class lanes, tiles, heavy cut
+        for (int v : kTrySync) {
+            if (v == cur.sync) continue;
+            BatchTrial t = cur;
+            t.sync = v;
+            rc = consider(t);
+            if (rc) return rc;
+        }
+        for (int v : kTryBlocks) {
+            if (v == cur.blocks_per_cu) continue;
+            BatchTrial t = cur;
+            t.blocks_per_cu = v;
+            rc = consider(t);
+            if (rc) return rc;
+        }
+        for (int cls = 0; cls < 3; ++cls) {
+            bool present = false;
+            for (const auto &j : base) present |= model_class(j.prm.model) == cls;
+            if (!present) continue;
+            for (int knob = 0; knob < 3; ++knob) {
+                const int *vals = knob == 0 ? kTryLanes : (knob == 1 ? kTryTile : kTryHeavy);
+                const int nv = knob == 0 ? 4 : 3;
+                const BatchTrial start = cur;
+                for (int k = 0; k < nv; ++k) {
+                    BatchTrial t = start;
+                    bool changed = false;
+                    for (int i = 0; i < n_jobs; ++i) {
+                        if (model_class(base[(size_t)i].prm.model) != cls) continue;
+                        fsg_schedule &sc = t.sched[(size_t)i];
+                        int32_t &field = knob == 0 ? sc.row_lanes
+                                                   : (knob == 1 ? sc.tile_edges : sc.heavy_threshold);
+                        if (field != vals[k]) {
+                            field = vals[k];
+                            changed = true;
+                        }
+                    }
+                    if (!changed) continue;
+                    rc = consider(t);
+                    if (rc) return rc;
+                }
+            }
+        }
+        for (int i = 0; i < n_jobs; ++i) {
+            tuned[i] = base[(size_t)i];
+            tuned[i].sched = cur.sched[(size_t)i];
+        }
+        *steps_per_sync = cur.sync;
+        *blocks_per_cu = cur.blocks_per_cu;
+        if (best_ms) *best_ms = cms;
+        if (default_ms) *default_ms = dms;
+        if (trials_run) *trials_run = trials;
         return FSG_OK;
     } catch (const std::bad_alloc &) {
         return fail(FSG_ENOMEM, "host allocation failed");

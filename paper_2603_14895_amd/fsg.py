@@ -130,6 +130,14 @@ _SIGS = {
     "fsg_batch_run": (ctypes.c_int, [_VP, _VP, _SZ, ctypes.POINTER(fsg_run_info),
                                      ctypes.POINTER(ctypes.c_double), _VP]),
     "fsg_plan_destroy": (ctypes.c_int, [_VP]),
+    "fsg_batch_set_launch": (ctypes.c_int, [_VP, _I32]),
+    "fsg_batch_autotune_workspace_size": (ctypes.c_int, [ctypes.POINTER(fsg_job), _I32,
+                                                         ctypes.POINTER(_SZ)]),
+    "fsg_batch_autotune": (ctypes.c_int, [ctypes.POINTER(fsg_job), _I32, _I32, _VP, _SZ,
+                                          ctypes.POINTER(fsg_job), ctypes.POINTER(_I32),
+                                          ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32),
+                                          _VP]),
     "fsg_gnn_create": (ctypes.c_int, [_I32, _I32, _U64, ctypes.POINTER(_VP)]),
     "fsg_gnn_destroy": (ctypes.c_int, [_VP]),
     "fsg_gnn_param_count": (ctypes.c_int, [_VP, ctypes.POINTER(_I64)]),
@@ -566,7 +574,8 @@ class Batch:
 
     PARAM_KEYS = ("p", "ic_prob", "edge_p", "beta", "gamma", "max_steps", "alpha")
 
-    def __init__(self, jobs, steps_per_sync=16, want_states=True, want_counts=True):
+    def __init__(self, jobs, steps_per_sync=16, want_states=True, want_counts=True,
+                 blocks_per_cu=None):
         import torch
         self.n = len(jobs)
         self._keep = []
@@ -596,8 +605,41 @@ class Batch:
             a.final_states = st.data_ptr() if st is not None else None
             a.infected_counts = ct.data_ptr() if ct is not None else None
         self._arr = arr
-        self.plan, self.ws_bytes = fsg_batch_plan(arr, self.n, int(steps_per_sync))
-        self._ws, self.ws_addr = _ws(self.ws_bytes, jobs[0]["graph"].device)
+        self.device = jobs[0]["graph"].device
+        self.steps_per_sync = int(steps_per_sync)
+        self.blocks_per_cu = None
+        self.plan, self.ws_bytes = fsg_batch_plan(arr, self.n, self.steps_per_sync)
+        if blocks_per_cu is not None:
+            self.set_launch(blocks_per_cu)
+        self._ws, self.ws_addr = _ws(self.ws_bytes, self.device)
+
+    def set_launch(self, blocks_per_cu: int):
+        _check(lib().fsg_batch_set_launch(self.plan, int(blocks_per_cu)))
+        self.blocks_per_cu = int(blocks_per_cu)
+
+    def autotune(self, max_trials: int = 32, stream=None):
+        """fsg_batch_autotune over this batch; then re-plans with the tuned
+        schedules and launch.  Returns a dict of the search's outcome."""
+        nb = _SZ(0)
+        _check(lib().fsg_batch_autotune_workspace_size(self._arr, self.n, ctypes.byref(nb)))
+        ws, addr = _ws(nb.value, self.device)
+        tuned = (fsg_job * self.n)()
+        sync, bpc, trials = _I32(0), _I32(0), _I32(0)
+        bms, dms = ctypes.c_double(0), ctypes.c_double(0)
+        _check(lib().fsg_batch_autotune(self._arr, self.n, int(max_trials), addr, nb.value, tuned,
+                                        ctypes.byref(sync), ctypes.byref(bpc), ctypes.byref(bms),
+                                        ctypes.byref(dms), ctypes.byref(trials), _stream_ptr(stream)))
+        del ws
+        for i in range(self.n):
+            self._arr[i].sched = tuned[i].sched
+        fsg_plan_destroy(self.plan)
+        self.steps_per_sync = sync.value
+        self.plan, self.ws_bytes = fsg_batch_plan(self._arr, self.n, self.steps_per_sync)
+        self.set_launch(bpc.value)
+        self._ws, self.ws_addr = _ws(self.ws_bytes, self.device)
+        return {"best_ms": bms.value, "default_ms": dms.value, "trials": trials.value,
+                "steps_per_sync": sync.value, "blocks_per_cu": bpc.value,
+                "schedules": [tuned[i].sched.as_dict() for i in range(self.n)]}
 
     def run(self, stream=None):
         """Returns (list of fsg_run_info, total device ms of the step chunks)."""

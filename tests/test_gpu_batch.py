@@ -119,6 +119,43 @@ def test_batch_mixed_workload_small():
     batch.close()
 
 
+def test_batch_autotune_tuned_batch_matches_oracle():
+    """The batch autotuner times whole batch runs over its search space and
+    never returns a configuration slower than the one it started from; the
+    batch re-planned with the tuned schedules and launch gives every job's
+    oracle bits (sampled replicates) and its solo run's bits."""
+    from paper_2603_14895_amd import fsg
+    specs = W.config_c3_jobs(n_jobs=7, n_hi=2e4, b_hi=600, seed_hi=80, seed=4242)
+    dgs, bj, grs = [], [], []
+    for sp in specs:
+        gr = W.build_c3_graph(sp)
+        grs.append(gr)
+        dg = fsg.DeviceGraph(*gr.numpy())
+        dgs.append(dg)
+        seeds = W.uniform_seeds(gr.n, sp["n_seeds"], sp["seed_seed"])
+        prm = {k: sp[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in sp}
+        bj.append(dict(graph=dg, model=sp["model"], B=sp["B"], seeds=seeds, rng_key=sp["key"], **prm))
+    batch = fsg.Batch(bj, steps_per_sync=16)
+    res = batch.autotune(max_trials=14)
+    log(f"[batch] autotune: {res['default_ms']:.2f} -> {res['best_ms']:.2f} ms in {res['trials']} "
+        f"trials, sync {res['steps_per_sync']}, blocks/CU {res['blocks_per_cu']}")
+    assert res["best_ms"] <= res["default_ms"] + 1e-9 and 1 <= res["trials"] <= 14
+    infos, _ = batch.run()
+    for i, (gr, j) in enumerate(zip(grs, bj)):
+        gnp = gr.numpy()
+        prm = {k: j[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in j}
+        st = batch.states[i].cpu().numpy()
+        got = (st, batch.counts[i].cpu().numpy().astype(np.uint32), int(infos[i].steps_run),
+               int(infos[i].absorbed))
+        assert_same(got, gpu_run(gnp, j["model"], j["seeds"], j["B"], j["rng_key"], **prm),
+                    f"tuned batch job {i} vs solo")
+        r0 = j["B"] // 2
+        rs, _, _, _ = oracle_run(gnp, j["model"], j["seeds"], 2, j["rng_key"], replicate_offset=r0,
+                                 **prm)
+        assert (st[:, r0:r0 + 2] == rs).all(), i
+    batch.close()
+
+
 def test_autotune_and_cache():
     from paper_2603_14895_amd import fsg
     gr = W.chung_lu(20000, 20.0, 2.5, 901)
