@@ -271,21 +271,36 @@ __device__ __forceinline__ void count_edges_bcast(const StepArgs &a, int G, bool
 // 1 - (1-beta)^k; the k-indexed thresholds come from the host.  One draw per
 // (node, replicate, step) decides whichever transition the node's state
 // allows (infection if S, recovery if I).
-// Draw classes of the aligned decision path: code = b0 | b1 << 1 | b2 << 2
-// per replicate, with 1, 2, 3 = that many infected in-neighbours, 4 = four
-// or more (threshold from the exact count), 5 = infected with a recovery
-// draw, 6 = latent (SEIR / SEIS) with an E -> I draw.  The table maps a code
-// to its threshold (0 for codes that never fire here).
-constexpr int kCodeTable = 8;
+// Draw classes of the aligned decision path: a 5-bit code per replicate from
+// five bit planes, code = k for k = 1 .. 15 infected in-neighbours, 16 for
+// sixteen or more (threshold from the exact count), 17 = infected with a
+// recovery draw, 18 = latent (SEIR / SEIS) with an E -> I draw.  The table
+// maps a code to its threshold (0 for codes that never fire here); its last
+// entry is not a threshold but the mask of the codes 1 .. 15 whose threshold
+// always fires (those replicates take no draw).
+constexpr int kCodeTable = 32;
+constexpr int kCodeAlwaysMask = kCodeTable - 1;
 
 __device__ __forceinline__ uint32_t code_threshold(const StepArgs &a, int code)
 {
-    switch (code) {
-    case 1: case 2: case 3: return a.tinf[code < a.khat ? code : a.khat];
-    case 5: return a.trec;
-    case 6: return a.talpha;
-    default: return 0u;
+    if (code >= 1 && code <= 15) return a.tinf[code < a.khat ? code : a.khat];
+    if (code == 17) return a.trec;
+    if (code == 18) return a.talpha;
+    if (code == kCodeAlwaysMask) {
+        uint32_t m = 0;
+        for (int k = 1; k <= 15; ++k)
+            if (a.tinf[k < a.khat ? k : a.khat] == kAlways) m |= 1u << k;
+        return m;
     }
+    return 0u;
+}
+
+// Bit plane K of a bit-sliced counter (zero past its last plane).
+template <int K, int L>
+__device__ __forceinline__ uint64_t plane(const uint64_t (&c)[L])
+{
+    if constexpr (K < L) return c[K];
+    else return 0ull;
 }
 
 // Spread the four bits of a nibble to bit 0 of the four bytes of a word.
@@ -370,25 +385,27 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
     if (tcode != nullptr && (a.goff & 3u) == 0u) {
         // generator blocks are nibbles of the word: one draw per block with
         // any replicate that needs one, the class of each replicate read from
-        // three bit planes, its threshold from the code table
-        uint64_t rest = 0;
+        // five bit planes, its threshold from the code table
+        uint64_t rest = 0;  // sixteen or more
 #pragma unroll
-        for (int l = 2; l < LC; ++l) rest |= c[l];
-        const uint64_t c0 = c[0], c1 = LC > 1 ? c[LC > 1 ? 1 : 0] : 0ull;
-        const uint64_t ninf = sus & share & (c0 | c1 | rest);  // k >= 1
-        const uint64_t m1 = c0 & ~c1 & ~rest, m2 = ~c0 & c1 & ~rest, m3 = c0 & c1 & ~rest;
-        const uint32_t t1 = tcode[1], t2 = tcode[2], t3 = tcode[3];
+        for (int l = 4; l < LC; ++l) rest |= c[l];
+        const uint64_t c0 = plane<0>(c), c1 = plane<1>(c), c2 = plane<2>(c), c3 = plane<3>(c);
+        const uint64_t ninf = sus & share & (c0 | c1 | c2 | c3 | rest);  // k >= 1
         uint64_t always = 0;  // classes whose threshold always fires
-        if (t1 == kAlways) always |= m1;
-        if (t2 == kAlways) always |= m2;
-        if (t3 == kAlways) always |= m3;
-        always &= ninf;
+        const uint32_t acodes = tcode[kCodeAlwaysMask];
+        if (acodes) {
+            for (int k = 1; k <= 15; ++k)
+                if ((acodes >> k) & 1u)
+                    always |= ~rest & ((k & 1) ? c0 : ~c0) & ((k & 2) ? c1 : ~c1) &
+                              ((k & 4) ? c2 : ~c2) & ((k & 8) ? c3 : ~c3);
+            always &= ninf;
+        }
         const uint64_t ndraw = ninf & ~always;
         const uint64_t nrec = draw_rec ? (h & share) : 0ull;
         const uint64_t nlat = draw_lat ? (e & share) : 0ull;
-        const uint64_t B0 = (ndraw & c0 & ~rest) | nrec;
-        const uint64_t B1 = (ndraw & c1 & ~rest) | nlat;
-        const uint64_t B2 = (ndraw & rest) | nrec | nlat;
+        const uint64_t low = ndraw & ~rest;
+        const uint64_t P0 = (low & c0) | nrec, P1 = (low & c1) | nlat, P2 = low & c2,
+                       P3 = low & c3, P4 = (ndraw & rest) | nrec | nlat;
         uint64_t need = ndraw | nrec | nlat;
         uint64_t fire = 0;
         const uint32_t blk0 = (uint32_t)(gbase >> 2);
@@ -398,13 +415,16 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
             need &= ~(0xFull << gs);
             const bool hi = gs >= 32;
             const uint32_t sh = (uint32_t)gs & 31u;
-            const uint32_t n0 = ((hi ? (uint32_t)(B0 >> 32) : (uint32_t)B0) >> sh) & 0xFu;
-            const uint32_t n1 = ((hi ? (uint32_t)(B1 >> 32) : (uint32_t)B1) >> sh) & 0xFu;
-            const uint32_t n2 = ((hi ? (uint32_t)(B2 >> 32) : (uint32_t)B2) >> sh) & 0xFu;
+            auto nib = [&](uint64_t P) -> uint32_t {
+                return ((hi ? (uint32_t)(P >> 32) : (uint32_t)P) >> sh) & 0xFu;
+            };
+            const uint32_t n0 = nib(P0), n1 = nib(P1), n2 = nib(P2), n3 = nib(P3), n4 = nib(P4);
             // byte j of T = 4 * code of replicate j (a byte offset into the table)
             const uint32_t T = spread4(n0, 0x810204u, 0x04040404u) |
                                (spread4(n1, 0x204081u, 0x01010101u) << 3) |
-                               (spread4(n2, 0x204081u, 0x01010101u) << 4);
+                               (spread4(n2, 0x204081u, 0x01010101u) << 4) |
+                               (spread4(n3, 0x204081u, 0x01010101u) << 5) |
+                               (spread4(n4, 0x204081u, 0x01010101u) << 6);
             const char *tb = reinterpret_cast<const char *>(tcode);
             const uint32_t q0 = *reinterpret_cast<const uint32_t *>(tb + (T & 0xFFu));
             const uint32_t q1 = *reinterpret_cast<const uint32_t *>(tb + ((T >> 8) & 0xFFu));
@@ -417,7 +437,7 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
             f = f + f + ((o.z < q2) ? 1u : 0u);
             f = f + f + ((o.y < q1) ? 1u : 0u);
             f = f + f + ((o.x < q0) ? 1u : 0u);
-            const uint32_t nb = n2 & ~n0 & ~n1;  // code 4: four or more infected neighbours
+            const uint32_t nb = n4 & ~n0 & ~n1;  // code 16: sixteen or more infected neighbours
             if (nb) {
                 const uint32_t ou[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll

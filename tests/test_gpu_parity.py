@@ -242,6 +242,30 @@ def test_edge_cases():
           gamma=1.0, max_steps=20)
 
 
+def test_si_family_draw_classes_and_saturated_thresholds():
+    """Every draw class of the SI-family decision: 1 to 15 infected
+    in-neighbours (read from the code table), 16 or more (exact count),
+    recovery and latent draws, and infection thresholds that saturate to
+    'always' for large counts (beta = 0.95: k >= 13 rounds 1 - (1-beta)^k to
+    1 in FP64, so those replicates take no draw).  Dense graphs and 10%
+    initial infected put many replicates in every class at the first steps."""
+    assert 1.0 - (1.0 - 0.95) ** 13 == 1.0 and 1.0 - (1.0 - 0.95) ** 12 < 1.0
+    assert 1.0 - (1.0 - 0.5) ** 53 < 1.0 and 1.0 - (1.0 - 0.5) ** 54 == 1.0
+    for gi, (n, deg) in enumerate(((1500, 40.0), (400, 120.0))):
+        gr = W.chung_lu(n, deg, 2.5, 300 + gi)
+        gnp = gr.numpy()
+        seeds = W.uniform_seeds(n, n // 10, 310 + gi)
+        for beta in (0.95, 0.5, 0.05):
+            for model in ("sir", "sis", "si", "seir", "seis"):
+                for B in (128, 100):
+                    _both(gnp, model, seeds, B, 320 + B, f"classes-{model}-b{beta}",
+                          beta=beta, gamma=0.3, alpha=0.4, max_steps=6)
+            # replicate offsets not a multiple of four take the general path
+            for off in (0, 2, 64):
+                _both(gnp, "sir", seeds, 70, 330, f"classes-off{off}", beta=beta, gamma=0.3,
+                      max_steps=6, replicate_offset=off)
+
+
 def test_replicate_split_and_repeat_invariance():
     """Splitting a batch with replicate_offset and repeating a run change
     nothing (counter-based draws keyed by the global replicate index)."""
