@@ -212,6 +212,12 @@ hipError_t launch_batch_step(const BatchCtl &c, int grid, hipStream_t s);
 hipError_t launch_batch_combine(const BatchCtl &c, int grid, hipStream_t s);
 hipError_t launch_batch_advance(const BatchCtl &c, hipStream_t s);
 constexpr int kBatchBlock = 256;  // block size of the batched kernels
+// Waves per SIMD the batched step kernel is compiled for.  One kernel holds every
+// (model, counter width) case, so unbounded it takes the register count of the
+// widest case plus what the case switch adds (229 VGPRs: two waves per SIMD);
+// three waves keep the LT and SI cases up to 12 counter planes unspilled,
+// four spill them.
+constexpr int kBatchWavesPerSimd = 3;
 
 // Heavy rows merged per wave by the combine kernels: each row takes G word
 // lanes times min(64 / G, 16) segment lanes.

@@ -1460,7 +1460,8 @@ __device__ __forceinline__ bool job_live(const BatchCtl &c, const StepArgs &a, i
     return t <= (uint32_t)c.max_step[j] && a.flags[(t - 1) % (uint32_t)a.ring] != 0u;
 }
 
-__global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchCtl c)
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(kBatchWavesPerSimd)))
+k_batch_step(BatchCtl c)
 {
     __shared__ int32_t s_off[kMaxBatchJobs + 1];
     __shared__ int s_item;
