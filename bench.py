@@ -701,6 +701,7 @@ def bench_surrogate(args):
     # held-out graphs: the gate is calibrated on the first 50 queries of each,
     # the rest are the test queries
     cal_s, cal_u, cal_r, cal_k, tests = [], [], [], [], []
+    raw_err, calib_err = [], []  # every held-out query (calibration and test halves)
     ref_ms = 0.0
     for gi in range(2):
         gr = Wl.chung_lu(n, 20.0, 2.5, Wl.BASE_SEED + 90 + gi, device="cuda")
@@ -712,6 +713,8 @@ def bench_surrogate(args):
         ref_ms += ms
         mean, unc = S.uncertainty(ens.predict_spreads(g, S.masks_of(qs, n), qb))
         cal = S.apply_calibration(mean, qb, qk, coef)
+        raw_err += list(np.abs(mean - ref) / ref)
+        calib_err += list(np.abs(cal - ref) / ref)
         cal_s += list(cal[:50]); cal_u += list(unc[:50]); cal_r += list(ref[:50])
         cal_k += list(qk[:50])
         tests.append((g, qs[50:], qb[50:], ref[50:]))
@@ -771,6 +774,11 @@ def bench_surrogate(args):
                    "ensemble": 4, "tau": tau, "min_seeds": gate["min_seeds"],
                    "calibration": [round(float(c), 6) for c in coef], "parallelism": "single GPU"},
         "surrogate": {"accepted": len(acc_err), "fallback": n_fb, "acceptance": len(acc_err) / 100.0,
+                      "heldout_raw_rel_err_median": float(np.median(raw_err)),
+                      "heldout_raw_rel_err_p90": float(np.quantile(raw_err, 0.9)),
+                      "heldout_calibrated_rel_err_median": float(np.median(calib_err)),
+                      "heldout_calibrated_rel_err_p90": float(np.quantile(calib_err, 0.9)),
+                      "heldout_queries": len(raw_err),
                       "accepted_rel_err_mean": e_sur,
                       "accepted_rel_err_max": float(np.max(acc_err)) if acc_err else None,
                       "fallback_rel_err_mean": float(np.mean(fb_err)) if fb_err else None,

@@ -5,7 +5,9 @@ surrogate (message = neighbour state, aggregation = mean over in-neighbours,
 update = ReLU of a linear map of [own state | aggregate]; the structure of the
 paper's Eq. ms / Eq. agg / Eq. updata with learned functions):
 
-    x_v  = [seed_v, 20 beta, log1p(indeg_v) / 8, 1, 0 x 12]
+    x_v  = [seed_v, 20 beta, log1p(indeg_v) / 8, 1, 20 beta log1p(indeg_v) / 8,
+            log1p(k) / 8, log1p(D) / 16, 0 x 9]
+           (k = number of seeds, D = sum of the seeds' in-degrees)
     h1_v = ReLU(W1^T [x_v  | mean_{u in N-(v)} x_u ] + b1)
     h2_v = ReLU(W2^T [h1_v | mean h1_u] + b2)
     h3_v = ReLU(W3^T [h2_v | mean h2_u] + b3)
@@ -81,11 +83,19 @@ def mean_agg_T(G, ptr, src):
 def features(mask, beta, ptr):
     n = len(ptr) - 1
     indeg = np.diff(np.asarray(ptr)).astype(np.float64)
+    seed = np.asarray(mask) != 0
+    k = float(np.count_nonzero(seed))
+    D = float(indeg[seed].sum())
+    xb = 20.0 * float(np.float32(beta))
+    xd = np.log1p(indeg) * 0.125
     X = np.zeros((n, F0))
-    X[:, 0] = mask
-    X[:, 1] = 20.0 * np.float32(beta)
-    X[:, 2] = np.log1p(indeg) * 0.125
+    X[:, 0] = seed
+    X[:, 1] = xb
+    X[:, 2] = xd
     X[:, 3] = 1.0
+    X[:, 4] = xb * xd
+    X[:, 5] = np.log1p(k) * 0.125
+    X[:, 6] = np.log1p(D) * 0.0625
     return X
 
 

@@ -6,7 +6,12 @@
 // kernels and Adam.
 //
 // Network (per node v, per seed set s; R = n_sets * n rows):
-//   x_v  = [seed_v, 20 beta, log1p(indeg_v) / 8, 1, 0 ... 0]      (16 wide)
+//   x_v  = [seed_v, 20 beta, log1p(indeg_v) / 8, 1,
+//           20 beta log1p(indeg_v) / 8, log1p(k_s) / 8, log1p(D_s) / 16, 0 ... 0]
+//                                                                   (16 wide)
+//   with k_s the number of seeds of the set and D_s the sum of their
+//   in-degrees (query-wide terms: a node further than three hops from every
+//   seed sees the seed set only through them)
 //   h1_v = ReLU(W1 [x_v | mean_{u in N-(v)} x_u] + b1)            (32 -> 64)
 //   h2_v = ReLU(W2 [h1_v | mean h1_u] + b2)                        (128 -> 64)
 //   h3_v = ReLU(W3 [h2_v | mean h2_u] + b3)                        (128 -> 64)
@@ -73,9 +78,48 @@ __host__ __device__ inline float from_bf16(uint16_t h)
 
 // ------------------------------------------------------------- kernels ----
 
+// Query-wide terms of seed set s (one block per set): qs[2s] = number of
+// seeds, qs[2s+1] = sum of their in-degrees.  Integer sums, so the result
+// does not depend on the order of the additions.
+constexpr int kQueryThreads = 1024;
+
+__global__ void __launch_bounds__(kQueryThreads) k_query_stats(const uint8_t *mask,
+                                                               const int32_t *ptr, int32_t n,
+                                                               unsigned long long *qs)
+{
+    const int s = blockIdx.x;
+    const uint8_t *m = mask + (int64_t)s * n;
+    unsigned long long k = 0, d = 0;
+    for (int v = threadIdx.x; v < n; v += blockDim.x)
+        if (m[v]) {
+            ++k;
+            d += (unsigned long long)(ptr[v + 1] - ptr[v]);
+        }
+    for (int off = 32; off >= 1; off >>= 1) {
+        k += __shfl_xor(k, off, 64);
+        d += __shfl_xor(d, off, 64);
+    }
+    __shared__ unsigned long long sk[kQueryThreads / 64], sd[kQueryThreads / 64];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sk[wave] = k;
+        sd[wave] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tk = 0, td = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            tk += sk[w];
+            td += sd[w];
+        }
+        qs[2 * s] = tk;
+        qs[2 * s + 1] = td;
+    }
+}
+
 // Input features of every (seed set, node) row into X1[:, 0:16].
 __global__ void k_input(uint16_t *X1, const uint8_t *mask, const float *beta, const int32_t *ptr,
-                        int32_t n, int32_t n_sets)
+                        const unsigned long long *qs, int32_t n, int32_t n_sets)
 {
     const int64_t R = (int64_t)n * n_sets;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
@@ -83,12 +127,16 @@ __global__ void k_input(uint16_t *X1, const uint8_t *mask, const float *beta, co
         const int s = (int)(r / n);
         const int v = (int)(r - (int64_t)s * n);
         const int d = ptr[v + 1] - ptr[v];
+        const double xb = 20.0 * (double)beta[s], xd = log1p((double)d) * 0.125;
         uint16_t *x = X1 + r * kK1;
         x[0] = to_bf16(mask[r] ? 1.f : 0.f);
-        x[1] = to_bf16(20.f * beta[s]);
-        x[2] = to_bf16((float)(log1p((double)d) * 0.125));
+        x[1] = to_bf16((float)xb);
+        x[2] = to_bf16((float)xd);
         x[3] = to_bf16(1.f);
-        for (int f = 4; f < kF0; ++f) x[f] = 0;
+        x[4] = to_bf16((float)(xb * xd));
+        x[5] = to_bf16((float)(log1p((double)qs[2 * s]) * 0.125));
+        x[6] = to_bf16((float)(log1p((double)qs[2 * s + 1]) * 0.0625));
+        for (int f = 7; f < kF0; ++f) x[f] = 0;
     }
 }
 
@@ -717,8 +765,8 @@ unsigned grid_of(int64_t work, int block, int cap = 65536)
 
 // Workspace of one forward/backward pass over R rows.
 struct GnnWs {
-    size_t X1, X2, X3, H3, prob, dH, dH2, dZ, dX, part, pwo, pbo, ploss, beta, sums, mask, seeds,
-        total;
+    size_t X1, X2, X3, H3, prob, dH, dH2, dZ, dX, part, pwo, pbo, ploss, beta, qstat, sums, mask,
+        seeds, total;
 };
 
 GnnWs gnn_layout(int64_t n, int32_t n_sets)
@@ -746,6 +794,7 @@ GnnWs gnn_layout(int64_t n, int32_t n_sets)
     w.pbo = take((size_t)kPartBlocks * 4);
     w.ploss = take((size_t)kPartBlocks * 4);
     w.beta = take((size_t)n_sets * 4);
+    w.qstat = take((size_t)n_sets * 16);
     w.sums = take((size_t)std::max<int32_t>(n_sets, kMaxMembers) * 4);
     w.mask = take((size_t)n);
     w.seeds = take((size_t)n * 4);
@@ -808,8 +857,13 @@ int forward_all(const fsg_gnn *gn, const GraphView &G, int32_t n_sets, const uin
              *X3 = (uint16_t *)(base + w.X3), *H3 = (uint16_t *)(base + w.H3);
     const float *P = gn->p();
     const uint16_t *Wb = gn->wb();
+    unsigned long long *qs = (unsigned long long *)(base + w.qstat);
+    hipLaunchKernelGGL(k_query_stats, dim3((unsigned)n_sets), dim3(kQueryThreads), 0, st, mask,
+                       G.ptr, (int32_t)G.n, qs);
+    GNN_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_input, dim3(grid_of(R, 256)), dim3(256), 0, st, X1, mask,
-                       (const float *)(base + w.beta), G.ptr, (int32_t)G.n, n_sets);
+                       (const float *)(base + w.beta), G.ptr, (const unsigned long long *)qs,
+                       (int32_t)G.n, n_sets);
     GNN_TRY(hipGetLastError());
     int rc = mean_agg(X1, kK1, kF0, G, n_sets, st);
     if (rc) return rc;

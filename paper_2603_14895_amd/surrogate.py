@@ -147,28 +147,39 @@ def apply_calibration(pred_mean, beta, k, coef):
 
 
 def calibrate_gate(spread, unc, ref, k, max_rel_err: float, min_seeds_floor: int = 5,
-                   quantile: float = 0.9, quantile_frac: float = 0.25, tau_slack: float = 2.0,
-                   min_queries: int = 10):
+                   quantile: float = 0.9, quantile_frac: float = 0.25, tau_slack: float = 1.0,
+                   min_queries: int = 10, safety: float = 2.0):
     """Acceptance gate from held-out calibration queries (calibrated spread,
     member uncertainty, Monte Carlo reference, seed count).
 
-    min_seeds is the smallest seed count k0 >= min_seeds_floor such that the
-    calibration queries with at least k0 seeds (at least min_queries of them)
-    have their `quantile` error below quantile_frac * max_rel_err and their
-    largest error below max_rel_err; tau is tau_slack times the largest
-    member uncertainty among them (a guard against queries unlike the
-    calibration set).  No such k0: everything falls back.  Returns
-    dict(tau, min_seeds)."""
+    A query is accepted iff its seed count is at least min_seeds and its
+    member uncertainty at most tau.  Over the pairs (k0 >= min_seeds_floor,
+    t) drawn from the calibration queries' own values, the gate takes the one
+    that accepts the most calibration queries (at least min_queries) while
+    their `quantile` error stays below quantile_frac * max_rel_err and their
+    largest error below max_rel_err / safety (a few dozen calibration queries
+    understate the largest error of the queries to come); then min_seeds and
+    tau / tau_slack are the smallest seed count and the largest uncertainty
+    among the queries it accepts.  Near the epidemic threshold the spread is
+    sensitive to beta and the members disagree, which the uncertainty bound
+    catches at any seed count.  No such pair: everything falls back.
+    Returns dict(tau, min_seeds)."""
     spread, unc, ref, k = (np.asarray(a, np.float64) for a in (spread, unc, ref, k))
     err = np.abs(spread - ref) / np.maximum(ref, 1e-12)
+    best = None
     for k0 in sorted(set(int(x) for x in k if x >= min_seeds_floor)):
-        sel = k >= k0
-        if sel.sum() < min_queries:
-            break
-        if np.quantile(err[sel], quantile) <= quantile_frac * max_rel_err and \
-                err[sel].max() <= max_rel_err:
-            return dict(tau=float(tau_slack * unc[sel].max()), min_seeds=int(k0))
-    return dict(tau=-1.0, min_seeds=int(k.max()) + 1)
+        for t in sorted(set(float(x) for x in unc)):
+            sel = (k >= k0) & (unc <= t)
+            cnt = int(sel.sum())
+            if cnt < min_queries or (best is not None and cnt <= best[0]):
+                continue
+            if np.quantile(err[sel], quantile) <= quantile_frac * max_rel_err and \
+                    err[sel].max() <= max_rel_err / safety:
+                best = (cnt, sel)
+    if best is None:
+        return dict(tau=-1.0, min_seeds=int(k.max()) + 1)
+    sel = best[1]
+    return dict(tau=float(tau_slack * unc[sel].max()), min_seeds=int(k[sel].min()))
 
 
 def calibrate_tau(mean, unc, ref, max_rel_err: float):

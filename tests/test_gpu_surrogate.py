@@ -78,6 +78,8 @@ def test_surrogate_gain_over_plain_mc():
             assert abs(sp - cal_sp[i]) <= 1e-4 * cal_sp[i]
             acc_err.append(abs(sp - ref[i]) / ref[i])
             acc.append(int(i))
+            log(f"[surrogate] accepted query {int(i)}: seeds {qk[i]}, beta {qb[i]:.4f}, "
+                f"uncertainty {u:.4f}, error {acc_err[-1]:.4f}")
             t_sur.append(dt)
     log(f"[surrogate] accepted {len(acc_err)}/{len(test)}, fallback {n_fb}; "
         f"accepted err mean {np.mean(acc_err) if acc_err else -1:.4f} "

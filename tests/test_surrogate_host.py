@@ -35,7 +35,7 @@ def test_gate_picks_smallest_reliable_seed_count():
     unc = np.where(k < 5, 0.05, 0.01)
     g = S.calibrate_gate(spread, unc, ref, k, 0.02, min_seeds_floor=1)
     assert g["min_seeds"] == 5
-    assert abs(g["tau"] - 2.0 * 0.01) < 1e-12
+    assert abs(g["tau"] - 0.01) < 1e-12
     # the floor is respected
     g = S.calibrate_gate(spread, unc, ref, k, 0.02, min_seeds_floor=7)
     assert g["min_seeds"] == 7
@@ -45,3 +45,24 @@ def test_gate_picks_smallest_reliable_seed_count():
     g = S.calibrate_gate(spread2, unc, ref, k, 0.02, min_seeds_floor=1)
     assert g["min_seeds"] > k.max()
     assert g["tau"] < 0
+    # the largest calibration error must stay below max_rel_err / safety
+    spread3 = spread.copy()
+    spread3[-1] = ref[-1] * 1.015
+    assert S.calibrate_gate(spread3, unc, ref, k, 0.02, min_seeds_floor=1,
+                            safety=1.0)["min_seeds"] == 5
+    assert S.calibrate_gate(spread3, unc, ref, k, 0.02, min_seeds_floor=1)["min_seeds"] > k.max()
+
+
+def test_gate_bounds_uncertainty_and_seed_count_together():
+    # near-threshold queries (large member disagreement, 3% error) at every
+    # seed count are excluded by the uncertainty bound, not by the seed floor
+    k = np.array(list(range(5, 45)) + [6, 15, 25, 35, 44])
+    ref = np.full(k.size, 1e4)
+    err = np.array([0.002] * 40 + [0.03] * 5)
+    unc = np.array([0.01] * 40 + [0.03] * 5)
+    g = S.calibrate_gate(ref * (1 + err), unc, ref, k, 0.02, min_seeds_floor=1)
+    assert g["min_seeds"] == 5
+    assert abs(g["tau"] - 0.01) < 1e-12
+    # no pair accepts min_queries queries: everything falls back
+    g = S.calibrate_gate(ref * (1 + err), unc, ref, k, 0.02, min_seeds_floor=1, min_queries=41)
+    assert g["tau"] < 0 and g["min_seeds"] > k.max()
