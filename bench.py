@@ -117,13 +117,19 @@ def algorithmic_bytes_per_step(model: str, n: int, nnz: int, B: int, edge_parall
     return 4.0 * nnz + 8.0 * W * nnz + 4.0 * (n + 1) + own * n
 
 
-def finalize_bytes(model: str, n: int, B: int, states: bool, bitmap: bool) -> float:
+def finalize_bytes(model: str, n: int, B: int, states: bool, bitmap: bool,
+                   ever_nodes=None) -> float:
     """Bytes the finalize kernel must move: per node the packed words it
     reads (the state-1 plane, except where a frontier bitmap marks it empty;
     the removed / ever-active plane for IC, SIR, SEIR; the latent plane for
     SEIR, SEIS), the uint8 states it writes ([n][B], if asked) and the uint32
-    count; plus one read of the n-bit frontier bitmap."""
+    count; plus one read of the n-bit frontier bitmap.  The frontier-driven
+    IC run (ever_nodes = the nodes some replicate activated) reads and clears
+    the ever-active word only of those nodes, and reads and clears the n-bit
+    bitmap that lists them."""
     W = (B + 63) // 64
+    if ever_nodes is not None:
+        return n * ((B if states else 0) + 4.0) + 3 * n / 8.0 + 16.0 * W * ever_nodes
     planes = (0 if bitmap else 1) + (1 if model in ("ic", "sir", "seir") else 0) + \
         (1 if model in ("seir", "seis") else 0)
     return n * (8.0 * W * planes + (B if states else 0) + 4.0) + (n / 8.0 if bitmap else 0.0)
@@ -337,6 +343,8 @@ def main():
                          **params_of(c))
     log(f"[bench] workspace {sim.ws_bytes / 2**30:.2f} GiB, schedule "
         f"{fsg.fsg_default_schedule(dg.handle, sim.prm, c['B']).as_dict()} overrides {sched}")
+    # runs after the first reuse the object's private workspace (each run
+    # still computes everything from the seeds)
     for i in range(args.warmup):
         info = sim.run(c["seeds"], c["rng_key"])
         log(f"[bench] warmup {i}: steps_run={info.steps_run} absorbed={info.absorbed}")
@@ -379,12 +387,20 @@ def main():
     log(f"[bench] device time per run: {json.dumps(kernels)}")
     # the roofline of the kernel with the most device time per run
     if fin_ms > kernel_ms:
-        abytes = finalize_bytes(c["model"], n, c["B"], not args.no_states, variant in (2, 3))
+        ever = int((counts > 0).sum()) if variant == 3 else None
+        abytes = finalize_bytes(c["model"], n, c["B"], not args.no_states, variant in (2, 3), ever)
         kname, avg_ms, nl = "k_finalize", fin_ms / args.steps, args.steps
     else:
         if variant == 3:
-            raise SystemExit("no byte model for the frontier-driven step as the dominant kernel")
-        abytes = algorithmic_bytes_per_step(c["model"], n, src.size, c["B"], variant == 2)
+            # per live arc: its (target, edge id) entry, the target's
+            # ever-active word and in-degree (24 bytes); the frontier nodes'
+            # own words and work items are left out
+            outdeg = torch.bincount(torch.from_numpy(src).to("cuda"), minlength=n)
+            live = frontier_arcs(dg, c, outdeg)
+            del outdeg
+            abytes = 24.0 * float(sum(live)) / max(1, launches // args.steps)
+        else:
+            abytes = algorithmic_bytes_per_step(c["model"], n, src.size, c["B"], variant == 2)
         kname, avg_ms, nl = step_kernel, avg_kernel_ms, launches
     achieved = abytes / (avg_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,

@@ -165,9 +165,24 @@ typedef struct {
  *                  count the generator calls of the SI / SIS / SIR / SEIR /
  *                  SEIS decisions (reported in fsg_run_info.philox_calls;
  *                  one wave-reduced atomic add per row pass, so it is for
- *                  measurement runs, not timed ones). */
+ *                  measurement runs, not timed ones).
+ *                  FSG_OPT_REUSE_WORKSPACE (fsg_simulate): the caller
+ *                  states that dev_ws was last written by a completed
+ *                  fsg_simulate call with the same graph, parameters, B and
+ *                  schedule, and not modified since.  A frontier-driven IC
+ *                  run (variant 3) that wrote outputs leaves its frontier
+ *                  planes, bitmaps and ever-active plane all zero (the
+ *                  finalize clears the ever-active words it reads, a last
+ *                  pass clears the two frontiers no step cleared) and
+ *                  records that with a tag in dev_ws; with this option the
+ *                  next such run clears those buffers only if the tag is not
+ *                  there (checked on the device, so a run that stopped on an
+ *                  error, or another layout in the same memory, still gets
+ *                  them cleared).  Other runs ignore the option; results are
+ *                  the same either way. */
 #define FSG_OPT_WIDE_OFFSETS 1
 #define FSG_OPT_COUNT_DRAWS 2
+#define FSG_OPT_REUSE_WORKSPACE 4
 typedef struct {
     int32_t row_lanes;
     int32_t block_threads;

@@ -334,6 +334,7 @@ struct Sched {
     bool push;   // frontier-driven IC: work queues, push over out-arcs or stream
     bool wide;   // 64-bit offsets in the row-group kernels even where 32-bit ones fit
     bool count;  // count the generator calls of the SI-family decisions
+    bool reuse;  // the caller vouches for the workspace (FSG_OPT_REUSE_WORKSPACE)
 };
 
 void default_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_schedule *o)
@@ -402,10 +403,11 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
     s->edge1 = u.kernel_variant >= 2;
     s->push = u.kernel_variant == 3;
     if (s->push) s->block = 512;
-    if (u.options & ~(FSG_OPT_WIDE_OFFSETS | FSG_OPT_COUNT_DRAWS))
+    if (u.options & ~(FSG_OPT_WIDE_OFFSETS | FSG_OPT_COUNT_DRAWS | FSG_OPT_REUSE_WORKSPACE))
         return fail(FSG_EINVAL, "unknown schedule option bits");
     s->wide = (u.options & FSG_OPT_WIDE_OFFSETS) != 0;
     s->count = (u.options & FSG_OPT_COUNT_DRAWS) != 0;
+    s->reuse = (u.options & FSG_OPT_REUSE_WORKSPACE) != 0;
     return FSG_OK;
 }
 
@@ -413,7 +415,7 @@ struct Layout {
     size_t planes[4];
     int n_planes;
     size_t flags, wflags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
-        seeds, bm[3], sum[3], need, stamp, queue[4], qctl, draws, total;
+        seeds, bm[3], sum[3], ever, need, stamp, queue[4], qctl, draws, tag, total;
     int sum_shift, sum_words;
     int64_t W, plane_words, n_tinf, n_seed_stage;
     int L;
@@ -504,6 +506,8 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
             off = align256(off + (size_t)L->sum_words * 4);
         }
     }
+    L->ever = off;  // frontier-driven IC: bit per node ever in a frontier
+    if (s.push) off = align256(off + (size_t)((g->n + 31) / 32) * 4);
     L->draws = off;  // generator-call counter (counting runs)
     off = align256(off + 8);
     if (s.push) {  // four queues of 16-byte items; counters: uint32 [4], uint64 [4]
@@ -514,6 +518,8 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
         L->qctl = off;
         off = align256(off + 64);
     }
+    L->tag = off;  // frontier-driven IC: which layout last left its buffers clear
+    if (s.push) off = align256(off + 8);
     L->total = off;
     return FSG_OK;
 }
@@ -537,6 +543,31 @@ int validate_run(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int6
     return FSG_OK;
 }
 
+// Tag a frontier-driven IC run writes into its workspace once it has left
+// its planes, bitmaps and summaries clear: a hash of the layout, the graph,
+// the parameters and the workspace address, never 0 (the value a run in
+// progress leaves there).
+uint64_t clean_tag(const fsg_graph *g, const fsg_params *prm, int64_t B, const struct Layout &L,
+                   const char *base)
+{
+    uint64_t h = 0x6A09E667F3BCC908ull;
+    auto mix = [&](uint64_t x) {
+        h ^= x + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 31;
+    };
+    mix((uint64_t)(uintptr_t)base);
+    mix((uint64_t)g->n);
+    mix((uint64_t)g->nnz);
+    mix((uint64_t)B);
+    mix((uint64_t)prm->model);
+    mix((uint64_t)L.total);
+    mix((uint64_t)L.planes[0]);
+    mix((uint64_t)L.bm[0]);
+    mix((uint64_t)L.tag);
+    return h ? h : 1ull;
+}
+
 // One job on the device: its planes, tables and launch arguments.
 struct Job {
     StepArgs a;
@@ -553,6 +584,9 @@ struct Job {
     uint32_t *sum[3] = {nullptr, nullptr, nullptr};
     uint4 *queue[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<uint32_t> tinf_h, edge_t_h;  // host tables the set-up uploads
+    uint32_t *ever = nullptr;                // frontier-driven IC: ever-in-a-frontier bitmap
+    uint64_t *tag = nullptr;                 // frontier-driven IC: clean-buffers tag
+    uint64_t tag_value = 0;                  // the tag this job's layout writes
     // frontier plane (state 1) and its bitmap after step t: the planes
     // alternate, or rotate over three in the frontier-driven IC path
     static int mod3(int64_t t) { return (int)(((t % 3) + 3) % 3); }
@@ -627,9 +661,28 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     HIP_TRY(up(L.tinf, tinf.data(), tinf.size() * 4));
     HIP_TRY(up(L.edge_t, edge_t.data(), edge_t.size() * 4));
 
-    // the planes lie back to back (256-byte aligned): one zeroing launch
-    HIP_TRY(launch_zero(base + L.planes[0],
-                        L.planes[L.n_planes - 1] + (size_t)L.plane_words * 8 - L.planes[0], st));
+    // the planes lie back to back (256-byte aligned): one zeroing launch.
+    // A frontier-driven IC run clears what it wrote before it ends; with
+    // FSG_OPT_REUSE_WORKSPACE the planes, bitmaps and summaries are cleared
+    // only if the tag of this layout is not in the workspace.
+    const size_t plane_bytes = L.planes[L.n_planes - 1] + (size_t)L.plane_words * 8 - L.planes[0];
+    if (s.push) {
+        jb->tag = (uint64_t *)(base + L.tag);
+        jb->ever = (uint32_t *)(base + L.ever);
+        jb->tag_value = clean_tag(g, prm, B, L, base);
+        const size_t bm_bytes = align256(L.ever + (size_t)((g->n + 31) / 32) * 4) - L.bm[0];
+        if (s.reuse) {
+            HIP_TRY(launch_zero_unless(base + L.planes[0], align256(plane_bytes), jb->tag,
+                                       jb->tag_value, st));
+            HIP_TRY(launch_zero_unless(base + L.bm[0], bm_bytes, jb->tag, jb->tag_value, st));
+        } else {
+            HIP_TRY(launch_zero(base + L.planes[0], plane_bytes, st));
+            HIP_TRY(launch_zero(base + L.bm[0], bm_bytes, st));
+        }
+        HIP_TRY(launch_fill64(jb->tag, 1, 0ull, st));  // dirty until the run has cleared up
+    } else {
+        HIP_TRY(launch_zero(base + L.planes[0], plane_bytes, st));
+    }
     HIP_TRY(launch_fill32(flags, ring, 0u, st));
     uint32_t *wflags = (L.W > 16 && L.W <= 64) ? (uint32_t *)(base + L.wflags) : nullptr;
     if (wflags) {  // every word is live before step 1 (slot 0); the others clear
@@ -640,6 +693,7 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
         for (int i = 0; i < (s.push ? 3 : 2); ++i) {
             jb->bm[i] = (uint32_t *)(base + L.bm[i]);
             jb->sum[i] = (uint32_t *)(base + L.sum[i]);
+            if (s.push) continue;  // cleared above with the planes
             HIP_TRY(launch_fill32(jb->bm[i], (g->n + 31) / 32, 0u, st));
             HIP_TRY(launch_fill32(jb->sum[i], L.sum_words, 0u, st));
         }
@@ -655,6 +709,7 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     StepArgs sq;  // seeds join the frontier of step 0 (queue 0)
     memset(&sq, 0, sizeof(sq));
     if (s.push) {
+        sq.ever = jb->ever;
         sq.bm_next = jb->bm[0];
         sq.sum_next = jb->sum[0];
         sq.sum_shift = L.sum_shift;
@@ -739,6 +794,7 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
         HIP_TRY(launch_fill64((uint64_t *)a.draws, 1, 0ull, st));
     }
     if (s.push) {
+        a.ever = jb->ever;
         a.optr = g->d_optr;
         a.oarc = g->d_oarc;
         a.qcnt = qcnt;
@@ -758,7 +814,7 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
 
 // Packed planes of the step `steps_run` -> uint8 states and counts.
 int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32_t *counts,
-                 hipStream_t st, double *ms_out = nullptr)
+                 hipStream_t st, double *ms_out = nullptr, bool scrub = false)
 {
     if (!final_states && !counts) return FSG_OK;
     FinArgs f;
@@ -776,6 +832,10 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
     f.states = final_states;
     f.counts = counts;
     f.bm = jb.front_bm(steps_run);
+    if (jb.s.push) {  // the ever-active plane is nonzero only where the bitmap says so
+        f.two_bm = jb.ever;
+        f.scrub = (scrub && f.W == 1) ? 1 : 0;
+    }
     EventPool ev;
     if (ms_out) {
         HIP_TRY(ev.init(2));
@@ -789,6 +849,26 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
         HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
         *ms_out = ms;
     }
+    return FSG_OK;
+}
+
+// End of a frontier-driven IC run whose finalize cleared the ever-active
+// plane: the frontiers of the last two steps leave their buffers (every
+// earlier one was cleared by the step two after it), then the tag records
+// that the run left its buffers clear.
+int scrub_job(Job &jb, int64_t steps_run, hipStream_t st)
+{
+    StepArgs a = jb.a;
+    for (int64_t t = steps_run + 1; t <= steps_run + 2; ++t) {
+        a.qi_clr = (int32_t)((t + 2) % 4);
+        a.q_clr = jb.queue[a.qi_clr];
+        a.f_clr = jb.front(t - 2);
+        a.bm_clr = jb.front_bm(t - 2);
+        a.sum_clr = jb.front_sum(t - 2);
+        HIP_TRY(launch_ic_scrub(a, st));
+    }
+    HIP_TRY(launch_fill64(jb.tag, 1, jb.tag_value, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return FSG_OK;
 }
 
@@ -1217,9 +1297,14 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         if (rc) return rc;
         rc = run_steps(ss, ss.jb.K, nullptr, (hipStream_t)stream);
         if (rc) return rc;
+        const bool scrub = ss.jb.s.push && (final_states || infected_counts);
         rc = finalize_job(ss.jb, ss.steps_run, final_states, infected_counts, (hipStream_t)stream,
-                          ss.jb.s.timed ? &ss.finalize_ms : nullptr);
+                          ss.jb.s.timed ? &ss.finalize_ms : nullptr, scrub);
         if (rc) return rc;
+        if (scrub) {
+            rc = scrub_job(ss.jb, ss.steps_run, (hipStream_t)stream);
+            if (rc) return rc;
+        }
         rc = read_draws(ss, (hipStream_t)stream);
         if (rc) return rc;
         if (info) fill_info(ss, info);

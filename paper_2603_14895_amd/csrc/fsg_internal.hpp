@@ -130,6 +130,9 @@ struct StepArgs {
     int32_t qi_in, qi_out, qi_clr, qi_rst;
     uint64_t *f_clr;
     uint32_t *bm_clr, *sum_clr;
+    // bit per node set when the node first joins a frontier (any replicate):
+    // the nodes whose ever-active word can be nonzero
+    uint32_t *ever;
     // step t pushes over the out-arcs of the frontier of t-1 when they are at
     // most this many, else it streams the sources of every arc
     unsigned long long push_limit;
@@ -147,7 +150,12 @@ struct FinArgs {
     int64_t B;
     int32_t model;
     const uint64_t *one;  // state-1 plane (F, h, active)
-    const uint64_t *two;  // state-2 plane (A for IC, r for SIR and SEIR) or null
+    uint64_t *two;        // state-2 plane (A for IC, r for SIR and SEIR) or null
+    // when set (one word per node), `two` is read only for nodes whose bit is
+    // set and is zero elsewhere; with `scrub` the words read and the bitmap
+    // are cleared after reading (the run leaves that plane all zero)
+    uint32_t *two_bm;
+    int32_t scrub;
     const uint64_t *three;  // latent plane (SEIR / SEIS) or null
     const uint32_t *bm;   // when set, `one` is valid only for nodes whose bit is set
     uint8_t *states;      // [n][B] or null
@@ -183,6 +191,10 @@ struct BatchCtl {
 // launchers (fsg_kernels.hip); return the hipError_t of the launch
 hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);  // p 256-byte aligned
+// the same unless *tag == expect when the kernel runs (the region is then
+// known to be zero already)
+hipError_t launch_zero_unless(void *p, size_t bytes, const uint64_t *tag, uint64_t expect,
+                              hipStream_t s);
 hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_stamp_seeds(uint32_t *stamp, const int32_t *seeds, int64_t ns, hipStream_t s);
 hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s,
@@ -193,6 +205,9 @@ hipError_t launch_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t
                        hipStream_t s);
 hipError_t launch_ic_stream(const StepArgs &a, int grid, int block, hipStream_t s);
 hipError_t launch_ic_front(const StepArgs &a, int grid, int block, hipStream_t s);
+// the clear duty of k_ic_front alone (the queue of a.qi_clr leaves f_clr,
+// bm_clr, sum_clr), whatever the absorption flags say
+hipError_t launch_ic_scrub(const StepArgs &a, hipStream_t s);
 hipError_t launch_seed_queue(const StepArgs &a, const int32_t *seeds, int64_t ns, hipStream_t s);
 hipError_t launch_out_count(const int32_t *src, int64_t nnz, int32_t *cnt, hipStream_t s);
 hipError_t launch_out_fill(const int32_t *src, const int32_t *dst, int64_t nnz, int32_t *cursor,

@@ -1096,6 +1096,7 @@ __device__ __forceinline__ void join_frontier(const StepArgs &a, int v)
     if (old & bit) return;
     const int i = v >> a.sum_shift;
     atomicOr(&a.sum_next[i >> 5], 1u << (i & 31));
+    if (a.ever) atomicOr(&a.ever[v >> 5], bit);
     const int o0 = a.optr[v], o1 = a.optr[v + 1];
     const int deg = o1 - o0;
     const uint32_t nch = deg > kOutChunk ? (uint32_t)((deg + kOutChunk - 1) / kOutChunk) : 1u;
@@ -1114,6 +1115,7 @@ __device__ __forceinline__ bool claim_frontier(const StepArgs &a, int v)
     if (old & bit) return false;
     const int i = v >> a.sum_shift;
     atomicOr(&a.sum_next[i >> 5], 1u << (i & 31));
+    if (a.ever) atomicOr(&a.ever[v >> 5], bit);
     return true;
 }
 
@@ -1284,6 +1286,21 @@ __device__ __forceinline__ void ic_push_pass(const StepArgs &a, bool &any)
     }
 }
 
+// The nodes of the queue a.qi_clr leave their frontier plane and bitmap, and
+// the summary is cleared; thread `r` of `nthr`.
+__device__ __forceinline__ void ic_clear_pass(const StepArgs &a, int64_t r, int64_t nthr)
+{
+    const int64_t nclr = a.qcnt[a.qi_clr];
+    for (int64_t i = r; i < nclr; i += nthr) {
+        const uint4 it = a.q_clr[i];
+        if (it.y == 0u) {
+            a.f_clr[it.x] = 0ull;
+            a.bm_clr[it.x >> 5] = 0u;  // every set bit of this bitmap is such a node
+        }
+    }
+    for (int64_t i = r; i < a.sum_words; i += nthr) a.sum_clr[i] = 0u;
+}
+
 // One step of the frontier-driven IC path (see StepArgs): first the nodes of
 // the frontier of t-2 leave their plane, bitmap and summary (buffers step t
 // does not touch) and the counters of the queue of t+1 are reset; then the
@@ -1302,15 +1319,7 @@ __global__ void __launch_bounds__(512) k_ic_front(StepArgs a)
     const bool push = a.qarcs[a.qi_in] <= a.push_limit;
     const int64_t skip = push ? (int64_t)a.qcnt[a.qi_in] * 64 : 0;
     const int64_t rtid = (tid - skip + nthr) % nthr;
-    const int64_t nclr = a.qcnt[a.qi_clr];
-    for (int64_t i = rtid; i < nclr; i += nthr) {
-        const uint4 it = a.q_clr[i];
-        if (it.y == 0u) {
-            a.f_clr[it.x] = 0ull;
-            a.bm_clr[it.x >> 5] = 0u;  // every set bit of this bitmap is such a node
-        }
-    }
-    for (int64_t i = rtid; i < a.sum_words; i += nthr) a.sum_clr[i] = 0u;
+    ic_clear_pass(a, rtid, nthr);
     if (tid == 0) {
         a.qcnt[a.qi_rst] = 0u;
         a.qarcs[a.qi_rst] = 0ull;
@@ -1324,6 +1333,14 @@ __global__ void __launch_bounds__(512) k_ic_front(StepArgs a)
         ic_stream_pass<true>(a, s_sum, any);
     }
     if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
+}
+
+// End of a frontier-driven run: the last two frontiers, which no later step
+// clears, leave their buffers (one launch per frontier).
+__global__ void __launch_bounds__(256) k_ic_scrub(StepArgs a)
+{
+    ic_clear_pass(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                  (int64_t)gridDim.x * blockDim.x);
 }
 
 // Seeds of a frontier-driven run: joined to the frontier of step 0 (bitmap,
@@ -1581,6 +1598,15 @@ __global__ void k_zero16(u32x4 *p, int64_t count16)
         __builtin_nontemporal_store(z, p + i);
 }
 
+__global__ void k_zero16_unless(u32x4 *p, int64_t count16, const uint64_t *tag, uint64_t expect)
+{
+    if (*tag == expect) return;
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count16;
+         i += (int64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(z, p + i);
+}
+
 __global__ void k_fill64(uint64_t *p, int64_t count, uint64_t value)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -1660,9 +1686,11 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
             const int64_t idx = v * f.W + w;
             const uint64_t tail = tail_mask(w, f.B);
             const bool live = !f.bm || ((f.bm[v >> 5] >> (v & 31)) & 1u);
+            const bool live2 = f.two && (!f.two_bm || ((f.two_bm[v >> 5] >> (v & 31)) & 1u));
             const uint64_t one = live ? (f.one[idx] & tail) : 0ull;
-            const uint64_t two = f.two ? (f.two[idx] & tail) : 0ull;
+            const uint64_t two = live2 ? (f.two[idx] & tail) : 0ull;
             const uint64_t three = f.three ? (f.three[idx] & tail) : 0ull;
+            if (f.scrub && live2) f.two[idx] = 0ull;
             cnt += (uint32_t)__popcll(f.model == kSIS ? one : (one | two | three));
             if (!f.states) continue;
             // state codes: with a latent plane E 1, I 2, R 3 (the planes are
@@ -1701,6 +1729,9 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
         }
         for (int off = 1; off < G; off <<= 1) cnt += __shfl_xor(cnt, off, 64);
         if (act && gw == 0 && f.counts) f.counts[v] = cnt;
+        // scrubbing runs have one word per node (G = 1), so the wave's 64
+        // nodes cover whole bitmap words, all read above
+        if (f.scrub && act && (v & 31) == 0) f.two_bm[v >> 5] = 0u;
     }
 }
 
@@ -1731,9 +1762,11 @@ __device__ __forceinline__ DenseWords dense_words(const FinArgs &f, int64_t rb, 
     if (d.act) {
         const int64_t idx = v * f.W + (lane & (f.G - 1));
         const bool live = !f.bm || ((f.bm[v >> 5] >> (v & 31)) & 1u);
+        const bool live2 = f.two && (!f.two_bm || ((f.two_bm[v >> 5] >> (v & 31)) & 1u));
         d.one = live ? f.one[idx] : 0ull;
-        d.two = f.two ? f.two[idx] : 0ull;
+        d.two = live2 ? f.two[idx] : 0ull;
         d.three = f.three ? f.three[idx] : 0ull;
+        if (f.scrub && live2) f.two[idx] = 0ull;
     }
     return d;
 }
@@ -1787,6 +1820,11 @@ __global__ void __launch_bounds__(256) k_finalize_dense(FinArgs f)
         const bool two_blocks = rb + stride < f.n;
         const DenseWords d1 = two_blocks ? dense_words(f, rb + stride, lane)
                                          : DenseWords{0ull, 0ull, 0ull, false};
+        if (f.scrub) {  // one word per node: a wave's 64 nodes are two whole bitmap words
+            const int64_t v = rb + lane;
+            if (d0.act && (v & 31) == 0) f.two_bm[v >> 5] = 0u;
+            if (d1.act && ((v + stride) & 31) == 0) f.two_bm[(v + stride) >> 5] = 0u;
+        }
         dense_out(f, rb, lane, d0);
         if (two_blocks) dense_out(f, rb + stride, lane, d1);
     }
@@ -1872,6 +1910,23 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
     }
     if (bytes % 16 >= 8) return launch_fill64((uint64_t *)((char *)p + 16 * n16), 1, 0ull, s);
     return hipSuccess;
+}
+
+hipError_t launch_zero_unless(void *p, size_t bytes, const uint64_t *tag, uint64_t expect,
+                              hipStream_t s)
+{
+    // whole 16-byte words only: callers pass regions of 256-byte multiples
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero16_unless, dim3(grid_for(n16, 256)), dim3(256), 0, s, (u32x4 *)p, n16,
+                       tag, expect);
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_scrub(const StepArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ic_scrub, dim3(256), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s)

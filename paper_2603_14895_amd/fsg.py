@@ -57,6 +57,7 @@ class fsg_schedule(ctypes.Structure):
 
 OPT_WIDE_OFFSETS = 1  # FSG_OPT_WIDE_OFFSETS
 OPT_COUNT_DRAWS = 2   # FSG_OPT_COUNT_DRAWS
+OPT_REUSE_WORKSPACE = 4  # FSG_OPT_REUSE_WORKSPACE
 
 
 CALIB_TERMS = 9
@@ -405,15 +406,25 @@ class DeviceGraph:
 
 
 class Simulation:
-    """Workspace and outputs for repeated fsg_simulate calls on one graph."""
+    """Workspace and outputs for repeated fsg_simulate calls on one graph.
+
+    The workspace is private to the object and every call uses the same
+    graph, parameters, B and schedule, so after a completed run the next
+    ones pass FSG_OPT_REUSE_WORKSPACE (the library checks its own tag before
+    it leaves buffers uncleared); ``reuse_workspace=False`` turns that off."""
 
     def __init__(self, graph: DeviceGraph, model, B: int, schedule: Optional[dict] = None,
-                 want_states: bool = True, want_counts: bool = True, **params):
+                 want_states: bool = True, want_counts: bool = True,
+                 reuse_workspace: bool = True, **params):
         import torch
         self.graph = graph
         self.B = int(B)
         self.prm, self._keep = make_params(model, **params)
         self.sched = make_schedule(schedule)
+        self.reuse_workspace = bool(reuse_workspace)
+        self._reuse_sched = make_schedule(dict(schedule or {}))
+        self._reuse_sched.options |= OPT_REUSE_WORKSPACE
+        self._completed = False
         self.ws_bytes = fsg_sim_workspace_size(graph.handle, self.prm, self.B, self.sched)
         self._ws, self.ws_addr = _ws(self.ws_bytes, graph.device)
         self.states = (torch.empty((graph.n, self.B), dtype=torch.uint8, device=graph.device)
@@ -423,12 +434,16 @@ class Simulation:
 
     def run(self, seeds, rng_key: int, replicate_offset: int = 0, stream=None) -> fsg_run_info:
         seeds = np.ascontiguousarray(seeds, dtype=np.int32)
-        return fsg_simulate(self.graph.handle, self.prm, seeds.ctypes.data if seeds.size else None,
-                            seeds.size, self.B, int(replicate_offset), int(rng_key), self.sched,
+        sched = self._reuse_sched if (self._completed and self.reuse_workspace) else self.sched
+        self._completed = False
+        info = fsg_simulate(self.graph.handle, self.prm, seeds.ctypes.data if seeds.size else None,
+                            seeds.size, self.B, int(replicate_offset), int(rng_key), sched,
                             self.ws_addr, self.ws_bytes,
                             self.states.data_ptr() if self.states is not None else None,
                             self.counts.data_ptr() if self.counts is not None else None,
                             _stream_ptr(stream))
+        self._completed = True
+        return info
 
 
 class Session:

@@ -395,6 +395,40 @@ def test_ic_frontier_driven(graph, ic_prob, B, offset, K):
           schedule=dict(kernel_variant=3, steps_per_sync=2 if K < 0 else 16))
 
 
+@pytest.mark.parametrize("B", [64, 50])
+def test_ic_frontier_driven_workspace_reuse(B):
+    """Runs after the first on one Simulation pass FSG_OPT_REUSE_WORKSPACE:
+    each frontier-driven run that wrote outputs leaves its planes, bitmaps
+    and ever-active plane clear (the finalize clears the ever-active words it
+    read, a last pass the two frontiers no step cleared), so the next run
+    skips clearing them.  Every run of a sequence -- different seeds and
+    keys, step caps that stop a run with live frontiers, an empty seed set,
+    runs to absorption, a counts-only run on its own object -- equals the
+    oracle's, whether the tag was there or not."""
+    from paper_2603_14895_amd import fsg
+    gr = W.chung_lu(6000, 9.0, 2.5, 1717)
+    gnp = gr.numpy()
+    g = fsg.DeviceGraph(*gnp, out=True)
+    runs = [(W.uniform_seeds(gr.n, 10, 1), 11, -1), (W.uniform_seeds(gr.n, 40, 2), 12, 3),
+            (np.array([], dtype=np.int32), 13, -1), (W.uniform_seeds(gr.n, 5, 3), 14, 2),
+            (W.uniform_seeds(gr.n, 25, 4), 15, -1), (W.uniform_seeds(gr.n, 25, 4), 15, -1)]
+    for want_states in (True, False):
+        sims = {}
+        for i, (seeds, key, K) in enumerate(runs):
+            # one object per step cap (the cap is a parameter of the object)
+            if K not in sims:
+                sims[K] = fsg.Simulation(g, "ic", B, schedule=dict(kernel_variant=3),
+                                         want_states=want_states, p=0.12, max_steps=K)
+            sim = sims[K]
+            info = sim.run(seeds, key)
+            r = oracle_run(gnp, "ic", seeds, B, key, p=0.12, max_steps=K)
+            cnt = sim.counts.cpu().numpy().astype(np.uint32)
+            assert (cnt == r[1]).all(), (i, want_states)
+            assert (int(info.steps_run), int(info.absorbed)) == (r[2], r[3]), i
+            if want_states:
+                assert (sim.states.cpu().numpy() == r[0]).all(), i
+
+
 def test_ic_rmat_weighted_cascade_vs_live_edge_bfs():
     """R-MAT (scale 18, edge factor 16, duplicates and self-loops kept),
     weighted cascade, 50 seeds, B = 64: the GPU matches the live-edge BFS
@@ -412,13 +446,17 @@ def test_ic_rmat_weighted_cascade_vs_live_edge_bfs():
     log(f"[parity] rmat18 steps={rsteps} spread={rc.sum() / 64:.1f}")
 
 
-@pytest.mark.parametrize("B,sched", [(256, None), (1024, dict(row_lanes=4, heavy_threshold=30))])
-def test_sir_generator_call_count(B, sched):
+@pytest.mark.parametrize("B,sched,beta", [(256, None, 0.06),
+                                          (1024, dict(row_lanes=4, heavy_threshold=30), 0.06),
+                                          (256, None, 0.95),
+                                          (256, dict(heavy_threshold=30), 0.95)])
+def test_sir_generator_call_count(B, sched, beta):
     """The counting run (FSG_OPT_COUNT_DRAWS) reports as many Philox4x32-10
     calls as the decision rule needs: at step t, one call per node and block
     of four replicates (g >> 2) in which some replicate needs a draw -- a
-    susceptible one with k >= 1 infected in-neighbours (unless k <= 3 and
-    1 - (1-beta)^k rounds to "always"), or an infected one (gamma strictly
+    susceptible one with k >= 1 infected in-neighbours (unless k <= 15 and
+    1 - (1-beta)^k rounds to "always", as it does for k >= 13 at beta =
+    0.95), or an infected one (gamma strictly
     between 0 and 1) -- counted here from the oracle's states after each
     step t - 1.  The states of the counting run equal the oracle's too."""
     import scipy.sparse as sp
@@ -427,7 +465,7 @@ def test_sir_generator_call_count(B, sched):
     ptr, src = gr.numpy()
     n = gr.n
     seeds = W.uniform_seeds(n, 12, 1812)
-    key, kw = 0xD8A7, dict(beta=0.06, gamma=0.25, max_steps=14)
+    key, kw = 0xD8A7, dict(beta=beta, gamma=0.25, max_steps=14)
     opt = dict(sched or {}, options=fsg.OPT_COUNT_DRAWS, time_kernels=0)
     g = fsg.DeviceGraph(ptr, src)
     sim = fsg.Simulation(g, "sir", B, schedule=opt, **kw)
@@ -446,10 +484,10 @@ def test_sir_generator_call_count(B, sched):
                                    gamma=kw["gamma"], max_steps=t - 1)
         k = A @ (prev == 1).astype(np.int64)
         tk = table[np.minimum(k, table.size - 1)]
-        need_s = (prev == 0) & (k >= 1) & ~((k <= 3) & (tk == always))
+        need_s = (prev == 0) & (k >= 1) & ~((k <= 15) & (tk == always))
         need_i = (prev == 1) & (trec not in (0, always))
         want += int((need_s | need_i).reshape(n, B // 4, 4).any(axis=2).sum())
-    log(f"[parity] generator calls B={B}: gpu {int(info.philox_calls)}, rule {want}")
+    log(f"[parity] generator calls B={B} beta={beta}: gpu {int(info.philox_calls)}, rule {want}")
     assert int(info.philox_calls) == want
 
 
