@@ -110,7 +110,9 @@ typedef struct {
  * the summed device time of the pull-step kernel (HIP events recorded on the
  * call's stream right around its launch in every step that did work; the
  * heavy-row combine and the frontier clear are not included) and the number
- * of steps timed; else 0.
+ * of steps timed; the frontier-driven IC step (one kernel a step, launched
+ * back to back) is timed per chunk of steps_per_sync launches instead, the
+ * launches after absorption, which return at once, included in both; else 0.
  * setup_ms: with kernel timing, the device time from the first to the last
  * set-up operation (table uploads, plane fills, seeding; host work between
  * them included); finalize_ms: the device time of the kernel that writes

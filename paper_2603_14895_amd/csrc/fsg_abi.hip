@@ -356,10 +356,12 @@ void default_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_sch
         o->tile_edges = 16384;
         o->heavy_threshold = 32768;
     }
-    // frontier-driven steps take microseconds, so a run's steps after
-    // absorption (up to a chunk's worth, each an early-exit launch) cost
-    // more than a poll: shorter chunks
-    if (o->kernel_variant == 3) o->steps_per_sync = 8;
+    // frontier-driven steps take microseconds and go back to back; a poll
+    // of the absorption flags (a host round trip with the GPU idle) costs
+    // more than the early-exit launches after absorption that longer chunks
+    // leave (web-scale run, 18 steps: 1.40 / 1.40 / 1.34 ms per run with
+    // chunks of 8 / 16 / 32)
+    if (o->kernel_variant == 3) o->steps_per_sync = 32;
 }
 
 int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fsg_schedule *in,
@@ -425,6 +427,9 @@ constexpr int64_t kSeedStage = 65536;
 
 // HIP events for optional per-step timing, released on scope exit.
 struct EventPool {
+    EventPool() = default;
+    EventPool(const EventPool &) = delete;
+    EventPool &operator=(const EventPool &) = delete;
     std::vector<hipEvent_t> e;
     hipError_t init(size_t count)
     {
@@ -435,11 +440,13 @@ struct EventPool {
         }
         return hipSuccess;
     }
-    ~EventPool()
+    void release()
     {
         for (auto x : e)
             if (x) (void)hipEventDestroy(x);
+        e.clear();
     }
+    ~EventPool() { release(); }
 };
 
 int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const Plan &p,
@@ -652,13 +659,15 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
         if (bytes == 0) return hipSuccess;
         return hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, st);
     };
-    HIP_TRY(up(L.tiles, p.tiles.data(), p.tiles.size() * 4));
-    HIP_TRY(up(L.heavy_rows, p.heavy_rows.data(), p.heavy_rows.size() * 4));
-    HIP_TRY(up(L.heavy_seg, p.heavy_seg.data(), p.heavy_seg.size() * 4));
-    HIP_TRY(up(L.seg_row, p.seg_row.data(), p.seg_row.size() * 4));
-    HIP_TRY(up(L.seg_e0, p.seg_e0.data(), p.seg_e0.size() * 4));
-    HIP_TRY(up(L.seg_e1, p.seg_e1.data(), p.seg_e1.size() * 4));
-    HIP_TRY(up(L.tinf, tinf.data(), tinf.size() * 4));
+    if (!s.push) {  // the frontier-driven IC step reads no row tiles, segments or tables
+        HIP_TRY(up(L.tiles, p.tiles.data(), p.tiles.size() * 4));
+        HIP_TRY(up(L.heavy_rows, p.heavy_rows.data(), p.heavy_rows.size() * 4));
+        HIP_TRY(up(L.heavy_seg, p.heavy_seg.data(), p.heavy_seg.size() * 4));
+        HIP_TRY(up(L.seg_row, p.seg_row.data(), p.seg_row.size() * 4));
+        HIP_TRY(up(L.seg_e0, p.seg_e0.data(), p.seg_e0.size() * 4));
+        HIP_TRY(up(L.seg_e1, p.seg_e1.data(), p.seg_e1.size() * 4));
+        HIP_TRY(up(L.tinf, tinf.data(), tinf.size() * 4));
+    }
     HIP_TRY(up(L.edge_t, edge_t.data(), edge_t.size() * 4));
 
     // the planes lie back to back (256-byte aligned): one zeroing launch.
@@ -812,7 +821,28 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     return FSG_OK;
 }
 
-// Packed planes of the step `steps_run` -> uint8 states and counts.
+// End of a frontier-driven IC run whose finalize clears the ever-active
+// plane: the frontiers of the last two steps leave their buffers (every
+// earlier one was cleared by the step two after it), then the tag records
+// that the run left its buffers clear.  Enqueued only.
+hipError_t scrub_frontiers(const Job &jb, int64_t steps_run, hipStream_t st)
+{
+    StepArgs a = jb.a;
+    for (int64_t t = steps_run + 1; t <= steps_run + 2; ++t) {
+        a.qi_clr = (int32_t)((t + 2) % 4);
+        a.q_clr = jb.queue[a.qi_clr];
+        a.f_clr = jb.front(t - 2);
+        a.bm_clr = jb.front_bm(t - 2);
+        a.sum_clr = jb.front_sum(t - 2);
+        hipError_t e = launch_ic_scrub(a, st);
+        if (e != hipSuccess) return e;
+    }
+    return launch_fill64(jb.tag, 1, jb.tag_value, st);
+}
+
+// Packed planes of the step `steps_run` -> uint8 states and counts; with
+// `scrub` (frontier-driven IC, one word per node) the run's buffers are left
+// clear as well.
 int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32_t *counts,
                  hipStream_t st, double *ms_out = nullptr, bool scrub = false)
 {
@@ -843,32 +873,13 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
     }
     HIP_TRY(launch_finalize(f, st));
     if (ms_out) HIP_TRY(hipEventRecord(ev.e[1], st));
+    if (f.scrub) HIP_TRY(scrub_frontiers(jb, steps_run, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (ms_out) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
         *ms_out = ms;
     }
-    return FSG_OK;
-}
-
-// End of a frontier-driven IC run whose finalize cleared the ever-active
-// plane: the frontiers of the last two steps leave their buffers (every
-// earlier one was cleared by the step two after it), then the tag records
-// that the run left its buffers clear.
-int scrub_job(Job &jb, int64_t steps_run, hipStream_t st)
-{
-    StepArgs a = jb.a;
-    for (int64_t t = steps_run + 1; t <= steps_run + 2; ++t) {
-        a.qi_clr = (int32_t)((t + 2) % 4);
-        a.q_clr = jb.queue[a.qi_clr];
-        a.f_clr = jb.front(t - 2);
-        a.bm_clr = jb.front_bm(t - 2);
-        a.sum_clr = jb.front_sum(t - 2);
-        HIP_TRY(launch_ic_scrub(a, st));
-    }
-    HIP_TRY(launch_fill64(jb.tag, 1, jb.tag_value, st));
-    HIP_TRY(hipStreamSynchronize(st));
     return FSG_OK;
 }
 
@@ -882,6 +893,7 @@ struct Session {
     double kernel_ms = 0.0;
     int64_t timed_steps = 0;
     double setup_ms = 0.0, finalize_ms = 0.0;
+    EventPool setup_ev;  // around the set-up, read once the stream has passed them
     int64_t philox_calls = 0;
 };
 
@@ -900,7 +912,8 @@ int begin_session(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int
     if (!dev_ws || ws_bytes < L.total) return fail(FSG_EWORKSPACE, "simulation workspace too small");
     if (((uintptr_t)dev_ws & 255) != 0) return fail(FSG_EWORKSPACE, "workspace not 256-byte aligned");
     char *base = (char *)dev_ws;
-    EventPool ev;
+    // timing events are read after the next synchronisation (run_steps)
+    EventPool &ev = ss->setup_ev;
     if (s.timed) {
         HIP_TRY(ev.init(2));
         HIP_TRY(hipEventRecord(ev.e[0], st));
@@ -910,13 +923,7 @@ int begin_session(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int
     if (rc) return rc;
     ss->setup_ms = 0.0;
     ss->finalize_ms = 0.0;
-    if (s.timed) {
-        HIP_TRY(hipEventRecord(ev.e[1], st));
-        HIP_TRY(hipEventSynchronize(ev.e[1]));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
-        ss->setup_ms = ms;
-    }
+    if (s.timed) HIP_TRY(hipEventRecord(ev.e[1], st));
     ss->edge_grid = 0;
     if (s.edge1) {
         int dev = 0, ncu = 0;
@@ -982,6 +989,18 @@ void fill_info(const Session &ss, fsg_run_info *info)
 }
 
 // Up to n_more further steps (never past the job's step cap), in chunks of
+// The set-up time of a timed session, once the stream has passed its events.
+hipError_t take_setup_time(Session &ss)
+{
+    if (ss.setup_ev.e.size() != 2) return hipSuccess;
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, ss.setup_ev.e[0], ss.setup_ev.e[1]);
+    if (e != hipSuccess) return e;
+    ss.setup_ms = ms;
+    ss.setup_ev.release();
+    return hipSuccess;
+}
+
 // `sync` steps with one poll of the absorption flags per chunk.  With
 // dev_tally, row i receives the state tally after the i-th step of this call.
 int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
@@ -1023,9 +1042,11 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 a.q_in = jb.queue[a.qi_in];
                 a.q_out = jb.queue[a.qi_out];
                 a.q_clr = jb.queue[a.qi_clr];
-                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
+                // one kernel a step, back to back: timed per chunk (events
+                // between the launches would hold each one back)
+                if (s.timed && i == 1) HIP_TRY(hipEventRecord(ev.e[0], st));
                 HIP_TRY(launch_ic_front(a, ss.edge_grid, s.block, st));
-                if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
+                if (s.timed && i == c) HIP_TRY(hipEventRecord(ev.e[1], st));
             } else if (s.edge1) {
                 a.bm_prev = jb.bm[(step - 1) & 1];
                 a.bm_next = jb.bm[step & 1];
@@ -1049,7 +1070,13 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
         }
         HIP_TRY(hipMemcpyAsync(hflags.data(), flags, (size_t)ring * 4, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (s.timed) {
+        HIP_TRY(take_setup_time(ss));
+        if (s.timed && s.push) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+            ss.kernel_ms += ms;
+            ss.timed_steps += c;
+        } else if (s.timed) {
             for (int64_t i = 1; i <= c; ++i) {
                 // steps after absorption return at once; count only live ones
                 if (i > 1 && hflags[(size_t)((t + i - 1) % ring)] == 0u) break;
@@ -1301,10 +1328,8 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         rc = finalize_job(ss.jb, ss.steps_run, final_states, infected_counts, (hipStream_t)stream,
                           ss.jb.s.timed ? &ss.finalize_ms : nullptr, scrub);
         if (rc) return rc;
-        if (scrub) {
-            rc = scrub_job(ss.jb, ss.steps_run, (hipStream_t)stream);
-            if (rc) return rc;
-        }
+        HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+        HIP_TRY(take_setup_time(ss));
         rc = read_draws(ss, (hipStream_t)stream);
         if (rc) return rc;
         if (info) fill_info(ss, info);

@@ -1918,8 +1918,10 @@ hipError_t launch_zero_unless(void *p, size_t bytes, const uint64_t *tag, uint64
     // whole 16-byte words only: callers pass regions of 256-byte multiples
     const int64_t n16 = (int64_t)(bytes / 16);
     if (n16 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero16_unless, dim3(grid_for(n16, 256)), dim3(256), 0, s, (u32x4 *)p, n16,
-                       tag, expect);
+    // a grid of at most 1024 blocks: when the tag is there every block only
+    // reads it, and a larger grid costs more to dispatch than that
+    const unsigned g = std::min<unsigned>(grid_for(n16, 256), 1024u);
+    hipLaunchKernelGGL(k_zero16_unless, dim3(g), dim3(256), 0, s, (u32x4 *)p, n16, tag, expect);
     return hipGetLastError();
 }
 
