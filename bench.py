@@ -403,9 +403,12 @@ def main():
             abytes = algorithmic_bytes_per_step(c["model"], n, src.size, c["B"], variant == 2)
         kname, avg_ms, nl = step_kernel, avg_kernel_ms, launches
     achieved = abytes / (avg_ms / 1e3) / 1e9
+    traffic = measured_traffic(args.workload, kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": measured_traffic(args.workload, kname),
+                "traffic": traffic,
+                "frac_measured": (round(traffic / (avg_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
+                                  if traffic else None),
                 "kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": nl,
                 "algorithmic_bytes_per_launch": abytes}
     roofline_other = None
@@ -666,6 +669,10 @@ def bench_batch(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic("c3"),
+                     "frac_measured": (round(measured_traffic("c3") / (dev_ms / args.steps /
+                                                                      max(1, max(steps_run)) / 1e3)
+                                             / 1e9 / PEAK_HBM_GBS, 4)
+                                       if measured_traffic("c3") else None),
                      "kernel": "k_batch_step + k_batch_combine (captured step chunks)",
                      "avg_launch_ms": round(dev_ms / args.steps / max(1, max(steps_run)), 5),
                      "launches": args.steps * max(steps_run),
