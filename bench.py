@@ -326,7 +326,10 @@ def main():
     c["graph"] = None
     # IC with one word per node: the graph's out-adjacency too, so the
     # frontier-driven step can push over the out-arcs of small frontiers
-    want_out = c["model"] == "ic" and c["B"] <= 64 and not args.no_out_adjacency
+    # the out-adjacency: the frontier-driven IC step, and the tail mode of the
+    # SI family (candidate rows from the out-arcs of the infected nodes)
+    want_out = ((c["model"] == "ic" and c["B"] <= 64) or c["model"] in ("si", "sis", "sir")) \
+        and not args.no_out_adjacency
     t_b = time.perf_counter()
     dg = fsg.DeviceGraph(ptr, src, device="cuda:0", out=want_out)
     log(f"[bench] graph bound{' with its out-adjacency' if want_out else ''} in "

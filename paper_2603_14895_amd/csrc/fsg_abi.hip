@@ -335,6 +335,8 @@ struct Sched {
     bool wide;   // 64-bit offsets in the row-group kernels even where 32-bit ones fit
     bool count;  // count the generator calls of the SI-family decisions
     bool reuse;  // the caller vouches for the workspace (FSG_OPT_REUSE_WORKSPACE)
+    bool tail;   // SI / SIS / SIR with one pass per row: tail mode allowed
+    bool tail_always;  // ... and taken from the second chunk on (FSG_OPT_TAIL_ALWAYS)
 };
 
 void default_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, fsg_schedule *o)
@@ -405,11 +407,19 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
     s->edge1 = u.kernel_variant >= 2;
     s->push = u.kernel_variant == 3;
     if (s->push) s->block = 512;
-    if (u.options & ~(FSG_OPT_WIDE_OFFSETS | FSG_OPT_COUNT_DRAWS | FSG_OPT_REUSE_WORKSPACE))
+    if (u.options & ~(FSG_OPT_WIDE_OFFSETS | FSG_OPT_COUNT_DRAWS | FSG_OPT_REUSE_WORKSPACE |
+                      FSG_OPT_TAIL_OFF | FSG_OPT_TAIL_ALWAYS))
         return fail(FSG_EINVAL, "unknown schedule option bits");
+    if ((u.options & FSG_OPT_TAIL_OFF) && (u.options & FSG_OPT_TAIL_ALWAYS))
+        return fail(FSG_EINVAL, "FSG_OPT_TAIL_OFF and FSG_OPT_TAIL_ALWAYS together");
     s->wide = (u.options & FSG_OPT_WIDE_OFFSETS) != 0;
     s->count = (u.options & FSG_OPT_COUNT_DRAWS) != 0;
     s->reuse = (u.options & FSG_OPT_REUSE_WORKSPACE) != 0;
+    // the tail mode: SI, SIS, SIR (no latent plane) with at most 16 words,
+    // where no word flags are kept
+    s->tail = (prm->model == FSG_SI || prm->model == FSG_SIS || prm->model == FSG_SIR) && W <= 16 &&
+              !(u.options & FSG_OPT_TAIL_OFF);
+    s->tail_always = s->tail && (u.options & FSG_OPT_TAIL_ALWAYS) != 0;
     return FSG_OK;
 }
 
@@ -417,7 +427,7 @@ struct Layout {
     size_t planes[4];
     int n_planes;
     size_t flags, wflags, tiles, heavy_rows, heavy_seg, seg_row, seg_e0, seg_e1, partial, tinf, edge_t,
-        seeds, bm[3], sum[3], ever, need, stamp, queue[4], qctl, draws, tag, total;
+        seeds, bm[3], sum[3], ever, need, stamp, ibm, icount, queue[4], qctl, draws, tag, total;
     int sum_shift, sum_words;
     int64_t W, plane_words, n_tinf, n_seed_stage;
     int L;
@@ -491,6 +501,10 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
         off = align256(off + (size_t)g->n * (size_t)L->L * (size_t)L->W * 8);
     L->stamp = off;
     if (kind == kKindLT) off = align256(off + (size_t)g->n * 8);  // gain steps, two arrays
+    L->ibm = off;  // SI family, tail mode: four infected-node and two candidate bitmaps
+    if (s.tail) off = align256(off + 6 * (size_t)((g->n + 31) / 32) * 4);
+    L->icount = off;  // nodes with an infected replicate (tail-mode decisions)
+    if (s.tail) off = align256(off + 8);
     for (int i = 0; i < 3; ++i) L->bm[i] = L->sum[i] = 0;
     for (int i = 0; i < 4; ++i) L->queue[i] = 0;
     L->qctl = 0;
@@ -592,6 +606,9 @@ struct Job {
     uint4 *queue[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<uint32_t> tinf_h, edge_t_h;  // host tables the set-up uploads
     uint32_t *ever = nullptr;                // frontier-driven IC: ever-in-a-frontier bitmap
+    uint32_t *ibm = nullptr;                 // SI-family tail mode: infected-node and candidate bitmaps
+    bool tail = false;                       // the tail mode can be taken (out-adjacency bound)
+    unsigned long long *icount = nullptr;    // SI-family tail mode: nodes with an infected replicate
     uint64_t *tag = nullptr;                 // frontier-driven IC: clean-buffers tag
     uint64_t tag_value = 0;                  // the tag this job's layout writes
     // frontier plane (state 1) and its bitmap after step t: the planes
@@ -730,6 +747,11 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     }
     int32_t *dseeds = (int32_t *)(base + L.seeds);
     if (kind == kKindLT) HIP_TRY(launch_fill32((uint32_t *)(base + L.stamp), 2 * g->n, 0xFFFFFFFFu, st));
+    if (s.tail) {
+        jb->ibm = (uint32_t *)(base + L.ibm);
+        jb->icount = (unsigned long long *)(base + L.icount);
+    }
+    jb->tail = s.tail && g->has_out;  // candidates come from the out-adjacency
     for (int64_t i0 = 0; i0 < n_seeds; i0 += L.n_seed_stage) {
         const int64_t cnt = std::min<int64_t>(L.n_seed_stage, n_seeds - i0);
         HIP_TRY(hipMemcpyAsync(dseeds, seeds + i0, (size_t)cnt * 4, hipMemcpyHostToDevice, st));
@@ -801,6 +823,10 @@ int setup_job(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int64_t
     if (s.count) {
         a.draws = (unsigned long long *)(base + L.draws);
         HIP_TRY(launch_fill64((uint64_t *)a.draws, 1, 0ull, st));
+    }
+    if (jb->tail) {
+        a.optr = g->d_optr;
+        a.oarc = g->d_oarc;
     }
     if (s.push) {
         a.ever = jb->ever;
@@ -892,6 +918,8 @@ struct Session {
     bool absorbed = false;
     double kernel_ms = 0.0;
     int64_t timed_steps = 0;
+    bool tail_on = false;                    // the last chunk ran in the tail mode
+    int64_t infected_rows = -1;              // nodes with an infected replicate at the last poll
     double setup_ms = 0.0, finalize_ms = 0.0;
     EventPool setup_ev;  // around the set-up, read once the stream has passed them
     int64_t philox_calls = 0;
@@ -989,6 +1017,10 @@ void fill_info(const Session &ss, fsg_run_info *info)
 }
 
 // Up to n_more further steps (never past the job's step cap), in chunks of
+// Tail mode of the SI family: taken for a chunk when the nodes holding an
+// infected replicate, times the mean in-degree, are at most this many times n.
+constexpr double kTailFactor = 1.0;
+
 // The set-up time of a timed session, once the stream has passed its events.
 hipError_t take_setup_time(Session &ss)
 {
@@ -1017,9 +1049,26 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
     EventPool ev;
     if (s.timed) HIP_TRY(ev.init(2 * (size_t)s.sync));
     int64_t t = t_begin;
+    std::vector<uint32_t> htail(2);
     while (!ss.absorbed && t < K) {
         const int64_t c = std::min<int64_t>(s.sync, K - t);
         HIP_TRY(launch_ring_clear(flags, ring, (int32_t)(t % ring), st, a.wflags, a.W, a.wring, t));
+        if (jb.tail) {
+            // tail mode for this chunk: when few nodes hold an infected
+            // replicate (a row can only change if it or an in-neighbour
+            // does); the stamps of steps t and t-1 are written on entry
+            const double n = (double)jb.n, deg = (double)a.nnz / std::max(n, 1.0);
+            const bool want = t >= 1 && (s.tail_always ||
+                                         (ss.infected_rows >= 0 && (double)ss.infected_rows * deg <= n * kTailFactor));
+            a.ibm_words = (int32_t)((jb.n + 31) / 32);
+            uint32_t *cand = jb.ibm + 4 * (size_t)a.ibm_words;
+            if (want && !ss.tail_on)
+                HIP_TRY(launch_mark_rows(jb.front(t), jb.front(t + 1), jb.ibm, cand, a.ibm_words,
+                                         jb.n, jb.L.W, (uint32_t)(t + 1), st));
+            ss.tail_on = want;
+            a.ibm = want ? jb.ibm : nullptr;
+            a.cand = want ? cand : nullptr;
+        }
         for (int64_t i = 1; i <= c; ++i) {
             const int64_t step = t + i;
             a.step = (uint32_t)step;
@@ -1058,6 +1107,7 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
             } else {
                 if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1)], st));
+                if (a.ibm) HIP_TRY(launch_tail_expand(a, st));
                 HIP_TRY(launch_step(a, kind, jb.L.L, s.block, st));
                 if (s.timed) HIP_TRY(hipEventRecord(ev.e[2 * (i - 1) + 1], st));
                 if (a.n_heavy > 0) HIP_TRY(launch_combine(a, kind, s.block, st));
@@ -1068,9 +1118,14 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 HIP_TRY(launch_tally(f, st));
             }
         }
+        if (jb.tail) {  // nodes with an infected replicate after the chunk
+            HIP_TRY(launch_count_rows(jb.front(t + c), jb.n, jb.L.W, jb.icount, st));
+            HIP_TRY(hipMemcpyAsync(htail.data(), jb.icount, 8, hipMemcpyDeviceToHost, st));
+        }
         HIP_TRY(hipMemcpyAsync(hflags.data(), flags, (size_t)ring * 4, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         HIP_TRY(take_setup_time(ss));
+        if (jb.tail) ss.infected_rows = (int64_t)((uint64_t)htail[0] | ((uint64_t)htail[1] << 32));
         if (s.timed && s.push) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));

@@ -90,6 +90,17 @@ struct StepArgs {
     // which no one writes during step t.  Seeds: 0 in array 0.  Null for
     // the other models.
     uint32_t *stamp;
+    // SI / SIS / SIR late in a run (the tail mode): four bitmaps of ibm_words
+    // words, bitmap t % 4 marking the nodes with an infected replicate after
+    // step t, and two candidate bitmaps: before step t the nodes of bitmap
+    // t-1 and their out-neighbours (optr / oarc) are marked in candidate
+    // bitmap t % 2.  Step t reads bitmap t-2 and candidate bitmap t % 2, sets
+    // bits in bitmap t and clears bitmap t+1 and candidate bitmap (t+1) % 2;
+    // a light row that is not a candidate is left out of step t (no count can
+    // be nonzero, no replicate can recover).  Null otherwise.
+    uint32_t *ibm;
+    uint32_t *cand;
+    int32_t ibm_words;
     // frontier bitmaps of the edge-parallel IC kernel: bit u of bm_prev is set
     // iff node u has a newly active replicate after step t-1 (prev is only
     // meaningful where it is set); bm_next is cleared before step t
@@ -197,6 +208,15 @@ hipError_t launch_zero_unless(void *p, size_t bytes, const uint64_t *tag, uint64
                               hipStream_t s);
 hipError_t launch_fill32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_stamp_seeds(uint32_t *stamp, const int32_t *seeds, int64_t ns, hipStream_t s);
+// Tail mode of the SI family: the bitmaps step t reads (state t-1 in `cur`,
+// state t-2 in `old`) and the cleared one it writes, and the number of nodes
+// with a nonzero word in a plane.
+hipError_t launch_mark_rows(const uint64_t *cur, const uint64_t *old, uint32_t *ibm, uint32_t *cand,
+                            int32_t ibm_words, int64_t n, int64_t W, uint32_t t, hipStream_t s);
+// Candidate rows of tail-mode step a.step (one wave per infected node).
+hipError_t launch_tail_expand(const StepArgs &a, hipStream_t s);
+hipError_t launch_count_rows(const uint64_t *plane, int64_t n, int64_t W, unsigned long long *count,
+                             hipStream_t s);
 hipError_t launch_ring_clear(uint32_t *flags, int32_t ring, int32_t keep, hipStream_t s,
                              uint32_t *wflags = nullptr, int32_t W = 0, int32_t wring = 0,
                              int64_t t = 0);

@@ -519,6 +519,10 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
     a.next[idx] = nh;
     a.aux[idx] = nr;
     any |= nh != 0;
+    // tail mode: the node has an infected replicate after step t
+    if (a.ibm != nullptr && nh != 0ull)
+        atomicOr(&a.ibm[(size_t)(a.step & 3u) * (size_t)a.ibm_words + (size_t)(v >> 5)],
+                 1u << (v & 31));
 }
 
 template <int L>
@@ -858,6 +862,12 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
         // has such a neighbour and the test would only add loads)
         const bool fresh_test = KIND == kKindLT && a.stamp != nullptr && wm.compact &&
                                 wm.count * 2 <= a.W;
+        // SI family in the tail mode: a row with no infected replicate and
+        // no infected in-neighbour at t-1 cannot change at step t
+        const bool tail_test = KIND == kKindEpidemic && a.ibm != nullptr;
+        const uint32_t *cand = tail_test ? a.cand + (size_t)(a.step & 1u) * a.ibm_words : nullptr;
+        const uint32_t *inf2 = tail_test ? a.ibm + (size_t)((a.step - 2u) & 3u) * a.ibm_words : nullptr;
+        auto marked = [](const uint32_t *bm, int u) { return (bm[u >> 5] >> (u & 31)) & 1u; };
         const int rl = 1 << (lgGe + a.lgS);  // lanes of a row
         const uint64_t rowmask = (rl == 64 ? ~0ull : ((1ull << rl) - 1ull)) << (slote * rl);
         for (int rb = t0 + wave * rpwe; rb < t1; rb += nwaves * rpwe) {
@@ -870,6 +880,18 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                 if (e1 - e0 > a.heavy) act = false;
             }
             uint64_t rowlm = ~0ull;
+            if (tail_test) {
+                if (act && !marked(cand, v)) {
+                    // left out: its state after step t is its state after
+                    // t-1, no infected replicate; the buffer step t writes
+                    // holds the state after t-2, nonzero only if the node
+                    // had an infected replicate then
+                    if (marked(inf2, v))
+                        for (int w = lane & (rl - 1); w < a.W; w += rl)
+                            a.next[(int64_t)v * a.W + w] = 0ull;
+                    act = false;
+                }
+            }
             if (fresh_test) {
                 const uint32_t *gained = a.stamp + (size_t)((a.step - 1u) & 1u) * (size_t)a.n;
                 bool f = false;
@@ -924,11 +946,43 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
     }
 }
 
+// Tail mode: whether light-row block `bid` has nothing to do at step t -- no
+// candidate row and no row infected after t-2 (whose buffer word must be
+// cleared) in its tile.  The bitmap words at the tile's ends may hold other
+// tiles' rows, which only makes the test keep a tile it could have left.
+// Every wave of the block reads the same words and gets the same answer.
+__device__ __forceinline__ bool tail_tile_idle(const StepArgs &a, int bid)
+{
+    const int nwaves = blockDim.x >> 6;
+    const int seg_blocks = (a.n_seg + nwaves - 1) / nwaves;
+    if (bid < seg_blocks) return false;
+    const int tile = bid - seg_blocks;
+    const int t0 = a.tiles[2 * tile], t1 = a.tiles[2 * tile + 1];
+    if (t1 <= t0) return true;
+    const uint32_t *cand = a.cand + (size_t)(a.step & 1u) * a.ibm_words;
+    const uint32_t *inf2 = a.ibm + (size_t)((a.step - 2u) & 3u) * a.ibm_words;
+    bool busy = false;
+    for (int i = (t0 >> 5) + (int)(threadIdx.x & 63); i <= ((t1 - 1) >> 5) && !busy; i += 64)
+        busy = (cand[i] | inf2[i]) != 0u;
+    return __ballot(busy) == 0ull;
+}
+
 // One synchronous step t = a.step of one job.
 template <int KIND, int L>
 __global__ void __launch_bounds__(1024) k_step(StepArgs a)
 {
     if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // nothing left to change
+    if (KIND == kKindEpidemic && a.ibm != nullptr) {
+        // the bitmaps step t+1 sets, then whether this block has work
+        uint32_t *clr = a.ibm + (size_t)((a.step + 1u) & 3u) * a.ibm_words;
+        uint32_t *cclr = a.cand + (size_t)((a.step + 1u) & 1u) * a.ibm_words;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.ibm_words;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            clr[i] = 0u;
+            cclr[i] = 0u;
+        }
+        if (tail_tile_idle(a, blockIdx.x)) return;
+    }
     __shared__ uint32_t s_tinf[KIND == kKindEpidemic ? kTinfLds : 1];
     __shared__ uint32_t s_code[kCodeTable];
     int tl_n = 0;
@@ -1598,6 +1652,81 @@ __global__ void k_zero16(u32x4 *p, int64_t count16)
         __builtin_nontemporal_store(z, p + i);
 }
 
+// Bitmaps of the tail mode for step t: bit v of bitmap (t-1) % 4 set iff
+// `cur` (the state after t-1) has a nonzero word in row v, of bitmap
+// (t-2) % 4 iff `old` (the state after t-2) does; bitmap t % 4 cleared.  One
+// thread per bitmap word (32 rows).
+__global__ void k_mark_rows(const uint64_t *cur, const uint64_t *old, uint32_t *ibm, uint32_t *cand,
+                            int32_t ibm_words, int64_t n, int64_t W, uint32_t t)
+{
+    uint32_t *b1 = ibm + (size_t)((t - 1u) & 3u) * ibm_words;
+    uint32_t *b2 = ibm + (size_t)((t - 2u) & 3u) * ibm_words;
+    uint32_t *b0 = ibm + (size_t)(t & 3u) * ibm_words;
+    uint32_t *c0 = cand + (size_t)(t & 1u) * ibm_words;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ibm_words;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t m1 = 0, m2 = 0;
+        for (int j = 0; j < 32; ++j) {
+            const int64_t v = 32 * i + j;
+            if (v >= n) break;
+            uint64_t c = 0, o = 0;
+            for (int64_t w = 0; w < W; ++w) {
+                c |= cur[v * W + w];
+                o |= old[v * W + w];
+            }
+            m1 |= (c ? 1u : 0u) << j;
+            m2 |= (o ? 1u : 0u) << j;
+        }
+        b1[i] = m1;
+        b2[i] = m2;
+        b0[i] = 0u;
+        c0[i] = 0u;
+    }
+}
+
+// Candidates of tail-mode step t: every node with an infected replicate
+// after t-1 (bitmap t-1) and its out-neighbours are marked in candidate
+// bitmap t % 2.  Wave k takes bitmap words k, k + waves, ...; each set bit is
+// a node whose out-arcs the wave's lanes mark.
+__global__ void __launch_bounds__(256) k_tail_expand(StepArgs a)
+{
+    if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // as the step: nothing left
+    const uint32_t *inf1 = a.ibm + (size_t)((a.step - 1u) & 3u) * a.ibm_words;
+    uint32_t *cand = a.cand + (size_t)(a.step & 1u) * a.ibm_words;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = wave; i < a.ibm_words; i += nwave) {
+        uint32_t m = inf1[i];
+        if (m == 0u) continue;
+        if (lane == 0) atomicOr(&cand[i], m);
+        while (m) {
+            const int u = (int)(32 * i) + __builtin_ctz(m);
+            m &= m - 1u;
+            const int o1 = a.optr[u + 1];
+            for (int e = a.optr[u] + lane; e < o1; e += 64) {
+                const int v = a.oarc[e].x;
+                atomicOr(&cand[v >> 5], 1u << (v & 31));
+            }
+        }
+    }
+}
+
+// Number of nodes with a nonzero word in `plane` (one integer atomic add per
+// wave).
+__global__ void k_count_rows(const uint64_t *plane, int64_t n, int64_t W, unsigned long long *count)
+{
+    unsigned long long c = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t x = 0;
+        for (int64_t w = 0; w < W; ++w) x |= plane[v * W + w];
+        c += x ? 1ull : 0ull;
+    }
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
 __global__ void k_zero16_unless(u32x4 *p, int64_t count16, const uint64_t *tag, uint64_t expect)
 {
     if (*tag == expect) return;
@@ -1922,6 +2051,34 @@ hipError_t launch_zero_unless(void *p, size_t bytes, const uint64_t *tag, uint64
     // reads it, and a larger grid costs more to dispatch than that
     const unsigned g = std::min<unsigned>(grid_for(n16, 256), 1024u);
     hipLaunchKernelGGL(k_zero16_unless, dim3(g), dim3(256), 0, s, (u32x4 *)p, n16, tag, expect);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_rows(const uint64_t *cur, const uint64_t *old, uint32_t *ibm, uint32_t *cand,
+                            int32_t ibm_words, int64_t n, int64_t W, uint32_t t, hipStream_t s)
+{
+    if (ibm_words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(ibm_words, 64)), dim3(64), 0, s, cur, old, ibm,
+                       cand, ibm_words, n, W, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_expand(const StepArgs &a, hipStream_t s)
+{
+    // a wave per bitmap word, at most 1024 blocks of four waves
+    const unsigned g = std::min<unsigned>(grid_for((int64_t)a.ibm_words * 64, 256), 1024u);
+    hipLaunchKernelGGL(k_tail_expand, dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_rows(const uint64_t *plane, int64_t n, int64_t W, unsigned long long *count,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill64, dim3(1), dim3(64), 0, s, (uint64_t *)count, (int64_t)1, 0ull);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n <= 0) return e;
+    hipLaunchKernelGGL(k_count_rows, dim3(std::min<unsigned>(grid_for(n, 256), 2048u)), dim3(256), 0,
+                       s, plane, n, W, count);
     return hipGetLastError();
 }
 

@@ -58,6 +58,8 @@ class fsg_schedule(ctypes.Structure):
 OPT_WIDE_OFFSETS = 1  # FSG_OPT_WIDE_OFFSETS
 OPT_COUNT_DRAWS = 2   # FSG_OPT_COUNT_DRAWS
 OPT_REUSE_WORKSPACE = 4  # FSG_OPT_REUSE_WORKSPACE
+OPT_TAIL_OFF = 8  # FSG_OPT_TAIL_OFF
+OPT_TAIL_ALWAYS = 16  # FSG_OPT_TAIL_ALWAYS
 
 
 CALIB_TERMS = 9

@@ -81,10 +81,12 @@ def test_schedule_options_validated():
     h = fsg.fsg_graph_create(n, nnz, ptr.ctypes.data, src.ctypes.data)
     try:
         prm, _ = fsg.make_params("sir", beta=0.1, gamma=0.1, max_steps=5)
-        for opt in (fsg.OPT_WIDE_OFFSETS, fsg.OPT_COUNT_DRAWS, fsg.OPT_REUSE_WORKSPACE, 7):
+        for opt in (fsg.OPT_WIDE_OFFSETS, fsg.OPT_COUNT_DRAWS, fsg.OPT_REUSE_WORKSPACE,
+                    fsg.OPT_TAIL_OFF, fsg.OPT_TAIL_ALWAYS, 7, 15, 23):
             ok = fsg.make_schedule({"options": opt})
             assert fsg.fsg_sim_workspace_size(h, prm, 64, ok) > 0
-        for bad in (8, 12, 1 << 30):
+        # unknown bits, and the two tail-mode options together
+        for bad in (32, 24, 1 << 30):
             with pytest.raises(fsg.FsgError) as e:
                 fsg.fsg_sim_workspace_size(h, prm, 64, fsg.make_schedule({"options": bad}))
             assert e.value.code == fsg.FSG_EINVAL

@@ -266,6 +266,43 @@ def test_si_family_draw_classes_and_saturated_thresholds():
                       max_steps=6, replicate_offset=off)
 
 
+@pytest.mark.parametrize("model", ["sir", "sis", "si"])
+def test_si_family_tail_mode(model):
+    """The tail mode (rows with no infected replicate and no infected
+    in-neighbour after step t-1 -- found from the out-arcs of the infected
+    nodes -- are left out of step t) gives the oracle's bits: forced from the second chunk on -- through the epidemic's growth,
+    with chunks of 1 and 3 steps, ragged and full words, edge-split rows and
+    heavy-row segments -- and left to the library's own switch; a session
+    stepped piece by piece in the tail mode ends in the same state."""
+    from paper_2603_14895_amd import fsg
+    gr = W.chung_lu(3000, 10.0, 2.5, 2101)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 40, 2102)
+    kw = dict(beta=0.05, gamma=0.2, max_steps=70 if model == "sir" else 25)
+    always = fsg.OPT_TAIL_ALWAYS
+    for B in (64, 100, 1024):
+        for sched in (dict(options=always, steps_per_sync=1), dict(options=always, steps_per_sync=3),
+                      dict(options=always, steps_per_sync=2, row_lanes=4, heavy_threshold=20),
+                      dict(steps_per_sync=4), dict(options=fsg.OPT_TAIL_OFF)):
+            _both(gnp, model, seeds, B, 0x7A11 + B, f"tail-{model}-{sched}", schedule=sched,
+                  out=True, **kw)
+    # without the out-adjacency the mode is never taken
+    _both(gnp, model, seeds, 100, 0x7A12, f"tail-{model}-no-out", out=False,
+          schedule=dict(options=always, steps_per_sync=1), **kw)
+    sess = fsg.Session(fsg.DeviceGraph(*gnp, out=True), model, seeds, 100, 0x7A77,
+                       schedule=dict(options=always, steps_per_sync=1), **kw)
+    try:
+        for n in (1, 2, 5, 30, 40):
+            info, _ = sess.step(n)
+        st, cnt, _ = sess.read(want_states=True)
+        got = (st.cpu().numpy(), cnt.cpu().numpy().astype(np.uint32), int(info.steps_run),
+               int(info.absorbed))
+    finally:
+        sess.close()
+    r = oracle_run(gnp, model, seeds, 100, 0x7A77, **kw)
+    assert_same(got, r, f"tail-session-{model}")
+
+
 def test_replicate_split_and_repeat_invariance():
     """Splitting a batch with replicate_offset and repeating a run change
     nothing (counter-based draws keyed by the global replicate index)."""
@@ -283,14 +320,16 @@ def test_replicate_split_and_repeat_invariance():
 
 def test_c2_full_size_sampled_replicates():
     """The SIR workload at full size (Chung-Lu n = 10^6, mean degree 20,
-    B = 1024, 200 steps) in the default schedule: replicates the oracle
-    computes one by one, including ones whose generator block straddles a
-    word boundary, match bit for bit; counts equal the states' tallies."""
+    B = 1024, 200 steps) in the default schedule, with the out-adjacency
+    bound as the benchmark binds it (so the late steps take the tail mode):
+    replicates the oracle computes one by one, including ones whose
+    generator block straddles a word boundary, match bit for bit; counts
+    equal the states' tallies."""
     c = W.config_c2()
     gr = c["graph"]
     gnp = gr.numpy()
     log(f"[parity] c2 full n={gr.n} nnz={gr.nnz}")
-    st, cnt, steps, absorbed = gpu_run(gnp, "sir", c["seeds"], c["B"], c["rng_key"],
+    st, cnt, steps, absorbed = gpu_run(gnp, "sir", c["seeds"], c["B"], c["rng_key"], out=True,
                                        beta=c["beta"], gamma=c["gamma"], max_steps=c["max_steps"])
     assert (((st == 1) | (st == 2)).sum(axis=1) == cnt).all()
     for r0 in (0, 61, 1021):
