@@ -183,14 +183,16 @@ typedef struct {
  *                  them cleared).  Other runs ignore the option; results are
  *                  the same either way.
  *                  Tail mode (SI, SIS, SIR with B <= 1024, fsg_simulate and
- *                  sessions): once few nodes hold an infected replicate, a
- *                  row whose in-neighbours and itself hold none after step
- *                  t-1 cannot change at step t and is left out of it (a test
- *                  of per-node step stamps instead of the count and the
- *                  draws).  The library checks the number of such nodes at
- *                  every poll of the absorption flags and takes the mode for
- *                  the next chunk of steps when it times the mean in-degree
- *                  is at most n / 4.  FSG_OPT_TAIL_OFF never takes it;
+ *                  sessions, on a graph with its out-adjacency bound): once
+ *                  few nodes hold an infected replicate, a row whose
+ *                  in-neighbours and itself hold none after step t-1 cannot
+ *                  change at step t and is left out of it; before each step
+ *                  the out-arcs of those nodes mark the rows that are not
+ *                  (one more small kernel a step, timed with the step
+ *                  kernel).  The library counts such nodes at every poll of
+ *                  the absorption flags and takes the mode for the next
+ *                  chunk of steps when that count times the mean in-degree
+ *                  is at most n.  FSG_OPT_TAIL_OFF never takes it;
  *                  FSG_OPT_TAIL_ALWAYS takes it for every chunk after the
  *                  first (for tests).  Results are the same either way. */
 #define FSG_OPT_WIDE_OFFSETS 1
