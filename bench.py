@@ -632,9 +632,16 @@ def bench_batch(args):
         # the batch is tuned as a batch: whole runs scored by device time
         t1 = time.perf_counter()
         tune = batch.autotune(max_trials=args.tune_trials)
+        by_model = {}
+        for j, sc in zip(jobs, tune["schedules"]):
+            key = {k: sc.get(k, 0) for k in ("row_lanes", "tile_edges", "heavy_threshold")}
+            by_model.setdefault(j["model"], [])
+            if key not in by_model[j["model"]]:
+                by_model[j["model"]].append(key)
+        tune["schedules_by_model"] = by_model
         log(f"[bench] batch autotune: {tune['default_ms']:.1f} -> {tune['best_ms']:.1f} ms device "
             f"in {tune['trials']} trials ({time.perf_counter() - t1:.1f}s); steps_per_sync "
-            f"{tune['steps_per_sync']}, blocks per CU {tune['blocks_per_cu']}")
+            f"{tune['steps_per_sync']}, blocks per CU {tune['blocks_per_cu']}; schedules {by_model}")
     log(f"[bench] batch workspace {batch.ws_bytes / 2**30:.2f} GiB")
     for i in range(args.warmup):
         infos, ms = batch.run()
@@ -668,7 +675,8 @@ def bench_batch(args):
                    "B": [j["B"] for j in jobs], "steps_run": steps_run,
                    "autotuned": bool(args.autotune), "parallelism": "single GPU"},
         "autotune": ({k: tune[k] for k in ("default_ms", "best_ms", "trials", "steps_per_sync",
-                                           "blocks_per_cu")} if tune else None),
+                                           "blocks_per_cu", "schedules_by_model")}
+                     if tune else None),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic("c3"),

@@ -519,10 +519,12 @@ __device__ __forceinline__ void epi_decide(const StepArgs &a, int G, int S, bool
     a.next[idx] = nh;
     a.aux[idx] = nr;
     any |= nh != 0;
-    // tail mode: the node has an infected replicate after step t
-    if (a.ibm != nullptr && nh != 0ull)
-        atomicOr(&a.ibm[(size_t)(a.step & 3u) * (size_t)a.ibm_words + (size_t)(v >> 5)],
-                 1u << (v & 31));
+}
+
+// Tail mode: node v has an infected replicate after step t (bitmap t % 4).
+__device__ __forceinline__ void mark_infected(const StepArgs &a, int v)
+{
+    atomicOr(&a.ibm[(size_t)(a.step & 3u) * (size_t)a.ibm_words + (size_t)(v >> 5)], 1u << (v & 31));
 }
 
 template <int L>
@@ -823,7 +825,7 @@ __device__ __forceinline__ void note_words(const StepArgs &a, int G, int w, bool
 // Work of one block of the pull step: block `bid` < seg_blocks owns heavy-row
 // segments (one per row slot; long, so they start first), the rest own light
 // tiles.  Returns through `any` whether a state-1 node remains.
-template <int KIND, int L>
+template <int KIND, int L, bool TAIL = false>
 __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uint32_t *tl,
                                            int tl_n, const uint32_t *tcode, bool &any)
 {
@@ -864,7 +866,7 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                                 wm.count * 2 <= a.W;
         // SI family in the tail mode: a row with no infected replicate and
         // no infected in-neighbour at t-1 cannot change at step t
-        const bool tail_test = KIND == kKindEpidemic && a.ibm != nullptr;
+        const bool tail_test = TAIL && KIND == kKindEpidemic && a.ibm != nullptr;
         const uint32_t *cand = tail_test ? a.cand + (size_t)(a.step & 1u) * a.ibm_words : nullptr;
         const uint32_t *inf2 = tail_test ? a.ibm + (size_t)((a.step - 2u) & 3u) * a.ibm_words : nullptr;
         auto marked = [](const uint32_t *bm, int u) { return (bm[u >> 5] >> (u & 31)) & 1u; };
@@ -908,6 +910,8 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                 row_word<KIND, L>(a, Ge, S, act && ok, v, w, e0, e1, (uint32_t)(e1 - e0), se, -1,
                                   share_e, tl, tl_n, tcode, lm & rowlm, anyw);
                 note_words(a, Ge, w, ok, anyw);
+                // SI family: anyw = an infected replicate in this word after the step
+                if (tail_test && anyw) mark_infected(a, v);
                 any |= anyw;
             }
         }
@@ -968,11 +972,11 @@ __device__ __forceinline__ bool tail_tile_idle(const StepArgs &a, int bid)
 }
 
 // One synchronous step t = a.step of one job.
-template <int KIND, int L>
+template <int KIND, int L, bool TAIL = false>
 __global__ void __launch_bounds__(1024) k_step(StepArgs a)
 {
     if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // nothing left to change
-    if (KIND == kKindEpidemic && a.ibm != nullptr) {
+    if (TAIL && KIND == kKindEpidemic && a.ibm != nullptr) {
         // the bitmaps step t+1 sets, then whether this block has work
         uint32_t *clr = a.ibm + (size_t)((a.step + 1u) & 3u) * a.ibm_words;
         uint32_t *cclr = a.cand + (size_t)((a.step + 1u) & 1u) * a.ibm_words;
@@ -993,7 +997,7 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
         __syncthreads();
     }
     bool any = false;
-    step_block<KIND, L>(a, blockIdx.x, s_tinf, tl_n, s_code, any);
+    step_block<KIND, L, TAIL>(a, blockIdx.x, s_tinf, tl_n, s_code, any);
     if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
 }
 
@@ -1067,6 +1071,7 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
                 for (int l = 0; l < LC; ++l) c[l] &= counted;
                 epi_decide<LC>(a, G, S2, valid, v, ww, idx, h, r, e, sus, c, ss, share, nullptr, 0,
                                tcode, anyw);
+                if (a.ibm != nullptr && anyw) mark_infected(a, v);  // tail mode
             } else {
                 const uint64_t act_w = valid ? a.prev[idx] : 0ull;
                 const uint64_t inact = valid ? (~act_w & tail_mask(ww, a.B) & lm) : 0ull;
@@ -2178,15 +2183,15 @@ int counter_planes_for(int64_t max_count)
     return 16;
 }
 
-template <int KIND>
+template <int KIND, bool TAIL>
 static hipError_t step_kind(const StepArgs &a, int L, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (L) {
-    case 2: hipLaunchKernelGGL((k_step<KIND, 2>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_step<KIND, 4>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_step<KIND, 8>), grid, block, 0, s, a); break;
-    case 12: hipLaunchKernelGGL((k_step<KIND, 12>), grid, block, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_step<KIND, 16>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_step<KIND, 2, TAIL>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_step<KIND, 4, TAIL>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_step<KIND, 8, TAIL>), grid, block, 0, s, a); break;
+    case 12: hipLaunchKernelGGL((k_step<KIND, 12, TAIL>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_step<KIND, 16, TAIL>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2201,8 +2206,12 @@ hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_
         hipLaunchKernelGGL((k_step<kKindIC, 1>), grid, blk, 0, s, a);
         return hipGetLastError();
     }
-    if (kind == kKindEpidemic) return step_kind<kKindEpidemic>(a, L, grid, blk, s);
-    return step_kind<kKindLT>(a, L, grid, blk, s);
+    // the tail-mode row test in its own instantiation: the other kernels
+    // keep their register allocation
+    if (kind == kKindEpidemic && a.ibm != nullptr)
+        return step_kind<kKindEpidemic, true>(a, L, grid, blk, s);
+    if (kind == kKindEpidemic) return step_kind<kKindEpidemic, false>(a, L, grid, blk, s);
+    return step_kind<kKindLT, false>(a, L, grid, blk, s);
 }
 
 hipError_t launch_combine(const StepArgs &a, int kind, int /*block*/, hipStream_t s)
