@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the schedule(s) first with the library autotuner")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
+    ap.add_argument("--steps-per-sync", type=int, default=0,
+                    help="c3: batched steps per captured chunk (0: the binding's default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0,
                     help="c3: persistent blocks of the batched kernels per CU (0: default)")
     ap.add_argument("--tune-trials", type=int, default=32,
@@ -625,7 +627,8 @@ def bench_batch(args):
     tot_nnz = sum(h[1].size for h in host)
     log(f"[bench] c3: {len(jobs)} jobs, {tot_nnz} arcs, B mean "
         f"{np.mean([j['B'] for j in jobs]):.0f} (built in {time.perf_counter() - t0:.1f}s)")
-    batch = fsg.Batch(jobs, steps_per_sync=16, want_states=not args.no_states,
+    batch = fsg.Batch(jobs, steps_per_sync=args.steps_per_sync or fsg.BATCH_STEPS_PER_SYNC,
+                      want_states=not args.no_states,
                       blocks_per_cu=args.blocks_per_cu or None)
     tune = None
     if args.autotune:

@@ -1559,12 +1559,20 @@ struct fsg_plan {
 
 namespace {
 
+// Defaults of a job in the batched launch: larger tiles and a higher heavy
+// cut than a job alone, since the other jobs already fill the GPU (the batch
+// autotuner chose both for every model class of the 64-job mixed batch).
+constexpr int32_t kBatchTileEdges = 8192;
+constexpr int32_t kBatchHeavy = 2048;
+
 int resolve_batch_sched(const fsg_job &j, Sched *s)
 {
     fsg_schedule u = j.sched;
     if (u.kernel_variant >= 2) return fail(FSG_EINVAL, "batched jobs use kernel_variant 0 or 1");
     u.kernel_variant = 1;
     u.block_threads = kBatchBlock;
+    if (u.tile_edges == 0) u.tile_edges = kBatchTileEdges;
+    if (u.heavy_threshold == 0) u.heavy_threshold = kBatchHeavy;
     return resolve_sched(j.g, &j.prm, j.B, &u, s);
 }
 
@@ -2020,8 +2028,8 @@ struct BatchTrial {
 
 // Knob values tried per model class (0 keeps the library default).
 const int kTryLanes[] = {0, 16, 32, 64};
-const int kTryTile[] = {0, 2048, 8192};
-const int kTryHeavy[] = {0, 512, 2048};
+const int kTryTile[] = {0, 4096, 16384};
+const int kTryHeavy[] = {0, 512, 1024};
 const int kTrySync[] = {16, 8, 32, 64};
 const int kTryBlocks[] = {4, 2, 8};
 

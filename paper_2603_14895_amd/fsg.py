@@ -583,6 +583,11 @@ def autotune(graph: DeviceGraph, model, seeds, B, rng_key, *, tune_steps=None, b
     return best.as_dict(), bms, dms
 
 
+# Batched steps per captured chunk (one poll of the absorption flags each):
+# the batch autotuner chose 8 on the 64-job mixed batch.
+BATCH_STEPS_PER_SYNC = 8
+
+
 class Batch:
     """Several jobs in one batched run (fsg_batch_plan / fsg_batch_run).
 
@@ -591,7 +596,7 @@ class Batch:
 
     PARAM_KEYS = ("p", "ic_prob", "edge_p", "beta", "gamma", "max_steps", "alpha")
 
-    def __init__(self, jobs, steps_per_sync=16, want_states=True, want_counts=True,
+    def __init__(self, jobs, steps_per_sync=None, want_states=True, want_counts=True,
                  blocks_per_cu=None):
         import torch
         self.n = len(jobs)
@@ -623,7 +628,7 @@ class Batch:
             a.infected_counts = ct.data_ptr() if ct is not None else None
         self._arr = arr
         self.device = jobs[0]["graph"].device
-        self.steps_per_sync = int(steps_per_sync)
+        self.steps_per_sync = int(steps_per_sync or BATCH_STEPS_PER_SYNC)
         self.blocks_per_cu = None
         self.plan, self.ws_bytes = fsg_batch_plan(arr, self.n, self.steps_per_sync)
         if blocks_per_cu is not None:

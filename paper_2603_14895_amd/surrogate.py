@@ -53,7 +53,7 @@ def mc_frequencies(graph: fsg.DeviceGraph, sets, betas, gamma: float, max_steps:
         idx = range(b0, min(len(sets), b0 + jobs_per_batch))
         jobs = [dict(graph=graph, model="sir", B=B, seeds=sets[i], rng_key=key_base + i,
                      beta=float(betas[i]), gamma=gamma, max_steps=max_steps) for i in idx]
-        batch = fsg.Batch(jobs, steps_per_sync=16, want_states=False)
+        batch = fsg.Batch(jobs, want_states=False)
         _, ms = batch.run()
         total_ms += ms
         for k, i in enumerate(idx):
