@@ -357,13 +357,14 @@ def main():
     t1 = time.perf_counter()
     total_updates = 0.0
     kernel_ms = fin_ms = setup_ms = 0.0
-    launches = 0
+    launches = tail_launches = 0
     steps_seen = []
     for i in range(args.steps):
         info = sim.run(c["seeds"], c["rng_key"])
         total_updates += float(src.size) * c["B"] * info.steps_run
         kernel_ms += info.step_kernel_ms
         launches += info.step_launches
+        tail_launches += info.tail_steps
         fin_ms += info.finalize_ms
         setup_ms += info.setup_ms
         steps_seen.append(int(info.steps_run))
@@ -406,6 +407,11 @@ def main():
             abytes = 24.0 * float(sum(live)) / max(1, launches // args.steps)
         else:
             abytes = algorithmic_bytes_per_step(c["model"], n, src.size, c["B"], variant == 2)
+            if tail_launches:
+                # tail-mode steps (SI family) leave out the rows that cannot
+                # change: counted here as moving nothing, so the mean over the
+                # launches is a lower bound
+                abytes *= (launches - tail_launches) / max(launches, 1)
         kname, avg_ms, nl = step_kernel, avg_kernel_ms, launches
     achieved = abytes / (avg_ms / 1e3) / 1e9
     traffic = measured_traffic(args.workload, kname)
@@ -415,7 +421,8 @@ def main():
                 "frac_measured": (round(traffic / (avg_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
                                   if traffic else None),
                 "kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": nl,
-                "algorithmic_bytes_per_launch": abytes}
+                "algorithmic_bytes_per_launch": abytes,
+                "tail_mode_launches": tail_launches}
     roofline_other = None
     if c["model"] in ("sir", "sis", "si", "seir", "seis") and kname == "k_step":
         # a counting run gives the generator calls per step: the arithmetic

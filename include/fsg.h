@@ -117,13 +117,15 @@ typedef struct {
  * set-up operation (table uploads, plane fills, seeding; host work between
  * them included); finalize_ms: the device time of the kernel that writes
  * final_states and infected_counts (fsg_simulate only); else 0.
+ * tail_steps: steps run in the tail mode of the SI family (see
+ * FSG_OPT_TAIL_OFF), which leave out the rows that cannot change; else 0.
  * philox_calls: with FSG_OPT_COUNT_DRAWS, the Philox4x32-10 calls of the
  * SI-family decisions over the steps run (each call gives the draws of four
  * consecutive replicates of one node and step); else 0. */
 typedef struct {
     int64_t steps_run;
     int32_t absorbed;
-    int32_t reserved;
+    int32_t tail_steps;
     double step_kernel_ms;
     int64_t step_launches;
     double setup_ms;

@@ -919,6 +919,7 @@ struct Session {
     double kernel_ms = 0.0;
     int64_t timed_steps = 0;
     bool tail_on = false;                    // the last chunk ran in the tail mode
+    int64_t tail_steps = 0;                  // live steps run in the tail mode
     int64_t infected_rows = -1;              // nodes with an infected replicate at the last poll
     double setup_ms = 0.0, finalize_ms = 0.0;
     EventPool setup_ev;  // around the set-up, read once the stream has passed them
@@ -1008,7 +1009,7 @@ void fill_info(const Session &ss, fsg_run_info *info)
 {
     info->steps_run = ss.steps_run;
     info->absorbed = ss.absorbed ? 1 : 0;
-    info->reserved = 0;
+    info->tail_steps = (int32_t)std::min<int64_t>(ss.tail_steps, INT32_MAX);
     info->step_kernel_ms = ss.kernel_ms;
     info->step_launches = ss.timed_steps;
     info->setup_ms = ss.setup_ms;
@@ -1148,6 +1149,7 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 ss.absorbed = true;
                 break;
             }
+        if (ss.tail_on) ss.tail_steps += ss.steps_run - t;
         t += c;
     }
     return FSG_OK;
@@ -1801,7 +1803,7 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
             if (infos) {
                 infos[i].steps_run = steps_run[(size_t)i];
                 infos[i].absorbed = absorbed[(size_t)i];
-                infos[i].reserved = 0;
+                infos[i].tail_steps = 0;
                 infos[i].step_kernel_ms = 0.0;
                 infos[i].step_launches = 0;
                 infos[i].setup_ms = 0.0;

@@ -490,7 +490,7 @@ int fsg_whk(const fsg_graph *g, float eps, float mu, int64_t max_steps, int64_t 
     if (info) {
         info->steps_run = t;
         info->absorbed = converged ? 1 : 0;
-        info->reserved = 0;
+        info->tail_steps = 0;
         info->step_kernel_ms = kernel_ms;
         info->step_launches = launches;
         info->setup_ms = 0.0;

@@ -40,7 +40,7 @@ class fsg_params(ctypes.Structure):
 
 class fsg_run_info(ctypes.Structure):
     _fields_ = [("steps_run", ctypes.c_int64), ("absorbed", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("step_kernel_ms", ctypes.c_double),
+                ("tail_steps", ctypes.c_int32), ("step_kernel_ms", ctypes.c_double),
                 ("step_launches", ctypes.c_int64), ("setup_ms", ctypes.c_double),
                 ("finalize_ms", ctypes.c_double), ("philox_calls", ctypes.c_int64)]
 
