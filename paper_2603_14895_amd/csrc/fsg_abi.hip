@@ -415,9 +415,9 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
     s->wide = (u.options & FSG_OPT_WIDE_OFFSETS) != 0;
     s->count = (u.options & FSG_OPT_COUNT_DRAWS) != 0;
     s->reuse = (u.options & FSG_OPT_REUSE_WORKSPACE) != 0;
-    // the tail mode: SI, SIS, SIR (no latent plane) with at most 16 words,
-    // where no word flags are kept
-    s->tail = (prm->model == FSG_SI || prm->model == FSG_SIS || prm->model == FSG_SIR) && W <= 16 &&
+    // the tail mode: SI, SIS, SIR (no latent plane) and LT
+    s->tail = (prm->model == FSG_SI || prm->model == FSG_SIS || prm->model == FSG_SIR ||
+               prm->model == FSG_LT) &&
               !(u.options & FSG_OPT_TAIL_OFF);
     s->tail_always = s->tail && (u.options & FSG_OPT_TAIL_ALWAYS) != 0;
     return FSG_OK;
@@ -1063,9 +1063,14 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                                          (ss.infected_rows >= 0 && (double)ss.infected_rows * deg <= n * kTailFactor));
             a.ibm_words = (int32_t)((jb.n + 31) / 32);
             uint32_t *cand = jb.ibm + 4 * (size_t)a.ibm_words;
-            if (want && !ss.tail_on)
-                HIP_TRY(launch_mark_rows(jb.front(t), jb.front(t + 1), jb.ibm, cand, a.ibm_words,
-                                         jb.n, jb.L.W, (uint32_t)(t + 1), st));
+            if (want && !ss.tail_on) {
+                if (kind == kKindLT)
+                    HIP_TRY(launch_mark_gained(a.stamp, jb.ibm, cand, a.ibm_words, jb.n,
+                                               (uint32_t)(t + 1), st));
+                else
+                    HIP_TRY(launch_mark_rows(jb.front(t), jb.front(t + 1), jb.ibm, cand, a.ibm_words,
+                                             jb.n, jb.L.W, (uint32_t)(t + 1), st));
+            }
             ss.tail_on = want;
             a.ibm = want ? jb.ibm : nullptr;
             a.cand = want ? cand : nullptr;
@@ -1119,8 +1124,11 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 HIP_TRY(launch_tally(f, st));
             }
         }
-        if (jb.tail) {  // nodes with an infected replicate after the chunk
-            HIP_TRY(launch_count_rows(jb.front(t + c), jb.n, jb.L.W, jb.icount, st));
+        if (jb.tail) {  // nodes with an infected replicate (LT: a new activation) after the chunk
+            if (kind == kKindLT)
+                HIP_TRY(launch_count_stamped(a.stamp, jb.n, (uint32_t)(t + c), jb.icount, st));
+            else
+                HIP_TRY(launch_count_rows(jb.front(t + c), jb.n, jb.L.W, jb.icount, st));
             HIP_TRY(hipMemcpyAsync(htail.data(), jb.icount, 8, hipMemcpyDeviceToHost, st));
         }
         HIP_TRY(hipMemcpyAsync(hflags.data(), flags, (size_t)ring * 4, hipMemcpyDeviceToHost, st));

@@ -90,9 +90,10 @@ struct StepArgs {
     // which no one writes during step t.  Seeds: 0 in array 0.  Null for
     // the other models.
     uint32_t *stamp;
-    // SI / SIS / SIR late in a run (the tail mode): four bitmaps of ibm_words
-    // words, bitmap t % 4 marking the nodes with an infected replicate after
-    // step t, and two candidate bitmaps: before step t the nodes of bitmap
+    // SI / SIS / SIR and LT late in a run (the tail mode): four bitmaps of
+    // ibm_words words, bitmap t % 4 marking the nodes with an infected
+    // replicate after step t (LT: with a new activation at step t), and two
+    // candidate bitmaps: before step t the nodes of bitmap
     // t-1 and their out-neighbours (optr / oarc) are marked in candidate
     // bitmap t % 2.  Step t reads bitmap t-2 and candidate bitmap t % 2, sets
     // bits in bitmap t and clears bitmap t+1 and candidate bitmap (t+1) % 2;
@@ -213,6 +214,12 @@ hipError_t launch_stamp_seeds(uint32_t *stamp, const int32_t *seeds, int64_t ns,
 // with a nonzero word in a plane.
 hipError_t launch_mark_rows(const uint64_t *cur, const uint64_t *old, uint32_t *ibm, uint32_t *cand,
                             int32_t ibm_words, int64_t n, int64_t W, uint32_t t, hipStream_t s);
+// LT: the bitmaps from the activation stamps, and the nodes with a new
+// activation at step t.
+hipError_t launch_mark_gained(const uint32_t *stamp, uint32_t *ibm, uint32_t *cand, int32_t ibm_words,
+                              int64_t n, uint32_t t, hipStream_t s);
+hipError_t launch_count_stamped(const uint32_t *stamp, int64_t n, uint32_t t,
+                                unsigned long long *count, hipStream_t s);
 // Candidate rows of tail-mode step a.step (one wave per infected node).
 hipError_t launch_tail_expand(const StepArgs &a, hipStream_t s);
 hipError_t launch_count_rows(const uint64_t *plane, int64_t n, int64_t W, unsigned long long *count,

@@ -862,11 +862,13 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
         // t-1 has the counts it was last decided on and cannot activate; it
         // takes the copy pass without counting (earlier, nearly every row
         // has such a neighbour and the test would only add loads)
+        // tail mode (SI family, LT): a row that is not a candidate -- itself
+        // and its in-neighbours without an infected replicate (SI family) or
+        // without a new activation (LT) after step t-1 -- cannot change at
+        // step t
+        const bool tail_test = TAIL && (KIND == kKindEpidemic || KIND == kKindLT) && a.ibm != nullptr;
         const bool fresh_test = KIND == kKindLT && a.stamp != nullptr && wm.compact &&
-                                wm.count * 2 <= a.W;
-        // SI family in the tail mode: a row with no infected replicate and
-        // no infected in-neighbour at t-1 cannot change at step t
-        const bool tail_test = TAIL && KIND == kKindEpidemic && a.ibm != nullptr;
+                                wm.count * 2 <= a.W && !tail_test;
         const uint32_t *cand = tail_test ? a.cand + (size_t)(a.step & 1u) * a.ibm_words : nullptr;
         const uint32_t *inf2 = tail_test ? a.ibm + (size_t)((a.step - 2u) & 3u) * a.ibm_words : nullptr;
         auto marked = [](const uint32_t *bm, int u) { return (bm[u >> 5] >> (u & 31)) & 1u; };
@@ -885,10 +887,11 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
             if (tail_test) {
                 if (act && !marked(cand, v)) {
                     // left out: its state after step t is its state after
-                    // t-1, no infected replicate; the buffer step t writes
-                    // holds the state after t-2, nonzero only if the node
-                    // had an infected replicate then
-                    if (marked(inf2, v))
+                    // t-1.  The buffer step t writes holds the state after
+                    // t-2: for LT that is the same (no activation at t-1);
+                    // for the SI family it differs only if the node had an
+                    // infected replicate then (none after t-1)
+                    if (KIND == kKindEpidemic && marked(inf2, v))
                         for (int w = lane & (rl - 1); w < a.W; w += rl)
                             a.next[(int64_t)v * a.W + w] = 0ull;
                     act = false;
@@ -910,7 +913,8 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                 row_word<KIND, L>(a, Ge, S, act && ok, v, w, e0, e1, (uint32_t)(e1 - e0), se, -1,
                                   share_e, tl, tl_n, tcode, lm & rowlm, anyw);
                 note_words(a, Ge, w, ok, anyw);
-                // SI family: anyw = an infected replicate in this word after the step
+                // anyw: an infected replicate (SI family) or a new activation
+                // (LT) in this word after the step
                 if (tail_test && anyw) mark_infected(a, v);
                 any |= anyw;
             }
@@ -955,7 +959,7 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
 // cleared) in its tile.  The bitmap words at the tile's ends may hold other
 // tiles' rows, which only makes the test keep a tile it could have left.
 // Every wave of the block reads the same words and gets the same answer.
-__device__ __forceinline__ bool tail_tile_idle(const StepArgs &a, int bid)
+__device__ __forceinline__ bool tail_tile_idle(const StepArgs &a, int bid, bool zero_store)
 {
     const int nwaves = blockDim.x >> 6;
     const int seg_blocks = (a.n_seg + nwaves - 1) / nwaves;
@@ -967,7 +971,7 @@ __device__ __forceinline__ bool tail_tile_idle(const StepArgs &a, int bid)
     const uint32_t *inf2 = a.ibm + (size_t)((a.step - 2u) & 3u) * a.ibm_words;
     bool busy = false;
     for (int i = (t0 >> 5) + (int)(threadIdx.x & 63); i <= ((t1 - 1) >> 5) && !busy; i += 64)
-        busy = (cand[i] | inf2[i]) != 0u;
+        busy = (cand[i] | (zero_store ? inf2[i] : 0u)) != 0u;
     return __ballot(busy) == 0ull;
 }
 
@@ -976,7 +980,7 @@ template <int KIND, int L, bool TAIL = false>
 __global__ void __launch_bounds__(1024) k_step(StepArgs a)
 {
     if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // nothing left to change
-    if (TAIL && KIND == kKindEpidemic && a.ibm != nullptr) {
+    if (TAIL && (KIND == kKindEpidemic || KIND == kKindLT) && a.ibm != nullptr) {
         // the bitmaps step t+1 sets, then whether this block has work
         uint32_t *clr = a.ibm + (size_t)((a.step + 1u) & 3u) * a.ibm_words;
         uint32_t *cclr = a.cand + (size_t)((a.step + 1u) & 1u) * a.ibm_words;
@@ -985,7 +989,7 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
             clr[i] = 0u;
             cclr[i] = 0u;
         }
-        if (tail_tile_idle(a, blockIdx.x)) return;
+        if (tail_tile_idle(a, blockIdx.x, KIND == kKindEpidemic)) return;
     }
     __shared__ uint32_t s_tinf[KIND == kKindEpidemic ? kTinfLds : 1];
     __shared__ uint32_t s_code[kCodeTable];
@@ -1080,6 +1084,7 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
                 const uint32_t indeg = act ? (uint32_t)(a.ptr[v + 1] - a.ptr[v]) : 0u;
                 lt_decide<LC>(a, G, S2, valid, v, ww, idx, act_w, inact, indeg, c, ss, share, false,
                               anyw);
+                if (a.ibm != nullptr && anyw) mark_infected(a, v);  // tail mode
             }
         }
         note_words(a, G, ww, ok, anyw);
@@ -1717,6 +1722,45 @@ __global__ void __launch_bounds__(256) k_tail_expand(StepArgs a)
     }
 }
 
+// The same for LT from its activation stamps: bitmap (t-1) % 4 marks the
+// nodes with a new activation at t-1, bitmap (t-2) % 4 those at t-2.
+__global__ void k_mark_gained(const uint32_t *stamp, uint32_t *ibm, uint32_t *cand,
+                              int32_t ibm_words, int64_t n, uint32_t t)
+{
+    const uint32_t *s1 = stamp + (size_t)((t - 1u) & 1u) * (size_t)n;
+    const uint32_t *s2 = stamp + (size_t)(t & 1u) * (size_t)n;
+    uint32_t *b1 = ibm + (size_t)((t - 1u) & 3u) * ibm_words;
+    uint32_t *b2 = ibm + (size_t)((t - 2u) & 3u) * ibm_words;
+    uint32_t *b0 = ibm + (size_t)(t & 3u) * ibm_words;
+    uint32_t *c0 = cand + (size_t)(t & 1u) * ibm_words;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ibm_words;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t m1 = 0, m2 = 0;
+        for (int j = 0; j < 32; ++j) {
+            const int64_t v = 32 * i + j;
+            if (v >= n) break;
+            m1 |= (s1[v] == t - 1u ? 1u : 0u) << j;
+            m2 |= (s2[v] == t - 2u ? 1u : 0u) << j;
+        }
+        b1[i] = m1;
+        b2[i] = m2;
+        b0[i] = 0u;
+        c0[i] = 0u;
+    }
+}
+
+// Number of LT nodes with a new activation at step t (stamp t in array t & 1).
+__global__ void k_count_stamped(const uint32_t *stamp, int64_t n, uint32_t t, unsigned long long *count)
+{
+    const uint32_t *s = stamp + (size_t)(t & 1u) * (size_t)n;
+    unsigned long long c = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        c += s[v] == t ? 1ull : 0ull;
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
 // Number of nodes with a nonzero word in `plane` (one integer atomic add per
 // wave).
 __global__ void k_count_rows(const uint64_t *plane, int64_t n, int64_t W, unsigned long long *count)
@@ -2068,6 +2112,26 @@ hipError_t launch_mark_rows(const uint64_t *cur, const uint64_t *old, uint32_t *
     return hipGetLastError();
 }
 
+hipError_t launch_mark_gained(const uint32_t *stamp, uint32_t *ibm, uint32_t *cand, int32_t ibm_words,
+                              int64_t n, uint32_t t, hipStream_t s)
+{
+    if (ibm_words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mark_gained, dim3(grid_for(ibm_words, 64)), dim3(64), 0, s, stamp, ibm, cand,
+                       ibm_words, n, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_stamped(const uint32_t *stamp, int64_t n, uint32_t t,
+                                unsigned long long *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill64, dim3(1), dim3(64), 0, s, (uint64_t *)count, (int64_t)1, 0ull);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n <= 0) return e;
+    hipLaunchKernelGGL(k_count_stamped, dim3(std::min<unsigned>(grid_for(n, 256), 2048u)), dim3(256),
+                       0, s, stamp, n, t, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_tail_expand(const StepArgs &a, hipStream_t s)
 {
     // a wave per bitmap word, at most 1024 blocks of four waves
@@ -2211,6 +2275,7 @@ hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_
     if (kind == kKindEpidemic && a.ibm != nullptr)
         return step_kind<kKindEpidemic, true>(a, L, grid, blk, s);
     if (kind == kKindEpidemic) return step_kind<kKindEpidemic, false>(a, L, grid, blk, s);
+    if (a.ibm != nullptr) return step_kind<kKindLT, true>(a, L, grid, blk, s);
     return step_kind<kKindLT, false>(a, L, grid, blk, s);
 }
 

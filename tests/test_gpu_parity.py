@@ -266,21 +266,26 @@ def test_si_family_draw_classes_and_saturated_thresholds():
                       max_steps=6, replicate_offset=off)
 
 
-@pytest.mark.parametrize("model", ["sir", "sis", "si"])
+@pytest.mark.parametrize("model", ["sir", "sis", "si", "lt"])
 def test_si_family_tail_mode(model):
-    """The tail mode (rows with no infected replicate and no infected
-    in-neighbour after step t-1 -- found from the out-arcs of the infected
-    nodes -- are left out of step t) gives the oracle's bits: forced from the second chunk on -- through the epidemic's growth,
-    with chunks of 1 and 3 steps, ragged and full words, edge-split rows and
-    heavy-row segments -- and left to the library's own switch; a session
-    stepped piece by piece in the tail mode ends in the same state."""
+    """The tail mode (a row that is not a candidate -- it and its
+    in-neighbours hold no infected replicate (SI family) or no new activation
+    (LT) after step t-1, found from the out-arcs of the nodes that do -- is
+    left out of step t) gives the oracle's bits: forced from the second chunk
+    on, through the epidemic's growth or the cascade's bulk, with chunks of 1
+    and 3 steps, ragged and full words, word flags (17 to 64 words), edge-split
+    rows and heavy-row segments, and left to the library's own switch; a
+    session stepped piece by piece in the tail mode ends in the same state."""
     from paper_2603_14895_amd import fsg
     gr = W.chung_lu(3000, 10.0, 2.5, 2101)
     gnp = gr.numpy()
     seeds = W.uniform_seeds(gr.n, 40, 2102)
     kw = dict(beta=0.05, gamma=0.2, max_steps=70 if model == "sir" else 25)
+    if model == "lt":
+        kw = dict(max_steps=-1)
     always = fsg.OPT_TAIL_ALWAYS
-    for B in (64, 100, 1024):
+    # 1100 and 3000 replicates keep word flags (17 to 64 words)
+    for B in (64, 100, 1024, 1100, 3000):
         for sched in (dict(options=always, steps_per_sync=1), dict(options=always, steps_per_sync=3),
                       dict(options=always, steps_per_sync=2, row_lanes=4, heavy_threshold=20),
                       dict(steps_per_sync=4), dict(options=fsg.OPT_TAIL_OFF)):
