@@ -625,7 +625,10 @@ def bench_batch(args):
         gr = Wl.build_c3_graph(sp, device="cuda")
         ptr, src = gr.numpy()
         del gr
-        dg = fsg.DeviceGraph(ptr, src, device="cuda:0")
+        # SIR and LT jobs bind the out-adjacency: their tail mode marks candidate
+        # rows from the out-arcs of the nodes that changed
+        dg = fsg.DeviceGraph(ptr, src, device="cuda:0",
+                             out=sp["model"] in ("sir", "lt") and not args.no_out_adjacency)
         seeds = Wl.uniform_seeds(dg.n, sp["n_seeds"], sp["seed_seed"])
         prm = {k: sp[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in sp}
         jobs.append(dict(graph=dg, model=sp["model"], B=sp["B"], seeds=seeds, rng_key=sp["key"],
@@ -667,10 +670,13 @@ def bench_batch(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     steps_run = [int(x.steps_run) for x in infos]
-    abytes = sum(algorithmic_bytes_per_step(j["model"], h[0].size - 1, h[1].size, j["B"], False) * x.steps_run
-                 for h, j, x in zip(host, jobs, infos))
+    # every word of a job counted at each of its dense steps; steps in the
+    # tail mode leave out the rows that cannot change and count as nothing
+    abytes = sum(algorithmic_bytes_per_step(j["model"], h[0].size - 1, h[1].size, j["B"], False)
+                 * (x.steps_run - x.tail_steps) for h, j, x in zip(host, jobs, infos))
     achieved = abytes * args.steps / (dev_ms / 1e3) / 1e9
-    log(f"[bench] {args.steps} batch runs in {dt:.3f}s ({dev_ms / args.steps:.1f} ms device each)")
+    log(f"[bench] {args.steps} batch runs in {dt:.3f}s ({dev_ms / args.steps:.1f} ms device each); "
+        f"tail-mode steps {sum(int(x.tail_steps) for x in infos)} of {sum(steps_run)}")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_batch(specs, jobs, host, args.cpu_seconds)
@@ -681,6 +687,7 @@ def bench_batch(args):
         "warmup": args.warmup, "ms_per_step": round(dt * 1000.0 / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64 bit-packed replicates / u32 integer draws", "data": "synthetic",
+        "tail_mode_steps": [int(x.tail_steps) for x in infos],
         "config": {"workload": "c3_mixed_batch_64_jobs", "jobs": len(jobs), "nnz_total": int(tot_nnz),
                    "B": [j["B"] for j in jobs], "steps_run": steps_run,
                    "autotuned": bool(args.autotune), "parallelism": "single GPU"},

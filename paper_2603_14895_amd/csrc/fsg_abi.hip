@@ -1629,6 +1629,8 @@ int fsg_batch_plan(const fsg_job *jobs, int32_t n_jobs, int32_t steps_per_sync, 
         off = align256(off + (n + 1) * 4 * 2 + n * 4 * 2);  // item_off, comb_off, code, max_step
         off = align256(off + 16);                           // queue[2], cur_step
         off = align256(off + n * ring * 4);                 // flag rings
+        off = align256(off + (n + 2 * (n + 1)) * 4);        // tail_on, word_off, row_off
+        off = align256(off + n * 8);                        // per-job counts (tail mode)
         pl->total = off;
         *ws_bytes = off;
         *out = pl.release();
@@ -1677,12 +1679,19 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
         uint32_t *d_step = d_queue + 2;
         q += align256(16);
         uint32_t *d_flags = (uint32_t *)q;
+        q += align256((size_t)n * ring * 4);
+        int32_t *d_tail_on = (int32_t *)q;
+        int32_t *d_word_off = d_tail_on + n;
+        int32_t *d_row_off = d_word_off + (n + 1);
+        q += align256((size_t)(n + 2 * (n + 1)) * 4);
+        unsigned long long *d_counts = (unsigned long long *)q;
 
         std::vector<Job> jb((size_t)n);
         std::vector<StepArgs> h_jobs((size_t)n);
         std::vector<int32_t> item_off((size_t)n + 1, 0), comb_off((size_t)n + 1, 0),
-            code((size_t)n), max_step((size_t)n);
-        bool any_heavy = false;
+            code((size_t)n), max_step((size_t)n), word_off((size_t)n + 1, 0),
+            row_off((size_t)n + 1, 0), tail_on((size_t)n, 0);
+        bool any_heavy = false, any_tail = false;
         for (int i = 0; i < n; ++i) {
             const fsg_job &j = pl->jobs[(size_t)i];
             fsg_graph *g = const_cast<fsg_graph *>(j.g);
@@ -1691,7 +1700,15 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
                                base + pl->job_off[(size_t)i], d_flags + (size_t)i * ring, st,
                                &jb[(size_t)i]);
             if (rc) return rc;
-            const StepArgs &a = jb[(size_t)i].a;
+            StepArgs &a = jb[(size_t)i].a;
+            if (jb[(size_t)i].tail) {  // the tail mode's bitmaps (used while tail_on)
+                a.ibm_words = (int32_t)((a.n + 31) / 32);
+                a.ibm = jb[(size_t)i].ibm;
+                a.cand = jb[(size_t)i].ibm + 4 * (size_t)a.ibm_words;
+                any_tail = true;
+            }
+            word_off[(size_t)i + 1] = word_off[(size_t)i] + (jb[(size_t)i].tail ? a.ibm_words : 0);
+            row_off[(size_t)i + 1] = row_off[(size_t)i] + (jb[(size_t)i].tail ? a.n : 0);
             h_jobs[(size_t)i] = a;  // prev/next hold planes 0 and 1
             item_off[(size_t)i + 1] = item_off[(size_t)i] + step_blocks(a, kBatchBlock);
             const int rows_per_combine = (kBatchBlock / 64) * combine_rows_per_wave(a.lgG);
@@ -1706,6 +1723,9 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
         HIP_TRY(hipMemcpyAsync(d_comb_off, comb_off.data(), comb_off.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(d_code, code.data(), code.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(d_max_step, max_step.data(), max_step.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_word_off, word_off.data(), word_off.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_row_off, row_off.data(), row_off.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_fill32((uint32_t *)d_tail_on, n, 0u, st));
         HIP_TRY(launch_fill32(d_queue, 2, 0u, st));
         HIP_TRY(launch_fill32(d_step, 1, 1u, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -1720,6 +1740,9 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
         c.ring = ring;
         c.queue = d_queue;
         c.cur_step = d_step;
+        c.tail_on = d_tail_on;
+        c.word_off = d_word_off;
+        c.row_off = d_row_off;
         int dev = 0, ncu = 0;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1742,6 +1765,16 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
         HIP_TRY(hipStreamCreateWithFlags(&cap.s, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < pl->sync; ++i) {
+            if (any_tail) {
+                hipError_t e0 = launch_batch_expand(c, cap.s);
+                if (e0 != hipSuccess) {
+                    hipGraph_t dummy = nullptr;
+                    (void)hipStreamEndCapture(cap.s, &dummy);
+                    if (dummy) (void)hipGraphDestroy(dummy);
+                    return fail(FSG_EDEVICE, std::string("batched launch capture failed: ") +
+                                                 hipGetErrorString(e0));
+                }
+            }
             hipError_t e1 = launch_batch_step(c, grid, cap.s);
             hipError_t e2 = any_heavy ? launch_batch_combine(c, cgrid, cap.s) : hipSuccess;
             hipError_t e3 = launch_batch_advance(c, cap.s);
@@ -1773,12 +1806,52 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
         HIP_TRY(ev.init(2));
         double kernel_ms = 0.0;
         int64_t t0 = 0;
+        // tail mode per job: nodes with an infected replicate (LT: a new
+        // activation) at the last poll, -1 before the first
+        std::vector<int64_t> icount((size_t)n, -1), tail_steps((size_t)n, 0);
+        std::vector<unsigned long long> hcount((size_t)n, 0);
         while (remaining > 0) {
+            if (any_tail) {
+                bool changed = false;
+                for (int i = 0; i < n; ++i) {
+                    const Job &J = jb[(size_t)i];
+                    if (!J.tail || done[(size_t)i]) continue;
+                    const double nn = (double)J.n, deg = (double)J.a.nnz / std::max(nn, 1.0);
+                    const bool want = t0 >= 1 && (pl->sched[(size_t)i].tail_always ||
+                                                  (icount[(size_t)i] >= 0 &&
+                                                   (double)icount[(size_t)i] * deg <= nn * kTailFactor));
+                    if (want && !tail_on[(size_t)i]) {  // the bitmaps of steps t0 and t0-1
+                        const StepArgs &a = h_jobs[(size_t)i];
+                        const uint32_t t = (uint32_t)(t0 + 1);
+                        if (J.kind == kKindLT) {
+                            HIP_TRY(launch_mark_gained(a.stamp, a.ibm, a.cand, a.ibm_words, a.n, t, st));
+                        } else {
+                            // base planes: prev holds odd steps' inputs (state of even steps)
+                            const uint64_t *p0 = a.prev, *p1 = a.next;
+                            const uint64_t *cur = (t & 1u) ? p0 : p1, *old = (t & 1u) ? p1 : p0;
+                            HIP_TRY(launch_mark_rows(cur, old, a.ibm, a.cand, a.ibm_words, a.n, a.W, t,
+                                                     st));
+                        }
+                    }
+                    if (want != (tail_on[(size_t)i] != 0)) changed = true;
+                    tail_on[(size_t)i] = want ? 1 : 0;
+                }
+                if (changed)
+                    HIP_TRY(hipMemcpyAsync(d_tail_on, tail_on.data(), (size_t)n * 4,
+                                           hipMemcpyHostToDevice, st));
+            }
             HIP_TRY(hipEventRecord(ev.e[0], st));
             HIP_TRY(hipGraphLaunch(cap.e, st));
             HIP_TRY(hipEventRecord(ev.e[1], st));
+            if (any_tail) {
+                HIP_TRY(launch_fill64((uint64_t *)d_counts, n, 0ull, st));
+                HIP_TRY(launch_batch_count(c, (uint32_t)(t0 + pl->sync), d_counts, st));
+                HIP_TRY(hipMemcpyAsync(hcount.data(), d_counts, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+            }
             HIP_TRY(hipMemcpyAsync(hf.data(), d_flags, hf.size() * 4, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
+            if (any_tail)
+                for (int i = 0; i < n; ++i) icount[(size_t)i] = (int64_t)hcount[(size_t)i];
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
             kernel_ms += ms;
@@ -1799,6 +1872,8 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
                         break;
                     }
                 }
+                if (tail_on[(size_t)i])
+                    tail_steps[(size_t)i] += (done[(size_t)i] ? steps_run[(size_t)i] : t0 + pl->sync) - t0;
                 if (done[(size_t)i]) --remaining;
             }
             t0 += pl->sync;
@@ -1811,7 +1886,7 @@ int fsg_batch_run(fsg_plan *pl, void *dev_ws, size_t ws_bytes, fsg_run_info *inf
             if (infos) {
                 infos[i].steps_run = steps_run[(size_t)i];
                 infos[i].absorbed = absorbed[(size_t)i];
-                infos[i].tail_steps = 0;
+                infos[i].tail_steps = (int32_t)std::min<int64_t>(tail_steps[(size_t)i], INT32_MAX);
                 infos[i].step_kernel_ms = 0.0;
                 infos[i].step_launches = 0;
                 infos[i].setup_ms = 0.0;

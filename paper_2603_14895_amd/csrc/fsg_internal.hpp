@@ -198,6 +198,14 @@ struct BatchCtl {
     int32_t ring;
     uint32_t *queue;          // [2] dequeue counters (step items, combine items)
     uint32_t *cur_step;       // the step the next launch executes
+    // tail mode (SI family, LT; jobs whose graph has its out-adjacency):
+    // tail_on[j] != 0 while job j runs in it (set by the host per chunk; the
+    // job's StepArgs carry its bitmaps, which job_at_step drops otherwise);
+    // word_off: prefix over the jobs of their bitmap words (0 for jobs that
+    // cannot take the mode), row_off: prefix of their node counts
+    const int32_t *tail_on;   // [n_jobs]
+    const int32_t *word_off;  // [n_jobs + 1]
+    const int32_t *row_off;   // [n_jobs + 1]
 };
 
 // launchers (fsg_kernels.hip); return the hipError_t of the launch
@@ -253,6 +261,11 @@ int step_blocks(const StepArgs &a, int block);  // blocks of one job's pull step
 hipError_t launch_batch_step(const BatchCtl &c, int grid, hipStream_t s);
 hipError_t launch_batch_combine(const BatchCtl &c, int grid, hipStream_t s);
 hipError_t launch_batch_advance(const BatchCtl &c, hipStream_t s);
+// tail mode of the batched launch: candidates of the next step of every job
+// in the mode (before each batched step), and per job the nodes with an
+// infected replicate / a new activation after step t into counts[j]
+hipError_t launch_batch_expand(const BatchCtl &c, hipStream_t s);
+hipError_t launch_batch_count(const BatchCtl &c, uint32_t t, unsigned long long *counts, hipStream_t s);
 constexpr int kBatchBlock = 256;  // block size of the batched kernels
 // Waves per SIMD the batched step kernel is compiled for.  One kernel holds every
 // (model, counter width) case, so unbounded it takes the register count of the

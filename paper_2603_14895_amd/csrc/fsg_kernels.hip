@@ -866,12 +866,9 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
         // and its in-neighbours without an infected replicate (SI family) or
         // without a new activation (LT) after step t-1 -- cannot change at
         // step t
-        const bool tail_test = TAIL && (KIND == kKindEpidemic || KIND == kKindLT) && a.ibm != nullptr;
+        constexpr bool kTailKind = TAIL && (KIND == kKindEpidemic || KIND == kKindLT);
         const bool fresh_test = KIND == kKindLT && a.stamp != nullptr && wm.compact &&
-                                wm.count * 2 <= a.W && !tail_test;
-        const uint32_t *cand = tail_test ? a.cand + (size_t)(a.step & 1u) * a.ibm_words : nullptr;
-        const uint32_t *inf2 = tail_test ? a.ibm + (size_t)((a.step - 2u) & 3u) * a.ibm_words : nullptr;
-        auto marked = [](const uint32_t *bm, int u) { return (bm[u >> 5] >> (u & 31)) & 1u; };
+                                wm.count * 2 <= a.W && !(kTailKind && a.ibm != nullptr);
         const int rl = 1 << (lgGe + a.lgS);  // lanes of a row
         const uint64_t rowmask = (rl == 64 ? ~0ull : ((1ull << rl) - 1ull)) << (slote * rl);
         for (int rb = t0 + wave * rpwe; rb < t1; rb += nwaves * rpwe) {
@@ -884,16 +881,20 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                 if (e1 - e0 > a.heavy) act = false;
             }
             uint64_t rowlm = ~0ull;
-            if (tail_test) {
-                if (act && !marked(cand, v)) {
+            if (kTailKind && a.ibm != nullptr && act) {
+                const uint32_t *cand = a.cand + (size_t)(a.step & 1u) * a.ibm_words;
+                if (!((cand[v >> 5] >> (v & 31)) & 1u)) {
                     // left out: its state after step t is its state after
                     // t-1.  The buffer step t writes holds the state after
                     // t-2: for LT that is the same (no activation at t-1);
                     // for the SI family it differs only if the node had an
                     // infected replicate then (none after t-1)
-                    if (KIND == kKindEpidemic && marked(inf2, v))
-                        for (int w = lane & (rl - 1); w < a.W; w += rl)
-                            a.next[(int64_t)v * a.W + w] = 0ull;
+                    if (KIND == kKindEpidemic) {
+                        const uint32_t *inf2 = a.ibm + (size_t)((a.step - 2u) & 3u) * a.ibm_words;
+                        if ((inf2[v >> 5] >> (v & 31)) & 1u)
+                            for (int w = lane & (rl - 1); w < a.W; w += rl)
+                                a.next[(int64_t)v * a.W + w] = 0ull;
+                    }
                     act = false;
                 }
             }
@@ -915,7 +916,7 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                 note_words(a, Ge, w, ok, anyw);
                 // anyw: an infected replicate (SI family) or a new activation
                 // (LT) in this word after the step
-                if (tail_test && anyw) mark_infected(a, v);
+                if (kTailKind && anyw && a.ibm != nullptr) mark_infected(a, v);
                 any |= anyw;
             }
         }
@@ -1533,6 +1534,10 @@ __device__ __forceinline__ StepArgs job_at_step(const BatchCtl &c, int j, uint32
     a.prev = (t & 1u) ? p0 : p1;   // state of step t-1
     a.next = (t & 1u) ? p1 : const_cast<uint64_t *>(p0);
     a.step = t;
+    if (c.tail_on[j] == 0) {  // not in the tail mode this chunk
+        a.ibm = nullptr;
+        a.cand = nullptr;
+    }
     return a;
 }
 
@@ -1561,6 +1566,9 @@ k_batch_step(BatchCtl c)
         const StepArgs a = job_at_step(c, j, t);
         if (!job_live(c, a, j, t)) continue;
         const int local = item - s_off[j];
+        // tail mode: a tile with no candidate row leaves at once (every
+        // thread of the block reads the same words)
+        if (a.ibm != nullptr && tail_tile_idle(a, local, c.code[j] / 32 == kKindEpidemic)) continue;
         if (c.code[j] / 32 == kKindEpidemic) {  // block-uniform
             if (threadIdx.x < kCodeTable) s_code[threadIdx.x] = code_threshold(a, threadIdx.x);
             __syncthreads();
@@ -1568,16 +1576,16 @@ k_batch_step(BatchCtl c)
         bool any = false;
         switch (c.code[j]) {
         case kKindIC * 32 + 1: step_block<kKindIC, 1>(a, local, nullptr, 0, s_code, any); break;
-        case kKindEpidemic * 32 + 2: step_block<kKindEpidemic, 2>(a, local, nullptr, 0, s_code, any); break;
-        case kKindEpidemic * 32 + 4: step_block<kKindEpidemic, 4>(a, local, nullptr, 0, s_code, any); break;
-        case kKindEpidemic * 32 + 8: step_block<kKindEpidemic, 8>(a, local, nullptr, 0, s_code, any); break;
-        case kKindEpidemic * 32 + 12: step_block<kKindEpidemic, 12>(a, local, nullptr, 0, s_code, any); break;
-        case kKindEpidemic * 32 + 16: step_block<kKindEpidemic, 16>(a, local, nullptr, 0, s_code, any); break;
-        case kKindLT * 32 + 2: step_block<kKindLT, 2>(a, local, nullptr, 0, s_code, any); break;
-        case kKindLT * 32 + 4: step_block<kKindLT, 4>(a, local, nullptr, 0, s_code, any); break;
-        case kKindLT * 32 + 8: step_block<kKindLT, 8>(a, local, nullptr, 0, s_code, any); break;
-        case kKindLT * 32 + 12: step_block<kKindLT, 12>(a, local, nullptr, 0, s_code, any); break;
-        case kKindLT * 32 + 16: step_block<kKindLT, 16>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 2: step_block<kKindEpidemic, 2, true>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 4: step_block<kKindEpidemic, 4, true>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 8: step_block<kKindEpidemic, 8, true>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 12: step_block<kKindEpidemic, 12, true>(a, local, nullptr, 0, s_code, any); break;
+        case kKindEpidemic * 32 + 16: step_block<kKindEpidemic, 16, true>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 2: step_block<kKindLT, 2, true>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 4: step_block<kKindLT, 4, true>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 8: step_block<kKindLT, 8, true>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 12: step_block<kKindLT, 12, true>(a, local, nullptr, 0, s_code, any); break;
+        case kKindLT * 32 + 16: step_block<kKindLT, 16, true>(a, local, nullptr, 0, s_code, any); break;
         default: break;
         }
         if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[t % (uint32_t)a.ring] = 1u;
@@ -1623,6 +1631,79 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_combine(BatchCtl c)
         default: break;
         }
         if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[t % (uint32_t)a.ring] = 1u;
+    }
+}
+
+// Tail mode of the batched launch, before batched step t: for every job in
+// the mode, the bitmaps step t+1 sets are cleared and the nodes of bitmap
+// t-1 and their out-neighbours are marked in candidate bitmap t % 2 (a wave
+// per bitmap word, over the words of all such jobs).
+__global__ void __launch_bounds__(256) k_batch_expand(BatchCtl c)
+{
+    const uint32_t t = *c.cur_step;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int total = c.word_off[c.n_jobs];
+    for (int64_t item = wave; item < total; item += nwave) {
+        const int j = find_job(c.word_off, c.n_jobs, (int)item);
+        if (c.tail_on[j] == 0) continue;
+        const StepArgs a = job_at_step(c, j, t);
+        if (!job_live(c, a, j, t)) continue;
+        const int i = (int)item - c.word_off[j];
+        if (lane == 0) {
+            a.ibm[(size_t)((t + 1u) & 3u) * a.ibm_words + i] = 0u;
+            a.cand[(size_t)((t + 1u) & 1u) * a.ibm_words + i] = 0u;
+        }
+        uint32_t m = a.ibm[(size_t)((t - 1u) & 3u) * a.ibm_words + i];
+        if (m == 0u) continue;
+        uint32_t *cand = a.cand + (size_t)(t & 1u) * a.ibm_words;
+        if (lane == 0) atomicOr(&cand[i], m);
+        while (m) {
+            const int u = 32 * i + __builtin_ctz(m);
+            m &= m - 1u;
+            const int o1 = a.optr[u + 1];
+            for (int e = a.optr[u] + lane; e < o1; e += 64) {
+                const int v = a.oarc[e].x;
+                atomicOr(&cand[v >> 5], 1u << (v & 31));
+            }
+        }
+    }
+}
+
+// Per job that can take the tail mode, the nodes with an infected replicate
+// (SI family: a nonzero word of the state plane after step t) or a new
+// activation at step t (LT: activation stamp t) into counts[j] (zeroed by
+// the caller).
+__global__ void k_batch_count(BatchCtl c, uint32_t t, unsigned long long *counts)
+{
+    const int total = c.row_off[c.n_jobs];
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every lane of a wave runs the same number of rounds (ballots below)
+    for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); r0 < total; r0 += stride) {
+        const int64_t r = r0 + lane;
+        bool hit = false;
+        int j = 0;
+        if (r < total) {
+            j = find_job(c.row_off, c.n_jobs, (int)r);
+            const int v = (int)r - c.row_off[j];
+            const StepArgs &a = c.jobs[j];
+            if (c.code[j] / 32 == kKindLT) {
+                hit = a.stamp[(size_t)(t & 1u) * (size_t)a.n + (size_t)v] == t;
+            } else {
+                const uint64_t *pl = (t & 1u) ? a.next : a.prev;  // state after step t
+                uint64_t x = 0;
+                for (int w = 0; w < a.W; ++w) x |= pl[(int64_t)v * a.W + w];
+                hit = x != 0ull;
+            }
+        }
+        // the rows of a wave belong to one job or to two neighbouring ones:
+        // one add for the first lane's job, one per hit of another
+        const int j0 = __shfl(j, 0, 64);
+        const uint64_t m = __ballot(hit && j == j0);
+        if (lane == 0 && m != 0ull) atomicAdd(&counts[j0], (unsigned long long)__popcll(m));
+        if (hit && j != j0) atomicAdd(&counts[j], 1ull);
     }
 }
 
@@ -2344,6 +2425,18 @@ hipError_t launch_batch_step(const BatchCtl &c, int grid, hipStream_t s)
 hipError_t launch_batch_combine(const BatchCtl &c, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_combine, dim3((unsigned)grid), dim3(kBatchBlock), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_expand(const BatchCtl &c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_expand, dim3(1024), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_count(const BatchCtl &c, uint32_t t, unsigned long long *counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_count, dim3(2048), dim3(256), 0, s, c, t, counts);
     return hipGetLastError();
 }
 

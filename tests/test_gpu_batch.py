@@ -86,6 +86,36 @@ def test_batch_equals_solo_and_oracle():
         batch.close()
 
 
+def test_batch_tail_mode():
+    """The tail mode in the batched launch: the mixed jobs on graphs with
+    their out-adjacency bound, the mode forced on from the second chunk for
+    every job that can take it (SI, SIS, SIR, LT), then left to the library's
+    per-job switch; every job equals the oracle, with chunks of 3 and 16."""
+    from paper_2603_14895_amd import fsg
+    jobs = _mixed_jobs()
+    dgs = [fsg.DeviceGraph(*j["gr"].numpy(), out=True) for j in jobs]
+    for forced, spsync in ((True, 3), (True, 16), (False, 3)):
+        bj = []
+        for dg, j in zip(dgs, jobs):
+            d = dict(graph=dg, **{k: v for k, v in j.items() if k != "gr"})
+            if forced:
+                d["schedule"] = dict(j["schedule"] or {}, options=fsg.OPT_TAIL_ALWAYS)
+            bj.append(d)
+        batch = fsg.Batch(bj, steps_per_sync=spsync)
+        infos, total_ms = batch.run()
+        log(f"[batch] tail forced={forced} sync {spsync}: {total_ms:.2f} ms, tail steps "
+            f"{[int(x.tail_steps) for x in infos]}")
+        if forced:
+            assert any(int(x.tail_steps) > 0 for x in infos)
+        for i, j in enumerate(jobs):
+            got = (batch.states[i].cpu().numpy(), batch.counts[i].cpu().numpy().astype(np.uint32),
+                   int(infos[i].steps_run), int(infos[i].absorbed))
+            ref = oracle_run(j["gr"].numpy(), j["model"], j["seeds"], j["B"], j["rng_key"],
+                             replicate_offset=j["replicate_offset"], **_params(j))
+            assert_same(got, ref, f"tail job {i} ({j['model']}) forced={forced} sync={spsync}")
+        batch.close()
+
+
 def test_batch_mixed_workload_small():
     """A reduced instance of the mixed batched workload (log-uniform sizes,
     B and seed-set sizes; IC / SIR / LT), every job checked on sampled
