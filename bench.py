@@ -277,7 +277,8 @@ def main():
     ap.add_argument("--no-frontier", action="store_true",
                     help="IC workloads: skip the per-step count of live frontier arcs")
     ap.add_argument("--no-out-adjacency", action="store_true",
-                    help="IC with B <= 64: do not bind the out-adjacency (streaming step only)")
+                    help="do not bind the out-adjacency (IC with B <= 64: streaming step only; "
+                         "no tail mode)")
     ap.add_argument("--stream-reference", type=int, default=5,
                     help="frontier-driven IC: also time this many runs of the streaming step")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -326,12 +327,10 @@ def main():
         f"(generated in {time.perf_counter() - t0:.1f}s)")
     del gr
     c["graph"] = None
-    # IC with one word per node: the graph's out-adjacency too, so the
-    # frontier-driven step can push over the out-arcs of small frontiers
-    # the out-adjacency: the frontier-driven IC step, and the tail mode of the
-    # SI family (candidate rows from the out-arcs of the infected nodes)
-    want_out = ((c["model"] == "ic" and c["B"] <= 64) or c["model"] in ("si", "sis", "sir")) \
-        and not args.no_out_adjacency
+    # the out-adjacency: the frontier-driven IC step (one word per node), and
+    # the tail mode of the pull step (candidate rows from the out-arcs of the
+    # infected or newly activated nodes)
+    want_out = c["model"] in ("ic", "si", "sis", "sir", "lt") and not args.no_out_adjacency
     t_b = time.perf_counter()
     dg = fsg.DeviceGraph(ptr, src, device="cuda:0", out=want_out)
     log(f"[bench] graph bound{' with its out-adjacency' if want_out else ''} in "
@@ -625,10 +624,9 @@ def bench_batch(args):
         gr = Wl.build_c3_graph(sp, device="cuda")
         ptr, src = gr.numpy()
         del gr
-        # SIR and LT jobs bind the out-adjacency: their tail mode marks candidate
-        # rows from the out-arcs of the nodes that changed
-        dg = fsg.DeviceGraph(ptr, src, device="cuda:0",
-                             out=sp["model"] in ("sir", "lt") and not args.no_out_adjacency)
+        # every job binds the out-adjacency: the tail mode marks candidate rows
+        # from the out-arcs of the nodes that changed
+        dg = fsg.DeviceGraph(ptr, src, device="cuda:0", out=not args.no_out_adjacency)
         seeds = Wl.uniform_seeds(dg.n, sp["n_seeds"], sp["seed_seed"])
         prm = {k: sp[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in sp}
         jobs.append(dict(graph=dg, model=sp["model"], B=sp["B"], seeds=seeds, rng_key=sp["key"],

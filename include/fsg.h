@@ -117,8 +117,8 @@ typedef struct {
  * set-up operation (table uploads, plane fills, seeding; host work between
  * them included); finalize_ms: the device time of the kernel that writes
  * final_states and infected_counts (fsg_simulate only); else 0.
- * tail_steps: steps run in the tail mode of the SI family (see
- * FSG_OPT_TAIL_OFF), which leave out the rows that cannot change; else 0.
+ * tail_steps: steps run in the tail mode (see FSG_OPT_TAIL_OFF), which
+ * leave out the rows that cannot change; else 0.
  * philox_calls: with FSG_OPT_COUNT_DRAWS, the Philox4x32-10 calls of the
  * SI-family decisions over the steps run (each call gives the draws of four
  * consecutive replicates of one node and step); else 0. */
@@ -184,19 +184,21 @@ typedef struct {
  *                  error, or another layout in the same memory, still gets
  *                  them cleared).  Other runs ignore the option; results are
  *                  the same either way.
- *                  Tail mode (SI, SIS, SIR with B <= 1024, fsg_simulate and
- *                  sessions, on a graph with its out-adjacency bound): once
- *                  few nodes hold an infected replicate, a row whose
- *                  in-neighbours and itself hold none after step t-1 cannot
- *                  change at step t and is left out of it; before each step
- *                  the out-arcs of those nodes mark the rows that are not
- *                  (one more small kernel a step, timed with the step
- *                  kernel).  The library counts such nodes at every poll of
- *                  the absorption flags and takes the mode for the next
- *                  chunk of steps when that count times the mean in-degree
- *                  is at most n.  FSG_OPT_TAIL_OFF never takes it;
- *                  FSG_OPT_TAIL_ALWAYS takes it for every chunk after the
- *                  first (for tests).  Results are the same either way. */
+ *                  Tail mode (SI, SIS, SIR, LT, and IC on the pull step,
+ *                  kernel_variant 1; any B; fsg_simulate, sessions and
+ *                  batches; on a graph with its out-adjacency bound): once
+ *                  few nodes hold an infected replicate (IC, LT: a new
+ *                  activation), a row whose in-neighbours and itself hold
+ *                  none after step t-1 cannot change at step t and is left
+ *                  out of it; before each step the out-arcs of those nodes
+ *                  mark the rows that are not (one more small kernel a step,
+ *                  timed with the step kernel).  The library counts such
+ *                  nodes at every poll of the absorption flags and takes the
+ *                  mode for the next chunk of steps when that count times
+ *                  the mean in-degree is at most n.  FSG_OPT_TAIL_OFF never
+ *                  takes it; FSG_OPT_TAIL_ALWAYS takes it for every chunk
+ *                  after the first (for tests).  Results are the same either
+ *                  way. */
 #define FSG_OPT_WIDE_OFFSETS 1
 #define FSG_OPT_COUNT_DRAWS 2
 #define FSG_OPT_REUSE_WORKSPACE 4

@@ -335,7 +335,7 @@ struct Sched {
     bool wide;   // 64-bit offsets in the row-group kernels even where 32-bit ones fit
     bool count;  // count the generator calls of the SI-family decisions
     bool reuse;  // the caller vouches for the workspace (FSG_OPT_REUSE_WORKSPACE)
-    bool tail;   // SI / SIS / SIR with one pass per row: tail mode allowed
+    bool tail;   // SI family, LT, pull-step IC: tail mode allowed
     bool tail_always;  // ... and taken from the second chunk on (FSG_OPT_TAIL_ALWAYS)
 };
 
@@ -415,9 +415,10 @@ int resolve_sched(const fsg_graph *g, const fsg_params *prm, int64_t B, const fs
     s->wide = (u.options & FSG_OPT_WIDE_OFFSETS) != 0;
     s->count = (u.options & FSG_OPT_COUNT_DRAWS) != 0;
     s->reuse = (u.options & FSG_OPT_REUSE_WORKSPACE) != 0;
-    // the tail mode: SI, SIS, SIR (no latent plane) and LT
+    // the tail mode: SI, SIS, SIR (no latent plane), LT, and IC on the pull
+    // step (the edge-parallel IC steps find their frontier themselves)
     s->tail = (prm->model == FSG_SI || prm->model == FSG_SIS || prm->model == FSG_SIR ||
-               prm->model == FSG_LT) &&
+               prm->model == FSG_LT || (prm->model == FSG_IC && !s->edge1)) &&
               !(u.options & FSG_OPT_TAIL_OFF);
     s->tail_always = s->tail && (u.options & FSG_OPT_TAIL_ALWAYS) != 0;
     return FSG_OK;
@@ -501,7 +502,7 @@ int layout(fsg_graph *g, const fsg_params *prm, int64_t B, const Sched &s, const
         off = align256(off + (size_t)g->n * (size_t)L->L * (size_t)L->W * 8);
     L->stamp = off;
     if (kind == kKindLT) off = align256(off + (size_t)g->n * 8);  // gain steps, two arrays
-    L->ibm = off;  // SI family, tail mode: four infected-node and two candidate bitmaps
+    L->ibm = off;  // tail mode: four infected-node (IC, LT: new-activation) and two candidate bitmaps
     if (s.tail) off = align256(off + 6 * (size_t)((g->n + 31) / 32) * 4);
     L->icount = off;  // nodes with an infected replicate (tail-mode decisions)
     if (s.tail) off = align256(off + 8);
@@ -606,9 +607,9 @@ struct Job {
     uint4 *queue[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<uint32_t> tinf_h, edge_t_h;  // host tables the set-up uploads
     uint32_t *ever = nullptr;                // frontier-driven IC: ever-in-a-frontier bitmap
-    uint32_t *ibm = nullptr;                 // SI-family tail mode: infected-node and candidate bitmaps
+    uint32_t *ibm = nullptr;                 // tail mode: infected-node and candidate bitmaps
     bool tail = false;                       // the tail mode can be taken (out-adjacency bound)
-    unsigned long long *icount = nullptr;    // SI-family tail mode: nodes with an infected replicate
+    unsigned long long *icount = nullptr;    // tail mode: nodes infected (IC, LT: newly activated)
     uint64_t *tag = nullptr;                 // frontier-driven IC: clean-buffers tag
     uint64_t tag_value = 0;                  // the tag this job's layout writes
     // frontier plane (state 1) and its bitmap after step t: the planes

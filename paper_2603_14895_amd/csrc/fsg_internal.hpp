@@ -198,7 +198,7 @@ struct BatchCtl {
     int32_t ring;
     uint32_t *queue;          // [2] dequeue counters (step items, combine items)
     uint32_t *cur_step;       // the step the next launch executes
-    // tail mode (SI family, LT; jobs whose graph has its out-adjacency):
+    // tail mode (SI family, LT, IC; jobs whose graph has its out-adjacency):
     // tail_on[j] != 0 while job j runs in it (set by the host per chunk; the
     // job's StepArgs carry its bitmaps, which job_at_step drops otherwise);
     // word_off: prefix over the jobs of their bitmap words (0 for jobs that

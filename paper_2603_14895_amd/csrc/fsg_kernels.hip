@@ -862,11 +862,10 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
         // t-1 has the counts it was last decided on and cannot activate; it
         // takes the copy pass without counting (earlier, nearly every row
         // has such a neighbour and the test would only add loads)
-        // tail mode (SI family, LT): a row that is not a candidate -- itself
-        // and its in-neighbours without an infected replicate (SI family) or
-        // without a new activation (LT) after step t-1 -- cannot change at
-        // step t
-        constexpr bool kTailKind = TAIL && (KIND == kKindEpidemic || KIND == kKindLT);
+        // tail mode: a row that is not a candidate -- itself and its
+        // in-neighbours without an infected replicate (SI family) or without
+        // a new activation (IC, LT) after step t-1 -- cannot change at step t
+        constexpr bool kTailKind = TAIL;
         const bool fresh_test = KIND == kKindLT && a.stamp != nullptr && wm.compact &&
                                 wm.count * 2 <= a.W && !(kTailKind && a.ibm != nullptr);
         const int rl = 1 << (lgGe + a.lgS);  // lanes of a row
@@ -888,8 +887,10 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                     // t-1.  The buffer step t writes holds the state after
                     // t-2: for LT that is the same (no activation at t-1);
                     // for the SI family it differs only if the node had an
-                    // infected replicate then (none after t-1)
-                    if (KIND == kKindEpidemic) {
+                    // infected replicate then (none after t-1), for IC (the
+                    // buffer holds new activations) if it had a new
+                    // activation then (none at t)
+                    if (KIND != kKindLT) {
                         const uint32_t *inf2 = a.ibm + (size_t)((a.step - 2u) & 3u) * a.ibm_words;
                         if ((inf2[v >> 5] >> (v & 31)) & 1u)
                             for (int w = lane & (rl - 1); w < a.W; w += rl)
@@ -915,7 +916,7 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
                                   share_e, tl, tl_n, tcode, lm & rowlm, anyw);
                 note_words(a, Ge, w, ok, anyw);
                 // anyw: an infected replicate (SI family) or a new activation
-                // (LT) in this word after the step
+                // (IC, LT) in this word after the step
                 if (kTailKind && anyw && a.ibm != nullptr) mark_infected(a, v);
                 any |= anyw;
             }
@@ -956,8 +957,8 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
 }
 
 // Tail mode: whether light-row block `bid` has nothing to do at step t -- no
-// candidate row and no row infected after t-2 (whose buffer word must be
-// cleared) in its tile.  The bitmap words at the tile's ends may hold other
+// candidate row and no row infected (IC: newly activated) after t-2, whose
+// buffer word must be cleared, in its tile.  The bitmap words at the tile's ends may hold other
 // tiles' rows, which only makes the test keep a tile it could have left.
 // Every wave of the block reads the same words and gets the same answer.
 __device__ __forceinline__ bool tail_tile_idle(const StepArgs &a, int bid, bool zero_store)
@@ -981,7 +982,7 @@ template <int KIND, int L, bool TAIL = false>
 __global__ void __launch_bounds__(1024) k_step(StepArgs a)
 {
     if (a.flags[(a.step - 1) % (uint32_t)a.ring] == 0u) return;  // nothing left to change
-    if (TAIL && (KIND == kKindEpidemic || KIND == kKindLT) && a.ibm != nullptr) {
+    if (TAIL && a.ibm != nullptr) {
         // the bitmaps step t+1 sets, then whether this block has work
         uint32_t *clr = a.ibm + (size_t)((a.step + 1u) & 3u) * a.ibm_words;
         uint32_t *cclr = a.cand + (size_t)((a.step + 1u) & 1u) * a.ibm_words;
@@ -990,7 +991,7 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs a)
             clr[i] = 0u;
             cclr[i] = 0u;
         }
-        if (tail_tile_idle(a, blockIdx.x, KIND == kKindEpidemic)) return;
+        if (tail_tile_idle(a, blockIdx.x, KIND != kKindLT)) return;
     }
     __shared__ uint32_t s_tinf[KIND == kKindEpidemic ? kTinfLds : 1];
     __shared__ uint32_t s_code[kCodeTable];
@@ -1052,6 +1053,7 @@ __device__ __forceinline__ void combine_block(const StepArgs &a, int bid, const 
                 a.aux[idx] = A | acc;
                 anyw = acc != 0;
             }
+            if (a.ibm != nullptr && anyw) mark_infected(a, v);  // tail mode
         } else {
             uint64_t c[LC];
 #pragma unroll
@@ -1568,14 +1570,14 @@ k_batch_step(BatchCtl c)
         const int local = item - s_off[j];
         // tail mode: a tile with no candidate row leaves at once (every
         // thread of the block reads the same words)
-        if (a.ibm != nullptr && tail_tile_idle(a, local, c.code[j] / 32 == kKindEpidemic)) continue;
+        if (a.ibm != nullptr && tail_tile_idle(a, local, c.code[j] / 32 != kKindLT)) continue;
         if (c.code[j] / 32 == kKindEpidemic) {  // block-uniform
             if (threadIdx.x < kCodeTable) s_code[threadIdx.x] = code_threshold(a, threadIdx.x);
             __syncthreads();
         }
         bool any = false;
         switch (c.code[j]) {
-        case kKindIC * 32 + 1: step_block<kKindIC, 1>(a, local, nullptr, 0, s_code, any); break;
+        case kKindIC * 32 + 1: step_block<kKindIC, 1, true>(a, local, nullptr, 0, s_code, any); break;
         case kKindEpidemic * 32 + 2: step_block<kKindEpidemic, 2, true>(a, local, nullptr, 0, s_code, any); break;
         case kKindEpidemic * 32 + 4: step_block<kKindEpidemic, 4, true>(a, local, nullptr, 0, s_code, any); break;
         case kKindEpidemic * 32 + 8: step_block<kKindEpidemic, 8, true>(a, local, nullptr, 0, s_code, any); break;
@@ -1674,7 +1676,10 @@ __global__ void __launch_bounds__(256) k_batch_expand(BatchCtl c)
 // Per job that can take the tail mode, the nodes with an infected replicate
 // (SI family: a nonzero word of the state plane after step t) or a new
 // activation at step t (LT: activation stamp t) into counts[j] (zeroed by
-// the caller).
+// the caller).  A job in the tail mode has these nodes in its bitmap t % 4
+// already (a node that is no candidate keeps no infected replicate and gains
+// no activation), so one bit is read instead of its row; a job that did not
+// run step t counts nothing (the host no longer reads its count).
 __global__ void k_batch_count(BatchCtl c, uint32_t t, unsigned long long *counts)
 {
     const int total = c.row_off[c.n_jobs];
@@ -1689,7 +1694,11 @@ __global__ void k_batch_count(BatchCtl c, uint32_t t, unsigned long long *counts
             j = find_job(c.row_off, c.n_jobs, (int)r);
             const int v = (int)r - c.row_off[j];
             const StepArgs &a = c.jobs[j];
-            if (c.code[j] / 32 == kKindLT) {
+            if (!job_live(c, a, j, t)) {
+                hit = false;
+            } else if (c.tail_on[j] != 0 && a.ibm != nullptr) {
+                hit = ((a.ibm[(size_t)(t & 3u) * a.ibm_words + (v >> 5)] >> (v & 31)) & 1u) != 0u;
+            } else if (c.code[j] / 32 == kKindLT) {
                 hit = a.stamp[(size_t)(t & 1u) * (size_t)a.n + (size_t)v] == t;
             } else {
                 const uint64_t *pl = (t & 1u) ? a.next : a.prev;  // state after step t
@@ -2347,12 +2356,15 @@ hipError_t launch_step(const StepArgs &a, int kind, int L, int block, hipStream_
     const int64_t nblocks = step_blocks(a, block);
     if (nblocks <= 0) return hipSuccess;
     const dim3 grid((unsigned)nblocks), blk((unsigned)block);
-    if (kind == kKindIC) {
-        hipLaunchKernelGGL((k_step<kKindIC, 1>), grid, blk, 0, s, a);
-        return hipGetLastError();
-    }
     // the tail-mode row test in its own instantiation: the other kernels
     // keep their register allocation
+    if (kind == kKindIC) {
+        if (a.ibm != nullptr)
+            hipLaunchKernelGGL((k_step<kKindIC, 1, true>), grid, blk, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_step<kKindIC, 1>), grid, blk, 0, s, a);
+        return hipGetLastError();
+    }
     if (kind == kKindEpidemic && a.ibm != nullptr)
         return step_kind<kKindEpidemic, true>(a, L, grid, blk, s);
     if (kind == kKindEpidemic) return step_kind<kKindEpidemic, false>(a, L, grid, blk, s);

@@ -89,8 +89,8 @@ def test_batch_equals_solo_and_oracle():
 def test_batch_tail_mode():
     """The tail mode in the batched launch: the mixed jobs on graphs with
     their out-adjacency bound, the mode forced on from the second chunk for
-    every job that can take it (SI, SIS, SIR, LT), then left to the library's
-    per-job switch; every job equals the oracle, with chunks of 3 and 16."""
+    every job (IC, SI, SIS, SIR, LT), then left to the library's per-job
+    switch; every job equals the oracle, with chunks of 3 and 16."""
     from paper_2603_14895_amd import fsg
     jobs = _mixed_jobs()
     dgs = [fsg.DeviceGraph(*j["gr"].numpy(), out=True) for j in jobs]
@@ -216,8 +216,8 @@ def test_autotune_and_cache():
 
 def test_c3_full_size_every_job():
     """The mixed batched workload at full size (64 jobs, 3.4e8 arcs) in the
-    launch configuration the benchmark times (SIR and LT graphs with their
-    out-adjacency, so those jobs switch to the tail mode late in their runs):
+    launch configuration the benchmark times (every graph with its
+    out-adjacency, so the jobs switch to the tail mode when few nodes change):
     every job equals its solo run bit for bit (compared on the device), and
     two sampled replicates of every job equal the oracle."""
     import torch
@@ -228,7 +228,7 @@ def test_c3_full_size_every_job():
         gr = W.build_c3_graph(sp, device="cuda")
         ptr, src = gr.numpy()
         del gr
-        dg = fsg.DeviceGraph(ptr, src, device="cuda:0", out=sp["model"] in ("sir", "lt"))
+        dg = fsg.DeviceGraph(ptr, src, device="cuda:0", out=True)
         seeds = W.uniform_seeds(dg.n, sp["n_seeds"], sp["seed_seed"])
         prm = {k: sp[k] for k in ("p", "ic_prob", "beta", "gamma", "max_steps") if k in sp}
         jobs.append(dict(graph=dg, model=sp["model"], B=sp["B"], seeds=seeds, rng_key=sp["key"],

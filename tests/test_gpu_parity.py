@@ -266,16 +266,18 @@ def test_si_family_draw_classes_and_saturated_thresholds():
                       max_steps=6, replicate_offset=off)
 
 
-@pytest.mark.parametrize("model", ["sir", "sis", "si", "lt"])
-def test_si_family_tail_mode(model):
+@pytest.mark.parametrize("model", ["sir", "sis", "si", "lt", "ic"])
+def test_tail_mode(model):
     """The tail mode (a row that is not a candidate -- it and its
     in-neighbours hold no infected replicate (SI family) or no new activation
-    (LT) after step t-1, found from the out-arcs of the nodes that do -- is
+    (IC, LT) after step t-1, found from the out-arcs of the nodes that do -- is
     left out of step t) gives the oracle's bits: forced from the second chunk
     on, through the epidemic's growth or the cascade's bulk, with chunks of 1
     and 3 steps, ragged and full words, word flags (17 to 64 words), edge-split
     rows and heavy-row segments, and left to the library's own switch; a
-    session stepped piece by piece in the tail mode ends in the same state."""
+    session stepped piece by piece in the tail mode ends in the same state.
+    IC takes the mode on the pull step only (with one word per node and the
+    out-adjacency bound, its default is the frontier-driven step)."""
     from paper_2603_14895_amd import fsg
     gr = W.chung_lu(3000, 10.0, 2.5, 2101)
     gnp = gr.numpy()
@@ -283,19 +285,22 @@ def test_si_family_tail_mode(model):
     kw = dict(beta=0.05, gamma=0.2, max_steps=70 if model == "sir" else 25)
     if model == "lt":
         kw = dict(max_steps=-1)
+    if model == "ic":
+        kw = dict(p=0.09, ic_prob="uniform", max_steps=-1)
     always = fsg.OPT_TAIL_ALWAYS
+    pull = dict(kernel_variant=1) if model == "ic" else {}
     # 1100 and 3000 replicates keep word flags (17 to 64 words)
     for B in (64, 100, 1024, 1100, 3000):
         for sched in (dict(options=always, steps_per_sync=1), dict(options=always, steps_per_sync=3),
                       dict(options=always, steps_per_sync=2, row_lanes=4, heavy_threshold=20),
                       dict(steps_per_sync=4), dict(options=fsg.OPT_TAIL_OFF)):
-            _both(gnp, model, seeds, B, 0x7A11 + B, f"tail-{model}-{sched}", schedule=sched,
-                  out=True, **kw)
+            _both(gnp, model, seeds, B, 0x7A11 + B, f"tail-{model}-{sched}",
+                  schedule=dict(sched, **pull), out=True, **kw)
     # without the out-adjacency the mode is never taken
     _both(gnp, model, seeds, 100, 0x7A12, f"tail-{model}-no-out", out=False,
           schedule=dict(options=always, steps_per_sync=1), **kw)
     sess = fsg.Session(fsg.DeviceGraph(*gnp, out=True), model, seeds, 100, 0x7A77,
-                       schedule=dict(options=always, steps_per_sync=1), **kw)
+                       schedule=dict(options=always, steps_per_sync=1, **pull), **kw)
     try:
         for n in (1, 2, 5, 30, 40):
             info, _ = sess.step(n)
