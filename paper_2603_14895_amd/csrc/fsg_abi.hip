@@ -915,6 +915,8 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
 struct Session {
     Job jb;
     int edge_grid = 0;
+    int push_grid = 0;      // frontier-driven IC: grid of a chunk that starts with a push
+    bool push_next = true;  // ... whether it does (the frontier's arcs at the last poll)
     int64_t steps_run = 0;  // steps executed so far
     bool absorbed = false;
     double kernel_ms = 0.0;
@@ -959,11 +961,17 @@ int begin_session(fsg_graph *g, const fsg_params *prm, const int32_t *seeds, int
         int dev = 0, ncu = 0;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        // four times more blocks than fit at once (32 KB of LDS each): blocks
-        // that finish early are replaced, which evens out the uneven work of
-        // frontier arcs (measured best on R-MAT scale 26 at B = 64)
+        // streaming: four times more blocks than fit at once (32 KB of LDS
+        // each), so blocks that finish early are replaced, which evens out
+        // the uneven work of frontier arcs (measured best on R-MAT scale 26 at
+        // B = 64).  Pushing over a small frontier, the blocks beyond one
+        // resident round only add dispatch time: R-MAT scale 26, 18 pushing
+        // steps and 14 steps after absorption take 0.39 ms with 16 blocks per
+        // CU, 0.24 ms with 2 or 4 (the streaming step slows 8% with 4)
         ss->edge_grid = 16 * std::max(ncu, 1);
+        ss->push_grid = 4 * std::max(ncu, 1);
     }
+    ss->push_next = true;  // the seeds' frontier is taken to be small
     ss->steps_run = 0;
     ss->absorbed = n_seeds == 0;
     ss->kernel_ms = 0.0;
@@ -1048,6 +1056,7 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
     const int64_t t_begin = ss.steps_run;
     const int64_t K = std::min<int64_t>(jb.K, t_begin + n_more);
     std::vector<uint32_t> hflags((size_t)ring);
+    unsigned long long hqarcs = 0ull;  // frontier-driven IC: the last frontier's out-arcs
     EventPool ev;
     if (s.timed) HIP_TRY(ev.init(2 * (size_t)s.sync));
     int64_t t = t_begin;
@@ -1101,7 +1110,7 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 // one kernel a step, back to back: timed per chunk (events
                 // between the launches would hold each one back)
                 if (s.timed && i == 1) HIP_TRY(hipEventRecord(ev.e[0], st));
-                HIP_TRY(launch_ic_front(a, ss.edge_grid, s.block, st));
+                HIP_TRY(launch_ic_front(a, ss.push_next ? ss.push_grid : ss.edge_grid, s.block, st));
                 if (s.timed && i == c) HIP_TRY(hipEventRecord(ev.e[1], st));
             } else if (s.edge1) {
                 a.bm_prev = jb.bm[(step - 1) & 1];
@@ -1125,6 +1134,8 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 HIP_TRY(launch_tally(f, st));
             }
         }
+        if (s.push)  // out-arcs of the frontier the next step starts from (queue of step t+c)
+            HIP_TRY(hipMemcpyAsync(&hqarcs, a.qarcs + (t + c) % 4, 8, hipMemcpyDeviceToHost, st));
         if (jb.tail) {  // nodes with an infected replicate (LT: a new activation) after the chunk
             if (kind == kKindLT)
                 HIP_TRY(launch_count_stamped(a.stamp, jb.n, (uint32_t)(t + c), jb.icount, st));
@@ -1136,6 +1147,7 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
         HIP_TRY(hipStreamSynchronize(st));
         HIP_TRY(take_setup_time(ss));
         if (jb.tail) ss.infected_rows = (int64_t)((uint64_t)htail[0] | ((uint64_t)htail[1] << 32));
+        if (s.push) ss.push_next = hqarcs <= a.push_limit;
         if (s.timed && s.push) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
