@@ -1851,19 +1851,40 @@ __global__ void k_count_stamped(const uint32_t *stamp, int64_t n, uint32_t t, un
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
 }
 
-// Number of nodes with a nonzero word in `plane` (one integer atomic add per
-// wave).
+// Nodes with a nonzero word in `plane` ([n][W]) into *count (zeroed by the
+// caller).  Lanes go over words so that a wave's loads are contiguous: with
+// W <= 64 a pass of the wave takes 64 / W whole rows (R W consecutive words)
+// and counts the rows whose W-bit group of the ballot is nonzero; wider rows
+// take a wave each, its lanes striding over the row.
 __global__ void k_count_rows(const uint64_t *plane, int64_t n, int64_t W, unsigned long long *count)
 {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
     unsigned long long c = 0;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t x = 0;
-        for (int64_t w = 0; w < W; ++w) x |= plane[v * W + w];
-        c += x ? 1ull : 0ull;
+    if (W <= 64) {
+        const int Wi = (int)W;
+        const int R = 64 / Wi;  // rows per pass
+        const int slot = lane / Wi, w = lane - slot * Wi;
+        const uint64_t gmask = Wi == 64 ? ~0ull : ((1ull << Wi) - 1ull);
+        for (int64_t r0 = wave * R; r0 < n; r0 += nwave * R) {
+            const int64_t v = r0 + slot;
+            const uint64_t x = (slot < R && v < n) ? plane[v * W + w] : 0ull;
+            const uint64_t m = __ballot(x != 0ull);
+            if (Wi == 1) {
+                c += (unsigned long long)__popcll(m);
+            } else {
+                for (int k = 0; k < R; ++k) c += ((m >> (k * Wi)) & gmask) != 0ull ? 1ull : 0ull;
+            }
+        }
+    } else {
+        for (int64_t v = wave; v < n; v += nwave) {
+            uint64_t x = 0;
+            for (int64_t w = lane; w < W; w += 64) x |= plane[v * W + w];
+            c += __ballot(x != 0ull) != 0ull ? 1ull : 0ull;
+        }
     }
-    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+    if (lane == 0 && c) atomicAdd(count, c);  // c is the same in every lane of the wave
 }
 
 __global__ void k_zero16_unless(u32x4 *p, int64_t count16, const uint64_t *tag, uint64_t expect)
