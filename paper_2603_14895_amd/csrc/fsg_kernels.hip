@@ -1639,20 +1639,43 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_combine(BatchCtl c)
 // Tail mode of the batched launch, before batched step t: for every job in
 // the mode, the bitmaps step t+1 sets are cleared and the nodes of bitmap
 // t-1 and their out-neighbours are marked in candidate bitmap t % 2 (a wave
-// per bitmap word, over the words of all such jobs).
+// per bitmap word, over the words of all jobs that can take the mode).  The
+// job offsets and mode switches are staged in LDS; a wave keeps a job's
+// arguments while its words follow one another, and jumps past the words of
+// a job that is not in the mode or has stopped.
 __global__ void __launch_bounds__(256) k_batch_expand(BatchCtl c)
 {
+    __shared__ int32_t s_off[kMaxBatchJobs + 1];
+    __shared__ int32_t s_on[kMaxBatchJobs];
     const uint32_t t = *c.cur_step;
+    for (int i = threadIdx.x; i <= c.n_jobs; i += blockDim.x) {
+        s_off[i] = c.word_off[i];
+        if (i < c.n_jobs) s_on[i] = c.tail_on[i];
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int total = c.word_off[c.n_jobs];
+    const int64_t total = s_off[c.n_jobs];
+    int jc = -1;  // the job `a` holds
+    bool on = false;
+    StepArgs a{};
     for (int64_t item = wave; item < total; item += nwave) {
-        const int j = find_job(c.word_off, c.n_jobs, (int)item);
-        if (c.tail_on[j] == 0) continue;
-        const StepArgs a = job_at_step(c, j, t);
-        if (!job_live(c, a, j, t)) continue;
-        const int i = (int)item - c.word_off[j];
+        const int j = __builtin_amdgcn_readfirstlane(find_job(s_off, c.n_jobs, (int)item));
+        if (j != jc) {
+            jc = j;
+            on = s_on[j] != 0;
+            if (on) {
+                a = job_at_step(c, j, t);
+                on = job_live(c, a, j, t);
+            }
+        }
+        if (!on) {
+            // the loop step then lands on this wave's first word of a later job
+            item += ((int64_t)s_off[j + 1] - 1 - item) / nwave * nwave;
+            continue;
+        }
+        const int i = (int)item - s_off[j];
         if (lane == 0) {
             a.ibm[(size_t)((t + 1u) & 3u) * a.ibm_words + i] = 0u;
             a.cand[(size_t)((t + 1u) & 1u) * a.ibm_words + i] = 0u;
@@ -1684,35 +1707,55 @@ __global__ void k_batch_count(BatchCtl c, uint32_t t, unsigned long long *counts
 {
     const int total = c.row_off[c.n_jobs];
     const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // every lane of a wave runs the same number of rounds (ballots below)
-    for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); r0 < total; r0 += stride) {
-        const int64_t r = r0 + lane;
-        bool hit = false;
-        int j = 0;
-        if (r < total) {
-            j = find_job(c.row_off, c.n_jobs, (int)r);
-            const int v = (int)r - c.row_off[j];
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    // a wave takes 64 consecutive rows at a time, job by job within them;
+    // state planes of several words a row are read with lanes over words
+    // (64 / W whole rows a pass), so the loads of a pass are contiguous
+    for (int64_t r0 = wave * 64; r0 < total; r0 += nwave * 64) {
+        const int64_t rend = r0 + 64 < total ? r0 + 64 : total;
+        for (int64_t r = r0; r < rend;) {
+            const int j = __builtin_amdgcn_readfirstlane(find_job(c.row_off, c.n_jobs, (int)r));
+            const int64_t je = c.row_off[j + 1] < rend ? (int64_t)c.row_off[j + 1] : rend;
             const StepArgs &a = c.jobs[j];
-            if (!job_live(c, a, j, t)) {
-                hit = false;
-            } else if (c.tail_on[j] != 0 && a.ibm != nullptr) {
-                hit = ((a.ibm[(size_t)(t & 3u) * a.ibm_words + (v >> 5)] >> (v & 31)) & 1u) != 0u;
-            } else if (c.code[j] / 32 == kKindLT) {
-                hit = a.stamp[(size_t)(t & 1u) * (size_t)a.n + (size_t)v] == t;
-            } else {
-                const uint64_t *pl = (t & 1u) ? a.next : a.prev;  // state after step t
-                uint64_t x = 0;
-                for (int w = 0; w < a.W; ++w) x |= pl[(int64_t)v * a.W + w];
-                hit = x != 0ull;
+            const int64_t v0 = r - c.row_off[j];  // first row of the job in [r, je)
+            const int64_t nr = je - r;
+            unsigned long long cnt = 0;
+            if (job_live(c, a, j, t)) {
+                if (c.tail_on[j] != 0 && a.ibm != nullptr) {
+                    const int64_t v = v0 + lane;
+                    const bool hit = lane < nr &&
+                                     ((a.ibm[(size_t)(t & 3u) * a.ibm_words + (v >> 5)] >> (v & 31)) & 1u);
+                    cnt = (unsigned long long)__popcll(__ballot(hit));
+                } else if (c.code[j] / 32 == kKindLT) {
+                    const int64_t v = v0 + lane;
+                    const bool hit = lane < nr && a.stamp[(size_t)(t & 1u) * (size_t)a.n + (size_t)v] == t;
+                    cnt = (unsigned long long)__popcll(__ballot(hit));
+                } else {
+                    const uint64_t *pl = (t & 1u) ? a.next : a.prev;  // state after step t
+                    const int W = a.W;
+                    if (W <= 64) {
+                        const int R = 64 / W;  // rows a pass
+                        const int slot = lane / W, w = lane - slot * W;
+                        const uint64_t gmask = W == 64 ? ~0ull : ((1ull << W) - 1ull);
+                        for (int64_t q = 0; q < nr; q += R) {
+                            const bool in = slot < R && q + slot < nr;
+                            const uint64_t x = in ? pl[(v0 + q + slot) * W + w] : 0ull;
+                            const uint64_t m = __ballot(x != 0ull);
+                            for (int k = 0; k < R; ++k) cnt += ((m >> (k * W)) & gmask) != 0ull ? 1ull : 0ull;
+                        }
+                    } else {
+                        for (int64_t q = 0; q < nr; ++q) {
+                            uint64_t x = 0;
+                            for (int w = lane; w < W; w += 64) x |= pl[(v0 + q) * W + w];
+                            cnt += __ballot(x != 0ull) != 0ull ? 1ull : 0ull;
+                        }
+                    }
+                }
             }
+            if (lane == 0 && cnt) atomicAdd(&counts[j], cnt);  // cnt is wave-uniform
+            r = je;
         }
-        // the rows of a wave belong to one job or to two neighbouring ones:
-        // one add for the first lane's job, one per hit of another
-        const int j0 = __shfl(j, 0, 64);
-        const uint64_t m = __ballot(hit && j == j0);
-        if (lane == 0 && m != 0ull) atomicAdd(&counts[j0], (unsigned long long)__popcll(m));
-        if (hit && j != j0) atomicAdd(&counts[j], 1ull);
     }
 }
 
