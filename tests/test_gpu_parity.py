@@ -444,6 +444,22 @@ def test_ic_frontier_driven(graph, ic_prob, B, offset, K):
           schedule=dict(kernel_variant=3, steps_per_sync=2 if K < 0 else 16))
 
 
+def test_ic_frontier_driven_launch_widths():
+    """A chunk of frontier-driven IC steps that starts from a pushable
+    frontier launches fewer blocks than one that starts by streaming; on a
+    graph large enough for the two widths to differ (20,000 nodes), a
+    cascade that streams at its peak and pushes before and after gives the
+    oracle's bits whether the width is chosen every step, every 3 steps or
+    once for the whole run."""
+    gr = W.erdos_renyi_directed(20000, 30.0, 131)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 8, 132)
+    for spsync in (1, 3, 32):
+        _both(gnp, "ic", seeds, 64, 0x51DE, f"ic-front-widths-sync{spsync}", p=0.12,
+              ic_prob="uniform", max_steps=-1, out=True,
+              schedule=dict(kernel_variant=3, steps_per_sync=spsync))
+
+
 @pytest.mark.parametrize("B", [64, 50])
 def test_ic_frontier_driven_workspace_reuse(B):
     """Runs after the first on one Simulation pass FSG_OPT_REUSE_WORKSPACE:
