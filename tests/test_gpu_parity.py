@@ -266,6 +266,26 @@ def test_si_family_draw_classes_and_saturated_thresholds():
                       max_steps=6, replicate_offset=off)
 
 
+@pytest.mark.parametrize("model", ["sir", "ic"])
+def test_tail_mode_wide_rows(model):
+    """Rows of more than 64 words (B = 4200, 66 words) in the tail mode: the
+    counts that switch the mode read such a row with a whole wave.  The mode
+    forced on, and left to its switch, gives the oracle's bits."""
+    from paper_2603_14895_amd import fsg
+    gr = W.chung_lu(900, 8.0, 2.5, 2201)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 15, 2202)
+    if model == "sir":
+        kw = dict(beta=0.08, gamma=0.2, max_steps=40)
+        pull = {}
+    else:
+        kw = dict(p=0.1, ic_prob="uniform", max_steps=-1)
+        pull = dict(kernel_variant=1)
+    for sched in (dict(options=fsg.OPT_TAIL_ALWAYS, steps_per_sync=2), dict(steps_per_sync=3)):
+        _both(gnp, model, seeds, 4200, 0x7B01, f"tail-wide-{model}-{sched}",
+              schedule=dict(sched, **pull), out=True, **kw)
+
+
 @pytest.mark.parametrize("model", ["sir", "sis", "si", "lt", "ic"])
 def test_tail_mode(model):
     """The tail mode (a row that is not a candidate -- it and its
