@@ -116,6 +116,38 @@ def test_batch_tail_mode():
         batch.close()
 
 
+def test_batch_tail_mode_wide_rows():
+    """The batched tail mode with rows of more than 64 words (B = 4200): the
+    batched count reads such a row with a whole wave.  SIR and IC jobs beside
+    a narrow LT job, the mode forced on and left to its switch; every job
+    equals the oracle."""
+    from paper_2603_14895_amd import fsg
+    specs = [("sir", 900, 8.0, 4200, dict(beta=0.08, gamma=0.2, max_steps=40)),
+             ("ic", 1100, 7.0, 4200, dict(p=0.1, max_steps=-1)),
+             ("lt", 700, 6.0, 100, dict(max_steps=-1))]
+    jobs = []
+    for i, (model, n, deg, B, prm) in enumerate(specs):
+        gr = W.chung_lu(n, deg, 2.5, 2301 + i)
+        jobs.append(dict(gr=gr, model=model, B=B, seeds=W.uniform_seeds(n, 12, 2311 + i),
+                         rng_key=0x7C00 + i, replicate_offset=0, **prm))
+    dgs = [fsg.DeviceGraph(*j["gr"].numpy(), out=True) for j in jobs]
+    for forced in (True, False):
+        bj = []
+        for dg, j in zip(dgs, jobs):
+            d = dict(graph=dg, **{k: v for k, v in j.items() if k != "gr"})
+            d["schedule"] = dict(options=fsg.OPT_TAIL_ALWAYS) if forced else None
+            bj.append(d)
+        batch = fsg.Batch(bj, steps_per_sync=3)
+        infos, _ = batch.run()
+        for i, j in enumerate(jobs):
+            got = (batch.states[i].cpu().numpy(), batch.counts[i].cpu().numpy().astype(np.uint32),
+                   int(infos[i].steps_run), int(infos[i].absorbed))
+            prm = {k: j[k] for k in ("p", "beta", "gamma", "max_steps") if k in j}
+            ref = oracle_run(j["gr"].numpy(), j["model"], j["seeds"], j["B"], j["rng_key"], **prm)
+            assert_same(got, ref, f"wide tail job {i} ({j['model']}) forced={forced}")
+        batch.close()
+
+
 def test_batch_mixed_workload_small():
     """A reduced instance of the mixed batched workload (log-uniform sizes,
     B and seed-set sizes; IC / SIR / LT), every job checked on sampled
