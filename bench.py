@@ -50,15 +50,41 @@ KERNEL_SOURCES = {
 SIM_SOURCES = ["fsg_kernels.hip", "fsg_device.hpp", "fsg_internal.hpp", "fsg_abi.hip"]
 
 
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments and with runs of whitespace made one
+    space (string and character literals kept as written)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c == "/" and src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif c == "/" and src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash(workload: str = "c2") -> str:
-    """Hash of the HIP sources behind a workload's kernels; a counter record
-    is valid only for the hash it was taken at."""
+    """Hash of the HIP sources behind a workload's kernels, comments and
+    layout left out; a counter record is valid only for the hash it was
+    taken at."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_14895_amd", "csrc")
     for name in sorted(KERNEL_SOURCES.get(workload, SIM_SOURCES)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            h.update(name.encode() + b"\0" + strip_comments(f.read()).encode())
     return h.hexdigest()[:16]
 
 

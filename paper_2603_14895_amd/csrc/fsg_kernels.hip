@@ -958,8 +958,9 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int bid, const uin
 
 // Tail mode: whether light-row block `bid` has nothing to do at step t -- no
 // candidate row and no row infected (IC: newly activated) after t-2, whose
-// buffer word must be cleared, in its tile.  The bitmap words at the tile's ends may hold other
-// tiles' rows, which only makes the test keep a tile it could have left.
+// buffer word must be cleared, in its tile.  The bitmap words at the tile's
+// ends may hold other tiles' rows, which only makes the test keep a tile it
+// could have left.
 // Every wave of the block reads the same words and gets the same answer.
 __device__ __forceinline__ bool tail_tile_idle(const StepArgs &a, int bid, bool zero_store)
 {
@@ -1697,9 +1698,9 @@ __global__ void __launch_bounds__(256) k_batch_expand(BatchCtl c)
 }
 
 // Per job that can take the tail mode, the nodes with an infected replicate
-// (SI family: a nonzero word of the state plane after step t) or a new
-// activation at step t (LT: activation stamp t) into counts[j] (zeroed by
-// the caller).  A job in the tail mode has these nodes in its bitmap t % 4
+// or a new activation after step t into counts[j] (zeroed by the caller): a
+// nonzero word of the state plane after step t (SI family: the infected
+// plane; IC: the frontier plane), or activation stamp t (LT).  A job in the tail mode has these nodes in its bitmap t % 4
 // already (a node that is no candidate keeps no infected replicate and gains
 // no activation), so one bit is read instead of its row; a job that did not
 // run step t counts nothing (the host no longer reads its count).

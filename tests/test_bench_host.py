@@ -57,3 +57,17 @@ def test_host_cpu_record():
     assert isinstance(hc["cpu_model"], str) and hc["cpu_model"]
     f = bench.cpu_fields(hc)
     assert f["cores"] == hc["threads"]
+
+
+def test_kernel_source_hash_ignores_comments_not_code():
+    """A counter record stays valid across comment and layout edits of the
+    kernels' sources, and not across code edits; literals are kept."""
+    sys.path.insert(0, ROOT)
+    import bench
+    src = ('int a = 1; // one\n/* block\n comment */ const char *s = "x // y /* z */";\n'
+           "char q = '\\''; int  b =\n 2;")
+    assert bench.strip_comments(src) == \
+        'int a = 1; const char *s = "x // y /* z */"; char q = \'\\\'\'; int b = 2;'
+    assert bench.strip_comments("a/* c */b") == "a b"
+    assert bench.strip_comments(src.replace("// one", "// two")) == bench.strip_comments(src)
+    assert bench.strip_comments(src.replace(" 2;", " 3;")) != bench.strip_comments(src)
