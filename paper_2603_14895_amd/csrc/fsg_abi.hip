@@ -437,24 +437,59 @@ struct Layout {
 constexpr int64_t kSeedStage = 65536;
 
 // HIP events for optional per-step timing, released on scope exit.
+// Events of a timed call come from a per-thread list of released ones, so a
+// run does not create and destroy its events (a timed SIR run polls 25 times,
+// with 16 events a poll).  Each entry remembers its device; the list is never
+// torn down (its events live until the process ends).
+struct CachedEvent {
+    int dev;
+    hipEvent_t ev;
+};
+constexpr size_t kEventCacheMax = 4096;
+std::vector<CachedEvent> &event_cache()
+{
+    thread_local std::vector<CachedEvent> *c = new std::vector<CachedEvent>();
+    return *c;
+}
+
 struct EventPool {
     EventPool() = default;
     EventPool(const EventPool &) = delete;
     EventPool &operator=(const EventPool &) = delete;
     std::vector<hipEvent_t> e;
+    int dev = -1;
     hipError_t init(size_t count)
     {
-        e.resize(count, nullptr);
+        release();
+        hipError_t r = hipGetDevice(&dev);
+        if (r != hipSuccess) return r;
+        std::vector<CachedEvent> &c = event_cache();
+        e.assign(count, nullptr);
         for (auto &x : e) {
-            hipError_t r = hipEventCreate(&x);
-            if (r != hipSuccess) return r;
+            for (size_t i = c.size(); i-- > 0;)
+                if (c[i].dev == dev) {
+                    x = c[i].ev;
+                    c[i] = c.back();
+                    c.pop_back();
+                    break;
+                }
+            if (!x) {
+                r = hipEventCreate(&x);
+                if (r != hipSuccess) return r;
+            }
         }
         return hipSuccess;
     }
     void release()
     {
-        for (auto x : e)
-            if (x) (void)hipEventDestroy(x);
+        std::vector<CachedEvent> &c = event_cache();
+        for (auto x : e) {
+            if (!x) continue;
+            if (c.size() < kEventCacheMax)
+                c.push_back({dev, x});
+            else
+                (void)hipEventDestroy(x);
+        }
         e.clear();
     }
     ~EventPool() { release(); }
@@ -1057,8 +1092,8 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
     const int64_t K = std::min<int64_t>(jb.K, t_begin + n_more);
     std::vector<uint32_t> hflags((size_t)ring);
     unsigned long long hqarcs = 0ull;  // frontier-driven IC: the last frontier's out-arcs
-    EventPool ev;
-    if (s.timed) HIP_TRY(ev.init(2 * (size_t)s.sync));
+    EventPool ev;  // a pair per step, or one pair per chunk for the frontier-driven IC step
+    if (s.timed) HIP_TRY(ev.init(s.push ? 2 : 2 * (size_t)s.sync));
     int64_t t = t_begin;
     std::vector<uint32_t> htail(2);
     while (!ss.absorbed && t < K) {
