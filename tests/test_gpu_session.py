@@ -133,3 +133,30 @@ def test_session_frontier_driven_ic(B, off):
         assert tallies[step - 1] == want, step
     ss.close()
     g.close()
+
+
+def test_session_frontier_driven_ic_launch_widths():
+    """A frontier-driven IC session on a graph large enough for pushing and
+    streaming chunks to get different grids (20,000 nodes; the cascade
+    streams at its peak): the grid choice carried from piece to piece gives
+    the same bits as one call and the oracle."""
+    from paper_2603_14895_amd import fsg
+    gr = W.erdos_renyi_directed(20000, 30.0, 141)
+    gnp = gr.numpy()
+    seeds = W.uniform_seeds(gr.n, 8, 142)
+    key, prm = 0x51DF, dict(p=0.12, max_steps=-1)
+    sched = dict(kernel_variant=3, steps_per_sync=2)
+    whole = gpu_run(gnp, "ic", seeds, 64, key, schedule=sched, out=True, **prm)
+    assert_same(whole, oracle_run(gnp, "ic", seeds, 64, key, **prm), "whole")
+    g = fsg.DeviceGraph(*gnp, out=True)
+    ss = fsg.Session(g, "ic", seeds, 64, key, schedule=sched, **prm)
+    for k in (1, 1, 3, 2, 5, 100):
+        info, _ = ss.step(k)
+        if info.absorbed:
+            break
+    st, cnt, _ = ss.read()
+    got = (st.cpu().numpy(), cnt.cpu().numpy().astype(np.uint32), int(info.steps_run),
+           int(info.absorbed))
+    assert_same(got, whole, "frontier-driven session (launch widths) vs one call")
+    ss.close()
+    g.close()
