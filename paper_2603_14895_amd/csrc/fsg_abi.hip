@@ -905,10 +905,9 @@ hipError_t scrub_frontiers(const Job &jb, int64_t steps_run, hipStream_t st)
 // Packed planes of the step `steps_run` -> uint8 states and counts; with
 // `scrub` (frontier-driven IC, one word per node) the run's buffers are left
 // clear as well.
-int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32_t *counts,
-                 hipStream_t st, double *ms_out = nullptr, bool scrub = false)
+FinArgs fin_args(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32_t *counts,
+                 bool scrub)
 {
-    if (!final_states && !counts) return FSG_OK;
     FinArgs f;
     memset(&f, 0, sizeof(f));
     f.n = (int32_t)jb.n;
@@ -928,6 +927,14 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
         f.two_bm = jb.ever;
         f.scrub = (scrub && f.W == 1) ? 1 : 0;
     }
+    return f;
+}
+
+int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32_t *counts,
+                 hipStream_t st, double *ms_out = nullptr, bool scrub = false)
+{
+    if (!final_states && !counts) return FSG_OK;
+    const FinArgs f = fin_args(jb, steps_run, final_states, counts, scrub);
     EventPool ev;
     if (ms_out) {
         HIP_TRY(ev.init(2));
@@ -943,6 +950,57 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
         *ms_out = ms;
     }
     return FSG_OK;
+}
+
+// Frontier-driven IC through fsg_simulate: the finalize, the clearing of the
+// last two frontiers and the tag are queued right after every chunk of
+// steps, before the host reads the absorption flags; on the device they act
+// only if the chunk ended the run (SpecFin), so the finalize follows the last
+// step without a host round trip.  `done` tells the caller the outputs are
+// written.
+struct SpecOut {
+    uint8_t *states = nullptr;
+    uint32_t *counts = nullptr;
+    bool done = false;
+    double ms = 0.0;  // finalize kernel time (timed schedules)
+    EventPool ev;
+};
+
+SpecFin spec_of(const Job &jb, int64_t t0, int64_t c)
+{
+    SpecFin sp;
+    memset(&sp, 0, sizeof(sp));
+    sp.flags = jb.a.flags;
+    sp.ring = jb.ring;
+    sp.c = (int32_t)c;
+    sp.t0 = t0;
+    for (int i = 0; i < 3; ++i) {  // front(t) and its bitmap and summary depend on t mod 3
+        sp.front3[i] = jb.front(i);
+        sp.bm3[i] = jb.front_bm(i);
+        sp.sum3[i] = jb.front_sum(i);
+    }
+    for (int i = 0; i < 4; ++i) sp.queue4[i] = jb.queue[i];
+    return sp;
+}
+
+hipError_t queue_spec_finalize(const Job &jb, int64_t t0, int64_t c, SpecOut &so, hipStream_t st)
+{
+    const SpecFin sp = spec_of(jb, t0, c);
+    FinArgs f = fin_args(jb, t0 + 1, so.states, so.counts, true);
+    f.spec = sp;
+    if (jb.s.timed) {
+        hipError_t e = hipEventRecord(so.ev.e[0], st);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_finalize(f, st);
+    if (e != hipSuccess) return e;
+    if (jb.s.timed) {
+        e = hipEventRecord(so.ev.e[1], st);
+        if (e != hipSuccess) return e;
+    }
+    e = launch_ic_scrub_spec(jb.a, sp, 1, nullptr, 0ull, st);
+    if (e != hipSuccess) return e;
+    return launch_ic_scrub_spec(jb.a, sp, 2, jb.tag, jb.tag_value, st);
 }
 
 // A run in progress: the job on the caller's workspace, its schedule, and
@@ -1080,7 +1138,8 @@ hipError_t take_setup_time(Session &ss)
 
 // `sync` steps with one poll of the absorption flags per chunk.  With
 // dev_tally, row i receives the state tally after the i-th step of this call.
-int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
+int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st,
+              SpecOut *so = nullptr)
 {
     Job &jb = ss.jb;
     const Sched &s = jb.s;
@@ -1169,6 +1228,7 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 HIP_TRY(launch_tally(f, st));
             }
         }
+        if (so) HIP_TRY(queue_spec_finalize(jb, t, c, *so, st));
         if (s.push)  // out-arcs of the frontier the next step starts from (queue of step t+c)
             HIP_TRY(hipMemcpyAsync(&hqarcs, a.qarcs + (t + c) % 4, 8, hipMemcpyDeviceToHost, st));
         if (jb.tail) {  // nodes with an infected replicate (LT: a new activation) after the chunk
@@ -1205,6 +1265,14 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st)
                 ss.absorbed = true;
                 break;
             }
+        if (so && ss.absorbed) {  // the queued finalize acted (the same first clear flag)
+            so->done = true;
+            if (s.timed) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, so->ev.e[0], so->ev.e[1]));
+                so->ms = ms;
+            }
+        }
         if (ss.tail_on) ss.tail_steps += ss.steps_run - t;
         t += c;
     }
@@ -1435,12 +1503,22 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
                                replicate_offset, rng_key, sched, dev_ws, ws_bytes,
                                (hipStream_t)stream, &ss);
         if (rc) return rc;
-        rc = run_steps(ss, ss.jb.K, nullptr, (hipStream_t)stream);
-        if (rc) return rc;
         const bool scrub = ss.jb.s.push && (final_states || infected_counts);
-        rc = finalize_job(ss.jb, ss.steps_run, final_states, infected_counts, (hipStream_t)stream,
-                          ss.jb.s.timed ? &ss.finalize_ms : nullptr, scrub);
+        SpecOut so;
+        if (scrub) {  // frontier-driven IC: the finalize goes in right behind the steps
+            so.states = final_states;
+            so.counts = infected_counts;
+            if (ss.jb.s.timed) HIP_TRY(so.ev.init(2));
+        }
+        rc = run_steps(ss, ss.jb.K, nullptr, (hipStream_t)stream, scrub ? &so : nullptr);
         if (rc) return rc;
+        if (so.done) {
+            ss.finalize_ms = so.ms;
+        } else {  // the run stopped at its step cap (or has no seeds)
+            rc = finalize_job(ss.jb, ss.steps_run, final_states, infected_counts, (hipStream_t)stream,
+                              ss.jb.s.timed ? &ss.finalize_ms : nullptr, scrub);
+            if (rc) return rc;
+        }
         HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
         HIP_TRY(take_setup_time(ss));
         rc = read_draws(ss, (hipStream_t)stream);

@@ -157,6 +157,22 @@ struct StepArgs {
 // the item's wave).
 constexpr int kOutChunk = 64;
 
+// A finalize queued right after a chunk of frontier-driven IC steps, before
+// the host has read whether the chunk ended the run: its kernels act only if
+// one of steps t0+1 .. t0+c left its absorption flag clear, and take the
+// first such step T as the run's last (the frontier buffers of a step t are
+// those of t mod 3, its work queue that of t mod 4).
+struct SpecFin {
+    const uint32_t *flags;  // absorption ring, or null: not speculative
+    int32_t ring;
+    int32_t c;
+    int64_t t0;
+    uint64_t *front3[3];  // frontier plane after a step t, t mod 3 = i
+    uint32_t *bm3[3];     // its bitmap
+    uint32_t *sum3[3];    // its summary
+    uint4 *queue4[4];     // the work queue step t fills, t mod 4 = i
+};
+
 struct FinArgs {
     int32_t n, W, G, lgG;
     int64_t B;
@@ -180,6 +196,7 @@ struct FinArgs {
     const uint32_t *flags;  // absorption ring, or null (always a live step)
     int32_t ring;
     uint32_t step;
+    SpecFin spec;  // finalize queued before the run's end was known (spec.flags set)
 };
 
 // Many jobs in one launch per synchronous step.  Each job keeps its own
@@ -243,6 +260,11 @@ hipError_t launch_ic_front(const StepArgs &a, int grid, int block, hipStream_t s
 // the clear duty of k_ic_front alone (the queue of a.qi_clr leaves f_clr,
 // bm_clr, sum_clr), whatever the absorption flags say
 hipError_t launch_ic_scrub(const StepArgs &a, hipStream_t s);
+// the same for a finalize queued before the run's end was known: the
+// frontier of step T - 2 + which, T the run's last step (1 or 2), and the
+// run's tag written after the second
+hipError_t launch_ic_scrub_spec(const StepArgs &a, const SpecFin &sp, int which, uint64_t *tag,
+                                uint64_t tag_value, hipStream_t s);
 hipError_t launch_seed_queue(const StepArgs &a, const int32_t *seeds, int64_t ns, hipStream_t s);
 hipError_t launch_out_count(const int32_t *src, int64_t nnz, int32_t *cnt, hipStream_t s);
 hipError_t launch_out_fill(const int32_t *src, const int32_t *dst, int64_t nnz, int32_t *cursor,

@@ -1403,12 +1403,77 @@ __global__ void __launch_bounds__(512) k_ic_front(StepArgs a)
     if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) a.flags[a.step % (uint32_t)a.ring] = 1u;
 }
 
+// A finalize queued before the host knew the run had ended: the first step
+// of t0+1 .. t0+c whose absorption flag is clear (the run's last step), or
+// -1 (the run goes on; nothing to do).  A load and a ballot per 64 steps;
+// every lane of the wave gets the same answer.
+__device__ __forceinline__ int64_t spec_last_step(const SpecFin &s)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    for (int b = 0; b < s.c; b += 64) {
+        const int i = b + lane;
+        const bool clear =
+            i < s.c && s.flags[(uint32_t)(s.t0 + 1 + i) % (uint32_t)s.ring] == 0u;
+        const uint64_t m = __ballot(clear);
+        if (m) return s.t0 + 1 + b + __builtin_ctzll(m);
+    }
+    return -1;
+}
+
+// Entry i of a 3- or 4-entry pointer array held in kernel arguments, with
+// constant indices only (a run-time index would copy the arguments to
+// per-lane scratch).
+template <typename P>
+__device__ __forceinline__ P pick3(const P (&a)[3], int i)
+{
+    return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
+}
+template <typename P>
+__device__ __forceinline__ P pick4(const P (&a)[4], int i)
+{
+    return i == 0 ? a[0] : (i == 1 ? a[1] : (i == 2 ? a[2] : a[3]));
+}
+
+// The planes of a speculative finalize: the frontier of the run's last step
+// (empty, since that step activated nothing), or false when the run has not
+// ended.
+__device__ __forceinline__ bool spec_planes(FinArgs &f)
+{
+    if (f.spec.flags == nullptr) return true;
+    const int64_t T = spec_last_step(f.spec);
+    if (T < 0) return false;
+    const int m = (int)(T % 3);
+    f.one = pick3(f.spec.front3, m);
+    f.bm = pick3(f.spec.bm3, m);
+    return true;
+}
+
 // End of a frontier-driven run: the last two frontiers, which no later step
 // clears, leave their buffers (one launch per frontier).
 __global__ void __launch_bounds__(256) k_ic_scrub(StepArgs a)
 {
     ic_clear_pass(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
                   (int64_t)gridDim.x * blockDim.x);
+}
+
+// The same, queued before the host knew the run had ended (SpecFin): the
+// frontier of step T - 2 + which, T the run's last step; after the second
+// one the tag records that the run left its buffers clear.
+__global__ void __launch_bounds__(256) k_ic_scrub_spec(StepArgs a, SpecFin sp, int which,
+                                                      uint64_t *tag, uint64_t tag_value)
+{
+    const int64_t T = spec_last_step(sp);
+    if (T < 0) return;
+    const int64_t t = T + which;  // the step whose clear duty this is
+    const int m = (int)((t - 2) % 3);
+    a.qi_clr = (int32_t)((t + 2) % 4);
+    a.q_clr = pick4(sp.queue4, a.qi_clr);
+    a.f_clr = pick3(sp.front3, m);
+    a.bm_clr = pick3(sp.bm3, m);
+    a.sum_clr = pick3(sp.sum3, m);
+    ic_clear_pass(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                  (int64_t)gridDim.x * blockDim.x);
+    if (tag != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *tag = tag_value;
 }
 
 // Seeds of a frontier-driven run: joined to the frontier of step 0 (bitmap,
@@ -2003,6 +2068,7 @@ __global__ void k_seed(uint64_t *p1, uint64_t *p2, const int32_t *seeds, int64_t
 // Packed planes -> uint8 states [n][B] and per-node counts.
 __global__ void __launch_bounds__(256) k_finalize(FinArgs f)
 {
+    if (!spec_planes(f)) return;
     const int lane = threadIdx.x & 63;
     const int G = f.G;
     const int rpw = 64 >> f.lgG;
@@ -2143,6 +2209,7 @@ __device__ __forceinline__ void dense_out(const FinArgs &f, int64_t rb, int lane
 // Two blocks of 64 words per pass, their loads issued before either's stores.
 __global__ void __launch_bounds__(256) k_finalize_dense(FinArgs f)
 {
+    if (!spec_planes(f)) return;
     const int lane = threadIdx.x & 63;
     const int rpw = 64 >> f.lgG;
     const int64_t gwave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -2309,6 +2376,13 @@ hipError_t launch_count_rows(const uint64_t *plane, int64_t n, int64_t W, unsign
 hipError_t launch_ic_scrub(const StepArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ic_scrub, dim3(256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_scrub_spec(const StepArgs &a, const SpecFin &sp, int which, uint64_t *tag,
+                                uint64_t tag_value, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ic_scrub_spec, dim3(256), dim3(256), 0, s, a, sp, which, tag, tag_value);
     return hipGetLastError();
 }
 
