@@ -953,11 +953,14 @@ int finalize_job(const Job &jb, int64_t steps_run, uint8_t *final_states, uint32
 }
 
 // Frontier-driven IC through fsg_simulate: the finalize, the clearing of the
-// last two frontiers and the tag are queued right after every chunk of
-// steps, before the host reads the absorption flags; on the device they act
-// only if the chunk ended the run (SpecFin), so the finalize follows the last
-// step without a host round trip.  `done` tells the caller the outputs are
-// written.
+// last two frontiers and the tag are queued right after the run's first
+// chunk of steps, before the host reads the absorption flags; on the device
+// they act only if the chunk ended the run (SpecFin), so the finalize follows
+// the last step without a host round trip.  When they do not act, the finalize
+// has still dispatched its whole grid (65-75 us at web scale), so later
+// chunks are not followed by one: a run that outlives its first chunk pays
+// that once and is finalized after the host has seen its end.  `done` tells
+// the caller the outputs are written.
 struct SpecOut {
     uint8_t *states = nullptr;
     uint32_t *counts = nullptr;
@@ -1228,7 +1231,8 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st,
                 HIP_TRY(launch_tally(f, st));
             }
         }
-        if (so) HIP_TRY(queue_spec_finalize(jb, t, c, *so, st));
+        const bool spec = so != nullptr && t == t_begin;  // the run's first chunk only
+        if (spec) HIP_TRY(queue_spec_finalize(jb, t, c, *so, st));
         if (s.push)  // out-arcs of the frontier the next step starts from (queue of step t+c)
             HIP_TRY(hipMemcpyAsync(&hqarcs, a.qarcs + (t + c) % 4, 8, hipMemcpyDeviceToHost, st));
         if (jb.tail) {  // nodes with an infected replicate (LT: a new activation) after the chunk
@@ -1265,7 +1269,7 @@ int run_steps(Session &ss, int64_t n_more, uint64_t *dev_tally, hipStream_t st,
                 ss.absorbed = true;
                 break;
             }
-        if (so && ss.absorbed) {  // the queued finalize acted (the same first clear flag)
+        if (spec && ss.absorbed) {  // the queued finalize acted (the same first clear flag)
             so->done = true;
             if (s.timed) {
                 float ms = 0.f;
