@@ -1518,7 +1518,7 @@ int fsg_simulate(const fsg_graph *g_, const fsg_params *prm, const int32_t *seed
         if (rc) return rc;
         if (so.done) {
             ss.finalize_ms = so.ms;
-        } else {  // the run stopped at its step cap (or has no seeds)
+        } else {  // the run outlived its first chunk, stopped at its step cap, or has no seeds
             rc = finalize_job(ss.jb, ss.steps_run, final_states, infected_counts, (hipStream_t)stream,
                               ss.jb.s.timed ? &ss.finalize_ms : nullptr, scrub);
             if (rc) return rc;
